@@ -1,0 +1,302 @@
+/*
+ * qcemu: FP32-accurate complex GEMM by emulation on gfx950 matrix cores, with
+ * per-GEMM automatic split-format selection from exponent statistics, and
+ * tensor contraction on top of it.
+ *
+ * Method: Ootomo, Manabe, Harada, Yokota, "Quantum Circuit Simulation by SGEMM
+ * Emulation on Tensor Cores and Automatic Precision Selection" (arXiv
+ * 2303.08989).  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are complex64: two interleaved FP32 values (re, im),
+ *   8-byte aligned (qce_c32).
+ * - Matrices follow the BLAS convention: column-major, element (i, j) of a
+ *   matrix with leading dimension ld sits at index i + j * ld.
+ * - Tensors are dense row-major (last axis fastest), described by
+ *   qce_tensor; every extent is >= 1 and the product of extents fits int64.
+ * - Pointers named "device" point to memory on the handle's GPU; pointers
+ *   named "host" point to CPU memory.  The caller owns every buffer it passes
+ *   in; the library never frees caller memory.
+ * - All device work is enqueued on the handle's stream and the call returns
+ *   after enqueueing (stream-ordered, like BLAS).  Only the calls documented as
+ *   "synchronises" wait for the device.
+ * - Errors are reported by return value; no exception crosses this interface.
+ *   On an argument error nothing is enqueued and no output is touched.
+ *   NaN/Inf in the data are not errors: they force the FP32 mode and
+ *   propagate per IEEE.
+ * - A handle is not thread-safe: calls on one handle must come from one host
+ *   thread at a time.  Calls on one handle share its statistics and workspace
+ *   buffers, so they are ordered on the handle's stream.
+ */
+#ifndef QCEMU_H
+#define QCEMU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qce_handle qce_handle; /* opaque */
+
+typedef struct {
+    float re, im;
+} qce_c32;
+
+typedef enum {
+    QCE_SUCCESS = 0,
+    QCE_ERR_INVALID_VALUE = 1, /* bad argument: sizes, strides, null pointers, labels */
+    QCE_ERR_NOT_SUPPORTED = 2, /* well-formed request outside what is implemented */
+    QCE_ERR_ALLOC = 3,         /* device memory allocation failed */
+    QCE_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed */
+    QCE_ERR_INTERNAL = 5
+} qce_status;
+
+/*
+ * GEMM computing modes.
+ * FP16X2         two-term FP16 split with the residual scaled by 2^11 and
+ *                three products per real GEMM (Sec. 2.1, Eq. 2: FP16TCEC).
+ * FP16X2_SCALED  the same after shifting each operand by a power of two so
+ *                that its largest exponent becomes 14, result shifted back
+ *                (Sec. 4, "FP16TCEC w/ scaling").
+ * BF16X3         three-term bfloat16 split, six products; takes the role of
+ *                TF32TCEC (FP32 exponent range; Sec. 2.1, Table 1), since
+ *                gfx950 has no TF32 matrix instruction.
+ * FP32           plain FP32 products with FP32 accumulation (the baseline
+ *                role of Sec. 5; also the fallback for non-finite data).
+ * AUTO           exponent statistics of both operands select one of the
+ *                above on the device, with no device-to-host transfer
+ *                (Sec. 4.1 and 4.2).
+ */
+typedef enum {
+    QCE_MODE_FP16X2 = 0,
+    QCE_MODE_FP16X2_SCALED = 1,
+    QCE_MODE_BF16X3 = 2,
+    QCE_MODE_FP32 = 3,
+    QCE_MODE_AUTO = 4
+} qce_mode;
+
+typedef enum { QCE_OP_N = 0, QCE_OP_T = 1, QCE_OP_C = 2 } qce_op;
+
+/* Row-major dense tensor shape: rank >= 0 axes with extents[0..rank-1]. */
+typedef struct {
+    int32_t rank;
+    const int64_t *extents; /* host pointer, rank entries (may be NULL if rank == 0) */
+} qce_tensor;
+
+/*
+ * Record of the most recent GEMM decision on a handle (Sec. 4.1 statistics
+ * and the selected mode).  Index 0 is operand A, index 1 is operand B.
+ *   nnz        nonzero finite FP32 components (real and imaginary parts are
+ *              separate elements)
+ *   n1         components with floor(log2|v|) >= -14 (stage 1: above the
+ *              smallest normal FP16)
+ *   n2         components with floor(log2|v|) >= emax - 28 (stage 2: inside
+ *              the FP16 exponent window once emax is shifted to 14); -1 when
+ *              stage 2 was not needed for that operand
+ *   n3         components with floor(log2|v|) >= -110 (BF16X3 floor)
+ *   nonfinite  Inf/NaN components
+ *   emax       largest floor(log2|v|) (INT32_MIN when nnz == 0)
+ *   sA, sB     power-of-two shifts applied in FP16X2_SCALED (else 0)
+ *   stats_taken 1 if exponent statistics ran, 0 for a forced mode
+ */
+typedef struct {
+    int32_t mode;
+    int32_t sA, sB;
+    int32_t stats_taken;
+    int64_t nnz[2], n1[2], n2[2], n3[2], nonfinite[2];
+    int32_t emax[2];
+} qce_decision;
+
+/* ---------------------------------------------------------------------- */
+/* Handle                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Create a handle bound to HIP device `device`.  The handle owns its
+ * statistics/decision buffers and a workspace that grows on demand.  Reads
+ * the environment once (the paper selects implementations by environment
+ * variable, Sec. 3):
+ *   QCE_MODE           auto | fp16x2 | fp16x2s | bf16x3 | fp32
+ *   QCE_UNDERFLOW_TOL  t  in [0, 1], default 0.1 (AUTO-0.1, Sec. 5.2)
+ *   QCE_BF16X3_TOL     t3 in [0, 1], default 0
+ *   QCE_AUTO_MIN_DIM   size policy threshold for statistics, default 2048
+ *   QCE_EMUL_MIN_DIM   size policy threshold for emulation, default 512
+ * The stream is the device's null stream until qce_set_stream.
+ * Errors: INVALID_VALUE (h NULL, bad device or bad environment value),
+ * ALLOC, HIP.
+ */
+qce_status qce_create(qce_handle **h, int device);
+
+/* Waits for the handle's stream, frees what the handle owns. NULL is a no-op. */
+qce_status qce_destroy(qce_handle *h);
+
+/*
+ * Use `stream` (a hipStream_t, passed as void*) for all later work.  The
+ * previous stream is synchronised first so that work on the two streams
+ * cannot overlap on the handle's shared buffers.
+ */
+qce_status qce_set_stream(qce_handle *h, void *stream);
+
+/* Mode for later calls (overrides QCE_MODE). INVALID_VALUE for unknown m. */
+qce_status qce_set_mode(qce_handle *h, qce_mode m);
+qce_status qce_get_mode(const qce_handle *h, qce_mode *m);
+
+/*
+ * Underflow tolerances of the selection rule (Sec. 4.1; AUTO-t of Sec. 5.2):
+ * an operand may use an FP16 mode when at most t * nnz of its nonzero
+ * components fall outside the FP16 window, and BF16X3 when at most t3 * nnz
+ * fall below 2^-110.  Both in [0, 1], else INVALID_VALUE.
+ */
+qce_status qce_set_underflow_tolerance(qce_handle *h, double t, double t3);
+
+/*
+ * Size policy used by qce_contract when the handle mode is AUTO (Sec. 4.3):
+ * min(m, n, k) >= auto_min -> AUTO (statistics + selection);
+ * otherwise min(m, n, k) >= emul_min -> BF16X3 (the wide-exponent emulation,
+ * as the paper uses TF32TCEC there); otherwise FP32.
+ * Requires 0 <= emul_min <= auto_min, else INVALID_VALUE.
+ */
+qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min);
+
+/*
+ * Hand the library a caller-owned device workspace of `bytes` bytes (NULL,0
+ * returns to library-owned workspace).  If a call needs more than `bytes`,
+ * it fails with ALLOC and enqueues nothing.  The library never frees it.
+ */
+qce_status qce_set_workspace(qce_handle *h, void *device_ptr, size_t bytes);
+
+/* Workspace bytes one qce_cgemm_emulated call of this shape needs. */
+size_t qce_cgemm_workspace_size(int64_t m, int64_t n, int64_t k);
+
+/* ---------------------------------------------------------------------- */
+/* GEMM                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * C <- alpha * op(A) * op(B) + beta * C, complex64, BLAS CGEMM semantics
+ * (the paper's library replaces cuBLAS CGEMM, Sec. 3), computed in the
+ * handle's mode:
+ *   - AUTO: exponent statistics of A and B (every element, Sec. 4 first
+ *     strategy), the two-stage rule of Sec. 4.1 extended by BF16X3 and FP32
+ *     levels, and device-side dispatch: all candidate kernels are enqueued
+ *     and those not selected return at once after reading the device mode
+ *     flag (Sec. 4.2).  No size policy applies here.
+ *   - a forced mode runs that mode without statistics (FP16X2_SCALED still
+ *     takes statistics to find its shifts).
+ * op(X) = X (QCE_OP_N), X^T (QCE_OP_T) or X^H (QCE_OP_C).
+ * A: device, op(A) is m x k; stored as m x k (N) or k x m (T, C) with
+ *    leading dimension lda >= max(1, rows stored).  B likewise, k x n, ldb.
+ * C: device, m x n, ldc >= max(1, m); must not overlap A or B.
+ * alpha, beta: host pointers to complex64 scalars (NULL means 1 and 0).
+ *    beta == 0 means C is not read (NaN in C does not propagate).
+ * A and B are read-only (the paper scales inputs in place, Sec. 4.2 note;
+ * here shifted copies live in the workspace).
+ * m == 0 or n == 0: success, nothing enqueued.  k == 0: C <- beta * C.
+ * Errors: INVALID_VALUE for h NULL, negative sizes, bad op, ld too small,
+ *   NULL A/B/C with nonzero sizes, or pointers not 8-byte aligned;
+ *   ALLOC / HIP.
+ */
+qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                              int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                              const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
+                              int64_t ldc);
+
+/*
+ * Synchronises the handle's stream, then copies the decision record of the
+ * most recent qce_cgemm_emulated (or the last GEMM inside qce_contract) to
+ * *out (host).  For tests and logging only.  INVALID_VALUE if no GEMM ran.
+ */
+qce_status qce_get_last_decision(qce_handle *h, qce_decision *out);
+
+/* ---------------------------------------------------------------------- */
+/* Tensor contraction                                                     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * C[lc] = sum over the labels shared by A and B of A[la] * B[lb]: one
+ * pairwise contraction of a tensor network (Sec. 2.2), computed by
+ * transpose-transpose-GEMM-transpose (Sec. 1): operands are permuted on the
+ * device only when their labels are not already grouped as the GEMM needs,
+ * the GEMM runs through the emulated CGEMM under the size policy (Sec. 4.3),
+ * and the result is permuted only if lc's order requires it.
+ * a, b, c: host shape descriptors; A, B: device complex64 inputs; C: device
+ * complex64 output of the shape c describes (must not overlap A or B).
+ * la, lb, lc: host int32 label arrays of lengths a->rank, b->rank, c->rank.
+ * Requirements (else INVALID_VALUE): labels unique within each tensor; a
+ * label in both A and B has equal extents there; every label of lc appears
+ * in exactly one of la, lb with the same extent; c's extents match.
+ * NOT_SUPPORTED: a label in A, B and C (batch), or a label in only one input
+ * and not in C (a trace).
+ */
+qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const int32_t *la,
+                        const qce_tensor *b, const void *B, const int32_t *lb,
+                        const qce_tensor *c, void *C, const int32_t *lc);
+
+/*
+ * Axis permutation of a dense row-major complex64 tensor (the "T" of TTGT,
+ * Sec. 1): Y has axes (perm[0], ..., perm[rank-1]) of X, i.e. output axis d
+ * is input axis perm[d].  X, Y: device, not overlapping.  x: host shape of X.
+ * perm: host, a permutation of 0..rank-1, else INVALID_VALUE.
+ */
+qce_status qce_permute(qce_handle *h, const qce_tensor *x, const void *X, const int32_t *perm,
+                       void *Y);
+
+/* ---------------------------------------------------------------------- */
+/* FP64 reductions (slice sum and fidelity)                               */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * acc2[0] += re(*src), acc2[1] += im(*src) in FP64 on the device: the sum of
+ * the amplitudes of independent slices of one network (Sec. 5.3).  src and
+ * acc2 are device pointers (one complex64 value, two doubles).
+ */
+qce_status qce_accumulate_f64(qce_handle *h, const qce_c32 *src, double *acc2);
+
+/*
+ * out4 (device, 4 doubles) <- { re(sum conj(b) a), im(sum conj(b) a),
+ * sum |a|^2, sum |b|^2 } over n complex64 values of a and b (device), in
+ * FP64: the terms of the fidelity |<b|a>|^2 / (<a|a><b|b>) between two
+ * amplitude vectors.  n == 0 writes zeros.
+ */
+qce_status qce_fidelity_f64(qce_handle *h, const qce_c32 *a, const qce_c32 *b, int64_t n,
+                            double *out4);
+
+/* ---------------------------------------------------------------------- */
+/* Steps of the GEMM path on their own (for tests)                         */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Exponent statistics of one rows x cols complex64 matrix X (device,
+ * column-major, leading dimension ld >= rows) as defined for qce_decision,
+ * with stage 2 always evaluated; t selects nothing here.  Synchronises;
+ * writes *out (host): nnz, n1, n2, n3, nonfinite, emax into index 0 of the
+ * arrays and the operand's own tolerance level (as a qce_mode value, under
+ * the handle's t, t3) into out->mode.
+ */
+qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t cols, int64_t ld,
+                        qce_decision *out);
+
+/*
+ * The split of Sec. 2.1 (Eq. 2) on n complex64 values x (device), written as
+ * planes (device, uint16 bit patterns): mode FP16X2 writes 4 planes of n
+ * values: hi(re), lo(re), hi(im), lo(im) of x * 2^shift (lo scaled by 2^11);
+ * mode BF16X3 writes 6 planes: b0(re), b1(re), b2(re), b0(im), b1(im),
+ * b2(im).  Plane p starts at planes + p * n.  Other modes: NOT_SUPPORTED.
+ */
+qce_status qce_split(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 *x, int64_t n,
+                     uint16_t *planes);
+
+/* Human-readable name of a status code (static string). */
+const char *qce_status_string(qce_status s);
+
+/* Last error message recorded on the handle (static storage per handle). */
+const char *qce_last_error(const qce_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCEMU_H */

@@ -1,0 +1,229 @@
+"""MI355X (gfx950) emulated-FP32 complex GEMM and tensor contraction for
+quantum-circuit tensor networks (arXiv 2303.08989).
+
+The functions here only marshal arguments to the C-ABI of libqcemu.so
+(``include/qcemu.h``): torch tensors provide device memory and the current
+stream, every computation runs in the library's HIP kernels.  Importing the
+package does not touch the GPU; the first call loads the library and fails
+loudly if it is not built.
+
+Tensors are dense row-major torch tensors (complex64 on the GPU).  The BLAS
+entry point ``cgemm`` takes column-major conventions exactly as the C-ABI;
+``matmul`` is the row-major convenience form.
+"""
+import ctypes
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    MODE_AUTO, MODE_BF16X3, MODE_FP16X2, MODE_FP16X2_SCALED, MODE_FP32, MODE_NAMES,
+    MODE_BY_NAME, QceError,
+)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(h, status):
+    if status != 0:
+        msg = ""
+        if h is not None:
+            msg = _lib.load().qce_last_error(h).decode(errors="replace")
+        raise QceError(status, msg)
+
+
+def _mode_value(mode):
+    if isinstance(mode, str):
+        return _lib.MODE_BY_NAME[mode]
+    return int(mode)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _c32(z):
+    z = complex(z)
+    return _lib.QceC32(z.real, z.imag)
+
+
+class Handle:
+    """A library handle on one GPU; work goes to torch's current stream."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._h = ctypes.c_void_p()
+        _check(None, self.lib.qce_create(ctypes.byref(self._h), self.device))
+        self._stream = None
+
+    def _bind_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            _check(self._h, self.lib.qce_set_stream(self._h, ctypes.c_void_p(s)))
+            self._stream = s
+        return self._h
+
+    def close(self):
+        if self._h:
+            self.lib.qce_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mode(self, mode):
+        _check(self._h, self.lib.qce_set_mode(self._h, _mode_value(mode)))
+
+    def get_mode(self):
+        m = ctypes.c_int()
+        _check(self._h, self.lib.qce_get_mode(self._h, ctypes.byref(m)))
+        return m.value
+
+    def set_tolerance(self, t, t3=0.0):
+        _check(self._h, self.lib.qce_set_underflow_tolerance(self._h, float(t), float(t3)))
+
+    def set_size_policy(self, auto_min, emul_min):
+        _check(self._h, self.lib.qce_set_size_policy(self._h, int(auto_min), int(emul_min)))
+
+    def set_workspace(self, tensor):
+        if tensor is None:
+            _check(self._h, self.lib.qce_set_workspace(self._h, None, 0))
+        else:
+            nbytes = tensor.numel() * tensor.element_size()
+            _check(self._h, self.lib.qce_set_workspace(self._h, _ptr(tensor), nbytes))
+
+    def last_decision(self):
+        """Synchronising read of the last GEMM decision record."""
+        d = _lib.QceDecision()
+        _check(self._h, self.lib.qce_get_last_decision(self._bind_stream(), ctypes.byref(d)))
+        return _decision_dict(d)
+
+
+def _decision_dict(d):
+    return {"mode": d.mode, "mode_name": MODE_NAMES.get(d.mode, str(d.mode)),
+            "sA": d.sA, "sB": d.sB, "stats_taken": d.stats_taken,
+            "nnz": list(d.nnz), "n1": list(d.n1), "n2": list(d.n2), "n3": list(d.n3),
+            "nonfinite": list(d.nonfinite), "emax": list(d.emax)}
+
+
+def cgemm_workspace_size(m, n, k):
+    return int(_lib.load().qce_cgemm_workspace_size(int(m), int(n), int(k)))
+
+
+def cgemm(h, opA, opB, m, n, k, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0):
+    """BLAS CGEMM, column-major: C <- alpha op(A) op(B) + beta C (C-ABI
+    ``qce_cgemm_emulated``).  A, B, C are complex64 device tensors used only
+    for their data pointers."""
+    hh = h._bind_stream()
+    a, b = _c32(alpha), _c32(beta)
+    _check(hh, h.lib.qce_cgemm_emulated(hh, _lib.OPS[opA], _lib.OPS[opB], int(m), int(n), int(k),
+                                        ctypes.byref(a), _ptr(A), int(lda), _ptr(B), int(ldb),
+                                        ctypes.byref(b), _ptr(C), int(ldc)))
+    return C
+
+
+def matmul(h, A, B, out=None):
+    """Row-major C = A @ B for 2-D complex64 device tensors.  A row-major
+    (M, K) tensor is the column-major K x M matrix A^T, so C^T = B^T A^T is
+    one column-major GEMM with the operands swapped."""
+    torch = _torch()
+    A = A.contiguous()
+    B = B.contiguous()
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.complex64, device=A.device)
+    cgemm(h, "N", "N", N, M, K, B, max(1, N), A, max(1, K), out, max(1, N))
+    return out
+
+
+def _tensor_desc(shape):
+    ext = (ctypes.c_int64 * max(1, len(shape)))(*[int(s) for s in shape])
+    return _lib.QceTensor(len(shape), ext), ext
+
+
+def _labels(ls):
+    return (ctypes.c_int32 * max(1, len(ls)))(*[int(x) for x in ls])
+
+
+def contract(h, A, la, B, lb, lc, out=None):
+    """C[lc] = sum A[la] B[lb] over the labels shared by A and B (C-ABI
+    ``qce_contract``).  Row-major complex64 device tensors."""
+    torch = _torch()
+    A = A.contiguous()
+    B = B.contiguous()
+    ext = {}
+    for t, ls in ((A, la), (B, lb)):
+        for d, lab in enumerate(ls):
+            ext[lab] = t.shape[d]
+    cshape = tuple(ext[x] for x in lc)
+    if out is None:
+        out = torch.empty(cshape, dtype=torch.complex64, device=A.device)
+    ta, ka = _tensor_desc(A.shape)
+    tb, kb = _tensor_desc(B.shape)
+    tc, kc = _tensor_desc(cshape)
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_contract(hh, ctypes.byref(ta), _ptr(A), _labels(la),
+                                  ctypes.byref(tb), _ptr(B), _labels(lb),
+                                  ctypes.byref(tc), _ptr(out), _labels(lc)))
+    return out
+
+
+def permute(h, X, perm, out=None):
+    """Y = X.permute(perm) materialised by the library (C-ABI ``qce_permute``)."""
+    torch = _torch()
+    X = X.contiguous()
+    shape = tuple(X.shape[p] for p in perm)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=X.device)
+    tx, kx = _tensor_desc(X.shape)
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_permute(hh, ctypes.byref(tx), _ptr(X), _labels(perm), _ptr(out)))
+    return out
+
+
+def accumulate_f64(h, src, acc):
+    """acc (float64[2], device) += src (complex64 scalar, device), in FP64."""
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_accumulate_f64(hh, _ptr(src), _ptr(acc)))
+    return acc
+
+
+def fidelity_terms(h, a, b, out=None):
+    """out (float64[4], device) = [re <b|a>, im <b|a>, <a|a>, <b|b>] in FP64."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=a.device)
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_fidelity_f64(hh, _ptr(a), _ptr(b), int(a.numel()), _ptr(out)))
+    return out
+
+
+def expstats(h, X, rows, cols, ld):
+    """Synchronising exponent statistics of a column-major matrix."""
+    d = _lib.QceDecision()
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_expstats(hh, _ptr(X), int(rows), int(cols), int(ld), ctypes.byref(d)))
+    r = _decision_dict(d)
+    return {"level": r["mode"], "nnz": r["nnz"][0], "n1": r["n1"][0], "n2": r["n2"][0],
+            "n3": r["n3"][0], "nonfinite": r["nonfinite"][0], "emax": r["emax"][0]}
+
+
+def split(h, mode, shift, x):
+    """Planar split of n complex64 values: int16 device tensor (planes, n)."""
+    torch = _torch()
+    mode = _mode_value(mode)
+    planes = 6 if mode == MODE_BF16X3 else 4
+    out = torch.empty((planes, x.numel()), dtype=torch.int16, device=x.device)
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_split(hh, mode, int(shift), _ptr(x), int(x.numel()), _ptr(out)))
+    return out

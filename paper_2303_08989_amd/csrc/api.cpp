@@ -1,0 +1,708 @@
+// C-ABI of the library: handle, emulated CGEMM orchestration, TTGT tensor
+// contraction planner, permute, FP64 reductions and the test entry points.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace qce;
+
+struct qce_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    qce_mode mode = QCE_MODE_AUTO;
+    double t = 0.1, t3 = 0.0;
+    int64_t auto_min = 2048, emul_min = 512;
+    DevState *st = nullptr;        // device
+    double *fid_partials = nullptr;  // device, kFidBlocks * 4
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = true;
+    bool stats_dirty = false;
+    bool have_decision = false;
+    bool last_on_device = false;
+    qce_decision last_host{};
+    char err[512] = {0};
+};
+
+namespace {
+
+constexpr int kFidBlocks = 512;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+qce_status fail(qce_handle *h, qce_status s, const char *fmt, ...) {
+    if (h) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(h->err, sizeof(h->err), fmt, ap);
+        va_end(ap);
+    }
+    return s;
+}
+
+#define QCE_HIP(h, expr)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((h), QCE_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+bool parse_mode(const char *s, qce_mode *m) {
+    std::string v(s);
+    for (auto &c : v) c = (char)tolower(c);
+    if (v == "auto") *m = QCE_MODE_AUTO;
+    else if (v == "fp16x2" || v == "fp16tcec") *m = QCE_MODE_FP16X2;
+    else if (v == "fp16x2s" || v == "fp16x2_scaled") *m = QCE_MODE_FP16X2_SCALED;
+    else if (v == "bf16x3") *m = QCE_MODE_BF16X3;
+    else if (v == "fp32") *m = QCE_MODE_FP32;
+    else return false;
+    return true;
+}
+
+bool parse_double(const char *s, double *out) {
+    char *end = nullptr;
+    double v = strtod(s, &end);
+    if (end == s || *end != '\0') return false;
+    *out = v;
+    return true;
+}
+
+bool parse_i64(const char *s, int64_t *out) {
+    char *end = nullptr;
+    long long v = strtoll(s, &end, 10);
+    if (end == s || *end != '\0') return false;
+    *out = v;
+    return true;
+}
+
+// Make sure the handle workspace holds `bytes`.
+qce_status ensure_ws(qce_handle *h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return QCE_SUCCESS;
+    if (!h->ws_owned)
+        return fail(h, QCE_ERR_ALLOC, "caller workspace of %zu bytes, %zu needed", h->ws_bytes, bytes);
+    if (h->ws) {
+        QCE_HIP(h, hipStreamSynchronize(h->stream));
+        QCE_HIP(h, hipFree(h->ws));
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    want = (want + 4095) & ~(size_t)4095;
+    if (hipMalloc(&h->ws, want) != hipSuccess) {
+        (void)hipGetLastError();
+        h->ws = nullptr;
+        return fail(h, QCE_ERR_ALLOC, "hipMalloc of %zu bytes failed", want);
+    }
+    h->ws_bytes = want;
+    return QCE_SUCCESS;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// A GEMM operand as the panel writer sees it: P[r][l] = kcontig ? x[l + r*ld]
+// : x[r + l*ld], conjugated if conj.
+struct OperandView {
+    const float2 *ptr;
+    int64_t ld;
+    bool kcontig;
+    bool conj;
+};
+
+MatDesc stored_desc(const OperandView &v, int64_t rows, int64_t k) {
+    // the stored column-major matrix behind the view
+    if (v.kcontig) return MatDesc{v.ptr, k, rows, v.ld};
+    return MatDesc{v.ptr, rows, k, v.ld};
+}
+
+// The emulated CGEMM of one GEMM: C = alpha * PA * PB^T + beta * C where PA
+// (m x k) and PB (n x k) are the panel views.  `ws` holds both panel buffers.
+qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const OperandView &b,
+                      int64_t m, int64_t n, int64_t k, float2 alpha, float2 beta, float2 *C,
+                      int64_t ldc, char *ws) {
+    hipStream_t s = h->stream;
+    const int beta_zero = beta.x == 0.f && beta.y == 0.f;
+    if (k == 0) {
+        QCE_HIP(h, launch_scale_c(C, m, n, ldc, beta, beta_zero, s));
+        h->have_decision = true;
+        h->last_on_device = false;
+        h->last_host = qce_decision{};
+        h->last_host.mode = QCE_MODE_FP32;
+        return QCE_SUCCESS;
+    }
+    char *panA = ws;
+    char *panB = ws + align256(panel_bytes(m, k));
+    const MatDesc da = stored_desc(a, m, k), db = stored_desc(b, n, k);
+    GemmArgs g{};
+    g.panelsA = panA;
+    g.panelsB = panB;
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.C = C;
+    g.ldc = ldc;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.beta_zero = beta_zero;
+    if (mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED) {
+        if (h->stats_dirty) QCE_HIP(h, launch_stats_clear(h->st, s));
+        h->stats_dirty = true;
+        QCE_HIP(h, launch_stats1(da, db, h->st, s));
+        if (mode == QCE_MODE_AUTO) {
+            QCE_HIP(h, launch_stats2(da, db, h->st, h->t, 0, s));
+            QCE_HIP(h, launch_select(h->st, h->t, h->t3, -1, s));
+        } else {
+            QCE_HIP(h, launch_select(h->st, h->t, h->t3, QCE_MODE_FP16X2_SCALED, s));
+        }
+        h->stats_dirty = false;
+        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, h->st, 0, 0, 0, s));
+        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, h->st, 1, 0, 0, s));
+        g.st = h->st;
+        g.forced_mode = -1;
+        if (mode == QCE_MODE_AUTO) {
+            QCE_HIP(h, launch_gemm(g, QCE_MODE_FP16X2, s));
+            QCE_HIP(h, launch_gemm(g, QCE_MODE_BF16X3, s));
+            QCE_HIP(h, launch_gemm(g, QCE_MODE_FP32, s));
+        } else {
+            QCE_HIP(h, launch_gemm(g, QCE_MODE_FP16X2, s));
+        }
+        h->have_decision = true;
+        h->last_on_device = true;
+    } else {
+        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, nullptr, 0, mode, 0, s));
+        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, nullptr, 1, mode, 0, s));
+        g.st = nullptr;
+        g.forced_mode = mode;
+        QCE_HIP(h, launch_gemm(g, mode == QCE_MODE_BF16X3 ? QCE_MODE_BF16X3
+                                  : mode == QCE_MODE_FP32 ? QCE_MODE_FP32 : QCE_MODE_FP16X2, s));
+        h->have_decision = true;
+        h->last_on_device = false;
+        h->last_host = qce_decision{};
+        h->last_host.mode = mode;
+        for (int o = 0; o < 2; ++o) {
+            h->last_host.n2[o] = -1;
+            h->last_host.emax[o] = INT32_MIN;
+        }
+    }
+    return QCE_SUCCESS;
+}
+
+size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k) {
+    if (k == 0) return 0;
+    return align256(panel_bytes(m, k)) + align256(panel_bytes(n, k));
+}
+
+bool valid_op(int op) { return op == QCE_OP_N || op == QCE_OP_T || op == QCE_OP_C; }
+
+// --- permute planning -----------------------------------------------------
+
+// Build the merged permutation descriptor: output axis d is input axis
+// perm[d] of a row-major tensor with extents ext.
+qce_status plan_permute(qce_handle *h, int rank, const int64_t *ext, const int32_t *perm,
+                        PermDesc &d, int64_t &total, bool &identity) {
+    std::vector<int64_t> istr(rank);
+    int64_t s = 1;
+    for (int a = rank - 1; a >= 0; --a) {
+        istr[a] = s;
+        s *= ext[a];
+    }
+    total = s;
+    std::vector<int64_t> oe, os;
+    for (int a = 0; a < rank; ++a) {
+        const int64_t e = ext[perm[a]];
+        if (e == 1) continue;
+        const int64_t st = istr[perm[a]];
+        if (!oe.empty() && os.back() == st * e) {
+            oe.back() *= e;
+            os.back() = st;
+        } else {
+            oe.push_back(e);
+            os.push_back(st);
+        }
+    }
+    identity = oe.size() <= 1 && (os.empty() || os[0] == 1);
+    if ((int)oe.size() > kMaxRank)
+        return fail(h, QCE_ERR_NOT_SUPPORTED, "permutation needs %zu merged axes (max %d)", oe.size(), kMaxRank);
+    memset(&d, 0, sizeof(d));
+    d.rank = (int)oe.size();
+    d.pow2 = 1;
+    for (int a = 0; a < d.rank; ++a) {
+        d.ext[a] = oe[a];
+        d.istride[a] = os[a];
+        int lg = 0;
+        while ((int64_t(1) << lg) < oe[a]) ++lg;
+        d.log2ext[a] = lg;
+        if ((int64_t(1) << lg) != oe[a]) d.pow2 = 0;
+    }
+    return QCE_SUCCESS;
+}
+
+qce_status run_permute(qce_handle *h, int rank, const int64_t *ext, const int32_t *perm,
+                       const float2 *x, float2 *y) {
+    PermDesc d;
+    int64_t total = 0;
+    bool identity = false;
+    qce_status st = plan_permute(h, rank, ext, perm, d, total, identity);
+    if (st != QCE_SUCCESS) return st;
+    if (total == 0) return QCE_SUCCESS;
+    if (identity) {
+        QCE_HIP(h, hipMemcpyAsync(y, x, (size_t)total * sizeof(float2), hipMemcpyDeviceToDevice, h->stream));
+        return QCE_SUCCESS;
+    }
+    QCE_HIP(h, launch_permute(x, y, total, d, h->stream));
+    return QCE_SUCCESS;
+}
+
+bool checked_numel(int rank, const int64_t *ext, int64_t &n) {
+    n = 1;
+    for (int a = 0; a < rank; ++a) {
+        if (ext[a] < 1) return false;
+        if (n > INT64_MAX / ext[a]) return false;
+        n *= ext[a];
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qce_status_string(qce_status s) {
+    switch (s) {
+    case QCE_SUCCESS: return "QCE_SUCCESS";
+    case QCE_ERR_INVALID_VALUE: return "QCE_ERR_INVALID_VALUE";
+    case QCE_ERR_NOT_SUPPORTED: return "QCE_ERR_NOT_SUPPORTED";
+    case QCE_ERR_ALLOC: return "QCE_ERR_ALLOC";
+    case QCE_ERR_HIP: return "QCE_ERR_HIP";
+    case QCE_ERR_INTERNAL: return "QCE_ERR_INTERNAL";
+    }
+    return "QCE_ERR_UNKNOWN";
+}
+
+const char *qce_last_error(const qce_handle *h) { return h ? h->err : "null handle"; }
+
+qce_status qce_create(qce_handle **out, int device) {
+    if (!out) return QCE_ERR_INVALID_VALUE;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return QCE_ERR_INVALID_VALUE;
+    qce_handle *h = new qce_handle();
+    h->device = device;
+    if (const char *v = getenv("QCE_MODE")) {
+        if (!parse_mode(v, &h->mode)) { delete h; return QCE_ERR_INVALID_VALUE; }
+    }
+    if (const char *v = getenv("QCE_UNDERFLOW_TOL")) {
+        if (!parse_double(v, &h->t) || !(h->t >= 0 && h->t <= 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
+    }
+    if (const char *v = getenv("QCE_BF16X3_TOL")) {
+        if (!parse_double(v, &h->t3) || !(h->t3 >= 0 && h->t3 <= 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
+    }
+    if (const char *v = getenv("QCE_AUTO_MIN_DIM")) {
+        if (!parse_i64(v, &h->auto_min) || h->auto_min < 0) { delete h; return QCE_ERR_INVALID_VALUE; }
+    }
+    if (const char *v = getenv("QCE_EMUL_MIN_DIM")) {
+        if (!parse_i64(v, &h->emul_min) || h->emul_min < 0) { delete h; return QCE_ERR_INVALID_VALUE; }
+    }
+    if (h->emul_min > h->auto_min) { delete h; return QCE_ERR_INVALID_VALUE; }
+    DeviceGuard g(device);
+    if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
+        hipMalloc(&h->fid_partials, sizeof(double) * 4 * kFidBlocks) != hipSuccess) {
+        (void)hipGetLastError();
+        if (h->st) (void)hipFree(h->st);
+        delete h;
+        return QCE_ERR_ALLOC;
+    }
+    if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(h->st);
+        (void)hipFree(h->fid_partials);
+        delete h;
+        return QCE_ERR_HIP;
+    }
+    *out = h;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_destroy(qce_handle *h) {
+    if (!h) return QCE_SUCCESS;
+    DeviceGuard g(h->device);
+    qce_status rc = QCE_SUCCESS;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = QCE_ERR_HIP;
+    if (h->ws && h->ws_owned) (void)hipFree(h->ws);
+    (void)hipFree(h->st);
+    (void)hipFree(h->fid_partials);
+    delete h;
+    return rc;
+}
+
+qce_status qce_set_stream(qce_handle *h, void *stream) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    DeviceGuard g(h->device);
+    hipStream_t ns = static_cast<hipStream_t>(stream);
+    if (ns != h->stream) QCE_HIP(h, hipStreamSynchronize(h->stream));
+    h->stream = ns;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_mode(qce_handle *h, qce_mode m) {
+    if (!h || (int)m < QCE_MODE_FP16X2 || (int)m > QCE_MODE_AUTO) return QCE_ERR_INVALID_VALUE;
+    h->mode = m;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_get_mode(const qce_handle *h, qce_mode *m) {
+    if (!h || !m) return QCE_ERR_INVALID_VALUE;
+    *m = h->mode;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_underflow_tolerance(qce_handle *h, double t, double t3) {
+    if (!h || !(t >= 0 && t <= 1) || !(t3 >= 0 && t3 <= 1)) return QCE_ERR_INVALID_VALUE;
+    h->t = t;
+    h->t3 = t3;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min) {
+    if (!h || emul_min < 0 || emul_min > auto_min) return QCE_ERR_INVALID_VALUE;
+    h->auto_min = auto_min;
+    h->emul_min = emul_min;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_workspace(qce_handle *h, void *ptr, size_t bytes) {
+    if (!h || (ptr == nullptr) != (bytes == 0)) return QCE_ERR_INVALID_VALUE;
+    DeviceGuard g(h->device);
+    if (h->ws && h->ws_owned) {
+        QCE_HIP(h, hipStreamSynchronize(h->stream));
+        QCE_HIP(h, hipFree(h->ws));
+    }
+    h->ws = ptr;
+    h->ws_bytes = bytes;
+    h->ws_owned = ptr == nullptr;
+    return QCE_SUCCESS;
+}
+
+size_t qce_cgemm_workspace_size(int64_t m, int64_t n, int64_t k) {
+    if (m <= 0 || n <= 0 || k < 0) return 0;
+    return cgemm_ws_bytes(m, n, k);
+}
+
+qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                              int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                              const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
+                              int64_t ldc) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (!valid_op(opA) || !valid_op(opB)) return fail(h, QCE_ERR_INVALID_VALUE, "bad op");
+    if (m < 0 || n < 0 || k < 0) return fail(h, QCE_ERR_INVALID_VALUE, "negative size");
+    const int64_t arows = opA == QCE_OP_N ? m : k, brows = opB == QCE_OP_N ? k : n;
+    if (lda < std::max<int64_t>(1, arows) || ldb < std::max<int64_t>(1, brows) ||
+        ldc < std::max<int64_t>(1, m))
+        return fail(h, QCE_ERR_INVALID_VALUE, "leading dimension too small");
+    if (m == 0 || n == 0) return QCE_SUCCESS;
+    if (!C || (k > 0 && (!A || !B))) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
+         reinterpret_cast<uintptr_t>(C)) & 7)
+        return fail(h, QCE_ERR_INVALID_VALUE, "pointer not 8-byte aligned");
+    DeviceGuard g(h->device);
+    const float2 al = alpha ? make_float2(alpha->re, alpha->im) : make_float2(1.f, 0.f);
+    const float2 be = beta ? make_float2(beta->re, beta->im) : make_float2(0.f, 0.f);
+    qce_status st = ensure_ws(h, cgemm_ws_bytes(m, n, k));
+    if (st != QCE_SUCCESS) return st;
+    OperandView va{reinterpret_cast<const float2 *>(A), lda, opA != QCE_OP_N, opA == QCE_OP_C};
+    OperandView vb{reinterpret_cast<const float2 *>(B), ldb, opB == QCE_OP_N, opB == QCE_OP_C};
+    return cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
+                      static_cast<char *>(h->ws));
+}
+
+qce_status qce_get_last_decision(qce_handle *h, qce_decision *out) {
+    if (!h || !out) return QCE_ERR_INVALID_VALUE;
+    if (!h->have_decision) return fail(h, QCE_ERR_INVALID_VALUE, "no GEMM has run on this handle");
+    DeviceGuard g(h->device);
+    QCE_HIP(h, hipStreamSynchronize(h->stream));
+    if (h->last_on_device) {
+        QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
+    } else {
+        *out = h->last_host;
+    }
+    return QCE_SUCCESS;
+}
+
+qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t cols, int64_t ld,
+                        qce_decision *out) {
+    if (!h || !out) return QCE_ERR_INVALID_VALUE;
+    if (rows < 0 || cols < 0 || ld < std::max<int64_t>(1, rows) || (rows * cols > 0 && !X))
+        return fail(h, QCE_ERR_INVALID_VALUE, "bad matrix");
+    DeviceGuard g(h->device);
+    hipStream_t s = h->stream;
+    MatDesc a{reinterpret_cast<const float2 *>(X), rows, cols, ld};
+    MatDesc none{nullptr, 0, 0, 1};
+    if (h->stats_dirty) QCE_HIP(h, launch_stats_clear(h->st, s));
+    h->stats_dirty = true;
+    QCE_HIP(h, launch_stats1(a, none, h->st, s));
+    QCE_HIP(h, launch_stats2(a, none, h->st, h->t, 2, s));
+    QCE_HIP(h, launch_select(h->st, h->t, h->t3, -2, s));
+    h->stats_dirty = false;
+    QCE_HIP(h, hipStreamSynchronize(s));
+    QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
+    return QCE_SUCCESS;
+}
+
+qce_status qce_split(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 *x, int64_t n,
+                     uint16_t *planes) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (mode != QCE_MODE_FP16X2 && mode != QCE_MODE_BF16X3)
+        return fail(h, QCE_ERR_NOT_SUPPORTED, "split is defined for FP16X2 and BF16X3");
+    if (n < 0 || (n > 0 && (!x || !planes))) return fail(h, QCE_ERR_INVALID_VALUE, "bad buffers");
+    if (mode == QCE_MODE_BF16X3 && shift != 0) return fail(h, QCE_ERR_INVALID_VALUE, "BF16X3 takes no shift");
+    DeviceGuard g(h->device);
+    QCE_HIP(h, launch_split_planar(mode, shift, reinterpret_cast<const float2 *>(x), n, planes, h->stream));
+    return QCE_SUCCESS;
+}
+
+qce_status qce_permute(qce_handle *h, const qce_tensor *x, const void *X, const int32_t *perm,
+                       void *Y) {
+    if (!h || !x || x->rank < 0 || (x->rank > 0 && (!x->extents || !perm)))
+        return QCE_ERR_INVALID_VALUE;
+    if (x->rank > 64) return fail(h, QCE_ERR_NOT_SUPPORTED, "rank above 64");
+    int64_t n = 0;
+    if (!checked_numel(x->rank, x->extents, n)) return fail(h, QCE_ERR_INVALID_VALUE, "bad extents");
+    std::vector<char> seen(x->rank, 0);
+    for (int a = 0; a < x->rank; ++a) {
+        if (perm[a] < 0 || perm[a] >= x->rank || seen[perm[a]])
+            return fail(h, QCE_ERR_INVALID_VALUE, "not a permutation");
+        seen[perm[a]] = 1;
+    }
+    if (!X || !Y) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
+    DeviceGuard g(h->device);
+    return run_permute(h, x->rank, x->extents, perm, static_cast<const float2 *>(X),
+                       static_cast<float2 *>(Y));
+}
+
+qce_status qce_accumulate_f64(qce_handle *h, const qce_c32 *src, double *acc2) {
+    if (!h || !src || !acc2) return QCE_ERR_INVALID_VALUE;
+    DeviceGuard g(h->device);
+    QCE_HIP(h, launch_accumulate_f64(reinterpret_cast<const float2 *>(src), acc2, h->stream));
+    return QCE_SUCCESS;
+}
+
+qce_status qce_fidelity_f64(qce_handle *h, const qce_c32 *a, const qce_c32 *b, int64_t n,
+                            double *out4) {
+    if (!h || !out4 || n < 0 || (n > 0 && (!a || !b))) return QCE_ERR_INVALID_VALUE;
+    DeviceGuard g(h->device);
+    int nb = (int)std::min<int64_t>(kFidBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    QCE_HIP(h, launch_fidelity_f64(reinterpret_cast<const float2 *>(a), reinterpret_cast<const float2 *>(b),
+                                   n, h->fid_partials, nb, out4, h->stream));
+    return QCE_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Tensor contraction by TTGT.
+// ---------------------------------------------------------------------------
+qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const int32_t *la,
+                        const qce_tensor *b, const void *B, const int32_t *lb,
+                        const qce_tensor *c, void *C, const int32_t *lc) {
+    if (!h || !a || !b || !c) return QCE_ERR_INVALID_VALUE;
+    const int ra = a->rank, rb = b->rank, rc = c->rank;
+    if (ra < 0 || rb < 0 || rc < 0 || ra > 64 || rb > 64 || rc > 64)
+        return fail(h, QCE_ERR_INVALID_VALUE, "bad rank");
+    if ((ra && (!a->extents || !la)) || (rb && (!b->extents || !lb)) || (rc && (!c->extents || !lc)))
+        return fail(h, QCE_ERR_INVALID_VALUE, "missing extents or labels");
+    int64_t na, nb_, nc;
+    if (!checked_numel(ra, a->extents, na) || !checked_numel(rb, b->extents, nb_) ||
+        !checked_numel(rc, c->extents, nc))
+        return fail(h, QCE_ERR_INVALID_VALUE, "bad extents");
+    if (!A || !B || !C) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & 7)
+        return fail(h, QCE_ERR_INVALID_VALUE, "pointer not 8-byte aligned");
+    auto find = [](const int32_t *l, int r, int32_t x) {
+        for (int i = 0; i < r; ++i)
+            if (l[i] == x) return i;
+        return -1;
+    };
+    auto unique = [&](const int32_t *l, int r) {
+        for (int i = 0; i < r; ++i)
+            if (find(l, i, l[i]) >= 0) return false;
+        return true;
+    };
+    if (!unique(la, ra) || !unique(lb, rb) || !unique(lc, rc))
+        return fail(h, QCE_ERR_INVALID_VALUE, "duplicate label within a tensor");
+    std::vector<int32_t> K, FA, FB;  // labels in A's / B's order
+    for (int i = 0; i < ra; ++i) {
+        const int jb = find(lb, rb, la[i]), jc = find(lc, rc, la[i]);
+        if (jb >= 0) {
+            if (a->extents[i] != b->extents[jb]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
+            if (jc >= 0) return fail(h, QCE_ERR_NOT_SUPPORTED, "batch label %d", la[i]);
+            K.push_back(la[i]);
+        } else {
+            if (jc < 0) return fail(h, QCE_ERR_NOT_SUPPORTED, "label %d summed over one input", la[i]);
+            if (c->extents[jc] != a->extents[i]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
+            FA.push_back(la[i]);
+        }
+    }
+    for (int i = 0; i < rb; ++i) {
+        if (find(la, ra, lb[i]) >= 0) continue;
+        const int jc = find(lc, rc, lb[i]);
+        if (jc < 0) return fail(h, QCE_ERR_NOT_SUPPORTED, "label %d summed over one input", lb[i]);
+        if (c->extents[jc] != b->extents[i]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
+        FB.push_back(lb[i]);
+    }
+    if ((int)(FA.size() + FB.size()) != rc) return fail(h, QCE_ERR_INVALID_VALUE, "output label not in any input");
+
+    auto ext_of = [&](int32_t lab) -> int64_t {
+        int i = find(la, ra, lab);
+        if (i >= 0) return a->extents[i];
+        return b->extents[find(lb, rb, lab)];
+    };
+    auto prod = [&](const std::vector<int32_t> &ls) {
+        int64_t p = 1;
+        for (int32_t x : ls) p *= ext_of(x);
+        return p;
+    };
+    const int64_t kk = prod(K), ma = prod(FA), nb = prod(FB);
+
+    // Output: C row-major with labels lc.  As a column-major matrix it is
+    // m x n when lc = [free labels of the "GEMM-B" operand][free labels of
+    // the "GEMM-A" operand].  Try both roles; otherwise compute into a
+    // temporary [FB (B order)][FA (A order)] and permute.
+    auto is_set_block = [&](int off, int len, const std::vector<int32_t> &set) {
+        if (len != (int)set.size()) return false;
+        for (int i = 0; i < len; ++i)
+            if (std::find(set.begin(), set.end(), lc[off + i]) == set.end()) return false;
+        return true;
+    };
+    bool swap = false, out_perm = false;
+    std::vector<int32_t> SA, SB;  // free-label order required of GEMM-A / GEMM-B operand
+    if (is_set_block(rc - (int)FA.size(), (int)FA.size(), FA) && is_set_block(0, (int)FB.size(), FB)) {
+        SA.assign(lc + rc - FA.size(), lc + rc);
+        SB.assign(lc, lc + FB.size());
+    } else if (is_set_block(rc - (int)FB.size(), (int)FB.size(), FB) && is_set_block(0, (int)FA.size(), FA)) {
+        swap = true;
+        SA.assign(lc + rc - FB.size(), lc + rc);
+        SB.assign(lc, lc + FA.size());
+    } else {
+        out_perm = true;
+        SA = FA;
+        SB = FB;
+    }
+    // GEMM-A = (swap ? B : A), GEMM-B = the other.
+    const int32_t *lx = swap ? lb : la, *ly = swap ? la : lb;
+    const int rx = swap ? rb : ra, ry = swap ? ra : rb;
+    const void *X = swap ? B : A, *Y = swap ? A : B;
+    const int64_t *ex = swap ? b->extents : a->extents, *ey = swap ? a->extents : b->extents;
+    const int64_t m = swap ? nb : ma, n = swap ? ma : nb;
+
+    // Does operand (labels l) hold [K][F] or [F][K] with the given orders?
+    auto layout = [&](const int32_t *l, int r, const std::vector<int32_t> &korder,
+                      const std::vector<int32_t> &forder) -> int {
+        // 0: [K][F], 1: [F][K], -1: neither
+        bool kf = true, fk = true;
+        const int nk = (int)korder.size(), nf = (int)forder.size();
+        for (int i = 0; i < r; ++i) {
+            if (i < nk ? l[i] != korder[i] : l[i] != forder[i - nk]) kf = false;
+            if (i < nf ? l[i] != forder[i] : l[i] != korder[i - nf]) fk = false;
+        }
+        return kf ? 0 : (fk ? 1 : -1);
+    };
+    auto korder_of = [&](const int32_t *l, int r) {
+        std::vector<int32_t> ko;
+        for (int i = 0; i < r; ++i)
+            if (std::find(K.begin(), K.end(), l[i]) != K.end()) ko.push_back(l[i]);
+        return ko;
+    };
+    // choose the K order (from X or from Y) that permutes fewer elements
+    std::vector<int32_t> kx = korder_of(lx, rx), ky = korder_of(ly, ry);
+    int64_t sx = 1, sy = 1;
+    for (int i = 0; i < rx; ++i) sx *= ex[i];
+    for (int i = 0; i < ry; ++i) sy *= ey[i];
+    auto cost = [&](const std::vector<int32_t> &ko) {
+        int64_t c0 = 0;
+        if (layout(lx, rx, ko, SA) < 0) c0 += sx;
+        if (layout(ly, ry, ko, SB) < 0) c0 += sy;
+        return c0;
+    };
+    const std::vector<int32_t> korder = cost(kx) <= cost(ky) ? kx : ky;
+    const int lay_x = layout(lx, rx, korder, SA), lay_y = layout(ly, ry, korder, SB);
+
+    // workspace: panels | permuted X | permuted Y | temporary C
+    size_t off = align256(cgemm_ws_bytes(m, n, kk));
+    const size_t offx = off;
+    if (lay_x < 0) off += align256((size_t)sx * 8);
+    const size_t offy = off;
+    if (lay_y < 0) off += align256((size_t)sy * 8);
+    const size_t offc = off;
+    if (out_perm) off += align256((size_t)nc * 8);
+    DeviceGuard g(h->device);
+    qce_status st = ensure_ws(h, off);
+    if (st != QCE_SUCCESS) return st;
+    char *ws = static_cast<char *>(h->ws);
+
+    auto permute_to_kf = [&](const int32_t *l, int r, const int64_t *e, const void *src,
+                             const std::vector<int32_t> &forder, void *dst) -> qce_status {
+        std::vector<int32_t> perm;
+        for (int32_t lab : korder) perm.push_back(find(l, r, lab));
+        for (int32_t lab : forder) perm.push_back(find(l, r, lab));
+        return run_permute(h, r, e, perm.data(), static_cast<const float2 *>(src),
+                           reinterpret_cast<float2 *>(dst));
+    };
+    OperandView vx, vy;
+    if (lay_x < 0) {
+        st = permute_to_kf(lx, rx, ex, X, SA, ws + offx);
+        if (st != QCE_SUCCESS) return st;
+        vx = OperandView{reinterpret_cast<const float2 *>(ws + offx), std::max<int64_t>(1, m), false, false};
+    } else if (lay_x == 0) {  // [K][F]: column-major m x k
+        vx = OperandView{static_cast<const float2 *>(X), std::max<int64_t>(1, m), false, false};
+    } else {  // [F][K]: column-major k x m
+        vx = OperandView{static_cast<const float2 *>(X), std::max<int64_t>(1, kk), true, false};
+    }
+    if (lay_y < 0) {
+        st = permute_to_kf(ly, ry, ey, Y, SB, ws + offy);
+        if (st != QCE_SUCCESS) return st;
+        vy = OperandView{reinterpret_cast<const float2 *>(ws + offy), std::max<int64_t>(1, n), false, false};
+    } else if (lay_y == 0) {  // [K][F]: rows j contiguous: P[j][l] = y[j + l*n]
+        vy = OperandView{static_cast<const float2 *>(Y), std::max<int64_t>(1, n), false, false};
+    } else {  // [F][K]: P[j][l] = y[l + j*k]
+        vy = OperandView{static_cast<const float2 *>(Y), std::max<int64_t>(1, kk), true, false};
+    }
+    int mode = h->mode;
+    if (mode == QCE_MODE_AUTO) {
+        const int64_t mn = std::min(std::min(m, n), kk);
+        if (mn >= h->auto_min) mode = QCE_MODE_AUTO;
+        else if (mn >= h->emul_min) mode = QCE_MODE_BF16X3;
+        else mode = QCE_MODE_FP32;
+    }
+    float2 *Cg = out_perm ? reinterpret_cast<float2 *>(ws + offc) : static_cast<float2 *>(C);
+    st = cgemm_core(h, mode, vx, vy, m, n, kk, make_float2(1.f, 0.f), make_float2(0.f, 0.f), Cg,
+                    std::max<int64_t>(1, m), ws);
+    if (st != QCE_SUCCESS) return st;
+    if (out_perm) {
+        // temporary has labels [SB][SA] (row-major); permute to lc
+        std::vector<int32_t> tl(SB);
+        tl.insert(tl.end(), SA.begin(), SA.end());
+        std::vector<int64_t> te;
+        for (int32_t lab : tl) te.push_back(ext_of(lab));
+        std::vector<int32_t> perm;
+        for (int i = 0; i < rc; ++i) perm.push_back(find(tl.data(), rc, lc[i]));
+        st = run_permute(h, rc, te.data(), perm.data(), Cg, static_cast<float2 *>(C));
+        if (st != QCE_SUCCESS) return st;
+    }
+    return QCE_SUCCESS;
+}
+
+}  // extern "C"

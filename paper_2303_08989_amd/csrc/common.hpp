@@ -1,0 +1,151 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qcemu.h"
+
+namespace qce {
+
+// ---------------------------------------------------------------------------
+// Device-side statistics and decision (the paper's "exp stats buffer" and
+// "mode flag buffer", Sec. 4.2).
+// ---------------------------------------------------------------------------
+struct OperandStats {
+    unsigned long long nnz;        // nonzero finite components
+    unsigned long long n1;         // floor(log2|v|) >= -14
+    unsigned long long n2;         // floor(log2|v|) >= emax - 28 (stage 2)
+    unsigned long long n3;         // floor(log2|v|) >= -110
+    unsigned long long nonfinite;  // Inf / NaN
+    unsigned int maxbits;          // largest |v| bit pattern among finite v
+    unsigned int pad;
+};
+
+struct DevState {
+    OperandStats acc[2];  // accumulated by the statistics kernels, cleared by select
+    int mode;             // selected qce_mode (never AUTO)
+    int shift[2];         // power-of-two shifts sA, sB
+    int stage2[2];        // 1 if stage 2 ran for that operand
+    int pad;
+    qce_decision last;    // record of the last decision
+};
+
+// Bit patterns of |v| thresholds (positive FP32 bit patterns order like values).
+constexpr unsigned int kInfBits = 0x7f800000u;
+constexpr unsigned int kFp16MinNormalBits = 113u << 23;  // 2^-14
+constexpr unsigned int kBf16x3FloorBits = 17u << 23;     // 2^-110
+constexpr int kFp16Emax = 14;
+constexpr int kFp16Emin = -14;
+constexpr int kBf16x3Emin = -110;
+constexpr int kBf16x3Emax = 126;
+constexpr int kWindowSpan = kFp16Emax - kFp16Emin;  // 28: FP16 window [-14, 14]
+
+// ---------------------------------------------------------------------------
+// Panel geometry.  Each GEMM operand is rewritten by the split kernel into
+// "panels": for a block of kPanelRows rows (rows of op(A) or columns of
+// op(B)) and a block of BK k-values, one contiguous chunk laid out as
+// [plane][row][k] with the k-values of a row in 16-byte granules whose
+// position is XOR-swizzled by row (bank-conflict-free fragment reads).
+// Rows and k beyond the matrix are zero.
+// ---------------------------------------------------------------------------
+constexpr int kPanelRows = 128;
+
+template <int MODE> struct PanelFmt;
+// FP16X2: planes hi(re), lo(re), hi(im), lo(im); FP16; 32 k per chunk.
+template <> struct PanelFmt<QCE_MODE_FP16X2> {
+    static constexpr int kPlanes = 4, kBK = 32, kElemBytes = 2;
+};
+// BF16X3: planes b0(re), b1(re), b2(re), b0(im), b1(im), b2(im); 16 k per chunk.
+template <> struct PanelFmt<QCE_MODE_BF16X3> {
+    static constexpr int kPlanes = 6, kBK = 16, kElemBytes = 2;
+};
+// FP32: planes re, im; 16 k per chunk.
+template <> struct PanelFmt<QCE_MODE_FP32> {
+    static constexpr int kPlanes = 2, kBK = 16, kElemBytes = 4;
+};
+
+template <int MODE> struct PanelGeom {
+    using F = PanelFmt<MODE>;
+    static constexpr int kRowBytes = F::kBK * F::kElemBytes;          // 64 or 32
+    static constexpr int kGranules = kRowBytes / 16;                  // 4 or 2
+    static constexpr int kPlaneBytes = kPanelRows * kRowBytes;
+    static constexpr int kChunkBytes = F::kPlanes * kPlaneBytes;
+    static constexpr int kKPerGranule = 16 / F::kElemBytes;           // 8 or 4
+    __host__ __device__ static constexpr int swz(int row) {
+        return kGranules == 4 ? ((row >> 1) & 3) : ((row >> 2) & 1);
+    }
+    // byte offset of (plane, row, granule) inside a chunk
+    __host__ __device__ static constexpr int offset(int plane, int row, int granule) {
+        return plane * kPlaneBytes + row * kRowBytes + ((granule ^ swz(row)) << 4);
+    }
+};
+
+// k is padded to a multiple of this for every mode (lcm of the BK values).
+constexpr int kKPad = 32;
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Bytes of the panel buffer of one operand with `rows` rows and k values,
+// large enough for every mode.
+inline size_t panel_bytes(int64_t rows, int64_t k) {
+    int64_t r = round_up(rows, kPanelRows), kk = round_up(k, kKPad);
+    return (size_t)r * (size_t)kk * 12u;  // BF16X3: 6 planes x 2 bytes
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers implemented in the .hip files.
+// ---------------------------------------------------------------------------
+struct MatDesc {  // a stored column-major complex64 matrix
+    const float2 *ptr;
+    int64_t rows, cols, ld;
+};
+
+hipError_t launch_stats_clear(DevState *st, hipStream_t s);
+hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s);
+hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int skip,
+                         hipStream_t s);
+hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, hipStream_t s);
+
+// Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
+// kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:
+// mode and shift come from the device decision (operand index `which`);
+// otherwise forced_mode / shift.
+hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int conj, int64_t rows,
+                               int64_t k, void *panels, const DevState *st, int which,
+                               int forced_mode, int shift, hipStream_t s);
+
+struct GemmArgs {
+    const void *panelsA;  // rows = m
+    const void *panelsB;  // rows = n
+    int64_t m, n, k;
+    float2 *C;
+    int64_t ldc;
+    float2 alpha, beta;
+    int beta_zero;
+    const DevState *st;  // nullable: forced mode
+    int forced_mode;
+};
+hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
+
+hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,
+                          hipStream_t s);
+
+struct PermDesc {
+    int rank;            // merged rank, <= kMaxRank
+    int pow2;            // all extents powers of two
+    int64_t ext[32];     // output extents (merged)
+    int64_t istride[32]; // input stride of each output axis
+    int log2ext[32];
+};
+constexpr int kMaxRank = 32;
+hipError_t launch_permute(const float2 *x, float2 *y, int64_t total, const PermDesc &d,
+                          hipStream_t s);
+
+hipError_t launch_accumulate_f64(const float2 *src, double *acc2, hipStream_t s);
+hipError_t launch_fidelity_f64(const float2 *a, const float2 *b, int64_t n, double *partials,
+                               int nblocks, double *out4, hipStream_t s);
+hipError_t launch_split_planar(int mode, int shift, const float2 *x, int64_t n, uint16_t *planes,
+                               hipStream_t s);
+
+}  // namespace qce

@@ -1,0 +1,380 @@
+// Complex GEMM on gfx950 matrix cores over split panels.
+//
+// C = alpha * op(A) op(B) + beta * C with the complex product written as four
+// real products (Sec. 3): Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br.  Each real
+// product is emulated from the split parts (Sec. 2.1, Eq. 2):
+//   FP16X2:  hi*hi + (lo*hi + hi*lo) / 2^11        (3 MFMA products)
+//   BF16X3:  b0*c0 + (b0*c1 + b1*c0 + b0*c2 + b1*c1 + b2*c0)   (6 products)
+//   FP32:    x*y on the FP32 matrix instruction (the plain baseline)
+// The leading product and the correction products go to separate FP32
+// accumulators and are combined in the epilogue.  gfx950's f16/bf16 MFMA
+// sums each instruction's products exactly and rounds once to nearest even
+// (measured), so the leading term needs no separate round-to-nearest
+// accumulation step (the paper's workaround for round-toward-zero inside the
+// Tensor Core, Sec. 2.1).
+//
+// Mapping: the MFMA "A" operand is read from the op(B) panels (rows j) and
+// the MFMA "B" operand from the op(A) panels (rows i), so D[j][i] = C[i][j]
+// and the 32 lanes of an output row of a 32x32 MFMA block hold 32 consecutive
+// rows i of column-major C: coalesced stores.
+//
+// One workgroup = 4 waves = a 128 x 128 complex tile; each wave owns 64 x 64
+// (2 x 2 blocks of 32 x 32).  K advances one panel chunk per iteration with
+// two LDS stages: global loads of chunk k+1 are issued before the MFMAs of
+// chunk k and written to the other stage afterwards.
+//
+// Device-side dispatch (Sec. 4.2): every kernel reads the mode flag at entry
+// and returns at once unless it is the selected mode.
+#include "common.hpp"
+
+namespace qce {
+
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kTile = 128;
+
+__device__ inline u32x4 neg_halves(u32x4 v) { return v ^ 0x80008000u; }
+
+__device__ inline floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a),
+                                                  __builtin_bit_cast(half8, b), c, 0, 0, 0);
+}
+__device__ inline floatx16 mfmab(u32x4 a, u32x4 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ inline floatx16 mfma32(float a, float b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Tile order: consecutive workgroup ids are dispatched round-robin over the
+// 8 XCDs (each with its own L2).  Remap so that each XCD receives a
+// contiguous range of tile ids, and walk tiles in groups of kGroupM tile-rows
+// so that concurrently running tiles share A and B panels.
+constexpr int kXcds = 8;
+constexpr int kGroupM = 8;
+
+__device__ inline void tile_of(int bid, int nbm, int nbn, int &mb, int &nb) {
+    const int total = nbm * nbn;
+    const int q = total / kXcds, rem = total % kXcds;
+    const int x = bid % kXcds, local = bid / kXcds;
+    const int id = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
+    const int group = kGroupM * nbn;
+    const int g = id / group;
+    const int first = g * kGroupM;
+    const int gm = min(nbm - first, kGroupM);
+    const int in = id % group;
+    mb = first + in % gm;
+    nb = in / gm;
+}
+
+template <int MODE> struct Acc;
+template <> struct Acc<QCE_MODE_FP16X2> { floatx16 re_m[2][2], im_m[2][2], re_c[2][2], im_c[2][2]; };
+template <> struct Acc<QCE_MODE_BF16X3> { floatx16 re_m[2][2], im_m[2][2], re_c[2][2], im_c[2][2]; };
+template <> struct Acc<QCE_MODE_FP32> { floatx16 re_m[2][2], im_m[2][2]; };
+
+// one chunk of FP16X2 panels in LDS: 2 k16 steps
+__device__ __attribute__((always_inline)) inline void compute_fp16x2(const char *sx, const char *sy, int wu, int wv, int lane,
+                                      Acc<QCE_MODE_FP16X2> &acc) {
+    using G = PanelGeom<QCE_MODE_FP16X2>;
+    const int l32 = lane & 31, hi = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int gr = 2 * ks + hi;
+        u32x4 x[2][4], y[2][4], nxi[2][2];
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub) {
+            const int row = wu * 64 + ub * 32 + l32;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) x[ub][p] = *reinterpret_cast<const u32x4 *>(sx + G::offset(p, row, gr));
+            nxi[ub][0] = neg_halves(x[ub][2]);
+            nxi[ub][1] = neg_halves(x[ub][3]);
+        }
+#pragma unroll
+        for (int vb = 0; vb < 2; ++vb) {
+            const int row = wv * 64 + vb * 32 + l32;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) y[vb][p] = *reinterpret_cast<const u32x4 *>(sy + G::offset(p, row, gr));
+        }
+        // planes: 0 = hi(re), 1 = lo(re), 2 = hi(im), 3 = lo(im)
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub)
+#pragma unroll
+            for (int vb = 0; vb < 2; ++vb) {
+                acc.re_c[ub][vb] = mfma16(x[ub][1], y[vb][0], acc.re_c[ub][vb]);
+                acc.re_c[ub][vb] = mfma16(x[ub][0], y[vb][1], acc.re_c[ub][vb]);
+                acc.re_c[ub][vb] = mfma16(nxi[ub][1], y[vb][2], acc.re_c[ub][vb]);
+                acc.re_c[ub][vb] = mfma16(nxi[ub][0], y[vb][3], acc.re_c[ub][vb]);
+                acc.im_c[ub][vb] = mfma16(x[ub][1], y[vb][2], acc.im_c[ub][vb]);
+                acc.im_c[ub][vb] = mfma16(x[ub][0], y[vb][3], acc.im_c[ub][vb]);
+                acc.im_c[ub][vb] = mfma16(x[ub][3], y[vb][0], acc.im_c[ub][vb]);
+                acc.im_c[ub][vb] = mfma16(x[ub][2], y[vb][1], acc.im_c[ub][vb]);
+                acc.re_m[ub][vb] = mfma16(x[ub][0], y[vb][0], acc.re_m[ub][vb]);
+                acc.re_m[ub][vb] = mfma16(nxi[ub][0], y[vb][2], acc.re_m[ub][vb]);
+                acc.im_m[ub][vb] = mfma16(x[ub][0], y[vb][2], acc.im_m[ub][vb]);
+                acc.im_m[ub][vb] = mfma16(x[ub][2], y[vb][0], acc.im_m[ub][vb]);
+            }
+    }
+}
+
+// one chunk of BF16X3 panels in LDS: 1 k16 step
+__device__ __attribute__((always_inline)) inline void compute_bf16x3(const char *sx, const char *sy, int wu, int wv, int lane,
+                                      Acc<QCE_MODE_BF16X3> &acc) {
+    using G = PanelGeom<QCE_MODE_BF16X3>;
+    const int l32 = lane & 31, gr = lane >> 5;
+    // planes: 0..2 = b0, b1, b2 of re; 3..5 = b0, b1, b2 of im
+    u32x4 x[2][6], y[2][6], nxi[2][3];
+#pragma unroll
+    for (int ub = 0; ub < 2; ++ub) {
+        const int row = wu * 64 + ub * 32 + l32;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) x[ub][p] = *reinterpret_cast<const u32x4 *>(sx + G::offset(p, row, gr));
+#pragma unroll
+        for (int p = 0; p < 3; ++p) nxi[ub][p] = neg_halves(x[ub][3 + p]);
+    }
+#pragma unroll
+    for (int vb = 0; vb < 2; ++vb) {
+        const int row = wv * 64 + vb * 32 + l32;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) y[vb][p] = *reinterpret_cast<const u32x4 *>(sy + G::offset(p, row, gr));
+    }
+#pragma unroll
+    for (int ub = 0; ub < 2; ++ub)
+#pragma unroll
+        for (int vb = 0; vb < 2; ++vb) {
+            // corrections, smallest first: (2,0) (1,1) (0,2) (1,0) (0,1)
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                const int i = t == 0 ? 2 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 1 : 0;
+                const int j = t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 2 : t == 3 ? 0 : 1;
+                acc.re_c[ub][vb] = mfmab(x[ub][i], y[vb][j], acc.re_c[ub][vb]);
+                acc.re_c[ub][vb] = mfmab(nxi[ub][i], y[vb][3 + j], acc.re_c[ub][vb]);
+                acc.im_c[ub][vb] = mfmab(x[ub][i], y[vb][3 + j], acc.im_c[ub][vb]);
+                acc.im_c[ub][vb] = mfmab(x[ub][3 + i], y[vb][j], acc.im_c[ub][vb]);
+            }
+            acc.re_m[ub][vb] = mfmab(x[ub][0], y[vb][0], acc.re_m[ub][vb]);
+            acc.re_m[ub][vb] = mfmab(nxi[ub][0], y[vb][3], acc.re_m[ub][vb]);
+            acc.im_m[ub][vb] = mfmab(x[ub][0], y[vb][3], acc.im_m[ub][vb]);
+            acc.im_m[ub][vb] = mfmab(x[ub][3], y[vb][0], acc.im_m[ub][vb]);
+        }
+}
+
+// one chunk of FP32 panels in LDS: 16 k-values.  Each lane reads four
+// consecutive k-values per row; MFMA step j takes value j, so lanes 0-31 and
+// 32-63 supply k = 8s + j and 8s + 4 + j (the same pairing for both
+// operands, so every k is summed once).
+__device__ __attribute__((always_inline)) inline void compute_fp32(const char *sx, const char *sy, int wu, int wv, int lane,
+                                    Acc<QCE_MODE_FP32> &acc) {
+    using G = PanelGeom<QCE_MODE_FP32>;
+    const int l32 = lane & 31, hi = lane >> 5;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int gr = 2 * s + hi;
+        f32x4 xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub) {
+            const int row = wu * 64 + ub * 32 + l32;
+            xr[ub] = *reinterpret_cast<const f32x4 *>(sx + G::offset(0, row, gr));
+            xi[ub] = *reinterpret_cast<const f32x4 *>(sx + G::offset(1, row, gr));
+        }
+#pragma unroll
+        for (int vb = 0; vb < 2; ++vb) {
+            const int row = wv * 64 + vb * 32 + l32;
+            yr[vb] = *reinterpret_cast<const f32x4 *>(sy + G::offset(0, row, gr));
+            yi[vb] = *reinterpret_cast<const f32x4 *>(sy + G::offset(1, row, gr));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int ub = 0; ub < 2; ++ub)
+#pragma unroll
+                for (int vb = 0; vb < 2; ++vb) {
+                    const float a_r = xr[ub][j], a_i = xi[ub][j];
+                    const float b_r = yr[vb][j], b_i = yi[vb][j];
+                    acc.re_m[ub][vb] = mfma32(a_r, b_r, acc.re_m[ub][vb]);
+                    acc.re_m[ub][vb] = mfma32(-a_i, b_i, acc.re_m[ub][vb]);
+                    acc.im_m[ub][vb] = mfma32(a_r, b_i, acc.im_m[ub][vb]);
+                    acc.im_m[ub][vb] = mfma32(a_i, b_r, acc.im_m[ub][vb]);
+                }
+    }
+}
+
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void compute_chunk(const char *sx, const char *sy, int wu, int wv, int lane,
+                                     Acc<MODE> &acc) {
+    if constexpr (MODE == QCE_MODE_FP16X2) compute_fp16x2(sx, sy, wu, wv, lane, acc);
+    else if constexpr (MODE == QCE_MODE_BF16X3) compute_bf16x3(sx, sy, wu, wv, lane, acc);
+    else compute_fp32(sx, sy, wu, wv, lane, acc);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
+    const int mode = g.st ? g.st->mode : g.forced_mode;
+    if constexpr (MODE == QCE_MODE_FP16X2) {
+        if (mode != QCE_MODE_FP16X2 && mode != QCE_MODE_FP16X2_SCALED) return;
+    } else {
+        if (mode != MODE) return;
+    }
+    int shift_total = 0;
+    if (MODE == QCE_MODE_FP16X2 && mode == QCE_MODE_FP16X2_SCALED && g.st)
+        shift_total = g.st->shift[0] + g.st->shift[1];
+
+    using G = PanelGeom<MODE>;
+    constexpr int kCB = G::kChunkBytes;
+    constexpr int kLoads = kCB / (16 * kThreads);  // uint4 loads per thread per operand
+    __shared__ __attribute__((aligned(16))) char smem[2][2][kCB];
+
+    int mb, nb;
+    tile_of(blockIdx.x, nbm, nbn, mb, nb);
+    const int64_t kpad = round_up(g.k, kKPad);
+    const int nkb = (int)(kpad / PanelFmt<MODE>::kBK);
+    const char *px = static_cast<const char *>(g.panelsB) + (int64_t)nb * nkb * kCB;
+    const char *py = static_cast<const char *>(g.panelsA) + (int64_t)mb * nkb * kCB;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wu = w >> 1, wv = w & 1;
+
+    Acc<MODE> acc;
+    {
+        floatx16 z;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) z[r] = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc.re_m[a][b] = z;
+                acc.im_m[a][b] = z;
+                if constexpr (MODE != QCE_MODE_FP32) {
+                    acc.re_c[a][b] = z;
+                    acc.im_c[a][b] = z;
+                }
+            }
+    }
+
+    u32x4 rx[kLoads], ry[kLoads];
+    if (nkb > 0) {
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) {
+            rx[i] = reinterpret_cast<const u32x4 *>(px)[tid + i * kThreads];
+            ry[i] = reinterpret_cast<const u32x4 *>(py)[tid + i * kThreads];
+        }
+#pragma unroll
+        for (int i = 0; i < kLoads; ++i) {
+            reinterpret_cast<u32x4 *>(smem[0][0])[tid + i * kThreads] = rx[i];
+            reinterpret_cast<u32x4 *>(smem[0][1])[tid + i * kThreads] = ry[i];
+        }
+        __syncthreads();
+    }
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int cur = kb & 1;
+        const bool more = kb + 1 < nkb;
+        if (more) {
+            const u32x4 *nx = reinterpret_cast<const u32x4 *>(px + (int64_t)(kb + 1) * kCB);
+            const u32x4 *ny = reinterpret_cast<const u32x4 *>(py + (int64_t)(kb + 1) * kCB);
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) {
+                rx[i] = nx[tid + i * kThreads];
+                ry[i] = ny[tid + i * kThreads];
+            }
+        }
+        compute_chunk<MODE>(smem[cur][0], smem[cur][1], wu, wv, lane, acc);
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < kLoads; ++i) {
+                reinterpret_cast<u32x4 *>(smem[cur ^ 1][0])[tid + i * kThreads] = rx[i];
+                reinterpret_cast<u32x4 *>(smem[cur ^ 1][1])[tid + i * kThreads] = ry[i];
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: D[j][i] -> C[i][j]
+    const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
+    const int l32 = lane & 31, hi = lane >> 5;
+#pragma unroll
+    for (int ub = 0; ub < 2; ++ub)
+#pragma unroll
+        for (int vb = 0; vb < 2; ++vb) {
+            const int64_t i = (int64_t)mb * kTile + wv * 64 + vb * 32 + l32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t j = (int64_t)nb * kTile + wu * 64 + ub * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                if (i >= g.m || j >= g.n) continue;
+                float re, im;
+                if constexpr (MODE == QCE_MODE_FP16X2) {
+                    re = acc.re_m[ub][vb][r] + acc.re_c[ub][vb][r] * (1.0f / 2048.0f);
+                    im = acc.im_m[ub][vb][r] + acc.im_c[ub][vb][r] * (1.0f / 2048.0f);
+                    if (shift_total) {
+                        re = ldexpf(re, -shift_total);
+                        im = ldexpf(im, -shift_total);
+                    }
+                } else if constexpr (MODE == QCE_MODE_BF16X3) {
+                    re = acc.re_m[ub][vb][r] + acc.re_c[ub][vb][r];
+                    im = acc.im_m[ub][vb][r] + acc.im_c[ub][vb][r];
+                } else {
+                    re = acc.re_m[ub][vb][r];
+                    im = acc.im_m[ub][vb][r];
+                }
+                float2 out;
+                if (alpha_one) {
+                    out = make_float2(re, im);
+                } else {
+                    out = make_float2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+                }
+                float2 *cp = g.C + i + j * g.ldc;
+                if (!g.beta_zero) {
+                    const float2 c = *cp;
+                    out.x += g.beta.x * c.x - g.beta.y * c.y;
+                    out.y += g.beta.x * c.y + g.beta.y * c.x;
+                }
+                *cp = out;
+            }
+        }
+}
+
+__global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta,
+                               int beta_zero) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * n) return;
+    const int64_t i = t % m, j = t / m;
+    float2 *cp = C + i + j * ldc;
+    if (beta_zero) {
+        *cp = make_float2(0.f, 0.f);
+    } else {
+        const float2 c = *cp;
+        *cp = make_float2(beta.x * c.x - beta.y * c.y, beta.x * c.y + beta.y * c.x);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs &g, int which, hipStream_t s) {
+    const int nbm = (int)((g.m + kTile - 1) / kTile), nbn = (int)((g.n + kTile - 1) / kTile);
+    const dim3 grid((unsigned)(nbm * nbn)), block(kThreads);
+    if (which == QCE_MODE_FP16X2)
+        hipLaunchKernelGGL(gemm_kernel<QCE_MODE_FP16X2>, grid, block, 0, s, g, nbm, nbn);
+    else if (which == QCE_MODE_BF16X3)
+        hipLaunchKernelGGL(gemm_kernel<QCE_MODE_BF16X3>, grid, block, 0, s, g, nbm, nbn);
+    else
+        hipLaunchKernelGGL(gemm_kernel<QCE_MODE_FP32>, grid, block, 0, s, g, nbm, nbn);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,
+                          hipStream_t s) {
+    const int64_t total = m * n;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, C,
+                       m, n, ldc, beta, beta_zero);
+    return hipGetLastError();
+}
+
+}  // namespace qce

@@ -1,0 +1,186 @@
+// Split and scale (Sec. 2.1, Eq. 2; scaling of Sec. 4.2).
+//
+// Each GEMM operand op(X) (rows x k) is read once and rewritten into panels
+// in the format of the selected mode (see PanelGeom in common.hpp):
+//   FP16X2 / FP16X2_SCALED: x' = x * 2^s, hi = fp16(x'), lo = fp16((x' - hi) * 2^11)
+//   BF16X3:                 b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)
+//   FP32:                   re and im de-interleaved into two FP32 planes
+// All conversions round to nearest even; the subtractions are exact in FP32
+// and the power-of-two scalings are exact (ldexp).  The mode and shift come
+// from the device decision when statistics ran, so no host round trip is
+// needed (Sec. 4.2).  Inputs are never modified.
+#include "common.hpp"
+
+namespace qce {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline uint16_t f16_bits(float v) {
+    _Float16 h = (_Float16)v;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float f16_val(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+__device__ inline uint16_t bf16_bits(float v) {
+    __bf16 h = (__bf16)v;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float bf16_val(uint16_t b) { return __uint_as_float((unsigned int)b << 16); }
+
+// FP16 two-term split of x' = x * 2^shift (Eq. 2)
+__device__ inline void split_fp16x2(float x, int shift, uint16_t &hi, uint16_t &lo) {
+    float xs = ldexpf(x, shift);
+    hi = f16_bits(xs);
+    float r = xs - f16_val(hi);  // exact
+    lo = f16_bits(r * 2048.0f);  // residual scaled by 2^11
+}
+
+// bfloat16 three-term split
+__device__ inline void split_bf16x3(float x, uint16_t &b0, uint16_t &b1, uint16_t &b2) {
+    b0 = bf16_bits(x);
+    float r1 = x - bf16_val(b0);  // exact
+    b1 = bf16_bits(r1);
+    float r2 = r1 - bf16_val(b1);  // exact
+    b2 = bf16_bits(r2);
+}
+
+__device__ inline uint4 pack8(const uint16_t *v) {
+    uint4 r;
+    r.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
+    r.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
+    r.z = (unsigned)v[4] | ((unsigned)v[5] << 16);
+    r.w = (unsigned)v[6] | ((unsigned)v[7] << 16);
+    return r;
+}
+
+// Panel row r holds P[r][l], l = 0..k-1.  KCONTIG = false: P[r][l] =
+// x[r + l * ldx] (rows contiguous: op(A) = A, or op(B) = B^T / B^H);
+// KCONTIG = true: P[r][l] = x[l + r * ldx] (k contiguous: op(A) = A^T / A^H,
+// or op(B) = B).  conj negates the imaginary part.
+template <bool KCONTIG>
+__global__ __launch_bounds__(kThreads) void split_panels_kernel(
+    const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
+    int64_t rows_pad, int64_t kq, char *__restrict__ panels, const DevState *st, int which,
+    int forced_mode, int forced_shift) {
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= rows_pad * kq) return;
+    int64_t r, q;  // row and group of 8 k-values
+    if (KCONTIG) {
+        q = t % kq;
+        r = t / kq;
+    } else {
+        r = t % rows_pad;
+        q = t / rows_pad;
+    }
+    const int mode = st ? st->mode : forced_mode;
+    const int shift = st ? st->shift[which] : forced_shift;
+
+    float re[8], im[8];
+    const int64_t l0 = q * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t l = l0 + j;
+        float2 v = make_float2(0.f, 0.f);
+        if (r < rows && l < k) v = KCONTIG ? x[l + r * ldx] : x[r + l * ldx];
+        re[j] = v.x;
+        im[j] = conj ? -v.y : v.y;
+    }
+    const int64_t rb = r / kPanelRows;
+    const int rin = (int)(r % kPanelRows);
+    if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED) {
+        using G = PanelGeom<QCE_MODE_FP16X2>;
+        const int64_t nkb = (kq * 8) / PanelFmt<QCE_MODE_FP16X2>::kBK;
+        const int64_t kb = l0 / PanelFmt<QCE_MODE_FP16X2>::kBK;
+        const int g = (int)((l0 % PanelFmt<QCE_MODE_FP16X2>::kBK) / 8);
+        char *chunk = panels + (rb * nkb + kb) * (int64_t)G::kChunkBytes;
+        const int sh = mode == QCE_MODE_FP16X2_SCALED ? shift : 0;
+        uint16_t h[4][8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            split_fp16x2(re[j], sh, h[0][j], h[1][j]);
+            split_fp16x2(im[j], sh, h[2][j], h[3][j]);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            *reinterpret_cast<uint4 *>(chunk + G::offset(p, rin, g)) = pack8(h[p]);
+    } else if (mode == QCE_MODE_BF16X3) {
+        using G = PanelGeom<QCE_MODE_BF16X3>;
+        const int64_t nkb = (kq * 8) / PanelFmt<QCE_MODE_BF16X3>::kBK;
+        const int64_t kb = l0 / PanelFmt<QCE_MODE_BF16X3>::kBK;
+        const int g = (int)((l0 % PanelFmt<QCE_MODE_BF16X3>::kBK) / 8);
+        char *chunk = panels + (rb * nkb + kb) * (int64_t)G::kChunkBytes;
+        uint16_t b[6][8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            split_bf16x3(re[j], b[0][j], b[1][j], b[2][j]);
+            split_bf16x3(im[j], b[3][j], b[4][j], b[5][j]);
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+            *reinterpret_cast<uint4 *>(chunk + G::offset(p, rin, g)) = pack8(b[p]);
+    } else {
+        using G = PanelGeom<QCE_MODE_FP32>;
+        const int64_t nkb = (kq * 8) / PanelFmt<QCE_MODE_FP32>::kBK;
+        const int64_t kb = l0 / PanelFmt<QCE_MODE_FP32>::kBK;
+        const int g0 = (int)((l0 % PanelFmt<QCE_MODE_FP32>::kBK) / 4);
+        char *chunk = panels + (rb * nkb + kb) * (int64_t)G::kChunkBytes;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            *reinterpret_cast<float4 *>(chunk + G::offset(0, rin, g0 + hh)) =
+                make_float4(re[4 * hh], re[4 * hh + 1], re[4 * hh + 2], re[4 * hh + 3]);
+            *reinterpret_cast<float4 *>(chunk + G::offset(1, rin, g0 + hh)) =
+                make_float4(im[4 * hh], im[4 * hh + 1], im[4 * hh + 2], im[4 * hh + 3]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void split_planar_kernel(int mode, int shift,
+                                                                const float2 *__restrict__ x,
+                                                                int64_t n, uint16_t *planes) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    float2 v = x[i];
+    if (mode == QCE_MODE_BF16X3) {
+        uint16_t b[6];
+        split_bf16x3(v.x, b[0], b[1], b[2]);
+        split_bf16x3(v.y, b[3], b[4], b[5]);
+        for (int p = 0; p < 6; ++p) planes[p * n + i] = b[p];
+    } else {
+        uint16_t h[4];
+        split_fp16x2(v.x, shift, h[0], h[1]);
+        split_fp16x2(v.y, shift, h[2], h[3]);
+        for (int p = 0; p < 4; ++p) planes[p * n + i] = h[p];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int conj, int64_t rows,
+                               int64_t k, void *panels, const DevState *st, int which,
+                               int forced_mode, int shift, hipStream_t s) {
+    const int64_t rows_pad = round_up(rows, kPanelRows);
+    const int64_t kq = round_up(k, kKPad) / 8;
+    const int64_t total = rows_pad * kq;
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + kThreads - 1) / kThreads;
+    char *p = static_cast<char *>(panels);
+    if (!kcontig)
+        hipLaunchKernelGGL(split_panels_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           x, ldx, conj, rows, k, rows_pad, kq, p, st, which, forced_mode, shift);
+    else
+        hipLaunchKernelGGL(split_panels_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           x, ldx, conj, rows, k, rows_pad, kq, p, st, which, forced_mode, shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_planar(int mode, int shift, const float2 *x, int64_t n, uint16_t *planes,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(split_planar_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, mode,
+                       shift, x, n, planes);
+    return hipGetLastError();
+}
+
+}  // namespace qce
