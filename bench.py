@@ -1,0 +1,278 @@
+"""Benchmark of the emulated-CGEMM hot path on one MI355X.
+
+One step = one pass over the standalone complex64 GEMM workload: M = N = K in
+{512, 2048, 8192} plus the tall-skinny (65536, 64, 64), each with operands
+drawn from three distributions -- (a) complex Gaussian, (b) log-uniform
+magnitudes over [2^-40, 1], (c) magnitudes over [2^-120, 1] with zeros -- in
+AUTO mode: exponent statistics, on-device mode selection, split/scale and the
+selected MFMA GEMM for every one of the 12 GEMMs.  Inputs are resident in HBM
+before the timed region.
+
+Printed: one JSON line with the whole-step effective throughput
+(sum of 8*m*n*k over the step / step time), per-case times, modes and
+sampled FP64 errors, the plain-FP32 baselines on the same GPU (the library's
+FP32 mode and rocBLAS through torch.matmul), the roofline of the dominant
+kernel from hipEvent timings of the timed region, and the FP64 CPU oracle
+timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "emulated CGEMM TFLOP/s & amplitudes/s vs plain FP32, at ≤2x FP32 rel. error"
+SHAPES = [(512, 512, 512), (2048, 2048, 2048), (8192, 8192, 8192), (65536, 64, 64)]
+DISTS = ["a", "b", "c"]
+PEAK = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}  # MI355X dense TFLOP/s (published)
+HBM_PEAK_GBS = 8000.0
+# MFMA products each mode issues per real product (Eq. 2: three for the FP16
+# two-term split; six for the BF16 three-term split; one for FP32)
+PRODUCTS = {"fp16x2": 3, "fp16x2_scaled": 3, "bf16x3": 6, "fp32": 1}
+KERNEL_OF_PHASE = {"gemm_fp16x2": "gemm_kernel<FP16X2>", "gemm_bf16x3": "gemm_kernel<BF16X3>",
+                   "gemm_fp32": "gemm_kernel<FP32>"}
+PEAK_OF_PHASE = {"gemm_fp16x2": "fp16", "gemm_bf16x3": "bf16", "gemm_fp32": "fp32"}
+PRODUCTS_OF_PHASE = {"gemm_fp16x2": 3, "gemm_bf16x3": 6, "gemm_fp32": 1}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse_cases(spec):
+    if not spec:
+        return [(si, d) for si in range(len(SHAPES)) for d in DISTS]
+    out = []
+    for item in spec.split(","):
+        s, d = item.split(":")
+        si = [str(x[0]) for x in SHAPES].index(s)
+        out.append((si, d))
+    return out
+
+
+def sample_error(C_dev_host, A, B, rng, nsamp=256):
+    """Relative error on sampled entries against FP64 dot products."""
+    m, k = A.shape
+    n = B.shape[1]
+    ii = rng.integers(0, m, nsamp)
+    jj = rng.integers(0, n, nsamp)
+    ref = np.einsum("sk,ks->s", A[ii, :].astype(np.complex128), B[:, jj].astype(np.complex128))
+    got = C_dev_host[ii, jj].astype(np.complex128)
+    den = np.sqrt(np.sum(np.abs(ref) ** 2))
+    return float(np.sqrt(np.sum(np.abs(got - ref) ** 2)) / den) if den > 0 else 0.0, (ii, jj)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cases", default="", help="e.g. 8192:a,2048:b (default: all 12)")
+    ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs on a "
+              "single MI355X and has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2303_08989_amd as qce
+    from synth.gemm_inputs import case_seed
+
+    torch.cuda.set_device(0)
+    h = qce.Handle(0)
+    h.set_mode("auto")
+    h.set_tolerance(0.1, 0.0)
+    cases = parse_cases(args.cases)
+
+    # ---- inputs (host generation, then resident in HBM) --------------------
+    data = []
+    for ci, (si, d) in enumerate(cases):
+        m, n, k = SHAPES[si]
+        log(f"generating case {ci}: {m}x{n}x{k} dist {d}")
+        A, B = synth.gemm_operands(m, n, k, d, case_seed(d, si, 0))
+        dA = torch.from_numpy(np.asfortranarray(A).ravel(order="F")).to("cuda")
+        dB = torch.from_numpy(np.asfortranarray(B).ravel(order="F")).to("cuda")
+        dC = torch.empty(m * n, dtype=torch.complex64, device="cuda")
+        data.append(dict(m=m, n=n, k=k, dist=d, A=A, B=B, dA=dA, dB=dB, dC=dC))
+    flops_step = sum(8.0 * c["m"] * c["n"] * c["k"] for c in data)
+
+    def run_case(c):
+        qce.cgemm(h, "N", "N", c["m"], c["n"], c["k"], c["dA"], c["m"], c["dB"], c["k"],
+                  c["dC"], c["m"])
+
+    # ---- warmup -------------------------------------------------------------
+    for _ in range(args.warmup):
+        for c in data:
+            run_case(c)
+    torch.cuda.synchronize()
+
+    # ---- timed region ---------------------------------------------------------
+    h.reset_timing()
+    h.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for ci, c in enumerate(data):
+            h.set_timing_tag(ci)
+            run_case(c)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.set_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = flops_step / (ms_per_step * 1e-3) / 1e12
+
+    # ---- per-case breakdown from the library's event records ----------------
+    rng = np.random.default_rng(1234)
+    case_out = []
+    dominant = None
+    per_kernel = {}
+    for ci, c in enumerate(data):
+        tm = h.timing(ci)
+        modes = tm["gemms_by_mode"]
+        mode = max(modes, key=modes.get)
+        phases = {p: tm[p][0] / args.steps for p in ("stats", "split", "gemm_fp16x2", "gemm_bf16x3",
+                                                     "gemm_fp32", "gemm_skipped")}
+        total = sum(phases.values())
+        eff = 8.0 * c["m"] * c["n"] * c["k"]
+        Ch = c["dC"].cpu().numpy().reshape((c["n"], c["m"])).T
+        err, idx = sample_error(Ch, c["A"], c["B"], rng)
+        entry = dict(shape=[c["m"], c["n"], c["k"]], dist=c["dist"], mode=mode,
+                     ms=round(total, 5), tflops=round(eff / (total * 1e-3) / 1e12, 3),
+                     phase_ms={p: round(v, 5) for p, v in phases.items()},
+                     rel_err_sampled=err)
+        for p in ("gemm_fp16x2", "gemm_bf16x3", "gemm_fp32"):
+            ms_p, cnt = tm[p]
+            if not cnt:
+                continue
+            rec = dict(phase=p, ms_total=ms_p, launches=cnt, case=ci, flops=PRODUCTS_OF_PHASE[p] * eff)
+            if dominant is None or ms_p > dominant["ms_total"]:
+                dominant = rec
+            if p not in per_kernel or ms_p > per_kernel[p]["ms_total"]:
+                per_kernel[p] = rec
+        entry["_idx"] = idx
+        case_out.append(entry)
+
+    # ---- plain FP32 baselines on the same GPU -------------------------------
+    base = {}
+    if not args.no_baselines:
+        for ci, c in enumerate(data):
+            # library FP32 mode (same path, forced FP32)
+            h.set_mode("fp32")
+            run_case(c)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3
+            ev0.record()
+            for _ in range(reps):
+                run_case(c)
+            ev1.record()
+            torch.cuda.synchronize()
+            t_lib = ev0.elapsed_time(ev1) / reps
+            C32 = c["dC"].cpu().numpy().reshape((c["n"], c["m"])).T
+            # rocBLAS through torch.matmul: row-major (n x k) @ (k x m) = C^T
+            tA = c["dA"].view(c["k"], c["m"])
+            tB = c["dB"].view(c["n"], c["k"])
+            out = torch.matmul(tB, tA)
+            torch.cuda.synchronize()
+            ev0.record()
+            for _ in range(reps):
+                torch.matmul(tB, tA, out=out)
+            ev1.record()
+            torch.cuda.synchronize()
+            t_rb = ev0.elapsed_time(ev1) / reps
+            Crb = out.cpu().numpy().T
+            e = case_out[ci]
+            ii, jj = e["_idx"]
+            ref = np.einsum("sk,ks->s", c["A"][ii, :].astype(np.complex128),
+                            c["B"][:, jj].astype(np.complex128))
+            den = np.sqrt(np.sum(np.abs(ref) ** 2))
+
+            def rerr(Cx):
+                return float(np.sqrt(np.sum(np.abs(Cx[ii, jj] - ref) ** 2)) / den) if den > 0 else 0.0
+
+            e_lib, e_rb = rerr(C32), rerr(Crb)
+            eff = 8.0 * c["m"] * c["n"] * c["k"]
+            e["fp32_lib_ms"] = round(t_lib, 5)
+            e["rocblas_ms"] = round(t_rb, 5)
+            e["speedup_vs_best_fp32"] = round(min(t_lib, t_rb) / e["ms"], 3)
+            e["fp32_rel_err_sampled"] = min(e_lib, e_rb)
+            e["err_ratio_vs_fp32"] = (e["rel_err_sampled"] / min(e_lib, e_rb)) if min(e_lib, e_rb) > 0 else None
+            base.setdefault("fp32_lib_ms", 0.0)
+            base.setdefault("rocblas_ms", 0.0)
+            base["fp32_lib_ms"] += t_lib
+            base["rocblas_ms"] += t_rb
+        h.set_mode("auto")
+        base["fp32_lib_tflops"] = round(flops_step / (base["fp32_lib_ms"] * 1e-3) / 1e12, 3)
+        base["rocblas_tflops"] = round(flops_step / (base["rocblas_ms"] * 1e-3) / 1e12, 3)
+        base["speedup_vs_best_fp32"] = round(min(base["fp32_lib_ms"], base["rocblas_ms"]) / ms_per_step, 3)
+    for e in case_out:
+        e.pop("_idx", None)
+
+    # ---- roofline of the dominant kernel (largest share of the step) ----------
+    def roofline(rec):
+        avg_ms = rec["ms_total"] / rec["launches"]
+        ach = rec["flops"] / (avg_ms * 1e-3) / 1e12
+        pk = PEAK[PEAK_OF_PHASE[rec["phase"]]]
+        c = data[rec["case"]]
+        return {"bound": "mfma", "achieved": round(ach, 2), "peak": pk, "unit": "TFLOP/s",
+                "frac": round(ach / pk, 4), "traffic": None,
+                "kernel": KERNEL_OF_PHASE[rec["phase"]],
+                "case": f"{c['m']}x{c['n']}x{c['k']} dist {c['dist']}",
+                "avg_launch_ms": round(avg_ms, 4),
+                "flops_per_launch": rec["flops"],
+                "flops_note": "MFMA flops the mode issues: products x 8*m*n*k"}
+
+    roof = roofline(dominant) if dominant is not None else None
+    roof_by_kernel = {KERNEL_OF_PHASE[p]: roofline(r) for p, r in per_kernel.items()}
+
+    # ---- CPU oracle baseline on a bounded sample --------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        big = [c for c in data if c["m"] == 8192] or data
+        c = big[0]
+        ms_rows = 8
+        Ab = np.asfortranarray(c["A"][:ms_rows, :])
+        t0c = time.perf_counter()
+        oracle.cgemm(Ab, c["B"])
+        dt = time.perf_counter() - t0c
+        rows = int(max(8, min(c["m"], ms_rows * args.cpu_seconds / max(dt, 1e-3))))
+        Ab = np.asfortranarray(c["A"][:rows, :])
+        t0c = time.perf_counter()
+        oracle.cgemm(Ab, c["B"])
+        dt = time.perf_counter() - t0c
+        cpu = {"value": round(8.0 * rows * c["n"] * c["k"] / dt / 1e12, 6), "unit": "TFLOP/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"FP64 nested-loop CGEMM of rows 0..{rows - 1} of the {c['m']}x{c['n']}x{c['k']} "
+                         f"dist-{c['dist']} case ({rows}x{c['n']}x{c['k']}), {dt:.1f} s"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "compute": "fp16x2 / bf16x3 / fp32 MFMA, fp32 accumulate (per-GEMM automatic)",
+        "data": "synthetic",
+        "config": {"workload": "standalone complex64 CGEMMs m=n=k in {512,2048,8192} and "
+                               "(65536,64,64) x distributions {complex Gaussian, log-uniform "
+                               "[2^-40,1], [2^-120,1] with zeros}, AUTO mode",
+                   "gemms_per_step": len(data), "eff_flops_per_step": flops_step},
+        "roofline": roof, "cpu_baseline": cpu, "fp32_baseline": base or None,
+        "roofline_by_kernel": roof_by_kernel,
+        "cases": case_out,
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -289,6 +289,53 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
 qce_status qce_split(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 *x, int64_t n,
                      uint16_t *planes);
 
+/* ---------------------------------------------------------------------- */
+/* Timing and decision log (opt-in tracing)                               */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Phases a call is broken into.  GEMM_* count only launches whose kernel
+ * was the selected one; launches that returned at once after reading the
+ * mode flag (Sec. 4.2) are counted under GEMM_SKIPPED.
+ */
+typedef enum {
+    QCE_PHASE_STATS = 0,   /* exponent statistics and mode selection */
+    QCE_PHASE_SPLIT = 1,   /* split / scale of both operands */
+    QCE_PHASE_GEMM_FP16X2 = 2,
+    QCE_PHASE_GEMM_BF16X3 = 3,
+    QCE_PHASE_GEMM_FP32 = 4,
+    QCE_PHASE_GEMM_SKIPPED = 5,
+    QCE_PHASE_PERMUTE = 6,
+    QCE_PHASE_OTHER = 7,   /* scaling of C for k == 0, reductions */
+    QCE_NUM_PHASES = 8
+} qce_phase;
+
+typedef struct {
+    double ms[QCE_NUM_PHASES];     /* summed device time (hipEvent intervals) */
+    int64_t count[QCE_NUM_PHASES]; /* intervals summed */
+    int64_t gemms_by_mode[4];      /* GEMMs per selected qce_mode (FP16X2..FP32) */
+} qce_timing;
+
+/*
+ * enable != 0: from now on every phase of every call is bracketed by hipEvents
+ * on the handle's stream and the selected mode of every GEMM is logged on the
+ * device (no synchronisation while recording).  enable == 0 stops recording;
+ * records are kept until qce_reset_timing.
+ */
+qce_status qce_set_timing(qce_handle *h, int enable);
+
+/* Tag attached to the records of later calls (default 0). */
+qce_status qce_set_timing_tag(qce_handle *h, int32_t tag);
+
+/* Drop all records. */
+qce_status qce_reset_timing(qce_handle *h);
+
+/*
+ * Synchronises the handle's stream and sums the records whose tag equals
+ * `tag` (every record if tag < 0) into *out (host).
+ */
+qce_status qce_get_timing(qce_handle *h, int32_t tag, qce_timing *out);
+
 /* Human-readable name of a status code (static string). */
 const char *qce_status_string(qce_status s);
 

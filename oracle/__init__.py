@@ -32,7 +32,7 @@ docstrings of the functions that depend on them.
 from .core import (  # noqa: F401
     MODE_FP16X2, MODE_FP16X2_SCALED, MODE_BF16X3, MODE_FP32, MODE_NAMES,
     cgemm, rel_fro, fp16_rne, bf16_rne, bf16_to_f32, split_fp16x2, split_bf16x3,
-    emulated_cgemm, exp_stats, select_level, select_mode, zcontract,
+    emulated_cgemm, exp_stats, select_level, select_mode, zcontract, threads,
 )
 from .circuit import (  # noqa: F401
     statevector, statevector_amplitudes, tn_build, tn_amplitude, tn_amplitude_sliced,

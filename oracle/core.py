@@ -34,8 +34,15 @@ def _clib():
         lib.oracle_zcontract.argtypes = [ctypes.c_int, i64p, ctypes.c_int, i32p, f64p,
                                          ctypes.c_int, i32p, f64p, ctypes.c_int, i32p, f64p,
                                          ctypes.c_int, i32p]
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
         _lib = lib
     return _lib
+
+
+def threads():
+    """OpenMP threads the C loops use."""
+    return int(_clib().oracle_threads())
 
 
 _OPS = {"N": 0, "T": 1, "C": 2}

@@ -19,9 +19,13 @@
  *                the shared edges of a tensor network (Sec. 2.2), by an
  *                odometer over every label.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* threads the OpenMP loops below use */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* op codes: 0 = N, 1 = T, 2 = C (conjugate transpose) */
 static inline void load_op(const float *M, int64_t ld, int op, int64_t row, int64_t col,

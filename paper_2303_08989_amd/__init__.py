@@ -99,6 +99,25 @@ class Handle:
             nbytes = tensor.numel() * tensor.element_size()
             _check(self._h, self.lib.qce_set_workspace(self._h, _ptr(tensor), nbytes))
 
+    def set_timing(self, enable=True):
+        """Record hipEvent timings of every phase (no synchronisation)."""
+        _check(self._h, self.lib.qce_set_timing(self._h, 1 if enable else 0))
+
+    def set_timing_tag(self, tag):
+        _check(self._h, self.lib.qce_set_timing_tag(self._h, int(tag)))
+
+    def reset_timing(self):
+        _check(self._h, self.lib.qce_reset_timing(self._bind_stream()))
+
+    def timing(self, tag=-1):
+        """Synchronising summary of the timing records with this tag (-1: all):
+        {phase: (ms, count)} plus 'gemms_by_mode'."""
+        t = _lib.QceTiming()
+        _check(self._h, self.lib.qce_get_timing(self._bind_stream(), int(tag), ctypes.byref(t)))
+        out = {name: (t.ms[i], t.count[i]) for i, name in enumerate(_lib.PHASES)}
+        out["gemms_by_mode"] = {MODE_NAMES[i]: t.gemms_by_mode[i] for i in range(4)}
+        return out
+
     def last_decision(self):
         """Synchronising read of the last GEMM decision record."""
         d = _lib.QceDecision()

@@ -25,7 +25,11 @@ EXPORTS = (
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
     "qce_contract", "qce_permute", "qce_accumulate_f64", "qce_fidelity_f64",
     "qce_expstats", "qce_split", "qce_status_string", "qce_last_error",
+    "qce_set_timing", "qce_set_timing_tag", "qce_reset_timing", "qce_get_timing",
 )
+
+PHASES = ("stats", "split", "gemm_fp16x2", "gemm_bf16x3", "gemm_fp32", "gemm_skipped",
+          "permute", "other")
 
 
 class QceC32(ctypes.Structure):
@@ -42,6 +46,11 @@ class QceDecision(ctypes.Structure):
                 ("nnz", ctypes.c_int64 * 2), ("n1", ctypes.c_int64 * 2),
                 ("n2", ctypes.c_int64 * 2), ("n3", ctypes.c_int64 * 2),
                 ("nonfinite", ctypes.c_int64 * 2), ("emax", ctypes.c_int32 * 2)]
+
+
+class QceTiming(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_int64 * 8),
+                ("gemms_by_mode", ctypes.c_int64 * 4)]
 
 
 class QceError(RuntimeError):
@@ -87,6 +96,10 @@ def load():
         "qce_split": (st, [vp, ctypes.c_int, i32, vp, i64, vp]),
         "qce_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "qce_last_error": (ctypes.c_char_p, [vp]),
+        "qce_set_timing": (st, [vp, ctypes.c_int]),
+        "qce_set_timing_tag": (st, [vp, i32]),
+        "qce_reset_timing": (st, [vp]),
+        "qce_get_timing": (st, [vp, i32, ctypes.POINTER(QceTiming)]),
     }
     for name in EXPORTS:
         fn = getattr(lib, name)

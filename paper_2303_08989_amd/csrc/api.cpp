@@ -29,11 +29,110 @@ struct qce_handle {
     bool last_on_device = false;
     qce_decision last_host{};
     char err[512] = {0};
+    // opt-in timing (qce_set_timing)
+    bool timing = false;
+    int32_t tag = 0;
+    int *mode_log = nullptr;  // device ring of selected modes, kLogCap entries
+    int64_t n_calls = 0;      // GEMM calls issued (ring position)
+    int64_t first_unresolved_call = 0;
+    struct Rec {
+        int32_t tag;
+        int kind;   // qce_phase for non-GEMM spans; -1 GEMM kernel span; -2 call marker
+        int cls;    // GEMM kernel class (mode of the kernel template) for kind == -1
+        int fixed;  // mode known on the host, else -1 (look up the device log)
+        int64_t call;
+        hipEvent_t a, b;
+        bool resolved;
+        double ms;
+        int phase;  // resolved phase
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
 
 constexpr int kFidBlocks = 512;
+constexpr int kLogCap = 1 << 15;
+
+// ---- timing helpers -------------------------------------------------------
+hipEvent_t ev_get(qce_handle *h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+hipEvent_t span_begin(qce_handle *h) {
+    if (!h->timing) return nullptr;
+    hipEvent_t e = ev_get(h);
+    if (e && hipEventRecord(e, h->stream) != hipSuccess) {
+        h->pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void span_end(qce_handle *h, hipEvent_t a, int kind, int cls = 0, int fixed = -1, int64_t call = -1) {
+    if (!a) return;
+    hipEvent_t b = ev_get(h);
+    if (!b || hipEventRecord(b, h->stream) != hipSuccess) {
+        h->pool.push_back(a);
+        if (b) h->pool.push_back(b);
+        return;
+    }
+    h->recs.push_back({h->tag, kind, cls, fixed, call, a, b, false, 0.0, 0});
+}
+
+bool class_matches(int cls, int mode) {
+    if (cls == QCE_MODE_FP16X2) return mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED;
+    return cls == mode;
+}
+
+int class_phase(int cls) {
+    return cls == QCE_MODE_FP16X2 ? QCE_PHASE_GEMM_FP16X2
+         : cls == QCE_MODE_BF16X3 ? QCE_PHASE_GEMM_BF16X3 : QCE_PHASE_GEMM_FP32;
+}
+
+// Synchronise and turn pending records into (phase, ms).
+hipError_t resolve_timing(qce_handle *h) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    std::vector<int> log;
+    bool need_log = false;
+    for (auto &r : h->recs)
+        if (!r.resolved && r.fixed < 0 && (r.kind == -1 || r.kind == -2)) need_log = true;
+    if (need_log && h->mode_log) {
+        log.resize(kLogCap);
+        e = hipMemcpy(log.data(), h->mode_log, sizeof(int) * kLogCap, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &r : h->recs) {
+        if (r.resolved) continue;
+        int mode = r.fixed;
+        if (mode < 0 && (r.kind == -1 || r.kind == -2))
+            mode = (r.call >= 0 && !log.empty()) ? log[r.call % kLogCap] : QCE_MODE_FP32;
+        if (r.kind == -2) {
+            r.phase = -1 - mode;  // call marker: encodes the mode
+            r.ms = 0.0;
+        } else {
+            float ms = 0.f;
+            if (r.a && r.b) (void)hipEventElapsedTime(&ms, r.a, r.b);
+            r.ms = ms;
+            r.phase = r.kind >= 0 ? r.kind : (class_matches(r.cls, mode) ? class_phase(r.cls) : QCE_PHASE_GEMM_SKIPPED);
+        }
+        if (r.a) h->pool.push_back(r.a);
+        if (r.b) h->pool.push_back(r.b);
+        r.a = r.b = nullptr;
+        r.resolved = true;
+    }
+    h->first_unresolved_call = h->n_calls;
+    return hipSuccess;
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -139,13 +238,22 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     hipStream_t s = h->stream;
     const int beta_zero = beta.x == 0.f && beta.y == 0.f;
     if (k == 0) {
+        hipEvent_t e0 = span_begin(h);
         QCE_HIP(h, launch_scale_c(C, m, n, ldc, beta, beta_zero, s));
+        span_end(h, e0, QCE_PHASE_OTHER);
         h->have_decision = true;
         h->last_on_device = false;
         h->last_host = qce_decision{};
         h->last_host.mode = QCE_MODE_FP32;
         return QCE_SUCCESS;
     }
+    // keep the device mode log from wrapping over unresolved timing records
+    if (h->timing && h->n_calls - h->first_unresolved_call >= kLogCap / 2)
+        QCE_HIP(h, resolve_timing(h));
+    const int64_t call = h->n_calls++;
+    const int slot = (int)(call % kLogCap);
+    int *log = h->timing ? h->mode_log : nullptr;
+
     char *panA = ws;
     char *panB = ws + align256(panel_bytes(m, k));
     const MatDesc da = stored_desc(a, m, k), db = stored_desc(b, n, k);
@@ -161,36 +269,47 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     g.beta = beta;
     g.beta_zero = beta_zero;
     if (mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED) {
+        hipEvent_t e0 = span_begin(h);
         if (h->stats_dirty) QCE_HIP(h, launch_stats_clear(h->st, s));
         h->stats_dirty = true;
         QCE_HIP(h, launch_stats1(da, db, h->st, s));
         if (mode == QCE_MODE_AUTO) {
             QCE_HIP(h, launch_stats2(da, db, h->st, h->t, 0, s));
-            QCE_HIP(h, launch_select(h->st, h->t, h->t3, -1, s));
+            QCE_HIP(h, launch_select(h->st, h->t, h->t3, -1, log, slot, s));
         } else {
-            QCE_HIP(h, launch_select(h->st, h->t, h->t3, QCE_MODE_FP16X2_SCALED, s));
+            QCE_HIP(h, launch_select(h->st, h->t, h->t3, QCE_MODE_FP16X2_SCALED, log, slot, s));
         }
         h->stats_dirty = false;
+        span_end(h, e0, QCE_PHASE_STATS);
+        hipEvent_t e1 = span_begin(h);
         QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, h->st, 0, 0, 0, s));
         QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, h->st, 1, 0, 0, s));
+        span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = h->st;
         g.forced_mode = -1;
-        if (mode == QCE_MODE_AUTO) {
-            QCE_HIP(h, launch_gemm(g, QCE_MODE_FP16X2, s));
-            QCE_HIP(h, launch_gemm(g, QCE_MODE_BF16X3, s));
-            QCE_HIP(h, launch_gemm(g, QCE_MODE_FP32, s));
-        } else {
-            QCE_HIP(h, launch_gemm(g, QCE_MODE_FP16X2, s));
+        const int classes[3] = {QCE_MODE_FP16X2, QCE_MODE_BF16X3, QCE_MODE_FP32};
+        const int nclass = mode == QCE_MODE_AUTO ? 3 : 1;
+        for (int c = 0; c < nclass; ++c) {
+            hipEvent_t eg = span_begin(h);
+            QCE_HIP(h, launch_gemm(g, classes[c], s));
+            span_end(h, eg, -1, classes[c], -1, call);
         }
+        if (h->timing) h->recs.push_back({h->tag, -2, 0, -1, call, nullptr, nullptr, false, 0.0, 0});
         h->have_decision = true;
         h->last_on_device = true;
     } else {
+        hipEvent_t e1 = span_begin(h);
         QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, nullptr, 0, mode, 0, s));
         QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, nullptr, 1, mode, 0, s));
+        span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = nullptr;
         g.forced_mode = mode;
-        QCE_HIP(h, launch_gemm(g, mode == QCE_MODE_BF16X3 ? QCE_MODE_BF16X3
-                                  : mode == QCE_MODE_FP32 ? QCE_MODE_FP32 : QCE_MODE_FP16X2, s));
+        const int cls = mode == QCE_MODE_BF16X3 ? QCE_MODE_BF16X3
+                      : mode == QCE_MODE_FP32 ? QCE_MODE_FP32 : QCE_MODE_FP16X2;
+        hipEvent_t eg = span_begin(h);
+        QCE_HIP(h, launch_gemm(g, cls, s));
+        span_end(h, eg, -1, cls, mode, call);
+        if (h->timing) h->recs.push_back({h->tag, -2, 0, mode, call, nullptr, nullptr, false, 0.0, 0});
         h->have_decision = true;
         h->last_on_device = false;
         h->last_host = qce_decision{};
@@ -262,10 +381,14 @@ qce_status run_permute(qce_handle *h, int rank, const int64_t *ext, const int32_
     if (st != QCE_SUCCESS) return st;
     if (total == 0) return QCE_SUCCESS;
     if (identity) {
+        hipEvent_t e0 = span_begin(h);
         QCE_HIP(h, hipMemcpyAsync(y, x, (size_t)total * sizeof(float2), hipMemcpyDeviceToDevice, h->stream));
+        span_end(h, e0, QCE_PHASE_PERMUTE);
         return QCE_SUCCESS;
     }
+    hipEvent_t e0 = span_begin(h);
     QCE_HIP(h, launch_permute(x, y, total, d, h->stream));
+    span_end(h, e0, QCE_PHASE_PERMUTE);
     return QCE_SUCCESS;
 }
 
@@ -323,9 +446,11 @@ qce_status qce_create(qce_handle **out, int device) {
     if (h->emul_min > h->auto_min) { delete h; return QCE_ERR_INVALID_VALUE; }
     DeviceGuard g(device);
     if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
-        hipMalloc(&h->fid_partials, sizeof(double) * 4 * kFidBlocks) != hipSuccess) {
+        hipMalloc(&h->fid_partials, sizeof(double) * 4 * kFidBlocks) != hipSuccess ||
+        hipMalloc(&h->mode_log, sizeof(int) * kLogCap) != hipSuccess) {
         (void)hipGetLastError();
         if (h->st) (void)hipFree(h->st);
+        if (h->fid_partials) (void)hipFree(h->fid_partials);
         delete h;
         return QCE_ERR_ALLOC;
     }
@@ -345,8 +470,14 @@ qce_status qce_destroy(qce_handle *h) {
     qce_status rc = QCE_SUCCESS;
     if (hipStreamSynchronize(h->stream) != hipSuccess) rc = QCE_ERR_HIP;
     if (h->ws && h->ws_owned) (void)hipFree(h->ws);
+    for (auto &r : h->recs) {
+        if (r.a) (void)hipEventDestroy(r.a);
+        if (r.b) (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     (void)hipFree(h->st);
     (void)hipFree(h->fid_partials);
+    (void)hipFree(h->mode_log);
     delete h;
     return rc;
 }
@@ -457,7 +588,7 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
     h->stats_dirty = true;
     QCE_HIP(h, launch_stats1(a, none, h->st, s));
     QCE_HIP(h, launch_stats2(a, none, h->st, h->t, 2, s));
-    QCE_HIP(h, launch_select(h->st, h->t, h->t3, -2, s));
+    QCE_HIP(h, launch_select(h->st, h->t, h->t3, -2, nullptr, 0, s));
     h->stats_dirty = false;
     QCE_HIP(h, hipStreamSynchronize(s));
     QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
@@ -498,7 +629,9 @@ qce_status qce_permute(qce_handle *h, const qce_tensor *x, const void *X, const 
 qce_status qce_accumulate_f64(qce_handle *h, const qce_c32 *src, double *acc2) {
     if (!h || !src || !acc2) return QCE_ERR_INVALID_VALUE;
     DeviceGuard g(h->device);
+    hipEvent_t e0 = span_begin(h);
     QCE_HIP(h, launch_accumulate_f64(reinterpret_cast<const float2 *>(src), acc2, h->stream));
+    span_end(h, e0, QCE_PHASE_OTHER);
     return QCE_SUCCESS;
 }
 
@@ -701,6 +834,45 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         for (int i = 0; i < rc; ++i) perm.push_back(find(tl.data(), rc, lc[i]));
         st = run_permute(h, rc, te.data(), perm.data(), Cg, static_cast<float2 *>(C));
         if (st != QCE_SUCCESS) return st;
+    }
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_timing(qce_handle *h, int enable) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    h->timing = enable != 0;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_timing_tag(qce_handle *h, int32_t tag) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    h->tag = tag;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_reset_timing(qce_handle *h) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    DeviceGuard g(h->device);
+    QCE_HIP(h, resolve_timing(h));
+    h->recs.clear();
+    return QCE_SUCCESS;
+}
+
+qce_status qce_get_timing(qce_handle *h, int32_t tag, qce_timing *out) {
+    if (!h || !out) return QCE_ERR_INVALID_VALUE;
+    DeviceGuard g(h->device);
+    QCE_HIP(h, resolve_timing(h));
+    *out = qce_timing{};
+    for (const auto &r : h->recs) {
+        if (tag >= 0 && r.tag != tag) continue;
+        if (r.kind == -2) {
+            const int mode = -1 - r.phase;
+            if (mode >= 0 && mode < 4) out->gemms_by_mode[mode]++;
+            continue;
+        }
+        if (r.phase < 0 || r.phase >= QCE_NUM_PHASES) continue;
+        out->ms[r.phase] += r.ms;
+        out->count[r.phase]++;
     }
     return QCE_SUCCESS;
 }

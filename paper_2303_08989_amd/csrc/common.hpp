@@ -105,7 +105,10 @@ hipError_t launch_stats_clear(DevState *st, hipStream_t s);
 hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s);
 hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int skip,
                          hipStream_t s);
-hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, hipStream_t s);
+// forced_mode: -1 = rule, -2 = statistics-only entry point (stage 2 always
+// evaluated), >= 0 = that mode.  mode_log (nullable) receives the mode at slot.
+hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, int *mode_log,
+                         int slot, hipStream_t s);
 
 // Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
 // kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:

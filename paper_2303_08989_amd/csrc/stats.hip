@@ -209,7 +209,8 @@ __device__ inline int operand_level(const OperandStats &s, double t, double t3, 
     return QCE_MODE_FP32;
 }
 
-__global__ void select_kernel(DevState *st, double t, double t3, int forced, int stage2_flag) {
+__global__ void select_kernel(DevState *st, double t, double t3, int forced, int stage2_flag,
+                              int *mode_log, int slot) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int level[2];
     bool ran[2];
@@ -223,6 +224,7 @@ __global__ void select_kernel(DevState *st, double t, double t3, int forced, int
         for (int o = 0; o < 2; ++o)
             sh[o] = st->acc[o].nnz ? kFp16Emax - emax_of_bits(st->acc[o].maxbits) : 0;
     st->mode = mode;
+    if (mode_log) mode_log[slot] = mode;
     st->shift[0] = sh[0];
     st->shift[1] = sh[1];
     qce_decision &r = st->last;
@@ -240,8 +242,6 @@ __global__ void select_kernel(DevState *st, double t, double t3, int forced, int
         r.nonfinite[o] = (int64_t)s.nonfinite;
         r.emax[o] = s.nnz ? emax_of_bits(s.maxbits) : INT32_MIN;
     }
-    // per-operand levels are reported through mode when only one operand is
-    // present (the statistics-only entry point passes an empty B)
     for (int o = 0; o < 2; ++o) {
         OperandStats &s = st->acc[o];
         s.nnz = s.n1 = s.n2 = s.n3 = s.nonfinite = 0;
@@ -279,12 +279,14 @@ hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, hipStream_t s) {
+hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, int *mode_log,
+                         int slot, hipStream_t s) {
     // stage-2 flag as used by launch_stats2: forced modes skip stage 2,
     // forced_mode == -2 is the statistics-only entry point (stage 2 always)
     int flag = forced_mode == -1 ? 0 : (forced_mode == -2 ? 2 : 1);
     int forced = forced_mode < 0 ? -1 : forced_mode;
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, st, t, t3, forced, flag);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, st, t, t3, forced, flag, mode_log,
+                       slot);
     return hipGetLastError();
 }
 
