@@ -1,0 +1,166 @@
+"""Sliced contraction of a circuit's tensor network on the GPU (Sec. 2.2,
+Sec. 5.3): the slice loop with an FP64 device sum of the slice amplitudes.
+
+Every pairwise contraction goes through the library's ``qce_contract``
+(TTGT: device permutes when needed, then the emulated CGEMM under the size
+policy); the per-slice scalars are added in FP64 on the device
+(``qce_accumulate_f64``).  Host work here is planning and input marshalling:
+the leaves (gate matrices, |0> and <x| vectors) are built on the host, and a
+slice fixes chosen labels by selecting entries of the leaves that carry them
+(every variant is uploaded before contraction starts).
+
+Slices: with sliced labels s_0 .. s_{S-1}, slice id sigma assigns
+s_i = (sigma >> i) & 1.  The labels varied by a run over slice ids
+[0, 2^V) are s_0 .. s_{V-1}; the planner orders them so that those labels
+enter the contraction tree as late as possible.  A node's result is kept
+between slices while the slice labels it depends on are unchanged and its
+parent will need it again (its sibling depends on a label it does not).
+"""
+import numpy as np
+
+from . import tn
+
+
+class CircuitPlan:
+    """Planning (structure only, independent of the bitstring)."""
+
+    def __init__(self, circuit, max_log2=28, restarts=8, seed=0, varied=6, path=None, sliced=None):
+        self.circuit = circuit
+        leaves = tn.circuit_network(circuit, 0)
+        self.label_sets = [tuple(l) for _, l in leaves]
+        L = len(self.label_sets)
+        if path is None:
+            path, sl = tn.best_greedy(self.label_sets, restarts=restarts, max_log2=max_log2, seed=seed)
+            if sliced is None:
+                sliced = sl
+        self.path = list(path)
+        sliced = list(sliced or [])
+        labs = tn.tree_labels(self.label_sets, self.path)
+        S = set(sliced)
+        deps = [frozenset(l for l in self.label_sets[i] if l in S) for i in range(L)]
+        for a, b in self.path:
+            deps.append(deps[a] | deps[b])
+        # order sliced labels: latest first-use first (they vary fastest)
+        first = {}
+        for s in range(len(self.path)):
+            for lab in deps[L + s]:
+                first.setdefault(lab, s)
+        self.sliced = sorted(sliced, key=lambda lab: (-first.get(lab, 0), lab))
+        self.varied = self.sliced[:min(varied, len(self.sliced))]
+        self.deps = deps
+        self.labels = [tuple(x for x in self.label_sets[i] if x not in S) for i in range(L)]
+        self.parent = {}
+        for s, (a, b) in enumerate(self.path):
+            self.parent[a] = (L + s, b)
+            self.parent[b] = (L + s, a)
+        ml, fl, steps = tn.path_cost(self.label_sets, self.path, frozenset(self.sliced))
+        self.max_log2 = ml
+        self.flops_per_slice = fl
+        self.gemm_shapes = steps  # log2 (m, n, k) per step
+
+    @property
+    def n_slices(self):
+        return 1 << len(self.sliced)
+
+
+class Executor:
+    """Runs a CircuitPlan on one GPU through the C-ABI."""
+
+    def __init__(self, handle, plan):
+        import torch
+        self.torch = torch
+        self.h = handle
+        self.plan = plan
+        self._out_labels = {}
+
+    def _leaf_variants(self, x):
+        """Device tensors of every leaf for bitstring x, with all variants of
+        leaves that carry sliced labels: {(leaf, values): tensor}."""
+        torch = self.torch
+        p = self.plan
+        leaves = tn.circuit_network(p.circuit, x)
+        S = p.sliced
+        pos = {lab: i for i, lab in enumerate(S)}
+        out = {}
+        for i, (arr, labels) in enumerate(leaves):
+            sl = [lab for lab in labels if lab in pos]
+            if not sl:
+                out[(i, ())] = torch.from_numpy(np.ascontiguousarray(arr)).to("cuda")
+                continue
+            for vals in np.ndindex(*(2,) * len(sl)):
+                idx = tuple(vals[sl.index(lab)] if lab in pos else slice(None) for lab in labels)
+                sub = np.ascontiguousarray(arr[idx])
+                out[(i, tuple(vals))] = torch.from_numpy(sub).to("cuda")
+        return out
+
+    def amplitude(self, x, slice_ids=None, acc=None):
+        """Sum over `slice_ids` (default: all) of the sliced network values,
+        accumulated in FP64 on the device.  Returns the device float64[2]
+        accumulator."""
+        import paper_2303_08989_amd as qce
+        torch = self.torch
+        p = self.plan
+        if slice_ids is None:
+            slice_ids = range(p.n_slices)
+        if acc is None:
+            acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+        leaves = self._leaf_variants(x)
+        L = len(p.label_sets)
+        pos = {lab: i for i, lab in enumerate(p.sliced)}
+        cache = {}  # node -> (key, tensor)
+        for sigma in slice_ids:
+            val = {lab: (sigma >> i) & 1 for lab, i in pos.items()}
+
+            def key_of(node):
+                return tuple(val[lab] for lab in sorted(p.deps[node]))
+
+            def leaf(i):
+                sl = [lab for lab in p.label_sets[i] if lab in pos]
+                return leaves[(i, tuple(val[lab] for lab in sl))]
+
+            def get(node):
+                if node < L:
+                    return leaf(node)
+                k = key_of(node)
+                hit = cache.get(node)
+                if hit is not None and hit[0] == k:
+                    return hit[1]
+                return None
+
+            live = {}
+            result = None
+            for s, (a, b) in enumerate(p.path):
+                node = L + s
+                k = key_of(node)
+                hit = cache.get(node)
+                if hit is not None and hit[0] == k:
+                    live[node] = hit[1]
+                    continue
+                ta = live.pop(a, None)
+                if ta is None:
+                    ta = get(a)
+                tb = live.pop(b, None)
+                if tb is None:
+                    tb = get(b)
+                la, lb = p.labels[a] if a < L else self._out_labels[a], \
+                    p.labels[b] if b < L else self._out_labels[b]
+                shared = set(la) & set(lb)
+                lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
+                self._out_labels[node] = tuple(lc)
+                out = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
+                live[node] = out
+                # keep for later slices when the parent will be recomputed
+                # while this node stays the same
+                par = p.parent.get(node)
+                if par is not None:
+                    sib = par[1]
+                    extra = (p.deps[sib] - p.deps[node]) & set(p.varied)
+                    if extra:
+                        cache[node] = (k, out)
+                    elif node in cache:
+                        del cache[node]
+                result = out
+            root = L + len(p.path) - 1 if p.path else 0
+            scalar = live.get(root, result)
+            qce.accumulate_f64(self.h, scalar.reshape(-1)[:1], acc)
+        return acc

@@ -1,0 +1,207 @@
+"""Host planning for circuit amplitudes: circuit -> tensor network ->
+pairwise contraction path -> sliced labels (Sec. 2.2, Sec. 5.3).
+
+Planning works on label structure only: every wire segment of the circuit is
+one label of extent 2 shared by exactly two tensors.  No arithmetic of the
+contraction happens here; the contractions run on the GPU (``executor``).
+
+* ``circuit_network``: |0> vectors, gate tensors (rank 2k for a k-qubit
+  gate, axes = outputs then inputs) and <x| vectors (Sec. 2.2).
+* ``greedy_path``: repeatedly contract the pair of connected tensors whose
+  contraction grows the network least, size(out) - size(a) - size(b), ties
+  broken by smaller flop count; optional random perturbation for restarts.
+  (The paper uses cotengra's hyper-optimised search, Sec. 5.1; this is the
+  project's own greedy order.)
+* ``choose_slices``: labels whose removal from every intermediate brings the
+  largest intermediate under a bound, picked greedily by total cost
+  (slicing, Sec. 5.3).
+"""
+import heapq
+import math
+import random
+
+import numpy as np
+
+
+def circuit_network(circuit, x):
+    """Leaves [(array complex64, labels)] of <x|U|0...0> for an n-qubit circuit.
+
+    Qubit q is bit n-1-q of x.  A gate's tensor has axes (outputs..., inputs...)
+    taken from its 2^k x 2^k matrix in the basis |b1 ... bk> with b1 the bit of
+    the first listed qubit.
+    """
+    n = circuit["n"]
+    leaves = []
+    nxt = [0]
+
+    def fresh():
+        nxt[0] += 1
+        return nxt[0] - 1
+
+    wire = [fresh() for _ in range(n)]
+    for q in range(n):
+        leaves.append((np.array([1, 0], dtype=np.complex64), (wire[q],)))
+    for g in circuit["gates"]:
+        qs = list(g["qubits"])
+        k = len(qs)
+        t = np.asarray(g["matrix"]).astype(np.complex64).reshape((2,) * (2 * k))
+        outs = [fresh() for _ in qs]
+        leaves.append((t, tuple(outs) + tuple(wire[q] for q in qs)))
+        for q, o in zip(qs, outs):
+            wire[q] = o
+    for q in range(n):
+        bit = (int(x) >> (n - 1 - q)) & 1
+        v = np.zeros(2, dtype=np.complex64)
+        v[bit] = 1
+        leaves.append((v, (wire[q],)))
+    return leaves
+
+
+def _lsize(labels, sliced=frozenset()):
+    return sum(1 for lab in labels if lab not in sliced)
+
+
+def greedy_path(label_sets, seed=None, noise=0.0, alpha=1.0):
+    """Pairwise contraction order for a network whose labels each join two
+    tensors.  Returns [(i, j)] in SSA numbering (leaves 0..L-1, the result of
+    step s is tensor L+s).  The cost of a candidate pair is
+    size(out) - alpha * (size(a) + size(b)); with ``seed``/``noise`` it is
+    perturbed by Gumbel noise for randomised restarts."""
+    rng = random.Random(seed)
+    tens = {i: frozenset(ls) for i, ls in enumerate(label_sets)}
+    owner = {}
+    for i, ls in tens.items():
+        for lab in ls:
+            owner.setdefault(lab, []).append(i)
+    nid = len(label_sets)
+    heap = []
+
+    def cost(a, b):
+        la, lb = tens[a], tens[b]
+        out = la ^ lb
+        c = 2.0 ** len(out) - alpha * (2.0 ** len(la) + 2.0 ** len(lb))
+        fl = 2.0 ** len(la | lb)
+        if noise:
+            g = -math.log(-math.log(rng.random() + 1e-300) + 1e-300)
+            c = c - noise * g * abs(c + 1.0)
+        return (c, fl, min(a, b), max(a, b))
+
+    def push_pairs(a):
+        seen = set()
+        for lab in tens[a]:
+            for b in owner.get(lab, ()):
+                if b != a and b in tens and b not in seen:
+                    seen.add(b)
+                    heapq.heappush(heap, (cost(a, b), a, b))
+
+    for i in list(tens):
+        push_pairs(i)
+    path = []
+    while len(tens) > 1:
+        while heap:
+            _, a, b = heapq.heappop(heap)
+            if a in tens and b in tens:
+                break
+        else:
+            # disconnected components: contract the two smallest (outer product)
+            a, b = sorted(tens, key=lambda i: (len(tens[i]), i))[:2]
+        la, lb = tens.pop(a), tens.pop(b)
+        out = la ^ lb
+        c = nid
+        nid += 1
+        tens[c] = out
+        for lab in la & lb:
+            owner.pop(lab, None)
+        for lab in out:
+            owner[lab] = [c if t in (a, b) else t for t in owner[lab]]
+        path.append((a, b))
+        push_pairs(c)
+    return path
+
+
+def tree_labels(label_sets, path):
+    """Labels of every SSA tensor (leaves then intermediates)."""
+    labs = [frozenset(ls) for ls in label_sets]
+    for a, b in path:
+        labs.append(labs[a] ^ labs[b])
+    return labs
+
+
+def path_cost(label_sets, path, sliced=frozenset()):
+    """(max log2 intermediate size, total effective flops per slice, steps)
+    with `sliced` labels removed everywhere."""
+    labs = tree_labels(label_sets, path)
+    L = len(label_sets)
+    maxlog = 0
+    flops = 0.0
+    steps = []
+    for s, (a, b) in enumerate(path):
+        la, lb = labs[a] - sliced, labs[b] - sliced
+        out = labs[L + s] - sliced
+        maxlog = max(maxlog, len(out))
+        k = len(la & lb)
+        m, n = len(la - lb), len(lb - la)
+        flops += 8.0 * 2.0 ** (m + n + k)
+        steps.append((m, n, k))
+    return maxlog, flops, steps
+
+
+def _step_matrices(label_sets, path):
+    """Boolean matrices (steps x labels): labels of each step's output and of
+    the union of its two operands."""
+    labs = tree_labels(label_sets, path)
+    L = len(label_sets)
+    universe = sorted(set().union(*labs[:L]))
+    col = {lab: i for i, lab in enumerate(universe)}
+    out = np.zeros((len(path), len(universe)), dtype=bool)
+    uni = np.zeros((len(path), len(universe)), dtype=bool)
+    for s, (a, b) in enumerate(path):
+        for lab in labs[L + s]:
+            out[s, col[lab]] = True
+        for lab in labs[a] | labs[b]:
+            uni[s, col[lab]] = True
+    return universe, out, uni
+
+
+def choose_slices(label_sets, path, max_log2, max_slices=None):
+    """Greedy slicing: while the largest intermediate exceeds 2^max_log2,
+    slice the label (among those of the largest intermediates) that gives the
+    smallest total flops over all slices."""
+    universe, out, uni = _step_matrices(label_sets, path)
+    keep = np.ones(len(universe), dtype=bool)
+    sliced = []
+    while True:
+        osz = (out & keep).sum(axis=1)
+        maxlog = int(osz.max()) if len(osz) else 0
+        if maxlog <= max_log2 or (max_slices is not None and len(sliced) >= max_slices):
+            return sorted(universe[i] for i in sliced)
+        usz = (uni & keep).sum(axis=1)
+        cands = np.nonzero((out[osz == maxlog] & keep).any(axis=0))[0]
+        # for each candidate: new max output size and total flops over all slices
+        o_c = osz[:, None] - out[:, cands]
+        u_c = usz[:, None] - uni[:, cands]
+        new_max = o_c.max(axis=0)
+        new_fl = np.exp2(u_c.astype(np.float64)).sum(axis=0) * 2.0 ** (len(sliced) + 1)
+        order = np.lexsort((cands, new_fl, new_max))
+        best = int(cands[order[0]])
+        keep[best] = False
+        sliced.append(best)
+
+
+def best_greedy(label_sets, restarts=8, max_log2=None, seed=0, noises=(0.1, 0.3, 1.0)):
+    """Best of one deterministic greedy path and `restarts` randomised ones,
+    ranked by (number of sliced labels needed for 2^max_log2, max
+    intermediate, total flops over all slices)."""
+    best = None
+    for r in range(restarts + 1):
+        noise = 0.0 if r == 0 else noises[r % len(noises)]
+        p = greedy_path(label_sets, seed=seed + r, noise=noise)
+        ml0, _, _ = path_cost(label_sets, p)
+        if best is not None and max_log2 is not None and ml0 - max_log2 > best[0][0] + 6:
+            continue
+        sl = choose_slices(label_sets, p, max_log2) if max_log2 is not None else []
+        ml, fl, _ = path_cost(label_sets, p, frozenset(sl))
+        key = (len(sl), ml, fl * 2.0 ** len(sl))
+        if best is None or key < best[0]:
+            best = (key, p, sl)
+    return best[1], best[2]

@@ -1,0 +1,210 @@
+"""GPU parity of the TTGT contraction path (permute -> emulated CGEMM ->
+permute), the FP64 reductions and circuit amplitudes, through the C-ABI,
+against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def qce():
+    import paper_2303_08989_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def h(qce):
+    hh = qce.Handle(0)
+    yield hh
+    hh.close()
+
+
+def rounded(circuit):
+    out = dict(circuit)
+    out["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                    for g in circuit["gates"]]
+    return out
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_permute_exact(qce, h, seed):
+    rng = np.random.default_rng(seed)
+    rank = int(rng.integers(1, 7))
+    shape = tuple(int(x) for x in rng.integers(1, 5, rank))
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    perm = [int(p) for p in rng.permutation(rank)]
+    y = qce.permute(h, torch.from_numpy(x).to("cuda"), perm).cpu().numpy()
+    assert np.array_equal(y, np.transpose(x, perm))
+
+
+def test_permute_rank20_pow2(qce, h):
+    rng = np.random.default_rng(1)
+    shape = (2,) * 20
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    perm = [int(p) for p in rng.permutation(20)]
+    y = qce.permute(h, torch.from_numpy(x).to("cuda"), perm).cpu().numpy()
+    assert np.array_equal(y, np.transpose(x, perm))
+
+
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated", "fp16x2", "bf16x3"])
+@pytest.mark.parametrize("seed", range(6))
+def test_contract_integer_exact(qce, h, mode, seed):
+    net = synth.random_network(seed, n_contracted=1 + seed % 3, n_free_a=1 + seed % 2,
+                               n_free_b=2 - seed % 2, max_extent=5, dist="int",
+                               shuffle_output=True)
+    if mode == "auto_emulated":
+        h.set_mode("auto")
+        h.set_size_policy(0, 0)      # statistics + selection on every GEMM
+    else:
+        h.set_mode(mode)
+    try:
+        C = qce.contract(h, torch.from_numpy(net["A"]).to("cuda"), net["la"],
+                         torch.from_numpy(net["B"]).to("cuda"), net["lb"], net["lc"]).cpu().numpy()
+    finally:
+        h.set_size_policy(2048, 512)
+        h.set_mode("auto")
+    want = oracle.zcontract(net["A"], net["la"], net["B"], net["lb"], net["lc"])
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
+@pytest.mark.parametrize("layout", ["natural", "swapped", "interleaved", "scalar", "outer"])
+def test_contract_layouts_float(qce, h, layout):
+    rng = np.random.default_rng(7)
+    ext = {0: 3, 1: 4, 2: 5, 3: 2, 4: 6}
+    if layout == "scalar":
+        la, lb, lc = [0, 1], [1, 0], []
+    elif layout == "outer":
+        la, lb, lc = [0, 1], [2], [2, 0, 1]
+    else:
+        la, lb = [2, 0, 1], [3, 1, 4, 2]
+        lc = {"natural": [3, 4, 0], "swapped": [0, 3, 4], "interleaved": [3, 0, 4]}[layout]
+
+    def t(ls):
+        shape = tuple(ext[x] for x in ls)
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    A, B = t(la), t(lb)
+    h.set_mode("fp32")
+    C = qce.contract(h, torch.from_numpy(A).to("cuda"), la, torch.from_numpy(B).to("cuda"), lb, lc)
+    h.set_mode("auto")
+    want = oracle.zcontract(A, la, B, lb, lc)
+    assert oracle.rel_fro(C.cpu().numpy(), want) < 1e-6
+
+
+def test_contract_errors(qce, h):
+    a = torch.zeros((2, 2), dtype=torch.complex64, device="cuda")
+    with pytest.raises(qce.QceError) as e:
+        qce.contract(h, a, [0, 1], a, [1, 2], [0, 1, 2])     # batch label
+    assert e.value.status == 2
+    with pytest.raises(qce.QceError) as e:
+        qce.contract(h, a, [0, 3], a, [1, 2], [1, 2])        # trace over one input
+    assert e.value.status == 2
+    b = torch.zeros((2, 3), dtype=torch.complex64, device="cuda")
+    with pytest.raises(qce.QceError) as e:
+        qce.contract(h, a, [0, 1], b, [2, 1], [0, 2])        # label 1: extent 2 vs 3
+    assert e.value.status == 1
+
+
+def test_accumulate_f64_exact(qce, h):
+    vals = np.array([1e8 + 1j, 3.25 - 2j, -1e8 + 0.5j, 1e-3 + 1e-3j], dtype=np.complex64)
+    acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+    src = torch.from_numpy(vals).to("cuda")
+    for i in range(len(vals)):
+        qce.accumulate_f64(h, src[i:i + 1], acc)
+    re = im = 0.0
+    for v in vals:
+        re += float(v.real)
+        im += float(v.imag)
+    got = acc.cpu().numpy()
+    assert got[0] == re and got[1] == im
+
+
+def test_fidelity_terms(qce, h):
+    rng = np.random.default_rng(3)
+    a = (rng.standard_normal(10000) + 1j * rng.standard_normal(10000)).astype(np.complex64)
+    b = (a + 1e-3 * rng.standard_normal(10000)).astype(np.complex64)
+    out = qce.fidelity_terms(h, torch.from_numpy(a).to("cuda"), torch.from_numpy(b).to("cuda")).cpu().numpy()
+    a64, b64 = a.astype(np.complex128), b.astype(np.complex128)
+    ov = np.vdot(b64, a64)
+    assert abs(out[0] - ov.real) <= 1e-12 * abs(ov) and abs(out[1] - ov.imag) <= 1e-12 * abs(ov)
+    assert out[2] == pytest.approx(np.vdot(a64, a64).real, rel=1e-13)
+    assert out[3] == pytest.approx(np.vdot(b64, b64).real, rel=1e-13)
+    fid = (out[0] ** 2 + out[1] ** 2) / (out[2] * out[3])
+    assert fid == pytest.approx(oracle.fidelity(a, b), rel=1e-12)
+
+
+# --- circuits ------------------------------------------------------------
+
+def _amplitudes(qce, h, circuit, xs, max_log2=30, mode="fp32", slice_ids=None, varied=6, policy=None):
+    from paper_2303_08989_amd.executor import CircuitPlan, Executor
+    plan = CircuitPlan(circuit, max_log2=max_log2, restarts=2, varied=varied)
+    h.set_mode(mode)
+    if policy:
+        h.set_size_policy(*policy)
+    try:
+        ex = Executor(h, plan)
+        out = []
+        for x in xs:
+            acc = ex.amplitude(x, slice_ids)
+            v = acc.cpu().numpy()
+            out.append(complex(v[0], v[1]))
+    finally:
+        h.set_size_policy(2048, 512)
+        h.set_mode("auto")
+    return np.array(out), plan
+
+
+def test_config1_amplitudes_fp32(qce, h):
+    # 12-qubit 3x4 grid, depth 8, ABCD layering, plain FP32 path
+    c = synth.grid_circuit(3, 4, 8, seed=0)
+    xs = synth.random_bitstrings(12, 10, seed=1)
+    got, plan = _amplitudes(qce, h, c, xs)
+    want = oracle.statevector_amplitudes(rounded(c), xs)
+    assert oracle.fidelity(got, want) >= 1 - 1e-6
+    assert np.max(np.abs(got - want) / np.abs(want)) < 1e-4
+    tn_want = np.array([oracle.tn_amplitude(rounded(c), x) for x in xs[:3]])
+    assert np.max(np.abs(got[:3] - tn_want)) < 1e-6 * np.max(np.abs(tn_want)) * 100
+
+
+def test_ghz_and_identity_closed_forms(qce, h):
+    n = 8
+    got, _ = _amplitudes(qce, h, synth.ghz_circuit(n), [0, (1 << n) - 1, 5])
+    assert abs(got[0] - 1 / math.sqrt(2)) < 1e-6 and abs(got[1] - 1 / math.sqrt(2)) < 1e-6
+    assert abs(got[2]) < 1e-7
+    got, _ = _amplitudes(qce, h, synth.identity_circuit(6, seed=3), [0, 9])
+    assert abs(got[0] - 1) < 1e-6 and abs(got[1]) < 1e-6
+
+
+def test_sliced_amplitude_all_slices(qce, h):
+    c = synth.grid_circuit(3, 4, 8, seed=2, pattern="ABCDCDAB")
+    x = 1234
+    got, plan = _amplitudes(qce, h, c, [x], max_log2=5, varied=3)
+    assert len(plan.sliced) >= 2
+    want = oracle.statevector_amplitudes(rounded(c), [x])[0]
+    assert abs(got[0] - want) < 1e-6 * max(abs(want), 1e-3)
+
+
+def test_emulated_amplitudes_auto_everywhere(qce, h):
+    # every GEMM through statistics + selection (size policy thresholds 0)
+    c = synth.grid_circuit(3, 4, 8, seed=5, pattern="ABCDCDAB")
+    xs = synth.random_bitstrings(12, 6, seed=2)
+    got, _ = _amplitudes(qce, h, c, xs, mode="auto", policy=(0, 0))
+    want = oracle.statevector_amplitudes(rounded(c), xs)
+    assert oracle.fidelity(got, want) >= 1 - 1e-6
+
+
+def test_reduced_config3_sliced(qce, h):
+    # the 53-qubit generator at reduced size: 4x5 grid, depth 12, ABCDCDAB,
+    # sliced, AUTO with the paper's size policy
+    c = synth.grid_circuit(4, 5, 12, seed=1, pattern="ABCDCDAB")
+    xs = synth.random_bitstrings(20, 2, seed=3)
+    got, plan = _amplitudes(qce, h, c, xs, max_log2=12, mode="auto", varied=4)
+    assert len(plan.sliced) >= 1
+    want = oracle.statevector_amplitudes(rounded(c), xs)
+    assert oracle.fidelity(got, want) >= 1 - 1e-6

@@ -1,0 +1,105 @@
+"""Host planning (circuit -> network -> greedy path -> slices): structural
+checks, and the plan executed by a plain numpy stand-in for the GPU (one
+einsum per pairwise step) against the FP64 oracle amplitudes."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2303_08989_amd import tn
+from paper_2303_08989_amd.executor import CircuitPlan
+
+
+def rounded(circuit):
+    """The same circuit with gate matrices rounded to complex64, the values
+    the GPU path receives."""
+    out = dict(circuit)
+    out["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                    for g in circuit["gates"]]
+    return out
+
+
+def _numpy_execute(plan, x, slice_ids=None):
+    leaves = tn.circuit_network(plan.circuit, x)
+    L = len(leaves)
+    S = plan.sliced
+    total = 0.0 + 0.0j
+    ids = range(plan.n_slices) if slice_ids is None else slice_ids
+    for sigma in ids:
+        val = {lab: (sigma >> i) & 1 for i, lab in enumerate(S)}
+        tens = {}
+        for i, (arr, labels) in enumerate(leaves):
+            idx = tuple(val[l] if l in val else slice(None) for l in labels)
+            tens[i] = (arr[idx].astype(np.complex128), [l for l in labels if l not in val])
+        for s, (a, b) in enumerate(plan.path):
+            ta, la = tens.pop(a)
+            tb, lb = tens.pop(b)
+            shared = set(la) & set(lb)
+            lc = [l for l in lb if l not in shared] + [l for l in la if l not in shared]
+            letters = {l: chr(97 + i) if i < 26 else chr(65 + i - 26)
+                       for i, l in enumerate(sorted(set(la) | set(lb)))}
+            expr = "".join(letters[l] for l in la) + "," + "".join(letters[l] for l in lb) + \
+                "->" + "".join(letters[l] for l in lc)
+            tens[L + s] = (np.einsum(expr, ta, tb), lc)
+        (t, _), = tens.values()
+        total += complex(t)
+    return total
+
+
+def test_network_structure():
+    c = synth.grid_circuit(3, 4, 8, seed=0)
+    leaves = tn.circuit_network(c, 5)
+    counts = {}
+    for arr, labels in leaves:
+        assert arr.shape == (2,) * len(labels)
+        for l in labels:
+            counts[l] = counts.get(l, 0) + 1
+    assert set(counts.values()) == {2}        # every wire joins two tensors
+    assert len(leaves) == 2 * c["n"] + len(c["gates"])
+
+
+def test_greedy_path_is_a_valid_tree():
+    c = synth.grid_circuit(3, 4, 8, seed=0)
+    ls = [l for _, l in tn.circuit_network(c, 0)]
+    for seed, noise in [(None, 0.0), (3, 0.3)]:
+        p = tn.greedy_path(ls, seed=seed, noise=noise)
+        L = len(ls)
+        assert len(p) == L - 1
+        used = [x for pair in p for x in pair]
+        assert sorted(used) == list(range(2 * L - 2))   # every tensor consumed once
+        labs = tn.tree_labels(ls, p)
+        assert labs[-1] == frozenset()                 # full contraction -> scalar
+
+
+def test_config1_plan_numpy_matches_oracle():
+    c = synth.grid_circuit(3, 4, 8, seed=0)
+    plan = CircuitPlan(c, max_log2=30, restarts=2)
+    assert plan.sliced == []
+    for x in synth.random_bitstrings(12, 4, seed=1):
+        assert abs(_numpy_execute(plan, x) - oracle.tn_amplitude(rounded(c), x)) < 1e-12
+
+
+def test_sliced_plan_numpy_matches_oracle():
+    c = synth.grid_circuit(3, 4, 8, seed=2, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=5, restarts=2, varied=2)
+    assert len(plan.sliced) >= 2 and plan.max_log2 <= 5
+    x = 1234
+    want = oracle.statevector_amplitudes(rounded(c), [x])[0]
+    assert abs(_numpy_execute(plan, x) - want) < 1e-12
+    # partial sums over disjoint slice ranges add up
+    half = plan.n_slices // 2
+    s1 = _numpy_execute(plan, x, range(half))
+    s2 = _numpy_execute(plan, x, range(half, plan.n_slices))
+    assert abs(s1 + s2 - want) < 1e-12
+
+
+def test_slicing_reduces_intermediates():
+    c = synth.grid_circuit(4, 5, 10, seed=3, pattern="ABCDCDAB")
+    ls = [l for _, l in tn.circuit_network(c, 0)]
+    p = tn.greedy_path(ls)
+    ml, fl, _ = tn.path_cost(ls, p)
+    sl = tn.choose_slices(ls, p, ml - 3)
+    ml2, fl2, _ = tn.path_cost(ls, p, frozenset(sl))
+    assert ml2 <= ml - 3 and len(sl) >= 3
