@@ -68,6 +68,83 @@ def sample_error(C_dev_host, A, B, rng, nsamp=256):
     return float(np.sqrt(np.sum(np.abs(got - ref) ** 2)) / den) if den > 0 else 0.0, (ii, jj)
 
 
+def run_circuits(h, args, torch, qce, synth):
+    """Config 1: 12-qubit 3x4 grid depth 8 (ABCD), 10 bitstrings, plain FP32.
+    Config 3: 53-qubit 6x9-minus-corner grid depth 12 (ABCDCDAB), sliced so
+    that every intermediate is at most 2^28 elements; this GPU runs slice
+    ids [0, c3_slices) in AUTO mode (size policy on), and again forced to FP32
+    as the baseline; per-slice values are compared in FP64 on the device."""
+    from paper_2303_08989_amd.executor import CircuitPlan, Executor
+    out = {}
+    # ---- config 1
+    c1 = synth.grid_circuit(3, 4, 8, seed=0)
+    plan1 = CircuitPlan(c1, max_log2=30, restarts=2)
+    xs = synth.random_bitstrings(12, 10, seed=1)
+    h.set_mode("fp32")
+    ex1 = Executor(h, plan1)
+    ex1.amplitude(xs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    accs = [ex1.amplitude(x) for x in xs]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    amps = np.array([complex(*a.cpu().numpy()) for a in accs])
+    out["config1"] = {"workload": "12-qubit 3x4 grid, depth 8, ABCD, fSim(pi/2,pi/6), plain FP32 path",
+                      "amplitudes_per_s": round(len(xs) / dt, 2), "ms_per_amplitude": round(dt / len(xs) * 1e3, 3),
+                      "contractions_per_amplitude": len(plan1.path), "_xs": xs, "_amps": amps}
+    # ---- config 3
+    c3 = synth.grid_circuit(pattern="ABCDCDAB", depth=12, seed=1, **synth.GRID_53)
+    t0 = time.perf_counter()
+    plan3 = CircuitPlan(c3, max_log2=28, restarts=args.c3_restarts, varied=6)
+    t_plan = time.perf_counter() - t0
+    x3 = synth.random_bitstrings(53, 1, seed=5)[0]
+    nsl = min(args.c3_slices, plan3.n_slices)
+    ids = range(nsl)
+    res = {}
+    for mode in ("auto", "fp32"):
+        h.set_mode(mode)
+        ex3 = Executor(h, plan3)
+        vec = torch.empty(nsl, dtype=torch.complex64, device="cuda")
+        ex3.amplitude(x3, ids, slice_out=vec)          # warm-up (allocations, workspace)
+        torch.cuda.synchronize()
+        h.reset_timing()
+        h.set_timing(True)
+        t0 = time.perf_counter()
+        acc = ex3.amplitude(x3, ids, slice_out=vec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h.set_timing(False)
+        tm = h.timing()
+        res[mode] = dict(seconds=dt, acc=acc.cpu().numpy(), vec=vec, timing=tm)
+    h.set_mode("auto")
+    fid = qce.fidelity_terms(h, res["auto"]["vec"], res["fp32"]["vec"]).cpu().numpy()
+    fidelity = float((fid[0] ** 2 + fid[1] ** 2) / (fid[2] * fid[3])) if fid[2] * fid[3] > 0 else 1.0
+    tm = res["auto"]["timing"]
+    gpu_ms = {k: round(v[0], 2) for k, v in tm.items() if k != "gemms_by_mode" and v[1]}
+    t64 = res["auto"]["seconds"]
+    share = plan3.varied_cost / plan3.total_cost
+    big = sorted(plan3.gemm_shapes, key=lambda s3: -(s3[0] + s3[1] + s3[2]))[:6]
+    out["config3"] = {
+        "workload": "53-qubit 6x9 grid minus corner, depth 12, ABCDCDAB, fSim(pi/2,pi/6); "
+                    f"{len(plan3.sliced)} sliced labels (2^{len(plan3.sliced)} slices), max intermediate "
+                    f"2^{plan3.max_log2}; slice ids 0..{nsl - 1} on this GPU, AUTO (t=0.1) with size policy",
+        "plan_seconds": round(t_plan, 1), "slices_run": nsl, "sliced_labels": len(plan3.sliced),
+        "seconds": round(t64, 4), "slices_per_s": round(nsl / t64, 2),
+        "fp32_seconds": round(res["fp32"]["seconds"], 4),
+        "speedup_vs_fp32": round(res["fp32"]["seconds"] / t64, 3),
+        "fidelity_auto_vs_fp32_over_slices": fidelity,
+        "partial_amplitude_auto": [float(v) for v in res["auto"]["acc"]],
+        "partial_amplitude_fp32": [float(v) for v in res["fp32"]["acc"]],
+        "memoized_tflop_run": round(plan3.varied_cost / 1e12, 2),
+        "effective_tflops": round(plan3.varied_cost / t64 / 1e12, 2),
+        "one_gpu_seconds_per_amplitude_extrapolated": round(t64 / share, 1),
+        "amplitudes_per_s_one_gpu_extrapolated": 1.0 / (t64 / share),
+        "gpu_ms_by_phase": gpu_ms, "gemms_by_mode": tm["gemms_by_mode"],
+        "largest_gemm_log2_mnk": [list(x) for x in big],
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +154,9 @@ def main():
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-circuits", action="store_true", help="skip the circuit-amplitude sections")
+    ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
+    ap.add_argument("--c3-restarts", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs on a "
@@ -235,6 +315,11 @@ def main():
     roof = roofline(dominant) if dominant is not None else None
     roof_by_kernel = {KERNEL_OF_PHASE[p]: roofline(r) for p, r in per_kernel.items()}
 
+    # ---- circuit amplitudes (12-qubit FP32 path; 53-qubit sliced share) ------
+    circuits = None
+    if not args.no_circuits:
+        circuits = run_circuits(h, args, torch, qce, synth)
+
     # ---- CPU oracle baseline on a bounded sample --------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -251,11 +336,27 @@ def main():
         t0c = time.perf_counter()
         oracle.cgemm(Ab, c["B"])
         dt = time.perf_counter() - t0c
+        if circuits is not None and "config1" in circuits:
+            c1 = circuits["config1"]
+            circ1 = synth.grid_circuit(3, 4, 8, seed=0)
+            rnd = dict(circ1)
+            rnd["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                            for g in circ1["gates"]]
+            t0c = time.perf_counter()
+            ref = oracle.statevector_amplitudes(rnd, c1.pop("_xs"))
+            dtc = time.perf_counter() - t0c
+            got = c1.pop("_amps")
+            c1["fidelity_vs_fp64_oracle"] = oracle.fidelity(got, ref)
+            c1["max_rel_err_vs_fp64_oracle"] = float(np.max(np.abs(got - ref) / np.abs(ref)))
+            c1["oracle_statevector_amplitudes_per_s"] = round(len(ref) / dtc, 2)
         cpu = {"value": round(8.0 * rows * c["n"] * c["k"] / dt / 1e12, 6), "unit": "TFLOP/s",
                "cores": oracle.threads(), "kind": "oracle",
                "sample": f"FP64 nested-loop CGEMM of rows 0..{rows - 1} of the {c['m']}x{c['n']}x{c['k']} "
                          f"dist-{c['dist']} case ({rows}x{c['n']}x{c['k']}), {dt:.1f} s"}
 
+    if circuits is not None and "config1" in circuits:
+        circuits["config1"].pop("_xs", None)
+        circuits["config1"].pop("_amps", None)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -268,6 +369,7 @@ def main():
                    "gemms_per_step": len(data), "eff_flops_per_step": flops_step},
         "roofline": roof, "cpu_baseline": cpu, "fp32_baseline": base or None,
         "roofline_by_kernel": roof_by_kernel,
+        "amplitudes": circuits,
         "cases": case_out,
     }
     print(json.dumps(out))

@@ -194,6 +194,9 @@ size_t qce_cgemm_workspace_size(int64_t m, int64_t n, int64_t k);
  *    beta == 0 means C is not read (NaN in C does not propagate).
  * A and B are read-only (the paper scales inputs in place, Sec. 4.2 note;
  * here shifted copies live in the workspace).
+ * Irregular shapes -- min(m, n) < 32 or k < 16 -- run a bandwidth-bound
+ * FP32 kernel in every mode, as the paper does for its irregular-shape GEMMs
+ * (Sec. 5.1.2); the decision record then reports FP32 without statistics.
  * m == 0 or n == 0: success, nothing enqueued.  k == 0: C <- beta * C.
  * Errors: INVALID_VALUE for h NULL, negative sizes, bad op, ld too small,
  *   NULL A/B/C with nonzero sizes, or pointers not 8-byte aligned;
@@ -307,7 +310,8 @@ typedef enum {
     QCE_PHASE_GEMM_SKIPPED = 5,
     QCE_PHASE_PERMUTE = 6,
     QCE_PHASE_OTHER = 7,   /* scaling of C for k == 0, reductions */
-    QCE_NUM_PHASES = 8
+    QCE_PHASE_GEMM_IRREGULAR = 8, /* bandwidth-bound FP32 kernel for irregular shapes */
+    QCE_NUM_PHASES = 9
 } qce_phase;
 
 typedef struct {

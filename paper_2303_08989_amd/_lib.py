@@ -29,7 +29,7 @@ EXPORTS = (
 )
 
 PHASES = ("stats", "split", "gemm_fp16x2", "gemm_bf16x3", "gemm_fp32", "gemm_skipped",
-          "permute", "other")
+          "permute", "other", "gemm_irregular")
 
 
 class QceC32(ctypes.Structure):
@@ -49,7 +49,7 @@ class QceDecision(ctypes.Structure):
 
 
 class QceTiming(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_int64 * 8),
+    _fields_ = [("ms", ctypes.c_double * 9), ("count", ctypes.c_int64 * 9),
                 ("gemms_by_mode", ctypes.c_int64 * 4)]
 
 

@@ -247,6 +247,38 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         h->last_host.mode = QCE_MODE_FP32;
         return QCE_SUCCESS;
     }
+    if (irregular_shape(m, n, k)) {
+        DirectArgs d{};
+        d.A = a.ptr;
+        d.lda = a.ld;
+        d.a_kcontig = a.kcontig;
+        d.a_conj = a.conj;
+        d.B = b.ptr;
+        d.ldb = b.ld;
+        d.b_kcontig = b.kcontig;
+        d.b_conj = b.conj;
+        d.m = m;
+        d.n = n;
+        d.k = k;
+        d.C = C;
+        d.ldc = ldc;
+        d.alpha = alpha;
+        d.beta = beta;
+        d.beta_zero = beta_zero;
+        d.partial = reinterpret_cast<float2 *>(ws);
+        hipEvent_t e0 = span_begin(h);
+        QCE_HIP(h, launch_direct(d, s));
+        span_end(h, e0, QCE_PHASE_GEMM_IRREGULAR);
+        h->have_decision = true;
+        h->last_on_device = false;
+        h->last_host = qce_decision{};
+        h->last_host.mode = QCE_MODE_FP32;
+        for (int o = 0; o < 2; ++o) {
+            h->last_host.n2[o] = -1;
+            h->last_host.emax[o] = INT32_MIN;
+        }
+        return QCE_SUCCESS;
+    }
     // keep the device mode log from wrapping over unresolved timing records
     if (h->timing && h->n_calls - h->first_unresolved_call >= kLogCap / 2)
         QCE_HIP(h, resolve_timing(h));
@@ -324,6 +356,7 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
 
 size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k) {
     if (k == 0) return 0;
+    if (irregular_shape(m, n, k)) return align256(direct_ws_bytes(m, n, k));
     return align256(panel_bytes(m, k)) + align256(panel_bytes(n, k));
 }
 

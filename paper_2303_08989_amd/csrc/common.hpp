@@ -131,6 +131,26 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
 
+// Irregular-shape CGEMM (direct.hip): PA[i][l], PB[j][l] read from the
+// stored matrices as in the split kernel; FP32 arithmetic.
+struct DirectArgs {
+    const float2 *A, *B;
+    int64_t lda, ldb;
+    int a_kcontig, a_conj, b_kcontig, b_conj;
+    int64_t m, n, k;
+    float2 *C;
+    int64_t ldc;
+    float2 alpha, beta;
+    int beta_zero;
+    float2 *partial;  // split-k partial tiles (workspace)
+    int kl, ti, tj;   // set by the planner
+    int64_t kchunk;
+};
+hipError_t launch_direct(DirectArgs d, hipStream_t s);
+size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k);
+// shapes sent to the irregular kernel in every mode
+inline bool irregular_shape(int64_t m, int64_t n, int64_t k) { return m < 32 || n < 32 || k < 16; }
+
 hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,
                           hipStream_t s);
 

@@ -1,0 +1,152 @@
+// Irregular-shape complex GEMM: a bandwidth-bound FP32 kernel for shapes
+// the tiled matrix-core kernels would pad heavily (a thin side, a tiny k, or
+// a small output with a long k).  The paper runs a specialised kernel for
+// such shapes in every computing mode (Sec. 5.1.2 and its appendix); so does
+// this library.
+//
+// Operand views are those of the split kernel: PA[i][l] (i < m) and PB[j][l]
+// (j < n) read straight from the stored matrices.  A block owns an output
+// tile of TI x TJ elements and a range of k; each output is shared by KL
+// threads that take every KL-th k-value of the range and are then summed in
+// LDS in a fixed order.  With several k-ranges the partial tiles go to a
+// workspace and a second kernel adds them in k order, so results are
+// deterministic.  Arithmetic: FP32 products with FP32 fused accumulation.
+#include "common.hpp"
+
+namespace qce {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline float2 load_view(const float2 *p, int64_t ld, int kcontig, int conj, int64_t r,
+                                   int64_t l) {
+    float2 v = kcontig ? p[l + r * ld] : p[r + l * ld];
+    if (conj) v.y = -v.y;
+    return v;
+}
+
+__global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs d) {
+    __shared__ float2 red[kThreads];
+    const int t = threadIdx.x;
+    const int kl = t % d.kl;
+    const int o = t / d.kl;           // output within the tile
+    const int ti = o % d.ti, tj = o / d.ti;
+    const int64_t tiles_i = (d.m + d.ti - 1) / d.ti;
+    const int64_t tile = blockIdx.x;
+    const int64_t i = (tile % tiles_i) * d.ti + ti;
+    const int64_t j = (tile / tiles_i) * d.tj + tj;
+    const int64_t k0 = (int64_t)blockIdx.y * d.kchunk;
+    const int64_t k1 = min(d.k, k0 + d.kchunk);
+    float re = 0.f, im = 0.f;
+    if (i < d.m && j < d.n) {
+        for (int64_t l = k0 + kl; l < k1; l += d.kl) {
+            const float2 a = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i, l);
+            const float2 b = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l);
+            re = fmaf(a.x, b.x, re);
+            re = fmaf(-a.y, b.y, re);
+            im = fmaf(a.x, b.y, im);
+            im = fmaf(a.y, b.x, im);
+        }
+    }
+    if (d.kl > 1) {
+        red[t] = make_float2(re, im);
+        __syncthreads();
+        for (int s = d.kl >> 1; s > 0; s >>= 1) {
+            if (kl < s) {
+                const float2 u = red[t + s];
+                red[t].x += u.x;
+                red[t].y += u.y;
+            }
+            __syncthreads();
+        }
+        re = red[t].x;
+        im = red[t].y;
+    }
+    if (kl != 0 || i >= d.m || j >= d.n) return;
+    if (gridDim.y > 1) {
+        d.partial[(int64_t)blockIdx.y * d.m * d.n + i + j * d.m] = make_float2(re, im);
+        return;
+    }
+    float2 out = make_float2(d.alpha.x * re - d.alpha.y * im, d.alpha.x * im + d.alpha.y * re);
+    if (d.alpha.x == 1.f && d.alpha.y == 0.f) out = make_float2(re, im);
+    float2 *cp = d.C + i + j * d.ldc;
+    if (!d.beta_zero) {
+        const float2 c = *cp;
+        out.x += d.beta.x * c.x - d.beta.y * c.y;
+        out.y += d.beta.x * c.y + d.beta.y * c.x;
+    }
+    *cp = out;
+}
+
+__global__ __launch_bounds__(kThreads) void direct_reduce_kernel(DirectArgs d, int splits) {
+    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (o >= d.m * d.n) return;
+    float re = 0.f, im = 0.f;
+    for (int s = 0; s < splits; ++s) {
+        const float2 p = d.partial[(int64_t)s * d.m * d.n + o];
+        re += p.x;
+        im += p.y;
+    }
+    const int64_t i = o % d.m, j = o / d.m;
+    float2 out = make_float2(d.alpha.x * re - d.alpha.y * im, d.alpha.x * im + d.alpha.y * re);
+    if (d.alpha.x == 1.f && d.alpha.y == 0.f) out = make_float2(re, im);
+    float2 *cp = d.C + i + j * d.ldc;
+    if (!d.beta_zero) {
+        const float2 c = *cp;
+        out.x += d.beta.x * c.x - d.beta.y * c.y;
+        out.y += d.beta.x * c.y + d.beta.y * c.x;
+    }
+    *cp = out;
+}
+
+}  // namespace
+
+void direct_plan(DirectArgs &d, int64_t &splits) {
+    // threads per output: enough to fill the block when the output is small,
+    // and to spread a long k
+    const int64_t mn = d.m * d.n;
+    int kl = 1;
+    while (kl < kThreads && mn * kl < kThreads && d.k >= 8 * (int64_t)kl) kl *= 2;
+    d.kl = kl;
+    const int outs = kThreads / kl;  // outputs per block
+    // tile shape: rows first (coalesced column-major access)
+    int ti = 1;
+    while (ti < outs && ti < d.m) ti *= 2;
+    if (ti > outs) ti = outs;
+    d.ti = ti;
+    d.tj = outs / ti;
+    const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);
+    // split k while the grid is small and k is long
+    splits = 1;
+    while (tiles * splits < 1024 && d.k / (splits * 2) >= 256 * (int64_t)kl / 4 && splits < 4096)
+        splits *= 2;
+    d.kchunk = (d.k + splits - 1) / splits;
+    splits = (d.k + d.kchunk - 1) / d.kchunk;
+    if (splits < 1) splits = 1;
+}
+
+size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k) {
+    DirectArgs d{};
+    d.m = m;
+    d.n = n;
+    d.k = k;
+    int64_t splits = 1;
+    direct_plan(d, splits);
+    return splits > 1 ? (size_t)splits * (size_t)(m * n) * sizeof(float2) : 0;
+}
+
+hipError_t launch_direct(DirectArgs d, hipStream_t s) {
+    int64_t splits = 1;
+    direct_plan(d, splits);
+    const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);
+    hipLaunchKernelGGL(direct_kernel, dim3((unsigned)tiles, (unsigned)splits), dim3(kThreads), 0, s, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splits == 1) return e;
+    const int64_t mn = d.m * d.n;
+    hipLaunchKernelGGL(direct_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, d, (int)splits);
+    return hipGetLastError();
+}
+
+}  // namespace qce

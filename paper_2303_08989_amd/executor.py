@@ -40,12 +40,8 @@ class CircuitPlan:
         deps = [frozenset(l for l in self.label_sets[i] if l in S) for i in range(L)]
         for a, b in self.path:
             deps.append(deps[a] | deps[b])
-        # order sliced labels: latest first-use first (they vary fastest)
-        first = {}
-        for s in range(len(self.path)):
-            for lab in deps[L + s]:
-                first.setdefault(lab, s)
-        self.sliced = sorted(sliced, key=lambda lab: (-first.get(lab, 0), lab))
+        # sliced labels entering the tree latest vary fastest
+        self.sliced = tn.order_sliced(self.label_sets, self.path, sliced)
         self.varied = self.sliced[:min(varied, len(self.sliced))]
         self.deps = deps
         self.labels = [tuple(x for x in self.label_sets[i] if x not in S) for i in range(L)]
@@ -57,6 +53,8 @@ class CircuitPlan:
         self.max_log2 = ml
         self.flops_per_slice = fl
         self.gemm_shapes = steps  # log2 (m, n, k) per step
+        self.varied_cost = tn.memoized_cost(self.label_sets, self.path, self.sliced, len(self.varied))
+        self.total_cost = tn.memoized_cost(self.label_sets, self.path, self.sliced, len(self.sliced))
 
     @property
     def n_slices(self):
@@ -93,10 +91,11 @@ class Executor:
                 out[(i, tuple(vals))] = torch.from_numpy(sub).to("cuda")
         return out
 
-    def amplitude(self, x, slice_ids=None, acc=None):
+    def amplitude(self, x, slice_ids=None, acc=None, slice_out=None):
         """Sum over `slice_ids` (default: all) of the sliced network values,
         accumulated in FP64 on the device.  Returns the device float64[2]
-        accumulator."""
+        accumulator.  `slice_out` (device complex64, one entry per slice id)
+        optionally receives each slice's value."""
         import paper_2303_08989_amd as qce
         torch = self.torch
         p = self.plan
@@ -108,6 +107,10 @@ class Executor:
         L = len(p.label_sets)
         pos = {lab: i for i, lab in enumerate(p.sliced)}
         cache = {}  # node -> (key, tensor)
+        root = L + len(p.path) - 1 if p.path else None
+        children = {L + s: (a, b) for s, (a, b) in enumerate(p.path)}
+        varied = set(p.varied)
+        n_done = 0
         for sigma in slice_ids:
             val = {lab: (sigma >> i) & 1 for lab, i in pos.items()}
 
@@ -118,49 +121,50 @@ class Executor:
                 sl = [lab for lab in p.label_sets[i] if lab in pos]
                 return leaves[(i, tuple(val[lab] for lab in sl))]
 
-            def get(node):
-                if node < L:
-                    return leaf(node)
-                k = key_of(node)
+            if root is None:
+                qce.accumulate_f64(self.h, leaf(0).reshape(-1)[:1], acc)
+                if slice_out is not None:
+                    slice_out[n_done:n_done + 1].copy_(leaf(0).reshape(-1)[:1])
+                n_done += 1
+                continue
+            # nodes to (re)compute this slice: top-down from the root, a node
+            # is needed when its parent is recomputed and it is not cached
+            # with the current values of the slice labels it depends on
+            need = set()
+            stack = [root]
+            while stack:
+                node = stack.pop()
                 hit = cache.get(node)
-                if hit is not None and hit[0] == k:
-                    return hit[1]
-                return None
-
-            live = {}
-            result = None
+                if node != root and hit is not None and hit[0] == key_of(node):
+                    continue
+                need.add(node)
+                for ch in children[node]:
+                    if ch >= L:
+                        stack.append(ch)
+            vals = {}
             for s, (a, b) in enumerate(p.path):
                 node = L + s
-                k = key_of(node)
-                hit = cache.get(node)
-                if hit is not None and hit[0] == k:
-                    live[node] = hit[1]
+                if node not in need:
                     continue
-                ta = live.pop(a, None)
-                if ta is None:
-                    ta = get(a)
-                tb = live.pop(b, None)
-                if tb is None:
-                    tb = get(b)
-                la, lb = p.labels[a] if a < L else self._out_labels[a], \
-                    p.labels[b] if b < L else self._out_labels[b]
+                ta = leaf(a) if a < L else (vals.pop(a) if a in vals else cache[a][1])
+                tb = leaf(b) if b < L else (vals.pop(b) if b in vals else cache[b][1])
+                la = p.labels[a] if a < L else self._out_labels[a]
+                lb = p.labels[b] if b < L else self._out_labels[b]
                 shared = set(la) & set(lb)
                 lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
                 self._out_labels[node] = tuple(lc)
                 out = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
-                live[node] = out
-                # keep for later slices when the parent will be recomputed
-                # while this node stays the same
+                vals[node] = out
+                # keep when the parent will be recomputed while this node
+                # stays the same (its sibling depends on a varied label it
+                # does not depend on)
                 par = p.parent.get(node)
-                if par is not None:
-                    sib = par[1]
-                    extra = (p.deps[sib] - p.deps[node]) & set(p.varied)
-                    if extra:
-                        cache[node] = (k, out)
-                    elif node in cache:
-                        del cache[node]
-                result = out
-            root = L + len(p.path) - 1 if p.path else 0
-            scalar = live.get(root, result)
-            qce.accumulate_f64(self.h, scalar.reshape(-1)[:1], acc)
+                if par is not None and (p.deps[par[1]] - p.deps[node]) & varied:
+                    cache[node] = (key_of(node), out)
+                elif node in cache:
+                    del cache[node]
+            qce.accumulate_f64(self.h, vals[root].reshape(-1)[:1], acc)
+            if slice_out is not None:
+                slice_out[n_done:n_done + 1].copy_(vals[root].reshape(-1)[:1])
+            n_done += 1
         return acc

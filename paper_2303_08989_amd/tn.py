@@ -188,20 +188,59 @@ def choose_slices(label_sets, path, max_log2, max_slices=None):
         sliced.append(best)
 
 
+def slice_dependencies(label_sets, path, sliced):
+    """Sliced labels each SSA tensor depends on (those of its leaves)."""
+    S = set(sliced)
+    deps = [frozenset(l for l in ls if l in S) for ls in label_sets]
+    for a, b in path:
+        deps.append(deps[a] | deps[b])
+    return deps
+
+
+def order_sliced(label_sets, path, sliced):
+    """Sliced labels ordered so that the ones entering the tree latest come
+    first (they are the ones varied fastest by a run over slice ids)."""
+    deps = slice_dependencies(label_sets, path, sliced)
+    L = len(label_sets)
+    first = {}
+    for s in range(len(path)):
+        for lab in deps[L + s]:
+            first.setdefault(lab, s)
+    return sorted(sliced, key=lambda lab: (-first.get(lab, 0), lab))
+
+
+def memoized_cost(label_sets, path, sliced, n_varied):
+    """Effective flops of a run over slice ids [0, 2^n_varied) when a node is
+    recomputed only when a varied sliced label it depends on changes."""
+    ordered = order_sliced(label_sets, path, sliced)
+    V = frozenset(ordered[:n_varied])
+    S = frozenset(sliced)
+    deps = slice_dependencies(label_sets, path, sliced)
+    labs = tree_labels(label_sets, path)
+    L = len(label_sets)
+    tot = 0.0
+    for s, (a, b) in enumerate(path):
+        u = (labs[a] | labs[b]) - S
+        tot += 2.0 ** len(deps[L + s] & V) * 8.0 * 2.0 ** len(u)
+    return tot * 2.0 ** max(0, n_varied - len(sliced))
+
+
 def best_greedy(label_sets, restarts=8, max_log2=None, seed=0, noises=(0.1, 0.3, 1.0)):
-    """Best of one deterministic greedy path and `restarts` randomised ones,
-    ranked by (number of sliced labels needed for 2^max_log2, max
-    intermediate, total flops over all slices)."""
+    """Best of one deterministic greedy path and `restarts` randomised ones.
+    With a size bound, each path is sliced to it and ranked by the memoized
+    cost of the whole amplitude (every slice); without, by (max
+    intermediate, flops)."""
     best = None
     for r in range(restarts + 1):
         noise = 0.0 if r == 0 else noises[r % len(noises)]
         p = greedy_path(label_sets, seed=seed + r, noise=noise)
-        ml0, _, _ = path_cost(label_sets, p)
-        if best is not None and max_log2 is not None and ml0 - max_log2 > best[0][0] + 6:
-            continue
-        sl = choose_slices(label_sets, p, max_log2) if max_log2 is not None else []
-        ml, fl, _ = path_cost(label_sets, p, frozenset(sl))
-        key = (len(sl), ml, fl * 2.0 ** len(sl))
+        if max_log2 is None:
+            ml, fl, _ = path_cost(label_sets, p)
+            key = (ml, fl)
+            sl = []
+        else:
+            sl = choose_slices(label_sets, p, max_log2)
+            key = (memoized_cost(label_sets, p, sl, len(sl)), len(sl))
         if best is None or key < best[0]:
             best = (key, p, sl)
     return best[1], best[2]

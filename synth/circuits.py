@@ -39,12 +39,26 @@ def _sqrt_pauli(p):
     return (1 + 1j) / 2 * (_I2 - 1j * p)
 
 
+def _exact_trig(angle):
+    """cos and sin with exact values at multiples of pi/2 (math.cos(pi/2) is
+    6e-17, not 0; the gate's entries there are exactly 0 and +-1)."""
+    q = angle / (math.pi / 2)
+    if abs(q - round(q)) < 1e-12:
+        return {0: (1.0, 0.0), 1: (0.0, 1.0), 2: (-1.0, 0.0), 3: (0.0, -1.0)}[int(round(q)) % 4]
+    return math.cos(angle), math.sin(angle)
+
+
+def _exact_phase(phi):
+    c, s = _exact_trig(phi)
+    return complex(c, s)
+
+
 def fsim(theta, phi):
-    c, s = math.cos(theta), math.sin(theta)
+    c, s = _exact_trig(theta)
     return np.array([[1, 0, 0, 0],
                      [0, c, -1j * s, 0],
                      [0, -1j * s, c, 0],
-                     [0, 0, 0, np.exp(-1j * phi)]], dtype=np.complex128)
+                     [0, 0, 0, _exact_phase(-phi)]], dtype=np.complex128)
 
 
 def gate_matrix(name, theta=math.pi / 2, phi=math.pi / 6):
@@ -57,7 +71,7 @@ def gate_matrix(name, theta=math.pi / 2, phi=math.pi / 6):
     if name == "H":
         return np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
     if name == "T":
-        return np.array([[1, 0], [0, np.exp(1j * math.pi / 4)]], dtype=np.complex128)
+        return np.array([[1, 0], [0, _exact_phase(math.pi / 4)]], dtype=np.complex128)
     if name == "X":
         return _X.copy()
     if name == "I":

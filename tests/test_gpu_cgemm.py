@@ -225,7 +225,7 @@ def test_power_of_two_invariance_auto(qce, handle):
 
 
 def test_nonfinite_forces_fp32_and_propagates(qce, handle):
-    m, n, k = 40, 30, 20
+    m, n, k = 64, 48, 40
     A, B = synth.gemm_operands(m, n, k, "a", seed=4)
     A[3, 5] = np.complex64(complex(np.inf, 0))
     C, dec = run(qce, handle, A, B, m, n, k, mode="auto")
@@ -272,3 +272,43 @@ def test_expstats_exact(qce, handle):
     got = qce.expstats(handle, dev(tiny), 64, 3, 64)
     ref = oracle.exp_stats(tiny)
     assert got["emax"] == ref["emax"] == -132 and got["n2"] == ref["n2"]
+
+
+IRREGULAR = [(1, 1, 5), (1, 1, 100000), (100000, 2, 2), (2, 70000, 2), (300, 400, 3),
+             (31, 500, 600), (500, 31, 600), (64, 64, 15), (1, 300, 4000), (5, 7, 3)]
+
+
+@pytest.mark.parametrize("m,n,k", IRREGULAR)
+@pytest.mark.parametrize("mode", ["auto", "fp16x2", "fp32"])
+def test_irregular_shapes_integer_exact(qce, handle, m, n, k, mode):
+    rng = np.random.default_rng(m + 3 * n + 7 * k)
+    A = synth.random_matrix(m, k, "int", rng)
+    B = synth.random_matrix(k, n, "int", rng)
+    C, dec = run(qce, handle, A, B, m, n, k, mode=mode)
+    assert np.array_equal(C.astype(np.complex128), oracle.cgemm(A, B))
+    assert dec["mode"] == oracle.MODE_FP32 and dec["stats_taken"] == 0
+
+
+@pytest.mark.parametrize("opA,opB", [("T", "N"), ("C", "T"), ("N", "C")])
+def test_irregular_ops_alpha_beta(qce, handle, opA, opB):
+    m, n, k = 3, 2, 50000          # small output, long k: split over k
+    rng = np.random.default_rng(11)
+    sa, sb = shapes_of(m, n, k, opA, opB)
+    A = synth.random_matrix(*sa, "int", rng)
+    B = synth.random_matrix(*sb, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    C, _ = run(qce, handle, A, B, m, n, k, opA, opB, alpha=complex(1, 2), beta=complex(0, -1), C0=C0)
+    want = oracle.cgemm(A, B, opA, opB, alpha=complex(1, 2), beta=complex(0, -1), C0=C0)
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1 << 22), (20000, 3, 5), (8, 9, 300000)])
+def test_irregular_float_accuracy(qce, handle, m, n, k):
+    A, B = synth.gemm_operands(m, n, k, "a", seed=31)
+    exact = oracle.cgemm(A, B)
+    C, _ = run(qce, handle, A, B, m, n, k, mode="auto")
+    tA = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
+    tB = torch.from_numpy(np.ascontiguousarray(B)).to("cuda")
+    Ct = torch.matmul(tA, tB).cpu().numpy()
+    e = oracle.rel_fro(C, exact)
+    assert e <= max(2 * oracle.rel_fro(Ct, exact), 4 * U * math.sqrt(k))
