@@ -35,8 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # MFMA products each mode issues per real product (Eq. 2: three for the FP16
 # two-term split; six for the BF16 three-term split; one for FP32)
 PRODUCTS = {"fp16x2": 3, "fp16x2_scaled": 3, "bf16x3": 6, "fp32": 1}
-KERNEL_OF_PHASE = {"gemm_fp16x2": "gemm_kernel<FP16X2>", "gemm_bf16x3": "gemm_kernel<BF16X3>",
-                   "gemm_fp32": "gemm_kernel<FP32>"}
+# in AUTO mode one launch (gemm_auto_kernel) runs the mode the device selected
+KERNEL_OF_PHASE = {"gemm_fp16x2": "gemm_auto_kernel[fp16x2]", "gemm_bf16x3": "gemm_auto_kernel[bf16x3]",
+                   "gemm_fp32": "gemm_auto_kernel[fp32]"}
 PEAK_OF_PHASE = {"gemm_fp16x2": "fp16", "gemm_bf16x3": "bf16", "gemm_fp32": "fp32"}
 PRODUCTS_OF_PHASE = {"gemm_fp16x2": 3, "gemm_bf16x3": 6, "gemm_fp32": 1}
 
@@ -155,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-circuits", action="store_true", help="skip the circuit-amplitude sections")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
     ap.add_argument("--c3-restarts", type=int, default=24)
     args = ap.parse_args()
@@ -169,6 +172,15 @@ def main():
     from synth.gemm_inputs import case_seed
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        n = args.calib_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": n * 4, "launches": 5}))
+        return
     h = qce.Handle(0)
     h.set_mode("auto")
     h.set_tolerance(0.1, 0.0)

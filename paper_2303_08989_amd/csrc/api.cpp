@@ -24,7 +24,6 @@ struct qce_handle {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_owned = true;
-    bool stats_dirty = false;
     bool have_decision = false;
     bool last_on_device = false;
     qce_decision last_host{};
@@ -94,7 +93,7 @@ bool class_matches(int cls, int mode) {
 }
 
 int class_phase(int cls) {
-    return cls == QCE_MODE_FP16X2 ? QCE_PHASE_GEMM_FP16X2
+    return (cls == QCE_MODE_FP16X2 || cls == QCE_MODE_FP16X2_SCALED) ? QCE_PHASE_GEMM_FP16X2
          : cls == QCE_MODE_BF16X3 ? QCE_PHASE_GEMM_BF16X3 : QCE_PHASE_GEMM_FP32;
 }
 
@@ -123,7 +122,10 @@ hipError_t resolve_timing(qce_handle *h) {
             float ms = 0.f;
             if (r.a && r.b) (void)hipEventElapsedTime(&ms, r.a, r.b);
             r.ms = ms;
-            r.phase = r.kind >= 0 ? r.kind : (class_matches(r.cls, mode) ? class_phase(r.cls) : QCE_PHASE_GEMM_SKIPPED);
+            // cls < 0: one launch that ran the mode it read from the device flag
+            r.phase = r.kind >= 0 ? r.kind
+                    : r.cls < 0 ? class_phase(mode)
+                    : (class_matches(r.cls, mode) ? class_phase(r.cls) : QCE_PHASE_GEMM_SKIPPED);
         }
         if (r.a) h->pool.push_back(r.a);
         if (r.b) h->pool.push_back(r.b);
@@ -287,7 +289,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     int *log = h->timing ? h->mode_log : nullptr;
 
     char *panA = ws;
-    char *panB = ws + align256(panel_bytes(m, k));
+    char *panB = panA + align256(panel_bytes(m, k));
+    char *part = panB + align256(panel_bytes(n, k));
     const MatDesc da = stored_desc(a, m, k), db = stored_desc(b, n, k);
     GemmArgs g{};
     g.panelsA = panA;
@@ -300,18 +303,16 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     g.alpha = alpha;
     g.beta = beta;
     g.beta_zero = beta_zero;
+    g.partial = gemm_partial_bytes(m, n, k) ? reinterpret_cast<float2 *>(part) : nullptr;
     if (mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED) {
         hipEvent_t e0 = span_begin(h);
-        if (h->stats_dirty) QCE_HIP(h, launch_stats_clear(h->st, s));
-        h->stats_dirty = true;
         QCE_HIP(h, launch_stats1(da, db, h->st, s));
         if (mode == QCE_MODE_AUTO) {
             QCE_HIP(h, launch_stats2(da, db, h->st, h->t, 0, s));
-            QCE_HIP(h, launch_select(h->st, h->t, h->t3, -1, log, slot, s));
+            QCE_HIP(h, launch_select(da, db, h->st, h->t, h->t3, -1, log, slot, s));
         } else {
-            QCE_HIP(h, launch_select(h->st, h->t, h->t3, QCE_MODE_FP16X2_SCALED, log, slot, s));
+            QCE_HIP(h, launch_select(da, db, h->st, h->t, h->t3, QCE_MODE_FP16X2_SCALED, log, slot, s));
         }
-        h->stats_dirty = false;
         span_end(h, e0, QCE_PHASE_STATS);
         hipEvent_t e1 = span_begin(h);
         QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, h->st, 0, 0, 0, s));
@@ -319,13 +320,9 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = h->st;
         g.forced_mode = -1;
-        const int classes[3] = {QCE_MODE_FP16X2, QCE_MODE_BF16X3, QCE_MODE_FP32};
-        const int nclass = mode == QCE_MODE_AUTO ? 3 : 1;
-        for (int c = 0; c < nclass; ++c) {
-            hipEvent_t eg = span_begin(h);
-            QCE_HIP(h, launch_gemm(g, classes[c], s));
-            span_end(h, eg, -1, classes[c], -1, call);
-        }
+        hipEvent_t eg = span_begin(h);
+        QCE_HIP(h, launch_gemm(g, -1, s));
+        span_end(h, eg, -1, -1, -1, call);
         if (h->timing) h->recs.push_back({h->tag, -2, 0, -1, call, nullptr, nullptr, false, 0.0, 0});
         h->have_decision = true;
         h->last_on_device = true;
@@ -357,7 +354,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
 size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k) {
     if (k == 0) return 0;
     if (irregular_shape(m, n, k)) return align256(direct_ws_bytes(m, n, k));
-    return align256(panel_bytes(m, k)) + align256(panel_bytes(n, k));
+    return align256(panel_bytes(m, k)) + align256(panel_bytes(n, k)) +
+           align256(gemm_partial_bytes(m, n, k));
 }
 
 bool valid_op(int op) { return op == QCE_OP_N || op == QCE_OP_T || op == QCE_OP_C; }
@@ -617,12 +615,9 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
     hipStream_t s = h->stream;
     MatDesc a{reinterpret_cast<const float2 *>(X), rows, cols, ld};
     MatDesc none{nullptr, 0, 0, 1};
-    if (h->stats_dirty) QCE_HIP(h, launch_stats_clear(h->st, s));
-    h->stats_dirty = true;
     QCE_HIP(h, launch_stats1(a, none, h->st, s));
     QCE_HIP(h, launch_stats2(a, none, h->st, h->t, 2, s));
-    QCE_HIP(h, launch_select(h->st, h->t, h->t3, -2, nullptr, 0, s));
-    h->stats_dirty = false;
+    QCE_HIP(h, launch_select(a, none, h->st, h->t, h->t3, -2, nullptr, 0, s));
     QCE_HIP(h, hipStreamSynchronize(s));
     QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
     return QCE_SUCCESS;

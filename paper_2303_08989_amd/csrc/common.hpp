@@ -22,8 +22,17 @@ struct OperandStats {
     unsigned int pad;
 };
 
+constexpr int kMaxStatsBlocks = 1024;  // per operand
+
+// per-block partial results of the statistics passes (no atomics: the
+// reduction reads them in block order, so results are deterministic)
+struct StatsPartial {
+    unsigned int gt0, ge1, ge3, inf, maxbits, ge2;
+};
+
 struct DevState {
-    OperandStats acc[2];  // accumulated by the statistics kernels, cleared by select
+    StatsPartial part[2][kMaxStatsBlocks];
+    OperandStats acc[2];  // reduced by select (kept for the record)
     int mode;             // selected qce_mode (never AUTO)
     int shift[2];         // power-of-two shifts sA, sB
     int stage2[2];        // 1 if stage 2 ran for that operand
@@ -101,14 +110,14 @@ struct MatDesc {  // a stored column-major complex64 matrix
     int64_t rows, cols, ld;
 };
 
-hipError_t launch_stats_clear(DevState *st, hipStream_t s);
 hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s);
-hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int skip,
+// flag: 0 = stage 2 for operands failing stage 1, 1 = never, 2 = always
+hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int flag,
                          hipStream_t s);
 // forced_mode: -1 = rule, -2 = statistics-only entry point (stage 2 always
 // evaluated), >= 0 = that mode.  mode_log (nullable) receives the mode at slot.
-hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, int *mode_log,
-                         int slot, hipStream_t s);
+hipError_t launch_select(const MatDesc &a, const MatDesc &b, DevState *st, double t, double t3,
+                         int forced_mode, int *mode_log, int slot, hipStream_t s);
 
 // Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
 // kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:
@@ -128,8 +137,12 @@ struct GemmArgs {
     int beta_zero;
     const DevState *st;  // nullable: forced mode
     int forced_mode;
+    float2 *partial;         // split-k partial tiles (workspace), may be null if no split
+    int64_t kpad_per_split;  // set by launch_gemm
 };
+// which_kernel: a mode (forced) or -1 (AUTO: read the device flag)
 hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
+size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k);
 
 // Irregular-shape CGEMM (direct.hip): PA[i][l], PB[j][l] read from the
 // stored matrices as in the split kernel; FP32 arithmetic.

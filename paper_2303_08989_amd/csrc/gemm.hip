@@ -23,8 +23,15 @@
 // two LDS stages: global loads of chunk k+1 are issued before the MFMAs of
 // chunk k and written to the other stage afterwards.
 //
-// Device-side dispatch (Sec. 4.2): every kernel reads the mode flag at entry
-// and returns at once unless it is the selected mode.
+// Device-side dispatch (Sec. 4.2): in AUTO mode a single launch reads the
+// mode flag written by the selection kernel and runs that mode's tile, so no
+// host round trip and no launch of unselected kernels is needed.
+//
+// Split-k: when the output has fewer tiles than the device has CUs and k is
+// long, blockIdx.y splits the k range; partial tiles are added in split order
+// by gemm_reduce_kernel, which also applies the shift, alpha and beta.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace qce {
@@ -214,27 +221,35 @@ __device__ __attribute__((always_inline)) inline void compute_chunk(const char *
     else compute_fp32(sx, sy, wu, wv, lane, acc);
 }
 
+constexpr int kSmemBytes = 2 * 2 * PanelGeom<QCE_MODE_FP16X2>::kChunkBytes;  // largest mode
+static_assert(2 * 2 * PanelGeom<QCE_MODE_BF16X3>::kChunkBytes <= kSmemBytes, "LDS budget");
+static_assert(2 * 2 * PanelGeom<QCE_MODE_FP32>::kChunkBytes <= kSmemBytes, "LDS budget");
+
+// The tile of one workgroup for one mode.  blockIdx.y selects a range of k
+// (split-k): with several ranges the unscaled partial tile goes to
+// g.partial and gemm_reduce_kernel finishes the sum and the epilogue.
 template <int MODE>
-__global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
-    const int mode = g.st ? g.st->mode : g.forced_mode;
-    if constexpr (MODE == QCE_MODE_FP16X2) {
-        if (mode != QCE_MODE_FP16X2 && mode != QCE_MODE_FP16X2_SCALED) return;
-    } else {
-        if (mode != MODE) return;
-    }
+__device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &g, int nbm, int nbn,
+                                                                int mode, char *smem_raw) {
     int shift_total = 0;
     if (MODE == QCE_MODE_FP16X2 && mode == QCE_MODE_FP16X2_SCALED && g.st)
         shift_total = g.st->shift[0] + g.st->shift[1];
 
     using G = PanelGeom<MODE>;
     constexpr int kCB = G::kChunkBytes;
-    constexpr int kLoads = kCB / (16 * kThreads);  // uint4 loads per thread per operand
-    __shared__ __attribute__((aligned(16))) char smem[2][2][kCB];
+    constexpr int kLoads = kCB / (16 * kThreads);  // 16-byte loads per thread per operand
+    typedef char Stage[2][kCB];
+    Stage *smem = reinterpret_cast<Stage *>(smem_raw);
 
     int mb, nb;
     tile_of(blockIdx.x, nbm, nbn, mb, nb);
     const int64_t kpad = round_up(g.k, kKPad);
     const int nkb = (int)(kpad / PanelFmt<MODE>::kBK);
+    // this split's chunk range (split boundaries are multiples of kKPad k-values)
+    constexpr int kChunksPerPad = kKPad / PanelFmt<MODE>::kBK;
+    const int kb0 = (int)((int64_t)blockIdx.y * g.kpad_per_split / PanelFmt<MODE>::kBK);
+    const int kb1 = min(nkb, kb0 + (int)(g.kpad_per_split / PanelFmt<MODE>::kBK));
+    (void)kChunksPerPad;
     const char *px = static_cast<const char *>(g.panelsB) + (int64_t)nb * nkb * kCB;
     const char *py = static_cast<const char *>(g.panelsA) + (int64_t)mb * nkb * kCB;
 
@@ -260,11 +275,13 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, 
     }
 
     u32x4 rx[kLoads], ry[kLoads];
-    if (nkb > 0) {
+    if (kb0 < kb1) {
+        const u32x4 *nx = reinterpret_cast<const u32x4 *>(px + (int64_t)kb0 * kCB);
+        const u32x4 *ny = reinterpret_cast<const u32x4 *>(py + (int64_t)kb0 * kCB);
 #pragma unroll
         for (int i = 0; i < kLoads; ++i) {
-            rx[i] = reinterpret_cast<const u32x4 *>(px)[tid + i * kThreads];
-            ry[i] = reinterpret_cast<const u32x4 *>(py)[tid + i * kThreads];
+            rx[i] = nx[tid + i * kThreads];
+            ry[i] = ny[tid + i * kThreads];
         }
 #pragma unroll
         for (int i = 0; i < kLoads; ++i) {
@@ -273,9 +290,9 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, 
         }
         __syncthreads();
     }
-    for (int kb = 0; kb < nkb; ++kb) {
-        const int cur = kb & 1;
-        const bool more = kb + 1 < nkb;
+    for (int kb = kb0; kb < kb1; ++kb) {
+        const int cur = (kb - kb0) & 1;
+        const bool more = kb + 1 < kb1;
         if (more) {
             const u32x4 *nx = reinterpret_cast<const u32x4 *>(px + (int64_t)(kb + 1) * kCB);
             const u32x4 *ny = reinterpret_cast<const u32x4 *>(py + (int64_t)(kb + 1) * kCB);
@@ -296,7 +313,8 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, 
         __syncthreads();
     }
 
-    // epilogue: D[j][i] -> C[i][j]
+    // epilogue: D[j][i] -> C[i][j] (or the split's partial tile)
+    const bool split = gridDim.y > 1;
     const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
     const int l32 = lane & 31, hi = lane >> 5;
 #pragma unroll
@@ -312,16 +330,20 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, 
                 if constexpr (MODE == QCE_MODE_FP16X2) {
                     re = acc.re_m[ub][vb][r] + acc.re_c[ub][vb][r] * (1.0f / 2048.0f);
                     im = acc.im_m[ub][vb][r] + acc.im_c[ub][vb][r] * (1.0f / 2048.0f);
-                    if (shift_total) {
-                        re = ldexpf(re, -shift_total);
-                        im = ldexpf(im, -shift_total);
-                    }
                 } else if constexpr (MODE == QCE_MODE_BF16X3) {
                     re = acc.re_m[ub][vb][r] + acc.re_c[ub][vb][r];
                     im = acc.im_m[ub][vb][r] + acc.im_c[ub][vb][r];
                 } else {
                     re = acc.re_m[ub][vb][r];
                     im = acc.im_m[ub][vb][r];
+                }
+                if (split) {
+                    g.partial[(int64_t)blockIdx.y * g.m * g.n + i + j * g.m] = make_float2(re, im);
+                    continue;
+                }
+                if (shift_total) {
+                    re = ldexpf(re, -shift_total);
+                    im = ldexpf(im, -shift_total);
                 }
                 float2 out;
                 if (alpha_one) {
@@ -340,6 +362,54 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, 
         }
 }
 
+// Forced mode: one kernel per mode.
+template <int MODE>
+__global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * 2 * PanelGeom<MODE>::kChunkBytes];
+    gemm_body<MODE>(g, nbm, nbn, g.forced_mode, smem);
+}
+
+// Statistics-selected mode: one launch that reads the device mode flag and
+// runs the selected mode's tile (the others never start).
+__global__ __launch_bounds__(kThreads, 1) void gemm_auto_kernel(GemmArgs g, int nbm, int nbn) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemBytes];
+    const int mode = g.st->mode;
+    if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
+        gemm_body<QCE_MODE_FP16X2>(g, nbm, nbn, mode, smem);
+    else if (mode == QCE_MODE_BF16X3)
+        gemm_body<QCE_MODE_BF16X3>(g, nbm, nbn, mode, smem);
+    else
+        gemm_body<QCE_MODE_FP32>(g, nbm, nbn, mode, smem);
+}
+
+// Split-k: add the partial tiles in split order, then shift / alpha / beta.
+__global__ __launch_bounds__(kThreads) void gemm_reduce_kernel(GemmArgs g, int splits) {
+    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (o >= g.m * g.n) return;
+    const int mode = g.st ? g.st->mode : g.forced_mode;
+    const int shift_total = (mode == QCE_MODE_FP16X2_SCALED && g.st) ? g.st->shift[0] + g.st->shift[1] : 0;
+    float re = 0.f, im = 0.f;
+    for (int s = 0; s < splits; ++s) {
+        const float2 p = g.partial[(int64_t)s * g.m * g.n + o];
+        re += p.x;
+        im += p.y;
+    }
+    if (shift_total) {
+        re = ldexpf(re, -shift_total);
+        im = ldexpf(im, -shift_total);
+    }
+    const int64_t i = o % g.m, j = o / g.m;
+    float2 out = make_float2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+    if (g.alpha.x == 1.f && g.alpha.y == 0.f) out = make_float2(re, im);
+    float2 *cp = g.C + i + j * g.ldc;
+    if (!g.beta_zero) {
+        const float2 c = *cp;
+        out.x += g.beta.x * c.x - g.beta.y * c.y;
+        out.y += g.beta.x * c.y + g.beta.y * c.x;
+    }
+    *cp = out;
+}
+
 __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta,
                                int beta_zero) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,16 +426,47 @@ __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, flo
 
 }  // namespace
 
-hipError_t launch_gemm(const GemmArgs &g, int which, hipStream_t s) {
+int gemm_splits(int64_t m, int64_t n, int64_t k) {
+    const int64_t tiles = ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
+    const int64_t pads = round_up(k, kKPad) / kKPad;  // 32-value k groups
+    if (tiles >= 256 || pads < 16) return 1;
+    int64_t s = 512 / tiles;          // aim at ~512 workgroups
+    s = std::min<int64_t>(s, pads / 8);  // keep >= 8 groups (256 k-values) per split
+    return (int)std::max<int64_t>(1, s);
+}
+
+hipError_t launch_gemm(const GemmArgs &g0, int which, hipStream_t s) {
+    GemmArgs g = g0;
     const int nbm = (int)((g.m + kTile - 1) / kTile), nbn = (int)((g.n + kTile - 1) / kTile);
-    const dim3 grid((unsigned)(nbm * nbn)), block(kThreads);
-    if (which == QCE_MODE_FP16X2)
+    const int splits = gemm_splits(g.m, g.n, g.k);
+    const int64_t pads = round_up(g.k, kKPad) / kKPad;
+    g.kpad_per_split = ((pads + splits - 1) / splits) * kKPad;
+    const int nsplit = (int)((round_up(g.k, kKPad) + g.kpad_per_split - 1) / g.kpad_per_split);
+    const dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit), block(kThreads);
+    if (nsplit > 1 && !g.partial) return hipErrorInvalidValue;
+    if (which < 0)
+        hipLaunchKernelGGL(gemm_auto_kernel, grid, block, 0, s, g, nbm, nbn);
+    else if (which == QCE_MODE_FP16X2)
         hipLaunchKernelGGL(gemm_kernel<QCE_MODE_FP16X2>, grid, block, 0, s, g, nbm, nbn);
     else if (which == QCE_MODE_BF16X3)
         hipLaunchKernelGGL(gemm_kernel<QCE_MODE_BF16X3>, grid, block, 0, s, g, nbm, nbn);
     else
         hipLaunchKernelGGL(gemm_kernel<QCE_MODE_FP32>, grid, block, 0, s, g, nbm, nbn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit == 1) return e;
+    const int64_t mn = g.m * g.n;
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads)), block, 0, s, g,
+                       nsplit);
     return hipGetLastError();
+}
+
+size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k) {
+    const int splits = gemm_splits(m, n, k);
+    if (splits <= 1) return 0;
+    const int64_t pads = round_up(k, kKPad) / kKPad;
+    const int64_t per = ((pads + splits - 1) / splits) * kKPad;
+    const int64_t nsplit = (round_up(k, kKPad) + per - 1) / per;
+    return nsplit > 1 ? (size_t)nsplit * (size_t)(m * n) * sizeof(float2) : 0;
 }
 
 hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,

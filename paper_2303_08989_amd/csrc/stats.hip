@@ -1,18 +1,20 @@
 // Exponent statistics and mode selection (Sec. 4.1 and 4.2).
 //
 // stats1 reads every FP32 component of both operands once (Sec. 4: all
-// elements are checked, no sampling) and accumulates, per operand: nnz, the
-// stage-1 count n1 = #{|v| >= 2^-14}, the BF16X3-floor count
+// elements are checked, no sampling) and writes, per block: the nonzero count,
+// the stage-1 count n1 = #{|v| >= 2^-14}, the BF16X3-floor count
 // n3 = #{|v| >= 2^-110}, the non-finite count and the largest |v| bit
 // pattern, from which emax = floor(log2 max|v|) follows.  Positive FP32 bit
 // patterns order like their values, so every count is one integer compare of
 // the absolute bit pattern.
-// stats2 (stage 2) runs over an operand only when stage 1 failed for it, and
+// stats2 (stage 2): each block first adds up the stage-1 partials of its
+// operand; it scans the operand again only when stage 1 failed for it, and
 // counts n2 = #{|v| >= 2^(emax-28)}: the elements inside the FP16 window once
 // emax is shifted to 14.
-// select turns both operands' statistics into the device mode flag and the
-// shifts, keeps a record for the host, and clears the accumulators for the
-// next call.  Nothing is copied to the host (Sec. 4.2).
+// select adds up the partials, turns both operands' statistics into the
+// device mode flag and the shifts and keeps a record for the host.  Partials
+// are summed in block order (no atomics), so the statistics are exact and
+// deterministic, and nothing is copied to the host (Sec. 4.2).
 #include "common.hpp"
 
 namespace qce {
@@ -119,9 +121,8 @@ __device__ inline unsigned long long block_sum(unsigned long long v, unsigned lo
     if (l == 0) sh[w] = v;
     __syncthreads();
     unsigned long long r = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
-    return r;  // valid in thread 0
+    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+    return r;  // valid in every thread
 }
 
 __device__ inline unsigned int block_max(unsigned int v, unsigned long long *sh) {
@@ -131,19 +132,40 @@ __device__ inline unsigned int block_max(unsigned int v, unsigned long long *sh)
     if (l == 0) sh[w] = v;
     __syncthreads();
     unsigned int r = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kThreads / 64; ++i) r = max(r, (unsigned int)sh[i]);
-    return r;
+    for (int i = 0; i < kThreads / 64; ++i) r = max(r, (unsigned int)sh[i]);
+    return r;  // valid in every thread
 }
 
-__global__ __launch_bounds__(kThreads) void stats_clear_kernel(DevState *st) {
-    if (threadIdx.x == 0) {
-        for (int o = 0; o < 2; ++o) {
-            st->acc[o].nnz = st->acc[o].n1 = st->acc[o].n2 = st->acc[o].n3 = 0;
-            st->acc[o].nonfinite = 0;
-            st->acc[o].maxbits = 0;
-        }
+// Stage-1 totals of one operand from its per-block partials, added in block
+// order; every thread of the calling block gets the result.
+__device__ inline OperandStats reduce_partials(const DevState *st, int op, int nb, bool with_ge2,
+                                               unsigned long long *sh) {
+    unsigned long long gt0 = 0, ge1 = 0, ge3 = 0, inf = 0, ge2 = 0;
+    unsigned int maxb = 0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) {
+        const StatsPartial &p = st->part[op][i];
+        gt0 += p.gt0;
+        ge1 += p.ge1;
+        ge3 += p.ge3;
+        inf += p.inf;
+        maxb = max(maxb, p.maxbits);
+        if (with_ge2) ge2 += p.ge2;
     }
+    OperandStats s;
+    gt0 = block_sum(gt0, sh);
+    ge1 = block_sum(ge1, sh);
+    ge3 = block_sum(ge3, sh);
+    inf = block_sum(inf, sh);
+    ge2 = with_ge2 ? block_sum(ge2, sh) : 0;
+    s.maxbits = block_max(maxb, sh);
+    // every count of "|v| >= x" includes the non-finite values; remove them
+    s.nnz = gt0 - inf;
+    s.n1 = ge1 - inf;
+    s.n3 = ge3 - inf;
+    s.n2 = ge2;
+    s.nonfinite = inf;
+    s.pad = 0;
+    return s;
 }
 
 __global__ __launch_bounds__(kThreads) void stats1_kernel(MatDesc a, MatDesc b, int blocks_a,
@@ -155,19 +177,19 @@ __global__ __launch_bounds__(kThreads) void stats1_kernel(MatDesc a, MatDesc b, 
     const int64_t nblk = is_a ? blocks_a : gridDim.x - blocks_a;
     Stage1Counter c;
     scan_matrix(d, blk, nblk, c);
-    unsigned long long gt0 = block_sum(c.gt0, sh);
-    unsigned long long ge1 = block_sum(c.ge1, sh);
-    unsigned long long ge3 = block_sum(c.ge3, sh);
-    unsigned long long inf = block_sum(c.inf, sh);
-    unsigned int maxb = block_max(c.maxb, sh);
+    const unsigned long long gt0 = block_sum(c.gt0, sh);
+    const unsigned long long ge1 = block_sum(c.ge1, sh);
+    const unsigned long long ge3 = block_sum(c.ge3, sh);
+    const unsigned long long inf = block_sum(c.inf, sh);
+    const unsigned int maxb = block_max(c.maxb, sh);
     if (threadIdx.x == 0) {
-        OperandStats &s = st->acc[is_a ? 0 : 1];
-        // every count of "|v| >= x" includes the non-finite values; remove them
-        if (gt0 - inf) atomicAdd(&s.nnz, gt0 - inf);
-        if (ge1 - inf) atomicAdd(&s.n1, ge1 - inf);
-        if (ge3 - inf) atomicAdd(&s.n3, ge3 - inf);
-        if (inf) atomicAdd(&s.nonfinite, inf);
-        if (maxb) atomicMax(&s.maxbits, maxb);
+        StatsPartial &p = st->part[is_a ? 0 : 1][blk];
+        p.gt0 = (unsigned int)gt0;
+        p.ge1 = (unsigned int)ge1;
+        p.ge3 = (unsigned int)ge3;
+        p.inf = (unsigned int)inf;
+        p.maxbits = maxb;
+        p.ge2 = 0;
     }
 }
 
@@ -182,16 +204,17 @@ __global__ __launch_bounds__(kThreads) void stats2_kernel(MatDesc a, MatDesc b, 
                                                           DevState *st, double t, int flag) {
     __shared__ unsigned long long sh[kThreads / 64];
     const bool is_a = (int)blockIdx.x < blocks_a;
-    OperandStats &s = st->acc[is_a ? 0 : 1];
-    if (!stage2_runs(s, t, flag)) return;  // uniform over the block
-    const MatDesc &d = is_a ? a : b;
+    const int op = is_a ? 0 : 1;
     const int64_t blk = is_a ? blockIdx.x : blockIdx.x - blocks_a;
     const int64_t nblk = is_a ? blocks_a : gridDim.x - blocks_a;
+    const OperandStats s = reduce_partials(st, op, (int)nblk, false, sh);
+    if (!stage2_runs(s, t, flag)) return;  // uniform over the block
+    const MatDesc &d = is_a ? a : b;
     Stage2Counter c;
     c.thr = pow2_bits(emax_of_bits(s.maxbits) - kWindowSpan);
     scan_matrix(d, blk, nblk, c);
-    unsigned long long ge = block_sum(c.ge, sh);
-    if (threadIdx.x == 0 && ge) atomicAdd(&s.n2, ge);
+    const unsigned long long ge = block_sum(c.ge, sh);
+    if (threadIdx.x == 0) st->part[op][blk].ge2 = (unsigned int)ge;
 }
 
 // Per-operand tolerance level (Sec. 4.1): FP16 if every element but a
@@ -209,64 +232,59 @@ __device__ inline int operand_level(const OperandStats &s, double t, double t3, 
     return QCE_MODE_FP32;
 }
 
-__global__ void select_kernel(DevState *st, double t, double t3, int forced, int stage2_flag,
-                              int *mode_log, int slot) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int level[2];
+__global__ __launch_bounds__(kThreads) void select_kernel(int blocks_a, int blocks_b, DevState *st,
+                                                          double t, double t3, int forced,
+                                                          int stage2_flag, int *mode_log, int slot) {
+    __shared__ unsigned long long sh[kThreads / 64];
+    OperandStats s[2];
     bool ran[2];
     for (int o = 0; o < 2; ++o) {
-        ran[o] = stage2_runs(st->acc[o], t, stage2_flag);
-        level[o] = operand_level(st->acc[o], t, t3, ran[o]);
+        const int nb = o == 0 ? blocks_a : blocks_b;
+        s[o] = reduce_partials(st, o, nb, false, sh);
+        ran[o] = stage2_runs(s[o], t, stage2_flag);  // uniform over the block
+        if (ran[o]) s[o].n2 = reduce_partials(st, o, nb, true, sh).n2;
     }
-    int mode = forced >= 0 ? forced : max(level[0], level[1]);
-    int sh[2] = {0, 0};
+    if (threadIdx.x != 0) return;
+    int level[2];
+    for (int o = 0; o < 2; ++o) level[o] = operand_level(s[o], t, t3, ran[o]);
+    const int mode = forced >= 0 ? forced : max(level[0], level[1]);
+    int shv[2] = {0, 0};
     if (mode == QCE_MODE_FP16X2_SCALED)
-        for (int o = 0; o < 2; ++o)
-            sh[o] = st->acc[o].nnz ? kFp16Emax - emax_of_bits(st->acc[o].maxbits) : 0;
+        for (int o = 0; o < 2; ++o) shv[o] = s[o].nnz ? kFp16Emax - emax_of_bits(s[o].maxbits) : 0;
     st->mode = mode;
     if (mode_log) mode_log[slot] = mode;
-    st->shift[0] = sh[0];
-    st->shift[1] = sh[1];
+    st->shift[0] = shv[0];
+    st->shift[1] = shv[1];
     qce_decision &r = st->last;
     r.mode = mode;
-    r.sA = sh[0];
-    r.sB = sh[1];
+    r.sA = shv[0];
+    r.sB = shv[1];
     r.stats_taken = 1;
     for (int o = 0; o < 2; ++o) {
-        const OperandStats &s = st->acc[o];
+        st->acc[o] = s[o];
         st->stage2[o] = ran[o];
-        r.nnz[o] = (int64_t)s.nnz;
-        r.n1[o] = (int64_t)s.n1;
-        r.n2[o] = ran[o] ? (int64_t)s.n2 : -1;
-        r.n3[o] = (int64_t)s.n3;
-        r.nonfinite[o] = (int64_t)s.nonfinite;
-        r.emax[o] = s.nnz ? emax_of_bits(s.maxbits) : INT32_MIN;
-    }
-    for (int o = 0; o < 2; ++o) {
-        OperandStats &s = st->acc[o];
-        s.nnz = s.n1 = s.n2 = s.n3 = s.nonfinite = 0;
-        s.maxbits = 0;
+        r.nnz[o] = (int64_t)s[o].nnz;
+        r.n1[o] = (int64_t)s[o].n1;
+        r.n2[o] = ran[o] ? (int64_t)s[o].n2 : -1;
+        r.n3[o] = (int64_t)s[o].n3;
+        r.nonfinite[o] = (int64_t)s[o].nonfinite;
+        r.emax[o] = s[o].nnz ? emax_of_bits(s[o].maxbits) : INT32_MIN;
     }
 }
 
 int stats_blocks(int64_t nf) {
     // enough blocks to cover the device several times, not more than needed
-    int64_t per_block = (int64_t)kThreads * 32;  // ~32 floats per thread minimum
+    const int64_t per_block = (int64_t)kThreads * 64;  // >= 64 floats per thread
     int64_t b = (nf + per_block - 1) / per_block;
     if (b < 1) b = 1;
-    if (b > 1024) b = 1024;
+    if (b > 512) b = 512;
     return (int)b;
 }
 
 }  // namespace
 
-hipError_t launch_stats_clear(DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(stats_clear_kernel, dim3(1), dim3(64), 0, s, st);
-    return hipGetLastError();
-}
-
 hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s) {
-    int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
+    const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
     hipLaunchKernelGGL(stats1_kernel, dim3(ba + bb), dim3(kThreads), 0, s, a, b, ba, st);
     return hipGetLastError();
 }
@@ -274,19 +292,20 @@ hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipSt
 hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int flag,
                          hipStream_t s) {
     if (flag == 1) return hipSuccess;
-    int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
+    const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
     hipLaunchKernelGGL(stats2_kernel, dim3(ba + bb), dim3(kThreads), 0, s, a, b, ba, st, t, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_select(DevState *st, double t, double t3, int forced_mode, int *mode_log,
-                         int slot, hipStream_t s) {
+hipError_t launch_select(const MatDesc &a, const MatDesc &b, DevState *st, double t, double t3,
+                         int forced_mode, int *mode_log, int slot, hipStream_t s) {
     // stage-2 flag as used by launch_stats2: forced modes skip stage 2,
     // forced_mode == -2 is the statistics-only entry point (stage 2 always)
-    int flag = forced_mode == -1 ? 0 : (forced_mode == -2 ? 2 : 1);
-    int forced = forced_mode < 0 ? -1 : forced_mode;
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, st, t, t3, forced, flag, mode_log,
-                       slot);
+    const int flag = forced_mode == -1 ? 0 : (forced_mode == -2 ? 2 : 1);
+    const int forced = forced_mode < 0 ? -1 : forced_mode;
+    const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kThreads), 0, s, ba, bb, st, t, t3, forced, flag,
+                       mode_log, slot);
     return hipGetLastError();
 }
 

@@ -312,3 +312,28 @@ def test_irregular_float_accuracy(qce, handle, m, n, k):
     Ct = torch.matmul(tA, tB).cpu().numpy()
     e = oracle.rel_fro(C, exact)
     assert e <= max(2 * oracle.rel_fro(Ct, exact), 4 * U * math.sqrt(k))
+
+
+@pytest.mark.parametrize("mode", ["auto", "fp16x2", "fp16x2_scaled", "bf16x3", "fp32"])
+@pytest.mark.parametrize("m,n,k", [(200, 150, 5000), (256, 256, 8192), (130, 1000, 3000)])
+def test_split_k_integer_exact(qce, handle, mode, m, n, k):
+    # few output tiles and a long k: the k range is split over workgroups
+    rng = np.random.default_rng(m + n + k)
+    A = synth.random_matrix(m, k, "int", rng)
+    B = synth.random_matrix(k, n, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    C, _ = run(qce, handle, A, B, m, n, k, alpha=complex(1, -1), beta=complex(2, 0), C0=C0, mode=mode)
+    want = oracle.cgemm(A, B, alpha=complex(1, -1), beta=complex(2, 0), C0=C0)
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
+@pytest.mark.parametrize("dist", ["a", "b", "c"])
+def test_split_k_float_accuracy(qce, handle, dist):
+    m, n, k = 300, 200, 20000
+    A, B = synth.gemm_operands(m, n, k, dist, seed=77)
+    A = (A * np.float32(2.0 ** -20)).astype(np.complex64)   # scaled mode for dist a
+    exact = oracle.cgemm(A, B)
+    C, dec = run(qce, handle, A, B, m, n, k, mode="auto")
+    C32, Ct = _fp32_refs(qce, handle, A, B, m, n, k)
+    e_fp32 = min(oracle.rel_fro(C32, exact), oracle.rel_fro(Ct, exact))
+    assert oracle.rel_fro(C, exact) <= 2.0 * e_fp32, (dec["mode_name"],)
