@@ -61,9 +61,9 @@ constexpr int kWindowSpan = kFp16Emax - kFp16Emin;  // 28: FP16 window [-14, 14]
 constexpr int kPanelRows = 128;
 
 template <int MODE> struct PanelFmt;
-// FP16X2: planes hi(re), lo(re), hi(im), lo(im); FP16; 32 k per chunk.
+// FP16X2: planes hi(re), lo(re), hi(im), lo(im); FP16; 16 k per chunk.
 template <> struct PanelFmt<QCE_MODE_FP16X2> {
-    static constexpr int kPlanes = 4, kBK = 32, kElemBytes = 2;
+    static constexpr int kPlanes = 4, kBK = 16, kElemBytes = 2;
 };
 // BF16X3: planes b0(re), b1(re), b2(re), b0(im), b1(im), b2(im); 16 k per chunk.
 template <> struct PanelFmt<QCE_MODE_BF16X3> {
@@ -76,13 +76,18 @@ template <> struct PanelFmt<QCE_MODE_FP32> {
 
 template <int MODE> struct PanelGeom {
     using F = PanelFmt<MODE>;
-    static constexpr int kRowBytes = F::kBK * F::kElemBytes;          // 64 or 32
-    static constexpr int kGranules = kRowBytes / 16;                  // 4 or 2
+    static constexpr int kRowBytes = F::kBK * F::kElemBytes;          // 32 (fp16/bf16) or 64 (fp32)
+    static constexpr int kGranules = kRowBytes / 16;                  // 2 or 4
     static constexpr int kPlaneBytes = kPanelRows * kRowBytes;
     static constexpr int kChunkBytes = F::kPlanes * kPlaneBytes;
     static constexpr int kKPerGranule = 16 / F::kElemBytes;           // 8 or 4
+    // Granule XOR swizzle: for the MFMA fragment reads (32 consecutive rows,
+    // one granule) every group of 8 or 16 consecutive lanes hits distinct
+    // 16-byte bank slots, i.e. conflict-free for 128- or 256-byte LDS
+    // bank rows.
     __host__ __device__ static constexpr int swz(int row) {
-        return kGranules == 4 ? ((row >> 1) & 3) : ((row >> 2) & 1);
+        return kGranules == 4 ? (((row >> 2) & 1) | ((((row >> 1) ^ (row >> 3)) & 1) << 1))
+                              : (((row >> 2) ^ (row >> 3)) & 1);
     }
     // byte offset of (plane, row, granule) inside a chunk
     __host__ __device__ static constexpr int offset(int plane, int row, int granule) {
@@ -90,8 +95,8 @@ template <int MODE> struct PanelGeom {
     }
 };
 
-// k is padded to a multiple of this for every mode (lcm of the BK values).
-constexpr int kKPad = 32;
+// k is padded to a multiple of this for every mode (the chunk depth).
+constexpr int kKPad = 16;
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -101,6 +106,8 @@ inline size_t panel_bytes(int64_t rows, int64_t k) {
     int64_t r = round_up(rows, kPanelRows), kk = round_up(k, kKPad);
     return (size_t)r * (size_t)kk * 12u;  // BF16X3: 6 planes x 2 bytes
 }
+static_assert(PanelFmt<QCE_MODE_FP16X2>::kBK == kKPad && PanelFmt<QCE_MODE_BF16X3>::kBK == kKPad &&
+                  PanelFmt<QCE_MODE_FP32>::kBK == kKPad, "one chunk depth for every mode");
 
 // ---------------------------------------------------------------------------
 // Launch wrappers implemented in the .hip files.

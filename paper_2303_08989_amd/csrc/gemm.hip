@@ -82,53 +82,82 @@ __device__ inline void tile_of(int bid, int nbm, int nbn, int &mb, int &nb) {
     nb = in / gm;
 }
 
+#define LDS_PTR(p) ((__attribute__((address_space(3))) void *)(p))
+
+// Wait until at most N vector-memory operations of this wave are
+// outstanding (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14, expcnt
+// and lgkmcnt left at their "no wait" maxima).
+template <int N>
+__device__ __attribute__((always_inline)) inline void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Wait until every LDS read of this wave has completed (lgkmcnt 0, vmcnt and
+// expcnt left at their maxima).
+__device__ __attribute__((always_inline)) inline void wait_lgkm0() {
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+}
+
+// LDS stages of the chunk ring per mode (stage = one chunk of each operand)
+template <int MODE> struct Stages { static constexpr int kNS = 4; };
+template <> struct Stages<QCE_MODE_BF16X3> { static constexpr int kNS = 3; };
+
 template <int MODE> struct Acc;
 template <> struct Acc<QCE_MODE_FP16X2> { floatx16 re_m[2][2], im_m[2][2], re_c[2][2], im_c[2][2]; };
 template <> struct Acc<QCE_MODE_BF16X3> { floatx16 re_m[2][2], im_m[2][2], re_c[2][2], im_c[2][2]; };
 template <> struct Acc<QCE_MODE_FP32> { floatx16 re_m[2][2], im_m[2][2]; };
 
-// one chunk of FP16X2 panels in LDS: 2 k16 steps
+// 12 MFMAs of one 32x32 block for one k16 step (planes: 0 = hi(re),
+// 1 = lo(re), 2 = hi(im), 3 = lo(im); nx = -hi(im), -lo(im) of x)
+__device__ __attribute__((always_inline)) inline void fp16x2_block(const u32x4 *x, const u32x4 *nx,
+                                                                   const u32x4 *y, floatx16 &re_m,
+                                                                   floatx16 &im_m, floatx16 &re_c,
+                                                                   floatx16 &im_c) {
+    re_c = mfma16(x[1], y[0], re_c);
+    re_c = mfma16(x[0], y[1], re_c);
+    re_c = mfma16(nx[1], y[2], re_c);
+    re_c = mfma16(nx[0], y[3], re_c);
+    im_c = mfma16(x[1], y[2], im_c);
+    im_c = mfma16(x[0], y[3], im_c);
+    im_c = mfma16(x[3], y[0], im_c);
+    im_c = mfma16(x[2], y[1], im_c);
+    re_m = mfma16(x[0], y[0], re_m);
+    re_m = mfma16(nx[0], y[2], re_m);
+    im_m = mfma16(x[0], y[2], im_m);
+    im_m = mfma16(x[2], y[0], im_m);
+}
+
+// one chunk of FP16X2 panels in LDS: one k16 step.  Fragments are read in
+// the order the 2x2 blocks use them, so the first block's MFMAs can start
+// while the remaining fragments are still in flight.
 __device__ __attribute__((always_inline)) inline void compute_fp16x2(const char *sx, const char *sy, int wu, int wv, int lane,
                                       Acc<QCE_MODE_FP16X2> &acc) {
     using G = PanelGeom<QCE_MODE_FP16X2>;
-    const int l32 = lane & 31, hi = lane >> 5;
+    const int l32 = lane & 31, gr = lane >> 5;
+    u32x4 x[2][4], y[2][4], nx[2][2];
+    auto load_x = [&](int ub) {
+        const int row = wu * 64 + ub * 32 + l32;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        const int gr = 2 * ks + hi;
-        u32x4 x[2][4], y[2][4], nxi[2][2];
+        for (int p = 0; p < 4; ++p) x[ub][p] = *reinterpret_cast<const u32x4 *>(sx + G::offset(p, row, gr));
+    };
+    auto load_y = [&](int vb) {
+        const int row = wv * 64 + vb * 32 + l32;
 #pragma unroll
-        for (int ub = 0; ub < 2; ++ub) {
-            const int row = wu * 64 + ub * 32 + l32;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) x[ub][p] = *reinterpret_cast<const u32x4 *>(sx + G::offset(p, row, gr));
-            nxi[ub][0] = neg_halves(x[ub][2]);
-            nxi[ub][1] = neg_halves(x[ub][3]);
-        }
-#pragma unroll
-        for (int vb = 0; vb < 2; ++vb) {
-            const int row = wv * 64 + vb * 32 + l32;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) y[vb][p] = *reinterpret_cast<const u32x4 *>(sy + G::offset(p, row, gr));
-        }
-        // planes: 0 = hi(re), 1 = lo(re), 2 = hi(im), 3 = lo(im)
-#pragma unroll
-        for (int ub = 0; ub < 2; ++ub)
-#pragma unroll
-            for (int vb = 0; vb < 2; ++vb) {
-                acc.re_c[ub][vb] = mfma16(x[ub][1], y[vb][0], acc.re_c[ub][vb]);
-                acc.re_c[ub][vb] = mfma16(x[ub][0], y[vb][1], acc.re_c[ub][vb]);
-                acc.re_c[ub][vb] = mfma16(nxi[ub][1], y[vb][2], acc.re_c[ub][vb]);
-                acc.re_c[ub][vb] = mfma16(nxi[ub][0], y[vb][3], acc.re_c[ub][vb]);
-                acc.im_c[ub][vb] = mfma16(x[ub][1], y[vb][2], acc.im_c[ub][vb]);
-                acc.im_c[ub][vb] = mfma16(x[ub][0], y[vb][3], acc.im_c[ub][vb]);
-                acc.im_c[ub][vb] = mfma16(x[ub][3], y[vb][0], acc.im_c[ub][vb]);
-                acc.im_c[ub][vb] = mfma16(x[ub][2], y[vb][1], acc.im_c[ub][vb]);
-                acc.re_m[ub][vb] = mfma16(x[ub][0], y[vb][0], acc.re_m[ub][vb]);
-                acc.re_m[ub][vb] = mfma16(nxi[ub][0], y[vb][2], acc.re_m[ub][vb]);
-                acc.im_m[ub][vb] = mfma16(x[ub][0], y[vb][2], acc.im_m[ub][vb]);
-                acc.im_m[ub][vb] = mfma16(x[ub][2], y[vb][0], acc.im_m[ub][vb]);
-            }
-    }
+        for (int p = 0; p < 4; ++p) y[vb][p] = *reinterpret_cast<const u32x4 *>(sy + G::offset(p, row, gr));
+    };
+    load_x(0);
+    load_y(0);
+    load_y(1);
+    load_x(1);
+    nx[0][0] = neg_halves(x[0][2]);
+    nx[0][1] = neg_halves(x[0][3]);
+    fp16x2_block(x[0], nx[0], y[0], acc.re_m[0][0], acc.im_m[0][0], acc.re_c[0][0], acc.im_c[0][0]);
+    fp16x2_block(x[0], nx[0], y[1], acc.re_m[0][1], acc.im_m[0][1], acc.re_c[0][1], acc.im_c[0][1]);
+    nx[1][0] = neg_halves(x[1][2]);
+    nx[1][1] = neg_halves(x[1][3]);
+    fp16x2_block(x[1], nx[1], y[0], acc.re_m[1][0], acc.im_m[1][0], acc.re_c[1][0], acc.im_c[1][0]);
+    fp16x2_block(x[1], nx[1], y[1], acc.re_m[1][1], acc.im_m[1][1], acc.re_c[1][1], acc.im_c[1][1]);
 }
 
 // one chunk of BF16X3 panels in LDS: 1 k16 step
@@ -221,9 +250,65 @@ __device__ __attribute__((always_inline)) inline void compute_chunk(const char *
     else compute_fp32(sx, sy, wu, wv, lane, acc);
 }
 
-constexpr int kSmemBytes = 2 * 2 * PanelGeom<QCE_MODE_FP16X2>::kChunkBytes;  // largest mode
-static_assert(2 * 2 * PanelGeom<QCE_MODE_BF16X3>::kChunkBytes <= kSmemBytes, "LDS budget");
-static_assert(2 * 2 * PanelGeom<QCE_MODE_FP32>::kChunkBytes <= kSmemBytes, "LDS budget");
+// ---------------------------------------------------------------------------
+// Software-pipelined main loop of the emulated modes.  A chunk's four 32x32
+// blocks (ub, vb) run in the order (0,0) (0,1) (1,0) (1,1); the fragments of
+// a block are read from LDS into registers freed by the block before, so the
+// reads overlap MFMAs: y1 during (0,0), x1 during (0,1), and the next
+// chunk's x0, y0 during (1,1) -- after the wait and barrier for that chunk,
+// which sit between (1,0) and (1,1).
+// ---------------------------------------------------------------------------
+template <int MODE> struct Frag;
+template <> struct Frag<QCE_MODE_FP16X2> {
+    static constexpr int kP = 4;  // planes: hi(re), lo(re), hi(im), lo(im)
+    u32x4 x[2][4], y[2][4];
+};
+template <> struct Frag<QCE_MODE_BF16X3> {
+    static constexpr int kP = 6;  // planes: b0, b1, b2 of re; b0, b1, b2 of im
+    u32x4 x[2][6], y[2][6];
+};
+
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void load_part(u32x4 *dst, const char *s, int row, int gr) {
+    using G = PanelGeom<MODE>;
+#pragma unroll
+    for (int p = 0; p < Frag<MODE>::kP; ++p) dst[p] = *reinterpret_cast<const u32x4 *>(s + G::offset(p, row, gr));
+}
+
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void mma_block(const Frag<MODE> &f, int ub, int vb, Acc<MODE> &acc) {
+    if constexpr (MODE == QCE_MODE_FP16X2) {
+        const u32x4 nx[2] = {neg_halves(f.x[ub][2]), neg_halves(f.x[ub][3])};
+        fp16x2_block(f.x[ub], nx, f.y[vb], acc.re_m[ub][vb], acc.im_m[ub][vb], acc.re_c[ub][vb], acc.im_c[ub][vb]);
+    } else {
+        const u32x4 *x = f.x[ub], *y = f.y[vb];
+        const u32x4 nx[3] = {neg_halves(x[3]), neg_halves(x[4]), neg_halves(x[5])};
+        floatx16 &re_c = acc.re_c[ub][vb], &im_c = acc.im_c[ub][vb];
+        // corrections, smallest first: (2,0) (1,1) (0,2) (1,0) (0,1)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const int i = t == 0 ? 2 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 1 : 0;
+            const int j = t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 2 : t == 3 ? 0 : 1;
+            re_c = mfmab(x[i], y[j], re_c);
+            re_c = mfmab(nx[i], y[3 + j], re_c);
+            im_c = mfmab(x[i], y[3 + j], im_c);
+            im_c = mfmab(x[3 + i], y[j], im_c);
+        }
+        floatx16 &re_m = acc.re_m[ub][vb], &im_m = acc.im_m[ub][vb];
+        re_m = mfmab(x[0], y[0], re_m);
+        re_m = mfmab(nx[0], y[3], re_m);
+        im_m = mfmab(x[0], y[3], im_m);
+        im_m = mfmab(x[3], y[0], im_m);
+    }
+}
+
+template <int MODE> constexpr int smem_bytes() {
+    return Stages<MODE>::kNS * 2 * PanelGeom<MODE>::kChunkBytes;
+}
+constexpr int kSmemBytes = smem_bytes<QCE_MODE_BF16X3>();  // largest mode
+static_assert(smem_bytes<QCE_MODE_FP16X2>() <= kSmemBytes && smem_bytes<QCE_MODE_FP32>() <= kSmemBytes,
+              "LDS budget");
+static_assert(kSmemBytes <= 160 * 1024, "gfx950 LDS");
 
 // The tile of one workgroup for one mode.  blockIdx.y selects a range of k
 // (split-k): with several ranges the unscaled partial tile goes to
@@ -237,7 +322,9 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
 
     using G = PanelGeom<MODE>;
     constexpr int kCB = G::kChunkBytes;
-    constexpr int kLoads = kCB / (16 * kThreads);  // 16-byte loads per thread per operand
+    constexpr int kNS = Stages<MODE>::kNS;          // LDS stages in the ring
+    constexpr int kL1 = kCB / (16 * kThreads);      // 16-byte copies per thread per operand chunk
+    constexpr int kL = 2 * kL1;                      // per stage (both operands)
     typedef char Stage[2][kCB];
     Stage *smem = reinterpret_cast<Stage *>(smem_raw);
 
@@ -245,13 +332,12 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
     tile_of(blockIdx.x, nbm, nbn, mb, nb);
     const int64_t kpad = round_up(g.k, kKPad);
     const int nkb = (int)(kpad / PanelFmt<MODE>::kBK);
-    // this split's chunk range (split boundaries are multiples of kKPad k-values)
-    constexpr int kChunksPerPad = kKPad / PanelFmt<MODE>::kBK;
+    // this split's chunk range (split boundaries are multiples of the chunk depth)
     const int kb0 = (int)((int64_t)blockIdx.y * g.kpad_per_split / PanelFmt<MODE>::kBK);
     const int kb1 = min(nkb, kb0 + (int)(g.kpad_per_split / PanelFmt<MODE>::kBK));
-    (void)kChunksPerPad;
-    const char *px = static_cast<const char *>(g.panelsB) + (int64_t)nb * nkb * kCB;
-    const char *py = static_cast<const char *>(g.panelsA) + (int64_t)mb * nkb * kCB;
+    const int nk = max(0, kb1 - kb0);
+    const char *px = static_cast<const char *>(g.panelsB) + ((int64_t)nb * nkb + kb0) * kCB;
+    const char *py = static_cast<const char *>(g.panelsA) + ((int64_t)mb * nkb + kb0) * kCB;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wu = w >> 1, wv = w & 1;
@@ -274,43 +360,69 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
             }
     }
 
-    u32x4 rx[kLoads], ry[kLoads];
-    if (kb0 < kb1) {
-        const u32x4 *nx = reinterpret_cast<const u32x4 *>(px + (int64_t)kb0 * kCB);
-        const u32x4 *ny = reinterpret_cast<const u32x4 *>(py + (int64_t)kb0 * kCB);
+    // Chunk c of both operands goes straight from global memory into LDS
+    // stage c % kNS (global_load_lds: lane l of a wave writes 16 bytes at the
+    // wave's LDS address + 16 l), kNS - 1 chunks ahead of the MFMAs.
+    auto issue = [&](int c) {
+        const char *gx = px + (int64_t)c * kCB;
+        const char *gy = py + (int64_t)c * kCB;
+        char *lx = smem[c % kNS][0];
+        char *ly = smem[c % kNS][1];
 #pragma unroll
-        for (int i = 0; i < kLoads; ++i) {
-            rx[i] = nx[tid + i * kThreads];
-            ry[i] = ny[tid + i * kThreads];
+        for (int i = 0; i < kL1; ++i) {
+            const int e = (tid + i * kThreads) * 16;
+            const int we = (w * 64 + i * kThreads) * 16;
+            __builtin_amdgcn_global_load_lds(gx + e, LDS_PTR(lx + we), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(gy + e, LDS_PTR(ly + we), 16, 0, 0);
         }
+    };
+    // wait until this thread's copies of a chunk are done: at most the
+    // copies of the `after` chunks issued later are still outstanding
+    auto wait_chunk = [&](int after) {
+        if (after >= 2) wait_vmcnt<2 * kL>();
+        else if (after == 1) wait_vmcnt<kL>();
+        else wait_vmcnt<0>();
+    };
 #pragma unroll
-        for (int i = 0; i < kLoads; ++i) {
-            reinterpret_cast<u32x4 *>(smem[0][0])[tid + i * kThreads] = rx[i];
-            reinterpret_cast<u32x4 *>(smem[0][1])[tid + i * kThreads] = ry[i];
+    for (int c = 0; c < kNS - 1; ++c)
+        if (c < nk) issue(c);
+    if constexpr (MODE == QCE_MODE_FP32) {
+        for (int it = 0; it < nk; ++it) {
+            // the barrier makes every thread's copies of chunk `it` visible
+            // and retires the reads of the stage the next issue overwrites
+            wait_chunk(min(kNS - 2, nk - 1 - it));
+            asm volatile("s_barrier" ::: "memory");
+            if (it + kNS - 1 < nk) issue(it + kNS - 1);
+            compute_chunk<MODE>(smem[it % kNS][0], smem[it % kNS][1], wu, wv, lane, acc);
         }
-        __syncthreads();
-    }
-    for (int kb = kb0; kb < kb1; ++kb) {
-        const int cur = (kb - kb0) & 1;
-        const bool more = kb + 1 < kb1;
-        if (more) {
-            const u32x4 *nx = reinterpret_cast<const u32x4 *>(px + (int64_t)(kb + 1) * kCB);
-            const u32x4 *ny = reinterpret_cast<const u32x4 *>(py + (int64_t)(kb + 1) * kCB);
-#pragma unroll
-            for (int i = 0; i < kLoads; ++i) {
-                rx[i] = nx[tid + i * kThreads];
-                ry[i] = ny[tid + i * kThreads];
+    } else if (nk > 0) {
+        const int l32 = lane & 31, gr = lane >> 5;
+        const int rx0 = wu * 64 + l32, rx1 = rx0 + 32, ry0 = wv * 64 + l32, ry1 = ry0 + 32;
+        Frag<MODE> f;
+        wait_chunk(min(kNS - 2, nk - 1));
+        asm volatile("s_barrier" ::: "memory");
+        if (kNS - 1 < nk) issue(kNS - 1);
+        load_part<MODE>(f.x[0], smem[0][0], rx0, gr);
+        load_part<MODE>(f.y[0], smem[0][1], ry0, gr);
+        for (int it = 0; it < nk; ++it) {
+            const char *sx = smem[it % kNS][0], *sy = smem[it % kNS][1];
+            load_part<MODE>(f.y[1], sy, ry1, gr);
+            mma_block<MODE>(f, 0, 0, acc);
+            load_part<MODE>(f.x[1], sx, rx1, gr);
+            mma_block<MODE>(f, 0, 1, acc);
+            mma_block<MODE>(f, 1, 0, acc);
+            if (it + 1 < nk) {
+                // chunk it+1: this thread's copies done, every LDS read of
+                // chunk `it` retired (its stage is refilled next), barrier
+                wait_chunk(min(kNS - 2, nk - 2 - it));
+                wait_lgkm0();
+                asm volatile("s_barrier" ::: "memory");
+                if (it + kNS < nk) issue(it + kNS);
+                load_part<MODE>(f.x[0], smem[(it + 1) % kNS][0], rx0, gr);
+                load_part<MODE>(f.y[0], smem[(it + 1) % kNS][1], ry0, gr);
             }
+            mma_block<MODE>(f, 1, 1, acc);
         }
-        compute_chunk<MODE>(smem[cur][0], smem[cur][1], wu, wv, lane, acc);
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < kLoads; ++i) {
-                reinterpret_cast<u32x4 *>(smem[cur ^ 1][0])[tid + i * kThreads] = rx[i];
-                reinterpret_cast<u32x4 *>(smem[cur ^ 1][1])[tid + i * kThreads] = ry[i];
-            }
-        }
-        __syncthreads();
     }
 
     // epilogue: D[j][i] -> C[i][j] (or the split's partial tile)
@@ -365,7 +477,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
 // Forced mode: one kernel per mode.
 template <int MODE>
 __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
-    __shared__ __attribute__((aligned(16))) char smem[2 * 2 * PanelGeom<MODE>::kChunkBytes];
+    __shared__ __attribute__((aligned(16))) char smem[smem_bytes<MODE>()];
     gemm_body<MODE>(g, nbm, nbn, g.forced_mode, smem);
 }
 
@@ -428,10 +540,10 @@ __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, flo
 
 int gemm_splits(int64_t m, int64_t n, int64_t k) {
     const int64_t tiles = ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
-    const int64_t pads = round_up(k, kKPad) / kKPad;  // 32-value k groups
-    if (tiles >= 256 || pads < 16) return 1;
-    int64_t s = 512 / tiles;          // aim at ~512 workgroups
-    s = std::min<int64_t>(s, pads / 8);  // keep >= 8 groups (256 k-values) per split
+    const int64_t pads = round_up(k, kKPad) / kKPad;  // chunks of 16 k-values
+    if (tiles >= 256 || pads < 32) return 1;
+    int64_t s = 512 / tiles;              // aim at ~512 workgroups
+    s = std::min<int64_t>(s, pads / 16);  // keep >= 16 chunks (256 k-values) per split
     return (int)std::max<int64_t>(1, s);
 }
 
