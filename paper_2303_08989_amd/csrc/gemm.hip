@@ -93,11 +93,36 @@ __device__ __attribute__((always_inline)) inline void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Wait until every LDS read of this wave has completed (lgkmcnt 0, vmcnt and
-// expcnt left at their maxima).
-__device__ __attribute__((always_inline)) inline void wait_lgkm0() {
-    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+// Workgroup barrier entered once at most N vector-memory operations and no
+// LDS operation of this wave are outstanding.  The scheduling fences keep
+// every instruction on its side, so no LDS read slips between the wait and
+// the barrier; the wait is an ordinary instruction the compiler's own wait
+// insertion takes into account.
+template <int N>
+__device__ __attribute__((always_inline)) inline void wait_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+    asm volatile("s_barrier" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
 }
+
+// A chunk of zeros in global memory: the source of the padding chunk that
+// makes a block's chunk count even (it adds exact zeros to the products).
+__device__ __attribute__((aligned(256))) uint4 g_zero_chunk[PanelGeom<QCE_MODE_BF16X3>::kChunkBytes / 16];
+
+// c < n ? p : z for wave-uniform operands, as one scalar compare and select
+// (the compiler would otherwise turn it into branches, which split the
+// scheduling region of the k-loop).
+__device__ __attribute__((always_inline)) inline const char *chunk_src(int c, int n, const char *p,
+                                                                      const char *z) {
+    const char *r;
+    asm("s_cmp_lt_i32 %1, %2\n\ts_cselect_b64 %0, %3, %4" : "=s"(r) : "s"(c), "s"(n), "s"(p), "s"(z) : "scc");
+    return r;
+}
+
+// Hides a value's origin from the optimizer (no instruction is emitted).
+__device__ __attribute__((always_inline)) inline void opaque(u32x4 &v) { asm volatile("" : "+v"(v)); }
 
 // LDS stages of the chunk ring per mode (stage = one chunk of each operand)
 template <int MODE> struct Stages { static constexpr int kNS = 4; };
@@ -383,10 +408,10 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         else if (after == 1) wait_vmcnt<kL>();
         else wait_vmcnt<0>();
     };
-#pragma unroll
-    for (int c = 0; c < kNS - 1; ++c)
-        if (c < nk) issue(c);
     if constexpr (MODE == QCE_MODE_FP32) {
+#pragma unroll
+        for (int c = 0; c < kNS - 1; ++c)
+            if (c < nk) issue(c);
         for (int it = 0; it < nk; ++it) {
             // the barrier makes every thread's copies of chunk `it` visible
             // and retires the reads of the stage the next issue overwrites
@@ -396,33 +421,87 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
             compute_chunk<MODE>(smem[it % kNS][0], smem[it % kNS][1], wu, wv, lane, acc);
         }
     } else if (nk > 0) {
+        // The k-steps run in pairs (two register sets, no dynamic
+        // indexing); an odd count gets one chunk of zeros, whose products
+        // add exact zeros.  Every k-step issues one chunk, and chunks past
+        // the end come from the zero chunk, so the number of copies
+        // outstanding after a chunk is a constant and the loop body has no
+        // branches to split the schedule.
+        const int nk2 = nk + (nk & 1);
+        const char *zero = reinterpret_cast<const char *>(g_zero_chunk);
+        asm volatile("" : "+s"(zero));   // computed once, kept in scalar registers
+        auto issue_to = [&](int c, int stage) {
+            const char *gx = chunk_src(c, nk, px + (int64_t)c * kCB, zero);
+            const char *gy = chunk_src(c, nk, py + (int64_t)c * kCB, zero);
+            char *lx = smem[stage][0];
+            char *ly = smem[stage][1];
+#pragma unroll
+            for (int i = 0; i < kL1; ++i) {
+                const int e = (tid + i * kThreads) * 16;
+                const int we = (w * 64 + i * kThreads) * 16;
+                __builtin_amdgcn_global_load_lds(gx + e, LDS_PTR(lx + we), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(gy + e, LDS_PTR(ly + we), 16, 0, 0);
+            }
+        };
         const int l32 = lane & 31, gr = lane >> 5;
         const int rx0 = wu * 64 + l32, rx1 = rx0 + 32, ry0 = wv * 64 + l32, ry1 = ry0 + 32;
-        Frag<MODE> f;
-        wait_chunk(min(kNS - 2, nk - 1));
-        asm volatile("s_barrier" ::: "memory");
-        if (kNS - 1 < nk) issue(kNS - 1);
-        load_part<MODE>(f.x[0], smem[0][0], rx0, gr);
-        load_part<MODE>(f.y[0], smem[0][1], ry0, gr);
-        for (int it = 0; it < nk; ++it) {
-            const char *sx = smem[it % kNS][0], *sy = smem[it % kNS][1];
-            load_part<MODE>(f.y[1], sy, ry1, gr);
-            mma_block<MODE>(f, 0, 0, acc);
-            load_part<MODE>(f.x[1], sx, rx1, gr);
-            mma_block<MODE>(f, 0, 1, acc);
-            mma_block<MODE>(f, 1, 0, acc);
-            if (it + 1 < nk) {
-                // chunk it+1: this thread's copies done, every LDS read of
-                // chunk `it` retired (its stage is refilled next), barrier
-                wait_chunk(min(kNS - 2, nk - 2 - it));
-                wait_lgkm0();
-                asm volatile("s_barrier" ::: "memory");
-                if (it + kNS < nk) issue(it + kNS);
-                load_part<MODE>(f.x[0], smem[(it + 1) % kNS][0], rx0, gr);
-                load_part<MODE>(f.y[0], smem[(it + 1) % kNS][1], ry0, gr);
+        // all fragments of one chunk (x: rows of the B panel, y: of A)
+        auto load_chunk = [&](Frag<MODE> &f, int stage) {
+            load_part<MODE>(f.x[0], smem[stage][0], rx0, gr);
+            load_part<MODE>(f.y[0], smem[stage][1], ry0, gr);
+            load_part<MODE>(f.y[1], smem[stage][1], ry1, gr);
+            load_part<MODE>(f.x[1], smem[stage][0], rx1, gr);
+        };
+        // One k-step: chunk `it` is in registers (fc).  Wait for chunk it+1
+        // (this thread's copies: kNS - 2 later chunks may be outstanding) and
+        // for this wave's reads of chunk `it`; after the barrier every wave
+        // has them, so chunk it's stage takes chunk it + kNS.  Chunk it+1's
+        // fragments are then read into fn while chunk it's MFMAs run: the
+        // reads first, spread over the first MFMAs, then the copies.
+        auto step = [&](int it, const Frag<MODE> &fc, Frag<MODE> &fn) {
+            wait_barrier<(kNS - 2) * kL>();
+            // (reads before copies in program order: the compiler cannot
+            // tell that they touch different stages and keeps their order)
+            load_chunk(fn, (it + 1) % kNS);
+            issue_to(it + kNS, it % kNS);
+            mma_block<MODE>(fc, 0, 0, acc);
+            mma_block<MODE>(fc, 0, 1, acc);
+            mma_block<MODE>(fc, 1, 0, acc);
+            mma_block<MODE>(fc, 1, 1, acc);
+            constexpr int kReads = 4 * Frag<MODE>::kP, kMfma = MODE == QCE_MODE_FP16X2 ? 48 : 96;
+            constexpr int kRp = kReads / 8;   // LDS reads per MFMA over the first 8 MFMAs
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, kRp, 0);   // LDS read
             }
-            mma_block<MODE>(f, 1, 1, acc);
+#pragma unroll
+            for (int i = 0; i < 2 * kL1; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);     // VMEM read (copy to LDS)
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, kMfma - 8 - 2 * kL1, 0);
+        };
+        Frag<MODE> f0, f1;
+#pragma unroll
+        for (int c = 0; c < kNS; ++c) issue_to(c, c);
+        wait_barrier<(kNS - 1) * kL>();  // chunk 0
+        load_chunk(f0, 0);
+        // keeps the optimizer from merging these reads with the loop's
+        // reads into f0 as one read at the top of the loop
+#pragma unroll
+        for (int p = 0; p < Frag<MODE>::kP; ++p) {
+            opaque(f0.x[0][p]);
+            opaque(f0.x[1][p]);
+            opaque(f0.y[0][p]);
+            opaque(f0.y[1][p]);
         }
+        for (int it = 0; it < nk2; it += 2) {
+            step(it, f0, f1);
+            step(it + 1, f1, f0);   // the last one reads a chunk past the end (unused)
+        }
+        // the copies issued by the last k-steps land before the end
+        wait_vmcnt<0>();
     }
 
     // epilogue: D[j][i] -> C[i][j] (or the split's partial tile)
