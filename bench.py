@@ -324,8 +324,32 @@ def main():
                 "flops_per_launch": rec["flops"],
                 "flops_note": "MFMA flops the mode issues: products x 8*m*n*k"}
 
+    def measured_traffic(r):
+        """HBM bytes per launch from the committed counter summary, only while
+        the GEMM kernel sources are the ones it was measured on."""
+        import hashlib
+        path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+        try:
+            t = json.load(open(path))
+        except (OSError, ValueError):
+            return None
+        for rel, digest in t["sources_sha256"].items():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        ent = t["kernels"].get(f"{r['kernel']} {r['case']}")
+        if not ent:
+            return None
+        cal = t["calibration"]
+        return round(1024.0 * (ent["fetch_kib_raw"] * cal["fetch_factor"] +
+                               ent["write_kib_raw"] * cal["write_factor"]))
+
     roof = roofline(dominant) if dominant is not None else None
+    if roof is not None:
+        roof["traffic"] = measured_traffic(roof)
     roof_by_kernel = {KERNEL_OF_PHASE[p]: roofline(r) for p, r in per_kernel.items()}
+    for r in roof_by_kernel.values():
+        r["traffic"] = measured_traffic(r)
 
     # ---- circuit amplitudes (12-qubit FP32 path; 53-qubit sliced share) ------
     circuits = None
