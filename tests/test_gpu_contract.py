@@ -53,6 +53,36 @@ def test_permute_rank20_pow2(qce, h):
     assert np.array_equal(y, np.transpose(x, perm))
 
 
+@pytest.mark.parametrize("seed", range(10))
+def test_permute_pow2_tiled(qce, h, seed):
+    # power-of-two extents: the tiled bit-permutation path (2^8 .. 2^22
+    # elements), including permutations that keep the lowest bits in place
+    rng = np.random.default_rng(100 + seed)
+    n_bits = int(rng.integers(8, 23))
+    exts = []
+    while sum(exts) < n_bits:
+        exts.append(int(min(rng.integers(1, 5), n_bits - sum(exts))))
+    shape = tuple(1 << e for e in exts)
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    rank = len(shape)
+    perm = [int(p) for p in rng.permutation(rank)]
+    if seed % 3 == 0 and rank > 1:            # innermost axis stays innermost
+        perm = [p for p in perm if p != rank - 1] + [rank - 1]
+    y = qce.permute(h, torch.from_numpy(x).to("cuda"), perm).cpu().numpy()
+    assert np.array_equal(y, np.transpose(x, perm))
+
+
+def test_permute_rank28_bits(qce, h):
+    # a 2^24-element tensor with every extent 2 and a random axis order, as
+    # the circuit intermediates
+    rng = np.random.default_rng(5)
+    shape = (2,) * 24
+    x = (np.arange(1 << 24, dtype=np.float32) + 1j * np.float32(0.5)).astype(np.complex64).reshape(shape)
+    perm = [int(p) for p in rng.permutation(24)]
+    y = qce.permute(h, torch.from_numpy(x).to("cuda"), perm).cpu().numpy()
+    assert np.array_equal(y, np.transpose(x, perm))
+
+
 @pytest.mark.parametrize("mode", ["fp32", "auto_emulated", "fp16x2", "bf16x3"])
 @pytest.mark.parametrize("seed", range(6))
 def test_contract_integer_exact(qce, h, mode, seed):
