@@ -58,28 +58,40 @@ __device__ inline uint4 pack8(const uint16_t *v) {
 // x[r + l * ldx] (rows contiguous: op(A) = A, or op(B) = B^T / B^H);
 // KCONTIG = true: P[r][l] = x[l + r * ldx] (k contiguous: op(A) = A^T / A^H,
 // or op(B) = B).  conj negates the imaginary part.
+//
+// A thread converts one chunk row: 16 k-values of one row, written as the
+// row's whole slot in every plane (32 bytes per plane, 64 for FP32).
+// KCONTIG = false: a wave takes 64 consecutive rows of one chunk, so each
+// of its 16 loads reads 512 contiguous bytes and each plane's stores cover
+// 2 KB.  KCONTIG = true: a wave takes 16 rows x 4 consecutive chunks, so a
+// row's 64 k-values (512 bytes) are read by 4 lanes and each plane's stores
+// cover 512 contiguous bytes per chunk.
 template <bool KCONTIG>
 __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
-    int64_t rows_pad, int64_t kq, char *__restrict__ panels, const DevState *st, int which,
+    int64_t rows_pad, int64_t nchunks, char *__restrict__ panels, const DevState *st, int which,
     int forced_mode, int forced_shift) {
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (t >= rows_pad * kq) return;
-    int64_t r, q;  // row and group of 8 k-values
+    int64_t r, c;  // row and chunk
     if (KCONTIG) {
-        q = t % kq;
-        r = t / kq;
+        const int64_t row_blocks = rows_pad / 64;
+        const int64_t b = blockIdx.x;
+        r = (b % row_blocks) * 64 + (threadIdx.x >> 2);
+        c = (b / row_blocks) * 4 + (threadIdx.x & 3);
+        if (c >= nchunks) return;
     } else {
+        const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+        if (t >= rows_pad * nchunks) return;
         r = t % rows_pad;
-        q = t / rows_pad;
+        c = t / rows_pad;
     }
     const int mode = st ? st->mode : forced_mode;
     const int shift = st ? st->shift[which] : forced_shift;
 
-    float re[8], im[8];
-    const int64_t l0 = q * 8;
+    constexpr int kK = 16;  // k-values per chunk row
+    float re[kK], im[kK];
+    const int64_t l0 = c * kK;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kK; ++j) {
         const int64_t l = l0 + j;
         float2 v = make_float2(0.f, 0.f);
         if (r < rows && l < k) v = KCONTIG ? x[l + r * ldx] : x[r + l * ldx];
@@ -90,47 +102,45 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     const int rin = (int)(r % kPanelRows);
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED) {
         using G = PanelGeom<QCE_MODE_FP16X2>;
-        const int64_t nkb = (kq * 8) / PanelFmt<QCE_MODE_FP16X2>::kBK;
-        const int64_t kb = l0 / PanelFmt<QCE_MODE_FP16X2>::kBK;
-        const int g = (int)((l0 % PanelFmt<QCE_MODE_FP16X2>::kBK) / 8);
-        char *chunk = panels + (rb * nkb + kb) * (int64_t)G::kChunkBytes;
+        static_assert(PanelFmt<QCE_MODE_FP16X2>::kBK == kK, "one chunk row per thread");
+        char *chunk = panels + (rb * nchunks + c) * (int64_t)G::kChunkBytes;
         const int sh = mode == QCE_MODE_FP16X2_SCALED ? shift : 0;
-        uint16_t h[4][8];
+        uint16_t h[4][kK];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kK; ++j) {
             split_fp16x2(re[j], sh, h[0][j], h[1][j]);
             split_fp16x2(im[j], sh, h[2][j], h[3][j]);
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-            *reinterpret_cast<uint4 *>(chunk + G::offset(p, rin, g)) = pack8(h[p]);
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+                *reinterpret_cast<uint4 *>(chunk + G::offset(p, rin, g)) = pack8(h[p] + 8 * g);
     } else if (mode == QCE_MODE_BF16X3) {
         using G = PanelGeom<QCE_MODE_BF16X3>;
-        const int64_t nkb = (kq * 8) / PanelFmt<QCE_MODE_BF16X3>::kBK;
-        const int64_t kb = l0 / PanelFmt<QCE_MODE_BF16X3>::kBK;
-        const int g = (int)((l0 % PanelFmt<QCE_MODE_BF16X3>::kBK) / 8);
-        char *chunk = panels + (rb * nkb + kb) * (int64_t)G::kChunkBytes;
-        uint16_t b[6][8];
+        static_assert(PanelFmt<QCE_MODE_BF16X3>::kBK == kK, "one chunk row per thread");
+        char *chunk = panels + (rb * nchunks + c) * (int64_t)G::kChunkBytes;
+        uint16_t b[6][kK];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kK; ++j) {
             split_bf16x3(re[j], b[0][j], b[1][j], b[2][j]);
             split_bf16x3(im[j], b[3][j], b[4][j], b[5][j]);
         }
 #pragma unroll
         for (int p = 0; p < 6; ++p)
-            *reinterpret_cast<uint4 *>(chunk + G::offset(p, rin, g)) = pack8(b[p]);
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+                *reinterpret_cast<uint4 *>(chunk + G::offset(p, rin, g)) = pack8(b[p] + 8 * g);
     } else {
         using G = PanelGeom<QCE_MODE_FP32>;
-        const int64_t nkb = (kq * 8) / PanelFmt<QCE_MODE_FP32>::kBK;
-        const int64_t kb = l0 / PanelFmt<QCE_MODE_FP32>::kBK;
-        const int g0 = (int)((l0 % PanelFmt<QCE_MODE_FP32>::kBK) / 4);
-        char *chunk = panels + (rb * nkb + kb) * (int64_t)G::kChunkBytes;
+        static_assert(PanelFmt<QCE_MODE_FP32>::kBK == kK, "one chunk row per thread");
+        char *chunk = panels + (rb * nchunks + c) * (int64_t)G::kChunkBytes;
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            *reinterpret_cast<float4 *>(chunk + G::offset(0, rin, g0 + hh)) =
-                make_float4(re[4 * hh], re[4 * hh + 1], re[4 * hh + 2], re[4 * hh + 3]);
-            *reinterpret_cast<float4 *>(chunk + G::offset(1, rin, g0 + hh)) =
-                make_float4(im[4 * hh], im[4 * hh + 1], im[4 * hh + 2], im[4 * hh + 3]);
+        for (int g = 0; g < 4; ++g) {
+            *reinterpret_cast<float4 *>(chunk + G::offset(0, rin, g)) =
+                make_float4(re[4 * g], re[4 * g + 1], re[4 * g + 2], re[4 * g + 3]);
+            *reinterpret_cast<float4 *>(chunk + G::offset(1, rin, g)) =
+                make_float4(im[4 * g], im[4 * g + 1], im[4 * g + 2], im[4 * g + 3]);
         }
     }
 }
@@ -160,17 +170,19 @@ hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int co
                                int64_t k, void *panels, const DevState *st, int which,
                                int forced_mode, int shift, hipStream_t s) {
     const int64_t rows_pad = round_up(rows, kPanelRows);
-    const int64_t kq = round_up(k, kKPad) / 8;
-    const int64_t total = rows_pad * kq;
+    const int64_t nchunks = round_up(k, kKPad) / kKPad;
+    const int64_t total = rows_pad * nchunks;
     if (total == 0) return hipSuccess;
-    const int64_t blocks = (total + kThreads - 1) / kThreads;
     char *p = static_cast<char *>(panels);
-    if (!kcontig)
+    if (!kcontig) {
+        const int64_t blocks = (total + kThreads - 1) / kThreads;
         hipLaunchKernelGGL(split_panels_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           x, ldx, conj, rows, k, rows_pad, kq, p, st, which, forced_mode, shift);
-    else
+                           x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift);
+    } else {
+        const int64_t blocks = (rows_pad / 64) * ((nchunks + 3) / 4);
         hipLaunchKernelGGL(split_panels_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           x, ldx, conj, rows, k, rows_pad, kq, p, st, which, forced_mode, shift);
+                           x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift);
+    }
     return hipGetLastError();
 }
 
