@@ -69,6 +69,48 @@ def sample_error(C_dev_host, A, B, rng, nsamp=256):
     return float(np.sqrt(np.sum(np.abs(got - ref) ** 2)) / den) if den > 0 else 0.0, (ii, jj)
 
 
+IRREGULAR_SHAPES = [(2, 1 << 26, 2), (1 << 26, 2, 2), (1 << 15, 1 << 13, 2), (4, 1 << 24, 4)]
+
+
+def run_irregular(h, torch, qce, reps=10):
+    """Irregular-shape CGEMMs (a gate absorbed into a large tensor, a short-k
+    outer product) run by the bandwidth-bound kernel in every mode: HBM rate
+    at minimal traffic 8(mk + kn + mn) bytes, next to a plain device copy."""
+    out = {"shapes": []}
+    n = 1 << 28                                    # 2 GiB of complex64
+    src = torch.ones(n, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_ms = ev0.elapsed_time(ev1) / reps
+    out["device_copy_gbs"] = round(16.0 * n / (copy_ms * 1e-3) / 1e9, 1)
+    del src, dst
+    for m, nn, k in IRREGULAR_SHAPES:
+        A = torch.randn(m * k, dtype=torch.complex64, device="cuda")
+        B = torch.randn(k * nn, dtype=torch.complex64, device="cuda")
+        C = torch.empty(m * nn, dtype=torch.complex64, device="cuda")
+        qce.cgemm(h, "N", "N", m, nn, k, A, m, B, k, C, m)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            qce.cgemm(h, "N", "N", m, nn, k, A, m, B, k, C, m)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        byts = 8.0 * (m * k + k * nn + m * nn)
+        gbs = byts / (ms * 1e-3) / 1e9
+        out["shapes"].append({"m": m, "n": nn, "k": k, "ms": round(ms, 4), "gbs": round(gbs, 1),
+                              "frac_of_8tbs": round(gbs / 8000.0, 3),
+                              "frac_of_copy": round(gbs / out["device_copy_gbs"], 3)})
+        del A, B, C
+    return out
+
+
 def run_circuits(h, args, torch, qce, synth):
     """Config 1: 12-qubit 3x4 grid depth 8 (ABCD), 10 bitstrings, plain FP32.
     Config 3: 53-qubit 6x9-minus-corner grid depth 12 (ABCDCDAB), sliced so
@@ -156,6 +198,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-circuits", action="store_true", help="skip the circuit-amplitude sections")
+    ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-shape section")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
@@ -351,6 +394,8 @@ def main():
     for r in roof_by_kernel.values():
         r["traffic"] = measured_traffic(r)
 
+    irregular = None if args.no_irregular else run_irregular(h, torch, qce)
+
     # ---- circuit amplitudes (12-qubit FP32 path; 53-qubit sliced share) ------
     circuits = None
     if not args.no_circuits:
@@ -406,6 +451,7 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "fp32_baseline": base or None,
         "roofline_by_kernel": roof_by_kernel,
         "amplitudes": circuits,
+        "irregular": irregular,
         "cases": case_out,
     }
     print(json.dumps(out))

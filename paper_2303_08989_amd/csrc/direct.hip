@@ -11,7 +11,17 @@
 // LDS in a fixed order.  With several k-ranges the partial tiles go to a
 // workspace and a second kernel adds them in k order, so results are
 // deterministic.  Arithmetic: FP32 products with FP32 fused accumulation.
+//
+// Short k (k <= 16, e.g. a gate absorbed into a large tensor, or an outer
+// product over a few labels) needs no reduction across threads; there the
+// cost is streaming the large operand and C, so a thread keeps a register
+// tile along the short side: direct_rows_kernel gives a thread one row and
+// up to 8 columns (its A values are read once for all of them; the B values
+// are the same for the whole block), direct_cols_kernel gives a thread one
+// column and every row of a short m (it writes m contiguous outputs).
 #include "common.hpp"
+
+#include <algorithm>
 
 namespace qce {
 
@@ -100,6 +110,82 @@ __global__ __launch_bounds__(kThreads) void direct_reduce_kernel(DirectArgs d, i
     *cp = out;
 }
 
+__device__ inline float2 scale_out(const DirectArgs &d, float re, float im, float2 *cp) {
+    float2 out = make_float2(d.alpha.x * re - d.alpha.y * im, d.alpha.x * im + d.alpha.y * re);
+    if (d.alpha.x == 1.f && d.alpha.y == 0.f) out = make_float2(re, im);
+    if (!d.beta_zero) {
+        const float2 c = *cp;
+        out.x += d.beta.x * c.x - d.beta.y * c.y;
+        out.y += d.beta.x * c.y + d.beta.y * c.x;
+    }
+    return out;
+}
+
+template <int JT>
+__global__ __launch_bounds__(kThreads) void direct_rows_kernel(DirectArgs d) {
+    const int64_t row_blocks = (d.m + kThreads - 1) / kThreads;
+    const int64_t b = blockIdx.x;
+    const int64_t i = (b % row_blocks) * kThreads + threadIdx.x;
+    const int64_t j0 = (b / row_blocks) * JT;
+    if (i >= d.m) return;
+    float re[JT], im[JT];
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj) re[jj] = im[jj] = 0.f;
+    for (int64_t l = 0; l < d.k; ++l) {
+        const float2 a = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i, l);
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) {
+            if (j0 + jj >= d.n) break;
+            const float2 bv = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j0 + jj, l);
+            re[jj] = fmaf(a.x, bv.x, re[jj]);
+            re[jj] = fmaf(-a.y, bv.y, re[jj]);
+            im[jj] = fmaf(a.x, bv.y, im[jj]);
+            im[jj] = fmaf(a.y, bv.x, im[jj]);
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj) {
+        if (j0 + jj >= d.n) break;
+        float2 *cp = d.C + i + (j0 + jj) * d.ldc;
+        *cp = scale_out(d, re[jj], im[jj], cp);
+    }
+}
+
+template <int MT>
+__global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= d.n) return;
+    float re[MT], im[MT];
+#pragma unroll
+    for (int ii = 0; ii < MT; ++ii) re[ii] = im[ii] = 0.f;
+    for (int64_t l = 0; l < d.k; ++l) {
+        const float2 bv = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l);
+#pragma unroll
+        for (int ii = 0; ii < MT; ++ii) {
+            if (ii >= d.m) break;
+            const float2 a = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, ii, l);
+            re[ii] = fmaf(a.x, bv.x, re[ii]);
+            re[ii] = fmaf(-a.y, bv.y, re[ii]);
+            im[ii] = fmaf(a.x, bv.y, im[ii]);
+            im[ii] = fmaf(a.y, bv.x, im[ii]);
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < MT; ++ii) {
+        if (ii >= d.m) break;
+        float2 *cp = d.C + ii + j * d.ldc;
+        *cp = scale_out(d, re[ii], im[ii], cp);
+    }
+}
+
+constexpr int64_t kShortK = 16;
+
+int pow2_at_least(int64_t x) {
+    int p = 1;
+    while (p < x) p *= 2;
+    return p;
+}
+
 }  // namespace
 
 void direct_plan(DirectArgs &d, int64_t &splits) {
@@ -127,6 +213,7 @@ void direct_plan(DirectArgs &d, int64_t &splits) {
 }
 
 size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k) {
+    if (k <= kShortK) return 0;
     DirectArgs d{};
     d.m = m;
     d.n = n;
@@ -137,6 +224,30 @@ size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k) {
 }
 
 hipError_t launch_direct(DirectArgs d, hipStream_t s) {
+    if (d.k <= kShortK) {
+        if (d.m >= 32) {
+            const int jt = std::min(8, pow2_at_least(d.n));
+            const int64_t blocks = ((d.m + kThreads - 1) / kThreads) * ((d.n + jt - 1) / jt);
+            const dim3 g((unsigned)blocks), t(kThreads);
+            switch (jt) {
+            case 1: hipLaunchKernelGGL(direct_rows_kernel<1>, g, t, 0, s, d); break;
+            case 2: hipLaunchKernelGGL(direct_rows_kernel<2>, g, t, 0, s, d); break;
+            case 4: hipLaunchKernelGGL(direct_rows_kernel<4>, g, t, 0, s, d); break;
+            default: hipLaunchKernelGGL(direct_rows_kernel<8>, g, t, 0, s, d); break;
+            }
+        } else {
+            const dim3 g((unsigned)((d.n + kThreads - 1) / kThreads)), t(kThreads);
+            switch (pow2_at_least(d.m)) {
+            case 1: hipLaunchKernelGGL(direct_cols_kernel<1>, g, t, 0, s, d); break;
+            case 2: hipLaunchKernelGGL(direct_cols_kernel<2>, g, t, 0, s, d); break;
+            case 4: hipLaunchKernelGGL(direct_cols_kernel<4>, g, t, 0, s, d); break;
+            case 8: hipLaunchKernelGGL(direct_cols_kernel<8>, g, t, 0, s, d); break;
+            case 16: hipLaunchKernelGGL(direct_cols_kernel<16>, g, t, 0, s, d); break;
+            default: hipLaunchKernelGGL(direct_cols_kernel<32>, g, t, 0, s, d); break;
+            }
+        }
+        return hipGetLastError();
+    }
     int64_t splits = 1;
     direct_plan(d, splits);
     const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);

@@ -275,7 +275,8 @@ def test_expstats_exact(qce, handle):
 
 
 IRREGULAR = [(1, 1, 5), (1, 1, 100000), (100000, 2, 2), (2, 70000, 2), (300, 400, 3),
-             (31, 500, 600), (500, 31, 600), (64, 64, 15), (1, 300, 4000), (5, 7, 3)]
+             (31, 500, 600), (500, 31, 600), (64, 64, 15), (1, 300, 4000), (5, 7, 3),
+             (33, 5, 16), (31, 3000, 16), (4000, 1000, 1), (32, 9, 17)]
 
 
 @pytest.mark.parametrize("m,n,k", IRREGULAR)
@@ -299,6 +300,20 @@ def test_irregular_ops_alpha_beta(qce, handle, opA, opB):
     C0 = synth.random_matrix(m, n, "int", rng)
     C, _ = run(qce, handle, A, B, m, n, k, opA, opB, alpha=complex(1, 2), beta=complex(0, -1), C0=C0)
     want = oracle.cgemm(A, B, opA, opB, alpha=complex(1, 2), beta=complex(0, -1), C0=C0)
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
+@pytest.mark.parametrize("opA,opB", [("T", "N"), ("C", "T"), ("N", "C")])
+@pytest.mark.parametrize("m,n,k", [(300, 7, 9), (7, 300, 9), (257, 300, 2)])
+def test_short_k_ops_alpha_beta(qce, handle, opA, opB, m, n, k):
+    # short k: row-tile and column-tile kernels, every operand layout
+    rng = np.random.default_rng(m + n + k)
+    sa, sb = shapes_of(m, n, k, opA, opB)
+    A = synth.random_matrix(*sa, "int", rng)
+    B = synth.random_matrix(*sb, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    C, _ = run(qce, handle, A, B, m, n, k, opA, opB, alpha=complex(-1, 2), beta=complex(1, 1), C0=C0)
+    want = oracle.cgemm(A, B, opA, opB, alpha=complex(-1, 2), beta=complex(1, 1), C0=C0)
     assert np.array_equal(C.astype(np.complex128), want)
 
 
