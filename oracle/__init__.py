@@ -24,7 +24,10 @@ What it computes, each following the paper (arXiv 2303.08989):
 * ``statevector_amplitudes`` / ``tn_amplitude``  amplitudes <x|U|0> of a
                       circuit (Sec. 5.3, Eq. 4) by brute-force state vector
                       and by tensor-network contraction (Sec. 2.2), the latter
-                      optionally sliced (Sec. 5.3).
+                      optionally sliced (Sec. 5.3);
+* ``probability_theta_gradient``  gradients of |<x|U|0>|^2 with respect to
+                      per-coupler fSim angles by the product rule (not in the
+                      paper; pinned by closed forms and finite differences).
 
 Readings of the paper taken where it is silent or garbled are listed in the
 docstrings of the functions that depend on them.
@@ -36,5 +39,5 @@ from .core import (  # noqa: F401
 )
 from .circuit import (  # noqa: F401
     statevector, statevector_amplitudes, tn_build, tn_amplitude, tn_amplitude_sliced,
-    fidelity,
+    fidelity, fsim_theta_derivative, probability_theta_gradient,
 )

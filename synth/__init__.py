@@ -10,6 +10,6 @@ sharing any computation.
 from .gemm_inputs import gemm_operands, random_matrix, DISTRIBUTIONS  # noqa: F401
 from .circuits import (  # noqa: F401
     grid_circuit, ghz_circuit, identity_circuit, product_circuit,
-    random_bitstrings, gate_matrix, GRID_53,
+    random_bitstrings, gate_matrix, GRID_53, with_thetas, coupler_thetas,
 )
 from .tn_random import random_network  # noqa: F401

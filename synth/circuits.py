@@ -148,6 +148,26 @@ def grid_circuit(rows, cols, depth, seed, pattern="ABCD", removed=(),
             "sites": sites, "n_couplers": len(coupler_ids)}
 
 
+def with_thetas(circuit, thetas):
+    """Copy of a grid circuit whose fSim gates take the angle of their
+    coupler: gate on coupler e gets fSim(thetas[e], its phi)."""
+    out = dict(circuit)
+    gates = []
+    for g in circuit["gates"]:
+        if g.get("name") == "fsim" and "coupler" in g:
+            th = float(thetas[g["coupler"]])
+            g = dict(g, theta=th, matrix=gate_matrix("fsim", th, g["phi"]))
+        gates.append(g)
+    out["gates"] = gates
+    return out
+
+
+def coupler_thetas(n_couplers, seed, low=0.2, high=1.4):
+    """Seeded per-coupler angles (radians), uniform in [low, high)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(low, high, n_couplers).astype(np.float32)
+
+
 # 53-qubit stand-in: a 6 x 9 grid with one corner site removed.
 GRID_53 = dict(rows=6, cols=9, removed=((5, 8),))
 
