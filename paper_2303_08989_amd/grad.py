@@ -1,0 +1,231 @@
+"""Gradients of circuit probabilities with respect to fSim angles: a
+hand-written adjoint through the contraction tree.
+
+For a bitstring x the amplitude a = <x|U|0> is the value of the circuit's
+tensor network (Sec. 2.2), contracted pairwise along the plan's tree, and
+p = |a|^2.  Every fSim gate on coupler e carries the angle theta_e (one
+trainable angle per coupler, shared by all cycles that use the coupler).
+
+Reverse pass.  a is a holomorphic (multilinear) function of every leaf
+tensor, so its adjoint E_T = da/dT (same labels as T) flows down the tree:
+E_root = 1 and, for a node C = sum_K A B,
+
+    E_A = sum_{free(B)} E_C B      (labels of A),
+    E_B = sum_{free(A)} E_C A      (labels of B),
+
+each one more pairwise contraction through ``qce_contract`` on the emulated
+GEMM (the same TTGT path, statistics and mode selection as the forward
+pass).  For an fSim leaf G_g, s_g = sum E_g * dG_g/dtheta (a full
+contraction over its four labels) is da/dtheta from that occurrence; the
+s_g of one coupler are added in FP64 on the device, as is the slice sum of
+a.  Then dp/dtheta_e = 2 Re(conj(a) sum_g s_g).
+
+Checkpointing: the forward pass of a slice keeps every intermediate of the
+tree (the values the reverse pass needs as the sibling operand B or A);
+each is released as soon as the reverse pass has used it, and slices are
+processed one at a time, so the peak is one slice's intermediates.
+Subtrees that hold no fSim leaf are not differentiated.
+
+Host work is marshalling only: leaf tensors (gate matrices from the angles,
+|0> and <x| vectors, sliced variants) are built on the host and uploaded;
+the final combination 2 Re(conj(a) D_e) and J^T g in the autograd function
+act on the handful of FP64 scalars the device returns.
+"""
+import math
+
+import numpy as np
+
+from . import tn
+
+
+def fsim_matrix(theta, phi):
+    """fSim(theta, phi) in the basis |00>, |01>, |10>, |11> (complex128)."""
+    c, s = math.cos(theta), math.sin(theta)
+    m = np.zeros((4, 4), dtype=np.complex128)
+    m[0, 0] = 1.0
+    m[1, 1] = m[2, 2] = c
+    m[1, 2] = m[2, 1] = -1j * s
+    m[3, 3] = complex(math.cos(phi), -math.sin(phi))
+    return m
+
+
+def fsim_dtheta(theta, phi):
+    """d fSim(theta, phi) / d theta."""
+    c, s = math.cos(theta), math.sin(theta)
+    m = np.zeros((4, 4), dtype=np.complex128)
+    m[1, 1] = m[2, 2] = -s
+    m[1, 2] = m[2, 1] = -1j * c
+    return m
+
+
+class GradientRunner:
+    """Probabilities and their theta-gradients for one circuit structure and
+    contraction plan (``executor.CircuitPlan``), on the handle's GPU."""
+
+    def __init__(self, handle, plan, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.h = handle
+        self.plan = plan
+        circ = plan.circuit
+        self.n = circ["n"]
+        self.n_couplers = circ.get("n_couplers", 0)
+        # leaf index of each gate: n |0> vectors come first
+        self.fsim_leaf = {}        # leaf -> (coupler, phi)
+        for gi, g in enumerate(circ["gates"]):
+            if g.get("name") == "fsim" and "coupler" in g:
+                self.fsim_leaf[self.n + gi] = (int(g["coupler"]), float(g["phi"]))
+        L = len(plan.label_sets)
+        # which nodes have an fSim leaf below them
+        self.has_param = [i in self.fsim_leaf for i in range(L)]
+        for a, b in plan.path:
+            self.has_param.append(self.has_param[a] or self.has_param[b])
+
+    # ---- leaves ---------------------------------------------------------
+    def _circuit_at(self, thetas):
+        circ = dict(self.plan.circuit)
+        gates = []
+        for g in circ["gates"]:
+            if g.get("name") == "fsim" and "coupler" in g:
+                g = dict(g, matrix=fsim_matrix(float(thetas[g["coupler"]]), float(g["phi"])))
+            gates.append(g)
+        circ["gates"] = gates
+        return circ
+
+    def _variants(self, arr, labels, pos):
+        """{values of the sliced labels it carries: device tensor}."""
+        torch = self.torch
+        sl = [lab for lab in labels if lab in pos]
+        if not sl:
+            return {(): torch.from_numpy(np.ascontiguousarray(arr)).to(self.device)}
+        out = {}
+        for vals in np.ndindex(*(2,) * len(sl)):
+            idx = tuple(vals[sl.index(lab)] if lab in pos else slice(None) for lab in labels)
+            out[tuple(vals)] = torch.from_numpy(np.ascontiguousarray(arr[idx])).to(self.device)
+        return out
+
+    def _leaves(self, thetas, x, cache):
+        """Device variants of every leaf and of every fSim leaf's derivative.
+        Gate leaves (and derivatives) depend only on the angles and are
+        uploaded once per angle vector; the <x| vectors (the last n leaves)
+        once per bitstring."""
+        p = self.plan
+        pos = {lab: i for i, lab in enumerate(p.sliced)}
+        leaves = tn.circuit_network(self._circuit_at(thetas), x)
+        nl = len(leaves)
+        if "gates" not in cache:
+            cache["gates"] = [self._variants(arr, labels, pos) for arr, labels in leaves[: nl - self.n]]
+            dvals = {}
+            for i, (cpl, phi) in self.fsim_leaf.items():
+                d = fsim_dtheta(float(thetas[cpl]), phi).astype(np.complex64).reshape(2, 2, 2, 2)
+                dvals[i] = self._variants(d, leaves[i][1], pos)
+            cache["d"] = dvals
+        vals = cache["gates"] + [self._variants(arr, labels, pos) for arr, labels in leaves[nl - self.n:]]
+        return vals, cache["d"]
+
+    # ---- one bitstring ----------------------------------------------------
+    def amplitude_and_derivatives(self, thetas, x, slice_ids=None, cache=None):
+        """Device float64 accumulators (a[2], D[n_couplers, 2]) with
+        a = sum over slices of the amplitude and D_e = da/dtheta_e.
+        ``cache`` (a dict) keeps the angle-dependent leaves between calls
+        with the same angles."""
+        import paper_2303_08989_amd as qce
+        torch = self.torch
+        p = self.plan
+        L = len(p.label_sets)
+        pos = {lab: i for i, lab in enumerate(p.sliced)}
+        vals, dvals = self._leaves(thetas, x, {} if cache is None else cache)
+        acc_a = torch.zeros(2, dtype=torch.float64, device=self.device)
+        acc_d = torch.zeros((max(1, self.n_couplers), 2), dtype=torch.float64, device=self.device)
+        if slice_ids is None:
+            slice_ids = range(p.n_slices)
+        one = torch.ones((), dtype=torch.complex64, device=self.device)
+        for sigma in slice_ids:
+            v = {lab: (sigma >> i) & 1 for lab, i in pos.items()}
+
+            def key(i):
+                return tuple(v[lab] for lab in p.label_sets[i] if lab in pos)
+
+            def leaf(i):
+                return vals[i][key(i)]
+
+            if not p.path:
+                qce.accumulate_f64(self.h, leaf(0).reshape(-1)[:1], acc_a)
+                continue
+            # forward, keeping every intermediate (the checkpoints)
+            node_val, node_lab = {}, {i: tuple(p.labels[i]) for i in range(L)}
+            for s, (a, b) in enumerate(p.path):
+                ta = leaf(a) if a < L else node_val[a]
+                tb = leaf(b) if b < L else node_val[b]
+                la, lb = node_lab[a], node_lab[b]
+                shared = set(la) & set(lb)
+                lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
+                node_lab[L + s] = tuple(lc)
+                node_val[L + s] = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
+            root = L + len(p.path) - 1
+            qce.accumulate_f64(self.h, node_val[root].reshape(-1)[:1], acc_a)
+            # reverse pass
+            adj = {root: one}
+            for s in range(len(p.path) - 1, -1, -1):
+                node = L + s
+                E = adj.pop(node, None)
+                a, b = p.path[s]
+                if E is not None:
+                    for ch, other in ((a, b), (b, a)):
+                        if not self.has_param[ch]:
+                            continue
+                        t_other = leaf(other) if other < L else node_val[other]
+                        E_ch = qce.contract(self.h, E, list(node_lab[node]), t_other,
+                                            list(node_lab[other]), list(node_lab[ch]))
+                        if ch < L:
+                            cpl, _ = self.fsim_leaf[ch]
+                            dG = dvals[ch][key(ch)]
+                            s_g = qce.contract(self.h, E_ch, list(node_lab[ch]), dG,
+                                               list(node_lab[ch]), [])
+                            qce.accumulate_f64(self.h, s_g.reshape(-1)[:1], acc_d[cpl])
+                        else:
+                            adj[ch] = E_ch
+                # the children's values are no longer needed
+                node_val.pop(a, None)
+                node_val.pop(b, None)
+            node_val.clear()
+        return acc_a, acc_d
+
+    def probabilities_and_jacobian(self, thetas, bitstrings, slice_ids=None):
+        """p_x = |a_x|^2 (float64, shape (X,)), the amplitudes (complex128)
+        and J[x, e] = dp_x / dtheta_e (float64, shape (X, n_couplers))."""
+        thetas = np.asarray(thetas, dtype=np.float32)
+        cache = {}
+        accs = [self.amplitude_and_derivatives(thetas, x, slice_ids, cache) for x in bitstrings]
+        if self.device != "cpu":
+            self.torch.cuda.synchronize()
+        amps = np.empty(len(bitstrings), dtype=np.complex128)
+        J = np.zeros((len(bitstrings), self.n_couplers), dtype=np.float64)
+        for i, (acc_a, acc_d) in enumerate(accs):
+            ar, ai = acc_a.cpu().numpy()
+            d = acc_d.cpu().numpy()[: self.n_couplers]
+            amps[i] = complex(ar, ai)
+            J[i] = 2.0 * (ar * d[:, 0] + ai * d[:, 1])
+        return np.abs(amps) ** 2, amps, J
+
+
+def circuit_probabilities(runner, thetas, bitstrings, slice_ids=None):
+    """p_x(theta) for the bitstrings as a differentiable torch function of
+    the FP32 angle tensor ``thetas`` (one per coupler)."""
+    import torch
+
+    class _Probabilities(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, th):
+            p, _, J = runner.probabilities_and_jacobian(th.detach().cpu().numpy(), bitstrings, slice_ids)
+            ctx.save_for_backward(torch.from_numpy(J))
+            return torch.from_numpy(p).to(th.device)
+
+        @staticmethod
+        def backward(ctx, grad_p):
+            (J,) = ctx.saved_tensors
+            g = J.numpy().T @ grad_p.detach().cpu().numpy().astype(np.float64)
+            return torch.from_numpy(g.astype(np.float32)).to(grad_p.device)
+
+    return _Probabilities.apply(thetas)

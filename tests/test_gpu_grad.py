@@ -1,0 +1,135 @@
+"""GPU adjoint gradients of |<x|U|0>|^2 with respect to per-coupler fSim
+angles (reverse pass through the contraction tree on the emulated GEMM)
+against the FP64 oracle gradient, central finite differences and a closed
+form."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def qce():
+    import paper_2303_08989_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def h(qce):
+    hh = qce.Handle(0)
+    yield hh
+    hh.close()
+
+
+def _runner(qce, h, circuit, max_log2=30, varied=4):
+    from paper_2303_08989_amd.executor import CircuitPlan
+    from paper_2303_08989_amd.grad import GradientRunner
+    plan = CircuitPlan(circuit, max_log2=max_log2, restarts=2, varied=varied)
+    return GradientRunner(h, plan), plan
+
+
+def _rounded(circuit):
+    out = dict(circuit)
+    out["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                    for g in circuit["gates"]]
+    return out
+
+
+def _with_mode(h, mode, fn):
+    if mode == "auto_emulated":
+        h.set_mode("auto")
+        h.set_size_policy(0, 0)
+    else:
+        h.set_mode(mode)
+    try:
+        return fn()
+    finally:
+        h.set_size_policy(2048, 512)
+        h.set_mode("auto")
+
+
+def test_closed_form_two_qubits(qce, h):
+    theta = 0.8
+    g = {"name": "fsim", "qubits": [0, 1], "matrix": synth.gate_matrix("fsim", theta, 0.5),
+         "coupler": 0, "theta": theta, "phi": 0.5}
+    c = {"n": 2, "n_couplers": 1,
+         "gates": [{"name": "X", "qubits": [1], "matrix": synth.gate_matrix("X")}, g]}
+    run, _ = _runner(qce, h, c)
+    p, amps, J = run.probabilities_and_jacobian(np.array([theta], np.float32), [0b10, 0b01, 0b00])
+    th = float(np.float32(theta))
+    assert J[0, 0] == pytest.approx(math.sin(2 * th), abs=1e-6)
+    assert J[1, 0] == pytest.approx(-math.sin(2 * th), abs=1e-6)
+    assert J[2, 0] == 0.0
+    assert p[0] == pytest.approx(math.sin(th) ** 2, abs=1e-6)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated"])
+def test_grid12_matches_oracle_gradient(qce, h, mode):
+    base = synth.grid_circuit(3, 4, 8, seed=4, pattern="ABCD")
+    th = synth.coupler_thetas(base["n_couplers"], seed=4)
+    c = synth.with_thetas(base, th)
+    xs = synth.random_bitstrings(12, 6, seed=9)
+    run, _ = _runner(qce, h, c)
+    p, amps, J = _with_mode(h, mode, lambda: run.probabilities_and_jacobian(th, xs))
+    a_ref, J_ref = oracle.probability_theta_gradient(_rounded(c), xs, base["n_couplers"])
+    scale = np.max(np.abs(J_ref))
+    assert np.max(np.abs(J - J_ref)) <= 2e-5 * scale
+    assert oracle.fidelity(amps, a_ref) >= 1 - 1e-6
+
+
+def test_sliced_equals_unsliced(qce, h):
+    base = synth.grid_circuit(3, 4, 8, seed=6, pattern="ABCDCDAB")
+    th = synth.coupler_thetas(base["n_couplers"], seed=6)
+    c = synth.with_thetas(base, th)
+    xs = synth.random_bitstrings(12, 3, seed=2)
+    run_full, plan_full = _runner(qce, h, c, max_log2=30)
+    run_sl, plan_sl = _runner(qce, h, c, max_log2=5, varied=3)
+    assert len(plan_sl.sliced) >= 2 and not plan_full.sliced
+    h.set_mode("fp32")
+    try:
+        _, a1, J1 = run_full.probabilities_and_jacobian(th, xs)
+        _, a2, J2 = run_sl.probabilities_and_jacobian(th, xs)
+    finally:
+        h.set_mode("auto")
+    assert np.max(np.abs(a1 - a2)) <= 1e-6 * np.max(np.abs(a1))
+    assert np.max(np.abs(J1 - J2)) <= 2e-5 * np.max(np.abs(J1))
+
+
+def test_central_finite_differences(qce, h):
+    base = synth.grid_circuit(3, 4, 6, seed=8, pattern="ABCD")
+    th = synth.coupler_thetas(base["n_couplers"], seed=8)
+    c = synth.with_thetas(base, th)
+    xs = synth.random_bitstrings(12, 2, seed=1)
+    run, _ = _runner(qce, h, c)
+    p, _, J = run.probabilities_and_jacobian(th, xs)
+    step = 1e-3
+    for e in (0, base["n_couplers"] // 2, base["n_couplers"] - 1):
+        tp, tm = th.copy(), th.copy()
+        tp[e] += np.float32(step)
+        tm[e] -= np.float32(step)
+        pp, _, _ = run.probabilities_and_jacobian(tp, xs)
+        pm, _, _ = run.probabilities_and_jacobian(tm, xs)
+        fd = (pp - pm) / (float(tp[e]) - float(tm[e]))
+        assert np.max(np.abs(fd - J[:, e])) <= 1e-2 * np.max(np.abs(J)) + 1e-9
+
+
+def test_autograd_function(qce, h):
+    from paper_2303_08989_amd.grad import circuit_probabilities
+    base = synth.grid_circuit(2, 3, 5, seed=2, pattern="ABCD")
+    th = synth.coupler_thetas(base["n_couplers"], seed=2)
+    c = synth.with_thetas(base, th)
+    xs = synth.random_bitstrings(6, 4, seed=3)
+    run, _ = _runner(qce, h, c)
+    t = torch.tensor(th, requires_grad=True)
+    p = circuit_probabilities(run, t, xs)
+    w = torch.tensor([1.0, -2.0, 0.5, 3.0], dtype=p.dtype)
+    (p * w).sum().backward()
+    _, J_ref = oracle.probability_theta_gradient(_rounded(c), xs, base["n_couplers"])
+    want = J_ref.T @ w.numpy()
+    assert np.max(np.abs(t.grad.numpy() - want)) <= 2e-5 * np.max(np.abs(want))
