@@ -111,6 +111,67 @@ def run_irregular(h, torch, qce, reps=10):
     return out
 
 
+def run_gradients(h, args, torch, qce, synth):
+    """Gradients of |<x|U|0>|^2 with respect to the per-coupler fSim angles
+    of a 30-qubit 5x6 grid circuit, depth 14, for a batch of bitstrings:
+    forward contraction keeping the tree's intermediates, reverse pass of
+    adjoint contractions on the emulated GEMM (AUTO with the size policy)."""
+    from paper_2303_08989_amd.executor import CircuitPlan
+    from paper_2303_08989_amd.grad import GradientRunner
+    base = synth.grid_circuit(5, 6, 14, seed=0, pattern="ABCDCDAB")
+    ne = base["n_couplers"]
+    th = synth.coupler_thetas(ne, seed=5)
+    c = synth.with_thetas(base, th)
+    t0 = time.perf_counter()
+    plan = CircuitPlan(c, max_log2=28, restarts=40, alphas=(1.0, 1.5, 2.0), noises=(0.05,))
+    t_plan = time.perf_counter() - t0
+    xs = synth.random_bitstrings(30, args.c5_bitstrings, seed=6)
+    run = GradientRunner(h, plan)
+    h.set_mode("auto")
+    run.probabilities_and_jacobian(th, xs[:1])            # warm-up (workspace, allocations)
+    torch.cuda.synchronize()
+    run.flops = 0.0
+    h.reset_timing()
+    h.set_timing(True)
+    t0 = time.perf_counter()
+    p, amps, J = run.probabilities_and_jacobian(th, xs)
+    dt = time.perf_counter() - t0
+    h.set_timing(False)
+    modes = h.timing()["gemms_by_mode"]
+    flops = run.flops
+    # the same Jacobian rows on the plain FP32 path
+    nchk = min(4, len(xs))
+    h.set_mode("fp32")
+    p32, _, J32 = run.probabilities_and_jacobian(th, xs[:nchk])
+    # central differences (h = 1e-3) on the plain FP32 path for one bitstring
+    fd_err = 0.0
+    for e in (0, ne // 2):
+        tp, tm_ = th.copy(), th.copy()
+        tp[e] += np.float32(1e-3)
+        tm_[e] -= np.float32(1e-3)
+        pp, _, _ = run.probabilities_and_jacobian(tp, xs[:1])
+        pm, _, _ = run.probabilities_and_jacobian(tm_, xs[:1])
+        fd = (pp[0] - pm[0]) / (float(tp[e]) - float(tm_[e]))
+        fd_err = max(fd_err, abs(fd - J32[0, e]) / max(np.max(np.abs(J32[0])), 1e-300))
+    h.set_mode("auto")
+    rel_auto_fp32 = float(np.linalg.norm(J[:nchk] - J32) / max(np.linalg.norm(J32), 1e-300))
+    return {
+        "workload": f"30-qubit 5x6 grid, depth 14, ABCDCDAB; {ne} trainable fSim angles (one per "
+                    f"coupler, FP32); gradient of |<x|U|0>|^2 for {len(xs)} random bitstrings; "
+                    f"{len(plan.sliced)} sliced labels, max intermediate 2^{plan.max_log2}; AUTO with "
+                    "size policy on forward and adjoint GEMMs",
+        "plan_seconds": round(t_plan, 1),
+        "seconds": round(dt, 4), "gradients_per_s": round(len(xs) / dt, 2),
+        "ms_per_bitstring": round(dt / len(xs) * 1e3, 3),
+        "contraction_flops_per_bitstring": flops / len(xs),
+        "effective_tflops": round(flops / dt / 1e12, 2),
+        "gemms_by_mode": modes,
+        "jacobian_rel_diff_auto_vs_fp32": rel_auto_fp32,
+        "fd_check_max_rel_err_fp32_h1e-3": fd_err,
+        "mean_probability": float(np.mean(p)),
+    }
+
+
 def run_circuits(h, args, torch, qce, synth):
     """Config 1: 12-qubit 3x4 grid depth 8 (ABCD), 10 bitstrings, plain FP32.
     Config 3: 53-qubit 6x9-minus-corner grid depth 12 (ABCDCDAB), sliced so
@@ -199,6 +260,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-circuits", action="store_true", help="skip the circuit-amplitude sections")
     ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-shape section")
+    ap.add_argument("--no-gradients", action="store_true", help="skip the circuit-gradient section")
+    ap.add_argument("--c5-bitstrings", type=int, default=64, help="bitstrings of the gradient section")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
@@ -395,6 +458,7 @@ def main():
         r["traffic"] = measured_traffic(r)
 
     irregular = None if args.no_irregular else run_irregular(h, torch, qce)
+    gradients = None if args.no_gradients else run_gradients(h, args, torch, qce, synth)
 
     # ---- circuit amplitudes (12-qubit FP32 path; 53-qubit sliced share) ------
     circuits = None
@@ -452,6 +516,7 @@ def main():
         "roofline_by_kernel": roof_by_kernel,
         "amplitudes": circuits,
         "irregular": irregular,
+        "gradients": gradients,
         "cases": case_out,
     }
     print(json.dumps(out))

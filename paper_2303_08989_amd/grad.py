@@ -58,6 +58,16 @@ def fsim_dtheta(theta, phi):
     return m
 
 
+def _flops(A, B, la, lb):
+    """8 m n k of a pairwise contraction (each label counted once)."""
+    ext = dict(zip(la, A.shape))
+    ext.update(zip(lb, B.shape))
+    n = 1
+    for e in ext.values():
+        n *= int(e)
+    return 8.0 * n
+
+
 class GradientRunner:
     """Probabilities and their theta-gradients for one circuit structure and
     contraction plan (``executor.CircuitPlan``), on the handle's GPU."""
@@ -67,6 +77,7 @@ class GradientRunner:
         self.torch = torch
         self.device = device
         self.h = handle
+        self.flops = 0.0           # 8mnk of every contraction issued (forward and reverse)
         self.plan = plan
         circ = plan.circuit
         self.n = circ["n"]
@@ -163,6 +174,7 @@ class GradientRunner:
                 lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
                 node_lab[L + s] = tuple(lc)
                 node_val[L + s] = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
+                self.flops += _flops(ta, tb, la, lb)
             root = L + len(p.path) - 1
             qce.accumulate_f64(self.h, node_val[root].reshape(-1)[:1], acc_a)
             # reverse pass
@@ -178,6 +190,7 @@ class GradientRunner:
                         t_other = leaf(other) if other < L else node_val[other]
                         E_ch = qce.contract(self.h, E, list(node_lab[node]), t_other,
                                             list(node_lab[other]), list(node_lab[ch]))
+                        self.flops += _flops(E, t_other, node_lab[node], node_lab[other])
                         if ch < L:
                             cpl, _ = self.fsim_leaf[ch]
                             dG = dvals[ch][key(ch)]

@@ -225,15 +225,15 @@ def memoized_cost(label_sets, path, sliced, n_varied):
     return tot * 2.0 ** max(0, n_varied - len(sliced))
 
 
-def best_greedy(label_sets, restarts=8, max_log2=None, seed=0, noises=(0.1, 0.3, 1.0)):
-    """Best of one deterministic greedy path and `restarts` randomised ones.
-    With a size bound, each path is sliced to it and ranked by the memoized
-    cost of the whole amplitude (every slice); without, by (max
-    intermediate, flops)."""
+def best_greedy(label_sets, restarts=8, max_log2=None, seed=0, noises=(0.1, 0.3, 1.0), alphas=(1.0,)):
+    """Best of one deterministic greedy path and `restarts` randomised ones,
+    for each size weight alpha of the greedy cost.  With a size bound, each
+    path is sliced to it and ranked by the memoized cost of the whole
+    amplitude (every slice); without, by (max intermediate, flops)."""
     best = None
-    for r in range(restarts + 1):
+    for r, alpha in ((r, a) for r in range(restarts + 1) for a in alphas):
         noise = 0.0 if r == 0 else noises[r % len(noises)]
-        p = greedy_path(label_sets, seed=seed + r, noise=noise)
+        p = greedy_path(label_sets, seed=seed + r, noise=noise, alpha=alpha)
         if max_log2 is None:
             ml, fl, _ = path_cost(label_sets, p)
             key = (ml, fl)
