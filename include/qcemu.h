@@ -171,6 +171,9 @@ qce_status qce_set_workspace(qce_handle *h, void *device_ptr, size_t bytes);
 /* Workspace bytes one qce_cgemm_emulated call of this shape needs. */
 size_t qce_cgemm_workspace_size(int64_t m, int64_t n, int64_t k);
 
+/* Workspace bytes one qce_cgemm_strided_batched call needs (0 if batch <= 0). */
+size_t qce_cgemm_batched_workspace_size(int64_t m, int64_t n, int64_t k, int64_t batch);
+
 /* ---------------------------------------------------------------------- */
 /* GEMM                                                                   */
 /* ---------------------------------------------------------------------- */
@@ -213,6 +216,38 @@ qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, 
  * *out (host).  For tests and logging only.  INVALID_VALUE if no GEMM ran.
  */
 qce_status qce_get_last_decision(qce_handle *h, qce_decision *out);
+
+/*
+ * Batched CGEMM: `batch` independent GEMMs of one shape, entry z being
+ *   C_z <- alpha op(A_z) op(B_z) + beta C_z,
+ *   A_z = A + z*strideA, B_z = B + z*strideB, C_z = C + z*strideC
+ * (strides in complex elements; strideA / strideB may be 0 to share an
+ * operand).  The batched variant of the cuBLAS-style CGEMM the paper's
+ * library intercepts (Sec. 3), and the grouped launch that runs the same
+ * contraction step of many slices at once (Sec. 5.3 slices).
+ *
+ * One launch per phase for the whole batch (statistics, selection, split,
+ * GEMM: the entry is blockIdx.z), and in AUTO mode every entry takes its own
+ * decision on the device (Sec. 4.1 rule per GEMM; its own shifts in
+ * FP16X2_SCALED).  Irregular shapes run the bandwidth-bound kernel for every
+ * entry, as qce_cgemm_emulated does.
+ *
+ * Errors: as qce_cgemm_emulated, plus INVALID_VALUE for batch < 0 or
+ * > 65535, negative strides, or strideC < ldc*(n-1)+m with batch > 1
+ * (overlapping outputs).  batch == 0 is a no-op success.
+ */
+qce_status qce_cgemm_strided_batched(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                                     int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                                     int64_t strideA, const qce_c32 *B, int64_t ldb, int64_t strideB,
+                                     const qce_c32 *beta, qce_c32 *C, int64_t ldc, int64_t strideC,
+                                     int64_t batch);
+
+/*
+ * Synchronises, then copies the decision record of entry `index` of the
+ * most recent GEMM call (index 0 for an unbatched call).  Valid until the
+ * next call on the handle.  INVALID_VALUE for an index outside the batch.
+ */
+qce_status qce_get_batch_decision(qce_handle *h, int64_t index, qce_decision *out);
 
 /* ---------------------------------------------------------------------- */
 /* Tensor contraction                                                     */
@@ -311,7 +346,8 @@ typedef enum {
     QCE_PHASE_PERMUTE = 6,
     QCE_PHASE_OTHER = 7,   /* scaling of C for k == 0, reductions */
     QCE_PHASE_GEMM_IRREGULAR = 8, /* bandwidth-bound FP32 kernel for irregular shapes */
-    QCE_NUM_PHASES = 9
+    QCE_PHASE_GEMM_BATCHED = 9,   /* one launch of a batch whose entries chose their modes */
+    QCE_NUM_PHASES = 10
 } qce_phase;
 
 typedef struct {

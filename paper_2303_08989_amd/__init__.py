@@ -124,6 +124,12 @@ class Handle:
         _check(self._h, self.lib.qce_get_last_decision(self._bind_stream(), ctypes.byref(d)))
         return _decision_dict(d)
 
+    def batch_decision(self, index):
+        """Synchronising read of entry ``index`` of the last (batched) GEMM."""
+        d = _lib.QceDecision()
+        _check(self._h, self.lib.qce_get_batch_decision(self._bind_stream(), int(index), ctypes.byref(d)))
+        return _decision_dict(d)
+
 
 def _decision_dict(d):
     return {"mode": d.mode, "mode_name": MODE_NAMES.get(d.mode, str(d.mode)),
@@ -145,6 +151,23 @@ def cgemm(h, opA, opB, m, n, k, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0):
     _check(hh, h.lib.qce_cgemm_emulated(hh, _lib.OPS[opA], _lib.OPS[opB], int(m), int(n), int(k),
                                         ctypes.byref(a), _ptr(A), int(lda), _ptr(B), int(ldb),
                                         ctypes.byref(b), _ptr(C), int(ldc)))
+    return C
+
+
+def cgemm_batched_workspace_size(m, n, k, batch):
+    return int(_lib.load().qce_cgemm_batched_workspace_size(int(m), int(n), int(k), int(batch)))
+
+
+def cgemm_strided_batched(h, opA, opB, m, n, k, A, lda, strideA, B, ldb, strideB, C, ldc, strideC,
+                          batch, alpha=1.0, beta=0.0):
+    """``batch`` column-major CGEMMs of one shape, entry z at A + z*strideA,
+    B + z*strideB, C + z*strideC (C-ABI ``qce_cgemm_strided_batched``)."""
+    hh = h._bind_stream()
+    a, b = _c32(alpha), _c32(beta)
+    _check(hh, h.lib.qce_cgemm_strided_batched(hh, _lib.OPS[opA], _lib.OPS[opB], int(m), int(n), int(k),
+                                               ctypes.byref(a), _ptr(A), int(lda), int(strideA),
+                                               _ptr(B), int(ldb), int(strideB), ctypes.byref(b),
+                                               _ptr(C), int(ldc), int(strideC), int(batch)))
     return C
 
 

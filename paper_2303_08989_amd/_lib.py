@@ -23,13 +23,14 @@ EXPORTS = (
     "qce_create", "qce_destroy", "qce_set_stream", "qce_set_mode", "qce_get_mode",
     "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_set_workspace",
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
+    "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_get_batch_decision",
     "qce_contract", "qce_permute", "qce_accumulate_f64", "qce_fidelity_f64",
     "qce_expstats", "qce_split", "qce_status_string", "qce_last_error",
     "qce_set_timing", "qce_set_timing_tag", "qce_reset_timing", "qce_get_timing",
 )
 
 PHASES = ("stats", "split", "gemm_fp16x2", "gemm_bf16x3", "gemm_fp32", "gemm_skipped",
-          "permute", "other", "gemm_irregular")
+          "permute", "other", "gemm_irregular", "gemm_batched")
 
 
 class QceC32(ctypes.Structure):
@@ -49,7 +50,7 @@ class QceDecision(ctypes.Structure):
 
 
 class QceTiming(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 9), ("count", ctypes.c_int64 * 9),
+    _fields_ = [("ms", ctypes.c_double * 10), ("count", ctypes.c_int64 * 10),
                 ("gemms_by_mode", ctypes.c_int64 * 4)]
 
 
@@ -88,6 +89,10 @@ def load():
         "qce_cgemm_emulated": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64,
                                     vp, i64, c32p, vp, i64]),
         "qce_get_last_decision": (st, [vp, ctypes.POINTER(QceDecision)]),
+        "qce_cgemm_batched_workspace_size": (ctypes.c_size_t, [i64, i64, i64, i64]),
+        "qce_cgemm_strided_batched": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64, i64,
+                                           vp, i64, i64, c32p, vp, i64, i64, i64]),
+        "qce_get_batch_decision": (st, [vp, i64, ctypes.POINTER(QceDecision)]),
         "qce_contract": (st, [vp, tp, vp, i32p, tp, vp, i32p, tp, vp, i32p]),
         "qce_permute": (st, [vp, tp, vp, i32p, vp]),
         "qce_accumulate_f64": (st, [vp, vp, vp]),

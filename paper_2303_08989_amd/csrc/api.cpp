@@ -20,6 +20,8 @@ struct qce_handle {
     double t = 0.1, t3 = 0.0;
     int64_t auto_min = 2048, emul_min = 512;
     DevState *st = nullptr;        // device
+    DevState *dec_base = nullptr;  // decisions of the last call (st, or a batch's states in the workspace)
+    int dec_count = 1;
     double *fid_partials = nullptr;  // device, kFidBlocks * 4
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -232,16 +234,48 @@ MatDesc stored_desc(const OperandView &v, int64_t rows, int64_t k) {
     return MatDesc{v.ptr, rows, k, v.ld};
 }
 
-// The emulated CGEMM of one GEMM: C = alpha * PA * PB^T + beta * C where PA
-// (m x k) and PB (n x k) are the panel views.  `ws` holds both panel buffers.
+// A batch of equally shaped GEMMs: entry z uses A + z*sa, B + z*sb,
+// C + z*sc (elements); count 1 is one GEMM.
+struct Batch {
+    int count = 1;
+    int64_t sa = 0, sb = 0, sc = 0;
+};
+
+// Workspace of one (batched) GEMM: panels of every entry, split-k partial
+// tiles, and for a batch the per-entry device states.
+struct CgemmWs {
+    size_t pa = 0, pb = 0, panels = 0, partial = 0, states = 0, total = 0;
+};
+CgemmWs cgemm_ws_layout(int64_t m, int64_t n, int64_t k, int count) {
+    CgemmWs w;
+    if (k == 0) return w;
+    if (irregular_shape(m, n, k)) {
+        w.total = align256(direct_ws_bytes(m, n, k, count));
+        return w;
+    }
+    w.pa = align256(panel_bytes(m, k));
+    w.pb = align256(panel_bytes(n, k));
+    w.panels = (w.pa + w.pb) * (size_t)count;
+    w.partial = align256(gemm_partial_bytes(m, n, k, count) * (size_t)count);
+    w.states = count > 1 ? align256(sizeof(DevState) * (size_t)count) : 0;
+    w.total = w.panels + w.partial + w.states;
+    return w;
+}
+
+// The emulated CGEMM of one GEMM (or a batch of them): C = alpha * PA * PB^T
+// + beta * C where PA (m x k) and PB (n x k) are the panel views.  `ws` holds
+// the panel buffers (cgemm_ws_layout).
 qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const OperandView &b,
                       int64_t m, int64_t n, int64_t k, float2 alpha, float2 beta, float2 *C,
-                      int64_t ldc, char *ws) {
+                      int64_t ldc, char *ws, const Batch &bt = Batch{}) {
     hipStream_t s = h->stream;
     const int beta_zero = beta.x == 0.f && beta.y == 0.f;
+    const bool batched = bt.count > 1;
+    h->dec_base = h->st;
+    h->dec_count = bt.count;  // host-side records (forced / irregular / k == 0) hold for every entry
     if (k == 0) {
         hipEvent_t e0 = span_begin(h);
-        QCE_HIP(h, launch_scale_c(C, m, n, ldc, beta, beta_zero, s));
+        QCE_HIP(h, launch_scale_c(C, m, n, ldc, beta, beta_zero, s, bt.count, bt.sc));
         span_end(h, e0, QCE_PHASE_OTHER);
         h->have_decision = true;
         h->last_on_device = false;
@@ -268,6 +302,10 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         d.beta = beta;
         d.beta_zero = beta_zero;
         d.partial = reinterpret_cast<float2 *>(ws);
+        d.batch = bt.count;
+        d.bsA = bt.sa;
+        d.bsB = bt.sb;
+        d.bsC = bt.sc;
         hipEvent_t e0 = span_begin(h);
         QCE_HIP(h, launch_direct(d, s));
         span_end(h, e0, QCE_PHASE_GEMM_IRREGULAR);
@@ -286,13 +324,22 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         QCE_HIP(h, resolve_timing(h));
     const int64_t call = h->n_calls++;
     const int slot = (int)(call % kLogCap);
-    int *log = h->timing ? h->mode_log : nullptr;
+    int *log = h->timing && !batched ? h->mode_log : nullptr;
 
+    const CgemmWs wl = cgemm_ws_layout(m, n, k, bt.count);
     char *panA = ws;
-    char *panB = panA + align256(panel_bytes(m, k));
-    char *part = panB + align256(panel_bytes(n, k));
-    const MatDesc da = stored_desc(a, m, k), db = stored_desc(b, n, k);
+    char *panB = panA + wl.pa * (size_t)bt.count;
+    char *part = ws + wl.panels;
+    DevState *dst = batched ? reinterpret_cast<DevState *>(ws + wl.panels + wl.partial) : h->st;
+    h->dec_base = dst;
+    MatDesc da = stored_desc(a, m, k), db = stored_desc(b, n, k);
+    da.bstride = bt.sa;
+    db.bstride = bt.sb;
     GemmArgs g{};
+    g.batch = bt.count;
+    g.bsA = (int64_t)wl.pa;
+    g.bsB = (int64_t)wl.pb;
+    g.bsC = bt.sc;
     g.panelsA = panA;
     g.panelsB = panB;
     g.m = m;
@@ -303,33 +350,42 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     g.alpha = alpha;
     g.beta = beta;
     g.beta_zero = beta_zero;
-    g.partial = gemm_partial_bytes(m, n, k) ? reinterpret_cast<float2 *>(part) : nullptr;
+    g.partial = gemm_partial_bytes(m, n, k, bt.count) ? reinterpret_cast<float2 *>(part) : nullptr;
+    const int nb = bt.count;
     if (mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED) {
         hipEvent_t e0 = span_begin(h);
-        QCE_HIP(h, launch_stats1(da, db, h->st, s));
+        QCE_HIP(h, launch_stats1(da, db, dst, s, nb));
         if (mode == QCE_MODE_AUTO) {
-            QCE_HIP(h, launch_stats2(da, db, h->st, h->t, 0, s));
-            QCE_HIP(h, launch_select(da, db, h->st, h->t, h->t3, -1, log, slot, s));
+            QCE_HIP(h, launch_stats2(da, db, dst, h->t, 0, s, nb));
+            QCE_HIP(h, launch_select(da, db, dst, h->t, h->t3, -1, log, slot, s, nb));
         } else {
-            QCE_HIP(h, launch_select(da, db, h->st, h->t, h->t3, QCE_MODE_FP16X2_SCALED, log, slot, s));
+            QCE_HIP(h, launch_select(da, db, dst, h->t, h->t3, QCE_MODE_FP16X2_SCALED, log, slot, s, nb));
         }
         span_end(h, e0, QCE_PHASE_STATS);
         hipEvent_t e1 = span_begin(h);
-        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, h->st, 0, 0, 0, s));
-        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, h->st, 1, 0, 0, s));
+        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, dst, 0, 0, 0, s, nb, bt.sa,
+                                       (int64_t)wl.pa));
+        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, dst, 1, 0, 0, s, nb, bt.sb,
+                                       (int64_t)wl.pb));
         span_end(h, e1, QCE_PHASE_SPLIT);
-        g.st = h->st;
+        g.st = dst;
         g.forced_mode = -1;
         hipEvent_t eg = span_begin(h);
         QCE_HIP(h, launch_gemm(g, -1, s));
-        span_end(h, eg, -1, -1, -1, call);
-        if (h->timing) h->recs.push_back({h->tag, -2, 0, -1, call, nullptr, nullptr, false, 0.0, 0});
+        if (batched) {
+            span_end(h, eg, QCE_PHASE_GEMM_BATCHED);
+        } else {
+            span_end(h, eg, -1, -1, -1, call);
+            if (h->timing) h->recs.push_back({h->tag, -2, 0, -1, call, nullptr, nullptr, false, 0.0, 0});
+        }
         h->have_decision = true;
         h->last_on_device = true;
     } else {
         hipEvent_t e1 = span_begin(h);
-        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, nullptr, 0, mode, 0, s));
-        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, nullptr, 1, mode, 0, s));
+        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, nullptr, 0, mode, 0, s, nb,
+                                       bt.sa, (int64_t)wl.pa));
+        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, nullptr, 1, mode, 0, s, nb,
+                                       bt.sb, (int64_t)wl.pb));
         span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = nullptr;
         g.forced_mode = mode;
@@ -351,11 +407,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     return QCE_SUCCESS;
 }
 
-size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k) {
-    if (k == 0) return 0;
-    if (irregular_shape(m, n, k)) return align256(direct_ws_bytes(m, n, k));
-    return align256(panel_bytes(m, k)) + align256(panel_bytes(n, k)) +
-           align256(gemm_partial_bytes(m, n, k));
+size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k, int count = 1) {
+    return cgemm_ws_layout(m, n, k, count).total;
 }
 
 bool valid_op(int op) { return op == QCE_OP_N || op == QCE_OP_T || op == QCE_OP_C; }
@@ -491,6 +544,7 @@ qce_status qce_create(qce_handle **out, int device) {
         delete h;
         return QCE_ERR_HIP;
     }
+    h->dec_base = h->st;
     *out = h;
     return QCE_SUCCESS;
 }
@@ -566,6 +620,11 @@ size_t qce_cgemm_workspace_size(int64_t m, int64_t n, int64_t k) {
     return cgemm_ws_bytes(m, n, k);
 }
 
+size_t qce_cgemm_batched_workspace_size(int64_t m, int64_t n, int64_t k, int64_t batch) {
+    if (m <= 0 || n <= 0 || k < 0 || batch <= 0 || batch > kMaxBatch) return 0;
+    return cgemm_ws_bytes(m, n, k, (int)batch);
+}
+
 qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
                               int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
                               const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
@@ -593,13 +652,65 @@ qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, 
                       static_cast<char *>(h->ws));
 }
 
+qce_status qce_cgemm_strided_batched(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                                     int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                                     int64_t strideA, const qce_c32 *B, int64_t ldb, int64_t strideB,
+                                     const qce_c32 *beta, qce_c32 *C, int64_t ldc, int64_t strideC,
+                                     int64_t batch) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (!valid_op(opA) || !valid_op(opB)) return fail(h, QCE_ERR_INVALID_VALUE, "bad op");
+    if (m < 0 || n < 0 || k < 0 || batch < 0) return fail(h, QCE_ERR_INVALID_VALUE, "negative size");
+    if (batch > kMaxBatch) return fail(h, QCE_ERR_INVALID_VALUE, "batch %lld > %d", (long long)batch, kMaxBatch);
+    const int64_t arows = opA == QCE_OP_N ? m : k, brows = opB == QCE_OP_N ? k : n;
+    if (lda < std::max<int64_t>(1, arows) || ldb < std::max<int64_t>(1, brows) ||
+        ldc < std::max<int64_t>(1, m))
+        return fail(h, QCE_ERR_INVALID_VALUE, "leading dimension too small");
+    if (strideA < 0 || strideB < 0 || strideC < 0) return fail(h, QCE_ERR_INVALID_VALUE, "negative stride");
+    if (batch > 1 && m > 0 && n > 0 && strideC < ldc * (n - 1) + m)
+        return fail(h, QCE_ERR_INVALID_VALUE, "C entries overlap (strideC too small)");
+    if (m == 0 || n == 0 || batch == 0) return QCE_SUCCESS;
+    if (!C || (k > 0 && (!A || !B))) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
+         reinterpret_cast<uintptr_t>(C)) & 7)
+        return fail(h, QCE_ERR_INVALID_VALUE, "pointer not 8-byte aligned");
+    DeviceGuard g(h->device);
+    const float2 al = alpha ? make_float2(alpha->re, alpha->im) : make_float2(1.f, 0.f);
+    const float2 be = beta ? make_float2(beta->re, beta->im) : make_float2(0.f, 0.f);
+    qce_status st = ensure_ws(h, cgemm_ws_bytes(m, n, k, (int)batch));
+    if (st != QCE_SUCCESS) return st;
+    OperandView va{reinterpret_cast<const float2 *>(A), lda, opA != QCE_OP_N, opA == QCE_OP_C};
+    OperandView vb{reinterpret_cast<const float2 *>(B), ldb, opB == QCE_OP_N, opB == QCE_OP_C};
+    Batch bt;
+    bt.count = (int)batch;
+    bt.sa = strideA;
+    bt.sb = strideB;
+    bt.sc = strideC;
+    return cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
+                      static_cast<char *>(h->ws), bt);
+}
+
 qce_status qce_get_last_decision(qce_handle *h, qce_decision *out) {
     if (!h || !out) return QCE_ERR_INVALID_VALUE;
     if (!h->have_decision) return fail(h, QCE_ERR_INVALID_VALUE, "no GEMM has run on this handle");
     DeviceGuard g(h->device);
     QCE_HIP(h, hipStreamSynchronize(h->stream));
     if (h->last_on_device) {
-        QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
+        QCE_HIP(h, hipMemcpy(out, &h->dec_base->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
+    } else {
+        *out = h->last_host;
+    }
+    return QCE_SUCCESS;
+}
+
+qce_status qce_get_batch_decision(qce_handle *h, int64_t index, qce_decision *out) {
+    if (!h || !out) return QCE_ERR_INVALID_VALUE;
+    if (!h->have_decision) return fail(h, QCE_ERR_INVALID_VALUE, "no GEMM has run on this handle");
+    if (index < 0 || index >= h->dec_count)
+        return fail(h, QCE_ERR_INVALID_VALUE, "entry %lld of a batch of %d", (long long)index, h->dec_count);
+    DeviceGuard g(h->device);
+    QCE_HIP(h, hipStreamSynchronize(h->stream));
+    if (h->last_on_device) {
+        QCE_HIP(h, hipMemcpy(out, &h->dec_base[index].last, sizeof(qce_decision), hipMemcpyDeviceToHost));
     } else {
         *out = h->last_host;
     }
@@ -613,8 +724,8 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
         return fail(h, QCE_ERR_INVALID_VALUE, "bad matrix");
     DeviceGuard g(h->device);
     hipStream_t s = h->stream;
-    MatDesc a{reinterpret_cast<const float2 *>(X), rows, cols, ld};
-    MatDesc none{nullptr, 0, 0, 1};
+    MatDesc a{reinterpret_cast<const float2 *>(X), rows, cols, ld, 0};
+    MatDesc none{nullptr, 0, 0, 1, 0};
     QCE_HIP(h, launch_stats1(a, none, h->st, s));
     QCE_HIP(h, launch_stats2(a, none, h->st, h->t, 2, s));
     QCE_HIP(h, launch_select(a, none, h->st, h->t, h->t3, -2, nullptr, 0, s));

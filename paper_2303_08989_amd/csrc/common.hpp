@@ -115,24 +115,33 @@ static_assert(PanelFmt<QCE_MODE_FP16X2>::kBK == kKPad && PanelFmt<QCE_MODE_BF16X
 struct MatDesc {  // a stored column-major complex64 matrix
     const float2 *ptr;
     int64_t rows, cols, ld;
+    int64_t bstride;  // elements between batch entries (entry z at ptr + z * bstride)
 };
 
-hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s);
+// Batched launches put the batch entry in blockIdx.z; entry z uses the
+// device state st + z (its own statistics, decision and record).
+constexpr int kMaxBatch = 65535;
+
+hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s,
+                         int batch = 1);
 // flag: 0 = stage 2 for operands failing stage 1, 1 = never, 2 = always
 hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int flag,
-                         hipStream_t s);
+                         hipStream_t s, int batch = 1);
 // forced_mode: -1 = rule, -2 = statistics-only entry point (stage 2 always
 // evaluated), >= 0 = that mode.  mode_log (nullable) receives the mode at slot.
 hipError_t launch_select(const MatDesc &a, const MatDesc &b, DevState *st, double t, double t3,
-                         int forced_mode, int *mode_log, int slot, hipStream_t s);
+                         int forced_mode, int *mode_log, int slot, hipStream_t s, int batch = 1);
 
 // Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
 // kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:
 // mode and shift come from the device decision (operand index `which`);
 // otherwise forced_mode / shift.
+// Batched: entry z reads x + z * xstride, writes panels + z * pstride bytes
+// and takes its decision from st + z.
 hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int conj, int64_t rows,
                                int64_t k, void *panels, const DevState *st, int which,
-                               int forced_mode, int shift, hipStream_t s);
+                               int forced_mode, int shift, hipStream_t s, int batch = 1,
+                               int64_t xstride = 0, int64_t pstride = 0);
 
 struct GemmArgs {
     const void *panelsA;  // rows = m
@@ -146,10 +155,14 @@ struct GemmArgs {
     int forced_mode;
     float2 *partial;         // split-k partial tiles (workspace), may be null if no split
     int64_t kpad_per_split;  // set by launch_gemm
+    int batch;               // entries (blockIdx.z); 0 or 1: one GEMM
+    int64_t bsA, bsB;        // panel bytes between entries
+    int64_t bsC;             // C elements between entries
+    int64_t bsPartial;       // partial elements between entries
 };
 // which_kernel: a mode (forced) or -1 (AUTO: read the device flag)
 hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
-size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k);
+size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch = 1);  // per entry
 
 // Irregular-shape CGEMM (direct.hip): PA[i][l], PB[j][l] read from the
 // stored matrices as in the split kernel; FP32 arithmetic.
@@ -165,14 +178,17 @@ struct DirectArgs {
     float2 *partial;  // split-k partial tiles (workspace)
     int kl, ti, tj;   // set by the planner
     int64_t kchunk;
+    int batch;                  // entries (blockIdx.z); 0 or 1: one GEMM
+    int64_t bsA, bsB, bsC;      // elements between entries
+    int64_t bsPartial;          // set by launch_direct
 };
 hipError_t launch_direct(DirectArgs d, hipStream_t s);
-size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k);
+size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k, int batch = 1);
 // shapes sent to the irregular kernel in every mode
 inline bool irregular_shape(int64_t m, int64_t n, int64_t k) { return m < 32 || n < 32 || k < 16; }
 
 hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,
-                          hipStream_t s);
+                          hipStream_t s, int batch = 1, int64_t bsC = 0);
 
 struct PermDesc {
     int rank;            // merged rank, <= kMaxRank

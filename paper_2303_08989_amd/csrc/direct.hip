@@ -36,8 +36,19 @@ __device__ inline float2 load_view(const float2 *p, int64_t ld, int kcontig, int
     return v;
 }
 
+// Batched launches: entry blockIdx.z works on its own operands, C and
+// partial tiles.
+__device__ inline void select_entry(DirectArgs &d) {
+    const int64_t z = blockIdx.z;
+    d.A += z * d.bsA;
+    d.B += z * d.bsB;
+    d.C += z * d.bsC;
+    if (d.partial) d.partial += z * d.bsPartial;
+}
+
 __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs d) {
     __shared__ float2 red[kThreads];
+    select_entry(d);
     const int t = threadIdx.x;
     const int kl = t % d.kl;
     const int o = t / d.kl;           // output within the tile
@@ -92,6 +103,7 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs d) {
 __global__ __launch_bounds__(kThreads) void direct_reduce_kernel(DirectArgs d, int splits) {
     const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (o >= d.m * d.n) return;
+    select_entry(d);
     float re = 0.f, im = 0.f;
     for (int s = 0; s < splits; ++s) {
         const float2 p = d.partial[(int64_t)s * d.m * d.n + o];
@@ -123,6 +135,7 @@ __device__ inline float2 scale_out(const DirectArgs &d, float re, float im, floa
 
 template <int JT>
 __global__ __launch_bounds__(kThreads) void direct_rows_kernel(DirectArgs d) {
+    select_entry(d);
     const int64_t row_blocks = (d.m + kThreads - 1) / kThreads;
     const int64_t b = blockIdx.x;
     const int64_t i = (b % row_blocks) * kThreads + threadIdx.x;
@@ -153,6 +166,7 @@ __global__ __launch_bounds__(kThreads) void direct_rows_kernel(DirectArgs d) {
 
 template <int MT>
 __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
+    select_entry(d);
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j >= d.n) return;
     float re[MT], im[MT];
@@ -212,7 +226,7 @@ void direct_plan(DirectArgs &d, int64_t &splits) {
     if (splits < 1) splits = 1;
 }
 
-size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k) {
+size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k, int batch) {
     if (k <= kShortK) return 0;
     DirectArgs d{};
     d.m = m;
@@ -220,15 +234,16 @@ size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k) {
     d.k = k;
     int64_t splits = 1;
     direct_plan(d, splits);
-    return splits > 1 ? (size_t)splits * (size_t)(m * n) * sizeof(float2) : 0;
+    return splits > 1 ? (size_t)std::max(1, batch) * (size_t)splits * (size_t)(m * n) * sizeof(float2) : 0;
 }
 
 hipError_t launch_direct(DirectArgs d, hipStream_t s) {
+    const unsigned nz = (unsigned)std::max(1, d.batch);
     if (d.k <= kShortK) {
         if (d.m >= 32) {
             const int jt = std::min(8, pow2_at_least(d.n));
             const int64_t blocks = ((d.m + kThreads - 1) / kThreads) * ((d.n + jt - 1) / jt);
-            const dim3 g((unsigned)blocks), t(kThreads);
+            const dim3 g((unsigned)blocks, 1, nz), t(kThreads);
             switch (jt) {
             case 1: hipLaunchKernelGGL(direct_rows_kernel<1>, g, t, 0, s, d); break;
             case 2: hipLaunchKernelGGL(direct_rows_kernel<2>, g, t, 0, s, d); break;
@@ -236,7 +251,7 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
             default: hipLaunchKernelGGL(direct_rows_kernel<8>, g, t, 0, s, d); break;
             }
         } else {
-            const dim3 g((unsigned)((d.n + kThreads - 1) / kThreads)), t(kThreads);
+            const dim3 g((unsigned)((d.n + kThreads - 1) / kThreads), 1, nz), t(kThreads);
             switch (pow2_at_least(d.m)) {
             case 1: hipLaunchKernelGGL(direct_cols_kernel<1>, g, t, 0, s, d); break;
             case 2: hipLaunchKernelGGL(direct_cols_kernel<2>, g, t, 0, s, d); break;
@@ -251,11 +266,12 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
     int64_t splits = 1;
     direct_plan(d, splits);
     const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);
-    hipLaunchKernelGGL(direct_kernel, dim3((unsigned)tiles, (unsigned)splits), dim3(kThreads), 0, s, d);
+    d.bsPartial = splits * d.m * d.n;
+    hipLaunchKernelGGL(direct_kernel, dim3((unsigned)tiles, (unsigned)splits, nz), dim3(kThreads), 0, s, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splits == 1) return e;
     const int64_t mn = d.m * d.n;
-    hipLaunchKernelGGL(direct_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads)),
+    hipLaunchKernelGGL(direct_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads), 1, nz),
                        dim3(kThreads), 0, s, d, (int)splits);
     return hipGetLastError();
 }

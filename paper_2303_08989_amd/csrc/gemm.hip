@@ -553,10 +553,22 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         }
 }
 
+// Batched launches: entry blockIdx.z works on its own panels, C, partial
+// tiles and device state.
+__device__ inline void select_entry(GemmArgs &g) {
+    const int64_t z = blockIdx.z;
+    g.panelsA = static_cast<const char *>(g.panelsA) + z * g.bsA;
+    g.panelsB = static_cast<const char *>(g.panelsB) + z * g.bsB;
+    g.C += z * g.bsC;
+    if (g.st) g.st += z;
+    if (g.partial) g.partial += z * g.bsPartial;
+}
+
 // Forced mode: one kernel per mode.
 template <int MODE>
 __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
     __shared__ __attribute__((aligned(16))) char smem[smem_bytes<MODE>()];
+    select_entry(g);
     gemm_body<MODE>(g, nbm, nbn, g.forced_mode, smem);
 }
 
@@ -564,6 +576,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, 
 // runs the selected mode's tile (the others never start).
 __global__ __launch_bounds__(kThreads, 1) void gemm_auto_kernel(GemmArgs g, int nbm, int nbn) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemBytes];
+    select_entry(g);
     const int mode = g.st->mode;
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
         gemm_body<QCE_MODE_FP16X2>(g, nbm, nbn, mode, smem);
@@ -577,6 +590,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_auto_kernel(GemmArgs g, int 
 __global__ __launch_bounds__(kThreads) void gemm_reduce_kernel(GemmArgs g, int splits) {
     const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (o >= g.m * g.n) return;
+    select_entry(g);
     const int mode = g.st ? g.st->mode : g.forced_mode;
     const int shift_total = (mode == QCE_MODE_FP16X2_SCALED && g.st) ? g.st->shift[0] + g.st->shift[1] : 0;
     float re = 0.f, im = 0.f;
@@ -602,9 +616,10 @@ __global__ __launch_bounds__(kThreads) void gemm_reduce_kernel(GemmArgs g, int s
 }
 
 __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta,
-                               int beta_zero) {
+                               int beta_zero, int64_t bsC) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m * n) return;
+    C += (int64_t)blockIdx.z * bsC;
     const int64_t i = t % m, j = t / m;
     float2 *cp = C + i + j * ldc;
     if (beta_zero) {
@@ -617,8 +632,8 @@ __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, flo
 
 }  // namespace
 
-int gemm_splits(int64_t m, int64_t n, int64_t k) {
-    const int64_t tiles = ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
+int gemm_splits(int64_t m, int64_t n, int64_t k, int batch) {
+    const int64_t tiles = ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile) * std::max(1, batch);
     const int64_t pads = round_up(k, kKPad) / kKPad;  // chunks of 16 k-values
     if (tiles >= 256 || pads < 32) return 1;
     int64_t s = 512 / tiles;              // aim at ~512 workgroups
@@ -629,11 +644,13 @@ int gemm_splits(int64_t m, int64_t n, int64_t k) {
 hipError_t launch_gemm(const GemmArgs &g0, int which, hipStream_t s) {
     GemmArgs g = g0;
     const int nbm = (int)((g.m + kTile - 1) / kTile), nbn = (int)((g.n + kTile - 1) / kTile);
-    const int splits = gemm_splits(g.m, g.n, g.k);
+    const int batch = std::max(1, g.batch);
+    const int splits = gemm_splits(g.m, g.n, g.k, batch);
     const int64_t pads = round_up(g.k, kKPad) / kKPad;
     g.kpad_per_split = ((pads + splits - 1) / splits) * kKPad;
     const int nsplit = (int)((round_up(g.k, kKPad) + g.kpad_per_split - 1) / g.kpad_per_split);
-    const dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit), block(kThreads);
+    g.bsPartial = (int64_t)nsplit * g.m * g.n;
+    const dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit, (unsigned)batch), block(kThreads);
     if (nsplit > 1 && !g.partial) return hipErrorInvalidValue;
     if (which < 0)
         hipLaunchKernelGGL(gemm_auto_kernel, grid, block, 0, s, g, nbm, nbn);
@@ -646,13 +663,13 @@ hipError_t launch_gemm(const GemmArgs &g0, int which, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsplit == 1) return e;
     const int64_t mn = g.m * g.n;
-    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads)), block, 0, s, g,
-                       nsplit);
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads), 1, (unsigned)batch),
+                       block, 0, s, g, nsplit);
     return hipGetLastError();
 }
 
-size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k) {
-    const int splits = gemm_splits(m, n, k);
+size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch) {
+    const int splits = gemm_splits(m, n, k, batch);
     if (splits <= 1) return 0;
     const int64_t pads = round_up(k, kKPad) / kKPad;
     const int64_t per = ((pads + splits - 1) / splits) * kKPad;
@@ -661,11 +678,11 @@ size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k) {
 }
 
 hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,
-                          hipStream_t s) {
+                          hipStream_t s, int batch, int64_t bsC) {
     const int64_t total = m * n;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, C,
-                       m, n, ldc, beta, beta_zero);
+    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)((total + 255) / 256), 1, (unsigned)std::max(1, batch)),
+                       dim3(256), 0, s, C, m, n, ldc, beta, beta_zero, bsC);
     return hipGetLastError();
 }
 

@@ -70,7 +70,11 @@ template <bool KCONTIG>
 __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
     int64_t rows_pad, int64_t nchunks, char *__restrict__ panels, const DevState *st, int which,
-    int forced_mode, int forced_shift) {
+    int forced_mode, int forced_shift, int64_t xstride, int64_t pstride) {
+    // batch entry
+    x += (int64_t)blockIdx.z * xstride;
+    panels += (int64_t)blockIdx.z * pstride;
+    if (st) st += blockIdx.z;
     int64_t r, c;  // row and chunk
     if (KCONTIG) {
         const int64_t row_blocks = rows_pad / 64;
@@ -168,7 +172,8 @@ __global__ __launch_bounds__(kThreads) void split_planar_kernel(int mode, int sh
 
 hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int conj, int64_t rows,
                                int64_t k, void *panels, const DevState *st, int which,
-                               int forced_mode, int shift, hipStream_t s) {
+                               int forced_mode, int shift, hipStream_t s, int batch,
+                               int64_t xstride, int64_t pstride) {
     const int64_t rows_pad = round_up(rows, kPanelRows);
     const int64_t nchunks = round_up(k, kKPad) / kKPad;
     const int64_t total = rows_pad * nchunks;
@@ -176,12 +181,14 @@ hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int co
     char *p = static_cast<char *>(panels);
     if (!kcontig) {
         const int64_t blocks = (total + kThreads - 1) / kThreads;
-        hipLaunchKernelGGL(split_panels_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift);
+        hipLaunchKernelGGL(split_panels_kernel<false>, dim3((unsigned)blocks, 1, batch), dim3(kThreads), 0,
+                           s, x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift,
+                           xstride, pstride);
     } else {
         const int64_t blocks = (rows_pad / 64) * ((nchunks + 3) / 4);
-        hipLaunchKernelGGL(split_panels_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                           x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift);
+        hipLaunchKernelGGL(split_panels_kernel<true>, dim3((unsigned)blocks, 1, batch), dim3(kThreads), 0,
+                           s, x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift,
+                           xstride, pstride);
     }
     return hipGetLastError();
 }

@@ -171,6 +171,9 @@ __device__ inline OperandStats reduce_partials(const DevState *st, int op, int n
 __global__ __launch_bounds__(kThreads) void stats1_kernel(MatDesc a, MatDesc b, int blocks_a,
                                                           DevState *st) {
     __shared__ unsigned long long sh[kThreads / 64];
+    st += blockIdx.z;
+    a.ptr += (int64_t)blockIdx.z * a.bstride;
+    b.ptr += (int64_t)blockIdx.z * b.bstride;
     const bool is_a = (int)blockIdx.x < blocks_a;
     const MatDesc &d = is_a ? a : b;
     const int64_t blk = is_a ? blockIdx.x : blockIdx.x - blocks_a;
@@ -203,6 +206,9 @@ __device__ inline bool stage2_runs(const OperandStats &s, double t, int flag) {
 __global__ __launch_bounds__(kThreads) void stats2_kernel(MatDesc a, MatDesc b, int blocks_a,
                                                           DevState *st, double t, int flag) {
     __shared__ unsigned long long sh[kThreads / 64];
+    st += blockIdx.z;
+    a.ptr += (int64_t)blockIdx.z * a.bstride;
+    b.ptr += (int64_t)blockIdx.z * b.bstride;
     const bool is_a = (int)blockIdx.x < blocks_a;
     const int op = is_a ? 0 : 1;
     const int64_t blk = is_a ? blockIdx.x : blockIdx.x - blocks_a;
@@ -236,6 +242,8 @@ __global__ __launch_bounds__(kThreads) void select_kernel(int blocks_a, int bloc
                                                           double t, double t3, int forced,
                                                           int stage2_flag, int *mode_log, int slot) {
     __shared__ unsigned long long sh[kThreads / 64];
+    st += blockIdx.x;                // one block per batch entry
+    if (blockIdx.x != 0) mode_log = nullptr;
     OperandStats s[2];
     bool ran[2];
     for (int o = 0; o < 2; ++o) {
@@ -283,28 +291,30 @@ int stats_blocks(int64_t nf) {
 
 }  // namespace
 
-hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s) {
+hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s,
+                         int batch) {
     const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
-    hipLaunchKernelGGL(stats1_kernel, dim3(ba + bb), dim3(kThreads), 0, s, a, b, ba, st);
+    hipLaunchKernelGGL(stats1_kernel, dim3(ba + bb, 1, batch), dim3(kThreads), 0, s, a, b, ba, st);
     return hipGetLastError();
 }
 
 hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int flag,
-                         hipStream_t s) {
+                         hipStream_t s, int batch) {
     if (flag == 1) return hipSuccess;
     const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
-    hipLaunchKernelGGL(stats2_kernel, dim3(ba + bb), dim3(kThreads), 0, s, a, b, ba, st, t, flag);
+    hipLaunchKernelGGL(stats2_kernel, dim3(ba + bb, 1, batch), dim3(kThreads), 0, s, a, b, ba, st, t,
+                       flag);
     return hipGetLastError();
 }
 
 hipError_t launch_select(const MatDesc &a, const MatDesc &b, DevState *st, double t, double t3,
-                         int forced_mode, int *mode_log, int slot, hipStream_t s) {
+                         int forced_mode, int *mode_log, int slot, hipStream_t s, int batch) {
     // stage-2 flag as used by launch_stats2: forced modes skip stage 2,
     // forced_mode == -2 is the statistics-only entry point (stage 2 always)
     const int flag = forced_mode == -1 ? 0 : (forced_mode == -2 ? 2 : 1);
     const int forced = forced_mode < 0 ? -1 : forced_mode;
     const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kThreads), 0, s, ba, bb, st, t, t3, forced, flag,
+    hipLaunchKernelGGL(select_kernel, dim3(batch), dim3(kThreads), 0, s, ba, bb, st, t, t3, forced, flag,
                        mode_log, slot);
     return hipGetLastError();
 }
