@@ -301,8 +301,11 @@ def select_mode(stA, stB, t=0.1, t3=0.0):
 def zcontract(A, la, B, lb, lc):
     """C[lc] = sum A[la] B[lb] in complex128 by nested loops (C odometer).
 
-    Labels shared by A and B and absent from lc are summed; every label of lc
-    must appear in exactly one input.  A and B may be complex64 or complex128
+    Labels shared by A and B and absent from lc are summed; a label shared by
+    A and B and present in lc is a batch label (it indexes A, B and C alike:
+    one independent contraction per value, as when the sliced labels of a
+    network are kept as an index instead of fixed, Sec. 5.3).  Every label of
+    lc appears in at least one input.  A and B may be complex64 or complex128
     (widened exactly).  Returns a complex128 array with axes ordered as lc.
     """
     A = np.ascontiguousarray(A, dtype=np.complex128)
@@ -321,8 +324,8 @@ def zcontract(A, la, B, lb, lc):
             ext[lab] = T.shape[d]
     summed = [lab for lab in union if lab in la and lab in lb and lab not in lc]
     for lab in lc:
-        if (lab in la) == (lab in lb):
-            raise ValueError("output label must appear in exactly one input")
+        if lab not in la and lab not in lb:
+            raise ValueError("output label must appear in an input")
     for lab in union:
         if lab not in lc and lab not in summed:
             raise ValueError("label summed over a single input is not supported")

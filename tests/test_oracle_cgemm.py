@@ -142,9 +142,42 @@ def test_contract_output_permutation_is_exact():
     assert np.array_equal(np.transpose(C, perm), C2)
 
 
-def test_contract_rejects_batch_and_dangling_labels():
+def test_contract_rejects_dangling_labels():
     A = np.ones((2, 2), dtype=np.complex64)
     with pytest.raises(ValueError):
-        oracle.zcontract(A, [0, 1], A, [1, 2], [0, 1, 2])   # batch label
-    with pytest.raises(ValueError):
         oracle.zcontract(A, [0, 3], A, [1, 2], [1, 2])      # label summed over one input
+    with pytest.raises(ValueError):
+        oracle.zcontract(A, [0, 1], A, [1, 2], [0, 2, 9])   # output label in no input
+
+
+def test_zcontract_batch_labels_are_independent_contractions():
+    # a label in A, B and C indexes one independent contraction per value:
+    # the result equals the per-value contractions stacked along that label,
+    # and the batched matrix product numpy computes
+    rng = np.random.default_rng(21)
+    A = (rng.standard_normal((3, 4, 5)) + 1j * rng.standard_normal((3, 4, 5))).astype(np.complex64)
+    B = (rng.standard_normal((5, 3, 2)) + 1j * rng.standard_normal((5, 3, 2))).astype(np.complex64)
+    # labels: batch 0 (extent 3), row 1 (4), contracted 2 (5), col 3 (2)
+    C = oracle.zcontract(A, [0, 1, 2], B, [2, 0, 3], [1, 0, 3])
+    for b in range(3):
+        per = oracle.zcontract(A[b], [1, 2], B[:, b, :], [2, 3], [1, 3])
+        assert np.array_equal(C[:, b, :], per)
+    want = np.matmul(A.astype(np.complex128), np.transpose(B, (1, 0, 2)).astype(np.complex128))
+    assert np.max(np.abs(np.transpose(C, (1, 0, 2)) - want)) < 1e-12
+
+
+def test_zcontract_batch_only_label():
+    # every label batch: an elementwise product
+    a = np.array([1 + 2j, 3 - 1j], dtype=np.complex64)
+    b = np.array([2 - 1j, 1j], dtype=np.complex64)
+    c = oracle.zcontract(a, [7], b, [7], [7])
+    assert np.array_equal(c, a.astype(np.complex128) * b.astype(np.complex128))
+
+
+def test_zcontract_batch_bruteforce():
+    rng = np.random.default_rng(4)
+    ext = {0: 2, 1: 3, 2: 2, 3: 3, 4: 2}
+    la, lb, lc = [0, 4, 1, 2], [2, 3, 0, 4], [3, 0, 1, 4]      # 0 and 4 batch, 2 summed
+    A = synth.random_matrix(1, 24, "int", rng).reshape(tuple(ext[x] for x in la))
+    B = synth.random_matrix(1, 24, "int", rng).reshape(tuple(ext[x] for x in lb))
+    assert np.array_equal(oracle.zcontract(A, la, B, lb, lc), _py_contract(A, la, B, lb, lc, ext))
