@@ -263,11 +263,15 @@ qce_status qce_get_batch_decision(qce_handle *h, int64_t index, qce_decision *ou
  * a, b, c: host shape descriptors; A, B: device complex64 inputs; C: device
  * complex64 output of the shape c describes (must not overlap A or B).
  * la, lb, lc: host int32 label arrays of lengths a->rank, b->rank, c->rank.
+ * A label in A, B and C is a batch label: one independent contraction per
+ * value (the sliced labels of a network kept as an index instead of fixed,
+ * Sec. 5.3); the batch runs as a strided batched GEMM
+ * (qce_cgemm_strided_batched semantics, per-entry modes in AUTO), in
+ * launches of at most 65535 entries, with the batch labels made outermost.
  * Requirements (else INVALID_VALUE): labels unique within each tensor; a
  * label in both A and B has equal extents there; every label of lc appears
- * in exactly one of la, lb with the same extent; c's extents match.
- * NOT_SUPPORTED: a label in A, B and C (batch), or a label in only one input
- * and not in C (a trace).
+ * in la or lb with the same extent; c's extents match.
+ * NOT_SUPPORTED: a label in only one input and not in C (a trace).
  */
 qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const int32_t *la,
                         const qce_tensor *b, const void *B, const int32_t *lb,

@@ -815,13 +815,17 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     };
     if (!unique(la, ra) || !unique(lb, rb) || !unique(lc, rc))
         return fail(h, QCE_ERR_INVALID_VALUE, "duplicate label within a tensor");
-    std::vector<int32_t> K, FA, FB;  // labels in A's / B's order
+    std::vector<int32_t> K, FA, FB, BT;  // labels in A's / B's order
     for (int i = 0; i < ra; ++i) {
         const int jb = find(lb, rb, la[i]), jc = find(lc, rc, la[i]);
         if (jb >= 0) {
             if (a->extents[i] != b->extents[jb]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
-            if (jc >= 0) return fail(h, QCE_ERR_NOT_SUPPORTED, "batch label %d", la[i]);
-            K.push_back(la[i]);
+            if (jc >= 0) {
+                if (c->extents[jc] != a->extents[i]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
+                BT.push_back(la[i]);
+            } else {
+                K.push_back(la[i]);
+            }
         } else {
             if (jc < 0) return fail(h, QCE_ERR_NOT_SUPPORTED, "label %d summed over one input", la[i]);
             if (c->extents[jc] != a->extents[i]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
@@ -835,7 +839,8 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         if (c->extents[jc] != b->extents[i]) return fail(h, QCE_ERR_INVALID_VALUE, "extent mismatch");
         FB.push_back(lb[i]);
     }
-    if ((int)(FA.size() + FB.size()) != rc) return fail(h, QCE_ERR_INVALID_VALUE, "output label not in any input");
+    if ((int)(FA.size() + FB.size() + BT.size()) != rc)
+        return fail(h, QCE_ERR_INVALID_VALUE, "output label not in any input");
 
     auto ext_of = [&](int32_t lab) -> int64_t {
         int i = find(la, ra, lab);
@@ -847,27 +852,40 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         for (int32_t x : ls) p *= ext_of(x);
         return p;
     };
-    const int64_t kk = prod(K), ma = prod(FA), nb = prod(FB);
+    // batch labels (in A, B and C): one independent GEMM per value, outermost
+    // everywhere, in the order C lists them
+    std::vector<int32_t> BO;
+    for (int i = 0; i < rc; ++i)
+        if (std::find(BT.begin(), BT.end(), lc[i]) != BT.end()) BO.push_back(lc[i]);
+    const int nbt = (int)BO.size();
+    const int64_t kk = prod(K), ma = prod(FA), nb = prod(FB), count = prod(BO);
+    bool bt_front = true;
+    for (int i = 0; i < nbt; ++i)
+        if (lc[i] != BO[i]) bt_front = false;
 
-    // Output: C row-major with labels lc.  As a column-major matrix it is
-    // m x n when lc = [free labels of the "GEMM-B" operand][free labels of
-    // the "GEMM-A" operand].  Try both roles; otherwise compute into a
-    // temporary [FB (B order)][FA (A order)] and permute.
+    // Output: C row-major with labels lc = [BO][rest].  Per batch entry the
+    // rest is, as a column-major matrix, m x n when rest = [free labels of
+    // the "GEMM-B" operand][free labels of the "GEMM-A" operand].  Try both
+    // roles; otherwise compute into a temporary [BO][FB (B order)][FA (A
+    // order)] and permute.
+    const int32_t *lcr = lc + nbt;
+    const int rcr = rc - nbt;
     auto is_set_block = [&](int off, int len, const std::vector<int32_t> &set) {
         if (len != (int)set.size()) return false;
         for (int i = 0; i < len; ++i)
-            if (std::find(set.begin(), set.end(), lc[off + i]) == set.end()) return false;
+            if (std::find(set.begin(), set.end(), lcr[off + i]) == set.end()) return false;
         return true;
     };
     bool swap = false, out_perm = false;
     std::vector<int32_t> SA, SB;  // free-label order required of GEMM-A / GEMM-B operand
-    if (is_set_block(rc - (int)FA.size(), (int)FA.size(), FA) && is_set_block(0, (int)FB.size(), FB)) {
-        SA.assign(lc + rc - FA.size(), lc + rc);
-        SB.assign(lc, lc + FB.size());
-    } else if (is_set_block(rc - (int)FB.size(), (int)FB.size(), FB) && is_set_block(0, (int)FA.size(), FA)) {
+    if (bt_front && is_set_block(rcr - (int)FA.size(), (int)FA.size(), FA) && is_set_block(0, (int)FB.size(), FB)) {
+        SA.assign(lcr + rcr - FA.size(), lcr + rcr);
+        SB.assign(lcr, lcr + FB.size());
+    } else if (bt_front && is_set_block(rcr - (int)FB.size(), (int)FB.size(), FB) &&
+               is_set_block(0, (int)FA.size(), FA)) {
         swap = true;
-        SA.assign(lc + rc - FB.size(), lc + rc);
-        SB.assign(lc, lc + FA.size());
+        SA.assign(lcr + rcr - FB.size(), lcr + rcr);
+        SB.assign(lcr, lcr + FA.size());
     } else {
         out_perm = true;
         SA = FA;
@@ -880,15 +898,19 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     const int64_t *ex = swap ? b->extents : a->extents, *ey = swap ? a->extents : b->extents;
     const int64_t m = swap ? nb : ma, n = swap ? ma : nb;
 
-    // Does operand (labels l) hold [K][F] or [F][K] with the given orders?
+    // Does operand (labels l) hold [BO][K][F] or [BO][F][K] with the given
+    // orders?  0: [K][F], 1: [F][K], -1: neither
     auto layout = [&](const int32_t *l, int r, const std::vector<int32_t> &korder,
                       const std::vector<int32_t> &forder) -> int {
-        // 0: [K][F], 1: [F][K], -1: neither
+        for (int i = 0; i < nbt; ++i)
+            if (l[i] != BO[i]) return -1;
+        const int32_t *q = l + nbt;
+        const int rq = r - nbt;
         bool kf = true, fk = true;
         const int nk = (int)korder.size(), nf = (int)forder.size();
-        for (int i = 0; i < r; ++i) {
-            if (i < nk ? l[i] != korder[i] : l[i] != forder[i - nk]) kf = false;
-            if (i < nf ? l[i] != forder[i] : l[i] != korder[i - nf]) fk = false;
+        for (int i = 0; i < rq; ++i) {
+            if (i < nk ? q[i] != korder[i] : q[i] != forder[i - nk]) kf = false;
+            if (i < nf ? q[i] != forder[i] : q[i] != korder[i - nf]) fk = false;
         }
         return kf ? 0 : (fk ? 1 : -1);
     };
@@ -913,7 +935,8 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     const int lay_x = layout(lx, rx, korder, SA), lay_y = layout(ly, ry, korder, SB);
 
     // workspace: panels | permuted X | permuted Y | temporary C
-    size_t off = align256(cgemm_ws_bytes(m, n, kk));
+    const int chunk = (int)std::min<int64_t>(std::max<int64_t>(count, 1), kMaxBatch);
+    size_t off = align256(cgemm_ws_bytes(m, n, kk, chunk));
     const size_t offx = off;
     if (lay_x < 0) off += align256((size_t)sx * 8);
     const size_t offy = off;
@@ -928,6 +951,7 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     auto permute_to_kf = [&](const int32_t *l, int r, const int64_t *e, const void *src,
                              const std::vector<int32_t> &forder, void *dst) -> qce_status {
         std::vector<int32_t> perm;
+        for (int32_t lab : BO) perm.push_back(find(l, r, lab));
         for (int32_t lab : korder) perm.push_back(find(l, r, lab));
         for (int32_t lab : forder) perm.push_back(find(l, r, lab));
         return run_permute(h, r, e, perm.data(), static_cast<const float2 *>(src),
@@ -960,12 +984,24 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         else mode = QCE_MODE_FP32;
     }
     float2 *Cg = out_perm ? reinterpret_cast<float2 *>(ws + offc) : static_cast<float2 *>(C);
-    st = cgemm_core(h, mode, vx, vy, m, n, kk, make_float2(1.f, 0.f), make_float2(0.f, 0.f), Cg,
-                    std::max<int64_t>(1, m), ws);
-    if (st != QCE_SUCCESS) return st;
+    // batch entries in launches of at most kMaxBatch
+    for (int64_t z0 = 0; z0 < std::max<int64_t>(count, 1); z0 += chunk) {
+        Batch bt;
+        bt.count = (int)std::min<int64_t>(chunk, std::max<int64_t>(count, 1) - z0);
+        bt.sa = kk * m;
+        bt.sb = kk * n;
+        bt.sc = m * n;
+        OperandView cx = vx, cy = vy;
+        cx.ptr += z0 * bt.sa;
+        cy.ptr += z0 * bt.sb;
+        st = cgemm_core(h, mode, cx, cy, m, n, kk, make_float2(1.f, 0.f), make_float2(0.f, 0.f),
+                        Cg + z0 * bt.sc, std::max<int64_t>(1, m), ws, bt);
+        if (st != QCE_SUCCESS) return st;
+    }
     if (out_perm) {
-        // temporary has labels [SB][SA] (row-major); permute to lc
-        std::vector<int32_t> tl(SB);
+        // temporary has labels [BO][SB][SA] (row-major); permute to lc
+        std::vector<int32_t> tl(BO);
+        tl.insert(tl.end(), SB.begin(), SB.end());
         tl.insert(tl.end(), SA.begin(), SA.end());
         std::vector<int64_t> te;
         for (int32_t lab : tl) te.push_back(ext_of(lab));

@@ -130,9 +130,6 @@ def test_contract_layouts_float(qce, h, layout):
 def test_contract_errors(qce, h):
     a = torch.zeros((2, 2), dtype=torch.complex64, device="cuda")
     with pytest.raises(qce.QceError) as e:
-        qce.contract(h, a, [0, 1], a, [1, 2], [0, 1, 2])     # batch label
-    assert e.value.status == 2
-    with pytest.raises(qce.QceError) as e:
         qce.contract(h, a, [0, 3], a, [1, 2], [1, 2])        # trace over one input
     assert e.value.status == 2
     b = torch.zeros((2, 3), dtype=torch.complex64, device="cuda")
@@ -238,3 +235,58 @@ def test_reduced_config3_sliced(qce, h):
     assert len(plan.sliced) >= 1
     want = oracle.statevector_amplitudes(rounded(c), xs)
     assert oracle.fidelity(got, want) >= 1 - 1e-6
+
+
+# --- batch labels (in both inputs and the output) ------------------------
+
+def _batch_case(rng, ext, la, lb, lc):
+    def t(ls):
+        shape = tuple(ext[x] for x in ls)
+        n = int(np.prod(shape)) if shape else 1
+        return synth.random_matrix(1, n, "int", rng).reshape(shape)
+    return t(la), t(lb)
+
+
+BATCH_CASES = [
+    # (extents, la, lb, lc)
+    ({0: 3, 1: 40, 2: 48, 3: 36}, [0, 1, 2], [0, 2, 3], [0, 3, 1]),          # batch in front everywhere
+    ({0: 3, 1: 40, 2: 48, 3: 36}, [1, 0, 2], [2, 3, 0], [3, 0, 1]),          # batch in the middle: permutes
+    ({0: 2, 5: 3, 1: 64, 2: 64, 3: 64}, [5, 0, 1, 2], [0, 5, 2, 3], [0, 5, 3, 1]),  # two batch labels
+    ({0: 4, 1: 2, 2: 2, 3: 2}, [0, 1, 2], [0, 2, 3], [1, 0, 3]),             # irregular entries
+    ({0: 5, 1: 33, 3: 40}, [0, 1], [0, 3], [0, 1, 3]),                       # no summed label
+    ({0: 7, 2: 300}, [0, 2], [2, 0], [0]),                                   # batched dot products
+]
+
+
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated", "fp16x2", "bf16x3"])
+@pytest.mark.parametrize("case", range(len(BATCH_CASES)))
+def test_contract_batch_labels_integer_exact(qce, h, mode, case):
+    ext, la, lb, lc = BATCH_CASES[case]
+    rng = np.random.default_rng(50 + case)
+    A, B = _batch_case(rng, ext, la, lb, lc)
+    if mode == "auto_emulated":
+        h.set_mode("auto")
+        h.set_size_policy(0, 0)
+    else:
+        h.set_mode(mode)
+    try:
+        C = qce.contract(h, torch.from_numpy(A).to("cuda"), la, torch.from_numpy(B).to("cuda"), lb, lc)
+        C = C.cpu().numpy()
+    finally:
+        h.set_size_policy(2048, 512)
+        h.set_mode("auto")
+    assert np.array_equal(C.astype(np.complex128), oracle.zcontract(A, la, B, lb, lc))
+
+
+def test_contract_batch_more_than_one_launch(qce, h):
+    # 2^17 batch entries (more than one launch of at most 65535)
+    rng = np.random.default_rng(8)
+    nb = 17
+    bl = list(range(10, 10 + nb))
+    ext = {x: 2 for x in bl}
+    ext.update({0: 2, 1: 2, 2: 2})
+    la, lb, lc = bl + [0, 1], bl + [1, 2], bl + [0, 2]
+    A, B = _batch_case(rng, ext, la, lb, lc)
+    C = qce.contract(h, torch.from_numpy(A).to("cuda"), la, torch.from_numpy(B).to("cuda"), lb, lc).cpu().numpy()
+    want = np.matmul(A.reshape(-1, 2, 2).astype(np.complex128), B.reshape(-1, 2, 2).astype(np.complex128))
+    assert np.array_equal(C.reshape(-1, 2, 2).astype(np.complex128), want)
