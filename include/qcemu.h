@@ -298,6 +298,16 @@ qce_status qce_permute(qce_handle *h, const qce_tensor *x, const void *X, const 
 qce_status qce_accumulate_f64(qce_handle *h, const qce_c32 *src, double *acc2);
 
 /*
+ * acc2[0..1] += (sum re, sum im) of n complex64 values src[0..n) (device),
+ * in FP64: the sum of the slice amplitudes that a batched pass over sliced
+ * labels returns as one tensor (Sec. 5.3).  Deterministic: fixed-order
+ * per-block partial sums, then one block adds them in block order.  Uses the
+ * handle's reduction scratch, so calls are stream-ordered per handle.
+ * INVALID_VALUE for NULL acc2, n < 0, or NULL src with n > 0.
+ */
+qce_status qce_accumulate_n_f64(qce_handle *h, const qce_c32 *src, int64_t n, double *acc2);
+
+/*
  * out4 (device, 4 doubles) <- { re(sum conj(b) a), im(sum conj(b) a),
  * sum |a|^2, sum |b|^2 } over n complex64 values of a and b (device), in
  * FP64: the terms of the fidelity |<b|a>|^2 / (<a|a><b|b>) between two

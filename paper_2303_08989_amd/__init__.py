@@ -240,6 +240,13 @@ def accumulate_f64(h, src, acc):
     return acc
 
 
+def accumulate_n_f64(h, src, acc):
+    """acc (float64[2], device) += sum of the complex64 device tensor src, in FP64."""
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_accumulate_n_f64(hh, _ptr(src), int(src.numel()), _ptr(acc)))
+    return acc
+
+
 def fidelity_terms(h, a, b, out=None):
     """out (float64[4], device) = [re <b|a>, im <b|a>, <a|a>, <b|b>] in FP64."""
     torch = _torch()

@@ -774,6 +774,18 @@ qce_status qce_accumulate_f64(qce_handle *h, const qce_c32 *src, double *acc2) {
     return QCE_SUCCESS;
 }
 
+qce_status qce_accumulate_n_f64(qce_handle *h, const qce_c32 *src, int64_t n, double *acc2) {
+    if (!h || !acc2 || n < 0 || (n > 0 && !src)) return QCE_ERR_INVALID_VALUE;
+    if (n == 0) return QCE_SUCCESS;
+    DeviceGuard g(h->device);
+    const int nb = (int)std::min<int64_t>(kFidBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    hipEvent_t e0 = span_begin(h);
+    QCE_HIP(h, launch_accumulate_n_f64(reinterpret_cast<const float2 *>(src), n, h->fid_partials, nb, acc2,
+                                       h->stream));
+    span_end(h, e0, QCE_PHASE_OTHER);
+    return QCE_SUCCESS;
+}
+
 qce_status qce_fidelity_f64(qce_handle *h, const qce_c32 *a, const qce_c32 *b, int64_t n,
                             double *out4) {
     if (!h || !out4 || n < 0 || (n > 0 && (!a || !b))) return QCE_ERR_INVALID_VALUE;

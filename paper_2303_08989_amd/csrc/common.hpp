@@ -202,6 +202,8 @@ hipError_t launch_permute(const float2 *x, float2 *y, int64_t total, const PermD
                           hipStream_t s);
 
 hipError_t launch_accumulate_f64(const float2 *src, double *acc2, hipStream_t s);
+hipError_t launch_accumulate_n_f64(const float2 *src, int64_t n, double *partials, int nblocks,
+                                   double *acc2, hipStream_t s);
 hipError_t launch_fidelity_f64(const float2 *a, const float2 *b, int64_t n, double *partials,
                                int nblocks, double *out4, hipStream_t s);
 hipError_t launch_split_planar(int mode, int shift, const float2 *x, int64_t n, uint16_t *planes,

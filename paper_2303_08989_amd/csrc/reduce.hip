@@ -67,7 +67,45 @@ __global__ void fidelity_final_kernel(const double *partials, int nblocks, doubl
     }
 }
 
+// Sum of n complex64 values in FP64 (the slice amplitudes of a batched
+// pass): per-block partial sums in a fixed order, then one block adds them
+// in block order to the accumulator.
+__global__ __launch_bounds__(kThreads) void sum_partial_kernel(const float2 *src, int64_t n,
+                                                               double *partials) {
+    __shared__ double sh[kThreads / 64];
+    double re = 0.0, im = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const float2 v = src[i];
+        re += (double)v.x;
+        im += (double)v.y;
+    }
+    re = block_sum_d(re, sh);
+    im = block_sum_d(im, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = re;
+        partials[2 * blockIdx.x + 1] = im;
+    }
+}
+
+__global__ void sum_final_kernel(const double *partials, int nblocks, double *acc2) {
+    if (threadIdx.x < 2 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nblocks; ++i) s += partials[2 * i + threadIdx.x];
+        acc2[threadIdx.x] += s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_accumulate_n_f64(const float2 *src, int64_t n, double *partials, int nblocks,
+                                   double *acc2, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partial_kernel, dim3(nblocks), dim3(kThreads), 0, s, src, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(64), 0, s, partials, nblocks, acc2);
+    return hipGetLastError();
+}
 
 hipError_t launch_accumulate_f64(const float2 *src, double *acc2, hipStream_t s) {
     hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, s, src, acc2);

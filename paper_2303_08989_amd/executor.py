@@ -170,3 +170,153 @@ class Executor:
                 slice_out[n_done:n_done + 1].copy_(vals[root].reshape(-1)[:1])
             n_done += 1
         return acc
+
+
+class BatchedExecutor:
+    """Runs a CircuitPlan with the first ``n_batch`` sliced labels (those
+    entering the tree latest) kept as batch labels instead of fixed: one
+    pass over the tree computes the 2^n_batch slices that differ only in
+    those labels, every contraction being one batched GEMM over the batch
+    labels both operands carry (``qce_contract`` with batch labels; a node
+    that depends on no batch label is computed once, which is the
+    memoization of ``Executor`` for free).  The root is the tensor of the
+    pass's slice values, summed in FP64 on the device.  The remaining sliced
+    labels are looped over ("outer" slices): outer value o covers slice ids
+    [o * 2^n_batch, (o + 1) * 2^n_batch) of ``Executor``."""
+
+    def __init__(self, handle, plan, n_batch, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.h = handle
+        self.plan = plan
+        self.n_batch = min(int(n_batch), len(plan.sliced))
+        self.batch_labels = list(plan.sliced[:self.n_batch])
+        self.outer_labels = list(plan.sliced[self.n_batch:])
+        self._bpos = {lab: i for i, lab in enumerate(self.batch_labels)}
+
+    @property
+    def n_outer(self):
+        return 1 << len(self.outer_labels)
+
+    def max_intermediate(self):
+        """log2 of the largest tensor of a pass (elements)."""
+        p = self.plan
+        L = len(p.label_sets)
+        B = set(self.batch_labels)
+        outer = set(self.outer_labels)
+        labs = [frozenset(ls) - outer for ls in p.label_sets]
+        best = max((len(x) for x in labs), default=0)
+        for a, b in p.path:
+            out = (labs[a] ^ labs[b]) | (labs[a] & labs[b] & B)
+            labs.append(out)
+            best = max(best, len(out))
+        return best
+
+    def _leaves_host(self, x, o):
+        """Host arrays of the leaves for bitstring x with the outer labels
+        fixed by o."""
+        p = self.plan
+        opos = {lab: i for i, lab in enumerate(self.outer_labels)}
+        out = []
+        for arr, labels in tn.circuit_network(p.circuit, x):
+            idx = tuple(((o >> opos[lab]) & 1) if lab in opos else slice(None) for lab in labels)
+            out.append(np.ascontiguousarray(arr[idx]))
+        return out
+
+    def _leaves(self, x, o, cache=None):
+        """Device leaves for bitstring x with the outer labels fixed by o."""
+        torch = self.torch
+        p = self.plan
+        opos = {lab: i for i, lab in enumerate(self.outer_labels)}
+        leaves = tn.circuit_network(p.circuit, x)
+        out = []
+        for i, (arr, labels) in enumerate(leaves):
+            idx = tuple(((o >> opos[lab]) & 1) if lab in opos else slice(None) for lab in labels)
+            key = (i, tuple(((o >> opos[lab]) & 1) for lab in labels if lab in opos))
+            if cache is not None and key in cache:
+                t = cache[key]
+            else:
+                t = torch.from_numpy(np.ascontiguousarray(arr[idx])).to(self.device)
+                if cache is not None and i < len(leaves) - p.circuit["n"]:
+                    cache[key] = t           # gate and |0> leaves do not depend on x
+            out.append((t, [lab for lab in labels if lab not in opos]))
+        return out
+
+    def run_pass(self, leaves):
+        """One pass over the tree on the given device leaves; returns the root
+        tensor and its labels (a subset of the batch labels)."""
+        import paper_2303_08989_amd as qce
+        p = self.plan
+        L = len(p.label_sets)
+        B = self._bpos
+        vals = {i: leaves[i] for i in range(L)}
+        for s, (a, b) in enumerate(p.path):
+            ta, la = vals.pop(a)
+            tb, lb = vals.pop(b)
+            shared = set(la) & set(lb)
+            bt = sorted((lab for lab in shared if lab in B), key=lambda lab: B[lab])
+            lc = bt + [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
+            vals[L + s] = (qce.contract(self.h, ta, list(la), tb, list(lb), lc), lc)
+        return vals[L + len(p.path) - 1] if p.path else vals[0]
+
+    def amplitude(self, x, outer_ids=None, acc=None, cache=None):
+        """Sum over the outer slices ``outer_ids`` (default: all) of the
+        batched passes, accumulated in FP64 on the device; returns the
+        float64[2] accumulator."""
+        import paper_2303_08989_amd as qce
+        torch = self.torch
+        if acc is None:
+            acc = torch.zeros(2, dtype=torch.float64, device=self.device)
+        if outer_ids is None:
+            outer_ids = range(self.n_outer)
+        for o in outer_ids:
+            root, _ = self.run_pass(self._leaves(x, o, cache))
+            qce.accumulate_n_f64(self.h, root.reshape(-1), acc)
+        return acc
+
+
+class GraphPass:
+    """One batched pass (``BatchedExecutor``, outer value ``outer``) captured
+    once in a HIP graph and replayed per bitstring.  Only the <x| leaves
+    change between bitstrings: they are overwritten in place (host-to-device
+    copies outside the graph) before each replay.
+
+    The graph owns a handle of its own, so its workspace (whose address the
+    captured kernels hold) is never reallocated by other calls; a warm-up
+    pass sizes it before capture.  No memset is captured: the accumulator is
+    cleared by a fill kernel inside the graph."""
+
+    def __init__(self, plan, n_batch, outer=0, device=0):
+        import torch
+        import paper_2303_08989_amd as qce
+        self.torch = torch
+        self.qce = qce
+        self.h = qce.Handle(device)
+        self.bx = BatchedExecutor(self.h, plan, n_batch)
+        self.outer = outer
+        self.n = plan.circuit["n"]
+        self.leaves = self.bx._leaves(0, outer)
+        self.acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+        root, _ = self.bx.run_pass(self.leaves)            # warm-up: workspace, allocator
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.acc.zero_()
+            root, _ = self.bx.run_pass(self.leaves)
+            qce.accumulate_n_f64(self.h, root.reshape(-1), self.acc)
+        self.root = root
+
+    def amplitude(self, x):
+        """Replay for bitstring x; returns the device float64[2] sum of the
+        pass's slice values (valid until the next replay)."""
+        host = self.bx._leaves_host(x, self.outer)
+        L = len(self.leaves)
+        for i in range(L - self.n, L):
+            self.leaves[i][0].copy_(self.torch.from_numpy(host[i]), non_blocking=False)
+        self.graph.replay()
+        return self.acc
+
+    def close(self):
+        self.graph = None
+        self.h.close()

@@ -1,0 +1,66 @@
+"""Host logic of the batched slice executor (batch labels, outer loop,
+label bookkeeping) driven by a complex128 einsum stand-in for the library's
+contraction, against the FP64 oracle amplitude.  No GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+
+def _einsum(A, la, B, lb, lc):
+    letters = {l: chr(97 + i) for i, l in enumerate(sorted(set(la) | set(lb)))}
+    expr = "".join(letters[l] for l in la) + "," + "".join(letters[l] for l in lb) + "->" + \
+        "".join(letters[l] for l in lc)
+    return torch.from_numpy(np.asarray(np.einsum(expr, A.numpy().astype(np.complex128),
+                                                 B.numpy().astype(np.complex128))))
+
+
+@pytest.fixture()
+def standin(monkeypatch):
+    import paper_2303_08989_amd as qce
+    monkeypatch.setattr(qce, "contract", lambda h, A, la, B, lb, lc, out=None: _einsum(A, la, B, lb, lc))
+
+    def acc_n(h, src, dst):
+        v = src.numpy().astype(np.complex128).sum()
+        dst[0] += v.real
+        dst[1] += v.imag
+    monkeypatch.setattr(qce, "accumulate_n_f64", acc_n)
+    return qce
+
+
+def _rounded(c):
+    out = dict(c)
+    out["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                    for g in c["gates"]]
+    return out
+
+
+@pytest.mark.parametrize("n_batch", [0, 2, 4, 99])
+def test_batched_pass_matches_oracle(standin, n_batch):
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan
+    c = synth.grid_circuit(3, 4, 6, seed=3, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=3, restarts=1, varied=3)
+    assert len(plan.sliced) >= 3
+    bx = BatchedExecutor(None, plan, n_batch, device="cpu")
+    xs = synth.random_bitstrings(12, 3, seed=4)
+    want = oracle.statevector_amplitudes(_rounded(c), xs)
+    for x, w in zip(xs, want):
+        acc = bx.amplitude(x).numpy()
+        assert abs(complex(acc[0], acc[1]) - w) < 1e-6 * max(abs(w), 1e-3)
+    assert bx.max_intermediate() >= plan.max_log2
+
+
+def test_outer_ids_partition_the_slices(standin):
+    # outer value o covers slice ids [o 2^b, (o+1) 2^b): partial sums add up
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan
+    c = synth.grid_circuit(3, 4, 6, seed=5, pattern="ABCD")
+    plan = CircuitPlan(c, max_log2=3, restarts=1, varied=3)
+    assert len(plan.sliced) >= 3
+    bx = BatchedExecutor(None, plan, 2, device="cpu")
+    x = 77
+    parts = [complex(*bx.amplitude(x, [o]).numpy()) for o in range(bx.n_outer)]
+    whole = complex(*bx.amplitude(x).numpy())
+    assert abs(sum(parts) - whole) < 1e-12

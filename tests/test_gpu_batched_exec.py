@@ -1,0 +1,102 @@
+"""GPU: batched slices (sliced labels kept as batch labels, one batched GEMM
+per contraction step), the FP64 sum of a pass's slice values, and the pass
+captured in a HIP graph and replayed per bitstring."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def qce():
+    import paper_2303_08989_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def h(qce):
+    hh = qce.Handle(0)
+    yield hh
+    hh.close()
+
+
+def _rounded(c):
+    out = dict(c)
+    out["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                    for g in c["gates"]]
+    return out
+
+
+def test_accumulate_n_f64(qce, h):
+    ints = np.arange(-500, 1500, dtype=np.float32)
+    src = torch.from_numpy((ints + 1j * (2 * ints)).astype(np.complex64)).to("cuda")
+    acc = torch.tensor([0.5, -1.0], dtype=torch.float64, device="cuda")
+    qce.accumulate_n_f64(h, src, acc)
+    got = acc.cpu().numpy()
+    assert got[0] == 0.5 + float(ints.sum()) and got[1] == -1.0 + 2 * float(ints.sum())
+    rng = np.random.default_rng(2)
+    v = (rng.standard_normal(1 << 20) + 1j * rng.standard_normal(1 << 20)).astype(np.complex64)
+    acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+    qce.accumulate_n_f64(h, torch.from_numpy(v).to("cuda"), acc)
+    ref = v.astype(np.complex128).sum()
+    assert abs(complex(*acc.cpu().numpy()) - ref) < 1e-9
+
+
+@pytest.mark.parametrize("n_batch", [2, 99])
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated"])
+def test_batched_equals_looped_and_oracle(qce, h, n_batch, mode):
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, Executor
+    c = synth.grid_circuit(3, 4, 8, seed=2, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=5, restarts=2, varied=3)
+    assert len(plan.sliced) >= 3
+    xs = synth.random_bitstrings(12, 4, seed=6)
+    if mode == "auto_emulated":
+        h.set_mode("auto")
+        h.set_size_policy(0, 0)
+    else:
+        h.set_mode(mode)
+    try:
+        bx = BatchedExecutor(h, plan, n_batch)
+        ex = Executor(h, plan)
+        got = np.array([complex(*bx.amplitude(x).cpu().numpy()) for x in xs])
+        loop = np.array([complex(*ex.amplitude(x).cpu().numpy()) for x in xs])
+    finally:
+        h.set_size_policy(2048, 512)
+        h.set_mode("auto")
+    want = oracle.statevector_amplitudes(_rounded(c), xs)
+    assert oracle.fidelity(got, want) >= 1 - 1e-6
+    assert np.max(np.abs(got - loop)) <= 1e-5 * np.max(np.abs(want))
+
+
+def test_reduced_config3_batched_auto(qce, h):
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan
+    c = synth.grid_circuit(4, 5, 12, seed=1, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=12, restarts=2, varied=4)
+    xs = synth.random_bitstrings(20, 2, seed=3)
+    bx = BatchedExecutor(h, plan, 8)
+    assert bx.n_outer <= 64 and bx.max_intermediate() <= 22
+    got = np.array([complex(*bx.amplitude(x).cpu().numpy()) for x in xs])
+    want = oracle.statevector_amplitudes(_rounded(c), xs)
+    assert oracle.fidelity(got, want) >= 1 - 1e-6
+
+
+def test_graph_replay_matches_eager(qce, h):
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, GraphPass
+    c = synth.grid_circuit(3, 4, 8, seed=7, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=5, restarts=2, varied=3)
+    gp = GraphPass(plan, n_batch=3, outer=1)
+    bx = BatchedExecutor(h, plan, 3)
+    try:
+        for x in synth.random_bitstrings(12, 4, seed=8):
+            eager = bx.amplitude(x, [1]).cpu().numpy()
+            torch.cuda.synchronize()
+            replay = gp.amplitude(x).cpu().numpy()
+            assert np.array_equal(replay, eager), x
+            # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        gp.close()
