@@ -172,6 +172,75 @@ def run_gradients(h, args, torch, qce, synth):
     }
 
 
+def run_batching(h, args, torch, qce, synth):
+    """1024 slices of the 53-qubit network (sliced until every per-slice
+    GEMM is small: max intermediate 2^18) three ways: the slice loop
+    (``Executor``: one contraction call per step and slice, memoized), one
+    batched pass (``BatchedExecutor``: the 10 sliced labels that vary keep
+    their index, so each step is one batched GEMM over 1024 slices with
+    per-entry modes), and that pass captured in a HIP graph and replayed."""
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, Executor, GraphPass
+    c = synth.grid_circuit(pattern="ABCDCDAB", depth=12, seed=1, **synth.GRID_53)
+    t0 = time.perf_counter()
+    plan = CircuitPlan(c, max_log2=18, restarts=4, varied=10)
+    t_plan = time.perf_counter() - t0
+    nb = 10
+    x = synth.random_bitstrings(53, 1, seed=5)[0]
+    h.set_mode("auto")
+    bx = BatchedExecutor(h, plan, nb)
+    ex = Executor(h, plan)
+    ids = range(1 << nb)
+    # looped slices
+    ex.amplitude(x, range(4))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a_loop = ex.amplitude(x, ids)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    # one batched pass
+    cache = {}
+    bx.amplitude(x, [0], cache=cache)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        a_b = bx.amplitude(x, [0], cache=cache)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    # graph replay
+    gp = GraphPass(plan, nb, outer=0)
+    gp.amplitude(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        a_g = gp.amplitude(x)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    v_loop = complex(*a_loop.cpu().numpy())
+    v_b = complex(*a_b.cpu().numpy())
+    v_g = complex(*a_g.cpu().numpy())
+    gp.close()
+    shapes = plan.gemm_shapes
+    n = len(ids)
+    return {
+        "workload": f"53-qubit network of the 53-qubit section sliced to max intermediate 2^{plan.max_log2} "
+                    f"({len(plan.sliced)} sliced labels); slice ids 0..{n - 1} ({nb} labels varied), "
+                    "AUTO with size policy",
+        "plan_seconds": round(t_plan, 1),
+        "per_slice_gemm_log2_dims_range": [min(min(s3) for s3 in shapes), max(max(s3) for s3 in shapes)],
+        "contractions_per_pass": len(plan.path),
+        "batched_max_intermediate_log2": bx.max_intermediate(),
+        "looped_seconds": round(t_loop, 4), "looped_slices_per_s": round(n / t_loop, 1),
+        "batched_seconds": round(t_batched, 5), "batched_slices_per_s": round(n / t_batched, 1),
+        "graph_seconds": round(t_graph, 5), "graph_slices_per_s": round(n / t_graph, 1),
+        "speedup_batched_vs_looped": round(t_loop / t_batched, 2),
+        "speedup_graph_vs_looped": round(t_loop / t_graph, 2),
+        "rel_diff_batched_vs_looped": abs(v_b - v_loop) / max(abs(v_loop), 1e-300),
+        "graph_equals_batched": v_g == v_b,
+        "partial_amplitude": [v_b.real, v_b.imag],
+    }
+
+
 def run_circuits(h, args, torch, qce, synth):
     """Config 1: 12-qubit 3x4 grid depth 8 (ABCD), 10 bitstrings, plain FP32.
     Config 3: 53-qubit 6x9-minus-corner grid depth 12 (ABCDCDAB), sliced so
@@ -261,6 +330,7 @@ def main():
     ap.add_argument("--no-circuits", action="store_true", help="skip the circuit-amplitude sections")
     ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-shape section")
     ap.add_argument("--no-gradients", action="store_true", help="skip the circuit-gradient section")
+    ap.add_argument("--no-batching", action="store_true", help="skip the batched-slices section")
     ap.add_argument("--c5-bitstrings", type=int, default=64, help="bitstrings of the gradient section")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
@@ -459,6 +529,7 @@ def main():
 
     irregular = None if args.no_irregular else run_irregular(h, torch, qce)
     gradients = None if args.no_gradients else run_gradients(h, args, torch, qce, synth)
+    batching = None if args.no_batching else run_batching(h, args, torch, qce, synth)
 
     # ---- circuit amplitudes (12-qubit FP32 path; 53-qubit sliced share) ------
     circuits = None
@@ -517,6 +588,7 @@ def main():
         "amplitudes": circuits,
         "irregular": irregular,
         "gradients": gradients,
+        "batching": batching,
         "cases": case_out,
     }
     print(json.dumps(out))
