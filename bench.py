@@ -331,12 +331,16 @@ def main():
     ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-shape section")
     ap.add_argument("--no-gradients", action="store_true", help="skip the circuit-gradient section")
     ap.add_argument("--no-batching", action="store_true", help="skip the batched-slices section")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="only the CGEMM step: skip the circuit, irregular, gradient and batching sections")
     ap.add_argument("--c5-bitstrings", type=int, default=64, help="bitstrings of the gradient section")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
     ap.add_argument("--c3-restarts", type=int, default=24)
     args = ap.parse_args()
+    if args.gemm_only:
+        args.no_circuits = args.no_irregular = args.no_gradients = args.no_batching = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs on a "
               "single MI355X and has no multi-GPU path.", file=sys.stderr)
