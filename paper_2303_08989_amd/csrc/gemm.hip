@@ -153,144 +153,30 @@ __device__ __attribute__((always_inline)) inline void fp16x2_block(const u32x4 *
     im_m = mfma16(x[2], y[0], im_m);
 }
 
-// one chunk of FP16X2 panels in LDS: one k16 step.  Fragments are read in
-// the order the 2x2 blocks use them, so the first block's MFMAs can start
-// while the remaining fragments are still in flight.
-__device__ __attribute__((always_inline)) inline void compute_fp16x2(const char *sx, const char *sy, int wu, int wv, int lane,
-                                      Acc<QCE_MODE_FP16X2> &acc) {
-    using G = PanelGeom<QCE_MODE_FP16X2>;
-    const int l32 = lane & 31, gr = lane >> 5;
-    u32x4 x[2][4], y[2][4], nx[2][2];
-    auto load_x = [&](int ub) {
-        const int row = wu * 64 + ub * 32 + l32;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) x[ub][p] = *reinterpret_cast<const u32x4 *>(sx + G::offset(p, row, gr));
-    };
-    auto load_y = [&](int vb) {
-        const int row = wv * 64 + vb * 32 + l32;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) y[vb][p] = *reinterpret_cast<const u32x4 *>(sy + G::offset(p, row, gr));
-    };
-    load_x(0);
-    load_y(0);
-    load_y(1);
-    load_x(1);
-    nx[0][0] = neg_halves(x[0][2]);
-    nx[0][1] = neg_halves(x[0][3]);
-    fp16x2_block(x[0], nx[0], y[0], acc.re_m[0][0], acc.im_m[0][0], acc.re_c[0][0], acc.im_c[0][0]);
-    fp16x2_block(x[0], nx[0], y[1], acc.re_m[0][1], acc.im_m[0][1], acc.re_c[0][1], acc.im_c[0][1]);
-    nx[1][0] = neg_halves(x[1][2]);
-    nx[1][1] = neg_halves(x[1][3]);
-    fp16x2_block(x[1], nx[1], y[0], acc.re_m[1][0], acc.im_m[1][0], acc.re_c[1][0], acc.im_c[1][0]);
-    fp16x2_block(x[1], nx[1], y[1], acc.re_m[1][1], acc.im_m[1][1], acc.re_c[1][1], acc.im_c[1][1]);
-}
-
-// one chunk of BF16X3 panels in LDS: 1 k16 step
-__device__ __attribute__((always_inline)) inline void compute_bf16x3(const char *sx, const char *sy, int wu, int wv, int lane,
-                                      Acc<QCE_MODE_BF16X3> &acc) {
-    using G = PanelGeom<QCE_MODE_BF16X3>;
-    const int l32 = lane & 31, gr = lane >> 5;
-    // planes: 0..2 = b0, b1, b2 of re; 3..5 = b0, b1, b2 of im
-    u32x4 x[2][6], y[2][6], nxi[2][3];
-#pragma unroll
-    for (int ub = 0; ub < 2; ++ub) {
-        const int row = wu * 64 + ub * 32 + l32;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) x[ub][p] = *reinterpret_cast<const u32x4 *>(sx + G::offset(p, row, gr));
-#pragma unroll
-        for (int p = 0; p < 3; ++p) nxi[ub][p] = neg_halves(x[ub][3 + p]);
-    }
-#pragma unroll
-    for (int vb = 0; vb < 2; ++vb) {
-        const int row = wv * 64 + vb * 32 + l32;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) y[vb][p] = *reinterpret_cast<const u32x4 *>(sy + G::offset(p, row, gr));
-    }
-#pragma unroll
-    for (int ub = 0; ub < 2; ++ub)
-#pragma unroll
-        for (int vb = 0; vb < 2; ++vb) {
-            // corrections, smallest first: (2,0) (1,1) (0,2) (1,0) (0,1)
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                const int i = t == 0 ? 2 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 1 : 0;
-                const int j = t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 2 : t == 3 ? 0 : 1;
-                acc.re_c[ub][vb] = mfmab(x[ub][i], y[vb][j], acc.re_c[ub][vb]);
-                acc.re_c[ub][vb] = mfmab(nxi[ub][i], y[vb][3 + j], acc.re_c[ub][vb]);
-                acc.im_c[ub][vb] = mfmab(x[ub][i], y[vb][3 + j], acc.im_c[ub][vb]);
-                acc.im_c[ub][vb] = mfmab(x[ub][3 + i], y[vb][j], acc.im_c[ub][vb]);
-            }
-            acc.re_m[ub][vb] = mfmab(x[ub][0], y[vb][0], acc.re_m[ub][vb]);
-            acc.re_m[ub][vb] = mfmab(nxi[ub][0], y[vb][3], acc.re_m[ub][vb]);
-            acc.im_m[ub][vb] = mfmab(x[ub][0], y[vb][3], acc.im_m[ub][vb]);
-            acc.im_m[ub][vb] = mfmab(x[ub][3], y[vb][0], acc.im_m[ub][vb]);
-        }
-}
-
-// one chunk of FP32 panels in LDS: 16 k-values.  Each lane reads four
-// consecutive k-values per row; MFMA step j takes value j, so lanes 0-31 and
-// 32-63 supply k = 8s + j and 8s + 4 + j (the same pairing for both
-// operands, so every k is summed once).
-__device__ __attribute__((always_inline)) inline void compute_fp32(const char *sx, const char *sy, int wu, int wv, int lane,
-                                    Acc<QCE_MODE_FP32> &acc) {
-    using G = PanelGeom<QCE_MODE_FP32>;
-    const int l32 = lane & 31, hi = lane >> 5;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const int gr = 2 * s + hi;
-        f32x4 xr[2], xi[2], yr[2], yi[2];
-#pragma unroll
-        for (int ub = 0; ub < 2; ++ub) {
-            const int row = wu * 64 + ub * 32 + l32;
-            xr[ub] = *reinterpret_cast<const f32x4 *>(sx + G::offset(0, row, gr));
-            xi[ub] = *reinterpret_cast<const f32x4 *>(sx + G::offset(1, row, gr));
-        }
-#pragma unroll
-        for (int vb = 0; vb < 2; ++vb) {
-            const int row = wv * 64 + vb * 32 + l32;
-            yr[vb] = *reinterpret_cast<const f32x4 *>(sy + G::offset(0, row, gr));
-            yi[vb] = *reinterpret_cast<const f32x4 *>(sy + G::offset(1, row, gr));
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int ub = 0; ub < 2; ++ub)
-#pragma unroll
-                for (int vb = 0; vb < 2; ++vb) {
-                    const float a_r = xr[ub][j], a_i = xi[ub][j];
-                    const float b_r = yr[vb][j], b_i = yi[vb][j];
-                    acc.re_m[ub][vb] = mfma32(a_r, b_r, acc.re_m[ub][vb]);
-                    acc.re_m[ub][vb] = mfma32(-a_i, b_i, acc.re_m[ub][vb]);
-                    acc.im_m[ub][vb] = mfma32(a_r, b_i, acc.im_m[ub][vb]);
-                    acc.im_m[ub][vb] = mfma32(a_i, b_r, acc.im_m[ub][vb]);
-                }
-    }
-}
-
-template <int MODE>
-__device__ __attribute__((always_inline)) inline void compute_chunk(const char *sx, const char *sy, int wu, int wv, int lane,
-                                     Acc<MODE> &acc) {
-    if constexpr (MODE == QCE_MODE_FP16X2) compute_fp16x2(sx, sy, wu, wv, lane, acc);
-    else if constexpr (MODE == QCE_MODE_BF16X3) compute_bf16x3(sx, sy, wu, wv, lane, acc);
-    else compute_fp32(sx, sy, wu, wv, lane, acc);
-}
-
 // ---------------------------------------------------------------------------
-// Software-pipelined main loop of the emulated modes.  A chunk's four 32x32
-// blocks (ub, vb) run in the order (0,0) (0,1) (1,0) (1,1); the fragments of
-// a block are read from LDS into registers freed by the block before, so the
-// reads overlap MFMAs: y1 during (0,0), x1 during (0,1), and the next
-// chunk's x0, y0 during (1,1) -- after the wait and barrier for that chunk,
-// which sit between (1,0) and (1,1).
+// Fragments of one chunk in registers (all rows of the wave's 64 x 64 tile,
+// 16 k-values) and the MFMAs of one chunk.  The k-loop keeps two such sets:
+// chunk i's MFMAs run from one while chunk i+1's fragments are read into the
+// other.
 // ---------------------------------------------------------------------------
 template <int MODE> struct Frag;
 template <> struct Frag<QCE_MODE_FP16X2> {
     static constexpr int kP = 4;  // planes: hi(re), lo(re), hi(im), lo(im)
+    static constexpr int kReads = 16, kMfma = 48;
     u32x4 x[2][4], y[2][4];
 };
 template <> struct Frag<QCE_MODE_BF16X3> {
     static constexpr int kP = 6;  // planes: b0, b1, b2 of re; b0, b1, b2 of im
+    static constexpr int kReads = 24, kMfma = 96;
     u32x4 x[2][6], y[2][6];
+};
+// FP32: per k8 half s and 32-row block, four consecutive k-values of re and
+// of im; MFMA step j takes value j, so lanes 0-31 and 32-63 supply
+// k = 8s + j and 8s + 4 + j (the same pairing for both operands, so every k
+// is summed once).
+template <> struct Frag<QCE_MODE_FP32> {
+    static constexpr int kReads = 16, kMfma = 128;
+    f32x4 xr[2][2], xi[2][2], yr[2][2], yi[2][2];  // [s][block]
 };
 
 template <int MODE>
@@ -300,12 +186,37 @@ __device__ __attribute__((always_inline)) inline void load_part(u32x4 *dst, cons
     for (int p = 0; p < Frag<MODE>::kP; ++p) dst[p] = *reinterpret_cast<const u32x4 *>(s + G::offset(p, row, gr));
 }
 
+// Every fragment of one chunk: x rows from the B panel (sx), y rows from
+// the A panel (sy); r0 = wave's first x row + lane%32, q0 likewise for y.
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void load_chunk(Frag<MODE> &f, const char *sx, const char *sy,
+                                                                 int rx0, int ry0, int lane) {
+    const int hi = lane >> 5;
+    if constexpr (MODE == QCE_MODE_FP32) {
+        using G = PanelGeom<QCE_MODE_FP32>;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                f.xr[s][b] = *reinterpret_cast<const f32x4 *>(sx + G::offset(0, rx0 + 32 * b, 2 * s + hi));
+                f.xi[s][b] = *reinterpret_cast<const f32x4 *>(sx + G::offset(1, rx0 + 32 * b, 2 * s + hi));
+                f.yr[s][b] = *reinterpret_cast<const f32x4 *>(sy + G::offset(0, ry0 + 32 * b, 2 * s + hi));
+                f.yi[s][b] = *reinterpret_cast<const f32x4 *>(sy + G::offset(1, ry0 + 32 * b, 2 * s + hi));
+            }
+    } else {
+        load_part<MODE>(f.x[0], sx, rx0, hi);
+        load_part<MODE>(f.y[0], sy, ry0, hi);
+        load_part<MODE>(f.y[1], sy, ry0 + 32, hi);
+        load_part<MODE>(f.x[1], sx, rx0 + 32, hi);
+    }
+}
+
 template <int MODE>
 __device__ __attribute__((always_inline)) inline void mma_block(const Frag<MODE> &f, int ub, int vb, Acc<MODE> &acc) {
     if constexpr (MODE == QCE_MODE_FP16X2) {
         const u32x4 nx[2] = {neg_halves(f.x[ub][2]), neg_halves(f.x[ub][3])};
         fp16x2_block(f.x[ub], nx, f.y[vb], acc.re_m[ub][vb], acc.im_m[ub][vb], acc.re_c[ub][vb], acc.im_c[ub][vb]);
-    } else {
+    } else if constexpr (MODE == QCE_MODE_BF16X3) {
         const u32x4 *x = f.x[ub], *y = f.y[vb];
         const u32x4 nx[3] = {neg_halves(x[3]), neg_halves(x[4]), neg_halves(x[5])};
         floatx16 &re_c = acc.re_c[ub][vb], &im_c = acc.im_c[ub][vb];
@@ -324,7 +235,52 @@ __device__ __attribute__((always_inline)) inline void mma_block(const Frag<MODE>
         re_m = mfmab(nx[0], y[3], re_m);
         im_m = mfmab(x[0], y[3], im_m);
         im_m = mfmab(x[3], y[0], im_m);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float a_r = f.xr[s][ub][j], a_i = f.xi[s][ub][j];
+                const float b_r = f.yr[s][vb][j], b_i = f.yi[s][vb][j];
+                acc.re_m[ub][vb] = mfma32(a_r, b_r, acc.re_m[ub][vb]);
+                acc.re_m[ub][vb] = mfma32(-a_i, b_i, acc.re_m[ub][vb]);
+                acc.im_m[ub][vb] = mfma32(a_r, b_i, acc.im_m[ub][vb]);
+                acc.im_m[ub][vb] = mfma32(a_i, b_r, acc.im_m[ub][vb]);
+            }
     }
+}
+
+__device__ __attribute__((always_inline)) inline void opaque(f32x4 &v) { asm volatile("" : "+v"(v)); }
+
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void opaque_frag(Frag<MODE> &f) {
+    if constexpr (MODE == QCE_MODE_FP32) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                opaque(f.xr[s][b]);
+                opaque(f.xi[s][b]);
+                opaque(f.yr[s][b]);
+                opaque(f.yi[s][b]);
+            }
+    } else {
+#pragma unroll
+        for (int p = 0; p < Frag<MODE>::kP; ++p) {
+            opaque(f.x[0][p]);
+            opaque(f.x[1][p]);
+            opaque(f.y[0][p]);
+            opaque(f.y[1][p]);
+        }
+    }
+}
+
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void mma_chunk(const Frag<MODE> &f, Acc<MODE> &acc) {
+    mma_block<MODE>(f, 0, 0, acc);
+    mma_block<MODE>(f, 0, 1, acc);
+    mma_block<MODE>(f, 1, 0, acc);
+    mma_block<MODE>(f, 1, 1, acc);
 }
 
 template <int MODE> constexpr int smem_bytes() {
@@ -386,47 +342,15 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
     }
 
     // Chunk c of both operands goes straight from global memory into LDS
-    // stage c % kNS (global_load_lds: lane l of a wave writes 16 bytes at the
-    // wave's LDS address + 16 l), kNS - 1 chunks ahead of the MFMAs.
-    auto issue = [&](int c) {
-        const char *gx = px + (int64_t)c * kCB;
-        const char *gy = py + (int64_t)c * kCB;
-        char *lx = smem[c % kNS][0];
-        char *ly = smem[c % kNS][1];
-#pragma unroll
-        for (int i = 0; i < kL1; ++i) {
-            const int e = (tid + i * kThreads) * 16;
-            const int we = (w * 64 + i * kThreads) * 16;
-            __builtin_amdgcn_global_load_lds(gx + e, LDS_PTR(lx + we), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds(gy + e, LDS_PTR(ly + we), 16, 0, 0);
-        }
-    };
-    // wait until this thread's copies of a chunk are done: at most the
-    // copies of the `after` chunks issued later are still outstanding
-    auto wait_chunk = [&](int after) {
-        if (after >= 2) wait_vmcnt<2 * kL>();
-        else if (after == 1) wait_vmcnt<kL>();
-        else wait_vmcnt<0>();
-    };
-    if constexpr (MODE == QCE_MODE_FP32) {
-#pragma unroll
-        for (int c = 0; c < kNS - 1; ++c)
-            if (c < nk) issue(c);
-        for (int it = 0; it < nk; ++it) {
-            // the barrier makes every thread's copies of chunk `it` visible
-            // and retires the reads of the stage the next issue overwrites
-            wait_chunk(min(kNS - 2, nk - 1 - it));
-            asm volatile("s_barrier" ::: "memory");
-            if (it + kNS - 1 < nk) issue(it + kNS - 1);
-            compute_chunk<MODE>(smem[it % kNS][0], smem[it % kNS][1], wu, wv, lane, acc);
-        }
-    } else if (nk > 0) {
-        // The k-steps run in pairs (two register sets, no dynamic
-        // indexing); an odd count gets one chunk of zeros, whose products
-        // add exact zeros.  Every k-step issues one chunk, and chunks past
-        // the end come from the zero chunk, so the number of copies
-        // outstanding after a chunk is a constant and the loop body has no
-        // branches to split the schedule.
+    // (global_load_lds: lane l of a wave writes 16 bytes at the wave's LDS
+    // address + 16 l), kNS - 1 chunks ahead of the MFMAs.
+    //
+    // The k-steps run in pairs (two register sets, no dynamic indexing); an
+    // odd count gets one chunk of zeros, whose products add exact zeros.
+    // Every k-step issues one chunk, and chunks past the end come from the
+    // zero chunk, so the number of copies outstanding after a chunk is a
+    // constant and the loop body has no branches to split the schedule.
+    if (nk > 0) {
         const int nk2 = nk + (nk & 1);
         const char *zero = reinterpret_cast<const char *>(g_zero_chunk);
         asm volatile("" : "+s"(zero));   // computed once, kept in scalar registers
@@ -443,15 +367,8 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
                 __builtin_amdgcn_global_load_lds(gy + e, LDS_PTR(ly + we), 16, 0, 0);
             }
         };
-        const int l32 = lane & 31, gr = lane >> 5;
-        const int rx0 = wu * 64 + l32, rx1 = rx0 + 32, ry0 = wv * 64 + l32, ry1 = ry0 + 32;
-        // all fragments of one chunk (x: rows of the B panel, y: of A)
-        auto load_chunk = [&](Frag<MODE> &f, int stage) {
-            load_part<MODE>(f.x[0], smem[stage][0], rx0, gr);
-            load_part<MODE>(f.y[0], smem[stage][1], ry0, gr);
-            load_part<MODE>(f.y[1], smem[stage][1], ry1, gr);
-            load_part<MODE>(f.x[1], smem[stage][0], rx1, gr);
-        };
+        const int l32 = lane & 31;
+        const int rx0 = wu * 64 + l32, ry0 = wv * 64 + l32;
         // One k-step: chunk `it` is in registers (fc).  Wait for chunk it+1
         // (this thread's copies: kNS - 2 later chunks may be outstanding) and
         // for this wave's reads of chunk `it`; after the barrier every wave
@@ -462,13 +379,11 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
             wait_barrier<(kNS - 2) * kL>();
             // (reads before copies in program order: the compiler cannot
             // tell that they touch different stages and keeps their order)
-            load_chunk(fn, (it + 1) % kNS);
+            const int ns = (it + 1) % kNS;
+            load_chunk<MODE>(fn, smem[ns][0], smem[ns][1], rx0, ry0, lane);
             issue_to(it + kNS, it % kNS);
-            mma_block<MODE>(fc, 0, 0, acc);
-            mma_block<MODE>(fc, 0, 1, acc);
-            mma_block<MODE>(fc, 1, 0, acc);
-            mma_block<MODE>(fc, 1, 1, acc);
-            constexpr int kReads = 4 * Frag<MODE>::kP, kMfma = MODE == QCE_MODE_FP16X2 ? 48 : 96;
+            mma_chunk<MODE>(fc, acc);
+            constexpr int kReads = Frag<MODE>::kReads, kMfma = Frag<MODE>::kMfma;
             constexpr int kRp = kReads / 8;   // LDS reads per MFMA over the first 8 MFMAs
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -486,16 +401,10 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
 #pragma unroll
         for (int c = 0; c < kNS; ++c) issue_to(c, c);
         wait_barrier<(kNS - 1) * kL>();  // chunk 0
-        load_chunk(f0, 0);
+        load_chunk<MODE>(f0, smem[0][0], smem[0][1], rx0, ry0, lane);
         // keeps the optimizer from merging these reads with the loop's
         // reads into f0 as one read at the top of the loop
-#pragma unroll
-        for (int p = 0; p < Frag<MODE>::kP; ++p) {
-            opaque(f0.x[0][p]);
-            opaque(f0.x[1][p]);
-            opaque(f0.y[0][p]);
-            opaque(f0.y[1][p]);
-        }
+        opaque_frag(f0);
         for (int it = 0; it < nk2; it += 2) {
             step(it, f0, f1);
             step(it + 1, f1, f0);   // the last one reads a chunk past the end (unused)
