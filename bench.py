@@ -241,6 +241,79 @@ def run_batching(h, args, torch, qce, synth):
     }
 
 
+def run_random_tn(h, args, torch, qce, synth):
+    """The paper's exploratory random network (Sec. 5.2): 10 nodes with 2-4
+    legs of dimension 64 (reduced from 128), element types 1-3, contracted
+    along the greedy path in each computing mode (size policy off: the rule
+    on every GEMM).  Intermediates are rescaled by powers of two (from the
+    FP32 chain, exact) to the type's element scale.  Reports GEMM-chain time
+    per mode, the modes AUTO-t chose, and the relative difference of the
+    final value from the plain FP32 chain."""
+    import math
+    from paper_2303_08989_amd import tn
+    dim = 64
+    type_rms = {1: 1e-2, 2: 1e-8, 3: 1e-8}
+    modes = [("fp32", None), ("fp16x2", None), ("fp16x2_scaled", None), ("bf16x3", None),
+             ("auto", 0.0), ("auto", 0.1), ("auto", 0.5)]
+    labels = synth.random_closed_network(7)
+    path = tn.greedy_path(labels)
+    L = len(labels)
+    out = {"workload": f"10-node closed network, legs 2-4 of dimension {dim}, {len(path)} contractions",
+           "types": {}}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        for tn_type in synth.TN_TYPES:
+            rng = np.random.default_rng(100 + tn_type)
+            leaves = [torch.from_numpy(synth.random_tn_tensor((dim,) * len(l), tn_type, rng)).to("cuda")
+                      for l in labels]
+            scales = None
+            res = {}
+            for mode, t in modes:
+                h.set_mode(mode)
+                h.set_tolerance(0.1 if t is None else t, 0.0)
+                h.set_size_policy(0, 0)
+                chosen = []
+
+                def chain(record):
+                    vals = {i: (leaves[i], list(labels[i])) for i in range(L)}
+                    sc = []
+                    for s_, (a, b) in enumerate(path):
+                        ta, la = vals.pop(a)
+                        tb, lb = vals.pop(b)
+                        sh = set(la) & set(lb)
+                        lc = [x for x in lb if x not in sh] + [x for x in la if x not in sh]
+                        c = qce.contract(h, ta, la, tb, lb, lc)
+                        if record:
+                            chosen.append(h.last_decision()["mode_name"])
+                        if scales is None:
+                            rms = float(torch.sqrt(torch.mean(torch.abs(c.to(torch.complex128)) ** 2)))
+                            sc.append(2.0 ** round(math.log2(type_rms[tn_type] / rms)) if rms > 0 else 1.0)
+                        f = sc[s_] if scales is None else scales[s_]
+                        vals[L + s_] = (c * f if s_ < len(path) - 1 else c, lc)
+                    (v, _), = vals.values()
+                    return complex(v.reshape(-1)[0].item()), sc
+                val, sc = chain(True)
+                if scales is None:
+                    scales = sc
+                torch.cuda.synchronize()
+                ev0.record()
+                chain(False)
+                ev1.record()
+                torch.cuda.synchronize()
+                key = mode if t is None else f"auto-{t}"
+                res[key] = {"ms": round(ev0.elapsed_time(ev1), 3), "value": val,
+                            "modes": {m_: chosen.count(m_) for m_ in sorted(set(chosen))}}
+            ref = res["fp32"]["value"]
+            for r in res.values():
+                r["rel_diff_vs_fp32"] = abs(r.pop("value") - ref) / max(abs(ref), 1e-300)
+            out["types"][f"type{tn_type}"] = res
+    finally:
+        h.set_tolerance(0.1, 0.0)
+        h.set_mode("auto")
+        h.set_size_policy(2048, 512)
+    return out
+
+
 def run_circuits(h, args, torch, qce, synth):
     """Config 1: 12-qubit 3x4 grid depth 8 (ABCD), 10 bitstrings, plain FP32.
     Config 3: 53-qubit 6x9-minus-corner grid depth 12 (ABCDCDAB), sliced so
@@ -331,6 +404,7 @@ def main():
     ap.add_argument("--no-irregular", action="store_true", help="skip the irregular-shape section")
     ap.add_argument("--no-gradients", action="store_true", help="skip the circuit-gradient section")
     ap.add_argument("--no-batching", action="store_true", help="skip the batched-slices section")
+    ap.add_argument("--no-random-tn", action="store_true", help="skip the random-network section")
     ap.add_argument("--gemm-only", action="store_true",
                     help="only the CGEMM step: skip the circuit, irregular, gradient and batching sections")
     ap.add_argument("--c5-bitstrings", type=int, default=64, help="bitstrings of the gradient section")
@@ -341,6 +415,7 @@ def main():
     args = ap.parse_args()
     if args.gemm_only:
         args.no_circuits = args.no_irregular = args.no_gradients = args.no_batching = True
+        args.no_random_tn = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs on a "
               "single MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -534,6 +609,7 @@ def main():
     irregular = None if args.no_irregular else run_irregular(h, torch, qce)
     gradients = None if args.no_gradients else run_gradients(h, args, torch, qce, synth)
     batching = None if args.no_batching else run_batching(h, args, torch, qce, synth)
+    random_tn = None if args.no_random_tn else run_random_tn(h, args, torch, qce, synth)
 
     # ---- circuit amplitudes (12-qubit FP32 path; 53-qubit sliced share) ------
     circuits = None
@@ -593,6 +669,7 @@ def main():
         "irregular": irregular,
         "gradients": gradients,
         "batching": batching,
+        "random_tn": random_tn,
         "cases": case_out,
     }
     print(json.dumps(out))

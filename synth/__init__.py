@@ -12,4 +12,4 @@ from .circuits import (  # noqa: F401
     grid_circuit, ghz_circuit, identity_circuit, product_circuit,
     random_bitstrings, gate_matrix, GRID_53, with_thetas, coupler_thetas,
 )
-from .tn_random import random_network  # noqa: F401
+from .tn_random import random_network, random_closed_network, random_tn_tensor, TN_TYPES  # noqa: F401

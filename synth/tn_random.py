@@ -39,3 +39,55 @@ def random_network(seed, n_contracted=2, n_free_a=2, n_free_b=2, max_extent=4,
 
     return {"A": tensor(la), "la": la, "B": tensor(lb), "lb": lb, "lc": lc,
             "extents": ext}
+
+
+def random_closed_network(seed, n_nodes=10, dmin=2, dmax=4):
+    """Label sets of a connected random network without open legs: node
+    degrees drawn in [dmin, dmax] (the paper's exploratory network: 10 nodes
+    with 2 to 4 legs, Sec. 5.2), legs paired at random (no self-loops),
+    redrawn until connected.  Returns a list of label tuples, one per node;
+    label e joins exactly two nodes."""
+    rng = np.random.default_rng(seed)
+    while True:
+        deg = rng.integers(dmin, dmax + 1, n_nodes)
+        if deg.sum() % 2:
+            continue
+        stubs = np.repeat(np.arange(n_nodes), deg)
+        rng.shuffle(stubs)
+        edges = list(zip(stubs[0::2].tolist(), stubs[1::2].tolist()))
+        if any(a == b for a, b in edges):
+            continue
+        parent = list(range(n_nodes))
+
+        def find(i):
+            while parent[i] != i:
+                i = parent[i]
+            return i
+        for a, b in edges:
+            parent[find(a)] = find(b)
+        if len({find(i) for i in range(n_nodes)}) != 1:
+            continue
+        labels = [[] for _ in range(n_nodes)]
+        for e, (a, b) in enumerate(edges):
+            labels[a].append(e)
+            labels[b].append(e)
+        return [tuple(ls) for ls in labels]
+
+
+TN_TYPES = (1, 2, 3)
+
+
+def random_tn_tensor(shape, tn_type, rng):
+    """Elements of the paper's random-network types (Sec. 5.2), complex64:
+    type 1: each component N(0, 1e-4); type 2: type 1 scaled by 1e-6;
+    type 3: type 2 with 10 to 20 randomly placed elements set to 1."""
+    n = int(np.prod(shape)) if shape else 1
+    t = np.empty(n, dtype=np.complex64)
+    t.real = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    t.imag = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    if tn_type >= 2:
+        t = (t.astype(np.complex128) * 1e-6).astype(np.complex64)
+    if tn_type == 3:
+        cnt = int(rng.integers(10, 21))
+        t[rng.choice(n, size=min(cnt, n), replace=False)] = 1.0
+    return t.reshape(shape)
