@@ -196,6 +196,16 @@ bool parse_i64(const char *s, int64_t *out) {
 }
 
 // Make sure the handle workspace holds `bytes`.
+// The decision records of a batched call live in the workspace: once it is
+// freed or replaced they are gone.
+void forget_batch_decisions(qce_handle *h) {
+    if (h->dec_base != h->st) {
+        h->dec_base = h->st;
+        h->dec_count = 1;
+        h->have_decision = false;
+    }
+}
+
 qce_status ensure_ws(qce_handle *h, size_t bytes) {
     if (bytes <= h->ws_bytes) return QCE_SUCCESS;
     if (!h->ws_owned)
@@ -205,6 +215,7 @@ qce_status ensure_ws(qce_handle *h, size_t bytes) {
         QCE_HIP(h, hipFree(h->ws));
         h->ws = nullptr;
         h->ws_bytes = 0;
+        forget_batch_decisions(h);
     }
     size_t want = bytes + bytes / 8;
     want = (want + 4095) & ~(size_t)4095;
@@ -612,6 +623,7 @@ qce_status qce_set_workspace(qce_handle *h, void *ptr, size_t bytes) {
     h->ws = ptr;
     h->ws_bytes = bytes;
     h->ws_owned = ptr == nullptr;
+    forget_batch_decisions(h);
     return QCE_SUCCESS;
 }
 
