@@ -178,7 +178,8 @@ def run_batching(h, args, torch, qce, synth):
     (``Executor``: one contraction call per step and slice, memoized), one
     batched pass (``BatchedExecutor``: the 10 sliced labels that vary keep
     their index, so each step is one batched GEMM over 1024 slices with
-    per-entry modes), and that pass captured in a HIP graph and replayed."""
+    per-entry modes; each tree level's small contractions grouped into one
+    launch), and that pass captured in a HIP graph and replayed."""
     from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, Executor, GraphPass
     c = synth.grid_circuit(pattern="ABCDCDAB", depth=12, seed=1, **synth.GRID_53)
     t0 = time.perf_counter()
@@ -197,11 +198,19 @@ def run_batching(h, args, torch, qce, synth):
     a_loop = ex.amplitude(x, ids)
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
-    # one batched pass
+    # one batched pass: contraction by contraction, then with each tree
+    # level's small contractions in one grouped launch
     cache = {}
+    reps = 5
+    bx.amplitude(x, [0], cache=cache, grouped=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        a_u = bx.amplitude(x, [0], cache=cache, grouped=False)
+    torch.cuda.synchronize()
+    t_ungrouped = (time.perf_counter() - t0) / reps
     bx.amplitude(x, [0], cache=cache)
     torch.cuda.synchronize()
-    reps = 5
     t0 = time.perf_counter()
     for _ in range(reps):
         a_b = bx.amplitude(x, [0], cache=cache)
@@ -231,11 +240,15 @@ def run_batching(h, args, torch, qce, synth):
         "contractions_per_pass": len(plan.path),
         "batched_max_intermediate_log2": bx.max_intermediate(),
         "looped_seconds": round(t_loop, 4), "looped_slices_per_s": round(n / t_loop, 1),
+        "batched_ungrouped_seconds": round(t_ungrouped, 5),
+        "batched_ungrouped_slices_per_s": round(n / t_ungrouped, 1),
+        "tree_levels": len(bx._levels()),
         "batched_seconds": round(t_batched, 5), "batched_slices_per_s": round(n / t_batched, 1),
         "graph_seconds": round(t_graph, 5), "graph_slices_per_s": round(n / t_graph, 1),
         "speedup_batched_vs_looped": round(t_loop / t_batched, 2),
         "speedup_graph_vs_looped": round(t_loop / t_graph, 2),
         "rel_diff_batched_vs_looped": abs(v_b - v_loop) / max(abs(v_loop), 1e-300),
+        "rel_diff_grouped_vs_ungrouped": abs(v_b - complex(*a_u.cpu().numpy())) / max(abs(v_loop), 1e-300),
         "graph_equals_batched": v_g == v_b,
         "partial_amplitude": [v_b.real, v_b.imag],
     }

@@ -278,6 +278,38 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
                         const qce_tensor *c, void *C, const int32_t *lc);
 
 /*
+ * Grouped small contractions.  Between qce_group_begin and qce_group_end,
+ * every qce_contract call whose GEMM the library would run with the
+ * irregular-shape kernel (min(m, n) < 32 or k < 16 per batch entry) and that
+ * is small (k <= 1024, at most 2^22 output elements, at most 2^24 products)
+ * is recorded instead of launched; qce_group_end runs all recorded ones in
+ * one launch (one thread per output element reading the operands through
+ * their strides: no transposes; FP32 fused multiply-add, k in a fixed
+ * order).  Other contractions in the group run at once as usual.  The
+ * contractions of one group must be independent (none reads another's
+ * output), the operands of a recorded contraction must stay allocated and
+ * unchanged until qce_group_end has been enqueued (it reads them then), and
+ * a recorded output holds its value only after that launch.  The batched counterpart, for launch-bound streams of
+ * tiny contractions, of the grouped launch a sliced network needs
+ * (Sec. 5.3 slices, irregular shapes of Sec. 5.1.2).
+ *
+ * Descriptors go to a device area owned by the handle through a pinned
+ * host mirror; both are reused only after the stream has drained them.
+ * Under stream capture the area must already be large enough (run the work
+ * once, then qce_group_reset, then capture): otherwise ALLOC.
+ * INVALID_VALUE: begin with a group open, end or reset without / with one.
+ */
+qce_status qce_group_begin(qce_handle *h);
+qce_status qce_group_end(qce_handle *h);
+
+/*
+ * Synchronises the stream, makes the descriptor area at least reserve_bytes
+ * large, and reuses it from its start (before a stream capture: capture the
+ * groups into a fresh area).  ALLOC if the area cannot be allocated.
+ */
+qce_status qce_group_reset(qce_handle *h, size_t reserve_bytes);
+
+/*
  * Axis permutation of a dense row-major complex64 tensor (the "T" of TTGT,
  * Sec. 1): Y has axes (perm[0], ..., perm[rank-1]) of X, i.e. output axis d
  * is input axis perm[d].  X, Y: device, not overlapping.  x: host shape of X.

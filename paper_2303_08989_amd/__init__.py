@@ -217,7 +217,41 @@ def contract(h, A, la, B, lb, lc, out=None):
     _check(hh, h.lib.qce_contract(hh, ctypes.byref(ta), _ptr(A), _labels(la),
                                   ctypes.byref(tb), _ptr(B), _labels(lb),
                                   ctypes.byref(tc), _ptr(out), _labels(lc)))
+    if getattr(h, "_group_refs", None) is not None:
+        h._group_refs.append((A, B))
     return out
+
+
+class group:
+    """``with group(h): ...`` records the small contractions of the block and
+    runs them in one launch at its end (C-ABI ``qce_group_begin`` /
+    ``qce_group_end``).  The block's contractions must be independent."""
+
+    def __init__(self, h):
+        self.h = h
+
+    def __enter__(self):
+        hh = self.h._bind_stream()
+        _check(hh, self.h.lib.qce_group_begin(hh))
+        self.h._group_refs = []      # operands a recorded contraction reads at the group's end
+        return self
+
+    def __exit__(self, *exc):
+        hh = self.h._bind_stream()
+        try:
+            _check(hh, self.h.lib.qce_group_end(hh))
+        finally:
+            # the group's launch is enqueued: later work on the stream runs
+            # after it, so the operands' memory may be reused from here on
+            self.h._group_refs = None
+        return False
+
+
+def group_reset(h, reserve_bytes=0):
+    """Drain the stream and reuse the group descriptor area from its start,
+    at least ``reserve_bytes`` large (C-ABI ``qce_group_reset``)."""
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_group_reset(hh, int(reserve_bytes)))
 
 
 def permute(h, X, perm, out=None):

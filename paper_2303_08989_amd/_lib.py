@@ -24,7 +24,7 @@ EXPORTS = (
     "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_set_workspace",
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
     "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_get_batch_decision",
-    "qce_contract", "qce_permute", "qce_accumulate_f64", "qce_accumulate_n_f64", "qce_fidelity_f64",
+    "qce_contract", "qce_group_begin", "qce_group_end", "qce_group_reset", "qce_permute", "qce_accumulate_f64", "qce_accumulate_n_f64", "qce_fidelity_f64",
     "qce_expstats", "qce_split", "qce_status_string", "qce_last_error",
     "qce_set_timing", "qce_set_timing_tag", "qce_reset_timing", "qce_get_timing",
 )
@@ -94,6 +94,9 @@ def load():
                                            vp, i64, i64, c32p, vp, i64, i64, i64]),
         "qce_get_batch_decision": (st, [vp, i64, ctypes.POINTER(QceDecision)]),
         "qce_contract": (st, [vp, tp, vp, i32p, tp, vp, i32p, tp, vp, i32p]),
+        "qce_group_begin": (st, [vp]),
+        "qce_group_end": (st, [vp]),
+        "qce_group_reset": (st, [vp, ctypes.c_size_t]),
         "qce_permute": (st, [vp, tp, vp, i32p, vp]),
         "qce_accumulate_f64": (st, [vp, vp, vp]),
         "qce_accumulate_n_f64": (st, [vp, vp, i64, vp]),

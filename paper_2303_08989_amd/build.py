@@ -28,7 +28,8 @@ COMMON_FLAGS = [
     "-Wall", "-Wno-unused-result",
 ]
 
-SOURCES = ["stats.hip", "split.hip", "gemm.hip", "direct.hip", "permute.hip", "reduce.hip", "api.cpp"]
+SOURCES = ["stats.hip", "split.hip", "gemm.hip", "direct.hip", "permute.hip", "reduce.hip", "group.hip",
+           "api.cpp"]
 
 
 def _compile(src, verbose):

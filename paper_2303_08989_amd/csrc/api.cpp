@@ -49,6 +49,13 @@ struct qce_handle {
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    // grouped small contractions (qce_group_begin / qce_group_end)
+    bool grouping = false;
+    std::vector<qce::SmallItem> pending;
+    char *grp_dev = nullptr;   // descriptor arena on the device
+    char *grp_host = nullptr;  // its pinned host mirror (source of the copies)
+    size_t grp_cap = 0, grp_used = 0;
+    std::vector<std::pair<char *, char *>> grp_old;  // outgrown arenas, freed at destroy
 };
 
 namespace {
@@ -487,6 +494,62 @@ qce_status run_permute(qce_handle *h, int rank, const int64_t *ext, const int32_
     return QCE_SUCCESS;
 }
 
+// Grouped small contractions: the descriptor of C[lc] = sum A[la] B[lb]
+// when the contraction is an irregular shape small enough for one thread per
+// output element (false otherwise, or when its dimensions do not fit).
+constexpr int64_t kSmallMaxSum = 1024, kSmallMaxOut = int64_t(1) << 22, kSmallMaxWork = int64_t(1) << 24;
+
+template <class ExtOf>
+bool small_item(const qce_tensor *a, const int32_t *la, const qce_tensor *b, const int32_t *lb,
+                const qce_tensor *c, const int32_t *lc, const std::vector<int32_t> &K, ExtOf ext_of,
+                int64_t m, int64_t n, int64_t k, int64_t nc, SmallItem &it) {
+    if (!irregular_shape(m, n, k) || k > kSmallMaxSum || nc > kSmallMaxOut || nc * k > kSmallMaxWork)
+        return false;
+    auto stride_in = [](const qce_tensor *t, const int32_t *l, int32_t lab) -> int64_t {
+        int64_t s = 1;
+        for (int i = t->rank - 1; i >= 0; --i) {
+            if (l[i] == lab) return s;
+            s *= t->extents[i];
+        }
+        return 0;  // label not in the tensor
+    };
+    struct Dim {
+        int64_t e, sa, sb;
+    };
+    // outer -> inner, merging a dimension into the one outside it when both
+    // operands step through them contiguously
+    auto push = [](std::vector<Dim> &v, Dim d) {
+        if (d.e == 1) return;
+        if (!v.empty() && v.back().sa == d.sa * d.e && v.back().sb == d.sb * d.e) {
+            v.back().e *= d.e;
+            v.back().sa = d.sa;
+            v.back().sb = d.sb;
+        } else {
+            v.push_back(d);
+        }
+    };
+    std::vector<Dim> out, sum;
+    for (int i = 0; i < c->rank; ++i) push(out, Dim{c->extents[i], stride_in(a, la, lc[i]), stride_in(b, lb, lc[i])});
+    for (int32_t lab : K) push(sum, Dim{ext_of(lab), stride_in(a, la, lab), stride_in(b, lb, lab)});
+    if ((int)out.size() > kSmallOut || (int)sum.size() > kSmallSum) return false;
+    it.n_out = nc;
+    it.n_sum = k;
+    it.nd_out = (int)out.size();
+    it.nd_sum = (int)sum.size();
+    for (int d = 0; d < it.nd_out; ++d) {
+        it.out_ext[d] = out[d].e;
+        it.out_sa[d] = out[d].sa;
+        it.out_sb[d] = out[d].sb;
+    }
+    for (int t = 0; t < it.nd_sum; ++t) {  // fastest first
+        const Dim &d = sum[sum.size() - 1 - t];
+        it.sum_ext[t] = d.e;
+        it.sum_sa[t] = d.sa;
+        it.sum_sb[t] = d.sb;
+    }
+    return true;
+}
+
 bool checked_numel(int rank, const int64_t *ext, int64_t &n) {
     n = 1;
     for (int a = 0; a < rank; ++a) {
@@ -574,6 +637,12 @@ qce_status qce_destroy(qce_handle *h) {
     (void)hipFree(h->st);
     (void)hipFree(h->fid_partials);
     (void)hipFree(h->mode_log);
+    if (h->grp_dev) (void)hipFree(h->grp_dev);
+    if (h->grp_host) (void)hipHostFree(h->grp_host);
+    for (auto &pr : h->grp_old) {
+        (void)hipFree(pr.first);
+        (void)hipHostFree(pr.second);
+    }
     delete h;
     return rc;
 }
@@ -876,6 +945,19 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         for (int32_t x : ls) p *= ext_of(x);
         return p;
     };
+    // Inside a group (qce_group_begin): a contraction the GEMM path would send
+    // to the irregular-shape kernel, and small enough, is recorded and runs at
+    // qce_group_end in one launch with the group's other small contractions.
+    if (h->grouping) {
+        SmallItem it{};
+        if (small_item(a, la, b, lb, c, lc, K, ext_of, prod(FA), prod(FB), prod(K), nc, it)) {
+            it.A = static_cast<const float2 *>(A);
+            it.B = static_cast<const float2 *>(B);
+            it.C = static_cast<float2 *>(C);
+            h->pending.push_back(it);
+            return QCE_SUCCESS;
+        }
+    }
     // batch labels (in A, B and C): one independent GEMM per value, outermost
     // everywhere, in the order C lists them
     std::vector<int32_t> BO;
@@ -1034,6 +1116,91 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         st = run_permute(h, rc, te.data(), perm.data(), Cg, static_cast<float2 *>(C));
         if (st != QCE_SUCCESS) return st;
     }
+    return QCE_SUCCESS;
+}
+
+qce_status qce_group_begin(qce_handle *h) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (h->grouping) return fail(h, QCE_ERR_INVALID_VALUE, "a group is already open");
+    h->grouping = true;
+    h->pending.clear();
+    return QCE_SUCCESS;
+}
+
+qce_status qce_group_end(qce_handle *h) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (!h->grouping) return fail(h, QCE_ERR_INVALID_VALUE, "no group is open");
+    h->grouping = false;
+    const int count = (int)h->pending.size();
+    if (count == 0) return QCE_SUCCESS;
+    DeviceGuard g(h->device);
+    std::vector<int64_t> starts(count + 1, 0);
+    for (int i = 0; i < count; ++i) starts[i + 1] = starts[i] + (h->pending[i].n_out + 255) / 256;
+    const size_t bi = align256(sizeof(SmallItem) * (size_t)count);
+    const size_t need = bi + align256(sizeof(int64_t) * (size_t)(count + 1));
+    if (h->grp_used + need > h->grp_cap) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        QCE_HIP(h, hipStreamIsCapturing(h->stream, &cs));
+        if (cs != hipStreamCaptureStatusNone) {
+            h->pending.clear();
+            return fail(h, QCE_ERR_ALLOC, "group descriptor space full during stream capture "
+                                          "(run the work once before capturing, then qce_group_reset)");
+        }
+        QCE_HIP(h, hipStreamSynchronize(h->stream));  // earlier copies and launches are done
+        if (need > h->grp_cap) {
+            if (h->grp_dev) h->grp_old.push_back({h->grp_dev, h->grp_host});
+            h->grp_dev = nullptr;
+            h->grp_host = nullptr;
+            const size_t cap = std::max<size_t>(size_t(1) << 20, 4 * need);
+            if (hipMalloc(&h->grp_dev, cap) != hipSuccess ||
+                hipHostMalloc(reinterpret_cast<void **>(&h->grp_host), cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                if (h->grp_dev) (void)hipFree(h->grp_dev);
+                h->grp_dev = nullptr;
+                h->grp_host = nullptr;
+                h->grp_cap = 0;
+                h->pending.clear();
+                return fail(h, QCE_ERR_ALLOC, "group descriptor space of %zu bytes", cap);
+            }
+            h->grp_cap = cap;
+        }
+        h->grp_used = 0;
+    }
+    char *hp = h->grp_host + h->grp_used;
+    char *dp = h->grp_dev + h->grp_used;
+    memcpy(hp, h->pending.data(), sizeof(SmallItem) * (size_t)count);
+    memcpy(hp + bi, starts.data(), sizeof(int64_t) * (size_t)(count + 1));
+    h->grp_used += need;
+    h->pending.clear();
+    hipEvent_t e0 = span_begin(h);
+    QCE_HIP(h, hipMemcpyAsync(dp, hp, need, hipMemcpyHostToDevice, h->stream));
+    QCE_HIP(h, launch_group(reinterpret_cast<const SmallItem *>(dp), reinterpret_cast<const int64_t *>(dp + bi),
+                            count, starts[count], h->stream));
+    span_end(h, e0, QCE_PHASE_GEMM_IRREGULAR);
+    return QCE_SUCCESS;
+}
+
+qce_status qce_group_reset(qce_handle *h, size_t reserve_bytes) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (h->grouping) return fail(h, QCE_ERR_INVALID_VALUE, "a group is open");
+    DeviceGuard g(h->device);
+    QCE_HIP(h, hipStreamSynchronize(h->stream));
+    if (reserve_bytes > h->grp_cap) {
+        if (h->grp_dev) h->grp_old.push_back({h->grp_dev, h->grp_host});
+        h->grp_dev = nullptr;
+        h->grp_host = nullptr;
+        h->grp_cap = 0;
+        if (hipMalloc(&h->grp_dev, reserve_bytes) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&h->grp_host), reserve_bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            if (h->grp_dev) (void)hipFree(h->grp_dev);
+            h->grp_dev = nullptr;
+            h->grp_host = nullptr;
+            return fail(h, QCE_ERR_ALLOC, "group descriptor space of %zu bytes", reserve_bytes);
+        }
+        h->grp_cap = reserve_bytes;
+    }
+    h->grp_used = 0;
     return QCE_SUCCESS;
 }
 

@@ -201,6 +201,23 @@ constexpr int kMaxRank = 32;
 hipError_t launch_permute(const float2 *x, float2 *y, int64_t total, const PermDesc &d,
                           hipStream_t s);
 
+// One small contraction of a grouped launch (group.hip): output dimensions
+// in C's row-major order (last fastest) with strides into A and B (0 where
+// the operand lacks the label), summed dimensions stored fastest first.
+constexpr int kSmallOut = 16, kSmallSum = 8;
+struct SmallItem {
+    const float2 *A, *B;
+    float2 *C;
+    int64_t n_out, n_sum;
+    int nd_out, nd_sum;
+    int64_t out_ext[kSmallOut], out_sa[kSmallOut], out_sb[kSmallOut];
+    int64_t sum_ext[kSmallSum], sum_sa[kSmallSum], sum_sb[kSmallSum];
+};
+// block_start[i]: first block of item i (block_start[0] = 0), items and
+// block_start in device memory.
+hipError_t launch_group(const SmallItem *items, const int64_t *block_start, int count,
+                        int64_t total_blocks, hipStream_t s);
+
 hipError_t launch_accumulate_f64(const float2 *src, double *acc2, hipStream_t s);
 hipError_t launch_accumulate_n_f64(const float2 *src, int64_t n, double *partials, int nblocks,
                                    double *acc2, hipStream_t s);

@@ -243,24 +243,49 @@ class BatchedExecutor:
             out.append((t, [lab for lab in labels if lab not in opos]))
         return out
 
-    def run_pass(self, leaves):
+    def _levels(self):
+        """Contraction steps grouped by tree level (a step's level is one more
+        than its children's): the steps of one level are independent."""
+        p = self.plan
+        L = len(p.label_sets)
+        lev = [0] * L
+        groups = {}
+        for s, (a, b) in enumerate(p.path):
+            lev.append(1 + max(lev[a], lev[b]))
+            groups.setdefault(lev[-1], []).append(s)
+        return [groups[k] for k in sorted(groups)]
+
+    def run_pass(self, leaves, grouped=True):
         """One pass over the tree on the given device leaves; returns the root
-        tensor and its labels (a subset of the batch labels)."""
+        tensor and its labels (a subset of the batch labels).  ``grouped``:
+        the steps of each tree level run inside one library group, so their
+        small contractions share one launch."""
         import paper_2303_08989_amd as qce
         p = self.plan
         L = len(p.label_sets)
         B = self._bpos
         vals = {i: leaves[i] for i in range(L)}
-        for s, (a, b) in enumerate(p.path):
+
+        def step(s):
+            a, b = p.path[s]
             ta, la = vals.pop(a)
             tb, lb = vals.pop(b)
             shared = set(la) & set(lb)
             bt = sorted((lab for lab in shared if lab in B), key=lambda lab: B[lab])
             lc = bt + [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
             vals[L + s] = (qce.contract(self.h, ta, list(la), tb, list(lb), lc), lc)
+
+        if grouped and self.device != "cpu":
+            for level in self._levels():
+                with qce.group(self.h):
+                    for s in level:
+                        step(s)
+        else:
+            for s in range(len(p.path)):
+                step(s)
         return vals[L + len(p.path) - 1] if p.path else vals[0]
 
-    def amplitude(self, x, outer_ids=None, acc=None, cache=None):
+    def amplitude(self, x, outer_ids=None, acc=None, cache=None, grouped=True):
         """Sum over the outer slices ``outer_ids`` (default: all) of the
         batched passes, accumulated in FP64 on the device; returns the
         float64[2] accumulator."""
@@ -271,7 +296,7 @@ class BatchedExecutor:
         if outer_ids is None:
             outer_ids = range(self.n_outer)
         for o in outer_ids:
-            root, _ = self.run_pass(self._leaves(x, o, cache))
+            root, _ = self.run_pass(self._leaves(x, o, cache), grouped)
             qce.accumulate_n_f64(self.h, root.reshape(-1), acc)
         return acc
 
@@ -300,6 +325,7 @@ class GraphPass:
         self.acc = torch.zeros(2, dtype=torch.float64, device="cuda")
         root, _ = self.bx.run_pass(self.leaves)            # warm-up: workspace, allocator
         torch.cuda.synchronize()
+        qce.group_reset(self.h, 64 << 20)                   # room for the captured groups' descriptors
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self.acc.zero_()
