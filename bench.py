@@ -72,6 +72,32 @@ def sample_error(C_dev_host, A, B, rng, nsamp=256):
 IRREGULAR_SHAPES = [(2, 1 << 26, 2), (1 << 26, 2, 2), (1 << 15, 1 << 13, 2), (4, 1 << 24, 4)]
 
 
+def library_peaks(torch, n=8192, reps=10):
+    """Real (not complex) n^3 GEMMs through torch.matmul (hipBLASLt / rocBLAS)
+    per input type: what the vendor library sustains on this part, quoted
+    beside the published dense peaks."""
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(7)
+    for name, dt in (("fp16", torch.float16), ("bf16", torch.bfloat16), ("fp32", torch.float32)):
+        a = torch.randn(n, n, device="cuda", generator=g).to(dt).contiguous()
+        b = torch.randn(n, n, device="cuda", generator=g).to(dt).contiguous()
+        c = torch.matmul(a, b)
+        for _ in range(3):
+            torch.matmul(a, b, out=c)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            torch.matmul(a, b, out=c)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        out[name] = {"ms": round(ms, 4), "tflops": round(tf, 1), "frac_of_published_peak": round(tf / PEAK[name], 4)}
+        del a, b, c
+    return out
+
+
 def run_irregular(h, torch, qce, reps=10):
     """Irregular-shape CGEMMs (a gate absorbed into a large tensor, a short-k
     outer product) run by the bandwidth-bound kernel in every mode: HBM rate
@@ -360,8 +386,11 @@ def run_circuits(h, args, torch, qce, synth):
     nsl = min(args.c3_slices, plan3.n_slices)
     ids = range(nsl)
     res = {}
-    for mode in ("auto", "fp32"):
+    # AUTO at the default t = 0.1, AUTO at the paper's looser t = 0.5, and
+    # the forced-FP32 baseline
+    for key, mode, t in (("auto", "auto", 0.1), ("auto_t05", "auto", 0.5), ("fp32", "fp32", 0.1)):
         h.set_mode(mode)
+        h.set_tolerance(t, 0.0)
         ex3 = Executor(h, plan3)
         vec = torch.empty(nsl, dtype=torch.complex64, device="cuda")
         ex3.amplitude(x3, ids, slice_out=vec)          # warm-up (allocations, workspace)
@@ -374,10 +403,15 @@ def run_circuits(h, args, torch, qce, synth):
         dt = time.perf_counter() - t0
         h.set_timing(False)
         tm = h.timing()
-        res[mode] = dict(seconds=dt, acc=acc.cpu().numpy(), vec=vec, timing=tm)
+        res[key] = dict(seconds=dt, acc=acc.cpu().numpy(), vec=vec, timing=tm)
     h.set_mode("auto")
-    fid = qce.fidelity_terms(h, res["auto"]["vec"], res["fp32"]["vec"]).cpu().numpy()
-    fidelity = float((fid[0] ** 2 + fid[1] ** 2) / (fid[2] * fid[3])) if fid[2] * fid[3] > 0 else 1.0
+    h.set_tolerance(0.1, 0.0)
+
+    def fidelity_vs_fp32(key):
+        fid = qce.fidelity_terms(h, res[key]["vec"], res["fp32"]["vec"]).cpu().numpy()
+        return float((fid[0] ** 2 + fid[1] ** 2) / (fid[2] * fid[3])) if fid[2] * fid[3] > 0 else 1.0
+
+    fidelity = fidelity_vs_fp32("auto")
     tm = res["auto"]["timing"]
     gpu_ms = {k: round(v[0], 2) for k, v in tm.items() if k != "gemms_by_mode" and v[1]}
     t64 = res["auto"]["seconds"]
@@ -400,6 +434,10 @@ def run_circuits(h, args, torch, qce, synth):
         "amplitudes_per_s_one_gpu_extrapolated": 1.0 / (t64 / share),
         "gpu_ms_by_phase": gpu_ms, "gemms_by_mode": tm["gemms_by_mode"],
         "largest_gemm_log2_mnk": [list(x) for x in big],
+        "auto_t05": {"seconds": round(res["auto_t05"]["seconds"], 4),
+                     "speedup_vs_fp32": round(res["fp32"]["seconds"] / res["auto_t05"]["seconds"], 3),
+                     "fidelity_vs_fp32_over_slices": fidelity_vs_fp32("auto_t05"),
+                     "gemms_by_mode": res["auto_t05"]["timing"]["gemms_by_mode"]},
     }
     return out
 
@@ -575,6 +613,7 @@ def main():
         base["fp32_lib_tflops"] = round(flops_step / (base["fp32_lib_ms"] * 1e-3) / 1e12, 3)
         base["rocblas_tflops"] = round(flops_step / (base["rocblas_ms"] * 1e-3) / 1e12, 3)
         base["speedup_vs_best_fp32"] = round(min(base["fp32_lib_ms"], base["rocblas_ms"]) / ms_per_step, 3)
+        base["library_real_gemm_8192"] = library_peaks(torch)
     for e in case_out:
         e.pop("_idx", None)
 

@@ -88,8 +88,7 @@ class Executor:
                 out[(i, ())] = torch.from_numpy(np.ascontiguousarray(arr)).to("cuda")
                 continue
             for vals in np.ndindex(*(2,) * len(sl)):
-                idx = tuple(vals[sl.index(lab)] if lab in pos else slice(None) for lab in labels)
-                sub = np.ascontiguousarray(arr[idx])
+                sub = tn.fix_labels(arr, labels, dict(zip(sl, vals)))
                 out[(i, tuple(vals))] = torch.from_numpy(sub).to("cuda")
         return out
 
@@ -213,35 +212,42 @@ class BatchedExecutor:
             best = max(best, len(out))
         return best
 
-    def _leaves_host(self, x, o):
-        """Host arrays of the leaves for bitstring x with the outer labels
-        fixed by o."""
-        p = self.plan
-        opos = {lab: i for i, lab in enumerate(self.outer_labels)}
-        out = []
-        for arr, labels in tn.circuit_network(p.circuit, x):
-            idx = tuple(((o >> opos[lab]) & 1) if lab in opos else slice(None) for lab in labels)
-            out.append(np.ascontiguousarray(arr[idx]))
-        return out
-
     def _leaves(self, x, o, cache=None):
         """Device leaves for bitstring x with the outer labels fixed by o."""
+        return self._leaves_and_xbuf(x, o, cache)[0]
+
+    def _leaves_and_xbuf(self, x, o, cache=None):
+        """``_leaves`` and the one device buffer the <x| leaves (the last n)
+        are views of: they go up in one host-to-device copy."""
         torch = self.torch
         p = self.plan
         opos = {lab: i for i, lab in enumerate(self.outer_labels)}
         leaves = tn.circuit_network(p.circuit, x)
+        first_x = len(leaves) - p.circuit["n"]
         out = []
+        xs = []
         for i, (arr, labels) in enumerate(leaves):
-            idx = tuple(((o >> opos[lab]) & 1) if lab in opos else slice(None) for lab in labels)
-            key = (i, tuple(((o >> opos[lab]) & 1) for lab in labels if lab in opos))
+            fixed = {lab: (o >> opos[lab]) & 1 for lab in labels if lab in opos}
+            kept = [lab for lab in labels if lab not in opos]
+            if i >= first_x:
+                xs.append((tn.fix_labels(arr, labels, fixed), kept))
+                continue
+            key = (i, tuple(fixed[lab] for lab in labels if lab in opos))
             if cache is not None and key in cache:
                 t = cache[key]
             else:
-                t = torch.from_numpy(np.ascontiguousarray(arr[idx])).to(self.device)
-                if cache is not None and i < len(leaves) - p.circuit["n"]:
+                t = torch.from_numpy(tn.fix_labels(arr, labels, fixed)).to(self.device)
+                if cache is not None:
                     cache[key] = t           # gate and |0> leaves do not depend on x
-            out.append((t, [lab for lab in labels if lab not in opos]))
-        return out
+            out.append((t, kept))
+        flat = None
+        if xs:
+            flat = torch.from_numpy(np.concatenate([a.reshape(-1) for a, _ in xs])).to(self.device)
+            off = 0
+            for a, kept in xs:
+                out.append((flat[off:off + a.size].view(a.shape), kept))
+                off += a.size
+        return out, flat
 
     def _levels(self):
         """Contraction steps grouped by tree level (a step's level is one more
@@ -304,8 +310,9 @@ class BatchedExecutor:
 class GraphPass:
     """One batched pass (``BatchedExecutor``, outer value ``outer``) captured
     once in a HIP graph and replayed per bitstring.  Only the <x| leaves
-    change between bitstrings: they are overwritten in place (host-to-device
-    copies outside the graph) before each replay.
+    change between bitstrings: they are overwritten in place (one
+    host-to-device copy from pinned memory, outside the graph) before each
+    replay.
 
     The graph owns a handle of its own, so its workspace (whose address the
     captured kernels hold) is never reallocated by other calls; a warm-up
@@ -321,7 +328,23 @@ class GraphPass:
         self.bx = BatchedExecutor(self.h, plan, n_batch)
         self.outer = outer
         self.n = plan.circuit["n"]
-        self.leaves = self.bx._leaves(0, outer)
+        # The <x| leaves are views of one device buffer, refilled per
+        # bitstring by one copy from pinned memory.  Per qubit: its offset in
+        # the buffer and, if its final wire is an outer label, that label's
+        # fixed value (the leaf is then a scalar).
+        self.leaves, self.xbuf = self.bx._leaves_and_xbuf(0, outer)
+        opos = {lab: i for i, lab in enumerate(self.bx.outer_labels)}
+        wires = [labels[0] for _, labels in tn.circuit_network(plan.circuit, 0)[-self.n:]]
+        self.xslots = []
+        off = 0
+        for w in wires:
+            fixed = ((outer >> opos[w]) & 1) if w in opos else None
+            self.xslots.append((off, fixed))
+            off += 1 if fixed is not None else 2
+        assert self.n == 0 or off == self.xbuf.numel()
+        self.xhost = torch.zeros(max(off, 1), dtype=torch.complex64, pin_memory=True)
+        self.xdone = torch.cuda.Event()
+        self.xdone.record()
         self.acc = torch.zeros(2, dtype=torch.float64, device="cuda")
         root, _ = self.bx.run_pass(self.leaves)            # warm-up: workspace, allocator
         torch.cuda.synchronize()
@@ -336,10 +359,18 @@ class GraphPass:
     def amplitude(self, x):
         """Replay for bitstring x; returns the device float64[2] sum of the
         pass's slice values (valid until the next replay)."""
-        host = self.bx._leaves_host(x, self.outer)
-        L = len(self.leaves)
-        for i in range(L - self.n, L):
-            self.leaves[i][0].copy_(self.torch.from_numpy(host[i]), non_blocking=False)
+        if self.n:
+            self.xdone.synchronize()          # the previous copy has read the pinned buffer
+            hv = self.xhost.numpy()
+            hv[:] = 0
+            for q, (off, fixed) in enumerate(self.xslots):
+                bit = (int(x) >> (self.n - 1 - q)) & 1
+                if fixed is None:
+                    hv[off + bit] = 1
+                elif fixed == bit:
+                    hv[off] = 1
+            self.xbuf.copy_(self.xhost[: self.xbuf.numel()], non_blocking=True)
+            self.xdone.record()
         self.graph.replay()
         return self.acc
 

@@ -112,8 +112,7 @@ class GradientRunner:
             return {(): torch.from_numpy(np.ascontiguousarray(arr)).to(self.device)}
         out = {}
         for vals in np.ndindex(*(2,) * len(sl)):
-            idx = tuple(vals[sl.index(lab)] if lab in pos else slice(None) for lab in labels)
-            out[tuple(vals)] = torch.from_numpy(np.ascontiguousarray(arr[idx])).to(self.device)
+            out[tuple(vals)] = torch.from_numpy(tn.fix_labels(arr, labels, dict(zip(sl, vals)))).to(self.device)
         return out
 
     def _leaves(self, thetas, x, cache):

@@ -57,6 +57,15 @@ def circuit_network(circuit, x):
     return leaves
 
 
+def fix_labels(arr, labels, values):
+    """The sub-array of ``arr`` (axes named by ``labels``) with each label in
+    ``values`` fixed to the index given there: a C-contiguous copy keeping the
+    other axes in order (0-d when every label is fixed)."""
+    idx = tuple(values[lab] if lab in values else slice(None) for lab in labels)
+    sub = np.asarray(arr[idx])
+    return np.ascontiguousarray(sub).reshape(sub.shape)
+
+
 def _lsize(labels, sliced=frozenset()):
     return sum(1 for lab in labels if lab not in sliced)
 

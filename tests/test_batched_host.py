@@ -64,3 +64,30 @@ def test_outer_ids_partition_the_slices(standin):
     parts = [complex(*bx.amplitude(x, [o]).numpy()) for o in range(bx.n_outer)]
     whole = complex(*bx.amplitude(x).numpy())
     assert abs(sum(parts) - whole) < 1e-12
+
+
+def test_fix_labels_keeps_rank():
+    from paper_2303_08989_amd import tn
+    arr = np.arange(8, dtype=np.complex64).reshape(2, 2, 2)
+    assert tn.fix_labels(arr, [5, 6, 7], {6: 1}).shape == (2, 2)
+    assert np.array_equal(tn.fix_labels(arr, [5, 6, 7], {6: 1}), arr[:, 1, :])
+    v = tn.fix_labels(arr[0, 0], [9], {9: 1})           # every label fixed: 0-d
+    assert v.shape == () and v == arr[0, 0, 1]
+    assert tn.fix_labels(arr, [5, 6, 7], {5: 0, 6: 1, 7: 0}).shape == ()
+
+
+def test_sliced_output_wires_give_scalar_leaves(standin):
+    # slicing final wires (labels of <x| leaves) leaves 0-d leaves: the sum
+    # over all outer values still equals the oracle's amplitude
+    from paper_2303_08989_amd import tn
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan
+    c = synth.grid_circuit(3, 4, 6, seed=3, pattern="ABCDCDAB")
+    base = CircuitPlan(c, max_log2=5, restarts=1, varied=3)
+    wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
+    plan = CircuitPlan(c, path=base.path, sliced=list(base.sliced) + wires[:2])
+    bx = BatchedExecutor(None, plan, len(base.sliced), device="cpu")
+    assert all(w in bx.outer_labels for w in wires[:2]) and bx.n_outer <= 64
+    for x in (1234, 4095):
+        want = oracle.statevector_amplitudes(_rounded(c), [x])[0]
+        acc = bx.amplitude(x).numpy()
+        assert abs(complex(acc[0], acc[1]) - want) < 1e-6 * max(abs(want), 1e-3)

@@ -100,3 +100,35 @@ def test_graph_replay_matches_eager(qce, h):
             torch.cuda.synchronize()
     finally:
         gp.close()
+
+
+def test_graph_replay_sliced_output_wires_back_to_back(qce, h):
+    # two final wires sliced as outer labels (their <x| leaves become
+    # scalars fixed by the outer value), replays issued back to back with
+    # no synchronisation in between: each replay's result must still equal
+    # the eager pass for its own bitstring
+    from paper_2303_08989_amd import tn
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, GraphPass
+    c = synth.grid_circuit(3, 4, 8, seed=7, pattern="ABCDCDAB")
+    base = CircuitPlan(c, max_log2=5, restarts=2, varied=3)
+    wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
+    plan = CircuitPlan(c, path=base.path, sliced=list(base.sliced) + wires[:2])
+    bx = BatchedExecutor(h, plan, 3)
+    pos = [bx.outer_labels.index(w) for w in wires[:2]]
+    outer = 1 << pos[0]                      # wire of qubit 0 fixed to 1, qubit 1 to 0
+    gp = GraphPass(plan, n_batch=3, outer=outer)
+    try:
+        assert sorted(f for _, f in gp.xslots if f is not None) == [0, 1]
+        n = c["n"]
+        xs = [int(x) for x in synth.random_bitstrings(n, 6, seed=9)]
+        xs += [(1 << (n - 1)) | 0b1011, (1 << (n - 1)) | (1 << (n - 2)) | 0b11]
+        replays = [gp.amplitude(x).clone() for x in xs]
+        for x, r in zip(xs, replays):
+            eager = bx.amplitude(x, [outer]).cpu().numpy()
+            assert np.array_equal(r.cpu().numpy(), eager), x
+        # the bitstring whose two leading bits match the fixed values has a
+        # nonzero partial amplitude; a mismatch gives exact zero
+        assert np.any(replays[-2].cpu().numpy() != 0)
+        assert not np.any(replays[-1].cpu().numpy() != 0)
+    finally:
+        gp.close()
