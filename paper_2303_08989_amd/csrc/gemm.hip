@@ -84,6 +84,10 @@ __device__ inline void tile_of(int bid, int nbm, int nbn, int &mb, int &nb) {
 
 #define LDS_PTR(p) ((__attribute__((address_space(3))) void *)(p))
 
+// Word 3 of a raw buffer descriptor on gfx9-family parts (32-bit data
+// format; no swizzle, no index stride).
+constexpr int kRsrcWord3 = 0x00020000;
+
 // Wait until at most N vector-memory operations of this wave are
 // outstanding (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14, expcnt
 // and lgkmcnt left at their "no wait" maxima).
@@ -131,7 +135,10 @@ template <> struct Stages<QCE_MODE_BF16X3> { static constexpr int kNS = 3; };
 template <int MODE> struct Acc;
 template <> struct Acc<QCE_MODE_FP16X2> { floatx16 re_m[2][2], im_m[2][2], re_c[2][2], im_c[2][2]; };
 template <> struct Acc<QCE_MODE_BF16X3> { floatx16 re_m[2][2], im_m[2][2], re_c[2][2], im_c[2][2]; };
-template <> struct Acc<QCE_MODE_FP32> { floatx16 re_m[2][2], im_m[2][2]; };
+// FP32: Re = sum Ar Br - sum Ai Bi with the subtracted sum in re_n (no
+// sign flip of a fragment: a vector instruction between two FP32 MFMAs does
+// not overlap them, it adds its own latency)
+template <> struct Acc<QCE_MODE_FP32> { floatx16 re_m[2][2], im_m[2][2], re_n[2][2]; };
 
 // 12 MFMAs of one 32x32 block for one k16 step (planes: 0 = hi(re),
 // 1 = lo(re), 2 = hi(im), 3 = lo(im); nx = -hi(im), -lo(im) of x)
@@ -243,7 +250,7 @@ __device__ __attribute__((always_inline)) inline void mma_block(const Frag<MODE>
                 const float a_r = f.xr[s][ub][j], a_i = f.xi[s][ub][j];
                 const float b_r = f.yr[s][vb][j], b_i = f.yi[s][vb][j];
                 acc.re_m[ub][vb] = mfma32(a_r, b_r, acc.re_m[ub][vb]);
-                acc.re_m[ub][vb] = mfma32(-a_i, b_i, acc.re_m[ub][vb]);
+                acc.re_n[ub][vb] = mfma32(a_i, b_i, acc.re_n[ub][vb]);
                 acc.im_m[ub][vb] = mfma32(a_r, b_i, acc.im_m[ub][vb]);
                 acc.im_m[ub][vb] = mfma32(a_i, b_r, acc.im_m[ub][vb]);
             }
@@ -337,6 +344,8 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
                 if constexpr (MODE != QCE_MODE_FP32) {
                     acc.re_c[a][b] = z;
                     acc.im_c[a][b] = z;
+                } else {
+                    acc.re_n[a][b] = z;
                 }
             }
     }
@@ -354,17 +363,27 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         const int nk2 = nk + (nk & 1);
         const char *zero = reinterpret_cast<const char *>(g_zero_chunk);
         asm volatile("" : "+s"(zero));   // computed once, kept in scalar registers
+        // Copies are buffer loads into LDS: the chunk's address lives in a
+        // scalar buffer descriptor (one chunk long, so no access can leave
+        // it), the lane's byte offset in one loop-invariant vector register,
+        // the copy's offset within the chunk and the LDS destination (M0) in
+        // scalar registers (the wave index read once).  Issuing a copy then
+        // takes no vector instruction, which matters because a vector
+        // instruction between two FP32 MFMAs adds its full latency.
+        const int wsc = __builtin_amdgcn_readfirstlane(w);
+        const unsigned lane_off = (unsigned)tid * 16u;
         auto issue_to = [&](int c, int stage) {
             const char *gx = chunk_src(c, nk, px + (int64_t)c * kCB, zero);
             const char *gy = chunk_src(c, nk, py + (int64_t)c * kCB, zero);
+            const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)gx, (short)0, kCB, kRsrcWord3);
+            const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc((void *)gy, (short)0, kCB, kRsrcWord3);
             char *lx = smem[stage][0];
             char *ly = smem[stage][1];
 #pragma unroll
             for (int i = 0; i < kL1; ++i) {
-                const int e = (tid + i * kThreads) * 16;
-                const int we = (w * 64 + i * kThreads) * 16;
-                __builtin_amdgcn_global_load_lds(gx + e, LDS_PTR(lx + we), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds(gy + e, LDS_PTR(ly + we), 16, 0, 0);
+                const int we = (wsc * 64 + i * kThreads) * 16;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, LDS_PTR(lx + we), 16, lane_off, i * kThreads * 16, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, LDS_PTR(ly + we), 16, lane_off, i * kThreads * 16, 0, 0);
             }
         };
         const int l32 = lane & 31;
@@ -434,7 +453,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
                     re = acc.re_m[ub][vb][r] + acc.re_c[ub][vb][r];
                     im = acc.im_m[ub][vb][r] + acc.im_c[ub][vb][r];
                 } else {
-                    re = acc.re_m[ub][vb][r];
+                    re = acc.re_m[ub][vb][r] - acc.re_n[ub][vb][r];
                     im = acc.im_m[ub][vb][r];
                 }
                 if (split) {
