@@ -31,6 +31,7 @@
 // long, blockIdx.y splits the k range; partial tiles are added in split order
 // by gemm_reduce_kernel, which also applies the shift, alpha and beta.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -388,19 +389,39 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         };
         const int l32 = lane & 31;
         const int rx0 = wu * 64 + l32, ry0 = wv * 64 + l32;
+        // 64 KB as a value the optimizer cannot see through: the address
+        // registers built on it are computed once, outside the loop
+        int hi_base = 65536;
+        asm volatile("" : "+s"(hi_base));
         // One k-step: chunk `it` is in registers (fc).  Wait for chunk it+1
         // (this thread's copies: kNS - 2 later chunks may be outstanding) and
         // for this wave's reads of chunk `it`; after the barrier every wave
         // has them, so chunk it's stage takes chunk it + kNS.  Chunk it+1's
         // fragments are then read into fn while chunk it's MFMAs run: the
         // reads first, spread over the first MFMAs, then the copies.
-        auto step = [&](int it, const Frag<MODE> &fc, Frag<MODE> &fn) {
+        // `stage` (= it % kNS) is a compile-time constant where the loop
+        // below is unrolled by the ring length (FP32 mode, whose MFMAs do not
+        // overlap vector instructions): then every LDS read address is a
+        // loop-invariant register plus an immediate offset.  The other modes
+        // keep a run-time stage: their fragment reads would need more
+        // address registers than remain beside 256 accumulators.
+        auto step = [&](int it, auto stage, const Frag<MODE> &fc, Frag<MODE> &fn) {
             wait_barrier<(kNS - 2) * kL>();
             // (reads before copies in program order: the compiler cannot
             // tell that they touch different stages and keeps their order)
-            const int ns = (it + 1) % kNS;
-            load_chunk<MODE>(fn, smem[ns][0], smem[ns][1], rx0, ry0, lane);
-            issue_to(it + kNS, it % kNS);
+            const int cur = stage;
+            const int ns = (cur + 1) % kNS;
+            if constexpr (std::is_integral_v<decltype(stage)>) {
+                load_chunk<MODE>(fn, smem[ns][0], smem[ns][1], rx0, ry0, lane);
+            } else {
+                // stages past 64 KB are read from a second base (an LDS
+                // read's immediate offset stops at 64 KB)
+                constexpr int kNext = (decltype(stage)::value + 1) % kNS;
+                const char *b = kNext * 2 * kCB < 65536 ? smem[kNext][0]
+                                                        : smem_raw + hi_base + (kNext * 2 * kCB - 65536);
+                load_chunk<MODE>(fn, b, b + kCB, rx0, ry0, lane);
+            }
+            issue_to(it + kNS, cur);
             mma_chunk<MODE>(fc, acc);
             constexpr int kReads = Frag<MODE>::kReads, kMfma = Frag<MODE>::kMfma;
             constexpr int kRp = kReads / 8;   // LDS reads per MFMA over the first 8 MFMAs
@@ -424,9 +445,28 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         // keeps the optimizer from merging these reads with the loop's
         // reads into f0 as one read at the top of the loop
         opaque_frag(f0);
-        for (int it = 0; it < nk2; it += 2) {
-            step(it, f0, f1);
-            step(it + 1, f1, f0);   // the last one reads a chunk past the end (unused)
+        // (the last k-step reads a chunk past the end, unused)
+        if constexpr (MODE == QCE_MODE_FP32 && kNS == 4) {
+            using S0 = std::integral_constant<int, 0>;
+            using S1 = std::integral_constant<int, 1>;
+            using S2 = std::integral_constant<int, 2>;
+            using S3 = std::integral_constant<int, 3>;
+            int it = 0;
+            for (; it + 4 <= nk2; it += 4) {
+                step(it, S0{}, f0, f1);
+                step(it + 1, S1{}, f1, f0);
+                step(it + 2, S2{}, f0, f1);
+                step(it + 3, S3{}, f1, f0);
+            }
+            if (it < nk2) {   // two k-steps left: stages 0 and 1 again
+                step(it, S0{}, f0, f1);
+                step(it + 1, S1{}, f1, f0);
+            }
+        } else {
+            for (int it = 0; it < nk2; it += 2) {
+                step(it, it % kNS, f0, f1);
+                step(it + 1, (it + 1) % kNS, f1, f0);
+            }
         }
         // the copies issued by the last k-steps land before the end
         wait_vmcnt<0>();
