@@ -170,12 +170,12 @@ __device__ __attribute__((always_inline)) inline void fp16x2_block(const u32x4 *
 template <int MODE> struct Frag;
 template <> struct Frag<QCE_MODE_FP16X2> {
     static constexpr int kP = 4;  // planes: hi(re), lo(re), hi(im), lo(im)
-    static constexpr int kReads = 16, kMfma = 48;
+    static constexpr int kReads = 16, kMfma = 48, kMfmaPerRead = 2;
     u32x4 x[2][4], y[2][4];
 };
 template <> struct Frag<QCE_MODE_BF16X3> {
     static constexpr int kP = 6;  // planes: b0, b1, b2 of re; b0, b1, b2 of im
-    static constexpr int kReads = 24, kMfma = 96;
+    static constexpr int kReads = 24, kMfma = 96, kMfmaPerRead = 3;
     u32x4 x[2][6], y[2][6];
 };
 // FP32: per k8 half s and 32-row block, four consecutive k-values of re and
@@ -183,7 +183,7 @@ template <> struct Frag<QCE_MODE_BF16X3> {
 // k = 8s + j and 8s + 4 + j (the same pairing for both operands, so every k
 // is summed once).
 template <> struct Frag<QCE_MODE_FP32> {
-    static constexpr int kReads = 16, kMfma = 128;
+    static constexpr int kReads = 16, kMfma = 128, kMfmaPerRead = 4;
     f32x4 xr[2][2], xi[2][2], yr[2][2], yi[2][2];  // [s][block]
 };
 
@@ -423,19 +423,28 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
             }
             issue_to(it + kNS, cur);
             mma_chunk<MODE>(fc, acc);
+            // Interleave: one fragment read every kA MFMAs, then one copy
+            // every kB MFMAs, then the remaining MFMAs.  The reads are
+            // spread rather than bunched because the four waves share the
+            // CU's LDS bandwidth (~128 B per clock): two 1 KB wave reads per
+            // 32-cycle f16 MFMA on every SIMD ask for twice that and stall
+            // the MFMAs; one per kA MFMAs stays well below it.
             constexpr int kReads = Frag<MODE>::kReads, kMfma = Frag<MODE>::kMfma;
-            constexpr int kRp = kReads / 8;   // LDS reads per MFMA over the first 8 MFMAs
+            constexpr int kA = Frag<MODE>::kMfmaPerRead;
+            constexpr int kCopies = 2 * kL1;
+            constexpr int kB = (kMfma - kA * kReads) / (kCopies + 1) > 0 ? (kMfma - kA * kReads) / (kCopies + 1) : 1;
+            static_assert(kA * kReads + kB * kCopies <= kMfma, "interleave exceeds the chunk's MFMAs");
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // MFMA
-                __builtin_amdgcn_sched_group_barrier(0x100, kRp, 0);   // LDS read
+            for (int i = 0; i < kReads; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, kA, 0);    // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);     // LDS read
             }
 #pragma unroll
-            for (int i = 0; i < 2 * kL1; ++i) {
+            for (int i = 0; i < kCopies; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, kB, 0);
                 __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);     // VMEM read (copy to LDS)
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             }
-            __builtin_amdgcn_sched_group_barrier(0x008, kMfma - 8 - 2 * kL1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, kMfma - kA * kReads - kB * kCopies, 0);
         };
         Frag<MODE> f0, f1;
 #pragma unroll
