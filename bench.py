@@ -374,9 +374,23 @@ def run_circuits(h, args, torch, qce, synth):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     amps = np.array([complex(*a.cpu().numpy()) for a in accs])
+    # the same amplitudes as one captured pass replayed per bitstring (grouped
+    # tree levels, one packed upload of the <x| leaves per replay)
+    from paper_2303_08989_amd.executor import GraphPass
+    gp = GraphPass(plan1, n_batch=0, mode="fp32")
+    gp.amplitude(xs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gvals = [gp.amplitude(x).clone() for x in xs]
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
+    amps_g = np.array([complex(*v.cpu().numpy()) for v in gvals])
+    gp.close()
     out["config1"] = {"workload": "12-qubit 3x4 grid, depth 8, ABCD, fSim(pi/2,pi/6), plain FP32 path",
                       "amplitudes_per_s": round(len(xs) / dt, 2), "ms_per_amplitude": round(dt / len(xs) * 1e3, 3),
-                      "contractions_per_amplitude": len(plan1.path), "_xs": xs, "_amps": amps}
+                      "graph_amplitudes_per_s": round(len(xs) / dtg, 2),
+                      "graph_ms_per_amplitude": round(dtg / len(xs) * 1e3, 4),
+                      "contractions_per_amplitude": len(plan1.path), "_xs": xs, "_amps": amps, "_amps_g": amps_g}
     # ---- config 3
     c3 = synth.grid_circuit(pattern="ABCDCDAB", depth=12, seed=1, **synth.GRID_53)
     t0 = time.perf_counter()
@@ -696,6 +710,9 @@ def main():
             got = c1.pop("_amps")
             c1["fidelity_vs_fp64_oracle"] = oracle.fidelity(got, ref)
             c1["max_rel_err_vs_fp64_oracle"] = float(np.max(np.abs(got - ref) / np.abs(ref)))
+            got_g = c1.pop("_amps_g")
+            c1["graph_fidelity_vs_fp64_oracle"] = oracle.fidelity(got_g, ref)
+            c1["graph_max_rel_err_vs_fp64_oracle"] = float(np.max(np.abs(got_g - ref) / np.abs(ref)))
             c1["oracle_statevector_amplitudes_per_s"] = round(len(ref) / dtc, 2)
         cpu = {"value": round(8.0 * rows * c["n"] * c["k"] / dt / 1e12, 6), "unit": "TFLOP/s",
                "cores": oracle.threads(), "kind": "oracle",
@@ -705,6 +722,7 @@ def main():
     if circuits is not None and "config1" in circuits:
         circuits["config1"].pop("_xs", None)
         circuits["config1"].pop("_amps", None)
+        circuits["config1"].pop("_amps_g", None)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),

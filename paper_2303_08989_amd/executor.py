@@ -319,12 +319,14 @@ class GraphPass:
     pass sizes it before capture.  No memset is captured: the accumulator is
     cleared by a fill kernel inside the graph."""
 
-    def __init__(self, plan, n_batch, outer=0, device=0):
+    def __init__(self, plan, n_batch, outer=0, device=0, mode=None):
         import torch
         import paper_2303_08989_amd as qce
         self.torch = torch
         self.qce = qce
         self.h = qce.Handle(device)
+        if mode is not None:
+            self.h.set_mode(mode)        # fixed for the captured pass
         self.bx = BatchedExecutor(self.h, plan, n_batch)
         self.outer = outer
         self.n = plan.circuit["n"]

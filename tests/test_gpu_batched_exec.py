@@ -132,3 +132,25 @@ def test_graph_replay_sliced_output_wires_back_to_back(qce, h):
         assert not np.any(replays[-1].cpu().numpy() != 0)
     finally:
         gp.close()
+
+
+def test_graph_pass_config1_matches_oracle(qce, h):
+    # the 12-qubit workload (3x4 grid, depth 8, ABCD, no slicing) as one
+    # captured pass in FP32, replayed per bitstring, against the FP64 state
+    # vector
+    from paper_2303_08989_amd.executor import CircuitPlan, GraphPass
+    c = synth.grid_circuit(3, 4, 8, seed=0)
+    plan = CircuitPlan(c, max_log2=30, restarts=2)
+    assert not plan.sliced
+    xs = synth.random_bitstrings(12, 10, seed=1)
+    gp = GraphPass(plan, n_batch=0, mode="fp32")
+    try:
+        got = np.array([complex(*gp.amplitude(x).cpu().numpy()) for x in xs])
+    finally:
+        gp.close()
+    rounded = dict(c)
+    rounded["gates"] = [dict(g, matrix=np.asarray(g["matrix"]).astype(np.complex64).astype(np.complex128))
+                        for g in c["gates"]]
+    want = oracle.statevector_amplitudes(rounded, xs)
+    assert oracle.fidelity(got, want) >= 1 - 1e-6
+    assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-4
