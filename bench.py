@@ -163,8 +163,20 @@ def run_gradients(h, args, torch, qce, synth):
     p, amps, J = run.probabilities_and_jacobian(th, xs)
     dt = time.perf_counter() - t0
     h.set_timing(False)
-    modes = h.timing()["gemms_by_mode"]
+    tmg = h.timing()
+    modes = tmg["gemms_by_mode"]
+    gpu_ms_g = {k: round(v[0], 2) for k, v in tmg.items() if k != "gemms_by_mode" and v[1]}
     flops = run.flops
+    # the same passes captured once and replayed per bitstring
+    from paper_2303_08989_amd.grad import GradientGraph
+    gg = GradientGraph(plan, th, mode="auto")
+    gg.probabilities_and_jacobian(xs[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p_g, amps_g, J_g = gg.probabilities_and_jacobian(xs)
+    dt_g = time.perf_counter() - t0
+    graph_equal = bool(np.array_equal(J_g, J) and np.array_equal(amps_g, amps))
+    gg.close()
     # the same Jacobian rows on the plain FP32 path
     nchk = min(4, len(xs))
     h.set_mode("fp32")
@@ -192,6 +204,10 @@ def run_gradients(h, args, torch, qce, synth):
         "contraction_flops_per_bitstring": flops / len(xs),
         "effective_tflops": round(flops / dt / 1e12, 2),
         "gemms_by_mode": modes,
+        "gpu_ms_by_phase": gpu_ms_g,
+        "graph_seconds": round(dt_g, 4), "graph_gradients_per_s": round(len(xs) / dt_g, 2),
+        "graph_effective_tflops": round(flops / dt_g / 1e12, 2),
+        "graph_equals_eager": graph_equal,
         "jacobian_rel_diff_auto_vs_fp32": rel_auto_fp32,
         "fd_check_max_rel_err_fp32_h1e-3": fd_err,
         "mean_probability": float(np.mean(p)),

@@ -140,14 +140,25 @@ class GradientRunner:
         a = sum over slices of the amplitude and D_e = da/dtheta_e.
         ``cache`` (a dict) keeps the angle-dependent leaves between calls
         with the same angles."""
+        torch = self.torch
+        vals, dvals = self._leaves(thetas, x, {} if cache is None else cache)
+        acc_a = torch.zeros(2, dtype=torch.float64, device=self.device)
+        acc_d = torch.zeros((max(1, self.n_couplers), 2), dtype=torch.float64, device=self.device)
+        self._pass(vals, dvals, slice_ids, acc_a, acc_d)
+        return acc_a, acc_d
+
+    def _pass(self, vals, dvals, slice_ids, acc_a, acc_d):
+        """Every device operation of one bitstring: for each slice the
+        forward pass (keeping the checkpoints) and the reverse pass, adding
+        the slice's amplitude to acc_a and each fSim occurrence's
+        derivative to its coupler's row of acc_d (FP64, on the device).
+        The sequence of calls depends only on the plan, not on the leaf
+        values, so it can be captured once and replayed."""
         import paper_2303_08989_amd as qce
         torch = self.torch
         p = self.plan
         L = len(p.label_sets)
         pos = {lab: i for i, lab in enumerate(p.sliced)}
-        vals, dvals = self._leaves(thetas, x, {} if cache is None else cache)
-        acc_a = torch.zeros(2, dtype=torch.float64, device=self.device)
-        acc_d = torch.zeros((max(1, self.n_couplers), 2), dtype=torch.float64, device=self.device)
         if slice_ids is None:
             slice_ids = range(p.n_slices)
         one = torch.ones((), dtype=torch.complex64, device=self.device)
@@ -202,7 +213,6 @@ class GradientRunner:
                 node_val.pop(a, None)
                 node_val.pop(b, None)
             node_val.clear()
-        return acc_a, acc_d
 
     def probabilities_and_jacobian(self, thetas, bitstrings, slice_ids=None):
         """p_x = |a_x|^2 (float64, shape (X,)), the amplitudes (complex128)
@@ -212,14 +222,113 @@ class GradientRunner:
         accs = [self.amplitude_and_derivatives(thetas, x, slice_ids, cache) for x in bitstrings]
         if self.device != "cpu":
             self.torch.cuda.synchronize()
-        amps = np.empty(len(bitstrings), dtype=np.complex128)
-        J = np.zeros((len(bitstrings), self.n_couplers), dtype=np.float64)
-        for i, (acc_a, acc_d) in enumerate(accs):
-            ar, ai = acc_a.cpu().numpy()
-            d = acc_d.cpu().numpy()[: self.n_couplers]
-            amps[i] = complex(ar, ai)
-            J[i] = 2.0 * (ar * d[:, 0] + ai * d[:, 1])
-        return np.abs(amps) ** 2, amps, J
+        return _combine(accs, self.n_couplers)
+
+
+def _combine(accs, n_couplers):
+    """(p, amplitudes, J) from per-bitstring device accumulators (a, D):
+    p = |a|^2 and J[x, e] = 2 Re(conj(a) D_e)."""
+    amps = np.empty(len(accs), dtype=np.complex128)
+    J = np.zeros((len(accs), n_couplers), dtype=np.float64)
+    for i, (acc_a, acc_d) in enumerate(accs):
+        ar, ai = acc_a.cpu().numpy()
+        d = acc_d.cpu().numpy()[:n_couplers]
+        amps[i] = complex(ar, ai)
+        J[i] = 2.0 * (ar * d[:, 0] + ai * d[:, 1])
+    return np.abs(amps) ** 2, amps, J
+
+
+class GradientGraph:
+    """The forward and reverse passes of ``GradientRunner`` for one angle
+    vector, captured once in a HIP graph and replayed per bitstring.
+
+    Only the <x| leaves (the last n) depend on the bitstring: each of their
+    device variants is a view of one buffer, refilled by one copy from
+    pinned memory before each replay (an event keeps the host from
+    rewriting the pinned buffer before the previous copy has run).  The
+    graph owns its handle, so the workspace whose address the captured
+    kernels hold is never reallocated; a warm-up pass sizes it before
+    capture.  The accumulators are cleared by fill kernels inside the graph
+    (no memset is captured)."""
+
+    def __init__(self, plan, thetas, device=0, mode="auto", slice_ids=None):
+        import torch
+        import paper_2303_08989_amd as qce
+        self.torch = torch
+        self.h = qce.Handle(device)
+        self.h.set_mode(mode)            # fixed for the captured passes
+        self.run = GradientRunner(self.h, plan)
+        self.n = self.run.n
+        self.n_couplers = self.run.n_couplers
+        self.thetas = np.asarray(thetas, dtype=np.float32)
+        vals, dvals = self.run._leaves(self.thetas, 0, {})
+        # every variant of the <x| leaves becomes a view of one buffer;
+        # per variant: its offset, the value of the sliced label it is fixed
+        # by (it is then a scalar) or None, and its qubit
+        nl = len(vals)
+        layout, total = [], 0
+        for q in range(self.n):
+            i = nl - self.n + q
+            for key, t in vals[i].items():
+                layout.append((i, key, q, total, t.shape))
+                total += t.numel()
+        self.xbuf = torch.zeros(max(total, 1), dtype=torch.complex64, device="cuda")
+        self.xslots = []
+        for i, key, q, off, shape in layout:
+            vals[i][key] = self.xbuf[off:off + int(np.prod(shape, dtype=np.int64))].view(shape)
+            self.xslots.append((off, key[0] if key else None, q))
+        self.xhost = torch.zeros(max(total, 1), dtype=torch.complex64, pin_memory=True)
+        self.xdone = torch.cuda.Event()
+        self.xdone.record()
+        self.acc_a = torch.zeros(2, dtype=torch.float64, device="cuda")
+        self.acc_d = torch.zeros((max(1, self.n_couplers), 2), dtype=torch.float64, device="cuda")
+        self._upload(0)
+        self.run._pass(vals, dvals, slice_ids, self.acc_a, self.acc_d)   # warm-up: workspace, allocator
+        torch.cuda.synchronize()
+        self.run.flops = 0.0
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.acc_a.zero_()
+            self.acc_d.zero_()
+            self.run._pass(vals, dvals, slice_ids, self.acc_a, self.acc_d)
+        self.flops_per_pass = self.run.flops   # 8mnk of every contraction of one replay
+        self._keep = (vals, dvals)
+
+    def _upload(self, x):
+        """Write the <x| leaves of bitstring x into the device buffer."""
+        self.xdone.synchronize()          # the previous copy has read the pinned buffer
+        hv = self.xhost.numpy()
+        hv[:] = 0
+        for off, fixed, q in self.xslots:
+            bit = (int(x) >> (self.n - 1 - q)) & 1
+            if fixed is None:
+                hv[off + bit] = 1
+            elif fixed == bit:
+                hv[off] = 1
+        self.xbuf.copy_(self.xhost[: self.xbuf.numel()], non_blocking=True)
+        self.xdone.record()
+
+    def amplitude_and_derivatives(self, x):
+        """Replay for bitstring x: the device accumulators (a[2], D[E, 2]),
+        valid until the next replay."""
+        self._upload(x)
+        self.graph.replay()
+        return self.acc_a, self.acc_d
+
+    def probabilities_and_jacobian(self, bitstrings):
+        """As ``GradientRunner.probabilities_and_jacobian`` at the captured
+        angles."""
+        accs = []
+        for x in bitstrings:
+            a, d = self.amplitude_and_derivatives(x)
+            accs.append((a.clone(), d.clone()))
+        self.torch.cuda.synchronize()
+        return _combine(accs, self.n_couplers)
+
+    def close(self):
+        self.graph = None
+        self._keep = None
+        self.h.close()
 
 
 def circuit_probabilities(runner, thetas, bitstrings, slice_ids=None):

@@ -133,3 +133,36 @@ def test_autograd_function(qce, h):
     _, J_ref = oracle.probability_theta_gradient(_rounded(c), xs, base["n_couplers"])
     want = J_ref.T @ w.numpy()
     assert np.max(np.abs(t.grad.numpy() - want)) <= 2e-5 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("max_log2", [30, 9])
+def test_gradient_graph_equals_eager(qce, h, max_log2):
+    # the captured forward + reverse passes, replayed per bitstring, give
+    # the eager runner's probabilities and Jacobian bit for bit (the same
+    # kernels in the same order); max_log2 = 9 slices the network, which
+    # also fixes sliced labels on some <x| leaves
+    from paper_2303_08989_amd import tn
+    from paper_2303_08989_amd.grad import GradientGraph
+    c0 = synth.grid_circuit(3, 4, 8, seed=2, pattern="ABCDCDAB")
+    th = synth.coupler_thetas(c0["n_couplers"], seed=3)
+    c = synth.with_thetas(c0, th)
+    run, plan = _runner(qce, h, c, max_log2=max_log2)
+    if max_log2 == 9:
+        from paper_2303_08989_amd.executor import CircuitPlan
+        wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
+        plan = CircuitPlan(c, path=plan.path, sliced=list(plan.sliced) + wires[:1])
+        from paper_2303_08989_amd.grad import GradientRunner
+        run = GradientRunner(h, plan)
+    xs = synth.random_bitstrings(12, 5, seed=4)
+    p_e, a_e, J_e = run.probabilities_and_jacobian(th, xs)
+    gg = GradientGraph(plan, th, mode="auto")
+    try:
+        if max_log2 == 9:
+            assert any(f is not None for _, f, _ in gg.xslots)
+        p_g, a_g, J_g = gg.probabilities_and_jacobian(xs)
+        assert np.array_equal(a_g, a_e) and np.array_equal(J_g, J_e)
+        # the same angles, again, after other replays
+        _, a_g2, J_g2 = gg.probabilities_and_jacobian(xs[::-1])
+        assert np.array_equal(a_g2, a_e[::-1]) and np.array_equal(J_g2, J_e[::-1])
+    finally:
+        gg.close()
