@@ -78,6 +78,7 @@ class GradientRunner:
         self.device = device
         self.h = handle
         self.flops = 0.0           # 8mnk of every contraction issued (forward and reverse)
+        self.last_pass_calls = 0   # upper bound on the contraction calls of the last pass
         self.plan = plan
         circ = plan.circuit
         self.n = circ["n"]
@@ -147,21 +148,56 @@ class GradientRunner:
         self._pass(vals, dvals, slice_ids, acc_a, acc_d)
         return acc_a, acc_d
 
-    def _pass(self, vals, dvals, slice_ids, acc_a, acc_d):
+    def _levels(self):
+        """Forward steps grouped by tree level (a step is one level above its
+        children) and reverse steps grouped by depth below the root: the
+        steps of one group are independent of each other."""
+        p = self.plan
+        L = len(p.label_sets)
+        lev = [0] * L
+        fwd = {}
+        for s, (a, b) in enumerate(p.path):
+            lev.append(1 + max(lev[a], lev[b]))
+            fwd.setdefault(lev[-1], []).append(s)
+        depth = {L + len(p.path) - 1: 0}
+        rev = {}
+        for s in range(len(p.path) - 1, -1, -1):
+            d = depth[L + s]
+            rev.setdefault(d, []).append(s)
+            for ch in p.path[s]:
+                depth[ch] = d + 1
+        return [fwd[k] for k in sorted(fwd)], [rev[k] for k in sorted(rev)]
+
+    def _pass(self, vals, dvals, slice_ids, acc_a, acc_d, grouped=True):
         """Every device operation of one bitstring: for each slice the
         forward pass (keeping the checkpoints) and the reverse pass, adding
         the slice's amplitude to acc_a and each fSim occurrence's
         derivative to its coupler's row of acc_d (FP64, on the device).
         The sequence of calls depends only on the plan, not on the leaf
-        values, so it can be captured once and replayed."""
+        values, so it can be captured once and replayed.
+
+        ``grouped``: the independent steps of each forward tree level and of
+        each reverse depth run inside one library group, so their small
+        contractions share one launch.  A grouped result exists only once
+        its group has ended, so the derivative contraction of an fSim
+        occurrence runs in the next group and its FP64 accumulation after
+        that group."""
         import paper_2303_08989_amd as qce
+        from contextlib import nullcontext
         torch = self.torch
         p = self.plan
         L = len(p.label_sets)
         pos = {lab: i for i, lab in enumerate(p.sliced)}
         if slice_ids is None:
             slice_ids = range(p.n_slices)
+        use_groups = grouped and self.device != "cpu"
+        fwd_levels, rev_levels = self._levels() if p.path else ([], [])
+
+        def group():
+            return qce.group(self.h) if use_groups else nullcontext()
+
         one = torch.ones((), dtype=torch.complex64, device=self.device)
+        calls = 0
         for sigma in slice_ids:
             v = {lab: (sigma >> i) & 1 for lab, i in pos.items()}
 
@@ -174,45 +210,60 @@ class GradientRunner:
             if not p.path:
                 qce.accumulate_f64(self.h, leaf(0).reshape(-1)[:1], acc_a)
                 continue
+            calls += 2 * len(p.path) + len(self.fsim_leaf)     # at most, per slice
             # forward, keeping every intermediate (the checkpoints)
             node_val, node_lab = {}, {i: tuple(p.labels[i]) for i in range(L)}
-            for s, (a, b) in enumerate(p.path):
-                ta = leaf(a) if a < L else node_val[a]
-                tb = leaf(b) if b < L else node_val[b]
-                la, lb = node_lab[a], node_lab[b]
-                shared = set(la) & set(lb)
-                lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
-                node_lab[L + s] = tuple(lc)
-                node_val[L + s] = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
-                self.flops += _flops(ta, tb, la, lb)
+            for level in fwd_levels:
+                with group():
+                    for s in level:
+                        a, b = p.path[s]
+                        ta = leaf(a) if a < L else node_val[a]
+                        tb = leaf(b) if b < L else node_val[b]
+                        la, lb = node_lab[a], node_lab[b]
+                        shared = set(la) & set(lb)
+                        lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
+                        node_lab[L + s] = tuple(lc)
+                        node_val[L + s] = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
+                        self.flops += _flops(ta, tb, la, lb)
             root = L + len(p.path) - 1
             qce.accumulate_f64(self.h, node_val[root].reshape(-1)[:1], acc_a)
-            # reverse pass
+            # reverse pass, one group per depth below the root
             adj = {root: one}
-            for s in range(len(p.path) - 1, -1, -1):
-                node = L + s
-                E = adj.pop(node, None)
-                a, b = p.path[s]
-                if E is not None:
-                    for ch, other in ((a, b), (b, a)):
-                        if not self.has_param[ch]:
+            pending = []          # (E of an fSim leaf, leaf) awaiting its derivative contraction
+            for level in rev_levels + [[]]:
+                sg = []
+                with group():
+                    for E_g, g in pending:
+                        dG = dvals[g][key(g)]
+                        sg.append((qce.contract(self.h, E_g, list(node_lab[g]), dG, list(node_lab[g]), []),
+                                   self.fsim_leaf[g][0]))
+                    pending = []
+                    for s in level:
+                        node = L + s
+                        E = adj.pop(node, None)
+                        a, b = p.path[s]
+                        if E is None:
                             continue
-                        t_other = leaf(other) if other < L else node_val[other]
-                        E_ch = qce.contract(self.h, E, list(node_lab[node]), t_other,
-                                            list(node_lab[other]), list(node_lab[ch]))
-                        self.flops += _flops(E, t_other, node_lab[node], node_lab[other])
-                        if ch < L:
-                            cpl, _ = self.fsim_leaf[ch]
-                            dG = dvals[ch][key(ch)]
-                            s_g = qce.contract(self.h, E_ch, list(node_lab[ch]), dG,
-                                               list(node_lab[ch]), [])
-                            qce.accumulate_f64(self.h, s_g.reshape(-1)[:1], acc_d[cpl])
-                        else:
-                            adj[ch] = E_ch
-                # the children's values are no longer needed
-                node_val.pop(a, None)
-                node_val.pop(b, None)
+                        for ch, other in ((a, b), (b, a)):
+                            if not self.has_param[ch]:
+                                continue
+                            t_other = leaf(other) if other < L else node_val[other]
+                            E_ch = qce.contract(self.h, E, list(node_lab[node]), t_other,
+                                                list(node_lab[other]), list(node_lab[ch]))
+                            self.flops += _flops(E, t_other, node_lab[node], node_lab[other])
+                            if ch < L:
+                                pending.append((E_ch, ch))
+                            else:
+                                adj[ch] = E_ch
+                for s_g, cpl in sg:
+                    qce.accumulate_f64(self.h, s_g.reshape(-1)[:1], acc_d[cpl])
+                # the forward values this depth consumed are no longer needed
+                for s in level:
+                    a, b = p.path[s]
+                    node_val.pop(a, None)
+                    node_val.pop(b, None)
             node_val.clear()
+        self.last_pass_calls = calls
 
     def probabilities_and_jacobian(self, thetas, bitstrings, slice_ids=None):
         """p_x = |a_x|^2 (float64, shape (X,)), the amplitudes (complex128)
@@ -285,6 +336,9 @@ class GradientGraph:
         self._upload(0)
         self.run._pass(vals, dvals, slice_ids, self.acc_a, self.acc_d)   # warm-up: workspace, allocator
         torch.cuda.synchronize()
+        # descriptor room for every group of one captured pass (a recorded
+        # contraction takes under 1 KB of descriptors)
+        qce.group_reset(self.h, (self.run.last_pass_calls << 10) + (1 << 20))
         self.run.flops = 0.0
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
