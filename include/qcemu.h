@@ -184,9 +184,9 @@ size_t qce_cgemm_batched_workspace_size(int64_t m, int64_t n, int64_t k, int64_t
  * handle's mode:
  *   - AUTO: exponent statistics of A and B (every element, Sec. 4 first
  *     strategy), the two-stage rule of Sec. 4.1 extended by BF16X3 and FP32
- *     levels, and device-side dispatch: all candidate kernels are enqueued
- *     and those not selected return at once after reading the device mode
- *     flag (Sec. 4.2).  No size policy applies here.
+ *     levels, and device-side dispatch (Sec. 4.2): the split launch and the
+ *     GEMM launch each read the device mode flag and run the selected mode,
+ *     with no device-to-host transfer.  No size policy applies here.
  *   - a forced mode runs that mode without statistics (FP16X2_SCALED still
  *     takes statistics to find its shifts).
  * op(X) = X (QCE_OP_N), X^T (QCE_OP_T) or X^H (QCE_OP_C).
@@ -289,9 +289,10 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
  * contractions of one group must be independent (none reads another's
  * output), the operands of a recorded contraction must stay allocated and
  * unchanged until qce_group_end has been enqueued (it reads them then), and
- * a recorded output holds its value only after that launch.  The batched counterpart, for launch-bound streams of
- * tiny contractions, of the grouped launch a sliced network needs
- * (Sec. 5.3 slices, irregular shapes of Sec. 5.1.2).
+ * a recorded output holds its value only after that launch.  This is the
+ * grouped launch for launch-bound streams of tiny contractions that a
+ * sliced network produces (Sec. 5.3 slices, irregular shapes of
+ * Sec. 5.1.2).
  *
  * Descriptors go to a device area owned by the handle through a pinned
  * host mirror; both are reused only after the stream has drained them.
@@ -378,9 +379,9 @@ qce_status qce_split(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 
 /* ---------------------------------------------------------------------- */
 
 /*
- * Phases a call is broken into.  GEMM_* count only launches whose kernel
- * was the selected one; launches that returned at once after reading the
- * mode flag (Sec. 4.2) are counted under GEMM_SKIPPED.
+ * Phases a call is broken into.  An AUTO GEMM launch is credited to the
+ * mode it read from the device flag.  GEMM_SKIPPED stays in the enumeration
+ * (and in qce_timing) but is never recorded: no launch returns unused.
  */
 typedef enum {
     QCE_PHASE_STATS = 0,   /* exponent statistics and mode selection */
