@@ -152,6 +152,21 @@ def run_gradients(h, args, torch, qce, synth):
     plan = CircuitPlan(c, max_log2=28, restarts=40, alphas=(1.0, 1.5, 2.0), noises=(0.05,))
     t_plan = time.perf_counter() - t0
     xs = synth.random_bitstrings(30, args.c5_bitstrings, seed=6)
+    from paper_2303_08989_amd.grad import GradientGraph
+    if args.graph_only:
+        gg = GradientGraph(plan, th, mode="auto")
+        gg.probabilities_and_jacobian(xs[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_g, _, _ = gg.probabilities_and_jacobian(xs)
+        dt_g = time.perf_counter() - t0
+        flops = gg.flops_per_pass * len(xs)
+        gg.close()
+        return {"workload": f"30-qubit 5x6 grid, depth 14, ABCDCDAB; {ne} fSim angles; {len(xs)} bitstrings; "
+                            "captured passes only",
+                "graph_seconds": round(dt_g, 4), "graph_gradients_per_s": round(len(xs) / dt_g, 2),
+                "graph_effective_tflops": round(flops / dt_g / 1e12, 2),
+                "mean_probability": float(np.mean(p_g))}
     run = GradientRunner(h, plan)
     h.set_mode("auto")
     run.probabilities_and_jacobian(th, xs[:1])            # warm-up (workspace, allocations)
@@ -168,7 +183,6 @@ def run_gradients(h, args, torch, qce, synth):
     gpu_ms_g = {k: round(v[0], 2) for k, v in tmg.items() if k != "gemms_by_mode" and v[1]}
     flops = run.flops
     # the same passes captured once and replayed per bitstring
-    from paper_2303_08989_amd.grad import GradientGraph
     gg = GradientGraph(plan, th, mode="auto")
     gg.probabilities_and_jacobian(xs[:1])
     torch.cuda.synchronize()
@@ -233,31 +247,44 @@ def run_batching(h, args, torch, qce, synth):
     bx = BatchedExecutor(h, plan, nb)
     ex = Executor(h, plan)
     ids = range(1 << nb)
-    # looped slices
-    ex.amplitude(x, range(4))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    a_loop = ex.amplitude(x, ids)
-    torch.cuda.synchronize()
-    t_loop = time.perf_counter() - t0
-    # one batched pass: contraction by contraction, then with each tree
-    # level's small contractions in one grouped launch
-    cache = {}
+    n = len(ids)
     reps = 5
-    bx.amplitude(x, [0], cache=cache, grouped=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        a_u = bx.amplitude(x, [0], cache=cache, grouped=False)
-    torch.cuda.synchronize()
-    t_ungrouped = (time.perf_counter() - t0) / reps
-    bx.amplitude(x, [0], cache=cache)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        a_b = bx.amplitude(x, [0], cache=cache)
-    torch.cuda.synchronize()
-    t_batched = (time.perf_counter() - t0) / reps
+    shapes = plan.gemm_shapes
+    out = {
+        "workload": f"53-qubit network of the 53-qubit section sliced to max intermediate 2^{plan.max_log2} "
+                    f"({len(plan.sliced)} sliced labels); slice ids 0..{n - 1} ({nb} labels varied), "
+                    "AUTO with size policy",
+        "plan_seconds": round(t_plan, 1),
+        "per_slice_gemm_log2_dims_range": [min(min(s3) for s3 in shapes), max(max(s3) for s3 in shapes)],
+        "contractions_per_pass": len(plan.path),
+        "batched_max_intermediate_log2": bx.max_intermediate(),
+        "tree_levels": len(bx._levels()),
+    }
+    if not args.graph_only:
+        # looped slices
+        ex.amplitude(x, range(4))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a_loop = ex.amplitude(x, ids)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t0
+        # one batched pass: contraction by contraction, then with each tree
+        # level's small contractions in one grouped launch
+        cache = {}
+        bx.amplitude(x, [0], cache=cache, grouped=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            a_u = bx.amplitude(x, [0], cache=cache, grouped=False)
+        torch.cuda.synchronize()
+        t_ungrouped = (time.perf_counter() - t0) / reps
+        bx.amplitude(x, [0], cache=cache)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            a_b = bx.amplitude(x, [0], cache=cache)
+        torch.cuda.synchronize()
+        t_batched = (time.perf_counter() - t0) / reps
     # graph replay
     gp = GraphPass(plan, nb, outer=0)
     gp.amplitude(x)
@@ -267,33 +294,27 @@ def run_batching(h, args, torch, qce, synth):
         a_g = gp.amplitude(x)
     torch.cuda.synchronize()
     t_graph = (time.perf_counter() - t0) / reps
-    v_loop = complex(*a_loop.cpu().numpy())
-    v_b = complex(*a_b.cpu().numpy())
     v_g = complex(*a_g.cpu().numpy())
     gp.close()
-    shapes = plan.gemm_shapes
-    n = len(ids)
-    return {
-        "workload": f"53-qubit network of the 53-qubit section sliced to max intermediate 2^{plan.max_log2} "
-                    f"({len(plan.sliced)} sliced labels); slice ids 0..{n - 1} ({nb} labels varied), "
-                    "AUTO with size policy",
-        "plan_seconds": round(t_plan, 1),
-        "per_slice_gemm_log2_dims_range": [min(min(s3) for s3 in shapes), max(max(s3) for s3 in shapes)],
-        "contractions_per_pass": len(plan.path),
-        "batched_max_intermediate_log2": bx.max_intermediate(),
+    out.update({"graph_seconds": round(t_graph, 5), "graph_slices_per_s": round(n / t_graph, 1)})
+    if args.graph_only:
+        out["partial_amplitude"] = [v_g.real, v_g.imag]
+        return out
+    v_loop = complex(*a_loop.cpu().numpy())
+    v_b = complex(*a_b.cpu().numpy())
+    out.update({
         "looped_seconds": round(t_loop, 4), "looped_slices_per_s": round(n / t_loop, 1),
         "batched_ungrouped_seconds": round(t_ungrouped, 5),
         "batched_ungrouped_slices_per_s": round(n / t_ungrouped, 1),
-        "tree_levels": len(bx._levels()),
         "batched_seconds": round(t_batched, 5), "batched_slices_per_s": round(n / t_batched, 1),
-        "graph_seconds": round(t_graph, 5), "graph_slices_per_s": round(n / t_graph, 1),
         "speedup_batched_vs_looped": round(t_loop / t_batched, 2),
         "speedup_graph_vs_looped": round(t_loop / t_graph, 2),
         "rel_diff_batched_vs_looped": abs(v_b - v_loop) / max(abs(v_loop), 1e-300),
         "rel_diff_grouped_vs_ungrouped": abs(v_b - complex(*a_u.cpu().numpy())) / max(abs(v_loop), 1e-300),
         "graph_equals_batched": v_g == v_b,
         "partial_amplitude": [v_b.real, v_b.imag],
-    }
+    })
+    return out
 
 
 def run_random_tn(h, args, torch, qce, synth):
@@ -489,6 +510,8 @@ def main():
     ap.add_argument("--gemm-only", action="store_true",
                     help="only the CGEMM step: skip the circuit, irregular, gradient and batching sections")
     ap.add_argument("--c5-bitstrings", type=int, default=64, help="bitstrings of the gradient section")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="the batching and gradient sections run only their captured-graph legs (for profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
