@@ -191,6 +191,15 @@ def run_gradients(h, args, torch, qce, synth):
     dt_g = time.perf_counter() - t0
     graph_equal = bool(np.array_equal(J_g, J) and np.array_equal(amps_g, amps))
     gg.close()
+    # the same under the paper's size thresholds (2048, 512): 512 <= min <
+    # 2048 goes to the wide-exponent split without statistics
+    gg5 = GradientGraph(plan, th, mode="auto", size_policy=(2048, 512))
+    gg5.probabilities_and_jacobian(xs[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, J_5 = gg5.probabilities_and_jacobian(xs)
+    dt_5 = time.perf_counter() - t0
+    gg5.close()
     # the same Jacobian rows on the plain FP32 path
     nchk = min(4, len(xs))
     h.set_mode("fp32")
@@ -222,6 +231,9 @@ def run_gradients(h, args, torch, qce, synth):
         "graph_seconds": round(dt_g, 4), "graph_gradients_per_s": round(len(xs) / dt_g, 2),
         "graph_effective_tflops": round(flops / dt_g / 1e12, 2),
         "graph_equals_eager": graph_equal,
+        "graph_paper_size_policy": {"gradients_per_s": round(len(xs) / dt_5, 2),
+                              "jacobian_rel_diff_vs_fp32": float(np.linalg.norm(J_5[:nchk] - J32) /
+                                                                 max(np.linalg.norm(J32), 1e-300))},
         "jacobian_rel_diff_auto_vs_fp32": rel_auto_fp32,
         "fd_check_max_rel_err_fp32_h1e-3": fd_err,
         "mean_probability": float(np.mean(p)),
@@ -386,7 +398,7 @@ def run_random_tn(h, args, torch, qce, synth):
     finally:
         h.set_tolerance(0.1, 0.0)
         h.set_mode("auto")
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
     return out
 
 
@@ -439,9 +451,16 @@ def run_circuits(h, args, torch, qce, synth):
     res = {}
     # AUTO at the default t = 0.1, AUTO at the paper's looser t = 0.5, and
     # the forced-FP32 baseline
-    for key, mode, t in (("auto", "auto", 0.1), ("auto_t05", "auto", 0.5), ("fp32", "fp32", 0.1)):
+    default_policy = h.size_policy()
+    # AUTO (t = 0.1, the library's size policy), AUTO at the paper's looser
+    # t = 0.5, AUTO under the paper's own size thresholds (2048, 512), and
+    # the forced-FP32 baseline
+    for key, mode, t, pol in (("auto", "auto", 0.1, default_policy), ("auto_t05", "auto", 0.5, default_policy),
+                              ("paper_size_policy", "auto", 0.1, (2048, 512)),
+                              ("fp32", "fp32", 0.1, default_policy)):
         h.set_mode(mode)
         h.set_tolerance(t, 0.0)
+        h.set_size_policy(*pol)
         ex3 = Executor(h, plan3)
         vec = torch.empty(nsl, dtype=torch.complex64, device="cuda")
         ex3.amplitude(x3, ids, slice_out=vec)          # warm-up (allocations, workspace)
@@ -457,6 +476,7 @@ def run_circuits(h, args, torch, qce, synth):
         res[key] = dict(seconds=dt, acc=acc.cpu().numpy(), vec=vec, timing=tm)
     h.set_mode("auto")
     h.set_tolerance(0.1, 0.0)
+    h.set_size_policy(*default_policy)
 
     def fidelity_vs_fp32(key):
         fid = qce.fidelity_terms(h, res[key]["vec"], res["fp32"]["vec"]).cpu().numpy()
@@ -485,6 +505,12 @@ def run_circuits(h, args, torch, qce, synth):
         "amplitudes_per_s_one_gpu_extrapolated": 1.0 / (t64 / share),
         "gpu_ms_by_phase": gpu_ms, "gemms_by_mode": tm["gemms_by_mode"],
         "largest_gemm_log2_mnk": [list(x) for x in big],
+        "size_policy": list(default_policy),
+        "paper_size_policy": {"size_policy": [2048, 512],
+                              "seconds": round(res["paper_size_policy"]["seconds"], 4),
+                              "speedup_vs_fp32": round(res["fp32"]["seconds"] / res["paper_size_policy"]["seconds"], 3),
+                              "fidelity_vs_fp32_over_slices": fidelity_vs_fp32("paper_size_policy"),
+                              "gemms_by_mode": res["paper_size_policy"]["timing"]["gemms_by_mode"]},
         "auto_t05": {"seconds": round(res["auto_t05"]["seconds"], 4),
                      "speedup_vs_fp32": round(res["fp32"]["seconds"] / res["auto_t05"]["seconds"], 3),
                      "fidelity_vs_fp32_over_slices": fidelity_vs_fp32("auto_t05"),

@@ -122,7 +122,7 @@ typedef struct {
  *   QCE_MODE           auto | fp16x2 | fp16x2s | bf16x3 | fp32
  *   QCE_UNDERFLOW_TOL  t  in [0, 1], default 0.1 (AUTO-0.1, Sec. 5.2)
  *   QCE_BF16X3_TOL     t3 in [0, 1], default 0
- *   QCE_AUTO_MIN_DIM   size policy threshold for statistics, default 2048
+ *   QCE_AUTO_MIN_DIM   size policy threshold for statistics, default 512
  *   QCE_EMUL_MIN_DIM   size policy threshold for emulation, default 512
  * The stream is the device's null stream until qce_set_stream.
  * Errors: INVALID_VALUE (h NULL, bad device or bad environment value),
@@ -158,8 +158,13 @@ qce_status qce_set_underflow_tolerance(qce_handle *h, double t, double t3);
  * otherwise min(m, n, k) >= emul_min -> BF16X3 (the wide-exponent emulation,
  * as the paper uses TF32TCEC there); otherwise FP32.
  * Requires 0 <= emul_min <= auto_min, else INVALID_VALUE.
+ * Default auto_min = emul_min = 512: the thresholds are a calibration of
+ * statistics cost against GEMM time; the paper's (2048, 512) are its A100
+ * values, and on gfx950 statistics already pay off from 512 (so the BF16X3
+ * tier is empty by default).
  */
 qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min);
+qce_status qce_get_size_policy(const qce_handle *h, int64_t *auto_min, int64_t *emul_min);
 
 /*
  * Hand the library a caller-owned device workspace of `bytes` bytes (NULL,0

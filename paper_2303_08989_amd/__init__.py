@@ -58,6 +58,9 @@ class Handle:
         self._h = ctypes.c_void_p()
         _check(None, self.lib.qce_create(ctypes.byref(self._h), self.device))
         self._stream = None
+        # the policy the handle was created with (library default or the
+        # QCE_AUTO_MIN_DIM / QCE_EMUL_MIN_DIM environment), to restore it
+        self.default_size_policy = self.size_policy()
 
     def _bind_stream(self):
         torch = _torch()
@@ -91,6 +94,12 @@ class Handle:
 
     def set_size_policy(self, auto_min, emul_min):
         _check(self._h, self.lib.qce_set_size_policy(self._h, int(auto_min), int(emul_min)))
+
+    def size_policy(self):
+        """(auto_min, emul_min) of the size policy (Sec. 4.3)."""
+        a, e = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._h, self.lib.qce_get_size_policy(self._h, ctypes.byref(a), ctypes.byref(e)))
+        return a.value, e.value
 
     def set_workspace(self, tensor):
         if tensor is None:

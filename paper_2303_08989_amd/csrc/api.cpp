@@ -18,7 +18,9 @@ struct qce_handle {
     hipStream_t stream = nullptr;
     qce_mode mode = QCE_MODE_AUTO;
     double t = 0.1, t3 = 0.0;
-    int64_t auto_min = 2048, emul_min = 512;
+    // size policy (Sec. 4.3) calibrated on gfx950: statistics pay off from
+    // min(m, n, k) = 512 (the paper's A100 values are 2048 and 512)
+    int64_t auto_min = 512, emul_min = 512;
     DevState *st = nullptr;        // device
     DevState *dec_base = nullptr;  // decisions of the last call (st, or a batch's states in the workspace)
     int dec_count = 1;
@@ -679,6 +681,13 @@ qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min
     if (!h || emul_min < 0 || emul_min > auto_min) return QCE_ERR_INVALID_VALUE;
     h->auto_min = auto_min;
     h->emul_min = emul_min;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_get_size_policy(const qce_handle *h, int64_t *auto_min, int64_t *emul_min) {
+    if (!h || !auto_min || !emul_min) return QCE_ERR_INVALID_VALUE;
+    *auto_min = h->auto_min;
+    *emul_min = h->emul_min;
     return QCE_SUCCESS;
 }
 

@@ -302,12 +302,14 @@ class GradientGraph:
     capture.  The accumulators are cleared by fill kernels inside the graph
     (no memset is captured)."""
 
-    def __init__(self, plan, thetas, device=0, mode="auto", slice_ids=None):
+    def __init__(self, plan, thetas, device=0, mode="auto", slice_ids=None, size_policy=None):
         import torch
         import paper_2303_08989_amd as qce
         self.torch = torch
         self.h = qce.Handle(device)
         self.h.set_mode(mode)            # fixed for the captured passes
+        if size_policy is not None:
+            self.h.set_size_policy(*size_policy)
         self.run = GradientRunner(self.h, plan)
         self.n = self.run.n
         self.n_couplers = self.run.n_couplers

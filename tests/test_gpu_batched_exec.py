@@ -65,7 +65,7 @@ def test_batched_equals_looped_and_oracle(qce, h, n_batch, mode):
         got = np.array([complex(*bx.amplitude(x).cpu().numpy()) for x in xs])
         loop = np.array([complex(*ex.amplitude(x).cpu().numpy()) for x in xs])
     finally:
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
         h.set_mode("auto")
     want = oracle.statevector_amplitudes(_rounded(c), xs)
     assert oracle.fidelity(got, want) >= 1 - 1e-6

@@ -98,7 +98,7 @@ def test_contract_integer_exact(qce, h, mode, seed):
         C = qce.contract(h, torch.from_numpy(net["A"]).to("cuda"), net["la"],
                          torch.from_numpy(net["B"]).to("cuda"), net["lb"], net["lc"]).cpu().numpy()
     finally:
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
         h.set_mode("auto")
     want = oracle.zcontract(net["A"], net["la"], net["B"], net["lb"], net["lc"])
     assert np.array_equal(C.astype(np.complex128), want)
@@ -182,7 +182,7 @@ def _amplitudes(qce, h, circuit, xs, max_log2=30, mode="fp32", slice_ids=None, v
             v = acc.cpu().numpy()
             out.append(complex(v[0], v[1]))
     finally:
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
         h.set_mode("auto")
     return np.array(out), plan
 
@@ -273,7 +273,7 @@ def test_contract_batch_labels_integer_exact(qce, h, mode, case):
         C = qce.contract(h, torch.from_numpy(A).to("cuda"), la, torch.from_numpy(B).to("cuda"), lb, lc)
         C = C.cpu().numpy()
     finally:
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
         h.set_mode("auto")
     assert np.array_equal(C.astype(np.complex128), oracle.zcontract(A, la, B, lb, lc))
 
@@ -290,3 +290,22 @@ def test_contract_batch_more_than_one_launch(qce, h):
     C = qce.contract(h, torch.from_numpy(A).to("cuda"), la, torch.from_numpy(B).to("cuda"), lb, lc).cpu().numpy()
     want = np.matmul(A.reshape(-1, 2, 2).astype(np.complex128), B.reshape(-1, 2, 2).astype(np.complex128))
     assert np.array_equal(C.reshape(-1, 2, 2).astype(np.complex128), want)
+
+
+def test_size_policy_default_and_roundtrip(qce, h):
+    # AUTO from min(m, n, k) >= 512 by default (gfx950 calibration of the
+    # Sec. 4.3 thresholds), settable and readable; invalid orders rejected
+    fresh = qce.Handle(0)
+    try:
+        assert fresh.size_policy() == (512, 512) == fresh.default_size_policy
+    finally:
+        fresh.close()
+    prev = h.size_policy()
+    try:
+        h.set_size_policy(2048, 512)
+        assert h.size_policy() == (2048, 512)
+        with pytest.raises(qce.QceError):
+            h.set_size_policy(256, 512)
+        assert h.size_policy() == (2048, 512)
+    finally:
+        h.set_size_policy(*prev)

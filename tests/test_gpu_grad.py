@@ -50,7 +50,7 @@ def _with_mode(h, mode, fn):
     try:
         return fn()
     finally:
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
         h.set_mode("auto")
 
 

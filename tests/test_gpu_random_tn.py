@@ -93,7 +93,7 @@ def results(qce, h):
     finally:
         h.set_tolerance(0.1, 0.0)
         h.set_mode("auto")
-        h.set_size_policy(2048, 512)
+        h.set_size_policy(*h.default_size_policy)
     return out
 
 
