@@ -63,9 +63,9 @@ __device__ inline uint4 pack8(const uint16_t *v) {
 // row's whole slot in every plane (32 bytes per plane, 64 for FP32).
 // KCONTIG = false: a wave takes 64 consecutive rows of one chunk, so each
 // of its 16 loads reads 512 contiguous bytes and each plane's stores cover
-// 2 KB.  KCONTIG = true: a wave takes 16 rows x 4 consecutive chunks, so a
-// row's 64 k-values (512 bytes) are read by 4 lanes and each plane's stores
-// cover 512 contiguous bytes per chunk.
+// 2 KB.  KCONTIG = true: a block stages 64 rows x 64 k-values through LDS
+// (512-byte row runs in), then converts like the other layout (64
+// consecutive rows of one chunk per wave, 2 KB stores per plane).
 template <bool KCONTIG>
 __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
@@ -75,33 +75,57 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     x += (int64_t)blockIdx.z * xstride;
     panels += (int64_t)blockIdx.z * pstride;
     if (st) st += blockIdx.z;
+    constexpr int kK = 16;  // k-values per chunk row
+    float re[kK], im[kK];
     int64_t r, c;  // row and chunk
     if (KCONTIG) {
+        // A block takes 64 rows x 4 chunks (64 k-values).  The tile is read
+        // in 512-byte row runs (a wave reads one row per load) into LDS,
+        // whose rows are padded by one element so that a wave reading one
+        // k-value of 64 rows hits distinct banks; each thread then takes
+        // one chunk row, with waves on consecutive rows as in the other
+        // layout (whose panel stores are contiguous).
+        __shared__ float2 tile[64][64 + 1];
         const int64_t row_blocks = rows_pad / 64;
-        const int64_t b = blockIdx.x;
-        r = (b % row_blocks) * 64 + (threadIdx.x >> 2);
-        c = (b / row_blocks) * 4 + (threadIdx.x & 3);
+        const int64_t r0 = (int64_t)(blockIdx.x % row_blocks) * 64;
+        const int64_t c0 = (int64_t)(blockIdx.x / row_blocks) * 4;
+#pragma unroll
+        for (int i = 0; i < 64 * 64 / kThreads; ++i) {
+            const int e = i * kThreads + threadIdx.x;
+            const int tr = e >> 6, tq = e & 63;
+            const int64_t rr = r0 + tr, l = c0 * kK + tq;
+            float2 v = make_float2(0.f, 0.f);
+            if (rr < rows && l < k) v = x[l + rr * ldx];
+            tile[tr][tq] = v;
+        }
+        __syncthreads();
+        const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+        r = r0 + tr;
+        c = c0 + tc;
         if (c >= nchunks) return;
+#pragma unroll
+        for (int j = 0; j < kK; ++j) {
+            const float2 v = tile[tr][tc * kK + j];
+            re[j] = v.x;
+            im[j] = conj ? -v.y : v.y;
+        }
     } else {
         const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
         if (t >= rows_pad * nchunks) return;
         r = t % rows_pad;
         c = t / rows_pad;
+        const int64_t l0 = c * kK;
+#pragma unroll
+        for (int j = 0; j < kK; ++j) {
+            const int64_t l = l0 + j;
+            float2 v = make_float2(0.f, 0.f);
+            if (r < rows && l < k) v = x[r + l * ldx];
+            re[j] = v.x;
+            im[j] = conj ? -v.y : v.y;
+        }
     }
     const int mode = st ? st->mode : forced_mode;
     const int shift = st ? st->shift[which] : forced_shift;
-
-    constexpr int kK = 16;  // k-values per chunk row
-    float re[kK], im[kK];
-    const int64_t l0 = c * kK;
-#pragma unroll
-    for (int j = 0; j < kK; ++j) {
-        const int64_t l = l0 + j;
-        float2 v = make_float2(0.f, 0.f);
-        if (r < rows && l < k) v = KCONTIG ? x[l + r * ldx] : x[r + l * ldx];
-        re[j] = v.x;
-        im[j] = conj ? -v.y : v.y;
-    }
     const int64_t rb = r / kPanelRows;
     const int rin = (int)(r % kPanelRows);
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED) {
