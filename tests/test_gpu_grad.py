@@ -166,3 +166,31 @@ def test_gradient_graph_equals_eager(qce, h, max_log2):
         assert np.array_equal(a_g2, a_e[::-1]) and np.array_equal(J_g2, J_e[::-1])
     finally:
         gg.close()
+
+
+def test_gradient_graph_emulated_modes_equals_eager(qce, h):
+    # statistics and selection on every GEMM (size policy (0, 0)): the
+    # captured passes run the device-side mode flag, the split and the
+    # emulated GEMMs inside the graph and must still equal the eager runner
+    # under the same policy, bit for bit, replay after replay
+    from paper_2303_08989_amd.grad import GradientGraph
+    c0 = synth.grid_circuit(3, 4, 8, seed=2, pattern="ABCDCDAB")
+    th = synth.coupler_thetas(c0["n_couplers"], seed=3)
+    c = synth.with_thetas(c0, th)
+    run, plan = _runner(qce, h, c, max_log2=30)
+    xs = synth.random_bitstrings(12, 4, seed=6)
+    h.set_size_policy(0, 0)
+    try:
+        _, a_e, J_e = run.probabilities_and_jacobian(th, xs)
+    finally:
+        h.set_size_policy(*h.default_size_policy)
+    gg = GradientGraph(plan, th, mode="auto", size_policy=(0, 0))
+    try:
+        for _ in range(2):
+            _, a_g, J_g = gg.probabilities_and_jacobian(xs)
+            assert np.array_equal(a_g, a_e) and np.array_equal(J_g, J_e)
+    finally:
+        gg.close()
+    # and close to the plain-FP32 Jacobian
+    _, _, J32 = _with_mode(h, "fp32", lambda: run.probabilities_and_jacobian(th, xs))
+    assert np.max(np.abs(J_e - J32)) <= 1e-4 * np.max(np.abs(J32))
