@@ -290,13 +290,15 @@ def _combine(accs, n_couplers):
 
 
 class GradientGraph:
-    """The forward and reverse passes of ``GradientRunner`` for one angle
-    vector, captured once in a HIP graph and replayed per bitstring.
+    """The forward and reverse passes of ``GradientRunner`` captured once in
+    a HIP graph and replayed per bitstring and angle vector.
 
-    Only the <x| leaves (the last n) depend on the bitstring: each of their
-    device variants is a view of one buffer, refilled by one copy from
-    pinned memory before each replay (an event keeps the host from
-    rewriting the pinned buffer before the previous copy has run).  The
+    The <x| leaves (the last n) depend on the bitstring and the fSim leaves
+    and their derivatives on the angles: each device variant of those leaves
+    is a view of one of two buffers, refilled by one copy from pinned memory
+    before a replay (``_upload``) or on ``set_thetas`` (an event keeps the
+    host from rewriting a pinned buffer before its previous copy has run).
+    The
     graph owns its handle, so the workspace whose address the captured
     kernels hold is never reallocated; a warm-up pass sizes it before
     capture.  The accumulators are cleared by fill kernels inside the graph
@@ -333,6 +335,26 @@ class GradientGraph:
         self.xhost = torch.zeros(max(total, 1), dtype=torch.complex64, pin_memory=True)
         self.xdone = torch.cuda.Event()
         self.xdone.record()
+        # likewise every variant of the fSim leaves and of their derivatives:
+        # (leaf, 0 = gate / 1 = derivative, variant key, offset, elements)
+        tlayout, ttotal = [], 0
+        for i in sorted(self.run.fsim_leaf):
+            for which, src in ((0, vals), (1, dvals)):
+                for key, t in src[i].items():
+                    tlayout.append((i, which, key, ttotal, t.shape))
+                    ttotal += t.numel()
+        self.tbuf = torch.zeros(max(ttotal, 1), dtype=torch.complex64, device="cuda")
+        self.tslots = []
+        for i, which, key, off, shape in tlayout:
+            src = vals if which == 0 else dvals
+            size = int(np.prod(shape, dtype=np.int64))
+            view = self.tbuf[off:off + size].view(shape)
+            view.copy_(src[i][key])
+            src[i][key] = view
+            self.tslots.append((i, which, key, off, size))
+        self.thost = torch.zeros(max(ttotal, 1), dtype=torch.complex64, pin_memory=True)
+        self.tdone = torch.cuda.Event()
+        self.tdone.record()
         self.acc_a = torch.zeros(2, dtype=torch.float64, device="cuda")
         self.acc_d = torch.zeros((max(1, self.n_couplers), 2), dtype=torch.float64, device="cuda")
         self._upload(0)
@@ -364,6 +386,30 @@ class GradientGraph:
         self.xbuf.copy_(self.xhost[: self.xbuf.numel()], non_blocking=True)
         self.xdone.record()
 
+    def set_thetas(self, thetas):
+        """Angles for the following replays: the fSim leaves and their
+        derivatives are rebuilt on the host and uploaded in one copy (no
+        recapture)."""
+        from . import tn
+        th = np.asarray(thetas, dtype=np.float32)
+        p = self.run.plan
+        pos = {lab: i for i, lab in enumerate(p.sliced)}
+        leaves = tn.circuit_network(self.run._circuit_at(th), 0)
+        self.tdone.synchronize()          # the previous copy has read the pinned buffer
+        hv = self.thost.numpy()
+        for i, which, key, off, size in self.tslots:
+            labels = leaves[i][1]
+            if which == 0:
+                arr = leaves[i][0]
+            else:
+                cpl, phi = self.run.fsim_leaf[i]
+                arr = fsim_dtheta(float(th[cpl]), phi).astype(np.complex64).reshape(2, 2, 2, 2)
+            sl = [lab for lab in labels if lab in pos]
+            hv[off:off + size] = tn.fix_labels(arr, labels, dict(zip(sl, key))).reshape(-1)
+        self.tbuf.copy_(self.thost[: self.tbuf.numel()], non_blocking=True)
+        self.tdone.record()
+        self.thetas = th
+
     def amplitude_and_derivatives(self, x):
         """Replay for bitstring x: the device accumulators (a[2], D[E, 2]),
         valid until the next replay."""
@@ -371,9 +417,11 @@ class GradientGraph:
         self.graph.replay()
         return self.acc_a, self.acc_d
 
-    def probabilities_and_jacobian(self, bitstrings):
-        """As ``GradientRunner.probabilities_and_jacobian`` at the captured
-        angles."""
+    def probabilities_and_jacobian(self, bitstrings, thetas=None):
+        """As ``GradientRunner.probabilities_and_jacobian``, at ``thetas``
+        (uploaded first) or at the angles set last."""
+        if thetas is not None and not np.array_equal(np.asarray(thetas, dtype=np.float32), self.thetas):
+            self.set_thetas(thetas)
         accs = []
         for x in bitstrings:
             a, d = self.amplitude_and_derivatives(x)
@@ -389,13 +437,18 @@ class GradientGraph:
 
 def circuit_probabilities(runner, thetas, bitstrings, slice_ids=None):
     """p_x(theta) for the bitstrings as a differentiable torch function of
-    the FP32 angle tensor ``thetas`` (one per coupler)."""
+    the FP32 angle tensor ``thetas`` (one per coupler).  ``runner`` is a
+    ``GradientRunner`` (eager passes) or a ``GradientGraph`` (captured
+    passes; ``slice_ids`` are then the ones it was captured with)."""
     import torch
 
     class _Probabilities(torch.autograd.Function):
         @staticmethod
         def forward(ctx, th):
-            p, _, J = runner.probabilities_and_jacobian(th.detach().cpu().numpy(), bitstrings, slice_ids)
+            if isinstance(runner, GradientGraph):
+                p, _, J = runner.probabilities_and_jacobian(bitstrings, thetas=th.detach().cpu().numpy())
+            else:
+                p, _, J = runner.probabilities_and_jacobian(th.detach().cpu().numpy(), bitstrings, slice_ids)
             ctx.save_for_backward(torch.from_numpy(J))
             return torch.from_numpy(p).to(th.device)
 

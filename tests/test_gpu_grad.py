@@ -194,3 +194,49 @@ def test_gradient_graph_emulated_modes_equals_eager(qce, h):
     # and close to the plain-FP32 Jacobian
     _, _, J32 = _with_mode(h, "fp32", lambda: run.probabilities_and_jacobian(th, xs))
     assert np.max(np.abs(J_e - J32)) <= 1e-4 * np.max(np.abs(J32))
+
+
+@pytest.mark.parametrize("max_log2", [30, 9])
+def test_gradient_graph_new_angles_without_recapture(qce, h, max_log2):
+    # one captured graph, angles changed by set_thetas (fSim leaves and
+    # derivatives re-uploaded, sliced variants included): equal to the eager
+    # runner at each angle vector, bit for bit, and back again
+    from paper_2303_08989_amd.grad import GradientGraph
+    c0 = synth.grid_circuit(3, 4, 8, seed=2, pattern="ABCDCDAB")
+    ne = c0["n_couplers"]
+    th1 = synth.coupler_thetas(ne, seed=3)
+    th2 = synth.coupler_thetas(ne, seed=11)
+    run, plan = _runner(qce, h, synth.with_thetas(c0, th1), max_log2=max_log2)
+    xs = synth.random_bitstrings(12, 3, seed=5)
+    gg = GradientGraph(plan, th1, mode="auto")
+    try:
+        for th in (th2, th1, th2):
+            _, a_e, J_e = run.probabilities_and_jacobian(th, xs)
+            _, a_g, J_g = gg.probabilities_and_jacobian(xs, thetas=th)
+            assert np.array_equal(a_g, a_e) and np.array_equal(J_g, J_e)
+    finally:
+        gg.close()
+
+
+def test_autograd_function_on_a_graph(qce, h):
+    # the autograd function driven by a GradientGraph over several angle
+    # updates matches the FP64 oracle gradient at each
+    from paper_2303_08989_amd.grad import GradientGraph, circuit_probabilities
+    from paper_2303_08989_amd.executor import CircuitPlan
+    base = synth.grid_circuit(2, 3, 5, seed=2, pattern="ABCD")
+    ne = base["n_couplers"]
+    xs = synth.random_bitstrings(6, 4, seed=3)
+    th0 = synth.coupler_thetas(ne, seed=2)
+    plan = CircuitPlan(synth.with_thetas(base, th0), max_log2=30, restarts=2)
+    gg = GradientGraph(plan, th0, mode="auto")
+    try:
+        w = torch.tensor([1.0, -2.0, 0.5, 3.0], dtype=torch.float64)
+        for seed in (2, 7):
+            th = synth.coupler_thetas(ne, seed=seed)
+            t = torch.tensor(th, requires_grad=True)
+            (circuit_probabilities(gg, t, xs) * w).sum().backward()
+            _, J_ref = oracle.probability_theta_gradient(_rounded(synth.with_thetas(base, th)), xs, ne)
+            want = J_ref.T @ w.numpy()
+            assert np.max(np.abs(t.grad.numpy() - want)) <= 2e-5 * np.max(np.abs(want))
+    finally:
+        gg.close()
