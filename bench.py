@@ -307,8 +307,21 @@ def run_batching(h, args, torch, qce, synth):
     torch.cuda.synchronize()
     t_graph = (time.perf_counter() - t0) / reps
     v_g = complex(*a_g.cpu().numpy())
+    # the same graph over several outer values (8 x 1024 slice ids): the
+    # leaves carrying outer labels are re-uploaded at every switch
+    n_out = min(8, gp.n_outer)
+    sums = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for o in range(n_out):
+        sums.append(gp.amplitude(x, outer=o).clone())
+    torch.cuda.synchronize()
+    t_outer = time.perf_counter() - t0
+    gp.set_outer(0)
     gp.close()
-    out.update({"graph_seconds": round(t_graph, 5), "graph_slices_per_s": round(n / t_graph, 1)})
+    out.update({"graph_seconds": round(t_graph, 5), "graph_slices_per_s": round(n / t_graph, 1),
+                "graph_outer_values": n_out, "graph_outer_seconds": round(t_outer, 5),
+                "graph_outer_slices_per_s": round(n * n_out / t_outer, 1)})
     if args.graph_only:
         out["partial_amplitude"] = [v_g.real, v_g.imag]
         return out

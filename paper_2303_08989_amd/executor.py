@@ -308,11 +308,12 @@ class BatchedExecutor:
 
 
 class GraphPass:
-    """One batched pass (``BatchedExecutor``, outer value ``outer``) captured
-    once in a HIP graph and replayed per bitstring.  Only the <x| leaves
-    change between bitstrings: they are overwritten in place (one
-    host-to-device copy from pinned memory, outside the graph) before each
-    replay.
+    """One batched pass (``BatchedExecutor``) captured once in a HIP graph
+    and replayed per bitstring and outer value.  Between replays only leaf
+    data changes, overwritten in place by host-to-device copies from pinned
+    memory outside the graph: the <x| leaves per bitstring, and the leaves
+    that carry outer labels (fixed to the outer value's bits) when the outer
+    value changes (``set_outer``).
 
     The graph owns a handle of its own, so its workspace (whose address the
     captured kernels hold) is never reallocated by other calls; a warm-up
@@ -330,23 +331,44 @@ class GraphPass:
         self.bx = BatchedExecutor(self.h, plan, n_batch)
         self.outer = outer
         self.n = plan.circuit["n"]
+        self._opos = {lab: i for i, lab in enumerate(self.bx.outer_labels)}
         # The <x| leaves are views of one device buffer, refilled per
         # bitstring by one copy from pinned memory.  Per qubit: its offset in
         # the buffer and, if its final wire is an outer label, that label's
-        # fixed value (the leaf is then a scalar).
+        # index among the outer labels (the leaf is then a scalar fixed by
+        # the outer value's bit).
         self.leaves, self.xbuf = self.bx._leaves_and_xbuf(0, outer)
-        opos = {lab: i for i, lab in enumerate(self.bx.outer_labels)}
-        wires = [labels[0] for _, labels in tn.circuit_network(plan.circuit, 0)[-self.n:]]
+        net = tn.circuit_network(plan.circuit, 0)
+        wires = [labels[0] for _, labels in net[-self.n:]] if self.n else []
         self.xslots = []
         off = 0
         for w in wires:
-            fixed = ((outer >> opos[w]) & 1) if w in opos else None
-            self.xslots.append((off, fixed))
-            off += 1 if fixed is not None else 2
+            bit = self._opos.get(w)
+            self.xslots.append((off, bit))
+            off += 1 if bit is not None else 2
         assert self.n == 0 or off == self.xbuf.numel()
         self.xhost = torch.zeros(max(off, 1), dtype=torch.complex64, pin_memory=True)
         self.xdone = torch.cuda.Event()
         self.xdone.record()
+        # the gate leaves that carry outer labels become views of a second
+        # buffer, refilled by set_outer: (leaf, offset, elements)
+        first_x = len(net) - self.n
+        self._gates = [(arr, labels) for arr, labels in net[:first_x]]
+        self.oslots, total = [], 0
+        for i, (arr, labels) in enumerate(self._gates):
+            if any(lab in self._opos for lab in labels):
+                t = self.leaves[i][0]
+                self.oslots.append((i, total, t.numel()))
+                total += t.numel()
+        self.obuf = torch.zeros(max(total, 1), dtype=torch.complex64, device="cuda")
+        for i, off, size in self.oslots:
+            t, kept = self.leaves[i]
+            view = self.obuf[off:off + size].view(t.shape)
+            view.copy_(t)
+            self.leaves[i] = (view, kept)
+        self.ohost = torch.zeros(max(total, 1), dtype=torch.complex64, pin_memory=True)
+        self.odone = torch.cuda.Event()
+        self.odone.record()
         self.acc = torch.zeros(2, dtype=torch.float64, device="cuda")
         root, _ = self.bx.run_pass(self.leaves)            # warm-up: workspace, allocator
         torch.cuda.synchronize()
@@ -358,18 +380,43 @@ class GraphPass:
             qce.accumulate_n_f64(self.h, root.reshape(-1), self.acc)
         self.root = root
 
-    def amplitude(self, x):
-        """Replay for bitstring x; returns the device float64[2] sum of the
-        pass's slice values (valid until the next replay)."""
+    @property
+    def n_outer(self):
+        return self.bx.n_outer
+
+    def set_outer(self, outer):
+        """Outer value for the following replays: the leaves that carry outer
+        labels are refilled (one copy) for slice ids [outer * 2^b, (outer +
+        1) * 2^b), b the number of batch labels."""
+        if not 0 <= int(outer) < self.n_outer:
+            raise ValueError(f"outer value {outer} outside [0, {self.n_outer})")
+        outer = int(outer)
+        if self.oslots:
+            self.odone.synchronize()          # the previous copy has read the pinned buffer
+            hv = self.ohost.numpy()
+            for i, off, size in self.oslots:
+                arr, labels = self._gates[i]
+                fixed = {lab: (outer >> self._opos[lab]) & 1 for lab in labels if lab in self._opos}
+                hv[off:off + size] = tn.fix_labels(arr, labels, fixed).reshape(-1)
+            self.obuf.copy_(self.ohost[: self.obuf.numel()], non_blocking=True)
+            self.odone.record()
+        self.outer = outer
+
+    def amplitude(self, x, outer=None):
+        """Replay for bitstring x (and outer value ``outer``, default the
+        current one); returns the device float64[2] sum of the pass's slice
+        values (valid until the next replay)."""
+        if outer is not None and int(outer) != self.outer:
+            self.set_outer(outer)
         if self.n:
             self.xdone.synchronize()          # the previous copy has read the pinned buffer
             hv = self.xhost.numpy()
             hv[:] = 0
-            for q, (off, fixed) in enumerate(self.xslots):
-                bit = (int(x) >> (self.n - 1 - q)) & 1
-                if fixed is None:
-                    hv[off + bit] = 1
-                elif fixed == bit:
+            for q, (off, bit) in enumerate(self.xslots):
+                xb = (int(x) >> (self.n - 1 - q)) & 1
+                if bit is None:
+                    hv[off + xb] = 1
+                elif (self.outer >> bit) & 1 == xb:
                     hv[off] = 1
             self.xbuf.copy_(self.xhost[: self.xbuf.numel()], non_blocking=True)
             self.xdone.record()

@@ -118,7 +118,7 @@ def test_graph_replay_sliced_output_wires_back_to_back(qce, h):
     outer = 1 << pos[0]                      # wire of qubit 0 fixed to 1, qubit 1 to 0
     gp = GraphPass(plan, n_batch=3, outer=outer)
     try:
-        assert sorted(f for _, f in gp.xslots if f is not None) == [0, 1]
+        assert sorted(b for _, b in gp.xslots if b is not None) == sorted(pos)
         n = c["n"]
         xs = [int(x) for x in synth.random_bitstrings(n, 6, seed=9)]
         xs += [(1 << (n - 1)) | 0b1011, (1 << (n - 1)) | (1 << (n - 2)) | 0b11]
@@ -154,3 +154,33 @@ def test_graph_pass_config1_matches_oracle(qce, h):
     want = oracle.statevector_amplitudes(rounded, xs)
     assert oracle.fidelity(got, want) >= 1 - 1e-6
     assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-4
+
+
+def test_graph_pass_every_outer_value(qce, h):
+    # one captured pass switched over every outer value (the leaves carrying
+    # outer labels re-uploaded, including <x| leaves fixed by outer bits):
+    # each replay equals the eager pass for that outer value bit for bit, and
+    # their sum is the amplitude over all slices
+    from paper_2303_08989_amd import tn
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, GraphPass
+    c = synth.grid_circuit(3, 4, 8, seed=7, pattern="ABCDCDAB")
+    base = CircuitPlan(c, max_log2=6, restarts=2, varied=3)
+    wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
+    plan = CircuitPlan(c, path=base.path, sliced=list(base.sliced) + wires[:1])
+    bx = BatchedExecutor(h, plan, 3)
+    assert 2 <= bx.n_outer <= 64 and wires[0] in bx.outer_labels
+    gp = GraphPass(plan, n_batch=3, outer=0)
+    try:
+        for x in [int(v) for v in synth.random_bitstrings(12, 2, seed=13)]:
+            total = 0j
+            for o in range(bx.n_outer):
+                got = gp.amplitude(x, outer=o).cpu().numpy()
+                want = bx.amplitude(x, [o]).cpu().numpy()
+                assert np.array_equal(got, want), (x, o)
+                total += complex(*got)
+            # and back to the first outer value
+            assert np.array_equal(gp.amplitude(x, outer=0).cpu().numpy(), bx.amplitude(x, [0]).cpu().numpy())
+            whole = complex(*bx.amplitude(x).cpu().numpy())
+            assert abs(total - whole) <= 1e-12 * max(abs(whole), 1e-30)
+    finally:
+        gp.close()
