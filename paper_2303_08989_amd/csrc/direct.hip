@@ -164,7 +164,10 @@ __global__ __launch_bounds__(kThreads) void direct_rows_kernel(DirectArgs d) {
     }
 }
 
-template <int MT>
+// VEC: column j of B holds its k values contiguously and column j of C its
+// m values, both 16-byte aligned with k and m even: two complex values per
+// load and per store (the products are added in the same order).
+template <int MT, bool VEC>
 __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
     select_entry(d);
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -172,8 +175,7 @@ __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
     float re[MT], im[MT];
 #pragma unroll
     for (int ii = 0; ii < MT; ++ii) re[ii] = im[ii] = 0.f;
-    for (int64_t l = 0; l < d.k; ++l) {
-        const float2 bv = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l);
+    auto add = [&](int64_t l, float2 bv) {
 #pragma unroll
         for (int ii = 0; ii < MT; ++ii) {
             if (ii >= d.m) break;
@@ -183,12 +185,30 @@ __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
             im[ii] = fmaf(a.x, bv.y, im[ii]);
             im[ii] = fmaf(a.y, bv.x, im[ii]);
         }
-    }
+    };
+    if constexpr (VEC) {
+        const float4 *bp = reinterpret_cast<const float4 *>(d.B + j * d.ldb);
+        for (int64_t l2 = 0; l2 < d.k / 2; ++l2) {
+            const float4 v = bp[l2];
+            add(2 * l2, make_float2(v.x, d.b_conj ? -v.y : v.y));
+            add(2 * l2 + 1, make_float2(v.z, d.b_conj ? -v.w : v.w));
+        }
 #pragma unroll
-    for (int ii = 0; ii < MT; ++ii) {
-        if (ii >= d.m) break;
-        float2 *cp = d.C + ii + j * d.ldc;
-        *cp = scale_out(d, re[ii], im[ii], cp);
+        for (int ii = 0; ii < MT; ii += 2) {
+            if (ii >= d.m) break;
+            float2 *cp = d.C + ii + j * d.ldc;
+            const float2 o0 = scale_out(d, re[ii], im[ii], cp);
+            const float2 o1 = scale_out(d, re[ii + 1], im[ii + 1], cp + 1);
+            *reinterpret_cast<float4 *>(cp) = make_float4(o0.x, o0.y, o1.x, o1.y);
+        }
+    } else {
+        for (int64_t l = 0; l < d.k; ++l) add(l, load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l));
+#pragma unroll
+        for (int ii = 0; ii < MT; ++ii) {
+            if (ii >= d.m) break;
+            float2 *cp = d.C + ii + j * d.ldc;
+            *cp = scale_out(d, re[ii], im[ii], cp);
+        }
     }
 }
 
@@ -252,13 +272,22 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
             }
         } else {
             const dim3 g((unsigned)((d.n + kThreads - 1) / kThreads), 1, nz), t(kThreads);
-            switch (pow2_at_least(d.m)) {
-            case 1: hipLaunchKernelGGL(direct_cols_kernel<1>, g, t, 0, s, d); break;
-            case 2: hipLaunchKernelGGL(direct_cols_kernel<2>, g, t, 0, s, d); break;
-            case 4: hipLaunchKernelGGL(direct_cols_kernel<4>, g, t, 0, s, d); break;
-            case 8: hipLaunchKernelGGL(direct_cols_kernel<8>, g, t, 0, s, d); break;
-            case 16: hipLaunchKernelGGL(direct_cols_kernel<16>, g, t, 0, s, d); break;
-            default: hipLaunchKernelGGL(direct_cols_kernel<32>, g, t, 0, s, d); break;
+            auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+            const bool vec = d.b_kcontig && d.k % 2 == 0 && d.ldb % 2 == 0 && al16(d.B) &&
+                             (nz == 1 || d.bsB % 2 == 0) && d.m % 2 == 0 && d.ldc % 2 == 0 && al16(d.C) &&
+                             (nz == 1 || d.bsC % 2 == 0);
+            switch (pow2_at_least(d.m) * (vec ? -1 : 1)) {
+            case 1: hipLaunchKernelGGL((direct_cols_kernel<1, false>), g, t, 0, s, d); break;
+            case 2: hipLaunchKernelGGL((direct_cols_kernel<2, false>), g, t, 0, s, d); break;
+            case 4: hipLaunchKernelGGL((direct_cols_kernel<4, false>), g, t, 0, s, d); break;
+            case 8: hipLaunchKernelGGL((direct_cols_kernel<8, false>), g, t, 0, s, d); break;
+            case 16: hipLaunchKernelGGL((direct_cols_kernel<16, false>), g, t, 0, s, d); break;
+            case 32: hipLaunchKernelGGL((direct_cols_kernel<32, false>), g, t, 0, s, d); break;
+            case -2: hipLaunchKernelGGL((direct_cols_kernel<2, true>), g, t, 0, s, d); break;
+            case -4: hipLaunchKernelGGL((direct_cols_kernel<4, true>), g, t, 0, s, d); break;
+            case -8: hipLaunchKernelGGL((direct_cols_kernel<8, true>), g, t, 0, s, d); break;
+            case -16: hipLaunchKernelGGL((direct_cols_kernel<16, true>), g, t, 0, s, d); break;
+            default: hipLaunchKernelGGL((direct_cols_kernel<32, true>), g, t, 0, s, d); break;
             }
         }
         return hipGetLastError();

@@ -101,6 +101,25 @@ def test_integer_exact(qce, h, mode, m, n, k):
         assert np.array_equal(out[z].astype(np.complex128), oracle.cgemm(As[z], Bs[z])), z
 
 
+@pytest.mark.parametrize("m,n,k", [(6, 2000, 4), (5, 2000, 4)])
+def test_short_k_columns_even_strides(qce, h, m, n, k):
+    # short k, few rows, entry strides that keep every entry's B and C
+    # 16-byte aligned (even m: two complex values per load and store)
+    rng = np.random.default_rng(m * n + k)
+    batch = 3
+    As = [synth.random_matrix(m, k, "int", rng) for _ in range(batch)]
+    Bs = [synth.random_matrix(k, n, "int", rng) for _ in range(batch)]
+    C0s = [synth.random_matrix(m, n, "int", rng) for _ in range(batch)]
+    sA, sB, sC = m * k + 4, k * n + 2, m * n + 6
+    dA, dB, dC = pack(As, sA), pack(Bs, sB), pack(C0s, sC)
+    qce.cgemm_strided_batched(h, "N", "N", m, n, k, dA, m, sA, dB, k, sB, dC, m, sC, batch,
+                              complex(0, 1), complex(1, -1))
+    torch.cuda.synchronize()
+    for z in range(batch):
+        want = oracle.cgemm(As[z], Bs[z], alpha=complex(0, 1), beta=complex(1, -1), C0=C0s[z])
+        assert np.array_equal(unpack(dC, z, sC, m, n, m).astype(np.complex128), want), z
+
+
 @pytest.mark.parametrize("opA,opB", [("T", "N"), ("C", "T"), ("N", "C")])
 def test_ops_alpha_beta_shared_a(qce, h, opA, opB):
     m, n, k = 160, 140, 80

@@ -317,6 +317,30 @@ def test_short_k_ops_alpha_beta(qce, handle, opA, opB, m, n, k):
     assert np.array_equal(C.astype(np.complex128), want)
 
 
+@pytest.mark.parametrize("shift", [0, 1])
+@pytest.mark.parametrize("m,n,k", [(2, 5000, 2), (6, 3000, 8), (16, 777, 16), (30, 513, 10),
+                                   (7, 300, 8), (6, 300, 5)])
+def test_short_k_columns_alpha_beta(qce, handle, m, n, k, shift):
+    # short k and fewer than 32 rows: one output column per thread. Even m
+    # and k with B and C 16-byte aligned move two complex values per load
+    # and store; odd sizes, or B and C one element off that alignment
+    # (shift), load element by element. Integer inputs: exact either way.
+    rng = np.random.default_rng(7 * m + n + k)
+    A = synth.random_matrix(m, k, "int", rng)
+    B = synth.random_matrix(k, n, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    alpha, beta = complex(2, -1), complex(-1, 1)
+    pad = torch.zeros(shift, dtype=torch.complex64, device="cuda")
+    dB = torch.cat([pad, dev(B)])[shift:]
+    dC = torch.cat([pad, dev(C0)])[shift:]
+    assert (dB.data_ptr() % 16 == 0) == (shift == 0)
+    handle.set_mode("auto")
+    qce.cgemm(handle, "N", "N", m, n, k, dev(A), m, dB, k, dC, m, alpha, beta)
+    torch.cuda.synchronize()
+    want = oracle.cgemm(A, B, alpha=alpha, beta=beta, C0=C0)
+    assert np.array_equal(host(dC, m, n).astype(np.complex128), want)
+
+
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1 << 22), (20000, 3, 5), (8, 9, 300000)])
 def test_irregular_float_accuracy(qce, handle, m, n, k):
     A, B = synth.gemm_operands(m, n, k, "a", seed=31)
