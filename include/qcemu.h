@@ -124,6 +124,8 @@ typedef struct {
  *   QCE_BF16X3_TOL     t3 in [0, 1], default 0
  *   QCE_AUTO_MIN_DIM   size policy threshold for statistics, default 512
  *   QCE_EMUL_MIN_DIM   size policy threshold for emulation, default 512
+ *   QCE_FUSED_GATHER   1 (default) or 0: permute fused into the split in
+ *                      qce_contract
  * The stream is the device's null stream until qce_set_stream.
  * Errors: INVALID_VALUE (h NULL, bad device or bad environment value),
  * ALLOC, HIP.
@@ -264,7 +266,13 @@ qce_status qce_get_batch_decision(qce_handle *h, int64_t index, qce_decision *ou
  * transpose-transpose-GEMM-transpose (Sec. 1): operands are permuted on the
  * device only when their labels are not already grouped as the GEMM needs,
  * the GEMM runs through the emulated CGEMM under the size policy (Sec. 4.3),
- * and the result is permuted only if lc's order requires it.
+ * and the result is permuted only if lc's order requires it.  When every
+ * extent is 2 (circuit tensors), there are no batch labels and the GEMM is
+ * not of irregular shape, an operand that needs a transpose is not copied:
+ * the split reads it through its index-bit permutation (the permute and the
+ * split are one pass; the K order is then chosen for contiguous reads of
+ * both operands, so the summation order over K may differ from that of the
+ * copied path).  Disabled by QCE_FUSED_GATHER=0 at qce_create.
  * a, b, c: host shape descriptors; A, B: device complex64 inputs; C: device
  * complex64 output of the shape c describes (must not overlap A or B).
  * la, lb, lc: host int32 label arrays of lengths a->rank, b->rank, c->rank.

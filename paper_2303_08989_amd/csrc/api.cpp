@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "gather.hpp"
 
 using namespace qce;
 
@@ -53,6 +54,7 @@ struct qce_handle {
     std::vector<hipEvent_t> pool;
     // grouped small contractions (qce_group_begin / qce_group_end)
     bool grouping = false;
+    bool fused_gather = true;  // permute fused into the split (qce_contract)
     std::vector<qce::SmallItem> pending;
     char *grp_dev = nullptr;   // descriptor arena on the device
     char *grp_host = nullptr;  // its pinned host mirror (source of the copies)
@@ -246,7 +248,23 @@ struct OperandView {
     int64_t ld;
     bool kcontig;
     bool conj;
+    // set: the operand is read through this bit map by the split (ptr is
+    // the whole tensor, contiguous; ld = rows, kcontig = conj = false)
+    const GatherMap *gm = nullptr;
 };
+
+// Split one operand into panels (the mode and shift from the device state
+// when st is set).
+hipError_t split_operand(const OperandView &v, int64_t rows, int64_t k, char *panels, const DevState *st,
+                         int which, int forced_mode, hipStream_t s, int nb, int64_t xstride, int64_t pstride) {
+    if (v.gm) {
+        if (nb != 1 || (int64_t(1) << v.gm->nr) != rows || (int64_t(1) << v.gm->nk) != k)
+            return hipErrorInvalidValue;
+        return launch_split_gather(v.ptr, *v.gm, panels, st, which, forced_mode, 0, s);
+    }
+    return launch_split_panels(v.ptr, v.ld, v.kcontig, v.conj, rows, k, panels, st, which, forced_mode, 0, s, nb,
+                               xstride, pstride);
+}
 
 MatDesc stored_desc(const OperandView &v, int64_t rows, int64_t k) {
     // the stored column-major matrix behind the view
@@ -304,6 +322,7 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         return QCE_SUCCESS;
     }
     if (irregular_shape(m, n, k)) {
+        if (a.gm || b.gm) return fail(h, QCE_ERR_INVALID_VALUE, "bit-map operands need a matrix-core shape");
         DirectArgs d{};
         d.A = a.ptr;
         d.lda = a.ld;
@@ -383,10 +402,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         }
         span_end(h, e0, QCE_PHASE_STATS);
         hipEvent_t e1 = span_begin(h);
-        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, dst, 0, 0, 0, s, nb, bt.sa,
-                                       (int64_t)wl.pa));
-        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, dst, 1, 0, 0, s, nb, bt.sb,
-                                       (int64_t)wl.pb));
+        QCE_HIP(h, split_operand(a, m, k, panA, dst, 0, 0, s, nb, bt.sa, (int64_t)wl.pa));
+        QCE_HIP(h, split_operand(b, n, k, panB, dst, 1, 0, s, nb, bt.sb, (int64_t)wl.pb));
         span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = dst;
         g.forced_mode = -1;
@@ -402,10 +419,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         h->last_on_device = true;
     } else {
         hipEvent_t e1 = span_begin(h);
-        QCE_HIP(h, launch_split_panels(a.ptr, a.ld, a.kcontig, a.conj, m, k, panA, nullptr, 0, mode, 0, s, nb,
-                                       bt.sa, (int64_t)wl.pa));
-        QCE_HIP(h, launch_split_panels(b.ptr, b.ld, b.kcontig, b.conj, n, k, panB, nullptr, 1, mode, 0, s, nb,
-                                       bt.sb, (int64_t)wl.pb));
+        QCE_HIP(h, split_operand(a, m, k, panA, nullptr, 0, mode, s, nb, bt.sa, (int64_t)wl.pa));
+        QCE_HIP(h, split_operand(b, n, k, panB, nullptr, 1, mode, s, nb, bt.sb, (int64_t)wl.pb));
         span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = nullptr;
         g.forced_mode = mode;
@@ -602,6 +617,11 @@ qce_status qce_create(qce_handle **out, int device) {
     }
     if (const char *v = getenv("QCE_EMUL_MIN_DIM")) {
         if (!parse_i64(v, &h->emul_min) || h->emul_min < 0) { delete h; return QCE_ERR_INVALID_VALUE; }
+    }
+    if (const char *v = getenv("QCE_FUSED_GATHER")) {
+        int64_t f = 0;
+        if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
+        h->fused_gather = f == 1;
     }
     if (h->emul_min > h->auto_min) { delete h; return QCE_ERR_INVALID_VALUE; }
     DeviceGuard g(device);
@@ -1046,16 +1066,106 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         if (layout(ly, ry, ko, SB) < 0) c0 += sy;
         return c0;
     };
-    const std::vector<int32_t> korder = cost(kx) <= cost(ky) ? kx : ky;
-    const int lay_x = layout(lx, rx, korder, SA), lay_y = layout(ly, ry, korder, SB);
+    std::vector<int32_t> korder = cost(kx) <= cost(ky) ? kx : ky;
+    int lay_x = layout(lx, rx, korder, SA), lay_y = layout(ly, ry, korder, SB);
+
+    // Permute fused into the split (every extent 2, no batch labels, a
+    // matrix-core shape): an operand in neither [K][F] nor [F][K] order is
+    // read by the split kernel through its bit permutation, one read
+    // instead of a permuted copy plus a read.  The kernel loads 64 x 64
+    // tiles whose bits are the last six labels of the F order and of the K
+    // order; the longest run of the operand's own last labels inside the
+    // tile is read contiguously.  Where a run is below 2^5 elements the
+    // six tile K labels are picked greedily, each time the next label of
+    // the operand with the shorter run; an operand left with a run below
+    // 2^3 elements (64 bytes) is permuted as before.
+    bool gx = false, gy = false;
+    GatherMap gmx, gmy;
+    bool all_two = nbt == 0 && h->fused_gather && !irregular_shape(m, n, kk) && (lay_x < 0 || lay_y < 0);
+    for (int i = 0; all_two && i < ra; ++i) all_two = a->extents[i] == 2;
+    for (int i = 0; all_two && i < rb; ++i) all_two = b->extents[i] == 2;
+    if (all_two && rx <= 62 && ry <= 62 && SA.size() <= 31 && SB.size() <= 31 && K.size() <= 31) {
+        auto in_last6 = [](const std::vector<int32_t> &v, int32_t lab) {
+            for (size_t i = v.size() > 6 ? v.size() - 6 : 0; i < v.size(); ++i)
+                if (v[i] == lab) return true;
+            return false;
+        };
+        auto run_of = [&](const int32_t *l, int r, const std::vector<int32_t> &F,
+                          const std::vector<int32_t> &ko) {
+            int run = 0;
+            for (int i = r - 1; i >= 0 && (in_last6(F, l[i]) || in_last6(ko, l[i])); --i) ++run;
+            return run;
+        };
+        constexpr int kMinRun = 3, kGoodRun = 5;
+        if ((lay_x < 0 && run_of(lx, rx, SA, korder) < kGoodRun) ||
+            (lay_y < 0 && run_of(ly, ry, SB, korder) < kGoodRun)) {
+            std::vector<int32_t> tk;
+            auto in_tk = [&](int32_t lab) { return std::find(tk.begin(), tk.end(), lab) != tk.end(); };
+            // index in l of the operand's next label outside the tile, if a
+            // K label (-1: a full run, or capped by an F label)
+            auto next_k = [&](const int32_t *l, int r, const std::vector<int32_t> &F, int &run) {
+                run = 0;
+                for (int i = r - 1; i >= 0; --i) {
+                    if (in_last6(F, l[i]) || in_tk(l[i])) {
+                        ++run;
+                        continue;
+                    }
+                    return std::find(K.begin(), K.end(), l[i]) != K.end() ? i : -1;
+                }
+                return -1;
+            };
+            while (tk.size() < std::min<size_t>(6, K.size())) {
+                int run_x = 0, run_y = 0;
+                const int ix = next_k(lx, rx, SA, run_x), iy = next_k(ly, ry, SB, run_y);
+                if (ix >= 0 && (iy < 0 || run_x <= run_y)) tk.push_back(lx[ix]);
+                else if (iy >= 0) tk.push_back(ly[iy]);
+                else break;
+            }
+            std::vector<int32_t> ko;
+            for (int32_t lab : korder)
+                if (!in_tk(lab)) ko.push_back(lab);
+            for (int32_t lab : korder)
+                if (in_tk(lab)) ko.push_back(lab);
+            korder = ko;
+            lay_x = layout(lx, rx, korder, SA);
+            lay_y = layout(ly, ry, korder, SB);
+        }
+        // P[r][l]: r's bit t is label F[|F| - 1 - t], l's bit t is label
+        // korder[|K| - 1 - t]; a label at position i of l holds stride 2^(r-1-i)
+        auto make_map = [&](const int32_t *l, int r, const std::vector<int32_t> &F) {
+            GatherMap g;
+            g.nr = (int)F.size();
+            g.nk = (int)korder.size();
+            for (int t = 0; t < g.nr; ++t) g.rsh[t] = (int8_t)(r - 1 - find(l, r, F[g.nr - 1 - t]));
+            for (int t = 0; t < g.nk; ++t) g.ksh[t] = (int8_t)(r - 1 - find(l, r, korder[g.nk - 1 - t]));
+            std::vector<std::pair<int, int>> tb;  // (stride exponent, tile position)
+            for (int t = 0; t < std::min(6, g.nr); ++t) tb.emplace_back(g.rsh[t], t);
+            for (int t = 0; t < std::min(6, g.nk); ++t) tb.emplace_back(g.ksh[t], 6 + t);
+            std::sort(tb.begin(), tb.end());
+            g.nt = (int)tb.size();
+            for (int i = 0; i < g.nt; ++i) {
+                g.tsh[i] = (int8_t)tb[i].first;
+                g.tpos[i] = (int8_t)tb[i].second;
+            }
+            return g;
+        };
+        if (lay_x < 0 && run_of(lx, rx, SA, korder) >= kMinRun) {
+            gmx = make_map(lx, rx, SA);
+            gx = gather_map_valid(gmx);
+        }
+        if (lay_y < 0 && run_of(ly, ry, SB, korder) >= kMinRun) {
+            gmy = make_map(ly, ry, SB);
+            gy = gather_map_valid(gmy);
+        }
+    }
 
     // workspace: panels | permuted X | permuted Y | temporary C
     const int chunk = (int)std::min<int64_t>(std::max<int64_t>(count, 1), kMaxBatch);
     size_t off = align256(cgemm_ws_bytes(m, n, kk, chunk));
     const size_t offx = off;
-    if (lay_x < 0) off += align256((size_t)sx * 8);
+    if (lay_x < 0 && !gx) off += align256((size_t)sx * 8);
     const size_t offy = off;
-    if (lay_y < 0) off += align256((size_t)sy * 8);
+    if (lay_y < 0 && !gy) off += align256((size_t)sy * 8);
     const size_t offc = off;
     if (out_perm) off += align256((size_t)nc * 8);
     DeviceGuard g(h->device);
@@ -1073,7 +1183,9 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
                            reinterpret_cast<float2 *>(dst));
     };
     OperandView vx, vy;
-    if (lay_x < 0) {
+    if (gx) {
+        vx = OperandView{static_cast<const float2 *>(X), m, false, false, &gmx};
+    } else if (lay_x < 0) {
         st = permute_to_kf(lx, rx, ex, X, SA, ws + offx);
         if (st != QCE_SUCCESS) return st;
         vx = OperandView{reinterpret_cast<const float2 *>(ws + offx), std::max<int64_t>(1, m), false, false};
@@ -1082,7 +1194,9 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     } else {  // [F][K]: column-major k x m
         vx = OperandView{static_cast<const float2 *>(X), std::max<int64_t>(1, kk), true, false};
     }
-    if (lay_y < 0) {
+    if (gy) {
+        vy = OperandView{static_cast<const float2 *>(Y), n, false, false, &gmy};
+    } else if (lay_y < 0) {
         st = permute_to_kf(ly, ry, ey, Y, SB, ws + offy);
         if (st != QCE_SUCCESS) return st;
         vy = OperandView{reinterpret_cast<const float2 *>(ws + offy), std::max<int64_t>(1, n), false, false};

@@ -9,7 +9,9 @@
 // and the power-of-two scalings are exact (ldexp).  The mode and shift come
 // from the device decision when statistics ran, so no host round trip is
 // needed (Sec. 4.2).  Inputs are never modified.
-#include "common.hpp"
+#include <algorithm>
+
+#include "gather.hpp"
 
 namespace qce {
 
@@ -54,23 +56,28 @@ __device__ inline uint4 pack8(const uint16_t *v) {
     return r;
 }
 
-// Panel row r holds P[r][l], l = 0..k-1.  KCONTIG = false: P[r][l] =
+// Operand layouts of the split
+constexpr int kRowsContig = 0, kKContig = 1, kGather = 2;
+
+// Panel row r holds P[r][l], l = 0..k-1.  kRowsContig: P[r][l] =
 // x[r + l * ldx] (rows contiguous: op(A) = A, or op(B) = B^T / B^H);
-// KCONTIG = true: P[r][l] = x[l + r * ldx] (k contiguous: op(A) = A^T / A^H,
-// or op(B) = B).  conj negates the imaginary part.
+// kKContig: P[r][l] = x[l + r * ldx] (k contiguous: op(A) = A^T / A^H, or
+// op(B) = B); kGather: P[r][l] read through the bit map gm.  conj negates
+// the imaginary part.
 //
 // A thread converts one chunk row: 16 k-values of one row, written as the
 // row's whole slot in every plane (32 bytes per plane, 64 for FP32).
-// KCONTIG = false: a wave takes 64 consecutive rows of one chunk, so each
-// of its 16 loads reads 512 contiguous bytes and each plane's stores cover
-// 2 KB.  KCONTIG = true: a block stages 64 rows x 64 k-values through LDS
-// (512-byte row runs in), then converts like the other layout (64
-// consecutive rows of one chunk per wave, 2 KB stores per plane).
-template <bool KCONTIG>
+// kRowsContig: a wave takes 64 consecutive rows of one chunk, so each of
+// its 16 loads reads 512 contiguous bytes and each plane's stores cover
+// 2 KB.  kKContig and kGather: a block stages 64 rows x 64 k-values
+// through LDS (read in runs of consecutive addresses), then converts like
+// the first layout (64 consecutive rows of one chunk per wave, 2 KB stores
+// per plane).
+template <int LAYOUT>
 __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
     int64_t rows_pad, int64_t nchunks, char *__restrict__ panels, const DevState *st, int which,
-    int forced_mode, int forced_shift, int64_t xstride, int64_t pstride) {
+    int forced_mode, int forced_shift, int64_t xstride, int64_t pstride, const GatherMap gm) {
     // batch entry
     x += (int64_t)blockIdx.z * xstride;
     panels += (int64_t)blockIdx.z * pstride;
@@ -78,7 +85,77 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     constexpr int kK = 16;  // k-values per chunk row
     float re[kK], im[kK];
     int64_t r, c;  // row and chunk
-    if (KCONTIG) {
+    if constexpr (LAYOUT == kGather) {
+        // A block takes 64 rows x 4 chunks (64 k-values) as in kKContig.
+        // Thread t loads the tile elements e = t + 256 i, whose bits are
+        // the tile's index bits by increasing stride in x: the low bits of
+        // e walk x's lowest bits wherever the tile holds them.
+        __shared__ float2 tile[64][64 + 1];
+        const int64_t row_blocks = rows_pad / 64;
+        const int64_t r0 = (int64_t)(blockIdx.x % row_blocks) * 64;
+        const int64_t c0 = (int64_t)(blockIdx.x / row_blocks) * 4;
+        const int64_t l0 = c0 * kK;
+        if (r0 < rows && l0 < k) {
+            int64_t base = 0;
+            for (int i = 6; i < gm.nr; ++i)
+                if ((r0 >> i) & 1) base += (int64_t)1 << gm.rsh[i];
+            for (int j = 6; j < gm.nk; ++j)
+                if ((l0 >> j) & 1) base += (int64_t)1 << gm.ksh[j];
+            // e's bits 0-7 come from the thread, bits 8-11 from the unrolled
+            // load index: every per-bit term is uniform or per thread
+            int tr0 = 0, tq0 = 0;
+            int64_t off0 = base;
+            for (int b = 0; b < 8 && b < gm.nt; ++b) {
+                if ((threadIdx.x >> b) & 1) {
+                    if (gm.tpos[b] < 6) tr0 += 1 << gm.tpos[b];
+                    else tq0 += 1 << (gm.tpos[b] - 6);
+                    off0 += (int64_t)1 << gm.tsh[b];
+                }
+            }
+            int hi_slot[4];
+            int64_t hi_off[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int b = 8 + j;
+                hi_slot[j] = b < gm.nt ? (gm.tpos[b] < 6 ? (1 << gm.tpos[b]) * 65 : 1 << (gm.tpos[b] - 6)) : 0;
+                hi_off[j] = b < gm.nt ? (int64_t)1 << gm.tsh[b] : 0;
+            }
+            const int ne = 1 << gm.nt;
+            constexpr int kE = 64 * 64 / kThreads;
+            float2 v[kE];
+            // all loads first, then the LDS stores
+#pragma unroll
+            for (int i = 0; i < kE; ++i) {
+                int64_t off = off0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((i >> j) & 1) off += hi_off[j];
+                if (i * kThreads + (int)threadIdx.x < ne) v[i] = x[off];
+            }
+            float2 *flat = &tile[0][0];
+            const int slot0 = tr0 * 65 + tq0;
+#pragma unroll
+            for (int i = 0; i < kE; ++i) {
+                int slot = slot0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((i >> j) & 1) slot += hi_slot[j];
+                if (i * kThreads + (int)threadIdx.x < ne) flat[slot] = v[i];
+            }
+        }
+        __syncthreads();
+        const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+        r = r0 + tr;
+        c = c0 + tc;
+        if (c >= nchunks) return;
+#pragma unroll
+        for (int j = 0; j < kK; ++j) {
+            const int64_t l = c * kK + j;
+            const float2 v = r < rows && l < k ? tile[tr][tc * kK + j] : make_float2(0.f, 0.f);
+            re[j] = v.x;
+            im[j] = v.y;
+        }
+    } else if constexpr (LAYOUT == kKContig) {
         // A block takes 64 rows x 4 chunks (64 k-values).  The tile is read
         // in 512-byte row runs (a wave reads one row per load) into LDS,
         // whose rows are padded by one element so that a wave reading one
@@ -205,15 +282,53 @@ hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int co
     char *p = static_cast<char *>(panels);
     if (!kcontig) {
         const int64_t blocks = (total + kThreads - 1) / kThreads;
-        hipLaunchKernelGGL(split_panels_kernel<false>, dim3((unsigned)blocks, 1, batch), dim3(kThreads), 0,
-                           s, x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift,
-                           xstride, pstride);
+        hipLaunchKernelGGL(split_panels_kernel<kRowsContig>, dim3((unsigned)blocks, 1, batch), dim3(kThreads),
+                           0, s, x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift,
+                           xstride, pstride, GatherMap{});
     } else {
         const int64_t blocks = (rows_pad / 64) * ((nchunks + 3) / 4);
-        hipLaunchKernelGGL(split_panels_kernel<true>, dim3((unsigned)blocks, 1, batch), dim3(kThreads), 0,
+        hipLaunchKernelGGL(split_panels_kernel<kKContig>, dim3((unsigned)blocks, 1, batch), dim3(kThreads), 0,
                            s, x, ldx, conj, rows, k, rows_pad, nchunks, p, st, which, forced_mode, shift,
-                           xstride, pstride);
+                           xstride, pstride, GatherMap{});
     }
+    return hipGetLastError();
+}
+
+bool gather_map_valid(const GatherMap &gm) {
+    if (gm.nr < 0 || gm.nk < 0 || gm.nr > 31 || gm.nk > 31 || gm.nr + gm.nk > 62) return false;
+    const int nb = gm.nr + gm.nk;
+    uint64_t seen = 0;
+    for (int i = 0; i < nb; ++i) {
+        const int sh = i < gm.nr ? gm.rsh[i] : gm.ksh[i - gm.nr];
+        if (sh < 0 || sh >= nb || ((seen >> sh) & 1)) return false;
+        seen |= uint64_t(1) << sh;
+    }
+    // the tile: the low min(6, nr) bits of r and min(6, nk) of l, each once,
+    // by increasing stride
+    const int tr = std::min(6, gm.nr), tk = std::min(6, gm.nk);
+    if (gm.nt != tr + tk) return false;
+    unsigned used = 0;
+    for (int b = 0; b < gm.nt; ++b) {
+        const int p = gm.tpos[b];
+        const bool is_r = p >= 0 && p < tr, is_k = p >= 6 && p < 6 + tk;
+        if (!(is_r || is_k) || ((used >> p) & 1)) return false;
+        used |= 1u << p;
+        if (gm.tsh[b] != (is_r ? gm.rsh[p] : gm.ksh[p - 6])) return false;
+        if (b > 0 && gm.tsh[b] <= gm.tsh[b - 1]) return false;
+    }
+    return true;
+}
+
+hipError_t launch_split_gather(const float2 *x, const GatherMap &gm, void *panels, const DevState *st,
+                               int which, int forced_mode, int shift, hipStream_t s) {
+    if (!gather_map_valid(gm)) return hipErrorInvalidValue;
+    const int64_t rows = int64_t(1) << gm.nr, k = int64_t(1) << gm.nk;
+    const int64_t rows_pad = round_up(rows, kPanelRows);
+    const int64_t nchunks = round_up(k, kKPad) / kKPad;
+    const int64_t blocks = (rows_pad / 64) * ((nchunks + 3) / 4);
+    hipLaunchKernelGGL(split_panels_kernel<kGather>, dim3((unsigned)blocks, 1, 1), dim3(kThreads), 0, s, x,
+                       int64_t(0), 0, rows, k, rows_pad, nchunks, static_cast<char *>(panels), st, which,
+                       forced_mode, shift, int64_t(0), int64_t(0), gm);
     return hipGetLastError();
 }
 

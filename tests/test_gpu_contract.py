@@ -104,6 +104,97 @@ def test_contract_integer_exact(qce, h, mode, seed):
     assert np.array_equal(C.astype(np.complex128), want)
 
 
+def _bits_network(rng, nk, nfa, nfb, ints, natural_out=True):
+    """Every extent 2; K and free labels interleaved at random in A and B."""
+    K = list(range(nk))
+    FA = list(range(100, 100 + nfa))
+    FB = list(range(200, 200 + nfb))
+    la = [int(v) for v in rng.permutation(K + FA)]
+    lb = [int(v) for v in rng.permutation(K + FB)]
+    lc = [v for v in lb if v in FB] + [v for v in la if v in FA]
+    if not natural_out:
+        lc = [int(v) for v in rng.permutation(lc)]
+
+    def t(r):
+        if ints:
+            return (rng.integers(-3, 4, (2,) * r) + 1j * rng.integers(-3, 4, (2,) * r)).astype(np.complex64)
+        return (rng.standard_normal((2,) * r) + 1j * rng.standard_normal((2,) * r)).astype(np.complex64)
+    return t(len(la)), la, t(len(lb)), lb, lc
+
+
+def _contract_counted(qce, hh, A, la, B, lb, lc, mode):
+    if mode == "auto_emulated":
+        hh.set_mode("auto")
+        hh.set_size_policy(0, 0)
+    else:
+        hh.set_mode(mode)
+    hh.set_timing(True)
+    hh.reset_timing()
+    try:
+        C = qce.contract(hh, torch.from_numpy(A).to("cuda"), la, torch.from_numpy(B).to("cuda"), lb, lc)
+        t = hh.timing()
+        dec = hh.last_decision()
+    finally:
+        hh.set_timing(False)
+        hh.set_size_policy(*hh.default_size_policy)
+        hh.set_mode("auto")
+    return C.cpu().numpy(), t["permute"][1], dec
+
+
+@pytest.fixture(scope="module")
+def h_unfused(qce):
+    import os
+    old = os.environ.get("QCE_FUSED_GATHER")
+    os.environ["QCE_FUSED_GATHER"] = "0"
+    try:
+        hh = qce.Handle(0)
+    finally:
+        if old is None:
+            del os.environ["QCE_FUSED_GATHER"]
+        else:
+            os.environ["QCE_FUSED_GATHER"] = old
+    yield hh
+    hh.close()
+
+
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated", "fp16x2", "bf16x3"])
+@pytest.mark.parametrize("seed", range(4))
+def test_contract_fused_gather_integer_exact(qce, h, h_unfused, mode, seed):
+    # interleaved K and free labels (every extent 2): the split reads each
+    # operand through its bit permutation (no permute launched when every
+    # label lies in the split's 64 x 64 tile); exact, and equal to the
+    # permute-then-split path
+    rng = np.random.default_rng(300 + seed)
+    nk, nfa, nfb = 4 + seed % 3, 5 + seed % 2, 6 - seed % 2
+    A, la, B, lb, lc = _bits_network(rng, nk, nfa, nfb, ints=True)
+    want = oracle.zcontract(A, la, B, lb, lc)
+    got, n_perm, _ = _contract_counted(qce, h, A, la, B, lb, lc, mode)
+    assert np.array_equal(got.astype(np.complex128), want)
+    assert n_perm == 0
+    ref, n_perm_ref, _ = _contract_counted(qce, h_unfused, A, la, B, lb, lc, mode)
+    assert n_perm_ref >= 1
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated", "bf16x3"])
+@pytest.mark.parametrize("seed", range(4))
+def test_contract_fused_gather_many_tiles(qce, h, h_unfused, mode, seed):
+    # more labels than the tile holds (several 64 x 64 tiles per operand,
+    # tile bases from the high bits), float inputs: both paths against the
+    # FP64 oracle, and the same device decision (the statistics of a tensor
+    # do not depend on its element order)
+    rng = np.random.default_rng(400 + seed)
+    nk, nfa, nfb = 7 + seed % 3, 8 + seed % 2, 9 - seed % 2
+    A, la, B, lb, lc = _bits_network(rng, nk, nfa, nfb, ints=False, natural_out=seed % 2 == 0)
+    want = oracle.zcontract(A, la, B, lb, lc)
+    got, _, dec = _contract_counted(qce, h, A, la, B, lb, lc, mode)
+    ref, _, dec_ref = _contract_counted(qce, h_unfused, A, la, B, lb, lc, mode)
+    bound = 2e-6 if mode in ("fp32", "bf16x3") else 4e-6
+    assert oracle.rel_fro(got, want) < bound
+    assert oracle.rel_fro(ref, want) < bound
+    assert (dec["mode"], dec["sA"], dec["sB"]) == (dec_ref["mode"], dec_ref["sA"], dec_ref["sB"])
+
+
 @pytest.mark.parametrize("layout", ["natural", "swapped", "interleaved", "scalar", "outer"])
 def test_contract_layouts_float(qce, h, layout):
     rng = np.random.default_rng(7)
