@@ -272,7 +272,10 @@ qce_status qce_get_batch_decision(qce_handle *h, int64_t index, qce_decision *ou
  * the split reads it through its index-bit permutation (the permute and the
  * split are one pass; the K order is then chosen for contiguous reads of
  * both operands, so the summation order over K may differ from that of the
- * copied path).  Disabled by QCE_FUSED_GATHER=0 at qce_create.
+ * copied path).  Likewise a contraction over every label of two such
+ * tensors in different orders reads one through its permutation and sums
+ * the products in one pass (FP32, a fixed summation order).  Both are
+ * disabled by QCE_FUSED_GATHER=0 at qce_create.
  * a, b, c: host shape descriptors; A, B: device complex64 inputs; C: device
  * complex64 output of the shape c describes (must not overlap A or B).
  * la, lb, lc: host int32 label arrays of lengths a->rank, b->rank, c->rank.

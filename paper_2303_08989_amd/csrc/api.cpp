@@ -1159,6 +1159,50 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         }
     }
 
+    // A full contraction (every label summed, every extent 2) of two
+    // tensors in different label orders: one pass reads the permuted
+    // operand through the tile of its bit permutation and sums the
+    // products (no permuted copy).
+    if (h->fused_gather && nbt == 0 && FA.empty() && FB.empty() && kk > 1 && (lay_x < 0) != (lay_y < 0)) {
+        bool two = true;
+        for (int i = 0; two && i < ra; ++i) two = a->extents[i] == 2;
+        for (int i = 0; two && i < rb; ++i) two = b->extents[i] == 2;
+        const bool px = lay_x < 0;
+        const int32_t *lp = px ? lx : ly;
+        const int rp = px ? rx : ry;
+        std::vector<int32_t> perm;
+        for (int32_t lab : korder) perm.push_back(find(lp, rp, lab));
+        PermDesc d;
+        int64_t total = 0;
+        bool identity = false;
+        if (two && rp == (int)korder.size() &&
+            plan_permute(h, rp, px ? ex : ey, perm.data(), d, total, identity) == QCE_SUCCESS && !identity) {
+            const int64_t parts = permuted_dot_partials(d);
+            if (parts > 0) {
+                DeviceGuard g(h->device);
+                qce_status st = ensure_ws(h, align256((size_t)parts * sizeof(float2)));
+                if (st != QCE_SUCCESS) return st;
+                h->dec_base = h->st;
+                h->dec_count = 1;
+                hipEvent_t e0 = span_begin(h);
+                QCE_HIP(h, launch_permuted_dot(static_cast<const float2 *>(px ? X : Y),
+                                               static_cast<const float2 *>(px ? Y : X), d,
+                                               static_cast<float2 *>(h->ws), static_cast<float2 *>(C),
+                                               h->stream));
+                span_end(h, e0, QCE_PHASE_GEMM_IRREGULAR);
+                h->have_decision = true;
+                h->last_on_device = false;
+                h->last_host = qce_decision{};
+                h->last_host.mode = QCE_MODE_FP32;
+                for (int o = 0; o < 2; ++o) {
+                    h->last_host.n2[o] = -1;
+                    h->last_host.emax[o] = INT32_MIN;
+                }
+                return QCE_SUCCESS;
+            }
+        }
+    }
+
     // workspace: panels | permuted X | permuted Y | temporary C
     const int chunk = (int)std::min<int64_t>(std::max<int64_t>(count, 1), kMaxBatch);
     size_t off = align256(cgemm_ws_bytes(m, n, kk, chunk));

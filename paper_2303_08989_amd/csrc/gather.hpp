@@ -29,4 +29,14 @@ bool gather_map_valid(const GatherMap &gm);
 hipError_t launch_split_gather(const float2 *x, const GatherMap &gm, void *panels, const DevState *st,
                                int which, int forced_mode, int shift, hipStream_t s);
 
+// Full contraction c[0] = sum_i x[perm(i)] * y[i] where d describes the
+// permutation taking x to y's index order (as for launch_permute): x is
+// read through the permutation's bit tile, y in order, products summed in
+// FP32 per block into `partial`, then in a fixed order into c[0].
+// permuted_dot_partials: partials needed (0: not a tiled power-of-two
+// permutation, use the permute instead).
+int64_t permuted_dot_partials(const PermDesc &d);
+hipError_t launch_permuted_dot(const float2 *x, const float2 *y, const PermDesc &d, float2 *partial,
+                               float2 *c, hipStream_t s);
+
 }  // namespace qce

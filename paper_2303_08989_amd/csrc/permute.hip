@@ -13,6 +13,7 @@
 // input offset is the dot product of the output coordinates with the input
 // strides).
 #include "common.hpp"
+#include "gather.hpp"
 
 #include <algorithm>
 #include <cstring>
@@ -132,6 +133,126 @@ __global__ __launch_bounds__(kThreads) void permute_tiled_kernel(const float2 *_
     }
 }
 
+// Full contraction sum_i x[i] * y[i] of two tensors over every label, x in
+// y's index order only after a bit permutation: the tile of that
+// permutation (x the input, y's order the output) is read from x in x's
+// order into LDS, as the permute does, and each thread multiplies the
+// elements it takes in y's order with y's (read in y's order) instead of
+// writing them.  FP32 products and sums, one partial per block, reduced in
+// a fixed order (deterministic).
+template <int E>
+__global__ __launch_bounds__(kThreads) void permuted_dot_kernel(const float2 *__restrict__ x,
+                                                                const float2 *__restrict__ y,
+                                                                float2 *__restrict__ partial, BitTile d) {
+    __shared__ float2 lds[1 << kTileMaxBits];
+    __shared__ float2 red[kThreads / 64];
+    const int64_t bid = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    int64_t bin = 0, bout = 0;
+    for (int i = 0; i < d.nrest; ++i)
+        if ((bid >> i) & 1) {
+            bin += d.rest_in[i];
+            bout += d.rest_out[i];
+        }
+    const int tid = threadIdx.x;
+    int64_t tin = bin;
+    int tsl = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            tin += d.in_u[i];
+            tsl ^= d.su[i];
+        }
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int64_t off = tin;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (((e >> i) & 1) && 8 + i < d.t) off += d.in_u[8 + i];
+        v[e] = x[off];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int sl = tsl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (((e >> i) & 1) && 8 + i < d.t) sl ^= d.su[8 + i];
+        lds[sl] = v[e];
+    }
+    __syncthreads();
+    int64_t tout = bout;
+    tsl = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if ((tid >> i) & 1) {
+            tout += d.out_v[i];
+            tsl ^= d.sv[i];
+        }
+    float2 w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int64_t off = tout;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (((e >> i) & 1) && 8 + i < d.t) off += d.out_v[8 + i];
+        w[e] = y[off];
+    }
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int sl = tsl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (((e >> i) & 1) && 8 + i < d.t) sl ^= d.sv[8 + i];
+        const float2 a = lds[sl], b = w[e];
+        re = fmaf(a.x, b.x, re);
+        re = fmaf(-a.y, b.y, re);
+        im = fmaf(a.x, b.y, im);
+        im = fmaf(a.y, b.x, im);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = make_float2(re, im);
+    __syncthreads();
+    if (tid == 0) {
+        float2 acc = red[0];
+        for (int w2 = 1; w2 < kThreads / 64; ++w2) {
+            acc.x += red[w2].x;
+            acc.y += red[w2].y;
+        }
+        partial[bid] = acc;
+    }
+}
+
+// c[0] = sum of n partials: thread t adds partials t, t + 256, ... in order,
+// then a fixed tree.
+__global__ __launch_bounds__(kThreads) void dot_reduce_kernel(const float2 *__restrict__ partial, int64_t n,
+                                                              float2 *__restrict__ c) {
+    __shared__ float2 red[kThreads / 64];
+    const int tid = threadIdx.x;
+    float re = 0.f, im = 0.f;
+    for (int64_t i = tid; i < n; i += kThreads) {
+        re += partial[i].x;
+        im += partial[i].y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = make_float2(re, im);
+    __syncthreads();
+    if (tid == 0) {
+        float2 acc = red[0];
+        for (int w2 = 1; w2 < kThreads / 64; ++w2) {
+            acc.x += red[w2].x;
+            acc.y += red[w2].y;
+        }
+        c[0] = acc;
+    }
+}
+
 // Tile for a power-of-two permutation, or false when the tensor is too
 // small to tile (fewer than 2^8 elements).
 bool plan_bit_tile(const PermDesc &d, BitTile &b) {
@@ -212,6 +333,33 @@ bool plan_bit_tile(const PermDesc &d, BitTile &b) {
 }
 
 }  // namespace
+
+int64_t permuted_dot_partials(const PermDesc &d) {
+    BitTile bt;
+    if (!d.pow2 || !plan_bit_tile(d, bt)) return 0;
+    return int64_t(1) << bt.nrest;
+}
+
+hipError_t launch_permuted_dot(const float2 *x, const float2 *y, const PermDesc &d, float2 *partial,
+                               float2 *c, hipStream_t s) {
+    BitTile bt;
+    if (!d.pow2 || !plan_bit_tile(d, bt)) return hipErrorInvalidValue;
+    const int64_t nblocks = int64_t(1) << bt.nrest;
+    const unsigned gx = (unsigned)std::min<int64_t>(nblocks, int64_t(1) << 30);
+    const unsigned gy = (unsigned)(nblocks / gx);
+    const dim3 grid(gx, gy);
+    switch (bt.t - 8) {
+    case 0: hipLaunchKernelGGL(permuted_dot_kernel<1>, grid, dim3(kThreads), 0, s, x, y, partial, bt); break;
+    case 1: hipLaunchKernelGGL(permuted_dot_kernel<2>, grid, dim3(kThreads), 0, s, x, y, partial, bt); break;
+    case 2: hipLaunchKernelGGL(permuted_dot_kernel<4>, grid, dim3(kThreads), 0, s, x, y, partial, bt); break;
+    case 3: hipLaunchKernelGGL(permuted_dot_kernel<8>, grid, dim3(kThreads), 0, s, x, y, partial, bt); break;
+    default: hipLaunchKernelGGL(permuted_dot_kernel<16>, grid, dim3(kThreads), 0, s, x, y, partial, bt); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dot_reduce_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, c);
+    return hipGetLastError();
+}
 
 hipError_t launch_permute(const float2 *x, float2 *y, int64_t total, const PermDesc &d,
                           hipStream_t s) {

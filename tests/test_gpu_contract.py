@@ -195,6 +195,37 @@ def test_contract_fused_gather_many_tiles(qce, h, h_unfused, mode, seed):
     assert (dec["mode"], dec["sA"], dec["sB"]) == (dec_ref["mode"], dec_ref["sA"], dec_ref["sB"])
 
 
+@pytest.mark.parametrize("rank", [8, 11, 16, 22])
+def test_contract_full_permuted_dot(qce, h, h_unfused, rank):
+    # every label summed, the two operands in different label orders: one
+    # pass reads one operand through its bit permutation (no permute
+    # launched).  Integer inputs: exact, equal to the permute-then-dot path;
+    # float inputs: FP32 accuracy against the FP64 oracle.
+    rng = np.random.default_rng(500 + rank)
+    la = list(range(rank))
+    lb = [int(v) for v in rng.permutation(rank)]
+    while lb == la:
+        lb = [int(v) for v in rng.permutation(rank)]
+    for ints in (True, False):
+        if ints:
+            A = (rng.integers(-3, 4, (2,) * rank) + 1j * rng.integers(-3, 4, (2,) * rank)).astype(np.complex64)
+            B = (rng.integers(-3, 4, (2,) * rank) + 1j * rng.integers(-3, 4, (2,) * rank)).astype(np.complex64)
+        else:
+            A = (rng.standard_normal((2,) * rank) + 1j * rng.standard_normal((2,) * rank)).astype(np.complex64)
+            B = (rng.standard_normal((2,) * rank) + 1j * rng.standard_normal((2,) * rank)).astype(np.complex64)
+        want = oracle.zcontract(A, la, B, lb, [])
+        got, n_perm, dec = _contract_counted(qce, h, A, la, B, lb, [], "auto")
+        ref, n_perm_ref, _ = _contract_counted(qce, h_unfused, A, la, B, lb, [], "auto")
+        assert dec["mode"] == oracle.MODE_FP32
+        assert n_perm == 0 and n_perm_ref == 1
+        if ints:
+            assert complex(got) == complex(want) == complex(ref)
+        else:
+            scale = float(np.sum(np.abs(A.astype(np.complex128)) * np.abs(np.transpose(B, np.argsort(lb)))))
+            assert abs(complex(got) - complex(want)) <= 4 * rank * 2.0 ** -24 * scale
+            assert abs(complex(ref) - complex(want)) <= 4 * rank * 2.0 ** -24 * scale
+
+
 @pytest.mark.parametrize("layout", ["natural", "swapped", "interleaved", "scalar", "outer"])
 def test_contract_layouts_float(qce, h, layout):
     rng = np.random.default_rng(7)
