@@ -226,16 +226,19 @@ __global__ __launch_bounds__(kThreads) void permuted_dot_kernel(const float2 *__
     }
 }
 
-// c[0] = sum of n partials: thread t adds partials t, t + 256, ... in order,
-// then a fixed tree.
-__global__ __launch_bounds__(kThreads) void dot_reduce_kernel(const float2 *__restrict__ partial, int64_t n,
-                                                              float2 *__restrict__ c) {
-    __shared__ float2 red[kThreads / 64];
+// c[0] = sum of n partials: thread t adds partials t, t + 1024, ... in
+// order (loads unrolled so that several are in flight), then a fixed tree.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void dot_reduce_kernel(const float2 *__restrict__ partial,
+                                                                    int64_t n, float2 *__restrict__ c) {
+    __shared__ float2 red[kReduceThreads / 64];
     const int tid = threadIdx.x;
     float re = 0.f, im = 0.f;
-    for (int64_t i = tid; i < n; i += kThreads) {
-        re += partial[i].x;
-        im += partial[i].y;
+#pragma unroll 8
+    for (int64_t i = tid; i < n; i += kReduceThreads) {
+        const float2 p = partial[i];
+        re += p.x;
+        im += p.y;
     }
     for (int o = 32; o > 0; o >>= 1) {
         re += __shfl_xor(re, o);
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void dot_reduce_kernel(const float2 *__re
     __syncthreads();
     if (tid == 0) {
         float2 acc = red[0];
-        for (int w2 = 1; w2 < kThreads / 64; ++w2) {
+        for (int w2 = 1; w2 < kReduceThreads / 64; ++w2) {
             acc.x += red[w2].x;
             acc.y += red[w2].y;
         }
@@ -357,7 +360,7 @@ hipError_t launch_permuted_dot(const float2 *x, const float2 *y, const PermDesc 
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dot_reduce_kernel, dim3(1), dim3(kThreads), 0, s, partial, nblocks, c);
+    hipLaunchKernelGGL(dot_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, partial, nblocks, c);
     return hipGetLastError();
 }
 

@@ -59,6 +59,13 @@ __device__ inline uint4 pack8(const uint16_t *v) {
 // Operand layouts of the split
 constexpr int kRowsContig = 0, kKContig = 1, kGather = 2;
 
+// LDS slot of tile element (row tr, k-value tq) of a 64 x 64 staging tile:
+// the k index is XORed with the row's low five bits, so that 32 lanes on
+// consecutive rows (the conversion reads) and 32 lanes on consecutive k
+// (the row-run loads) hit distinct 8-byte bank pairs, without padding:
+// 32 KB per block, five blocks per CU.
+__device__ inline int tile_slot(int tr, int tq) { return tr * 64 + (tq ^ (tr & 31)); }
+
 // Panel row r holds P[r][l], l = 0..k-1.  kRowsContig: P[r][l] =
 // x[r + l * ldx] (rows contiguous: op(A) = A, or op(B) = B^T / B^H);
 // kKContig: P[r][l] = x[l + r * ldx] (k contiguous: op(A) = A^T / A^H, or
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
         // Thread t loads the tile elements e = t + 256 i, whose bits are
         // the tile's index bits by increasing stride in x: the low bits of
         // e walk x's lowest bits wherever the tile holds them.
-        __shared__ float2 tile[64][64 + 1];
+        __shared__ float2 tile[64 * 64];
         const int64_t row_blocks = rows_pad / 64;
         const int64_t r0 = (int64_t)(blockIdx.x % row_blocks) * 64;
         const int64_t c0 = (int64_t)(blockIdx.x / row_blocks) * 4;
@@ -112,12 +119,13 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
                     off0 += (int64_t)1 << gm.tsh[b];
                 }
             }
-            int hi_slot[4];
+            int hi_tr[4], hi_tq[4];
             int64_t hi_off[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int b = 8 + j;
-                hi_slot[j] = b < gm.nt ? (gm.tpos[b] < 6 ? (1 << gm.tpos[b]) * 65 : 1 << (gm.tpos[b] - 6)) : 0;
+                hi_tr[j] = b < gm.nt && gm.tpos[b] < 6 ? 1 << gm.tpos[b] : 0;
+                hi_tq[j] = b < gm.nt && gm.tpos[b] >= 6 ? 1 << (gm.tpos[b] - 6) : 0;
                 hi_off[j] = b < gm.nt ? (int64_t)1 << gm.tsh[b] : 0;
             }
             const int ne = 1 << gm.nt;
@@ -132,15 +140,16 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
                     if ((i >> j) & 1) off += hi_off[j];
                 if (i * kThreads + (int)threadIdx.x < ne) v[i] = x[off];
             }
-            float2 *flat = &tile[0][0];
-            const int slot0 = tr0 * 65 + tq0;
 #pragma unroll
             for (int i = 0; i < kE; ++i) {
-                int slot = slot0;
+                int tr = tr0, tq = tq0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if ((i >> j) & 1) slot += hi_slot[j];
-                if (i * kThreads + (int)threadIdx.x < ne) flat[slot] = v[i];
+                    if ((i >> j) & 1) {
+                        tr += hi_tr[j];
+                        tq += hi_tq[j];
+                    }
+                if (i * kThreads + (int)threadIdx.x < ne) tile[tile_slot(tr, tq)] = v[i];
             }
         }
         __syncthreads();
@@ -151,29 +160,34 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
 #pragma unroll
         for (int j = 0; j < kK; ++j) {
             const int64_t l = c * kK + j;
-            const float2 v = r < rows && l < k ? tile[tr][tc * kK + j] : make_float2(0.f, 0.f);
+            const float2 v = r < rows && l < k ? tile[tile_slot(tr, tc * kK + j)] : make_float2(0.f, 0.f);
             re[j] = v.x;
             im[j] = v.y;
         }
     } else if constexpr (LAYOUT == kKContig) {
         // A block takes 64 rows x 4 chunks (64 k-values).  The tile is read
         // in 512-byte row runs (a wave reads one row per load) into LDS,
-        // whose rows are padded by one element so that a wave reading one
-        // k-value of 64 rows hits distinct banks; each thread then takes
-        // one chunk row, with waves on consecutive rows as in the other
-        // layout (whose panel stores are contiguous).
-        __shared__ float2 tile[64][64 + 1];
+        // in the swizzled layout of tile_slot (all 16 loads of a thread are
+        // issued before its LDS stores); each thread then takes one chunk
+        // row, with waves on consecutive rows as in the other layout (whose
+        // panel stores are contiguous).
+        __shared__ float2 tile[64 * 64];
         const int64_t row_blocks = rows_pad / 64;
         const int64_t r0 = (int64_t)(blockIdx.x % row_blocks) * 64;
         const int64_t c0 = (int64_t)(blockIdx.x / row_blocks) * 4;
+        constexpr int kE = 64 * 64 / kThreads;
+        float2 v[kE];
 #pragma unroll
-        for (int i = 0; i < 64 * 64 / kThreads; ++i) {
+        for (int i = 0; i < kE; ++i) {
             const int e = i * kThreads + threadIdx.x;
             const int tr = e >> 6, tq = e & 63;
             const int64_t rr = r0 + tr, l = c0 * kK + tq;
-            float2 v = make_float2(0.f, 0.f);
-            if (rr < rows && l < k) v = x[l + rr * ldx];
-            tile[tr][tq] = v;
+            v[i] = rr < rows && l < k ? x[l + rr * ldx] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            const int e = i * kThreads + threadIdx.x;
+            tile[tile_slot(e >> 6, e & 63)] = v[i];
         }
         __syncthreads();
         const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
         if (c >= nchunks) return;
 #pragma unroll
         for (int j = 0; j < kK; ++j) {
-            const float2 v = tile[tr][tc * kK + j];
+            const float2 v = tile[tile_slot(tr, tc * kK + j)];
             re[j] = v.x;
             im[j] = conj ? -v.y : v.y;
         }
