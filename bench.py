@@ -468,9 +468,11 @@ def run_circuits(h, args, torch, qce, synth):
     # AUTO (t = 0.1, the library's size policy), AUTO at the paper's looser
     # t = 0.5, AUTO under the paper's own size thresholds (2048, 512), and
     # the forced-FP32 baseline
-    for key, mode, t, pol in (("auto", "auto", 0.1, default_policy), ("auto_t05", "auto", 0.5, default_policy),
-                              ("paper_size_policy", "auto", 0.1, (2048, 512)),
-                              ("fp32", "fp32", 0.1, default_policy)):
+    legs = (("auto", "auto", 0.1, default_policy), ("auto_t05", "auto", 0.5, default_policy),
+            ("paper_size_policy", "auto", 0.1, (2048, 512)), ("fp32", "fp32", 0.1, default_policy))
+    if args.c3_auto_only:
+        legs = legs[:1]
+    for key, mode, t, pol in legs:
         h.set_mode(mode)
         h.set_tolerance(t, 0.0)
         h.set_size_policy(*pol)
@@ -492,6 +494,8 @@ def run_circuits(h, args, torch, qce, synth):
     h.set_size_policy(*default_policy)
 
     def fidelity_vs_fp32(key):
+        if key not in res or "fp32" not in res:
+            return None
         fid = qce.fidelity_terms(h, res[key]["vec"], res["fp32"]["vec"]).cpu().numpy()
         return float((fid[0] ** 2 + fid[1] ** 2) / (fid[2] * fid[3])) if fid[2] * fid[3] > 0 else 1.0
 
@@ -507,11 +511,11 @@ def run_circuits(h, args, torch, qce, synth):
                     f"2^{plan3.max_log2}; slice ids 0..{nsl - 1} on this GPU, AUTO (t=0.1) with size policy",
         "plan_seconds": round(t_plan, 1), "slices_run": nsl, "sliced_labels": len(plan3.sliced),
         "seconds": round(t64, 4), "slices_per_s": round(nsl / t64, 2),
-        "fp32_seconds": round(res["fp32"]["seconds"], 4),
-        "speedup_vs_fp32": round(res["fp32"]["seconds"] / t64, 3),
+        "fp32_seconds": round(res["fp32"]["seconds"], 4) if "fp32" in res else None,
+        "speedup_vs_fp32": round(res["fp32"]["seconds"] / t64, 3) if "fp32" in res else None,
         "fidelity_auto_vs_fp32_over_slices": fidelity,
         "partial_amplitude_auto": [float(v) for v in res["auto"]["acc"]],
-        "partial_amplitude_fp32": [float(v) for v in res["fp32"]["acc"]],
+        "partial_amplitude_fp32": [float(v) for v in res["fp32"]["acc"]] if "fp32" in res else None,
         "memoized_tflop_run": round(plan3.varied_cost / 1e12, 2),
         "effective_tflops": round(plan3.varied_cost / t64 / 1e12, 2),
         "one_gpu_seconds_per_amplitude_extrapolated": round(t64 / share, 1),
@@ -519,6 +523,10 @@ def run_circuits(h, args, torch, qce, synth):
         "gpu_ms_by_phase": gpu_ms, "gemms_by_mode": tm["gemms_by_mode"],
         "largest_gemm_log2_mnk": [list(x) for x in big],
         "size_policy": list(default_policy),
+    }
+    if args.c3_auto_only:
+        return out
+    out["config3"].update({
         "paper_size_policy": {"size_policy": [2048, 512],
                               "seconds": round(res["paper_size_policy"]["seconds"], 4),
                               "speedup_vs_fp32": round(res["fp32"]["seconds"] / res["paper_size_policy"]["seconds"], 3),
@@ -528,7 +536,7 @@ def run_circuits(h, args, torch, qce, synth):
                      "speedup_vs_fp32": round(res["fp32"]["seconds"] / res["auto_t05"]["seconds"], 3),
                      "fidelity_vs_fp32_over_slices": fidelity_vs_fp32("auto_t05"),
                      "gemms_by_mode": res["auto_t05"]["timing"]["gemms_by_mode"]},
-    }
+    })
     return out
 
 
@@ -555,6 +563,8 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
     ap.add_argument("--c3-restarts", type=int, default=24)
+    ap.add_argument("--c3-auto-only", action="store_true",
+                    help="53-qubit section: only the AUTO leg (no FP32 / policy comparisons; for profiling)")
     args = ap.parse_args()
     if args.gemm_only:
         args.no_circuits = args.no_irregular = args.no_gradients = args.no_batching = True
