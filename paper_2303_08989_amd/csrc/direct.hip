@@ -133,34 +133,59 @@ __device__ inline float2 scale_out(const DirectArgs &d, float re, float im, floa
     return out;
 }
 
-template <int JT>
+// VEC: A's columns hold its rows contiguously (op(A) = A) and C's rows are
+// contiguous too, both 16-byte aligned with m even: a thread takes two
+// consecutive rows, one 16-byte load per k-value and one 16-byte store per
+// column (each row's products are added in the same order as one row per
+// thread).
+template <int JT, bool VEC>
 __global__ __launch_bounds__(kThreads) void direct_rows_kernel(DirectArgs d) {
+    constexpr int RT = VEC ? 2 : 1;  // rows per thread
     select_entry(d);
-    const int64_t row_blocks = (d.m + kThreads - 1) / kThreads;
+    const int64_t mt = (d.m + RT - 1) / RT;
+    const int64_t row_blocks = (mt + kThreads - 1) / kThreads;
     const int64_t b = blockIdx.x;
-    const int64_t i = (b % row_blocks) * kThreads + threadIdx.x;
+    const int64_t i = ((b % row_blocks) * kThreads + threadIdx.x) * RT;
     const int64_t j0 = (b / row_blocks) * JT;
     if (i >= d.m) return;
-    float re[JT], im[JT];
+    float re[RT][JT], im[RT][JT];
 #pragma unroll
-    for (int jj = 0; jj < JT; ++jj) re[jj] = im[jj] = 0.f;
+    for (int rr = 0; rr < RT; ++rr)
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) re[rr][jj] = im[rr][jj] = 0.f;
     for (int64_t l = 0; l < d.k; ++l) {
-        const float2 a = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i, l);
+        float2 a[RT];
+        if constexpr (VEC) {
+            const float4 v = *reinterpret_cast<const float4 *>(d.A + i + l * d.lda);
+            a[0] = make_float2(v.x, d.a_conj ? -v.y : v.y);
+            a[1] = make_float2(v.z, d.a_conj ? -v.w : v.w);
+        } else {
+            a[0] = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i, l);
+        }
 #pragma unroll
         for (int jj = 0; jj < JT; ++jj) {
             if (j0 + jj >= d.n) break;
             const float2 bv = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j0 + jj, l);
-            re[jj] = fmaf(a.x, bv.x, re[jj]);
-            re[jj] = fmaf(-a.y, bv.y, re[jj]);
-            im[jj] = fmaf(a.x, bv.y, im[jj]);
-            im[jj] = fmaf(a.y, bv.x, im[jj]);
+#pragma unroll
+            for (int rr = 0; rr < RT; ++rr) {
+                re[rr][jj] = fmaf(a[rr].x, bv.x, re[rr][jj]);
+                re[rr][jj] = fmaf(-a[rr].y, bv.y, re[rr][jj]);
+                im[rr][jj] = fmaf(a[rr].x, bv.y, im[rr][jj]);
+                im[rr][jj] = fmaf(a[rr].y, bv.x, im[rr][jj]);
+            }
         }
     }
 #pragma unroll
     for (int jj = 0; jj < JT; ++jj) {
         if (j0 + jj >= d.n) break;
         float2 *cp = d.C + i + (j0 + jj) * d.ldc;
-        *cp = scale_out(d, re[jj], im[jj], cp);
+        if constexpr (VEC) {
+            const float2 o0 = scale_out(d, re[0][jj], im[0][jj], cp);
+            const float2 o1 = scale_out(d, re[1][jj], im[1][jj], cp + 1);
+            *reinterpret_cast<float4 *>(cp) = make_float4(o0.x, o0.y, o1.x, o1.y);
+        } else {
+            *cp = scale_out(d, re[0][jj], im[0][jj], cp);
+        }
     }
 }
 
@@ -261,14 +286,22 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
     const unsigned nz = (unsigned)std::max(1, d.batch);
     if (d.k <= kShortK) {
         if (d.m >= 32) {
+            auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+            const bool vec = !d.a_kcontig && d.lda % 2 == 0 && al16(d.A) && (nz == 1 || d.bsA % 2 == 0) &&
+                             d.m % 2 == 0 && d.ldc % 2 == 0 && al16(d.C) && (nz == 1 || d.bsC % 2 == 0);
             const int jt = std::min(8, pow2_at_least(d.n));
-            const int64_t blocks = ((d.m + kThreads - 1) / kThreads) * ((d.n + jt - 1) / jt);
+            const int64_t mt = vec ? d.m / 2 : d.m;
+            const int64_t blocks = ((mt + kThreads - 1) / kThreads) * ((d.n + jt - 1) / jt);
             const dim3 g((unsigned)blocks, 1, nz), t(kThreads);
-            switch (jt) {
-            case 1: hipLaunchKernelGGL(direct_rows_kernel<1>, g, t, 0, s, d); break;
-            case 2: hipLaunchKernelGGL(direct_rows_kernel<2>, g, t, 0, s, d); break;
-            case 4: hipLaunchKernelGGL(direct_rows_kernel<4>, g, t, 0, s, d); break;
-            default: hipLaunchKernelGGL(direct_rows_kernel<8>, g, t, 0, s, d); break;
+            switch (jt * (vec ? -1 : 1)) {
+            case 1: hipLaunchKernelGGL((direct_rows_kernel<1, false>), g, t, 0, s, d); break;
+            case 2: hipLaunchKernelGGL((direct_rows_kernel<2, false>), g, t, 0, s, d); break;
+            case 4: hipLaunchKernelGGL((direct_rows_kernel<4, false>), g, t, 0, s, d); break;
+            case 8: hipLaunchKernelGGL((direct_rows_kernel<8, false>), g, t, 0, s, d); break;
+            case -1: hipLaunchKernelGGL((direct_rows_kernel<1, true>), g, t, 0, s, d); break;
+            case -2: hipLaunchKernelGGL((direct_rows_kernel<2, true>), g, t, 0, s, d); break;
+            case -4: hipLaunchKernelGGL((direct_rows_kernel<4, true>), g, t, 0, s, d); break;
+            default: hipLaunchKernelGGL((direct_rows_kernel<8, true>), g, t, 0, s, d); break;
             }
         } else {
             const dim3 g((unsigned)((d.n + kThreads - 1) / kThreads), 1, nz), t(kThreads);

@@ -101,10 +101,11 @@ def test_integer_exact(qce, h, mode, m, n, k):
         assert np.array_equal(out[z].astype(np.complex128), oracle.cgemm(As[z], Bs[z])), z
 
 
-@pytest.mark.parametrize("m,n,k", [(6, 2000, 4), (5, 2000, 4)])
+@pytest.mark.parametrize("m,n,k", [(6, 2000, 4), (5, 2000, 4), (64, 50, 4), (66, 9, 3), (33, 9, 3)])
 def test_short_k_columns_even_strides(qce, h, m, n, k):
-    # short k, few rows, entry strides that keep every entry's B and C
-    # 16-byte aligned (even m: two complex values per load and store)
+    # short k, entry strides that keep every entry's operands and C 16-byte
+    # aligned (even m: two complex values per load and store, in the
+    # column kernel below 32 rows and the row kernel from 32)
     rng = np.random.default_rng(m * n + k)
     batch = 3
     As = [synth.random_matrix(m, k, "int", rng) for _ in range(batch)]

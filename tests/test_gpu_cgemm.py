@@ -319,12 +319,14 @@ def test_short_k_ops_alpha_beta(qce, handle, opA, opB, m, n, k):
 
 @pytest.mark.parametrize("shift", [0, 1])
 @pytest.mark.parametrize("m,n,k", [(2, 5000, 2), (6, 3000, 8), (16, 777, 16), (30, 513, 10),
-                                   (7, 300, 8), (6, 300, 5)])
+                                   (7, 300, 8), (6, 300, 5), (64, 300, 8), (1000, 5, 16), (34, 100, 3),
+                                   (33, 70, 2)])
 def test_short_k_columns_alpha_beta(qce, handle, m, n, k, shift):
-    # short k and fewer than 32 rows: one output column per thread. Even m
-    # and k with B and C 16-byte aligned move two complex values per load
-    # and store; odd sizes, or B and C one element off that alignment
-    # (shift), load element by element. Integer inputs: exact either way.
+    # short k: one output column per thread below 32 rows, one or two rows
+    # per thread from 32.  Even sizes with the operands read whole and C
+    # 16-byte aligned move two complex values per load and store; odd
+    # sizes, or B and C one element off that alignment (shift), go element
+    # by element.  Integer inputs: exact either way.
     rng = np.random.default_rng(7 * m + n + k)
     A = synth.random_matrix(m, k, "int", rng)
     B = synth.random_matrix(k, n, "int", rng)
