@@ -1081,10 +1081,11 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     // 2^3 elements (64 bytes) is permuted as before.
     bool gx = false, gy = false;
     GatherMap gmx, gmy;
-    bool all_two = nbt == 0 && h->fused_gather && !irregular_shape(m, n, kk) && (lay_x < 0 || lay_y < 0);
-    for (int i = 0; all_two && i < ra; ++i) all_two = a->extents[i] == 2;
-    for (int i = 0; all_two && i < rb; ++i) all_two = b->extents[i] == 2;
-    if (all_two && rx <= 62 && ry <= 62 && SA.size() <= 31 && SB.size() <= 31 && K.size() <= 31) {
+    bool fuse = nbt == 0 && h->fused_gather && !irregular_shape(m, n, kk) && (lay_x < 0 || lay_y < 0) &&
+                SA.size() <= 31 && SB.size() <= 31 && K.size() <= 31;
+    for (int i = 0; fuse && i < ra; ++i) fuse = a->extents[i] == 2;
+    for (int i = 0; fuse && i < rb; ++i) fuse = b->extents[i] == 2;
+    if (fuse) {
         auto in_last6 = [](const std::vector<int32_t> &v, int32_t lab) {
             for (size_t i = v.size() > 6 ? v.size() - 6 : 0; i < v.size(); ++i)
                 if (v[i] == lab) return true;
