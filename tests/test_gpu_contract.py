@@ -104,14 +104,19 @@ def test_contract_integer_exact(qce, h, mode, seed):
     assert np.array_equal(C.astype(np.complex128), want)
 
 
-def _bits_network(rng, nk, nfa, nfb, ints, natural_out=True):
-    """Every extent 2; K and free labels interleaved at random in A and B."""
+def _bits_network(rng, nk, nfa, nfb, ints, natural_out=True, swapped_out=False):
+    """Every extent 2; K and free labels interleaved at random in A and B.
+    Output order: B's free labels then A's (the GEMM's own order), A's then
+    B's (swapped_out: the GEMM runs with the operands' roles exchanged), or
+    a random order (natural_out False: an output permute)."""
     K = list(range(nk))
     FA = list(range(100, 100 + nfa))
     FB = list(range(200, 200 + nfb))
     la = [int(v) for v in rng.permutation(K + FA)]
     lb = [int(v) for v in rng.permutation(K + FB)]
     lc = [v for v in lb if v in FB] + [v for v in la if v in FA]
+    if swapped_out:
+        lc = [v for v in la if v in FA] + [v for v in lb if v in FB]
     if not natural_out:
         lc = [int(v) for v in rng.permutation(lc)]
 
@@ -158,7 +163,7 @@ def h_unfused(qce):
 
 
 @pytest.mark.parametrize("mode", ["fp32", "auto_emulated", "fp16x2", "bf16x3"])
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(6))
 def test_contract_fused_gather_integer_exact(qce, h, h_unfused, mode, seed):
     # interleaved K and free labels (every extent 2): the split reads each
     # operand through its bit permutation (no permute launched when every
@@ -166,7 +171,7 @@ def test_contract_fused_gather_integer_exact(qce, h, h_unfused, mode, seed):
     # permute-then-split path
     rng = np.random.default_rng(300 + seed)
     nk, nfa, nfb = 4 + seed % 3, 5 + seed % 2, 6 - seed % 2
-    A, la, B, lb, lc = _bits_network(rng, nk, nfa, nfb, ints=True)
+    A, la, B, lb, lc = _bits_network(rng, nk, nfa, nfb, ints=True, swapped_out=seed >= 4)
     want = oracle.zcontract(A, la, B, lb, lc)
     got, n_perm, _ = _contract_counted(qce, h, A, la, B, lb, lc, mode)
     assert np.array_equal(got.astype(np.complex128), want)
