@@ -16,6 +16,8 @@ enter the contraction tree as late as possible.  A node's result is kept
 between slices while the slice labels it depends on are unchanged and its
 parent will need it again (its sibling depends on a label it does not).
 """
+from contextlib import nullcontext
+
 import numpy as np
 
 from . import tn
@@ -92,11 +94,15 @@ class Executor:
                 out[(i, tuple(vals))] = torch.from_numpy(sub).to("cuda")
         return out
 
-    def amplitude(self, x, slice_ids=None, acc=None, slice_out=None):
+    def amplitude(self, x, slice_ids=None, acc=None, slice_out=None, grouped=True):
         """Sum over `slice_ids` (default: all) of the sliced network values,
         accumulated in FP64 on the device.  Returns the device float64[2]
         accumulator.  `slice_out` (device complex64, one entry per slice id)
-        optionally receives each slice's value."""
+        optionally receives each slice's value.  `grouped`: the recomputed
+        steps of a slice run level by level (a step one level above the
+        recomputed steps it consumes), each level inside one library group,
+        so that its small contractions share one launch; otherwise in path
+        order, one launch each."""
         import paper_2303_08989_amd as qce
         torch = self.torch
         p = self.plan
@@ -143,32 +149,52 @@ class Executor:
                     if ch >= L:
                         stack.append(ch)
             vals = {}
-            for s, (a, b) in enumerate(p.path):
-                node = L + s
-                if node not in need:
-                    continue
-                ta = leaf(a) if a < L else (vals.pop(a) if a in vals else cache[a][1])
-                tb = leaf(b) if b < L else (vals.pop(b) if b in vals else cache[b][1])
-                la = p.labels[a] if a < L else self._out_labels[a]
-                lb = p.labels[b] if b < L else self._out_labels[b]
-                shared = set(la) & set(lb)
-                lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
-                self._out_labels[node] = tuple(lc)
-                out = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
-                vals[node] = out
-                # keep when the parent will be recomputed while this node
-                # stays the same (its sibling depends on a varied label it
-                # does not depend on)
-                par = p.parent.get(node)
-                if par is not None and (p.deps[par[1]] - p.deps[node]) & varied:
-                    cache[node] = (key_of(node), out)
-                elif node in cache:
-                    del cache[node]
+            order = [s for s in range(len(p.path)) if L + s in need]
+            if grouped:
+                lev = {}
+                for s in order:
+                    a, b = p.path[s]
+                    lev[L + s] = 1 + max(lev.get(a, 0), lev.get(b, 0))
+                levels = {}
+                for s in order:
+                    levels.setdefault(lev[L + s], []).append(s)
+                batches = [levels[k] for k in sorted(levels)]
+            else:
+                batches = [[s] for s in order]
+            for steps in batches:
+                with (qce.group(self.h) if grouped else nullcontext()):
+                    for s in steps:
+                        self._step(s, leaf, vals, cache, key_of, varied)
             qce.accumulate_f64(self.h, vals[root].reshape(-1)[:1], acc)
             if slice_out is not None:
                 slice_out[n_done:n_done + 1].copy_(vals[root].reshape(-1)[:1])
             n_done += 1
         return acc
+
+    def _step(self, s, leaf, vals, cache, key_of, varied):
+        """Contraction step s of the path for the current slice."""
+        import paper_2303_08989_amd as qce
+        p = self.plan
+        L = len(p.label_sets)
+        node = L + s
+        a, b = p.path[s]
+        ta = leaf(a) if a < L else (vals.pop(a) if a in vals else cache[a][1])
+        tb = leaf(b) if b < L else (vals.pop(b) if b in vals else cache[b][1])
+        la = p.labels[a] if a < L else self._out_labels[a]
+        lb = p.labels[b] if b < L else self._out_labels[b]
+        shared = set(la) & set(lb)
+        lc = [lab for lab in lb if lab not in shared] + [lab for lab in la if lab not in shared]
+        self._out_labels[node] = tuple(lc)
+        out = qce.contract(self.h, ta, list(la), tb, list(lb), lc)
+        vals[node] = out
+        # keep when the parent will be recomputed while this node
+        # stays the same (its sibling depends on a varied label it
+        # does not depend on)
+        par = p.parent.get(node)
+        if par is not None and (p.deps[par[1]] - p.deps[node]) & varied:
+            cache[node] = (key_of(node), out)
+        elif node in cache:
+            del cache[node]
 
 
 class BatchedExecutor:

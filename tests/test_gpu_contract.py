@@ -326,6 +326,36 @@ def test_config1_amplitudes_fp32(qce, h):
     assert np.max(np.abs(got[:3] - tn_want)) < 1e-6 * np.max(np.abs(tn_want)) * 100
 
 
+def test_executor_grouped_levels_match_path_order(qce, h):
+    # a sliced 20-qubit network: the slices' recomputed steps run level by
+    # level with small contractions grouped, or one by one in path order;
+    # both against the FP64 state vector and each other, every slice value
+    from paper_2303_08989_amd.executor import CircuitPlan, Executor
+    c = synth.grid_circuit(4, 5, 10, seed=4, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=12, restarts=2, varied=4)
+    assert len(plan.sliced) >= 2
+    xs = synth.random_bitstrings(20, 3, seed=8)
+    ex = Executor(h, plan)
+    ids = range(min(plan.n_slices, 16))
+    h.set_mode("fp32")
+    try:
+        for x in xs:
+            v = {}
+            for grouped in (True, False):
+                out = torch.empty(len(ids), dtype=torch.complex64, device="cuda")
+                ex.amplitude(x, ids, slice_out=out, grouped=grouped)
+                v[grouped] = out.cpu().numpy().astype(np.complex128)
+            scale = np.max(np.abs(v[False]))
+            assert np.max(np.abs(v[True] - v[False])) <= 1e-5 * scale
+    finally:
+        h.set_mode("auto")
+    got = []
+    for x in xs:
+        got.append(complex(*Executor(h, plan).amplitude(x).cpu().numpy()))
+    want = oracle.statevector_amplitudes(rounded(c), xs)
+    assert oracle.fidelity(np.array(got), want) >= 1 - 1e-6
+
+
 def test_ghz_and_identity_closed_forms(qce, h):
     n = 8
     got, _ = _amplitudes(qce, h, synth.ghz_circuit(n), [0, (1 << n) - 1, 5])
