@@ -77,21 +77,28 @@ class Executor:
 
     def _leaf_variants(self, x):
         """Device tensors of every leaf for bitstring x, with all variants of
-        leaves that carry sliced labels: {(leaf, values): tensor}."""
+        leaves that carry sliced labels: {(leaf, values): tensor}.  They are
+        views of one device buffer filled by a single host-to-device copy."""
         torch = self.torch
         p = self.plan
         leaves = tn.circuit_network(p.circuit, x)
         S = p.sliced
         pos = {lab: i for i, lab in enumerate(S)}
-        out = {}
+        host = []
         for i, (arr, labels) in enumerate(leaves):
             sl = [lab for lab in labels if lab in pos]
             if not sl:
-                out[(i, ())] = torch.from_numpy(np.ascontiguousarray(arr)).to("cuda")
+                host.append(((i, ()), np.ascontiguousarray(arr)))
                 continue
             for vals in np.ndindex(*(2,) * len(sl)):
-                sub = tn.fix_labels(arr, labels, dict(zip(sl, vals)))
-                out[(i, tuple(vals))] = torch.from_numpy(sub).to("cuda")
+                host.append(((i, tuple(vals)), tn.fix_labels(arr, labels, dict(zip(sl, vals)))))
+        flat = np.concatenate([a.reshape(-1) for _, a in host]).astype(np.complex64, copy=False)
+        dev = torch.from_numpy(flat).to("cuda")
+        out = {}
+        off = 0
+        for key, a in host:
+            out[key] = dev[off:off + a.size].view(a.shape)
+            off += a.size
         return out
 
     def amplitude(self, x, slice_ids=None, acc=None, slice_out=None, grouped=True):
