@@ -570,7 +570,7 @@ def main():
         args.no_circuits = args.no_irregular = args.no_gradients = args.no_batching = True
         args.no_random_tn = True
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs on a "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on a "
               "single MI355X and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
