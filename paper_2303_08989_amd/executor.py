@@ -65,14 +65,32 @@ class CircuitPlan:
         return 1 << len(self.sliced)
 
 
-class Executor:
-    """Runs a CircuitPlan on one GPU through the C-ABI."""
+def level_batches(path, n_leaves, steps):
+    """The path steps `steps` (ascending) in tree levels: a step is one level
+    above the highest of its operands computed among `steps` (leaves and
+    nodes computed earlier count as level 0), so the steps of one level are
+    independent of each other and every operand of a level is ready before
+    it.  Returns the levels in order, each a list of steps in path order."""
+    lev = {}
+    for s in steps:
+        a, b = path[s]
+        lev[n_leaves + s] = 1 + max(lev.get(a, 0), lev.get(b, 0))
+    levels = {}
+    for s in steps:
+        levels.setdefault(lev[n_leaves + s], []).append(s)
+    return [levels[k] for k in sorted(levels)]
 
-    def __init__(self, handle, plan):
+
+class Executor:
+    """Runs a CircuitPlan on one GPU through the C-ABI.  (`device` "cpu" is
+    for tests of the host logic with a stand-in contraction.)"""
+
+    def __init__(self, handle, plan, device="cuda"):
         import torch
         self.torch = torch
         self.h = handle
         self.plan = plan
+        self.device = device
         self._out_labels = {}
 
     def _leaf_variants(self, x):
@@ -93,7 +111,7 @@ class Executor:
             for vals in np.ndindex(*(2,) * len(sl)):
                 host.append(((i, tuple(vals)), tn.fix_labels(arr, labels, dict(zip(sl, vals)))))
         flat = np.concatenate([a.reshape(-1) for _, a in host]).astype(np.complex64, copy=False)
-        dev = torch.from_numpy(flat).to("cuda")
+        dev = torch.from_numpy(flat).to(self.device)
         out = {}
         off = 0
         for key, a in host:
@@ -116,7 +134,7 @@ class Executor:
         if slice_ids is None:
             slice_ids = range(p.n_slices)
         if acc is None:
-            acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+            acc = torch.zeros(2, dtype=torch.float64, device=self.device)
         leaves = self._leaf_variants(x)
         L = len(p.label_sets)
         pos = {lab: i for i, lab in enumerate(p.sliced)}
@@ -157,19 +175,9 @@ class Executor:
                         stack.append(ch)
             vals = {}
             order = [s for s in range(len(p.path)) if L + s in need]
-            if grouped:
-                lev = {}
-                for s in order:
-                    a, b = p.path[s]
-                    lev[L + s] = 1 + max(lev.get(a, 0), lev.get(b, 0))
-                levels = {}
-                for s in order:
-                    levels.setdefault(lev[L + s], []).append(s)
-                batches = [levels[k] for k in sorted(levels)]
-            else:
-                batches = [[s] for s in order]
+            batches = level_batches(p.path, L, order) if grouped else [[s] for s in order]
             for steps in batches:
-                with (qce.group(self.h) if grouped else nullcontext()):
+                with (qce.group(self.h) if grouped and self.device != "cpu" else nullcontext()):
                     for s in steps:
                         self._step(s, leaf, vals, cache, key_of, varied)
             qce.accumulate_f64(self.h, vals[root].reshape(-1)[:1], acc)

@@ -66,6 +66,53 @@ def test_outer_ids_partition_the_slices(standin):
     assert abs(sum(parts) - whole) < 1e-12
 
 
+def test_level_batches_order_operands_first():
+    # every step's operands computed among the steps come from an earlier
+    # level; the levels partition the steps, each level in path order
+    from paper_2303_08989_amd.executor import CircuitPlan, level_batches
+    c = synth.grid_circuit(3, 4, 6, seed=2, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=30, restarts=1)
+    L = len(plan.label_sets)
+    rng = np.random.default_rng(0)
+    for steps in (list(range(len(plan.path))),
+                  sorted(int(s) for s in rng.choice(len(plan.path), len(plan.path) // 2, replace=False))):
+        levels = level_batches(plan.path, L, steps)
+        assert sorted(s for lev in levels for s in lev) == steps
+        where = {L + s: k for k, lev in enumerate(levels) for s in lev}
+        for k, lev in enumerate(levels):
+            assert lev == sorted(lev)
+            for s in lev:
+                for ch in plan.path[s]:
+                    if ch in where:
+                        assert where[ch] < k
+
+
+@pytest.mark.parametrize("grouped", [True, False])
+def test_executor_memoized_slices_match_oracle(standin, monkeypatch, grouped):
+    # the sliced executor (subtrees cached across slices while their labels
+    # keep their values) with level order or path order, summed over every
+    # slice, against the FP64 state vector; and the per-slice values add up
+    import paper_2303_08989_amd as qce
+    from paper_2303_08989_amd.executor import CircuitPlan, Executor
+
+    def acc1(h, src, dst):
+        v = complex(src.numpy().astype(np.complex128).reshape(-1)[0])
+        dst[0] += v.real
+        dst[1] += v.imag
+    monkeypatch.setattr(qce, "accumulate_f64", acc1)
+    c = synth.grid_circuit(3, 4, 6, seed=3, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=3, restarts=1, varied=3)
+    assert len(plan.sliced) >= 3 and plan.varied
+    ex = Executor(None, plan, device="cpu")
+    xs = synth.random_bitstrings(12, 3, seed=4)
+    want = oracle.statevector_amplitudes(_rounded(c), xs)
+    for x, w in zip(xs, want):
+        out = torch.zeros(plan.n_slices, dtype=torch.complex128)
+        acc = ex.amplitude(x, slice_out=out, grouped=grouped).numpy()
+        assert abs(complex(acc[0], acc[1]) - w) < 1e-6 * max(abs(w), 1e-3)
+        assert abs(complex(out.sum()) - complex(acc[0], acc[1])) < 1e-9
+
+
 def test_fix_labels_keeps_rank():
     from paper_2303_08989_amd import tn
     arr = np.arange(8, dtype=np.complex64).reshape(2, 2, 2)
