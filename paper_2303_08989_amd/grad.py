@@ -228,14 +228,16 @@ class GradientRunner:
             root = L + len(p.path) - 1
             qce.accumulate_f64(self.h, node_val[root].reshape(-1)[:1], acc_a)
             # reverse pass, one group per depth below the root
-            adj = {root: one}
-            pending = []          # (E of an fSim leaf, leaf) awaiting its derivative contraction
+            # adjoints keep the contraction's own output order (no output
+            # permute); adj_lab holds each adjoint's label order
+            adj, adj_lab = {root: one}, {root: ()}
+            pending = []          # (E of an fSim leaf, its labels, leaf) awaiting its derivative contraction
             for level in rev_levels + [[]]:
                 sg = []
                 with group():
-                    for E_g, g in pending:
+                    for E_g, lab_g, g in pending:
                         dG = dvals[g][key(g)]
-                        sg.append((qce.contract(self.h, E_g, list(node_lab[g]), dG, list(node_lab[g]), []),
+                        sg.append((qce.contract(self.h, E_g, list(lab_g), dG, list(node_lab[g]), []),
                                    self.fsim_leaf[g][0]))
                     pending = []
                     for s in level:
@@ -244,17 +246,22 @@ class GradientRunner:
                         a, b = p.path[s]
                         if E is None:
                             continue
+                        E_lab = adj_lab.pop(node)
                         for ch, other in ((a, b), (b, a)):
                             if not self.has_param[ch]:
                                 continue
                             t_other = leaf(other) if other < L else node_val[other]
-                            E_ch = qce.contract(self.h, E, list(node_lab[node]), t_other,
-                                                list(node_lab[other]), list(node_lab[ch]))
-                            self.flops += _flops(E, t_other, node_lab[node], node_lab[other])
+                            lo = node_lab[other]
+                            # the child's labels: the other operand's labels it
+                            # shares, then the adjoint's labels the other lacks
+                            lc = [lab for lab in lo if lab not in E_lab] + [lab for lab in E_lab if lab not in lo]
+                            E_ch = qce.contract(self.h, E, list(E_lab), t_other, list(lo), lc)
+                            self.flops += _flops(E, t_other, E_lab, lo)
                             if ch < L:
-                                pending.append((E_ch, ch))
+                                pending.append((E_ch, tuple(lc), ch))
                             else:
                                 adj[ch] = E_ch
+                                adj_lab[ch] = tuple(lc)
                 for s_g, cpl in sg:
                     qce.accumulate_f64(self.h, s_g.reshape(-1)[:1], acc_d[cpl])
                 # the forward values this depth consumed are no longer needed
