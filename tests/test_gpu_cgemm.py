@@ -343,6 +343,21 @@ def test_short_k_columns_alpha_beta(qce, handle, m, n, k, shift):
     assert np.array_equal(host(dC, m, n).astype(np.complex128), want)
 
 
+@pytest.mark.parametrize("opA", ["N", "T"])
+@pytest.mark.parametrize("m,n,k", [(8, 1, 70000), (24, 1, 5000), (100, 1, 3000), (500, 31, 600)])
+def test_long_k_thin_outputs_alpha_beta(qce, handle, opA, m, n, k):
+    # long k, thin outputs (GEMV-like, as the root of a batched slice pass),
+    # A stored both ways: integer inputs exact with alpha and beta
+    rng = np.random.default_rng(m + n + k)
+    sa, sb = shapes_of(m, n, k, opA, "N")
+    A = synth.random_matrix(*sa, "int", rng)
+    B = synth.random_matrix(*sb, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    C, _ = run(qce, handle, A, B, m, n, k, opA, "N", alpha=complex(1, -1), beta=complex(2, 0), C0=C0)
+    want = oracle.cgemm(A, B, opA, "N", alpha=complex(1, -1), beta=complex(2, 0), C0=C0)
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1 << 22), (20000, 3, 5), (8, 9, 300000)])
 def test_irregular_float_accuracy(qce, handle, m, n, k):
     A, B = synth.gemm_operands(m, n, k, "a", seed=31)
