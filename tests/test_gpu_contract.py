@@ -200,7 +200,7 @@ def test_contract_fused_gather_many_tiles(qce, h, h_unfused, mode, seed):
     assert (dec["mode"], dec["sA"], dec["sB"]) == (dec_ref["mode"], dec_ref["sA"], dec_ref["sB"])
 
 
-@pytest.mark.parametrize("rank", [8, 11, 16, 22])
+@pytest.mark.parametrize("rank", [8, 11, 16, 22, 26])
 def test_contract_full_permuted_dot(qce, h, h_unfused, rank):
     # every label summed, the two operands in different label orders: one
     # pass reads one operand through its bit permutation (no permute
@@ -211,7 +211,9 @@ def test_contract_full_permuted_dot(qce, h, h_unfused, rank):
     lb = [int(v) for v in rng.permutation(rank)]
     while lb == la:
         lb = [int(v) for v in rng.permutation(rank)]
-    for ints in (True, False):
+    # integer sums stay exact in FP32 up to rank 22; rank 26 (the size of
+    # the last step of a 53-qubit slice) checks floats only
+    for ints in ((True, False) if rank <= 22 else (False,)):
         if ints:
             A = (rng.integers(-3, 4, (2,) * rank) + 1j * rng.integers(-3, 4, (2,) * rank)).astype(np.complex64)
             B = (rng.integers(-3, 4, (2,) * rank) + 1j * rng.integers(-3, 4, (2,) * rank)).astype(np.complex64)
