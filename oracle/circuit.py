@@ -133,22 +133,26 @@ def fsim_theta_derivative(theta, phi):
     return d
 
 
-def probability_theta_gradient(circuit, bitstrings, n_couplers=None):
+def probability_theta_gradient(circuit, bitstrings, n_couplers=None, couplers=None):
     """Amplitudes a_x and the gradient of p_x = |a_x|^2 with respect to the
     per-coupler fSim angles theta_e, in complex128.
 
     U is the product of the circuit's gates, so by the product rule
     dU/dtheta_e is the sum, over the fSim gates g on coupler e, of U with g
     replaced by dg/dtheta; then dp/dtheta_e = 2 Re(conj(a) da/dtheta_e).
-    Each replaced circuit is evaluated by the state vector.  Returns
-    (a of shape (X,), grad of shape (X, n_couplers))."""
+    Each replaced circuit is evaluated by the state vector.  ``couplers``
+    (optional) limits the work to those couplers' columns; the other columns
+    stay 0.  Returns (a of shape (X,), grad of shape (X, n_couplers))."""
     gates = circuit["gates"]
     if n_couplers is None:
         n_couplers = circuit.get("n_couplers", 1 + max(g["coupler"] for g in gates if "coupler" in g))
+    wanted = None if couplers is None else set(int(e) for e in couplers)
     a = statevector_amplitudes(circuit, bitstrings)
     grad = np.zeros((len(bitstrings), n_couplers), dtype=np.float64)
     for gi, g in enumerate(gates):
         if g.get("name") != "fsim" or "coupler" not in g:
+            continue
+        if wanted is not None and g["coupler"] not in wanted:
             continue
         mod = dict(circuit)
         mod["gates"] = list(gates)

@@ -85,3 +85,19 @@ def test_shared_coupler_sums_occurrences():
         return np.abs(oracle.statevector_amplitudes(cc, xs)) ** 2
     fd = (probs(th + h) - probs(th - h)) / (2 * h)
     assert np.max(np.abs(fd - g[:, 0])) < 1e-9
+
+
+def test_coupler_subset_equals_full_columns():
+    # restricting the product rule to some couplers gives exactly those
+    # columns of the full gradient (and zeros elsewhere)
+    base = synth.grid_circuit(2, 3, 5, seed=3, pattern="ABCD")
+    ne = base["n_couplers"]
+    c = synth.with_thetas(base, synth.coupler_thetas(ne, seed=3).astype(np.float64))
+    xs = synth.random_bitstrings(c["n"], 4, seed=1)
+    a_full, g_full = oracle.probability_theta_gradient(c, xs, ne)
+    sub = [0, ne - 1]
+    a_sub, g_sub = oracle.probability_theta_gradient(c, xs, ne, couplers=sub)
+    assert np.array_equal(a_full, a_sub)
+    assert np.array_equal(g_sub[:, sub], g_full[:, sub])
+    rest = [e for e in range(ne) if e not in sub]
+    assert not g_sub[:, rest].any()
