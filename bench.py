@@ -137,6 +137,82 @@ def run_irregular(h, torch, qce, reps=10):
     return out
 
 
+def run_protocol(h, args, torch, qce, synth, data):
+    """Per-case timing under the measurement protocol: every (shape,
+    distribution) case with seeds 0, 1, 2 (seed 0 is the headline step's
+    operands), hipEvent time of each call on the library's stream, median
+    over the repetitions, and a 512 MiB buffer write before each repetition
+    so that the 256 MB Infinity Cache does not serve the operands.  The
+    AUTO call, the library's FP32 mode and rocBLAS (torch.matmul) run under
+    the same protocol."""
+    from synth.gemm_inputs import case_seed
+    flush = torch.empty(512 << 18, dtype=torch.float32, device="cuda")   # 512 MiB
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = args.protocol_reps
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        ts = []
+        for r in range(reps):
+            flush.fill_(float(r))
+            ev0.record()
+            fn()
+            ev1.record()
+            ev1.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        return ts
+
+    cases = []
+    for c in data:
+        si = SHAPES.index((c["m"], c["n"], c["k"]))
+        m, n, k = c["m"], c["n"], c["k"]
+        per_seed = []
+        all_auto, all_best = [], []
+        for rep in range(args.protocol_seeds):
+            if rep == 0:
+                dA, dB, dC = c["dA"], c["dB"], c["dC"]
+            else:
+                A, B = synth.gemm_operands(m, n, k, c["dist"], case_seed(c["dist"], si, rep))
+                dA = torch.from_numpy(np.asfortranarray(A).ravel(order="F")).to("cuda")
+                dB = torch.from_numpy(np.asfortranarray(B).ravel(order="F")).to("cuda")
+                dC = torch.empty(m * n, dtype=torch.complex64, device="cuda")
+                del A, B
+
+            def gemm(mode):
+                h.set_mode(mode)
+                return lambda: qce.cgemm(h, "N", "N", m, n, k, dA, m, dB, k, dC, m)
+
+            t_auto = timed(gemm("auto"))
+            dec = h.last_decision()
+            t_lib = timed(gemm("fp32"))
+            h.set_mode("auto")
+            tA = dA.view(k, m)
+            tB = dB.view(n, k)
+            out = torch.empty((n, m), dtype=torch.complex64, device="cuda")
+            t_rb = timed(lambda: torch.matmul(tB, tA, out=out))
+            med = lambda v: float(np.median(v))  # noqa: E731
+            per_seed.append({"seed": case_seed(c["dist"], si, rep), "mode": dec["mode_name"],
+                             "auto_ms": round(med(t_auto), 5), "fp32_lib_ms": round(med(t_lib), 5),
+                             "rocblas_ms": round(med(t_rb), 5)})
+            all_auto += t_auto
+            all_best.append(min(med(t_lib), med(t_rb)))
+            del out
+            if rep:
+                del dA, dB, dC
+        med_auto = float(np.median(all_auto))
+        best = float(np.median(all_best))
+        eff = 8.0 * m * n * k
+        cases.append({"shape": [m, n, k], "dist": c["dist"], "median_ms": round(med_auto, 5),
+                      "tflops": round(eff / (med_auto * 1e-3) / 1e12, 3),
+                      "median_best_fp32_ms": round(best, 5),
+                      "speedup_vs_best_fp32": round(best / med_auto, 3), "seeds": per_seed})
+    del flush
+    torch.cuda.synchronize()
+    return {"reps_per_seed": reps, "seeds": args.protocol_seeds, "flush_bytes": 512 << 20,
+            "statistic": "median of hipEvent times per call", "cases": cases}
+
+
 def run_gradients(h, args, torch, qce, synth):
     """Gradients of |<x|U|0>|^2 with respect to the per-coupler fSim angles
     of a 30-qubit 5x6 grid circuit, depth 14, for a batch of bitstrings:
@@ -563,12 +639,17 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
     ap.add_argument("--c3-restarts", type=int, default=24)
+    ap.add_argument("--no-protocol", action="store_true",
+                    help="skip the per-case median / cache-flush / three-seed timing section")
+    ap.add_argument("--protocol-reps", type=int, default=20)
+    ap.add_argument("--protocol-seeds", type=int, default=3)
     ap.add_argument("--c3-auto-only", action="store_true",
                     help="53-qubit section: only the AUTO leg (no FP32 / policy comparisons; for profiling)")
     args = ap.parse_args()
     if args.gemm_only:
         args.no_circuits = args.no_irregular = args.no_gradients = args.no_batching = True
         args.no_random_tn = True
+        args.no_protocol = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on a "
               "single MI355X and has no multi-GPU path.", file=sys.stderr)
@@ -753,13 +834,22 @@ def main():
         return round(1024.0 * (ent["fetch_kib_raw"] * cal["fetch_factor"] +
                                ent["write_kib_raw"] * cal["write_factor"]))
 
+    def set_traffic(r):
+        r["traffic"] = measured_traffic(r)
+        r["traffic_source"] = ("taken from the committed rocprofv3 counter summary profiles/hbm_traffic.json "
+                               "(FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per dispatch, same kernel sources), "
+                               "not measured in this run") if r["traffic"] is not None else None
+
     roof = roofline(dominant) if dominant is not None else None
     if roof is not None:
-        roof["traffic"] = measured_traffic(roof)
+        set_traffic(roof)
     roof_by_kernel = {KERNEL_OF_PHASE[p]: roofline(r) for p, r in per_kernel.items()}
     for r in roof_by_kernel.values():
-        r["traffic"] = measured_traffic(r)
+        set_traffic(r)
+    # the emulated hot path's kernels against the FP16 / BF16 MFMA peak
+    roof_emulated = {k2: v for k2, v in roof_by_kernel.items() if "fp32" not in k2}
 
+    protocol = None if args.no_protocol else run_protocol(h, args, torch, qce, synth, data)
     irregular = None if args.no_irregular else run_irregular(h, torch, qce)
     gradients = None if args.no_gradients else run_gradients(h, args, torch, qce, synth)
     batching = None if args.no_batching else run_batching(h, args, torch, qce, synth)
@@ -823,6 +913,8 @@ def main():
                    "gemms_per_step": len(data), "eff_flops_per_step": flops_step},
         "roofline": roof, "cpu_baseline": cpu, "fp32_baseline": base or None,
         "roofline_by_kernel": roof_by_kernel,
+        "roofline_emulated": roof_emulated,
+        "protocol": protocol,
         "amplitudes": circuits,
         "irregular": irregular,
         "gradients": gradients,
