@@ -94,8 +94,8 @@ typedef struct {
  *   n1         components with floor(log2|v|) >= -14 (stage 1: above the
  *              smallest normal FP16)
  *   n2         components with floor(log2|v|) >= emax - 28 (stage 2: inside
- *              the FP16 exponent window once emax is shifted to 14); -1 when
- *              stage 2 was not needed for that operand
+ *              the FP16 exponent window once emax is shifted to 14; taken in
+ *              the same pass as the other counts); -1 when no statistics ran
  *   n3         components with floor(log2|v|) >= -110 (BF16X3 floor)
  *   nonfinite  Inf/NaN components
  *   emax       largest floor(log2|v|) (INT32_MIN when nnz == 0)
@@ -126,6 +126,9 @@ typedef struct {
  *   QCE_EMUL_MIN_DIM   size policy threshold for emulation, default 512
  *   QCE_FUSED_GATHER   1 (default) or 0: permute fused into the split in
  *                      qce_contract
+ *   QCE_SMALLK         1 (default) or 0: GEMMs with k <= 128 and n <= 64
+ *                      split their operands as they load them (no panel
+ *                      pass); 0 sends them through the panel path
  * The stream is the device's null stream until qce_set_stream.
  * Errors: INVALID_VALUE (h NULL, bad device or bad environment value),
  * ALLOC, HIP.
@@ -389,6 +392,41 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
  */
 qce_status qce_split(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 *x, int64_t n,
                      uint16_t *planes);
+
+/*
+ * The panel writer every GEMM of the library runs (the split of Sec. 2.1,
+ * Eq. 2, with the shift of Sec. 4.2), on its own for tests.  It writes the
+ * operand P (rows x k) in the library's internal panel format:
+ *   chunk (b, c) holds rows 128b..128b+127 and k-values 16c..16c+15 and
+ *   starts at byte (b * ceil(k/16) + c) * chunk_bytes;
+ *   inside a chunk, plane p, row r (0..127) and 16-byte granule g (k-values
+ *   g*E..g*E+E-1, E = 8 two-byte or 4 four-byte values) sit at byte
+ *   p * 128 * R + r * R + 16 * (g XOR swz(r)), R = 32 (two-byte planes) or
+ *   64 (FP32 planes); swz(r) = ((r >> 2) ^ (r >> 3)) & 1 for two granules
+ *   per row, and ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1) for
+ *   four;
+ *   planes: FP16X2 / FP16X2_SCALED: hi(re), lo(re), hi(im), lo(im) (FP16
+ *   bits of x' = x * 2^shift and of (x' - hi) * 2^11); BF16X3: b0, b1, b2 of
+ *   re, then of im (bfloat16 bits); FP32: re, im (FP32 bits);
+ *   rows >= rows and k-values >= k are zero.
+ * qce_split_panels: layout 0 reads P[r][l] = X[r + l*ld] (ld >= rows),
+ *   layout 1 reads P[r][l] = X[l + r*ld] (ld >= k); conj != 0 negates the
+ *   imaginary part.  X: device complex64, 8-byte aligned.
+ * qce_split_panels_bitmap: the transpose-fused layout of qce_contract:
+ *   P[r][l] = X[sum_t bit_t(r) 2^rsh[t] + sum_t bit_t(l) 2^ksh[t]] for a
+ *   dense tensor X of 2^(nr+nk) elements (rows = 2^nr, k = 2^nk); rsh (nr
+ *   entries) and ksh (nk entries), host arrays, together a permutation of
+ *   0..nr+nk-1; 5 <= nr <= 31, 4 <= nk <= 31, nr + nk <= 40.
+ * mode: FP16X2 (shift 0), FP16X2_SCALED (any shift in [-150, 150]), BF16X3
+ * or FP32 (shift 0), else INVALID_VALUE.  panels: device, 16-byte aligned,
+ * qce_panel_bytes(mode, rows, k) bytes, written completely (padding
+ * included).  Enqueued on the handle's stream.
+ */
+size_t qce_panel_bytes(qce_mode mode, int64_t rows, int64_t k);
+qce_status qce_split_panels(qce_handle *h, qce_mode mode, int32_t shift, int32_t layout, int32_t conj,
+                            const qce_c32 *X, int64_t rows, int64_t k, int64_t ld, void *panels);
+qce_status qce_split_panels_bitmap(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 *X, int32_t nr,
+                                   int32_t nk, const int32_t *rsh, const int32_t *ksh, void *panels);
 
 /* ---------------------------------------------------------------------- */
 /* Timing and decision log (opt-in tracing)                               */

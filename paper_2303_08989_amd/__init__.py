@@ -319,3 +319,30 @@ def split(h, mode, shift, x):
     hh = h._bind_stream()
     _check(hh, h.lib.qce_split(hh, mode, int(shift), _ptr(x), int(x.numel()), _ptr(out)))
     return out
+
+
+def split_panels(h, mode, shift, X, rows, k, ld, layout=0, conj=False):
+    """The GEMM path's panel writer on one operand (C-ABI
+    ``qce_split_panels``): uint8 device tensor in the panel format."""
+    torch = _torch()
+    mode = _mode_value(mode)
+    nbytes = int(h.lib.qce_panel_bytes(mode, int(rows), int(k)))
+    out = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=X.device)
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_split_panels(hh, mode, int(shift), int(layout), 1 if conj else 0, _ptr(X),
+                                      int(rows), int(k), int(ld), _ptr(out)))
+    return out[:nbytes]
+
+
+def split_panels_bitmap(h, mode, shift, X, rsh, ksh):
+    """The transpose-fused panel writer (C-ABI ``qce_split_panels_bitmap``):
+    P[r][l] = X[sum bit_t(r) 2^rsh[t] + sum bit_t(l) 2^ksh[t]]."""
+    torch = _torch()
+    mode = _mode_value(mode)
+    nr, nk = len(rsh), len(ksh)
+    nbytes = int(h.lib.qce_panel_bytes(mode, 1 << nr, 1 << nk))
+    out = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=X.device)
+    hh = h._bind_stream()
+    _check(hh, h.lib.qce_split_panels_bitmap(hh, mode, int(shift), _ptr(X), nr, nk, _labels(rsh),
+                                             _labels(ksh), _ptr(out)))
+    return out[:nbytes]

@@ -25,7 +25,8 @@ EXPORTS = (
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
     "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_get_batch_decision",
     "qce_contract", "qce_group_begin", "qce_group_end", "qce_group_reset", "qce_permute", "qce_accumulate_f64", "qce_accumulate_n_f64", "qce_fidelity_f64",
-    "qce_expstats", "qce_split", "qce_status_string", "qce_last_error",
+    "qce_expstats", "qce_split", "qce_panel_bytes", "qce_split_panels", "qce_split_panels_bitmap",
+    "qce_status_string", "qce_last_error",
     "qce_set_timing", "qce_set_timing_tag", "qce_reset_timing", "qce_get_timing",
 )
 
@@ -104,6 +105,9 @@ def load():
         "qce_fidelity_f64": (st, [vp, vp, vp, i64, vp]),
         "qce_expstats": (st, [vp, vp, i64, i64, i64, ctypes.POINTER(QceDecision)]),
         "qce_split": (st, [vp, ctypes.c_int, i32, vp, i64, vp]),
+        "qce_panel_bytes": (ctypes.c_size_t, [ctypes.c_int, i64, i64]),
+        "qce_split_panels": (st, [vp, ctypes.c_int, i32, i32, i32, vp, i64, i64, i64, vp]),
+        "qce_split_panels_bitmap": (st, [vp, ctypes.c_int, i32, vp, i32, i32, i32p, i32p, vp]),
         "qce_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "qce_last_error": (ctypes.c_char_p, [vp]),
         "qce_set_timing": (st, [vp, ctypes.c_int]),

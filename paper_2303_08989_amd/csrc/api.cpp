@@ -23,6 +23,7 @@ struct qce_handle {
     // min(m, n, k) = 512 (the paper's A100 values are 2048 and 512)
     int64_t auto_min = 512, emul_min = 512;
     DevState *st = nullptr;        // device
+    unsigned int *arrived = nullptr;  // device, kMaxBatch + 1 zeroed arrival counters of the statistics launch
     DevState *dec_base = nullptr;  // decisions of the last call (st, or a batch's states in the workspace)
     int dec_count = 1;
     double *fid_partials = nullptr;  // device, kFidBlocks * 4
@@ -55,6 +56,7 @@ struct qce_handle {
     // grouped small contractions (qce_group_begin / qce_group_end)
     bool grouping = false;
     bool fused_gather = true;  // permute fused into the split (qce_contract)
+    bool smallk = true;        // short-k narrow GEMMs split on load (no panel pass)
     std::vector<qce::SmallItem> pending;
     char *grp_dev = nullptr;   // descriptor arena on the device
     char *grp_host = nullptr;  // its pinned host mirror (source of the copies)
@@ -282,7 +284,7 @@ struct Batch {
 // Workspace of one (batched) GEMM: panels of every entry, split-k partial
 // tiles, and for a batch the per-entry device states.
 struct CgemmWs {
-    size_t pa = 0, pb = 0, panels = 0, partial = 0, states = 0, total = 0;
+    size_t pa = 0, pb = 0, panels = 0, partial = 0, states = 0, records = 0, total = 0;
 };
 CgemmWs cgemm_ws_layout(int64_t m, int64_t n, int64_t k, int count) {
     CgemmWs w;
@@ -296,7 +298,10 @@ CgemmWs cgemm_ws_layout(int64_t m, int64_t n, int64_t k, int count) {
     w.panels = (w.pa + w.pb) * (size_t)count;
     w.partial = align256(gemm_partial_bytes(m, n, k, count) * (size_t)count);
     w.states = count > 1 ? align256(sizeof(DevState) * (size_t)count) : 0;
-    w.total = w.panels + w.partial + w.states;
+    // statistics block records (bounded over every leading dimension)
+    w.records = align256(sizeof(StatsRecord) * (size_t)(stats_blocks_bound(m, k) + stats_blocks_bound(k, n)) *
+                         (size_t)count);
+    w.total = w.panels + w.partial + w.states + w.records;
     return w;
 }
 
@@ -370,6 +375,7 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     char *panB = panA + wl.pa * (size_t)bt.count;
     char *part = ws + wl.panels;
     DevState *dst = batched ? reinterpret_cast<DevState *>(ws + wl.panels + wl.partial) : h->st;
+    StatsRecord *rec = reinterpret_cast<StatsRecord *>(ws + wl.panels + wl.partial + wl.states);
     h->dec_base = dst;
     MatDesc da = stored_desc(a, m, k), db = stored_desc(b, n, k);
     da.bstride = bt.sa;
@@ -391,15 +397,70 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     g.beta_zero = beta_zero;
     g.partial = gemm_partial_bytes(m, n, k, bt.count) ? reinterpret_cast<float2 *>(part) : nullptr;
     const int nb = bt.count;
+    if (h->smallk && !a.gm && !b.gm && smallk_shape(m, n, k)) {
+        // short k, narrow C: split on load, no panel pass
+        SmallKArgs q{};
+        q.A = a.ptr;
+        q.lda = a.ld;
+        q.a_kcontig = a.kcontig;
+        q.a_conj = a.conj;
+        q.B = b.ptr;
+        q.ldb = b.ld;
+        q.b_kcontig = b.kcontig;
+        q.b_conj = b.conj;
+        q.m = m;
+        q.n = n;
+        q.k = k;
+        q.C = C;
+        q.ldc = ldc;
+        q.alpha = alpha;
+        q.beta = beta;
+        q.beta_zero = beta_zero;
+        q.batch = nb;
+        q.bsA = bt.sa;
+        q.bsB = bt.sb;
+        q.bsC = bt.sc;
+        const bool stats = mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED;
+        if (stats) {
+            hipEvent_t e0 = span_begin(h);
+            QCE_HIP(h, launch_stats(da, db, dst, rec, h->arrived, h->t, h->t3,
+                                    mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, log, slot, s, nb));
+            span_end(h, e0, QCE_PHASE_STATS);
+            q.st = dst;
+            q.forced_mode = mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED;
+        } else {
+            q.st = nullptr;
+            q.forced_mode = mode;
+        }
+        hipEvent_t eg = span_begin(h);
+        QCE_HIP(h, launch_smallk(q, s));
+        if (batched) {
+            span_end(h, eg, QCE_PHASE_GEMM_BATCHED);
+        } else if (mode == QCE_MODE_AUTO) {
+            span_end(h, eg, -1, -1, -1, call);
+            if (h->timing) h->recs.push_back({h->tag, -2, 0, -1, call, nullptr, nullptr, false, 0.0, 0});
+        } else {
+            const int cls = mode == QCE_MODE_BF16X3 ? QCE_MODE_BF16X3
+                          : mode == QCE_MODE_FP32 ? QCE_MODE_FP32 : QCE_MODE_FP16X2;
+            span_end(h, eg, -1, cls, mode, call);
+            if (h->timing) h->recs.push_back({h->tag, -2, 0, mode, call, nullptr, nullptr, false, 0.0, 0});
+        }
+        h->have_decision = true;
+        h->last_on_device = stats;
+        if (!stats) {
+            h->last_host = qce_decision{};
+            h->last_host.mode = mode;
+            for (int o = 0; o < 2; ++o) {
+                h->last_host.n2[o] = -1;
+                h->last_host.emax[o] = INT32_MIN;
+            }
+        }
+        return QCE_SUCCESS;
+    }
     if (mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED) {
         hipEvent_t e0 = span_begin(h);
-        QCE_HIP(h, launch_stats1(da, db, dst, s, nb));
-        if (mode == QCE_MODE_AUTO) {
-            QCE_HIP(h, launch_stats2(da, db, dst, h->t, 0, s, nb));
-            QCE_HIP(h, launch_select(da, db, dst, h->t, h->t3, -1, log, slot, s, nb));
-        } else {
-            QCE_HIP(h, launch_select(da, db, dst, h->t, h->t3, QCE_MODE_FP16X2_SCALED, log, slot, s, nb));
-        }
+        QCE_HIP(h, launch_stats(da, db, dst, rec, h->arrived, h->t, h->t3,
+                                mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, log, slot, s, nb));
         span_end(h, e0, QCE_PHASE_STATS);
         hipEvent_t e1 = span_begin(h);
         QCE_HIP(h, split_operand(a, m, k, panA, dst, 0, 0, s, nb, bt.sa, (int64_t)wl.pa));
@@ -567,6 +628,27 @@ bool small_item(const qce_tensor *a, const int32_t *la, const qce_tensor *b, con
     return true;
 }
 
+// The bit map of an operand whose row bit t sits at stride 2^rsh[t] and k
+// bit t at 2^ksh[t] in its tensor, with the split's 64 x 64 tile bits (the
+// low six of each index) listed by increasing stride.
+GatherMap gather_map_from_shifts(int nr, int nk, const int8_t *rsh, const int8_t *ksh) {
+    GatherMap g;
+    g.nr = nr;
+    g.nk = nk;
+    for (int t = 0; t < nr && t < 32; ++t) g.rsh[t] = rsh[t];
+    for (int t = 0; t < nk && t < 32; ++t) g.ksh[t] = ksh[t];
+    std::vector<std::pair<int, int>> tb;  // (stride exponent, tile position)
+    for (int t = 0; t < std::min(6, nr); ++t) tb.emplace_back(g.rsh[t], t);
+    for (int t = 0; t < std::min(6, nk); ++t) tb.emplace_back(g.ksh[t], 6 + t);
+    std::sort(tb.begin(), tb.end());
+    g.nt = (int)tb.size();
+    for (int i = 0; i < g.nt; ++i) {
+        g.tsh[i] = (int8_t)tb[i].first;
+        g.tpos[i] = (int8_t)tb[i].second;
+    }
+    return g;
+}
+
 bool checked_numel(int rank, const int64_t *ext, int64_t &n) {
     n = 1;
     for (int a = 0; a < rank; ++a) {
@@ -623,21 +705,32 @@ qce_status qce_create(qce_handle **out, int device) {
         if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
         h->fused_gather = f == 1;
     }
+    if (const char *v = getenv("QCE_SMALLK")) {
+        int64_t f = 0;
+        if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
+        h->smallk = f == 1;
+    }
     if (h->emul_min > h->auto_min) { delete h; return QCE_ERR_INVALID_VALUE; }
     DeviceGuard g(device);
+    const size_t arrived_bytes = sizeof(unsigned int) * (kMaxBatch + 1);
+    auto release = [h]() {
+        if (h->st) (void)hipFree(h->st);
+        if (h->arrived) (void)hipFree(h->arrived);
+        if (h->fid_partials) (void)hipFree(h->fid_partials);
+        if (h->mode_log) (void)hipFree(h->mode_log);
+        delete h;
+    };
     if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
+        hipMalloc(&h->arrived, arrived_bytes) != hipSuccess ||
         hipMalloc(&h->fid_partials, sizeof(double) * 4 * kFidBlocks) != hipSuccess ||
         hipMalloc(&h->mode_log, sizeof(int) * kLogCap) != hipSuccess) {
         (void)hipGetLastError();
-        if (h->st) (void)hipFree(h->st);
-        if (h->fid_partials) (void)hipFree(h->fid_partials);
-        delete h;
+        release();
         return QCE_ERR_ALLOC;
     }
-    if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        (void)hipFree(h->st);
-        (void)hipFree(h->fid_partials);
-        delete h;
+    if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess || hipMemset(h->arrived, 0, arrived_bytes) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        release();
         return QCE_ERR_HIP;
     }
     h->dec_base = h->st;
@@ -657,6 +750,7 @@ qce_status qce_destroy(qce_handle *h) {
     }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     (void)hipFree(h->st);
+    (void)hipFree(h->arrived);
     (void)hipFree(h->fid_partials);
     (void)hipFree(h->mode_log);
     if (h->grp_dev) (void)hipFree(h->grp_dev);
@@ -735,26 +829,43 @@ size_t qce_cgemm_batched_workspace_size(int64_t m, int64_t n, int64_t k, int64_t
     return cgemm_ws_bytes(m, n, k, (int)batch);
 }
 
-qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
-                              int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
-                              const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
-                              int64_t ldc) {
-    if (!h) return QCE_ERR_INVALID_VALUE;
+namespace {
+// Argument checks shared by the single-GEMM entry points; QCE_SUCCESS with
+// *noop set when there is nothing to do.
+qce_status cgemm_check(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n, int64_t k,
+                       const qce_c32 *A, int64_t lda, const qce_c32 *B, int64_t ldb, const qce_c32 *C,
+                       int64_t ldc, bool *noop) {
+    *noop = false;
     if (!valid_op(opA) || !valid_op(opB)) return fail(h, QCE_ERR_INVALID_VALUE, "bad op");
     if (m < 0 || n < 0 || k < 0) return fail(h, QCE_ERR_INVALID_VALUE, "negative size");
     const int64_t arows = opA == QCE_OP_N ? m : k, brows = opB == QCE_OP_N ? k : n;
     if (lda < std::max<int64_t>(1, arows) || ldb < std::max<int64_t>(1, brows) ||
         ldc < std::max<int64_t>(1, m))
         return fail(h, QCE_ERR_INVALID_VALUE, "leading dimension too small");
-    if (m == 0 || n == 0) return QCE_SUCCESS;
+    if (m == 0 || n == 0) {
+        *noop = true;
+        return QCE_SUCCESS;
+    }
     if (!C || (k > 0 && (!A || !B))) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
     if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
          reinterpret_cast<uintptr_t>(C)) & 7)
         return fail(h, QCE_ERR_INVALID_VALUE, "pointer not 8-byte aligned");
+    return QCE_SUCCESS;
+}
+}  // namespace
+
+qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                              int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                              const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
+                              int64_t ldc) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    bool noop = false;
+    qce_status st = cgemm_check(h, opA, opB, m, n, k, A, lda, B, ldb, C, ldc, &noop);
+    if (st != QCE_SUCCESS || noop) return st;
     DeviceGuard g(h->device);
     const float2 al = alpha ? make_float2(alpha->re, alpha->im) : make_float2(1.f, 0.f);
     const float2 be = beta ? make_float2(beta->re, beta->im) : make_float2(0.f, 0.f);
-    qce_status st = ensure_ws(h, cgemm_ws_bytes(m, n, k));
+    st = ensure_ws(h, cgemm_ws_bytes(m, n, k));
     if (st != QCE_SUCCESS) return st;
     OperandView va{reinterpret_cast<const float2 *>(A), lda, opA != QCE_OP_N, opA == QCE_OP_C};
     OperandView vb{reinterpret_cast<const float2 *>(B), ldb, opB == QCE_OP_N, opB == QCE_OP_C};
@@ -836,9 +947,16 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
     hipStream_t s = h->stream;
     MatDesc a{reinterpret_cast<const float2 *>(X), rows, cols, ld, 0};
     MatDesc none{nullptr, 0, 0, 1, 0};
-    QCE_HIP(h, launch_stats1(a, none, h->st, s));
-    QCE_HIP(h, launch_stats2(a, none, h->st, h->t, 2, s));
-    QCE_HIP(h, launch_select(a, none, h->st, h->t, h->t3, -2, nullptr, 0, s));
+    if (rows == 0 || cols == 0) {
+        *out = qce_decision{};
+        out->emax[0] = out->emax[1] = INT32_MIN;
+        out->stats_taken = 1;
+        return QCE_SUCCESS;
+    }
+    qce_status sts = ensure_ws(h, stats_record_bytes(a, none));
+    if (sts != QCE_SUCCESS) return sts;
+    QCE_HIP(h, launch_stats(a, none, h->st, static_cast<StatsRecord *>(h->ws), h->arrived, h->t, h->t3, -1,
+                            nullptr, 0, s));
     QCE_HIP(h, hipStreamSynchronize(s));
     QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
     return QCE_SUCCESS;
@@ -853,6 +971,65 @@ qce_status qce_split(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 
     if (mode == QCE_MODE_BF16X3 && shift != 0) return fail(h, QCE_ERR_INVALID_VALUE, "BF16X3 takes no shift");
     DeviceGuard g(h->device);
     QCE_HIP(h, launch_split_planar(mode, shift, reinterpret_cast<const float2 *>(x), n, planes, h->stream));
+    return QCE_SUCCESS;
+}
+
+size_t qce_panel_bytes(qce_mode mode, int64_t rows, int64_t k) {
+    if (rows <= 0 || k <= 0) return 0;
+    const size_t per = mode == QCE_MODE_BF16X3 ? 12 : (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED ||
+                                                         mode == QCE_MODE_FP32) ? 8 : 0;
+    return (size_t)round_up(rows, kPanelRows) * (size_t)round_up(k, kKPad) * per;
+}
+
+namespace {
+qce_status panel_mode_check(qce_handle *h, qce_mode mode, int32_t shift) {
+    if (mode != QCE_MODE_FP16X2 && mode != QCE_MODE_FP16X2_SCALED && mode != QCE_MODE_BF16X3 &&
+        mode != QCE_MODE_FP32)
+        return fail(h, QCE_ERR_INVALID_VALUE, "panels are written for FP16X2, FP16X2_SCALED, BF16X3 or FP32");
+    if (mode != QCE_MODE_FP16X2_SCALED && shift != 0)
+        return fail(h, QCE_ERR_INVALID_VALUE, "only FP16X2_SCALED takes a shift");
+    if (shift < -150 || shift > 150) return fail(h, QCE_ERR_INVALID_VALUE, "shift out of range");
+    return QCE_SUCCESS;
+}
+}  // namespace
+
+qce_status qce_split_panels(qce_handle *h, qce_mode mode, int32_t shift, int32_t layout, int32_t conj,
+                            const qce_c32 *X, int64_t rows, int64_t k, int64_t ld, void *panels) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    qce_status st = panel_mode_check(h, mode, shift);
+    if (st != QCE_SUCCESS) return st;
+    if (layout != 0 && layout != 1) return fail(h, QCE_ERR_INVALID_VALUE, "layout is 0 or 1");
+    if (rows < 0 || k < 0) return fail(h, QCE_ERR_INVALID_VALUE, "negative size");
+    if (rows == 0 || k == 0) return QCE_SUCCESS;
+    if (ld < (layout == 0 ? rows : k)) return fail(h, QCE_ERR_INVALID_VALUE, "leading dimension too small");
+    if (!X || !panels) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(X) & 7) || (reinterpret_cast<uintptr_t>(panels) & 15))
+        return fail(h, QCE_ERR_INVALID_VALUE, "misaligned pointer");
+    DeviceGuard g(h->device);
+    QCE_HIP(h, launch_split_panels(reinterpret_cast<const float2 *>(X), ld, layout, conj != 0, rows, k, panels,
+                                   nullptr, 0, mode, shift, h->stream));
+    return QCE_SUCCESS;
+}
+
+qce_status qce_split_panels_bitmap(qce_handle *h, qce_mode mode, int32_t shift, const qce_c32 *X, int32_t nr,
+                                   int32_t nk, const int32_t *rsh, const int32_t *ksh, void *panels) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    qce_status st = panel_mode_check(h, mode, shift);
+    if (st != QCE_SUCCESS) return st;
+    if (nr < 5 || nk < 4 || nr > 31 || nk > 31 || nr + nk > 40)
+        return fail(h, QCE_ERR_INVALID_VALUE, "need 5 <= nr, 4 <= nk, nr, nk <= 31, nr + nk <= 40");
+    if (!X || !panels || !rsh || !ksh) return fail(h, QCE_ERR_INVALID_VALUE, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(X) & 7) || (reinterpret_cast<uintptr_t>(panels) & 15))
+        return fail(h, QCE_ERR_INVALID_VALUE, "misaligned pointer");
+    int8_t r8[32], k8[32];
+    for (int t = 0; t < nr; ++t) r8[t] = (int8_t)std::max(-1, std::min(127, rsh[t]));
+    for (int t = 0; t < nk; ++t) k8[t] = (int8_t)std::max(-1, std::min(127, ksh[t]));
+    const GatherMap gm = gather_map_from_shifts(nr, nk, r8, k8);
+    if (!gather_map_valid(gm))
+        return fail(h, QCE_ERR_INVALID_VALUE, "rsh and ksh are not a permutation of 0..nr+nk-1");
+    DeviceGuard g(h->device);
+    QCE_HIP(h, launch_split_gather(reinterpret_cast<const float2 *>(X), gm, panels, nullptr, 0, mode, shift,
+                                   h->stream));
     return QCE_SUCCESS;
 }
 
@@ -1134,21 +1311,11 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         // P[r][l]: r's bit t is label F[|F| - 1 - t], l's bit t is label
         // korder[|K| - 1 - t]; a label at position i of l holds stride 2^(r-1-i)
         auto make_map = [&](const int32_t *l, int r, const std::vector<int32_t> &F) {
-            GatherMap g;
-            g.nr = (int)F.size();
-            g.nk = (int)korder.size();
-            for (int t = 0; t < g.nr; ++t) g.rsh[t] = (int8_t)(r - 1 - find(l, r, F[g.nr - 1 - t]));
-            for (int t = 0; t < g.nk; ++t) g.ksh[t] = (int8_t)(r - 1 - find(l, r, korder[g.nk - 1 - t]));
-            std::vector<std::pair<int, int>> tb;  // (stride exponent, tile position)
-            for (int t = 0; t < std::min(6, g.nr); ++t) tb.emplace_back(g.rsh[t], t);
-            for (int t = 0; t < std::min(6, g.nk); ++t) tb.emplace_back(g.ksh[t], 6 + t);
-            std::sort(tb.begin(), tb.end());
-            g.nt = (int)tb.size();
-            for (int i = 0; i < g.nt; ++i) {
-                g.tsh[i] = (int8_t)tb[i].first;
-                g.tpos[i] = (int8_t)tb[i].second;
-            }
-            return g;
+            const int nr = (int)F.size(), nk = (int)korder.size();
+            int8_t rsh[32], ksh[32];
+            for (int t = 0; t < nr; ++t) rsh[t] = (int8_t)(r - 1 - find(l, r, F[nr - 1 - t]));
+            for (int t = 0; t < nk; ++t) ksh[t] = (int8_t)(r - 1 - find(l, r, korder[nk - 1 - t]));
+            return gather_map_from_shifts(nr, nk, rsh, ksh);
         };
         if (lay_x < 0 && run_of(lx, rx, SA, korder) >= kMinRun) {
             gmx = make_map(lx, rx, SA);

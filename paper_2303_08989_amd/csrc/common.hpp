@@ -22,28 +22,27 @@ struct OperandStats {
     unsigned int pad;
 };
 
-constexpr int kMaxStatsBlocks = 1024;  // per operand
+constexpr int kMaxStatsBlocks = 4096;  // per operand
+constexpr int kRelBins = 31;            // exponent bins a block record keeps below its maximum
 
-// per-block partial results of the statistics passes (no atomics: the
-// reduction reads them in block order, so results are deterministic)
-struct StatsPartial {
-    unsigned int gt0, ge1, ge3, inf, maxbits, ge2;
+// One statistics block's summary of its share of one operand (exact counts
+// of its FP32 components): nonzero finite, floor(log2|v|) >= -14 and
+// >= -110, non-finite, its largest exponent bin (e + 149; -1 if none) and
+// the counts of the kRelBins bins from there down (rel[d]: bin maxbin - d).
+struct StatsRecord {
+    unsigned int nnz, n1, n3, nonfinite;
+    int maxbin;
+    unsigned int rel[kRelBins];
 };
 
 struct DevState {
-    StatsPartial part[2][kMaxStatsBlocks];
-    OperandStats acc[2];  // reduced by select (kept for the record)
     int mode;             // selected qce_mode (never AUTO)
     int shift[2];         // power-of-two shifts sA, sB
-    int stage2[2];        // 1 if stage 2 ran for that operand
     int pad;
+    OperandStats acc[2];  // statistics of both operands (kept for the record)
     qce_decision last;    // record of the last decision
 };
 
-// Bit patterns of |v| thresholds (positive FP32 bit patterns order like values).
-constexpr unsigned int kInfBits = 0x7f800000u;
-constexpr unsigned int kFp16MinNormalBits = 113u << 23;  // 2^-14
-constexpr unsigned int kBf16x3FloorBits = 17u << 23;     // 2^-110
 constexpr int kFp16Emax = 14;
 constexpr int kFp16Emin = -14;
 constexpr int kBf16x3Emin = -110;
@@ -122,15 +121,20 @@ struct MatDesc {  // a stored column-major complex64 matrix
 // device state st + z (its own statistics, decision and record).
 constexpr int kMaxBatch = 65535;
 
-hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s,
-                         int batch = 1);
-// flag: 0 = stage 2 for operands failing stage 1, 1 = never, 2 = always
-hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int flag,
-                         hipStream_t s, int batch = 1);
-// forced_mode: -1 = rule, -2 = statistics-only entry point (stage 2 always
-// evaluated), >= 0 = that mode.  mode_log (nullable) receives the mode at slot.
-hipError_t launch_select(const MatDesc &a, const MatDesc &b, DevState *st, double t, double t3,
-                         int forced_mode, int *mode_log, int slot, hipStream_t s, int batch = 1);
+// Exponent statistics of both operands and the mode selection of Sec. 4.1
+// in one launch (stats.hip).  rec: stats_record_bytes of device scratch;
+// arrived: one zeroed counter per batch entry (left zeroed).  forced_mode:
+// -1 = the rule; >= 0 = that mode (statistics taken for its shifts and the
+// record).  mode_log (nullable) receives entry 0's mode at slot.  Batched:
+// entry z reads a / b shifted by z * bstride and writes st + z.
+int stats_blocks(const MatDesc &d);
+// upper bound of stats_blocks over every leading dimension of a rows x cols
+// operand stored either way (rows x cols or cols x rows)
+int stats_blocks_bound(int64_t rows, int64_t cols);
+size_t stats_record_bytes(const MatDesc &a, const MatDesc &b, int batch = 1);
+hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
+                        unsigned int *arrived, double t, double t3, int forced_mode, int *mode_log,
+                        int slot, hipStream_t s, int batch = 1);
 
 // Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
 // kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:
@@ -163,6 +167,30 @@ struct GemmArgs {
 // which_kernel: a mode (forced) or -1 (AUTO: read the device flag)
 hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
 size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch = 1);  // per entry
+
+// Short-k, narrow-output GEMM with the split done on load (gemm.hip):
+// C (m x n, n <= 64) = alpha op(A) op(B) + beta C for k <= 128, reading the
+// stored operands directly (op(A)[i][l] = a_kcontig ? A[l + i lda] :
+// A[i + l lda]; op(B)[l][j] = b_kcontig ? B[l + j ldb] : B[j + l ldb];
+// conj negates the imaginary part).  Mode and shifts from st (AUTO,
+// forced_mode < 0, or FP16X2_SCALED) or forced_mode.  Batched: entry
+// blockIdx.z at A + z bsA, B + z bsB, C + z bsC (elements), st + z.
+struct SmallKArgs {
+    const float2 *A, *B;
+    int64_t lda, ldb;
+    int a_kcontig, a_conj, b_kcontig, b_conj;
+    int64_t m, n, k;
+    float2 *C;
+    int64_t ldc;
+    float2 alpha, beta;
+    int beta_zero;
+    const DevState *st;
+    int forced_mode;
+    int batch;
+    int64_t bsA, bsB, bsC;
+};
+bool smallk_shape(int64_t m, int64_t n, int64_t k);
+hipError_t launch_smallk(const SmallKArgs &g, hipStream_t s);
 
 // Irregular-shape CGEMM (direct.hip): PA[i][l], PB[j][l] read from the
 // stored matrices as in the split kernel; FP32 arithmetic.

@@ -34,6 +34,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "split_math.hpp"
 
 namespace qce {
 
@@ -161,6 +162,27 @@ __device__ __attribute__((always_inline)) inline void fp16x2_block(const u32x4 *
     im_m = mfma16(x[2], y[0], im_m);
 }
 
+// 24 MFMAs of one 32x32 block for one k16 step (planes: b0, b1, b2 of re,
+// then of im; x from op(B), y from op(A))
+__device__ __attribute__((always_inline)) inline void bf16x3_block(const u32x4 *x, const u32x4 *y, floatx16 &re_m,
+                                                                   floatx16 &im_m, floatx16 &re_c, floatx16 &im_c) {
+    const u32x4 nx[3] = {neg_halves(x[3]), neg_halves(x[4]), neg_halves(x[5])};
+    // corrections, smallest first: (2,0) (1,1) (0,2) (1,0) (0,1)
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        const int i = t == 0 ? 2 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 1 : 0;
+        const int j = t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 2 : t == 3 ? 0 : 1;
+        re_c = mfmab(x[i], y[j], re_c);
+        re_c = mfmab(nx[i], y[3 + j], re_c);
+        im_c = mfmab(x[i], y[3 + j], im_c);
+        im_c = mfmab(x[3 + i], y[j], im_c);
+    }
+    re_m = mfmab(x[0], y[0], re_m);
+    re_m = mfmab(nx[0], y[3], re_m);
+    im_m = mfmab(x[0], y[3], im_m);
+    im_m = mfmab(x[3], y[0], im_m);
+}
+
 // ---------------------------------------------------------------------------
 // Fragments of one chunk in registers (all rows of the wave's 64 x 64 tile,
 // 16 k-values) and the MFMAs of one chunk.  The k-loop keeps two such sets:
@@ -225,24 +247,7 @@ __device__ __attribute__((always_inline)) inline void mma_block(const Frag<MODE>
         const u32x4 nx[2] = {neg_halves(f.x[ub][2]), neg_halves(f.x[ub][3])};
         fp16x2_block(f.x[ub], nx, f.y[vb], acc.re_m[ub][vb], acc.im_m[ub][vb], acc.re_c[ub][vb], acc.im_c[ub][vb]);
     } else if constexpr (MODE == QCE_MODE_BF16X3) {
-        const u32x4 *x = f.x[ub], *y = f.y[vb];
-        const u32x4 nx[3] = {neg_halves(x[3]), neg_halves(x[4]), neg_halves(x[5])};
-        floatx16 &re_c = acc.re_c[ub][vb], &im_c = acc.im_c[ub][vb];
-        // corrections, smallest first: (2,0) (1,1) (0,2) (1,0) (0,1)
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            const int i = t == 0 ? 2 : t == 1 ? 1 : t == 2 ? 0 : t == 3 ? 1 : 0;
-            const int j = t == 0 ? 0 : t == 1 ? 1 : t == 2 ? 2 : t == 3 ? 0 : 1;
-            re_c = mfmab(x[i], y[j], re_c);
-            re_c = mfmab(nx[i], y[3 + j], re_c);
-            im_c = mfmab(x[i], y[3 + j], im_c);
-            im_c = mfmab(x[3 + i], y[j], im_c);
-        }
-        floatx16 &re_m = acc.re_m[ub][vb], &im_m = acc.im_m[ub][vb];
-        re_m = mfmab(x[0], y[0], re_m);
-        re_m = mfmab(nx[0], y[3], re_m);
-        im_m = mfmab(x[0], y[3], im_m);
-        im_m = mfmab(x[3], y[0], im_m);
+        bf16x3_block(f.x[ub], f.y[vb], acc.re_m[ub][vb], acc.im_m[ub][vb], acc.re_c[ub][vb], acc.im_c[ub][vb]);
     } else {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
@@ -607,6 +612,237 @@ __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, flo
     }
 }
 
+// ---------------------------------------------------------------------------
+// Short k, narrow C (tall-skinny shapes such as 65536 x 64 x 64): the split
+// is done as the operands are loaded, with no panel pass.  A workgroup owns
+// 128 rows of C (four waves of 32) and all of its <= 64 columns.  It splits
+// op(B) (k x n, at most 128 x 64) into LDS planes once; each wave then loads
+// its rows of op(A) chunk by chunk (16 k-values) straight from global memory
+// into registers, splits them there, and runs the same MFMA sequence per
+// chunk as the panel kernel (the same fragments in the same order, so the
+// sums are the same).  Only op(A) and C stream through HBM.
+// ---------------------------------------------------------------------------
+constexpr int kSkRows = 128;  // rows of C per workgroup
+constexpr int kSkCols = 64;   // columns of C: two 32-column blocks
+
+// LDS row of op(B) (one column j of C): kpad values plus 16 bytes, a stride
+// that puts 8 consecutive rows' 16-byte fragment reads on distinct banks
+__host__ __device__ constexpr int sk_row_bytes(int kpad, int elem) { return kpad * elem + 16; }
+__host__ __device__ constexpr int sk_lds_bytes(int kpad) {
+    // the largest mode: BF16X3 (6 two-byte planes) vs FP32 (2 four-byte planes)
+    return 6 * kSkCols * sk_row_bytes(kpad, 2) > 2 * kSkCols * sk_row_bytes(kpad, 4)
+               ? 6 * kSkCols * sk_row_bytes(kpad, 2)
+               : 2 * kSkCols * sk_row_bytes(kpad, 4);
+}
+
+template <int MODE>
+__device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, char *lds) {
+    constexpr int kE = MODE == QCE_MODE_FP32 ? 4 : 2;
+    const int kpad = (int)round_up(g.k, kKPad);
+    const int rb = sk_row_bytes(kpad, kE);
+    const int pb = kSkCols * rb;
+    const int nchunks = kpad / kKPad;
+    int shA = 0, shB = 0;
+    if (MODE == QCE_MODE_FP16X2 && mode == QCE_MODE_FP16X2_SCALED && g.st) {
+        shA = g.st->shift[0];
+        shB = g.st->shift[1];
+    }
+
+    // op(B) -> LDS planes (zeros beyond n and k)
+    for (int e = threadIdx.x; e < kSkCols * kpad; e += kThreads) {
+        int j, kk;
+        if (g.b_kcontig) {
+            kk = e % kpad;
+            j = e / kpad;
+        } else {
+            j = e % kSkCols;
+            kk = e / kSkCols;
+        }
+        float2 v = make_float2(0.f, 0.f);
+        if (j < g.n && kk < g.k) v = g.b_kcontig ? g.B[kk + j * g.ldb] : g.B[j + kk * g.ldb];
+        if (g.b_conj) v.y = -v.y;
+        char *row = lds + j * rb;
+        if constexpr (MODE == QCE_MODE_FP16X2) {
+            uint16_t h[4];
+            split_fp16x2(v.x, shB, h[0], h[1]);
+            split_fp16x2(v.y, shB, h[2], h[3]);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) *reinterpret_cast<uint16_t *>(row + p * pb + 2 * kk) = h[p];
+        } else if constexpr (MODE == QCE_MODE_BF16X3) {
+            uint16_t b[6];
+            split_bf16x3(v.x, b[0], b[1], b[2]);
+            split_bf16x3(v.y, b[3], b[4], b[5]);
+#pragma unroll
+            for (int p = 0; p < 6; ++p) *reinterpret_cast<uint16_t *>(row + p * pb + 2 * kk) = b[p];
+        } else {
+            *reinterpret_cast<float *>(row + 4 * kk) = v.x;
+            *reinterpret_cast<float *>(row + pb + 4 * kk) = v.y;
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, l32 = lane & 31, hi = lane >> 5;
+    const int nbk = g.n > 32 ? 2 : 1;
+    const int64_t ntiles = (g.m + kSkRows - 1) / kSkRows;
+    // the workgroup walks row tiles with op(B) kept in LDS
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t i = tile * kSkRows + w * 32 + l32;
+    const bool row_ok = i < g.m;
+    Acc<MODE> acc;
+    {
+        floatx16 zf;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) zf[r] = 0.f;
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub) {
+            acc.re_m[ub][0] = zf;
+            acc.im_m[ub][0] = zf;
+            if constexpr (MODE != QCE_MODE_FP32) {
+                acc.re_c[ub][0] = zf;
+                acc.im_c[ub][0] = zf;
+            } else {
+                acc.re_n[ub][0] = zf;
+            }
+        }
+    }
+    // the 8 k-values of op(A) row i this lane supplies in chunk c: 16c + 8hi + u
+    // (FP16 / BF16 fragments), or 16c + 8s + 4hi + jj with u = 4s + jj (FP32)
+    auto kval = [&](int c, int u) {
+        return MODE == QCE_MODE_FP32 ? 16 * c + 8 * (u >> 2) + 4 * hi + (u & 3) : 16 * c + 8 * hi + u;
+    };
+    auto load = [&](float2 *v, int c) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kk = kval(c, u);
+            float2 x = make_float2(0.f, 0.f);
+            if (row_ok && kk < g.k) x = g.a_kcontig ? g.A[kk + i * g.lda] : g.A[i + (int64_t)kk * g.lda];
+            if (g.a_conj) x.y = -x.y;
+            v[u] = x;
+        }
+    };
+    float2 cur[8], nxt[8];
+    load(cur, 0);
+    for (int c = 0; c < nchunks; ++c) {
+        if (c + 1 < nchunks) load(nxt, c + 1);
+        if constexpr (MODE == QCE_MODE_FP16X2) {
+            uint16_t h[4][8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                split_fp16x2(cur[u].x, shA, h[0][u], h[1][u]);
+                split_fp16x2(cur[u].y, shA, h[2][u], h[3][u]);
+            }
+            u32x4 y[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) y[p] = __builtin_bit_cast(u32x4, pack8(h[p]));
+#pragma unroll
+            for (int ub = 0; ub < 2; ++ub) {
+                if (ub >= nbk) break;
+                const char *src = lds + (ub * 32 + l32) * rb + 2 * (16 * c + 8 * hi);
+                u32x4 x[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) x[p] = *reinterpret_cast<const u32x4 *>(src + p * pb);
+                const u32x4 nx[2] = {neg_halves(x[2]), neg_halves(x[3])};
+                fp16x2_block(x, nx, y, acc.re_m[ub][0], acc.im_m[ub][0], acc.re_c[ub][0], acc.im_c[ub][0]);
+            }
+        } else if constexpr (MODE == QCE_MODE_BF16X3) {
+            uint16_t b[6][8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                split_bf16x3(cur[u].x, b[0][u], b[1][u], b[2][u]);
+                split_bf16x3(cur[u].y, b[3][u], b[4][u], b[5][u]);
+            }
+            u32x4 y[6];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) y[p] = __builtin_bit_cast(u32x4, pack8(b[p]));
+#pragma unroll
+            for (int ub = 0; ub < 2; ++ub) {
+                if (ub >= nbk) break;
+                const char *src = lds + (ub * 32 + l32) * rb + 2 * (16 * c + 8 * hi);
+                u32x4 x[6];
+#pragma unroll
+                for (int p = 0; p < 6; ++p) x[p] = *reinterpret_cast<const u32x4 *>(src + p * pb);
+                bf16x3_block(x, y, acc.re_m[ub][0], acc.im_m[ub][0], acc.re_c[ub][0], acc.im_c[ub][0]);
+            }
+        } else {
+#pragma unroll
+            for (int ub = 0; ub < 2; ++ub) {
+                if (ub >= nbk) break;
+#pragma unroll
+                for (int sh = 0; sh < 2; ++sh) {
+                    const char *src = lds + (ub * 32 + l32) * rb + 4 * (16 * c + 8 * sh + 4 * hi);
+                    const f32x4 xr = *reinterpret_cast<const f32x4 *>(src);
+                    const f32x4 xi = *reinterpret_cast<const f32x4 *>(src + pb);
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const float b_r = cur[4 * sh + jj].x, b_i = cur[4 * sh + jj].y;
+                        acc.re_m[ub][0] = mfma32(xr[jj], b_r, acc.re_m[ub][0]);
+                        acc.re_n[ub][0] = mfma32(xi[jj], b_i, acc.re_n[ub][0]);
+                        acc.im_m[ub][0] = mfma32(xr[jj], b_i, acc.im_m[ub][0]);
+                        acc.im_m[ub][0] = mfma32(xi[jj], b_r, acc.im_m[ub][0]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+    }
+
+    // epilogue: D[j][i] -> C[i][j]
+    const int shift_total = shA + shB;
+    const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
+#pragma unroll
+    for (int ub = 0; ub < 2; ++ub) {
+        if (ub >= nbk) break;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t j = ub * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+            if (!row_ok || j >= g.n) continue;
+            float re, im;
+            if constexpr (MODE == QCE_MODE_FP16X2) {
+                re = acc.re_m[ub][0][r] + acc.re_c[ub][0][r] * (1.0f / 2048.0f);
+                im = acc.im_m[ub][0][r] + acc.im_c[ub][0][r] * (1.0f / 2048.0f);
+            } else if constexpr (MODE == QCE_MODE_BF16X3) {
+                re = acc.re_m[ub][0][r] + acc.re_c[ub][0][r];
+                im = acc.im_m[ub][0][r] + acc.im_c[ub][0][r];
+            } else {
+                re = acc.re_m[ub][0][r] - acc.re_n[ub][0][r];
+                im = acc.im_m[ub][0][r];
+            }
+            if (shift_total) {
+                re = ldexpf(re, -shift_total);
+                im = ldexpf(im, -shift_total);
+            }
+            float2 out = alpha_one ? make_float2(re, im)
+                                   : make_float2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+            float2 *cp = g.C + i + j * g.ldc;
+            if (!g.beta_zero) {
+                const float2 cv = *cp;
+                out.x += g.beta.x * cv.x - g.beta.y * cv.y;
+                out.y += g.beta.x * cv.y + g.beta.y * cv.x;
+            }
+            *cp = out;
+        }
+    }
+    }  // row tiles
+}
+
+template <int KPAD>
+__global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
+    __shared__ __attribute__((aligned(16))) char lds[sk_lds_bytes(KPAD)];
+    const int64_t z = blockIdx.z;
+    g.A += z * g.bsA;
+    g.B += z * g.bsB;
+    g.C += z * g.bsC;
+    if (g.st) g.st += z;
+    const int mode = g.forced_mode >= 0 ? g.forced_mode : g.st->mode;
+    if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
+        smallk_body<QCE_MODE_FP16X2>(g, mode, lds);
+    else if (mode == QCE_MODE_BF16X3)
+        smallk_body<QCE_MODE_BF16X3>(g, mode, lds);
+    else
+        smallk_body<QCE_MODE_FP32>(g, mode, lds);
+}
+
 }  // namespace
 
 int gemm_splits(int64_t m, int64_t n, int64_t k, int batch) {
@@ -652,6 +888,25 @@ size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch) {
     const int64_t per = ((pads + splits - 1) / splits) * kKPad;
     const int64_t nsplit = (round_up(k, kKPad) + per - 1) / per;
     return nsplit > 1 ? (size_t)nsplit * (size_t)(m * n) * sizeof(float2) : 0;
+}
+
+bool smallk_shape(int64_t m, int64_t n, int64_t k) {
+    return !irregular_shape(m, n, k) && n <= kSkCols && k <= 128;
+}
+
+hipError_t launch_smallk(const SmallKArgs &g, hipStream_t s) {
+    if (!smallk_shape(g.m, g.n, g.k)) return hipErrorInvalidValue;
+    if (g.forced_mode < 0 && !g.st) return hipErrorInvalidValue;
+    const int batch = std::max(1, g.batch);
+    // at most one workgroup per CU per entry: op(B) is split into LDS once
+    // per workgroup and reused for every row tile it walks
+    const int64_t tiles = (g.m + kSkRows - 1) / kSkRows;
+    const dim3 grid((unsigned)std::min<int64_t>(tiles, 256), 1, (unsigned)batch), block(kThreads);
+    if (round_up(g.k, kKPad) <= 64)
+        hipLaunchKernelGGL(smallk_kernel<64>, grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL(smallk_kernel<128>, grid, block, 0, s, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale_c(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta, int beta_zero,

@@ -1,20 +1,25 @@
-// Exponent statistics and mode selection (Sec. 4.1 and 4.2).
+// Exponent statistics and mode selection (Sec. 4.1 and 4.2) in one launch.
 //
-// stats1 reads every FP32 component of both operands once (Sec. 4: all
-// elements are checked, no sampling) and writes, per block: the nonzero count,
-// the stage-1 count n1 = #{|v| >= 2^-14}, the BF16X3-floor count
-// n3 = #{|v| >= 2^-110}, the non-finite count and the largest |v| bit
-// pattern, from which emax = floor(log2 max|v|) follows.  Positive FP32 bit
-// patterns order like their values, so every count is one integer compare of
-// the absolute bit pattern.
-// stats2 (stage 2): each block first adds up the stage-1 partials of its
-// operand; it scans the operand again only when stage 1 failed for it, and
-// counts n2 = #{|v| >= 2^(emax-28)}: the elements inside the FP16 window once
-// emax is shifted to 14.
-// select adds up the partials, turns both operands' statistics into the
-// device mode flag and the shifts and keeps a record for the host.  Partials
-// are summed in block order (no atomics), so the statistics are exact and
-// deterministic, and nothing is copied to the host (Sec. 4.2).
+// Every FP32 component of both operands is read once (Sec. 4: all elements
+// are checked, no sampling) and binned by its exact exponent
+// e = floor(log2|v|) (bin = e + 149, FP32 subnormals included; zeros and
+// Inf/NaN in bins of their own).  One pass gives both stages of the rule:
+// stage 1 needs the counts above 2^-14 and 2^-110 and e_max, stage 2 the
+// count inside [e_max - 28, e_max], which only a histogram can give before
+// e_max is known.
+//
+// A block bins its share of one operand into a histogram in LDS (each lane
+// pair owns a column of 16-bit counters, so the LDS adds never contend on
+// an address across a wave), then writes a record: its nonzero, stage-1,
+// BF16X3-floor and non-finite counts, its largest exponent bin and the 31
+// bins just below it.  The last block of the launch to finish (an arrival
+// counter per GEMM) adds up the records in block order -- the stage-2 count
+// of a block is the part of its 31 bins inside the global window -- turns
+// both operands' statistics into the device mode flag and shifts, keeps a
+// record for the host and clears the counter for the next call.  Counts are
+// exact and deterministic, and nothing is copied to the host (Sec. 4.2).
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace qce {
@@ -22,27 +27,35 @@ namespace qce {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kBinZero = 277, kBinNonfinite = 278;
+constexpr int kBins = 279;                 // exponent bins 0..276, zero, non-finite
+constexpr int kWords = (kBins + 1) / 2;    // two 16-bit counters per word
+constexpr int kCols = 32;                  // lanes l and l + 32 share a column
+constexpr int kBin1 = kFp16Emin + 149;     // stage 1: e >= -14
+constexpr int kBin3 = kBf16x3Emin + 149;   // BF16X3 floor: e >= -110
+// elements one lane may bin before a 16-bit counter of its column could
+// overflow (two lanes per column)
+constexpr int64_t kMaxPerLane = 32000;
 
-__device__ inline int emax_of_bits(unsigned int maxbits) {
-    unsigned int e = maxbits >> 23;
-    if (e) return (int)e - 127;
-    unsigned int mant = maxbits & 0x7fffffu;  // subnormal: mant * 2^-149
-    return -118 - __clz(mant);
+// exact exponent bin of one FP32 component
+__device__ inline int bin_of(float v) {
+    const unsigned int b = __float_as_uint(v) & 0x7fffffffu;
+    const unsigned int e8 = b >> 23;
+    int bin = e8 ? (int)e8 + 22 : 31 - (int)__clz(b);  // subnormal: -118 - clz(mantissa) + 149
+    bin = b == 0u ? kBinZero : bin;
+    bin = e8 == 255u ? kBinNonfinite : bin;
+    return bin;
 }
 
-// threshold bit pattern of 2^e (for e below the subnormal range: smallest
-// positive value, i.e. every nonzero counts)
-__device__ inline unsigned int pow2_bits(int e) {
-    if (e >= -126) return (unsigned int)(e + 127) << 23;
-    if (e >= -149) return 1u << (e + 149);
-    return 1u;
-}
-
-__device__ inline bool stage1_pass(const OperandStats &s, double t) {
-    if (s.nnz == 0) return true;
-    int emax = emax_of_bits(s.maxbits);
-    return emax <= kFp16Emax && (double)(s.nnz - s.n1) <= t * (double)s.nnz;
-}
+struct HistCounter {
+    unsigned int *col;  // this lane's column (LDS)
+    __device__ inline void operator()(float v) {
+        const int bin = bin_of(v);
+        __hip_atomic_fetch_add(col + (bin >> 1) * kCols, 1u << ((bin & 1) << 4), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
 
 // Visit every FP32 component of a stored column-major complex matrix; the
 // work is split over `nblk` blocks starting at block index `blk`.
@@ -58,12 +71,14 @@ __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, 
             const int64_t n4 = nf >> 2;
             const float4 *p4 = reinterpret_cast<const float4 *>(p);
             int64_t i = tid;
-            for (; i + 3 * nthr < n4; i += 4 * nthr) {
-                float4 v0 = p4[i], v1 = p4[i + nthr], v2 = p4[i + 2 * nthr], v3 = p4[i + 3 * nthr];
-                f(v0.x); f(v0.y); f(v0.z); f(v0.w);
-                f(v1.x); f(v1.y); f(v1.z); f(v1.w);
-                f(v2.x); f(v2.y); f(v2.z); f(v2.w);
-                f(v3.x); f(v3.y); f(v3.z); f(v3.w);
+            for (; i + 7 * nthr < n4; i += 8 * nthr) {
+                float4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = p4[i + u * nthr];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    f(v[u].x); f(v[u].y); f(v[u].z); f(v[u].w);
+                }
             }
             for (; i < n4; i += nthr) {
                 float4 v = p4[i];
@@ -90,179 +105,170 @@ __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, 
     }
 }
 
-__device__ inline unsigned int abs_bits(float v) { return __float_as_uint(v) & 0x7fffffffu; }
-
-struct Stage1Counter {
-    unsigned int gt0 = 0, ge1 = 0, ge3 = 0, inf = 0, maxb = 0;
-    __device__ inline void operator()(float v) {
-        unsigned int ab = abs_bits(v);
-        gt0 += ab != 0u;
-        ge1 += ab >= kFp16MinNormalBits;
-        ge3 += ab >= kBf16x3FloorBits;
-        bool nf = ab >= kInfBits;
-        inf += nf;
-        maxb = max(maxb, nf ? 0u : ab);
-    }
-};
-
-struct Stage2Counter {
-    unsigned int thr;
-    unsigned int ge = 0;
-    __device__ inline void operator()(float v) {
-        unsigned int ab = abs_bits(v);
-        ge += (ab >= thr) & (ab < kInfBits);
-    }
-};
-
-__device__ inline unsigned long long block_sum(unsigned long long v, unsigned long long *sh) {
+__device__ inline unsigned int wave_sum(unsigned int v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    unsigned long long r = 0;
-    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
-    return r;  // valid in every thread
+    return v;
 }
-
-__device__ inline unsigned int block_max(unsigned int v, unsigned long long *sh) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o));
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    unsigned int r = 0;
-    for (int i = 0; i < kThreads / 64; ++i) r = max(r, (unsigned int)sh[i]);
-    return r;  // valid in every thread
+__device__ inline unsigned long long wave_sum64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
-
-// Stage-1 totals of one operand from its per-block partials, added in block
-// order; every thread of the calling block gets the result.
-__device__ inline OperandStats reduce_partials(const DevState *st, int op, int nb, bool with_ge2,
-                                               unsigned long long *sh) {
-    unsigned long long gt0 = 0, ge1 = 0, ge3 = 0, inf = 0, ge2 = 0;
-    unsigned int maxb = 0;
-    for (int i = threadIdx.x; i < nb; i += kThreads) {
-        const StatsPartial &p = st->part[op][i];
-        gt0 += p.gt0;
-        ge1 += p.ge1;
-        ge3 += p.ge3;
-        inf += p.inf;
-        maxb = max(maxb, p.maxbits);
-        if (with_ge2) ge2 += p.ge2;
-    }
-    OperandStats s;
-    gt0 = block_sum(gt0, sh);
-    ge1 = block_sum(ge1, sh);
-    ge3 = block_sum(ge3, sh);
-    inf = block_sum(inf, sh);
-    ge2 = with_ge2 ? block_sum(ge2, sh) : 0;
-    s.maxbits = block_max(maxb, sh);
-    // every count of "|v| >= x" includes the non-finite values; remove them
-    s.nnz = gt0 - inf;
-    s.n1 = ge1 - inf;
-    s.n3 = ge3 - inf;
-    s.n2 = ge2;
-    s.nonfinite = inf;
-    s.pad = 0;
-    return s;
-}
-
-__global__ __launch_bounds__(kThreads) void stats1_kernel(MatDesc a, MatDesc b, int blocks_a,
-                                                          DevState *st) {
-    __shared__ unsigned long long sh[kThreads / 64];
-    st += blockIdx.z;
-    a.ptr += (int64_t)blockIdx.z * a.bstride;
-    b.ptr += (int64_t)blockIdx.z * b.bstride;
-    const bool is_a = (int)blockIdx.x < blocks_a;
-    const MatDesc &d = is_a ? a : b;
-    const int64_t blk = is_a ? blockIdx.x : blockIdx.x - blocks_a;
-    const int64_t nblk = is_a ? blocks_a : gridDim.x - blocks_a;
-    Stage1Counter c;
-    scan_matrix(d, blk, nblk, c);
-    const unsigned long long gt0 = block_sum(c.gt0, sh);
-    const unsigned long long ge1 = block_sum(c.ge1, sh);
-    const unsigned long long ge3 = block_sum(c.ge3, sh);
-    const unsigned long long inf = block_sum(c.inf, sh);
-    const unsigned int maxb = block_max(c.maxb, sh);
-    if (threadIdx.x == 0) {
-        StatsPartial &p = st->part[is_a ? 0 : 1][blk];
-        p.gt0 = (unsigned int)gt0;
-        p.ge1 = (unsigned int)ge1;
-        p.ge3 = (unsigned int)ge3;
-        p.inf = (unsigned int)inf;
-        p.maxbits = maxb;
-        p.ge2 = 0;
-    }
-}
-
-// flag: 0 = stage 2 only for operands failing stage 1, 1 = never, 2 = always
-__device__ inline bool stage2_runs(const OperandStats &s, double t, int flag) {
-    if (flag == 1 || s.nnz == 0) return false;
-    if (flag == 2) return true;
-    return s.nonfinite == 0 && !stage1_pass(s, t);
-}
-
-__global__ __launch_bounds__(kThreads) void stats2_kernel(MatDesc a, MatDesc b, int blocks_a,
-                                                          DevState *st, double t, int flag) {
-    __shared__ unsigned long long sh[kThreads / 64];
-    st += blockIdx.z;
-    a.ptr += (int64_t)blockIdx.z * a.bstride;
-    b.ptr += (int64_t)blockIdx.z * b.bstride;
-    const bool is_a = (int)blockIdx.x < blocks_a;
-    const int op = is_a ? 0 : 1;
-    const int64_t blk = is_a ? blockIdx.x : blockIdx.x - blocks_a;
-    const int64_t nblk = is_a ? blocks_a : gridDim.x - blocks_a;
-    const OperandStats s = reduce_partials(st, op, (int)nblk, false, sh);
-    if (!stage2_runs(s, t, flag)) return;  // uniform over the block
-    const MatDesc &d = is_a ? a : b;
-    Stage2Counter c;
-    c.thr = pow2_bits(emax_of_bits(s.maxbits) - kWindowSpan);
-    scan_matrix(d, blk, nblk, c);
-    const unsigned long long ge = block_sum(c.ge, sh);
-    if (threadIdx.x == 0) st->part[op][blk].ge2 = (unsigned int)ge;
+__device__ inline int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
 }
 
 // Per-operand tolerance level (Sec. 4.1): FP16 if every element but a
-// fraction t lies in the FP16 window without shifting; FP16 with scaling if
-// the window shifted to emax holds all but a fraction t; BF16X3 if all but a
-// fraction t3 lie above its floor; else FP32.  Non-finite data -> FP32.
-__device__ inline int operand_level(const OperandStats &s, double t, double t3, bool stage2_ran) {
+// fraction t lies in the FP16 window without shifting (and e_max <= 14: no
+// overflow); FP16 with scaling if the window shifted to e_max holds all but
+// a fraction t; BF16X3 if all but a fraction t3 lie above its floor and
+// e_max <= 126; else FP32.  Non-finite data -> FP32.
+__device__ inline int operand_level(const OperandStats &s, int emax, double t, double t3) {
     if (s.nonfinite) return QCE_MODE_FP32;
     if (s.nnz == 0) return QCE_MODE_FP16X2;
     const double nnz = (double)s.nnz;
-    const int emax = emax_of_bits(s.maxbits);
     if (emax <= kFp16Emax && (double)(s.nnz - s.n1) <= t * nnz) return QCE_MODE_FP16X2;
-    if (stage2_ran && (double)(s.nnz - s.n2) <= t * nnz) return QCE_MODE_FP16X2_SCALED;
+    if ((double)(s.nnz - s.n2) <= t * nnz) return QCE_MODE_FP16X2_SCALED;
     if (emax <= kBf16x3Emax && (double)(s.nnz - s.n3) <= t3 * nnz) return QCE_MODE_BF16X3;
     return QCE_MODE_FP32;
 }
 
-__global__ __launch_bounds__(kThreads) void select_kernel(int blocks_a, int blocks_b, DevState *st,
-                                                          double t, double t3, int forced,
-                                                          int stage2_flag, int *mode_log, int slot) {
-    __shared__ unsigned long long sh[kThreads / 64];
-    st += blockIdx.x;                // one block per batch entry
-    if (blockIdx.x != 0) mode_log = nullptr;
+struct StatsArgs {
+    MatDesc a, b;
+    int blocks_a, blocks_b;
+    DevState *st;           // entry z: st + z
+    StatsRecord *rec;       // entry z: rec + z * (blocks_a + blocks_b)
+    unsigned int *arrived;  // entry z: arrived[z] (zero between calls)
+    double t, t3;
+    int forced;             // -1: rule; >= 0: that mode (statistics for its shifts)
+    int *mode_log;          // nullable: mode of entry 0 at mode_log[slot]
+    int slot;
+};
+
+__global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
+    __shared__ unsigned int hist[kWaves * kWords * kCols];
+    __shared__ unsigned int bins[kWords * 2];
+    __shared__ int flag;
+    const int z = blockIdx.z;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    MatDesc a = g.a, b = g.b;
+    a.ptr += (int64_t)z * a.bstride;
+    b.ptr += (int64_t)z * b.bstride;
+    const int total = g.blocks_a + g.blocks_b;
+    StatsRecord *rec = g.rec + (int64_t)z * total;
+    const bool is_a = (int)blockIdx.x < g.blocks_a;
+    const int blk = is_a ? blockIdx.x : blockIdx.x - g.blocks_a;
+    const int nblk = is_a ? g.blocks_a : g.blocks_b;
+
+    {
+        uint4 *h4 = reinterpret_cast<uint4 *>(hist);
+        for (int i = threadIdx.x; i < kWaves * kWords * kCols / 4; i += kThreads) h4[i] = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    HistCounter c;
+    c.col = hist + w * kWords * kCols + (lane & 31);
+    scan_matrix(is_a ? a : b, blk, nblk, c);
+    __syncthreads();
+    // the block's histogram: word t holds bins 2t and 2t + 1
+    for (int t = threadIdx.x; t < kWords; t += kThreads) {
+        unsigned int lo = 0, hi = 0;
+        for (int ww = 0; ww < kWaves; ++ww)
+            for (int col = 0; col < kCols; ++col) {
+                const unsigned int v = hist[(ww * kWords + t) * kCols + col];
+                lo += v & 0xffffu;
+                hi += v >> 16;
+            }
+        bins[2 * t] = lo;
+        bins[2 * t + 1] = hi;
+    }
+    __syncthreads();
+    // the block's record (wave 0)
+    if (w == 0) {
+        unsigned int nnz = 0, n1 = 0, n3 = 0;
+        int mb = -1;
+        for (int bI = lane; bI < kBinZero; bI += 64) {
+            const unsigned int v = bins[bI];
+            nnz += v;
+            n1 += bI >= kBin1 ? v : 0u;
+            n3 += bI >= kBin3 ? v : 0u;
+            if (v) mb = bI;
+        }
+        nnz = wave_sum(nnz);
+        n1 = wave_sum(n1);
+        n3 = wave_sum(n3);
+        mb = wave_max(mb);
+        StatsRecord &r = rec[blockIdx.x];
+        if (lane == 0) {
+            r.nnz = nnz;
+            r.n1 = n1;
+            r.n3 = n3;
+            r.nonfinite = bins[kBinNonfinite];
+            r.maxbin = mb;
+        }
+        if (lane < kRelBins) r.rel[lane] = (mb - lane >= 0) ? bins[mb - lane] : 0u;
+        __threadfence();  // the record is visible before this block arrives
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) flag = atomicAdd(&g.arrived[z], 1u) == (unsigned int)(total - 1);
+    __syncthreads();
+    if (!flag) return;
+    __threadfence();  // every other block's record is visible to this one
+
+    // last block: both operands' statistics from the records, in block order
     OperandStats s[2];
-    bool ran[2];
+    int emaxbin[2];
     for (int o = 0; o < 2; ++o) {
-        const int nb = o == 0 ? blocks_a : blocks_b;
-        s[o] = reduce_partials(st, o, nb, false, sh);
-        ran[o] = stage2_runs(s[o], t, stage2_flag);  // uniform over the block
-        if (ran[o]) s[o].n2 = reduce_partials(st, o, nb, true, sh).n2;
+        const int r0 = o == 0 ? 0 : g.blocks_a, nr = o == 0 ? g.blocks_a : g.blocks_b;
+        if (w == 0) {
+            unsigned long long nnz = 0, n1 = 0, n3 = 0, nf = 0;
+            int mb = -1;
+            for (int i = lane; i < nr; i += 64) {
+                const StatsRecord &r = rec[r0 + i];
+                nnz += r.nnz;
+                n1 += r.n1;
+                n3 += r.n3;
+                nf += r.nonfinite;
+                mb = max(mb, r.maxbin);
+            }
+            nnz = wave_sum64(nnz);
+            n1 = wave_sum64(n1);
+            n3 = wave_sum64(n3);
+            nf = wave_sum64(nf);
+            mb = wave_max(mb);
+            // stage 2: the part of each block's top bins inside [mb - 28, mb]
+            unsigned long long n2 = 0;
+            for (int i = lane; i < nr; i += 64) {
+                const StatsRecord &r = rec[r0 + i];
+                if (r.maxbin < 0) continue;
+                const int top = kWindowSpan - (mb - r.maxbin);  // highest d inside the window
+                for (int d = 0; d <= top && d < kRelBins; ++d) n2 += r.rel[d];
+            }
+            n2 = wave_sum64(n2);
+            s[o].nnz = nnz;
+            s[o].n1 = n1;
+            s[o].n2 = n2;
+            s[o].n3 = n3;
+            s[o].nonfinite = nf;
+            s[o].maxbits = 0;
+            s[o].pad = 0;
+            emaxbin[o] = mb;
+        }
     }
     if (threadIdx.x != 0) return;
-    int level[2];
-    for (int o = 0; o < 2; ++o) level[o] = operand_level(s[o], t, t3, ran[o]);
-    const int mode = forced >= 0 ? forced : max(level[0], level[1]);
+    DevState *st = g.st + z;
+    int level[2], emax[2];
+    for (int o = 0; o < 2; ++o) {
+        emax[o] = s[o].nnz ? emaxbin[o] - 149 : INT32_MIN;
+        level[o] = operand_level(s[o], emax[o], g.t, g.t3);
+    }
+    const int mode = g.forced >= 0 ? g.forced : max(level[0], level[1]);
     int shv[2] = {0, 0};
     if (mode == QCE_MODE_FP16X2_SCALED)
-        for (int o = 0; o < 2; ++o) shv[o] = s[o].nnz ? kFp16Emax - emax_of_bits(s[o].maxbits) : 0;
+        for (int o = 0; o < 2; ++o) shv[o] = s[o].nnz ? kFp16Emax - emax[o] : 0;
     st->mode = mode;
-    if (mode_log) mode_log[slot] = mode;
     st->shift[0] = shv[0];
     st->shift[1] = shv[1];
+    if (g.mode_log && z == 0) g.mode_log[g.slot] = mode;
     qce_decision &r = st->last;
     r.mode = mode;
     r.sA = shv[0];
@@ -270,52 +276,84 @@ __global__ __launch_bounds__(kThreads) void select_kernel(int blocks_a, int bloc
     r.stats_taken = 1;
     for (int o = 0; o < 2; ++o) {
         st->acc[o] = s[o];
-        st->stage2[o] = ran[o];
         r.nnz[o] = (int64_t)s[o].nnz;
         r.n1[o] = (int64_t)s[o].n1;
-        r.n2[o] = ran[o] ? (int64_t)s[o].n2 : -1;
+        r.n2[o] = (int64_t)s[o].n2;
         r.n3[o] = (int64_t)s[o].n3;
         r.nonfinite[o] = (int64_t)s[o].nonfinite;
-        r.emax[o] = s[o].nnz ? emax_of_bits(s[o].maxbits) : INT32_MIN;
+        r.emax[o] = emax[o];
     }
-}
-
-int stats_blocks(int64_t nf) {
-    // enough blocks to cover the device several times, not more than needed
-    const int64_t per_block = (int64_t)kThreads * 64;  // >= 64 floats per thread
-    int64_t b = (nf + per_block - 1) / per_block;
-    if (b < 1) b = 1;
-    if (b > 512) b = 512;
-    return (int)b;
+    g.arrived[z] = 0u;  // ready for the next call (stream order)
 }
 
 }  // namespace
 
-hipError_t launch_stats1(const MatDesc &a, const MatDesc &b, DevState *st, hipStream_t s,
-                         int batch) {
-    const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
-    hipLaunchKernelGGL(stats1_kernel, dim3(ba + bb, 1, batch), dim3(kThreads), 0, s, a, b, ba, st);
-    return hipGetLastError();
+namespace {
+// blocks of the contiguous and of the strided scan of a rows x cols operand
+int64_t blocks_base(int64_t nf) {
+    // enough blocks to cover the device several times, not more than needed
+    const int64_t b = (nf + (int64_t)kThreads * 64 - 1) / ((int64_t)kThreads * 64);
+    return std::max<int64_t>(1, std::min<int64_t>(b, 512));
+}
+// ... and enough that no lane bins more than kMaxPerLane components
+int64_t blocks_contig(int64_t rows, int64_t cols) {
+    const int64_t nf = 2 * rows * cols;
+    const int64_t need = (nf + kThreads * (kMaxPerLane - 8) - 1) / (kThreads * (kMaxPerLane - 8));
+    return std::max(blocks_base(nf), need);
+}
+int64_t blocks_strided(int64_t rows, int64_t cols) {
+    const int64_t per_col = 2 * ((rows + kThreads - 1) / kThreads);  // per lane per column
+    const int64_t cols_per_block = std::max<int64_t>(1, kMaxPerLane / per_col);
+    return std::max(blocks_base(2 * rows * cols), (cols + cols_per_block - 1) / cols_per_block);
+}
+}  // namespace
+
+int stats_blocks(const MatDesc &d) {
+    if (d.rows <= 0 || d.cols <= 0) return 0;
+    const bool contig = d.ld == d.rows || d.cols == 1;
+    const int64_t b = contig ? blocks_contig(d.rows, d.cols) : blocks_strided(d.rows, d.cols);
+    return (int)std::min<int64_t>(b, kMaxStatsBlocks);
 }
 
-hipError_t launch_stats2(const MatDesc &a, const MatDesc &b, DevState *st, double t, int flag,
-                         hipStream_t s, int batch) {
-    if (flag == 1) return hipSuccess;
-    const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
-    hipLaunchKernelGGL(stats2_kernel, dim3(ba + bb, 1, batch), dim3(kThreads), 0, s, a, b, ba, st, t,
-                       flag);
-    return hipGetLastError();
+int stats_blocks_bound(int64_t rows, int64_t cols) {
+    if (rows <= 0 || cols <= 0) return 0;
+    // either orientation (the stored matrix of op(X) may be X or X^T)
+    const int64_t b = std::max({blocks_contig(rows, cols), blocks_strided(rows, cols), blocks_strided(cols, rows)});
+    return (int)std::min<int64_t>(b, kMaxStatsBlocks);
 }
 
-hipError_t launch_select(const MatDesc &a, const MatDesc &b, DevState *st, double t, double t3,
-                         int forced_mode, int *mode_log, int slot, hipStream_t s, int batch) {
-    // stage-2 flag as used by launch_stats2: forced modes skip stage 2,
-    // forced_mode == -2 is the statistics-only entry point (stage 2 always)
-    const int flag = forced_mode == -1 ? 0 : (forced_mode == -2 ? 2 : 1);
-    const int forced = forced_mode < 0 ? -1 : forced_mode;
-    const int ba = stats_blocks(2 * a.rows * a.cols), bb = stats_blocks(2 * b.rows * b.cols);
-    hipLaunchKernelGGL(select_kernel, dim3(batch), dim3(kThreads), 0, s, ba, bb, st, t, t3, forced, flag,
-                       mode_log, slot);
+bool stats_supported(const MatDesc &d) {
+    if (d.rows <= 0 || d.cols <= 0) return true;
+    const int b = stats_blocks(d);
+    if (d.ld == d.rows || d.cols == 1) return 2 * d.rows * d.cols <= (int64_t)b * kThreads * (kMaxPerLane - 8);
+    const int64_t per_col = 2 * ((d.rows + kThreads - 1) / kThreads);
+    return per_col <= kMaxPerLane && ((d.cols + b - 1) / b) * per_col <= kMaxPerLane;
+}
+
+size_t stats_record_bytes(const MatDesc &a, const MatDesc &b, int batch) {
+    return sizeof(StatsRecord) * (size_t)(stats_blocks(a) + stats_blocks(b)) * (size_t)std::max(1, batch);
+}
+
+hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
+                        unsigned int *arrived, double t, double t3, int forced_mode, int *mode_log,
+                        int slot, hipStream_t s, int batch) {
+    if (!stats_supported(a) || !stats_supported(b)) return hipErrorInvalidValue;
+    StatsArgs g;
+    g.a = a;
+    g.b = b;
+    g.blocks_a = stats_blocks(a);
+    g.blocks_b = stats_blocks(b);
+    g.st = st;
+    g.rec = rec;
+    g.arrived = arrived;
+    g.t = t;
+    g.t3 = t3;
+    g.forced = forced_mode;
+    g.mode_log = mode_log;
+    g.slot = slot;
+    const int total = g.blocks_a + g.blocks_b;
+    if (total == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stats_kernel, dim3(total, 1, std::max(1, batch)), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 

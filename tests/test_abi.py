@@ -33,8 +33,9 @@ def test_status_strings_and_workspace_size():
     assert lib.qce_status_string(0) == b"QCE_SUCCESS"
     assert lib.qce_status_string(2) == b"QCE_ERR_NOT_SUPPORTED"
     assert lib.qce_cgemm_workspace_size(0, 5, 5) == 0
-    # two panel buffers, padded to 128 rows and 16 k, 12 bytes per element
-    assert lib.qce_cgemm_workspace_size(100, 200, 40) == 128 * 48 * 12 + 256 * 48 * 12
+    # two panel buffers, padded to 128 rows and 16 k, 12 bytes per element,
+    # and one 144-byte statistics record per operand (rounded to 256 bytes)
+    assert lib.qce_cgemm_workspace_size(100, 200, 40) == 128 * 48 * 12 + 256 * 48 * 12 + 512
 
 
 def test_null_arguments_rejected_without_device():

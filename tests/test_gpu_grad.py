@@ -83,6 +83,29 @@ def test_grid12_matches_oracle_gradient(qce, h, mode):
     assert oracle.fidelity(amps, a_ref) >= 1 - 1e-6
 
 
+@pytest.mark.parametrize("mode", ["fp32", "auto_emulated"])
+def test_grid20_sliced_matches_oracle_gradient(qce, h, mode):
+    # 4 x 5 grid (20 qubits), depth 14, the network sliced (intermediates
+    # capped at 2^16 elements: 4 sliced labels): the adjoint Jacobian against the FP64
+    # product-rule gradient of the state vector on four couplers spread over
+    # the grid (each differentiated occurrence is one 2^20 state vector)
+    base = synth.grid_circuit(4, 5, 14, seed=4, pattern="ABCDCDAB")
+    ne = base["n_couplers"]
+    th = synth.coupler_thetas(ne, seed=5)
+    c = synth.with_thetas(base, th)
+    xs = synth.random_bitstrings(20, 4, seed=13)
+    run, plan = _runner(qce, h, c, max_log2=16, varied=3)
+    assert len(plan.sliced) >= 2
+    p, amps, J = _with_mode(h, mode, lambda: run.probabilities_and_jacobian(th, xs))
+    cols = [0, ne // 3, (2 * ne) // 3, ne - 1]
+    a_ref, J_ref = oracle.probability_theta_gradient(_rounded(c), xs, ne, couplers=cols)
+    assert oracle.fidelity(amps, a_ref) >= 1 - 1e-6
+    assert np.max(np.abs(amps - a_ref)) <= 1e-5 * np.max(np.abs(a_ref))
+    scale = np.max(np.abs(J_ref[:, cols]))
+    assert scale > 0
+    assert np.max(np.abs(J[:, cols] - J_ref[:, cols])) <= 2e-5 * scale
+
+
 def test_sliced_equals_unsliced(qce, h):
     base = synth.grid_circuit(3, 4, 8, seed=6, pattern="ABCDCDAB")
     th = synth.coupler_thetas(base["n_couplers"], seed=6)
