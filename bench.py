@@ -225,7 +225,7 @@ def run_gradients(h, args, torch, qce, synth):
     th = synth.coupler_thetas(ne, seed=5)
     c = synth.with_thetas(base, th)
     t0 = time.perf_counter()
-    plan = CircuitPlan(c, max_log2=28, restarts=40, alphas=(1.0, 1.5, 2.0), noises=(0.05,))
+    plan = CircuitPlan(c, max_log2=28, restarts=40, alphas=(1.0, 1.5, 2.0), noises=(0.05,), reconfigure="best")
     t_plan = time.perf_counter() - t0
     xs = synth.random_bitstrings(30, args.c5_bitstrings, seed=6)
     from paper_2303_08989_amd.grad import GradientGraph
@@ -638,7 +638,7 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
-    ap.add_argument("--c3-restarts", type=int, default=24)
+    ap.add_argument("--c3-restarts", type=int, default=8)
     ap.add_argument("--no-protocol", action="store_true",
                     help="skip the per-case median / cache-flush / three-seed timing section")
     ap.add_argument("--protocol-reps", type=int, default=20)

@@ -27,14 +27,14 @@ class CircuitPlan:
     """Planning (structure only, independent of the bitstring)."""
 
     def __init__(self, circuit, max_log2=28, restarts=8, seed=0, varied=6, path=None, sliced=None,
-                 alphas=(1.0,), noises=(0.1, 0.3, 1.0)):
+                 alphas=(1.0, 1.5), noises=(0.1, 0.3), reconfigure=True):
         self.circuit = circuit
         leaves = tn.circuit_network(circuit, 0)
         self.label_sets = [tuple(l) for _, l in leaves]
         L = len(self.label_sets)
         if path is None:
             path, sl = tn.best_greedy(self.label_sets, restarts=restarts, max_log2=max_log2, seed=seed,
-                                      alphas=alphas, noises=noises)
+                                      alphas=alphas, noises=noises, reconfigure=reconfigure)
             if sliced is None:
                 sliced = sl
         self.path = list(path)

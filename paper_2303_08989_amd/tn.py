@@ -12,6 +12,9 @@ contraction happens here; the contractions run on the GPU (``executor``).
   broken by smaller flop count; optional random perturbation for restarts.
   (The paper uses cotengra's hyper-optimised search, Sec. 5.1; this is the
   project's own greedy order.)
+* ``subtree_reconfigure``: local re-optimisation of a path: every subtree cut
+  at a frontier of up to 8 tensors is re-ordered optimally (dynamic
+  programming over subsets) for its largest intermediate, then flops.
 * ``choose_slices``: labels whose removal from every intermediate brings the
   largest intermediate under a bound, picked greedily by total cost
   (slicing, Sec. 5.3).
@@ -128,6 +131,131 @@ def greedy_path(label_sets, seed=None, noise=0.0, alpha=1.0):
     return path
 
 
+def subtree_reconfigure(label_sets, path, frontier=8, passes=4):
+    """Locally optimal re-ordering of a contraction tree.
+
+    For every node, largest tensor first, the subtree below it is cut at a
+    frontier of up to ``frontier`` tensors (expanding the largest internal
+    tensor each time) and the frontier's best contraction order is found by
+    dynamic programming over its subsets, ranked by (largest intermediate,
+    flops); a better order replaces the subtree.  Repeated for ``passes``
+    sweeps or until nothing changes.  Structure only: every label joins two
+    tensors, so the labels of a merged subset are the symmetric difference
+    of its members' labels.  Returns a new SSA path with the same leaves."""
+    L = len(label_sets)
+    children = {L + s: (a, b) for s, (a, b) in enumerate(path)}
+    labs = {i: frozenset(ls) for i, ls in enumerate(label_sets)}
+    for v in sorted(children):
+        a, b = children[v]
+        labs[v] = labs[a] ^ labs[b]
+    nid = L + len(path)
+
+    def subtree_cost(v, stop):
+        if v in stop:
+            return (0, 0.0)
+        a, b = children[v]
+        wa, fa = subtree_cost(a, stop)
+        wb, fb = subtree_cost(b, stop)
+        return (max(wa, wb, len(labs[v])), fa + fb + 2.0 ** len(labs[a] | labs[b]))
+
+    def remove(v, stop):
+        if v in stop:
+            return
+        a, b = children.pop(v)
+        remove(a, stop)
+        remove(b, stop)
+
+    for _ in range(passes):
+        changed = 0
+        for root in sorted(children, key=lambda v: (-len(labs[v]), v)):
+            if root not in children:
+                continue
+            front = [root]
+            while len(front) < frontier:
+                inner = [v for v in front if v in children]
+                if not inner:
+                    break
+                v = max(inner, key=lambda x: (len(labs[x]), x))
+                front.remove(v)
+                front.extend(children[v])
+            n = len(front)
+            if n < 3:
+                continue
+            col = {}
+            for v in front:
+                for lab in labs[v]:
+                    col.setdefault(lab, len(col))
+            bits = [sum(1 << col[lab] for lab in labs[v]) for v in front]
+            lab_of = [0] * (1 << n)
+            for S in range(1, 1 << n):
+                low = S & -S
+                lab_of[S] = lab_of[S ^ low] ^ bits[low.bit_length() - 1]
+            best = [None] * (1 << n)
+            for i in range(n):
+                best[1 << i] = ((0, 0.0), None)
+            for S in range(1, 1 << n):
+                if S & (S - 1) == 0:
+                    continue
+                size = bin(lab_of[S]).count("1")
+                pick = None
+                sub = (S - 1) & S
+                while sub:
+                    other = S ^ sub
+                    if sub < other:
+                        (wa, fa), _ = best[sub]
+                        (wb, fb), _ = best[other]
+                        key = (max(wa, wb, size), fa + fb + 2.0 ** bin(lab_of[sub] | lab_of[other]).count("1"))
+                        if pick is None or key < pick[0]:
+                            pick = (key, (sub, other))
+                    sub = (sub - 1) & S
+                best[S] = pick
+            full = (1 << n) - 1
+            stop = set(front)
+            if not best[full][0] < subtree_cost(root, stop):
+                continue
+            remove(root, stop)
+
+            def build(S):
+                nonlocal nid
+                if S & (S - 1) == 0:
+                    return front[S.bit_length() - 1]
+                a, b = best[S][1]
+                va, vb = build(a), build(b)
+                if S == full:
+                    v = root
+                else:
+                    v = nid
+                    nid += 1
+                children[v] = (va, vb)
+                labs[v] = labs[va] ^ labs[vb]
+                return v
+
+            build(full)
+            changed += 1
+        if not changed:
+            break
+    # back to SSA numbering, children before parents
+    kids = {x for ab in children.values() for x in ab}
+    roots = [v for v in children if v not in kids]
+    ren = {i: i for i in range(L)}
+    out = []
+    stack = [(r, False) for r in sorted(roots)]
+    while stack:
+        v, done = stack.pop()
+        if v < L:
+            continue
+        if done:
+            a, b = children[v]
+            out.append((ren[a], ren[b]))
+            ren[v] = L + len(out) - 1
+        else:
+            stack.append((v, True))
+            a, b = children[v]
+            stack.append((b, False))
+            stack.append((a, False))
+    return out
+
+
 def tree_labels(label_sets, path):
     """Labels of every SSA tensor (leaves then intermediates)."""
     labs = [frozenset(ls) for ls in label_sets]
@@ -234,22 +362,32 @@ def memoized_cost(label_sets, path, sliced, n_varied):
     return tot * 2.0 ** max(0, n_varied - len(sliced))
 
 
-def best_greedy(label_sets, restarts=8, max_log2=None, seed=0, noises=(0.1, 0.3, 1.0), alphas=(1.0,)):
+def best_greedy(label_sets, restarts=8, max_log2=None, seed=0, noises=(0.1, 0.3, 1.0), alphas=(1.0,),
+                reconfigure=False):
     """Best of one deterministic greedy path and `restarts` randomised ones,
-    for each size weight alpha of the greedy cost.  With a size bound, each
-    path is sliced to it and ranked by the memoized cost of the whole
-    amplitude (every slice); without, by (max intermediate, flops)."""
+    for each size weight alpha of the greedy cost.  ``reconfigure``: True
+    re-orders every candidate by ``subtree_reconfigure``, "best" only the
+    chosen one (kept if it ranks better).  With a size bound, each path is
+    sliced to it and ranked by the memoized cost of the whole amplitude
+    (every slice); without, by (max intermediate, flops)."""
+    def ranked(p):
+        if max_log2 is None:
+            ml, fl, _ = path_cost(label_sets, p)
+            return (ml, fl), p, []
+        sl = choose_slices(label_sets, p, max_log2)
+        return (memoized_cost(label_sets, p, sl, len(sl)), len(sl)), p, sl
+
     best = None
     for r, alpha in ((r, a) for r in range(restarts + 1) for a in alphas):
         noise = 0.0 if r == 0 else noises[r % len(noises)]
         p = greedy_path(label_sets, seed=seed + r, noise=noise, alpha=alpha)
-        if max_log2 is None:
-            ml, fl, _ = path_cost(label_sets, p)
-            key = (ml, fl)
-            sl = []
-        else:
-            sl = choose_slices(label_sets, p, max_log2)
-            key = (memoized_cost(label_sets, p, sl, len(sl)), len(sl))
-        if best is None or key < best[0]:
-            best = (key, p, sl)
+        if reconfigure is True:
+            p = subtree_reconfigure(label_sets, p)
+        cand = ranked(p)
+        if best is None or cand[0] < best[0]:
+            best = cand
+    if reconfigure == "best":
+        cand = ranked(subtree_reconfigure(label_sets, best[1]))
+        if cand[0] < best[0]:
+            best = cand
     return best[1], best[2]

@@ -129,7 +129,8 @@ def test_sliced_output_wires_give_scalar_leaves(standin):
     from paper_2303_08989_amd import tn
     from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan
     c = synth.grid_circuit(3, 4, 6, seed=3, pattern="ABCDCDAB")
-    base = CircuitPlan(c, max_log2=5, restarts=1, varied=3)
+    # the plain greedy path, whose batch labels enter the tree after these wires
+    base = CircuitPlan(c, max_log2=5, restarts=1, varied=3, reconfigure=False)
     wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
     plan = CircuitPlan(c, path=base.path, sliced=list(base.sliced) + wires[:2])
     bx = BatchedExecutor(None, plan, len(base.sliced), device="cpu")

@@ -110,7 +110,7 @@ def test_graph_replay_sliced_output_wires_back_to_back(qce, h):
     from paper_2303_08989_amd import tn
     from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, GraphPass
     c = synth.grid_circuit(3, 4, 8, seed=7, pattern="ABCDCDAB")
-    base = CircuitPlan(c, max_log2=5, restarts=2, varied=3)
+    base = CircuitPlan(c, max_log2=5, restarts=2, varied=3, reconfigure=False)   # batch labels enter after the wires
     wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
     plan = CircuitPlan(c, path=base.path, sliced=list(base.sliced) + wires[:2])
     bx = BatchedExecutor(h, plan, 3)
@@ -164,7 +164,7 @@ def test_graph_pass_every_outer_value(qce, h):
     from paper_2303_08989_amd import tn
     from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, GraphPass
     c = synth.grid_circuit(3, 4, 8, seed=7, pattern="ABCDCDAB")
-    base = CircuitPlan(c, max_log2=6, restarts=2, varied=3)
+    base = CircuitPlan(c, max_log2=6, restarts=2, varied=3, reconfigure=False)   # batch labels enter after the wire
     wires = [labels[0] for _, labels in tn.circuit_network(c, 0)[-c["n"]:]]
     plan = CircuitPlan(c, path=base.path, sliced=list(base.sliced) + wires[:1])
     bx = BatchedExecutor(h, plan, 3)

@@ -41,7 +41,7 @@ def h(qce):
 def plan():
     from paper_2303_08989_amd.executor import CircuitPlan
     c = synth.grid_circuit(pattern="ABCDCDAB", depth=12, seed=1, **synth.GRID_53)
-    return CircuitPlan(c, max_log2=28, restarts=24, varied=6)
+    return CircuitPlan(c, max_log2=28, restarts=8, varied=6)
 
 
 def _offsets(labels, sub, idx):
@@ -74,10 +74,10 @@ def _bound(mode, kk, S, sum_a, sum_b, s_min):
 
 
 def test_config3_slice_gemms_sampled(qce, h, plan):
-    # every contraction of the slice up to k = 2^20 (the 2^9 x 2^9 x 2^19
-    # split-k step included) on 16 sampled rows x 16 sampled columns; the
-    # final full contraction (k = 2^28, the fused permuted dot) has its own
-    # oracle test at 2^26 elements in tests/test_gpu_contract.py
+    # every contraction of the slice up to k = 2^20 (long split-k steps
+    # included) on 16 sampled rows x 16 sampled columns; a final full
+    # contraction of two 2^28-element tensors (the fused permuted dot) has
+    # its own oracle test at 2^26 elements in tests/test_gpu_contract.py
     from paper_2303_08989_amd import tn
     c = plan.circuit
     x = synth.random_bitstrings(53, 1, seed=5)[0]
@@ -135,8 +135,8 @@ def test_config3_slice_gemms_sampled(qce, h, plan):
     print("checked contractions by mode:", checked, "longest k:", longest_k, flush=True)
     # the big GEMMs of a slice take the emulated modes
     assert checked.get("bf16x3", 0) + checked.get("fp16x2", 0) + checked.get("fp16x2_scaled", 0) >= 1
-    assert sum(checked.values()) >= len(plan.path) - 2
-    assert longest_k >= 2 ** 19
+    assert sum(checked.values()) == sum(1 for (_, _, k2) in plan.gemm_shapes if k2 <= 20)
+    assert longest_k == 2 ** max(k2 for (_, _, k2) in plan.gemm_shapes if k2 <= 20)
 
 
 def test_config3_auto_vs_fp32_fidelity(qce, h, plan):

@@ -30,7 +30,8 @@ def h(qce):
 def _runner(qce, h, circuit, max_log2=30, varied=4):
     from paper_2303_08989_amd.executor import CircuitPlan
     from paper_2303_08989_amd.grad import GradientRunner
-    plan = CircuitPlan(circuit, max_log2=max_log2, restarts=2, varied=varied)
+    # the plain greedy path (the sliced-wire cases rely on its label order)
+    plan = CircuitPlan(circuit, max_log2=max_log2, restarts=2, varied=varied, reconfigure=False)
     return GradientRunner(h, plan), plan
 
 
