@@ -159,9 +159,12 @@ qce_status qce_set_underflow_tolerance(qce_handle *h, double t, double t3);
 
 /*
  * Size policy used by qce_contract when the handle mode is AUTO (Sec. 4.3):
- * min(m, n, k) >= auto_min -> AUTO (statistics + selection);
- * otherwise min(m, n, k) >= emul_min -> BF16X3 (the wide-exponent emulation,
- * as the paper uses TF32TCEC there); otherwise FP32.
+ * min(m, n, k) >= auto_min -> AUTO (statistics + selection); so are
+ * output-dominated GEMMs with k >= 64, min(m, n) >= auto_min and
+ * m n k >= 8 auto_min^3 (their FP32 products outlast the write of C, and the
+ * statistics read only the small operands); otherwise min(m, n, k) >=
+ * emul_min -> BF16X3 (the wide-exponent emulation, as the paper uses
+ * TF32TCEC there); otherwise FP32.
  * Requires 0 <= emul_min <= auto_min, else INVALID_VALUE.
  * Default auto_min = emul_min = 512: the thresholds are a calibration of
  * statistics cost against GEMM time; the paper's (2048, 512) are its A100
@@ -170,6 +173,18 @@ qce_status qce_set_underflow_tolerance(qce_handle *h, double t, double t3);
  */
 qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min);
 qce_status qce_get_size_policy(const qce_handle *h, int64_t *auto_min, int64_t *emul_min);
+
+/*
+ * Tile of the panel GEMM kernel for later calls: 128 (128 x 128 outputs per
+ * workgroup), 64 (64 x 64, for outputs too small to occupy the device), or
+ * 0 (default): the choice of the library's tile table, written by its
+ * autotuner from timings of both tiles (the batched GEMM variants of Sec. 3
+ * and the many small GEMMs of sliced networks, Sec. 5.3).  Results do not
+ * depend on the tile, except through the number of k splits (split-k
+ * shapes: few output tiles, long k), which follows the tile.
+ * INVALID_VALUE for any other value.
+ */
+qce_status qce_set_gemm_tile(qce_handle *h, int32_t tile);
 
 /*
  * Hand the library a caller-owned device workspace of `bytes` bytes (NULL,0

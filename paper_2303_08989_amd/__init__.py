@@ -101,6 +101,10 @@ class Handle:
         _check(self._h, self.lib.qce_get_size_policy(self._h, ctypes.byref(a), ctypes.byref(e)))
         return a.value, e.value
 
+    def set_gemm_tile(self, tile):
+        """Panel GEMM tile: 64, 128, or 0 for the library's tuned table."""
+        _check(self._h, self.lib.qce_set_gemm_tile(self._h, int(tile)))
+
     def set_workspace(self, tensor):
         if tensor is None:
             _check(self._h, self.lib.qce_set_workspace(self._h, None, 0))

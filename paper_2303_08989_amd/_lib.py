@@ -21,7 +21,8 @@ STATUS = {0: "QCE_SUCCESS", 1: "QCE_ERR_INVALID_VALUE", 2: "QCE_ERR_NOT_SUPPORTE
 # every symbol include/qcemu.h declares
 EXPORTS = (
     "qce_create", "qce_destroy", "qce_set_stream", "qce_set_mode", "qce_get_mode",
-    "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_get_size_policy", "qce_set_workspace",
+    "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_get_size_policy", "qce_set_gemm_tile",
+    "qce_set_workspace",
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
     "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_get_batch_decision",
     "qce_contract", "qce_group_begin", "qce_group_end", "qce_group_reset", "qce_permute", "qce_accumulate_f64", "qce_accumulate_n_f64", "qce_fidelity_f64",
@@ -86,6 +87,7 @@ def load():
         "qce_set_underflow_tolerance": (st, [vp, f64, f64]),
         "qce_set_size_policy": (st, [vp, i64, i64]),
         "qce_get_size_policy": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "qce_set_gemm_tile": (st, [vp, i32]),
         "qce_set_workspace": (st, [vp, vp, ctypes.c_size_t]),
         "qce_cgemm_workspace_size": (ctypes.c_size_t, [i64, i64, i64]),
         "qce_cgemm_emulated": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64,

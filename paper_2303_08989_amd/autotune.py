@@ -1,0 +1,134 @@
+"""Tile autotuner of the panel GEMM (64 x 64 vs 128 x 128 outputs per
+workgroup), run on the GPU.
+
+For a set of GEMM shapes -- the standalone CGEMM sizes and the matrix-core
+GEMMs of the batched sliced-network pass (each with its batch count) -- and
+for the FP16X2, BF16X3 and FP32 kernels, it times both tiles (hipEvents,
+median of repetitions, a 512 MiB buffer write before each so that operands
+are not served from the Infinity Cache), then writes
+
+* ``tile_table.inc``: rules by the number of 128 x 128 output tiles over all
+  batch entries (power-of-two buckets): each bucket takes the tile with the
+  smaller summed time over its shapes and modes; consecutive buckets with
+  the same tile merge.  The library compiles it in (``gemm_tile``).
+* ``autotune.json``: every timing.
+
+Usage (GPU): ``python -m paper_2303_08989_amd.autotune --out DIR``; copy
+DIR/tile_table.inc to csrc/ and rebuild.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# (m, n, k, batch): standalone sizes, then GEMMs of the batched pass of the
+# 53-qubit network (2^18 intermediates, 1024 slices) seen in its plan
+DEFAULT_SHAPES = [
+    (512, 512, 512, 1), (768, 768, 768, 1), (1024, 1024, 1024, 1), (1536, 1536, 1536, 1),
+    (2048, 2048, 2048, 1), (4096, 4096, 4096, 1),
+    (256, 256, 1024, 4), (4096, 4096, 64, 4), (512, 512, 256, 16), (1024, 256, 128, 32),
+    (256, 512, 2048, 2), (2048, 1024, 512, 1), (8192, 256, 256, 1), (128, 128, 4096, 8),
+]
+MODES = ("fp16x2", "bf16x3", "fp32")
+
+
+def _bucket(tiles128):
+    return 0 if tiles128 <= 1 else int(math.floor(math.log2(tiles128)))
+
+
+def measure(shapes, reps=10):
+    import torch
+    import paper_2303_08989_amd as qce
+    h = qce.Handle(0)
+    flush = torch.empty(512 << 18, dtype=torch.float32, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    rows = []
+    for (m, n, k, batch) in shapes:
+        A = torch.randn(batch * m * k, dtype=torch.complex64, device="cuda", generator=g)
+        B = torch.randn(batch * k * n, dtype=torch.complex64, device="cuda", generator=g)
+        C = torch.empty(batch * m * n, dtype=torch.complex64, device="cuda")
+        for mode in MODES:
+            h.set_mode(mode)
+            rec = {"m": m, "n": n, "k": k, "batch": batch, "mode": mode}
+            for tile in (64, 128):
+                h.set_gemm_tile(tile)
+
+                def call():
+                    qce.cgemm_strided_batched(h, "N", "N", m, n, k, A, m, m * k, B, k, k * n, C, m, m * n, batch)
+                for _ in range(2):
+                    call()
+                ts = []
+                for r in range(reps):
+                    flush.fill_(float(r))
+                    ev0.record()
+                    call()
+                    ev1.record()
+                    ev1.synchronize()
+                    ts.append(ev0.elapsed_time(ev1))
+                rec[f"ms_{tile}"] = float(np.median(ts))
+            rows.append(rec)
+            print(json.dumps(rec), flush=True)
+        del A, B, C
+    h.set_gemm_tile(0)
+    h.close()
+    return rows
+
+
+def table(rows):
+    """Rules {min_tiles128, min_chunks, tile} from the timings."""
+    sums = {}
+    for r in rows:
+        t128 = -(-r["m"] // 128) * -(-r["n"] // 128) * r["batch"]
+        b = _bucket(t128)
+        s = sums.setdefault(b, [0.0, 0.0])
+        s[0] += r["ms_64"]
+        s[1] += r["ms_128"]
+    rules = []
+    for b in sorted(sums):
+        tile = 64 if sums[b][0] < sums[b][1] else 128
+        lo = 0 if b == 0 else 1 << b
+        if not rules or rules[-1][2] != tile:
+            rules.append((lo, 0, tile))
+    if rules and rules[0][0] != 0:
+        rules[0] = (0, 0, rules[0][2])
+    return rules, {str(b): v for b, v in sums.items()}
+
+
+def write_table(rules, path):
+    lines = [
+        "// Tile shape of the panel GEMM by output size, written by",
+        "// paper_2303_08989_amd/autotune.py from timings of both tiles (the summed",
+        "// median time over the measured shapes and modes of each power-of-two",
+        "// bucket of 128 x 128 output tiles, batch entries included).",
+        "// { first count of 128 x 128 tiles (all batch entries), first chunk count",
+        "//   (k / 16), tile }: the last rule whose firsts are both reached applies.",
+        "static const TileRule kTileRules[] = {",
+    ]
+    lines += [f"    {{{lo}, {ch}, {tile}}}," for lo, ch, tile in rules]
+    lines.append("};")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default="gpurun_out/autotune")
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    rows = measure(DEFAULT_SHAPES, args.reps)
+    rules, sums = table(rows)
+    write_table(rules, os.path.join(args.out, "tile_table.inc"))
+    with open(os.path.join(args.out, "autotune.json"), "w") as f:
+        json.dump({"rows": rows, "bucket_ms_64_128": sums, "rules": rules}, f, indent=1)
+    print("rules:", rules, file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,6 +57,7 @@ struct qce_handle {
     bool grouping = false;
     bool fused_gather = true;  // permute fused into the split (qce_contract)
     bool smallk = true;        // short-k narrow GEMMs split on load (no panel pass)
+    int gemm_tile = 0;         // panel GEMM tile: 64, 128, or 0 for the tuned table
     std::vector<qce::SmallItem> pending;
     char *grp_dev = nullptr;   // descriptor arena on the device
     char *grp_host = nullptr;  // its pinned host mirror (source of the copies)
@@ -396,6 +397,7 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     g.beta = beta;
     g.beta_zero = beta_zero;
     g.partial = gemm_partial_bytes(m, n, k, bt.count) ? reinterpret_cast<float2 *>(part) : nullptr;
+    g.tile = h->gemm_tile;
     const int nb = bt.count;
     if (h->smallk && !a.gm && !b.gm && smallk_shape(m, n, k)) {
         // short k, narrow C: split on load, no panel pass
@@ -501,6 +503,22 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         }
     }
     return QCE_SUCCESS;
+}
+
+// Size policy of qce_contract in AUTO mode (Sec. 4.3): statistics for
+// min(m, n, k) >= auto_min, and for output-dominated GEMMs too (k >= 64,
+// min(m, n) >= auto_min, m n k >= 8 auto_min^3: there the FP32 products
+// take longer than writing C, so the emulation pays while the statistics
+// read only the small operands); BF16X3 for min(m, n, k) >= emul_min;
+// otherwise FP32.
+int policy_mode(const qce_handle *h, int64_t m, int64_t n, int64_t k) {
+    const int64_t mn = std::min(std::min(m, n), k);
+    if (mn >= h->auto_min) return QCE_MODE_AUTO;
+    const double a = (double)h->auto_min;
+    if (k >= 64 && std::min(m, n) >= h->auto_min && (double)m * (double)n * (double)k >= 8.0 * a * a * a)
+        return QCE_MODE_AUTO;
+    if (mn >= h->emul_min) return QCE_MODE_BF16X3;
+    return QCE_MODE_FP32;
 }
 
 size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k, int count = 1) {
@@ -795,6 +813,12 @@ qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min
     if (!h || emul_min < 0 || emul_min > auto_min) return QCE_ERR_INVALID_VALUE;
     h->auto_min = auto_min;
     h->emul_min = emul_min;
+    return QCE_SUCCESS;
+}
+
+qce_status qce_set_gemm_tile(qce_handle *h, int32_t tile) {
+    if (!h || (tile != 0 && tile != 64 && tile != 128)) return QCE_ERR_INVALID_VALUE;
+    h->gemm_tile = tile;
     return QCE_SUCCESS;
 }
 
@@ -1418,12 +1442,7 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
         vy = OperandView{static_cast<const float2 *>(Y), std::max<int64_t>(1, kk), true, false};
     }
     int mode = h->mode;
-    if (mode == QCE_MODE_AUTO) {
-        const int64_t mn = std::min(std::min(m, n), kk);
-        if (mn >= h->auto_min) mode = QCE_MODE_AUTO;
-        else if (mn >= h->emul_min) mode = QCE_MODE_BF16X3;
-        else mode = QCE_MODE_FP32;
-    }
+    if (mode == QCE_MODE_AUTO) mode = policy_mode(h, m, n, kk);
     float2 *Cg = out_perm ? reinterpret_cast<float2 *>(ws + offc) : static_cast<float2 *>(C);
     // batch entries in launches of at most kMaxBatch
     for (int64_t z0 = 0; z0 < std::max<int64_t>(count, 1); z0 += chunk) {

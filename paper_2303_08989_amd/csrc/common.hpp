@@ -163,10 +163,13 @@ struct GemmArgs {
     int64_t bsA, bsB;        // panel bytes between entries
     int64_t bsC;             // C elements between entries
     int64_t bsPartial;       // partial elements between entries
+    int tile;                // 64 or 128: that tile; else the tile table's choice
 };
 // which_kernel: a mode (forced) or -1 (AUTO: read the device flag)
 hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
-size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch = 1);  // per entry
+size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch = 1);  // per entry, either tile
+// tile of the panel GEMM for this output size (the tuned table)
+int gemm_tile(int64_t m, int64_t n, int64_t k, int batch = 1);
 
 // Short-k, narrow-output GEMM with the split done on load (gemm.hip):
 // C (m x n, n <= 64) = alpha op(A) op(B) + beta C for k <= 128, reading the

@@ -47,7 +47,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kTile = 128;
 
 __device__ inline u32x4 neg_halves(u32x4 v) { return v ^ 0x80008000u; }
 
@@ -209,35 +208,54 @@ template <> struct Frag<QCE_MODE_FP32> {
     f32x4 xr[2][2], xi[2][2], yr[2][2], yi[2][2];  // [s][block]
 };
 
-template <int MODE>
-__device__ __attribute__((always_inline)) inline void load_part(u32x4 *dst, const char *s, int row, int gr) {
+// Per-chunk counts of a wave with WB x WB blocks of 32 x 32 (WB = 2: the
+// 128 x 128 tile, WB = 1: the 64 x 64 tile): fragment reads and MFMAs.
+template <int MODE, int WB> struct ChunkWork {
+    static constexpr int kReads = Frag<MODE>::kReads * WB / 2;
+    static constexpr int kMfma = Frag<MODE>::kMfma * WB * WB / 4;
+};
+
+// LDS offset of (plane, row, granule) in a stage holding ROWS rows of each
+// plane (the panel chunk, or the half of it a 64-row tile copies); the
+// granule swizzle depends on the row's low bits only, so either half of a
+// chunk keeps the panel's swizzle.
+template <int MODE, int ROWS>
+__device__ __host__ constexpr int lds_offset(int plane, int row, int granule) {
     using G = PanelGeom<MODE>;
+    return plane * ROWS * G::kRowBytes + row * G::kRowBytes + ((granule ^ G::swz(row)) << 4);
+}
+
+template <int MODE, int ROWS>
+__device__ __attribute__((always_inline)) inline void load_part(u32x4 *dst, const char *s, int row, int gr) {
 #pragma unroll
-    for (int p = 0; p < Frag<MODE>::kP; ++p) dst[p] = *reinterpret_cast<const u32x4 *>(s + G::offset(p, row, gr));
+    for (int p = 0; p < Frag<MODE>::kP; ++p)
+        dst[p] = *reinterpret_cast<const u32x4 *>(s + lds_offset<MODE, ROWS>(p, row, gr));
 }
 
 // Every fragment of one chunk: x rows from the B panel (sx), y rows from
 // the A panel (sy); r0 = wave's first x row + lane%32, q0 likewise for y.
-template <int MODE>
+template <int MODE, int WB>
 __device__ __attribute__((always_inline)) inline void load_chunk(Frag<MODE> &f, const char *sx, const char *sy,
                                                                  int rx0, int ry0, int lane) {
+    constexpr int kRows = 64 * WB;  // rows of each plane in the stage
     const int hi = lane >> 5;
     if constexpr (MODE == QCE_MODE_FP32) {
-        using G = PanelGeom<QCE_MODE_FP32>;
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                f.xr[s][b] = *reinterpret_cast<const f32x4 *>(sx + G::offset(0, rx0 + 32 * b, 2 * s + hi));
-                f.xi[s][b] = *reinterpret_cast<const f32x4 *>(sx + G::offset(1, rx0 + 32 * b, 2 * s + hi));
-                f.yr[s][b] = *reinterpret_cast<const f32x4 *>(sy + G::offset(0, ry0 + 32 * b, 2 * s + hi));
-                f.yi[s][b] = *reinterpret_cast<const f32x4 *>(sy + G::offset(1, ry0 + 32 * b, 2 * s + hi));
+            for (int b = 0; b < WB; ++b) {
+                f.xr[s][b] = *reinterpret_cast<const f32x4 *>(sx + lds_offset<MODE, kRows>(0, rx0 + 32 * b, 2 * s + hi));
+                f.xi[s][b] = *reinterpret_cast<const f32x4 *>(sx + lds_offset<MODE, kRows>(1, rx0 + 32 * b, 2 * s + hi));
+                f.yr[s][b] = *reinterpret_cast<const f32x4 *>(sy + lds_offset<MODE, kRows>(0, ry0 + 32 * b, 2 * s + hi));
+                f.yi[s][b] = *reinterpret_cast<const f32x4 *>(sy + lds_offset<MODE, kRows>(1, ry0 + 32 * b, 2 * s + hi));
             }
     } else {
-        load_part<MODE>(f.x[0], sx, rx0, hi);
-        load_part<MODE>(f.y[0], sy, ry0, hi);
-        load_part<MODE>(f.y[1], sy, ry0 + 32, hi);
-        load_part<MODE>(f.x[1], sx, rx0 + 32, hi);
+        load_part<MODE, kRows>(f.x[0], sx, rx0, hi);
+        load_part<MODE, kRows>(f.y[0], sy, ry0, hi);
+        if constexpr (WB == 2) {
+            load_part<MODE, kRows>(f.y[1], sy, ry0 + 32, hi);
+            load_part<MODE, kRows>(f.x[1], sx, rx0 + 32, hi);
+        }
     }
 }
 
@@ -265,13 +283,13 @@ __device__ __attribute__((always_inline)) inline void mma_block(const Frag<MODE>
 
 __device__ __attribute__((always_inline)) inline void opaque(f32x4 &v) { asm volatile("" : "+v"(v)); }
 
-template <int MODE>
+template <int MODE, int WB>
 __device__ __attribute__((always_inline)) inline void opaque_frag(Frag<MODE> &f) {
     if constexpr (MODE == QCE_MODE_FP32) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < WB; ++b) {
                 opaque(f.xr[s][b]);
                 opaque(f.xi[s][b]);
                 opaque(f.yr[s][b]);
@@ -279,21 +297,23 @@ __device__ __attribute__((always_inline)) inline void opaque_frag(Frag<MODE> &f)
             }
     } else {
 #pragma unroll
-        for (int p = 0; p < Frag<MODE>::kP; ++p) {
-            opaque(f.x[0][p]);
-            opaque(f.x[1][p]);
-            opaque(f.y[0][p]);
-            opaque(f.y[1][p]);
-        }
+        for (int p = 0; p < Frag<MODE>::kP; ++p)
+#pragma unroll
+            for (int b = 0; b < WB; ++b) {
+                opaque(f.x[b][p]);
+                opaque(f.y[b][p]);
+            }
     }
 }
 
-template <int MODE>
+template <int MODE, int WB>
 __device__ __attribute__((always_inline)) inline void mma_chunk(const Frag<MODE> &f, Acc<MODE> &acc) {
     mma_block<MODE>(f, 0, 0, acc);
-    mma_block<MODE>(f, 0, 1, acc);
-    mma_block<MODE>(f, 1, 0, acc);
-    mma_block<MODE>(f, 1, 1, acc);
+    if constexpr (WB == 2) {
+        mma_block<MODE>(f, 0, 1, acc);
+        mma_block<MODE>(f, 1, 0, acc);
+        mma_block<MODE>(f, 1, 1, acc);
+    }
 }
 
 template <int MODE> constexpr int smem_bytes() {
@@ -304,10 +324,12 @@ static_assert(smem_bytes<QCE_MODE_FP16X2>() <= kSmemBytes && smem_bytes<QCE_MODE
               "LDS budget");
 static_assert(kSmemBytes <= 160 * 1024, "gfx950 LDS");
 
-// The tile of one workgroup for one mode.  blockIdx.y selects a range of k
-// (split-k): with several ranges the unscaled partial tile goes to
-// g.partial and gemm_reduce_kernel finishes the sum and the epilogue.
-template <int MODE>
+// The tile of one workgroup for one mode: TILE x TILE outputs (128: four
+// waves of 64 x 64; 64: four waves of 32 x 32, reading half of each panel
+// chunk).  blockIdx.y selects a range of k (split-k): with several ranges
+// the unscaled partial tile goes to g.partial and gemm_reduce_kernel
+// finishes the sum and the epilogue.
+template <int MODE, int TILE>
 __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &g, int nbm, int nbn,
                                                                 int mode, char *smem_raw) {
     int shift_total = 0;
@@ -315,11 +337,16 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         shift_total = g.st->shift[0] + g.st->shift[1];
 
     using G = PanelGeom<MODE>;
-    constexpr int kCB = G::kChunkBytes;
+    static_assert(TILE == 128 || TILE == 64, "tile shapes");
+    constexpr int kWB = TILE / 64;                  // 32 x 32 blocks per wave and dimension
+    constexpr int kCB = G::kChunkBytes;             // one panel chunk (128 rows) in HBM
+    constexpr int kOB = kCB * TILE / kPanelRows;    // the rows of it one operand copies
+    constexpr int kHalf = G::kPlaneBytes / 2;       // a 64-row half of one plane
     constexpr int kNS = Stages<MODE>::kNS;          // LDS stages in the ring
-    constexpr int kL1 = kCB / (16 * kThreads);      // 16-byte copies per thread per operand chunk
+    constexpr int kL1 = kOB / (16 * kThreads);      // 16-byte copies per thread per operand chunk
     constexpr int kL = 2 * kL1;                      // per stage (both operands)
-    typedef char Stage[2][kCB];
+    static_assert(kOB % (16 * kThreads) == 0, "whole copies");
+    typedef char Stage[2][kOB];
     Stage *smem = reinterpret_cast<Stage *>(smem_raw);
 
     int mb, nb;
@@ -330,8 +357,11 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
     const int kb0 = (int)((int64_t)blockIdx.y * g.kpad_per_split / PanelFmt<MODE>::kBK);
     const int kb1 = min(nkb, kb0 + (int)(g.kpad_per_split / PanelFmt<MODE>::kBK));
     const int nk = max(0, kb1 - kb0);
-    const char *px = static_cast<const char *>(g.panelsB) + ((int64_t)nb * nkb + kb0) * kCB;
-    const char *py = static_cast<const char *>(g.panelsA) + ((int64_t)mb * nkb + kb0) * kCB;
+    // panel row block of the tile and, for 64-row tiles, its half
+    const int64_t pnb = (int64_t)nb * TILE / kPanelRows, pmb = (int64_t)mb * TILE / kPanelRows;
+    const int hnb = TILE == 64 ? (nb & 1) : 0, hmb = TILE == 64 ? (mb & 1) : 0;
+    const char *px = static_cast<const char *>(g.panelsB) + (pnb * nkb + kb0) * kCB;
+    const char *py = static_cast<const char *>(g.panelsA) + (pmb * nkb + kb0) * kCB;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wu = w >> 1, wv = w & 1;
@@ -377,7 +407,18 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
         // takes no vector instruction, which matters because a vector
         // instruction between two FP32 MFMAs adds its full latency.
         const int wsc = __builtin_amdgcn_readfirstlane(w);
-        const unsigned lane_off = (unsigned)tid * 16u;
+        // source byte of this lane's first copy: the whole chunk is copied
+        // in order for 128-row tiles; a 64-row tile copies, plane by plane,
+        // the half holding its rows (LDS byte b of the stage comes from
+        // plane b / kHalf, byte kHalf * half + b % kHalf of that plane)
+        const unsigned off_x = TILE == kPanelRows ? (unsigned)tid * 16u
+                             : (unsigned)((tid * 16 / kHalf) * G::kPlaneBytes + (tid * 16) % kHalf + hnb * kHalf);
+        const unsigned off_y = TILE == kPanelRows ? (unsigned)tid * 16u
+                             : (unsigned)((tid * 16 / kHalf) * G::kPlaneBytes + (tid * 16) % kHalf + hmb * kHalf);
+        // source distance between a thread's consecutive copies
+        constexpr int kSrcStep = TILE == kPanelRows ? kThreads * 16 : 2 * kThreads * 16;
+        static_assert(TILE == kPanelRows || kHalf % (kThreads * 16) == 0 || (kThreads * 16) % kHalf == 0,
+                      "copy rows align with half planes");
         auto issue_to = [&](int c, int stage) {
             const char *gx = chunk_src(c, nk, px + (int64_t)c * kCB, zero);
             const char *gy = chunk_src(c, nk, py + (int64_t)c * kCB, zero);
@@ -388,12 +429,12 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
 #pragma unroll
             for (int i = 0; i < kL1; ++i) {
                 const int we = (wsc * 64 + i * kThreads) * 16;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, LDS_PTR(lx + we), 16, lane_off, i * kThreads * 16, 0, 0);
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, LDS_PTR(ly + we), 16, lane_off, i * kThreads * 16, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, LDS_PTR(lx + we), 16, off_x, i * kSrcStep, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, LDS_PTR(ly + we), 16, off_y, i * kSrcStep, 0, 0);
             }
         };
         const int l32 = lane & 31;
-        const int rx0 = wu * 64 + l32, ry0 = wv * 64 + l32;
+        const int rx0 = wu * 32 * kWB + l32, ry0 = wv * 32 * kWB + l32;
         // 64 KB as a value the optimizer cannot see through: the address
         // registers built on it are computed once, outside the loop
         int hi_base = 65536;
@@ -417,26 +458,28 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
             const int cur = stage;
             const int ns = (cur + 1) % kNS;
             if constexpr (std::is_integral_v<decltype(stage)>) {
-                load_chunk<MODE>(fn, smem[ns][0], smem[ns][1], rx0, ry0, lane);
+                load_chunk<MODE, kWB>(fn, smem[ns][0], smem[ns][1], rx0, ry0, lane);
             } else {
                 // stages past 64 KB are read from a second base (an LDS
                 // read's immediate offset stops at 64 KB)
                 constexpr int kNext = (decltype(stage)::value + 1) % kNS;
-                const char *b = kNext * 2 * kCB < 65536 ? smem[kNext][0]
-                                                        : smem_raw + hi_base + (kNext * 2 * kCB - 65536);
-                load_chunk<MODE>(fn, b, b + kCB, rx0, ry0, lane);
+                const char *b = kNext * 2 * kOB < 65536 ? smem[kNext][0]
+                                                        : smem_raw + hi_base + (kNext * 2 * kOB - 65536);
+                load_chunk<MODE, kWB>(fn, b, b + kOB, rx0, ry0, lane);
             }
             issue_to(it + kNS, cur);
-            mma_chunk<MODE>(fc, acc);
+            mma_chunk<MODE, kWB>(fc, acc);
             // Interleave: one fragment read every kA MFMAs, then one copy
             // every kB MFMAs, then the remaining MFMAs.  The reads are
             // spread rather than bunched because the four waves share the
             // CU's LDS bandwidth (~128 B per clock): two 1 KB wave reads per
             // 32-cycle f16 MFMA on every SIMD ask for twice that and stall
             // the MFMAs; one per kA MFMAs stays well below it.
-            constexpr int kReads = Frag<MODE>::kReads, kMfma = Frag<MODE>::kMfma;
-            constexpr int kA = Frag<MODE>::kMfmaPerRead;
+            constexpr int kReads = ChunkWork<MODE, kWB>::kReads, kMfma = ChunkWork<MODE, kWB>::kMfma;
             constexpr int kCopies = 2 * kL1;
+            // (the 64 x 64 tile has fewer MFMAs per read: leave room for the copies)
+            constexpr int kAFit = (kMfma - kCopies) / kReads > 0 ? (kMfma - kCopies) / kReads : 1;
+            constexpr int kA = kAFit < Frag<MODE>::kMfmaPerRead ? kAFit : Frag<MODE>::kMfmaPerRead;
             constexpr int kB = (kMfma - kA * kReads) / (kCopies + 1) > 0 ? (kMfma - kA * kReads) / (kCopies + 1) : 1;
             static_assert(kA * kReads + kB * kCopies <= kMfma, "interleave exceeds the chunk's MFMAs");
 #pragma unroll
@@ -455,10 +498,10 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
 #pragma unroll
         for (int c = 0; c < kNS; ++c) issue_to(c, c);
         wait_barrier<(kNS - 1) * kL>();  // chunk 0
-        load_chunk<MODE>(f0, smem[0][0], smem[0][1], rx0, ry0, lane);
+        load_chunk<MODE, kWB>(f0, smem[0][0], smem[0][1], rx0, ry0, lane);
         // keeps the optimizer from merging these reads with the loop's
         // reads into f0 as one read at the top of the loop
-        opaque_frag(f0);
+        opaque_frag<MODE, kWB>(f0);
         // (the last k-step reads a chunk past the end, unused)
         if constexpr (MODE == QCE_MODE_FP32 && kNS == 4) {
             using S0 = std::integral_constant<int, 0>;
@@ -491,13 +534,13 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
     const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
     const int l32 = lane & 31, hi = lane >> 5;
 #pragma unroll
-    for (int ub = 0; ub < 2; ++ub)
+    for (int ub = 0; ub < kWB; ++ub)
 #pragma unroll
-        for (int vb = 0; vb < 2; ++vb) {
-            const int64_t i = (int64_t)mb * kTile + wv * 64 + vb * 32 + l32;
+        for (int vb = 0; vb < kWB; ++vb) {
+            const int64_t i = (int64_t)mb * TILE + wv * 32 * kWB + vb * 32 + l32;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t j = (int64_t)nb * kTile + wu * 64 + ub * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                const int64_t j = (int64_t)nb * TILE + wu * 32 * kWB + ub * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
                 if (i >= g.m || j >= g.n) continue;
                 float re, im;
                 if constexpr (MODE == QCE_MODE_FP16X2) {
@@ -546,26 +589,29 @@ __device__ inline void select_entry(GemmArgs &g) {
     if (g.partial) g.partial += z * g.bsPartial;
 }
 
-// Forced mode: one kernel per mode.
-template <int MODE>
-__global__ __launch_bounds__(kThreads, 1) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
-    __shared__ __attribute__((aligned(16))) char smem[smem_bytes<MODE>()];
+// Forced mode: one kernel per mode and tile.  A 128 x 128 tile holds one
+// workgroup per CU; a 64 x 64 tile needs half the LDS and registers, so two
+// fit.
+template <int MODE, int TILE>
+__global__ __launch_bounds__(kThreads, TILE == 128 ? 1 : 2) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
+    __shared__ __attribute__((aligned(16))) char smem[smem_bytes<MODE>() * TILE / kPanelRows];
     select_entry(g);
-    gemm_body<MODE>(g, nbm, nbn, g.forced_mode, smem);
+    gemm_body<MODE, TILE>(g, nbm, nbn, g.forced_mode, smem);
 }
 
 // Statistics-selected mode: one launch that reads the device mode flag and
 // runs the selected mode's tile (the others never start).
-__global__ __launch_bounds__(kThreads, 1) void gemm_auto_kernel(GemmArgs g, int nbm, int nbn) {
-    __shared__ __attribute__((aligned(16))) char smem[kSmemBytes];
+template <int TILE>
+__global__ __launch_bounds__(kThreads, TILE == 128 ? 1 : 2) void gemm_auto_kernel(GemmArgs g, int nbm, int nbn) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemBytes * TILE / kPanelRows];
     select_entry(g);
     const int mode = g.st->mode;
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
-        gemm_body<QCE_MODE_FP16X2>(g, nbm, nbn, mode, smem);
+        gemm_body<QCE_MODE_FP16X2, TILE>(g, nbm, nbn, mode, smem);
     else if (mode == QCE_MODE_BF16X3)
-        gemm_body<QCE_MODE_BF16X3>(g, nbm, nbn, mode, smem);
+        gemm_body<QCE_MODE_BF16X3, TILE>(g, nbm, nbn, mode, smem);
     else
-        gemm_body<QCE_MODE_FP32>(g, nbm, nbn, mode, smem);
+        gemm_body<QCE_MODE_FP32, TILE>(g, nbm, nbn, mode, smem);
 }
 
 // Split-k: add the partial tiles in split order, then shift / alpha / beta.
@@ -845,34 +891,66 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
 
 }  // namespace
 
-int gemm_splits(int64_t m, int64_t n, int64_t k, int batch) {
-    const int64_t tiles = ((m + kTile - 1) / kTile) * ((n + kTile - 1) / kTile) * std::max(1, batch);
+namespace {
+struct TileRule {
+    int64_t min_tiles128, min_chunks;
+    int tile;
+};
+#include "tile_table.inc"
+}  // namespace
+
+int gemm_tile(int64_t m, int64_t n, int64_t k, int batch) {
+    const int64_t tiles = ((m + 127) / 128) * ((n + 127) / 128) * std::max(1, batch);
+    const int64_t chunks = round_up(k, kKPad) / kKPad;
+    int tile = 128;
+    for (const TileRule &r : kTileRules)
+        if (tiles >= r.min_tiles128 && chunks >= r.min_chunks) tile = r.tile;
+    return tile;
+}
+
+int gemm_splits(int64_t m, int64_t n, int64_t k, int batch, int tile) {
+    const int64_t tiles = ((m + tile - 1) / tile) * ((n + tile - 1) / tile) * std::max(1, batch);
     const int64_t pads = round_up(k, kKPad) / kKPad;  // chunks of 16 k-values
-    if (tiles >= 256 || pads < 32) return 1;
-    int64_t s = 512 / tiles;              // aim at ~512 workgroups
-    s = std::min<int64_t>(s, pads / 16);  // keep >= 16 chunks (256 k-values) per split
+    // keep >= 16 chunks (256 k-values) per split for 128 x 128 tiles, >= 8
+    // for the 64 x 64 tile (a quarter of the MFMAs per chunk)
+    const int64_t min_chunks = tile == 64 ? 8 : 16;
+    if (tiles >= 256 || pads < 2 * min_chunks) return 1;
+    int64_t s = 512 / tiles;                      // aim at ~512 workgroups
+    s = std::min<int64_t>(s, pads / min_chunks);
     return (int)std::max<int64_t>(1, s);
 }
 
 hipError_t launch_gemm(const GemmArgs &g0, int which, hipStream_t s) {
     GemmArgs g = g0;
-    const int nbm = (int)((g.m + kTile - 1) / kTile), nbn = (int)((g.n + kTile - 1) / kTile);
+    const int tile = g.tile == 64 || g.tile == 128 ? g.tile : gemm_tile(g.m, g.n, g.k, std::max(1, g.batch));
+    const int nbm = (int)((g.m + tile - 1) / tile), nbn = (int)((g.n + tile - 1) / tile);
     const int batch = std::max(1, g.batch);
-    const int splits = gemm_splits(g.m, g.n, g.k, batch);
+    const int splits = gemm_splits(g.m, g.n, g.k, batch, tile);
     const int64_t pads = round_up(g.k, kKPad) / kKPad;
     g.kpad_per_split = ((pads + splits - 1) / splits) * kKPad;
     const int nsplit = (int)((round_up(g.k, kKPad) + g.kpad_per_split - 1) / g.kpad_per_split);
     g.bsPartial = (int64_t)nsplit * g.m * g.n;
     const dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit, (unsigned)batch), block(kThreads);
     if (nsplit > 1 && !g.partial) return hipErrorInvalidValue;
-    if (which < 0)
-        hipLaunchKernelGGL(gemm_auto_kernel, grid, block, 0, s, g, nbm, nbn);
-    else if (which == QCE_MODE_FP16X2)
-        hipLaunchKernelGGL(gemm_kernel<QCE_MODE_FP16X2>, grid, block, 0, s, g, nbm, nbn);
-    else if (which == QCE_MODE_BF16X3)
-        hipLaunchKernelGGL(gemm_kernel<QCE_MODE_BF16X3>, grid, block, 0, s, g, nbm, nbn);
-    else
-        hipLaunchKernelGGL(gemm_kernel<QCE_MODE_FP32>, grid, block, 0, s, g, nbm, nbn);
+    if (tile == 64) {
+        if (which < 0)
+            hipLaunchKernelGGL(gemm_auto_kernel<64>, grid, block, 0, s, g, nbm, nbn);
+        else if (which == QCE_MODE_FP16X2)
+            hipLaunchKernelGGL((gemm_kernel<QCE_MODE_FP16X2, 64>), grid, block, 0, s, g, nbm, nbn);
+        else if (which == QCE_MODE_BF16X3)
+            hipLaunchKernelGGL((gemm_kernel<QCE_MODE_BF16X3, 64>), grid, block, 0, s, g, nbm, nbn);
+        else
+            hipLaunchKernelGGL((gemm_kernel<QCE_MODE_FP32, 64>), grid, block, 0, s, g, nbm, nbn);
+    } else {
+        if (which < 0)
+            hipLaunchKernelGGL(gemm_auto_kernel<128>, grid, block, 0, s, g, nbm, nbn);
+        else if (which == QCE_MODE_FP16X2)
+            hipLaunchKernelGGL((gemm_kernel<QCE_MODE_FP16X2, 128>), grid, block, 0, s, g, nbm, nbn);
+        else if (which == QCE_MODE_BF16X3)
+            hipLaunchKernelGGL((gemm_kernel<QCE_MODE_BF16X3, 128>), grid, block, 0, s, g, nbm, nbn);
+        else
+            hipLaunchKernelGGL((gemm_kernel<QCE_MODE_FP32, 128>), grid, block, 0, s, g, nbm, nbn);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsplit == 1) return e;
     const int64_t mn = g.m * g.n;
@@ -882,12 +960,17 @@ hipError_t launch_gemm(const GemmArgs &g0, int which, hipStream_t s) {
 }
 
 size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch) {
-    const int splits = gemm_splits(m, n, k, batch);
-    if (splits <= 1) return 0;
-    const int64_t pads = round_up(k, kKPad) / kKPad;
-    const int64_t per = ((pads + splits - 1) / splits) * kKPad;
-    const int64_t nsplit = (round_up(k, kKPad) + per - 1) / per;
-    return nsplit > 1 ? (size_t)nsplit * (size_t)(m * n) * sizeof(float2) : 0;
+    // enough for either tile (the launch may be told which)
+    size_t most = 0;
+    for (int tile : {64, 128}) {
+        const int splits = gemm_splits(m, n, k, batch, tile);
+        if (splits <= 1) continue;
+        const int64_t pads = round_up(k, kKPad) / kKPad;
+        const int64_t per = ((pads + splits - 1) / splits) * kKPad;
+        const int64_t nsplit = (round_up(k, kKPad) + per - 1) / per;
+        if (nsplit > 1) most = std::max(most, (size_t)nsplit * (size_t)(m * n) * sizeof(float2));
+    }
+    return most;
 }
 
 bool smallk_shape(int64_t m, int64_t n, int64_t k) {

@@ -103,3 +103,41 @@ def test_slicing_reduces_intermediates():
     sl = tn.choose_slices(ls, p, ml - 3)
     ml2, fl2, _ = tn.path_cost(ls, p, frozenset(sl))
     assert ml2 <= ml - 3 and len(sl) >= 3
+
+
+def test_subtree_reconfigure_keeps_a_valid_cheaper_tree():
+    c = synth.grid_circuit(4, 5, 10, seed=3, pattern="ABCDCDAB")
+    ls = [l for _, l in tn.circuit_network(c, 0)]
+    L = len(ls)
+    for seed, noise in [(None, 0.0), (1, 0.3)]:
+        p = tn.greedy_path(ls, seed=seed, noise=noise)
+        q = tn.subtree_reconfigure(ls, p)
+        assert len(q) == L - 1
+        assert sorted(x for pair in q for x in pair) == list(range(2 * L - 2))
+        assert tn.tree_labels(ls, q)[-1] == frozenset()
+        ml, fl, _ = tn.path_cost(ls, p)
+        ml2, fl2, _ = tn.path_cost(ls, q)
+        assert (ml2, fl2) <= (ml, fl)
+
+
+def test_reconfigured_sliced_plan_numpy_matches_oracle():
+    c = synth.grid_circuit(3, 4, 8, seed=5, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=6, restarts=1, varied=2, reconfigure=True)
+    assert plan.max_log2 <= 6
+    x = 777
+    want = oracle.statevector_amplitudes(rounded(c), [x])[0]
+    assert abs(_numpy_execute(plan, x) - want) < 1e-12
+
+
+def test_autotune_table_rules():
+    # buckets of 128 x 128 tile counts take the faster tile; equal
+    # neighbours merge; the first rule starts at zero tiles
+    from paper_2303_08989_amd import autotune
+    rows = [dict(m=512, n=512, k=512, batch=1, ms_64=1.0, ms_128=2.0),      # 16 tiles -> 64
+            dict(m=1024, n=1024, k=512, batch=1, ms_64=3.0, ms_128=2.0),    # 64 tiles -> 128
+            dict(m=256, n=256, k=64, batch=16, ms_64=1.0, ms_128=1.5),      # 64 tiles (batched)
+            dict(m=4096, n=4096, k=64, batch=1, ms_64=5.0, ms_128=4.0)]     # 1024 tiles -> 128
+    rules, sums = autotune.table(rows)
+    assert rules[0] == (0, 0, 64)
+    assert rules[1][2] == 128 and rules[1][0] == 64
+    assert len(rules) == 2
