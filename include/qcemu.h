@@ -268,6 +268,54 @@ qce_status qce_cgemm_strided_batched(qce_handle *h, qce_op opA, qce_op opB, int6
                                      int64_t batch);
 
 /*
+ * One GEMM of a grouped call: C <- alpha op(A) op(B) + beta C with the
+ * arguments of qce_cgemm_emulated (A, B, C device pointers; alpha and beta
+ * by value).
+ */
+typedef struct {
+    qce_op opA, opB;
+    int64_t m, n, k;
+    qce_c32 alpha, beta;
+    const qce_c32 *A;
+    int64_t lda;
+    const qce_c32 *B;
+    int64_t ldb;
+    qce_c32 *C;
+    int64_t ldc;
+} qce_gemm_desc;
+
+/*
+ * Grouped CGEMM: `count` independent GEMMs of any shapes (descs: host array
+ * of count descriptors), computed in the handle's mode -- the batched
+ * variants of the cuBLAS-style CGEMM the paper's library replaces (Sec. 3),
+ * for the many uneven GEMMs of one step of a sliced network (Sec. 5.3).
+ *
+ * All entries of matrix-core shape run together, one launch per phase: one
+ * statistics launch (AUTO: every entry takes its own decision on the
+ * device, Sec. 4.1 / 4.2), one split launch for both operands of every
+ * entry, and one persistent GEMM launch whose workgroups take output tiles
+ * of all entries from a device work list (heaviest tiles first, spread over
+ * the XCDs), each tile running its own entry's mode, plus one launch adding
+ * the k-split partial tiles where an entry's k is split.  The tile shape
+ * (64 x 64 or 128 x 128) comes from the tuned table applied to the whole
+ * group's output (or qce_set_gemm_tile).  Irregular shapes (min(m, n) < 32
+ * or k < 16) and k == 0 run their own kernels as in qce_cgemm_emulated.
+ * Each entry's result equals that of qce_cgemm_emulated on the same
+ * arguments whenever both use the same tile and k splits (always when one
+ * entry fills the device or none splits k); otherwise only the order of
+ * its FP32 partial sums over k differs.
+ *
+ * Outputs must not overlap each other or any input.  The descriptors are
+ * read before the call returns.  qce_get_batch_decision(h, i) reports entry
+ * i (caller order; irregular shapes, k == 0 and empty outputs report FP32
+ * without statistics).
+ * Errors: INVALID_VALUE for count < 0 or > 65536, NULL descs with
+ * count > 0, or any entry failing qce_cgemm_emulated's checks (the message
+ * names it; nothing is enqueued); ALLOC / HIP.  count == 0: no-op success.
+ */
+qce_status qce_cgemm_grouped(qce_handle *h, int64_t count, const qce_gemm_desc *descs);
+
+/*
  * Synchronises, then copies the decision record of entry `index` of the
  * most recent GEMM call (index 0 for an unbatched call).  Valid until the
  * next call on the handle.  INVALID_VALUE for an index outside the batch.
@@ -312,14 +360,24 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
                         const qce_tensor *c, void *C, const int32_t *lc);
 
 /*
- * Grouped small contractions.  Between qce_group_begin and qce_group_end,
+ * Grouped contractions.  Between qce_group_begin and qce_group_end,
  * every qce_contract call whose GEMM the library would run with the
  * irregular-shape kernel (min(m, n) < 32 or k < 16 per batch entry) and that
  * is small (k <= 1024, at most 2^22 output elements, at most 2^24 products)
  * is recorded instead of launched; qce_group_end runs all recorded ones in
  * one launch (one thread per output element reading the operands through
  * their strides: no transposes; FP32 fused multiply-add, k in a fixed
- * order).  Other contractions in the group run at once as usual.  The
+ * order).  Contractions whose GEMM takes the panel path (matrix-core
+ * shapes other than the short-k kernel's, operands not read through a bit
+ * permutation, at most 65535 batch entries) are recorded too: qce_group_end
+ * runs their operand permutes, then all of them as one grouped GEMM
+ * (qce_cgemm_grouped's launches: one statistics, one split, one persistent
+ * GEMM launch; each entry in the mode the size policy gives it, AUTO
+ * entries selecting their own), then their output permutes.  Results equal
+ * those of the same contractions outside a group up to the order of FP32
+ * partial sums over k where the group splits k differently.  No decision
+ * record is kept for a group's GEMMs.  Other contractions in the group run
+ * at once as usual.  The
  * contractions of one group must be independent (none reads another's
  * output), the operands of a recorded contraction must stay allocated and
  * unchanged until qce_group_end has been enqueued (it reads them then), and

@@ -184,6 +184,25 @@ def cgemm_strided_batched(h, opA, opB, m, n, k, A, lda, strideA, B, ldb, strideB
     return C
 
 
+def cgemm_grouped(h, gemms):
+    """Independent column-major CGEMMs of any shapes in one grouped call
+    (C-ABI ``qce_cgemm_grouped``).  ``gemms``: sequence of dicts with keys
+    opA, opB, m, n, k, A, lda, B, ldb, C, ldc and optional alpha, beta
+    (A, B, C complex64 device tensors used for their data pointers)."""
+    hh = h._bind_stream()
+    arr = (_lib.QceGemmDesc * max(1, len(gemms)))()
+    for i, g in enumerate(gemms):
+        d = arr[i]
+        d.opA, d.opB = _lib.OPS[g.get("opA", "N")], _lib.OPS[g.get("opB", "N")]
+        d.m, d.n, d.k = int(g["m"]), int(g["n"]), int(g["k"])
+        d.alpha, d.beta = _c32(g.get("alpha", 1.0)), _c32(g.get("beta", 0.0))
+        d.A, d.lda = _ptr(g["A"]).value, int(g["lda"])
+        d.B, d.ldb = _ptr(g["B"]).value, int(g["ldb"])
+        d.C, d.ldc = _ptr(g["C"]).value, int(g["ldc"])
+    _check(hh, h.lib.qce_cgemm_grouped(hh, len(gemms), arr))
+    return [g["C"] for g in gemms]
+
+
 def matmul(h, A, B, out=None):
     """Row-major C = A @ B for 2-D complex64 device tensors.  A row-major
     (M, K) tensor is the column-major K x M matrix A^T, so C^T = B^T A^T is

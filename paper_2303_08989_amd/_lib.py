@@ -24,7 +24,8 @@ EXPORTS = (
     "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_get_size_policy", "qce_set_gemm_tile",
     "qce_set_workspace",
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
-    "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_get_batch_decision",
+    "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_cgemm_grouped",
+    "qce_get_batch_decision",
     "qce_contract", "qce_group_begin", "qce_group_end", "qce_group_reset", "qce_permute", "qce_accumulate_f64", "qce_accumulate_n_f64", "qce_fidelity_f64",
     "qce_expstats", "qce_split", "qce_panel_bytes", "qce_split_panels", "qce_split_panels_bitmap",
     "qce_status_string", "qce_last_error",
@@ -37,6 +38,15 @@ PHASES = ("stats", "split", "gemm_fp16x2", "gemm_bf16x3", "gemm_fp32", "gemm_ski
 
 class QceC32(ctypes.Structure):
     _fields_ = [("re", ctypes.c_float), ("im", ctypes.c_float)]
+
+
+class QceGemmDesc(ctypes.Structure):
+    _fields_ = [("opA", ctypes.c_int), ("opB", ctypes.c_int),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("alpha", QceC32), ("beta", QceC32),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
 
 
 class QceTensor(ctypes.Structure):
@@ -96,6 +106,7 @@ def load():
         "qce_cgemm_batched_workspace_size": (ctypes.c_size_t, [i64, i64, i64, i64]),
         "qce_cgemm_strided_batched": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64, i64,
                                            vp, i64, i64, c32p, vp, i64, i64, i64]),
+        "qce_cgemm_grouped": (st, [vp, i64, ctypes.POINTER(QceGemmDesc)]),
         "qce_get_batch_decision": (st, [vp, i64, ctypes.POINTER(QceDecision)]),
         "qce_contract": (st, [vp, tp, vp, i32p, tp, vp, i32p, tp, vp, i32p]),
         "qce_group_begin": (st, [vp]),

@@ -14,6 +14,40 @@
 
 using namespace qce;
 
+namespace {
+// A GEMM recorded for a grouped launch.  Operands as the panel writer reads
+// them (P[r][l] = kcontig ? x[l + r*ld] : x[r + l*ld], conjugated if conj),
+// each a caller pointer or, when ws >= 0, a byte offset into the group's
+// temporaries at the start of the workspace (a permuted copy).
+struct GroupOperand {
+    const float2 *ptr = nullptr;
+    int64_t ld = 1;
+    bool kcontig = false, conj = false;
+    int64_t ws = -1;
+};
+struct GroupItem {
+    int mode = QCE_MODE_AUTO;  // AUTO (statistics), FP16X2_SCALED (statistics) or a forced mode
+    GroupOperand a, b;
+    int64_t m = 0, n = 0, k = 0;
+    float2 alpha{1.f, 0.f}, beta{0.f, 0.f};
+    float2 *C = nullptr;  // or c_ws >= 0: a temporary
+    int64_t ldc = 1, c_ws = -1;
+    int count = 1;                  // batch entries
+    int64_t sa = 0, sb = 0, sc = 0;  // elements between entries
+    int64_t index = 0;              // first decision index (qce_cgemm_grouped: caller order)
+};
+// A permute run before (operands) or after (outputs) a group's GEMMs.
+struct GroupPermute {
+    const float2 *src = nullptr;
+    int64_t src_ws = -1;
+    float2 *dst = nullptr;
+    int64_t dst_ws = -1;
+    PermDesc d;
+    int64_t total = 0;
+    bool identity = false;
+};
+}  // namespace
+
 struct qce_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -63,6 +97,17 @@ struct qce_handle {
     char *grp_host = nullptr;  // its pinned host mirror (source of the copies)
     size_t grp_cap = 0, grp_used = 0;
     std::vector<std::pair<char *, char *>> grp_old;  // outgrown arenas, freed at destroy
+    // panel-path GEMMs of qce_contract recorded in the open group, their
+    // permutes and the bytes of their temporaries
+    std::vector<GroupItem> gitems;
+    std::vector<GroupPermute> gpre, gpost;
+    size_t gtemp = 0;
+    int64_t gentries = 0;            // batch entries of gitems (arrival counters)
+    unsigned int *gqueue = nullptr;  // device, kGroupQueueWords zeroed tile counters of the grouped GEMM
+    // decisions of the last grouped call in caller order: state index (>= 0)
+    // or -1 - index into dec_host (entries that took no statistics)
+    std::vector<int64_t> dec_map;
+    std::vector<qce_decision> dec_host;
 };
 
 namespace {
@@ -213,7 +258,9 @@ bool parse_i64(const char *s, int64_t *out) {
 // The decision records of a batched call live in the workspace: once it is
 // freed or replaced they are gone.
 void forget_batch_decisions(qce_handle *h) {
-    if (h->dec_base != h->st) {
+    if (h->dec_base != h->st || !h->dec_map.empty()) {
+        h->dec_map.clear();
+        h->dec_host.clear();
         h->dec_base = h->st;
         h->dec_count = 1;
         h->have_decision = false;
@@ -317,6 +364,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     const bool batched = bt.count > 1;
     h->dec_base = h->st;
     h->dec_count = bt.count;  // host-side records (forced / irregular / k == 0) hold for every entry
+    h->dec_map.clear();
+    h->dec_host.clear();
     if (k == 0) {
         hipEvent_t e0 = span_begin(h);
         QCE_HIP(h, launch_scale_c(C, m, n, ldc, beta, beta_zero, s, bt.count, bt.sc));
@@ -667,6 +716,237 @@ GatherMap gather_map_from_shifts(int nr, int nk, const int8_t *rsh, const int8_t
     return g;
 }
 
+// `need` bytes of the group descriptor arena: hp in its pinned host mirror
+// (filled by the caller, then copied to dp on the stream), dp on the device.
+// The arena is reused from its start only after the stream has drained it,
+// and never grown during stream capture.
+qce_status grp_reserve(qce_handle *h, size_t need, char *&hp, char *&dp) {
+    need = align256(need);
+    if (h->grp_used + need > h->grp_cap) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        QCE_HIP(h, hipStreamIsCapturing(h->stream, &cs));
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(h, QCE_ERR_ALLOC, "group descriptor space full during stream capture "
+                                          "(run the work once before capturing, then qce_group_reset)");
+        QCE_HIP(h, hipStreamSynchronize(h->stream));  // earlier copies and launches are done
+        if (need > h->grp_cap) {
+            if (h->grp_dev) h->grp_old.push_back({h->grp_dev, h->grp_host});
+            h->grp_dev = nullptr;
+            h->grp_host = nullptr;
+            const size_t cap = std::max<size_t>(size_t(1) << 20, 4 * need);
+            if (hipMalloc(&h->grp_dev, cap) != hipSuccess ||
+                hipHostMalloc(reinterpret_cast<void **>(&h->grp_host), cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                if (h->grp_dev) (void)hipFree(h->grp_dev);
+                h->grp_dev = nullptr;
+                h->grp_host = nullptr;
+                h->grp_cap = 0;
+                return fail(h, QCE_ERR_ALLOC, "group descriptor space of %zu bytes", cap);
+            }
+            h->grp_cap = cap;
+        }
+        h->grp_used = 0;
+    }
+    hp = h->grp_host + h->grp_used;
+    dp = h->grp_dev + h->grp_used;
+    h->grp_used += need;
+    return QCE_SUCCESS;
+}
+
+qce_status run_group_permute(qce_handle *h, const GroupPermute &p, char *ws) {
+    if (p.total == 0) return QCE_SUCCESS;
+    const float2 *src = p.src_ws >= 0 ? reinterpret_cast<const float2 *>(ws + p.src_ws) : p.src;
+    float2 *dst = p.dst_ws >= 0 ? reinterpret_cast<float2 *>(ws + p.dst_ws) : p.dst;
+    hipEvent_t e0 = span_begin(h);
+    if (p.identity)
+        QCE_HIP(h, hipMemcpyAsync(dst, src, (size_t)p.total * sizeof(float2), hipMemcpyDeviceToDevice, h->stream));
+    else
+        QCE_HIP(h, launch_permute(src, dst, p.total, p.d, h->stream));
+    span_end(h, e0, QCE_PHASE_PERMUTE);
+    return QCE_SUCCESS;
+}
+
+// The GEMMs of a group in one launch per phase: operand permutes, one
+// statistics launch (every entry that selects its mode), one split launch
+// (both operands of every entry), one persistent grouped GEMM launch (and
+// one split-k sum launch), output permutes.  Workspace: the temporaries
+// (temp_bytes, offsets used by the items and permutes) | decision states of
+// every entry that takes statistics | per item: panels of A, of B, partial
+// tiles, statistics records.  Items must be matrix-core shapes with k > 0.
+// first_state (optional) receives each item's first decision state index
+// (states at h->dec_base afterwards), -1 for items without statistics.
+qce_status run_group_gemms(qce_handle *h, std::vector<GroupItem> &items, const std::vector<GroupPermute> &pre,
+                           const std::vector<GroupPermute> &post, size_t temp_bytes,
+                           std::vector<int64_t> *first_state = nullptr) {
+    const int count = (int)items.size();
+    if (first_state) first_state->assign(items.size(), -1);
+    if (count == 0 && pre.empty() && post.empty()) return QCE_SUCCESS;
+    std::vector<GroupGemmEntry> ents(count);
+    int64_t n_states = 0;
+    for (int i = 0; i < count; ++i) {
+        const GroupItem &it = items[i];
+        if (it.m <= 0 || it.n <= 0 || it.k <= 0 || irregular_shape(it.m, it.n, it.k) || it.count < 1)
+            return fail(h, QCE_ERR_INTERNAL, "grouped GEMM entry of shape %lld x %lld x %lld", (long long)it.m,
+                        (long long)it.n, (long long)it.k);
+        GemmArgs &g = ents[i].g;
+        g = GemmArgs{};
+        g.m = it.m;
+        g.n = it.n;
+        g.k = it.k;
+        g.ldc = it.ldc;
+        g.alpha = it.alpha;
+        g.beta = it.beta;
+        g.beta_zero = it.beta.x == 0.f && it.beta.y == 0.f;
+        g.batch = it.count;
+        g.bsA = (int64_t)align256(panel_bytes(it.m, it.k));
+        g.bsB = (int64_t)align256(panel_bytes(it.n, it.k));
+        g.bsC = it.sc;
+        if (it.mode == QCE_MODE_AUTO || it.mode == QCE_MODE_FP16X2_SCALED) n_states += it.count;
+    }
+    if (n_states > kMaxBatch + 1)
+        return fail(h, QCE_ERR_NOT_SUPPORTED, "%lld grouped entries take statistics (at most %d)",
+                    (long long)n_states, kMaxBatch + 1);
+    const int tile = count ? gemm_group_tile(ents.data(), count, h->gemm_tile) : 128;
+    if (count) gemm_group_shape(ents.data(), count, tile);
+    struct Off {
+        size_t pa, pb, part, rec;
+        int64_t st;  // first state index, -1: no statistics
+    };
+    std::vector<Off> off(count);
+    size_t total = align256(temp_bytes);
+    const size_t states_off = total;
+    total += align256(sizeof(DevState) * (size_t)n_states);
+    int64_t si = 0;
+    for (int i = 0; i < count; ++i) {
+        const GroupItem &it = items[i];
+        const GemmArgs &g = ents[i].g;
+        Off &o = off[i];
+        const bool stats = it.mode == QCE_MODE_AUTO || it.mode == QCE_MODE_FP16X2_SCALED;
+        o.st = stats ? si : -1;
+        if (stats) si += it.count;
+        o.pa = total;
+        total += (size_t)g.bsA * (size_t)it.count;
+        o.pb = total;
+        total += (size_t)g.bsB * (size_t)it.count;
+        o.part = total;
+        if (ents[i].nsplit > 1) total += align256((size_t)g.bsPartial * sizeof(float2) * (size_t)it.count);
+        o.rec = total;
+        if (stats)
+            total += align256(sizeof(StatsRecord) *
+                              (size_t)(stats_blocks_bound(it.m, it.k) + stats_blocks_bound(it.k, it.n)) *
+                              (size_t)it.count);
+    }
+    DeviceGuard dg(h->device);
+    qce_status rs = ensure_ws(h, total);
+    if (rs != QCE_SUCCESS) return rs;
+    char *ws = static_cast<char *>(h->ws);
+    DevState *states = reinterpret_cast<DevState *>(ws + states_off);
+    auto resolve = [&](const GroupOperand &v) {
+        return v.ws >= 0 ? reinterpret_cast<const float2 *>(ws + v.ws) : v.ptr;
+    };
+    std::vector<GroupStatsEntry> sents;
+    std::vector<SplitJob> jobs;
+    int64_t stat_blocks = 0, split_blocks = 0;
+    for (int i = 0; i < count; ++i) {
+        const GroupItem &it = items[i];
+        GemmArgs &g = ents[i].g;
+        const Off &o = off[i];
+        const float2 *pa = resolve(it.a), *pb = resolve(it.b);
+        g.panelsA = ws + o.pa;
+        g.panelsB = ws + o.pb;
+        g.C = it.c_ws >= 0 ? reinterpret_cast<float2 *>(ws + it.c_ws) : it.C;
+        g.partial = ents[i].nsplit > 1 ? reinterpret_cast<float2 *>(ws + o.part) : nullptr;
+        DevState *dst = o.st >= 0 ? states + o.st : nullptr;
+        g.st = dst;
+        g.forced_mode = dst ? -1 : it.mode;
+        if (dst) {
+            MatDesc da = it.a.kcontig ? MatDesc{pa, it.k, it.m, it.a.ld, it.sa} : MatDesc{pa, it.m, it.k, it.a.ld, it.sa};
+            MatDesc db = it.b.kcontig ? MatDesc{pb, it.k, it.n, it.b.ld, it.sb} : MatDesc{pb, it.n, it.k, it.b.ld, it.sb};
+            GroupStatsEntry se;
+            if (stats_group_entry(da, db, dst, reinterpret_cast<StatsRecord *>(ws + o.rec), h->arrived + o.st, h->t,
+                                  h->t3, it.mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, it.count,
+                                  se) != hipSuccess)
+                return fail(h, QCE_ERR_NOT_SUPPORTED, "statistics of a %lld x %lld x %lld grouped entry",
+                            (long long)it.m, (long long)it.n, (long long)it.k);
+            se.block_start = stat_blocks;
+            stat_blocks += (int64_t)(se.args.blocks_a + se.args.blocks_b) * se.batch;
+            sents.push_back(se);
+        }
+        for (int w = 0; w < 2; ++w) {
+            const GroupOperand &v = w ? it.b : it.a;
+            SplitJob j{};
+            j.x = w ? pb : pa;
+            j.ldx = v.ld;
+            j.kcontig = v.kcontig;
+            j.conj = v.conj;
+            j.rows = w ? it.n : it.m;
+            j.k = it.k;
+            j.panels = ws + (w ? o.pb : o.pa);
+            j.st = dst;
+            j.which = w;
+            j.forced_mode = it.mode;
+            j.shift = 0;
+            j.batch = it.count;
+            j.xstride = w ? it.sb : it.sa;
+            j.pstride = w ? g.bsB : g.bsA;
+            j.blocks = split_job_blocks(j.rows, j.k, j.kcontig);
+            j.block_start = split_blocks;
+            split_blocks += j.blocks * j.batch;
+            jobs.push_back(j);
+        }
+    }
+    int64_t total_tiles = 0, total_red = 0;
+    if (count) gemm_group_schedule(ents.data(), count, total_tiles, total_red);
+    // descriptors: statistics entries | split jobs | GEMM entries
+    const size_t b0 = align256(sizeof(GroupStatsEntry) * sents.size());
+    const size_t b1 = align256(sizeof(SplitJob) * jobs.size());
+    const size_t b2 = align256(sizeof(GroupGemmEntry) * ents.size());
+    char *hp = nullptr, *dp = nullptr;
+    if (count) {
+        rs = grp_reserve(h, b0 + b1 + b2, hp, dp);
+        if (rs != QCE_SUCCESS) return rs;
+        if (!sents.empty()) memcpy(hp, sents.data(), sizeof(GroupStatsEntry) * sents.size());
+        memcpy(hp + b0, jobs.data(), sizeof(SplitJob) * jobs.size());
+        memcpy(hp + b0 + b1, ents.data(), sizeof(GroupGemmEntry) * ents.size());
+        QCE_HIP(h, hipMemcpyAsync(dp, hp, b0 + b1 + b2, hipMemcpyHostToDevice, h->stream));
+    }
+    for (const GroupPermute &p : pre) {
+        rs = run_group_permute(h, p, ws);
+        if (rs != QCE_SUCCESS) return rs;
+    }
+    if (count) {
+        if (!sents.empty()) {
+            hipEvent_t e0 = span_begin(h);
+            QCE_HIP(h, launch_stats_grouped(reinterpret_cast<const GroupStatsEntry *>(dp), (int)sents.size(),
+                                            stat_blocks, h->stream));
+            span_end(h, e0, QCE_PHASE_STATS);
+        }
+        hipEvent_t e1 = span_begin(h);
+        QCE_HIP(h, launch_split_grouped(reinterpret_cast<const SplitJob *>(dp + b0), (int)jobs.size(), split_blocks,
+                                        h->stream));
+        span_end(h, e1, QCE_PHASE_SPLIT);
+        hipEvent_t e2 = span_begin(h);
+        QCE_HIP(h, launch_gemm_grouped(reinterpret_cast<const GroupGemmEntry *>(dp + b0 + b1), count, total_tiles,
+                                       total_red, tile, h->gqueue, h->stream));
+        span_end(h, e2, QCE_PHASE_GEMM_BATCHED);
+    }
+    for (const GroupPermute &p : post) {
+        rs = run_group_permute(h, p, ws);
+        if (rs != QCE_SUCCESS) return rs;
+    }
+    // the group's decision states (forget_batch_decisions resets them when
+    // the workspace changes)
+    h->dec_base = states;
+    h->dec_map.clear();
+    h->dec_host.clear();
+    h->dec_count = 1;
+    h->have_decision = false;
+    h->last_on_device = false;
+    if (first_state)
+        for (int i = 0; i < count; ++i) (*first_state)[i] = off[i].st;
+    return QCE_SUCCESS;
+}
+
 bool checked_numel(int rank, const int64_t *ext, int64_t &n) {
     n = 1;
     for (int a = 0; a < rank; ++a) {
@@ -736,17 +1016,20 @@ qce_status qce_create(qce_handle **out, int device) {
         if (h->arrived) (void)hipFree(h->arrived);
         if (h->fid_partials) (void)hipFree(h->fid_partials);
         if (h->mode_log) (void)hipFree(h->mode_log);
+        if (h->gqueue) (void)hipFree(h->gqueue);
         delete h;
     };
     if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
         hipMalloc(&h->arrived, arrived_bytes) != hipSuccess ||
         hipMalloc(&h->fid_partials, sizeof(double) * 4 * kFidBlocks) != hipSuccess ||
-        hipMalloc(&h->mode_log, sizeof(int) * kLogCap) != hipSuccess) {
+        hipMalloc(&h->mode_log, sizeof(int) * kLogCap) != hipSuccess ||
+        hipMalloc(&h->gqueue, sizeof(unsigned int) * kGroupQueueWords) != hipSuccess) {
         (void)hipGetLastError();
         release();
         return QCE_ERR_ALLOC;
     }
     if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess || hipMemset(h->arrived, 0, arrived_bytes) != hipSuccess ||
+        hipMemset(h->gqueue, 0, sizeof(unsigned int) * kGroupQueueWords) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         release();
         return QCE_ERR_HIP;
@@ -771,6 +1054,7 @@ qce_status qce_destroy(qce_handle *h) {
     (void)hipFree(h->arrived);
     (void)hipFree(h->fid_partials);
     (void)hipFree(h->mode_log);
+    (void)hipFree(h->gqueue);
     if (h->grp_dev) (void)hipFree(h->grp_dev);
     if (h->grp_host) (void)hipHostFree(h->grp_host);
     for (auto &pr : h->grp_old) {
@@ -934,9 +1218,94 @@ qce_status qce_cgemm_strided_batched(qce_handle *h, qce_op opA, qce_op opB, int6
                       static_cast<char *>(h->ws), bt);
 }
 
+qce_status qce_cgemm_grouped(qce_handle *h, int64_t count, const qce_gemm_desc *descs) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    if (count < 0 || count > kMaxBatch + 1)
+        return fail(h, QCE_ERR_INVALID_VALUE, "group of %lld GEMMs (0..%d)", (long long)count, kMaxBatch + 1);
+    if (count == 0) return QCE_SUCCESS;
+    if (!descs) return fail(h, QCE_ERR_INVALID_VALUE, "null descriptor array");
+    std::vector<char> noop((size_t)count, 0);
+    for (int64_t i = 0; i < count; ++i) {
+        const qce_gemm_desc &d = descs[i];
+        bool nop = false;
+        qce_status st = cgemm_check(h, d.opA, d.opB, d.m, d.n, d.k, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, &nop);
+        if (st != QCE_SUCCESS) {
+            char msg[sizeof(h->err)];
+            snprintf(msg, sizeof(msg), "%s", h->err);
+            return fail(h, st, "entry %lld: %s", (long long)i, msg);
+        }
+        noop[(size_t)i] = nop;
+    }
+    DeviceGuard g(h->device);
+    std::vector<GroupItem> items;
+    std::vector<int64_t> direct;  // irregular shapes and k == 0: their own kernels
+    for (int64_t i = 0; i < count; ++i) {
+        if (noop[(size_t)i]) continue;
+        const qce_gemm_desc &d = descs[i];
+        if (d.k == 0 || irregular_shape(d.m, d.n, d.k)) {
+            direct.push_back(i);
+            continue;
+        }
+        GroupItem it;
+        it.mode = h->mode;
+        it.a = GroupOperand{reinterpret_cast<const float2 *>(d.A), d.lda, d.opA != QCE_OP_N, d.opA == QCE_OP_C, -1};
+        it.b = GroupOperand{reinterpret_cast<const float2 *>(d.B), d.ldb, d.opB == QCE_OP_N, d.opB == QCE_OP_C, -1};
+        it.m = d.m;
+        it.n = d.n;
+        it.k = d.k;
+        it.alpha = make_float2(d.alpha.re, d.alpha.im);
+        it.beta = make_float2(d.beta.re, d.beta.im);
+        it.C = reinterpret_cast<float2 *>(d.C);
+        it.ldc = d.ldc;
+        it.index = i;
+        items.push_back(it);
+    }
+    // the workspace use of these ends before the group's, in stream order
+    for (int64_t i : direct) {
+        const qce_gemm_desc &d = descs[i];
+        qce_status st = ensure_ws(h, cgemm_ws_bytes(d.m, d.n, d.k));
+        if (st != QCE_SUCCESS) return st;
+        OperandView va{reinterpret_cast<const float2 *>(d.A), d.lda, d.opA != QCE_OP_N, d.opA == QCE_OP_C};
+        OperandView vb{reinterpret_cast<const float2 *>(d.B), d.ldb, d.opB == QCE_OP_N, d.opB == QCE_OP_C};
+        st = cgemm_core(h, h->mode, va, vb, d.m, d.n, d.k, make_float2(d.alpha.re, d.alpha.im),
+                        make_float2(d.beta.re, d.beta.im), reinterpret_cast<float2 *>(d.C), d.ldc,
+                        static_cast<char *>(h->ws));
+        if (st != QCE_SUCCESS) return st;
+    }
+    std::vector<int64_t> first;
+    qce_status st = run_group_gemms(h, items, {}, {}, 0, &first);
+    if (st != QCE_SUCCESS) return st;
+    // decision records in the caller's order
+    if (items.empty()) h->dec_base = h->st;
+    h->dec_map.assign((size_t)count, 0);
+    h->dec_host.clear();
+    qce_decision hostrec{};
+    hostrec.mode = QCE_MODE_FP32;  // irregular shapes, k == 0, empty outputs: FP32, no statistics
+    for (int o = 0; o < 2; ++o) {
+        hostrec.n2[o] = -1;
+        hostrec.emax[o] = INT32_MIN;
+    }
+    for (int64_t i = 0; i < count; ++i) {
+        h->dec_host.push_back(hostrec);
+        h->dec_map[(size_t)i] = -(int64_t)h->dec_host.size();
+    }
+    for (size_t j = 0; j < items.size(); ++j) {
+        if (first[j] >= 0) {
+            h->dec_map[(size_t)items[j].index] = first[j];
+        } else {
+            h->dec_host[(size_t)items[j].index].mode = items[j].mode;
+        }
+    }
+    h->dec_count = (int)count;
+    h->have_decision = true;
+    h->last_on_device = false;
+    return QCE_SUCCESS;
+}
+
 qce_status qce_get_last_decision(qce_handle *h, qce_decision *out) {
     if (!h || !out) return QCE_ERR_INVALID_VALUE;
     if (!h->have_decision) return fail(h, QCE_ERR_INVALID_VALUE, "no GEMM has run on this handle");
+    if (!h->dec_map.empty()) return qce_get_batch_decision(h, (int64_t)h->dec_map.size() - 1, out);
     DeviceGuard g(h->device);
     QCE_HIP(h, hipStreamSynchronize(h->stream));
     if (h->last_on_device) {
@@ -954,6 +1323,14 @@ qce_status qce_get_batch_decision(qce_handle *h, int64_t index, qce_decision *ou
         return fail(h, QCE_ERR_INVALID_VALUE, "entry %lld of a batch of %d", (long long)index, h->dec_count);
     DeviceGuard g(h->device);
     QCE_HIP(h, hipStreamSynchronize(h->stream));
+    if (!h->dec_map.empty()) {
+        const int64_t w = h->dec_map[(size_t)index];
+        if (w >= 0)
+            QCE_HIP(h, hipMemcpy(out, &h->dec_base[w].last, sizeof(qce_decision), hipMemcpyDeviceToHost));
+        else
+            *out = h->dec_host[(size_t)(-1 - w)];
+        return QCE_SUCCESS;
+    }
     if (h->last_on_device) {
         QCE_HIP(h, hipMemcpy(out, &h->dec_base[index].last, sizeof(qce_decision), hipMemcpyDeviceToHost));
     } else {
@@ -1376,6 +1753,8 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
                 if (st != QCE_SUCCESS) return st;
                 h->dec_base = h->st;
                 h->dec_count = 1;
+                h->dec_map.clear();
+                h->dec_host.clear();
                 hipEvent_t e0 = span_begin(h);
                 QCE_HIP(h, launch_permuted_dot(static_cast<const float2 *>(px ? X : Y),
                                                static_cast<const float2 *>(px ? Y : X), d,
@@ -1393,6 +1772,83 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
                 return QCE_SUCCESS;
             }
         }
+    }
+
+    int mode = h->mode;
+    if (mode == QCE_MODE_AUTO) mode = policy_mode(h, m, n, kk);
+    // Inside a group, a GEMM of the panel path is recorded too: it runs at
+    // qce_group_end with the group's other such GEMMs, one launch per phase
+    // (its permutes run there as well, into temporaries of the group).
+    const bool takes_stats = mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED;
+    if (h->grouping && !gx && !gy && kk > 0 && m > 0 && n > 0 && !irregular_shape(m, n, kk) &&
+        !(h->smallk && smallk_shape(m, n, kk)) && count >= 1 && count <= kMaxBatch &&
+        (!takes_stats || h->gentries + count <= kMaxBatch + 1)) {
+        GroupItem it;
+        it.mode = mode;
+        std::vector<GroupPermute> pre;
+        size_t temp = h->gtemp;  // end of the group's temporaries
+        auto operand = [&](int lay, const int32_t *l, int r, const int64_t *e, const void *src, int64_t rows,
+                           const std::vector<int32_t> &forder, GroupOperand &v) -> qce_status {
+            if (lay == 0) {  // [K][F]: column-major rows x k
+                v = GroupOperand{static_cast<const float2 *>(src), std::max<int64_t>(1, rows), false, false, -1};
+                return QCE_SUCCESS;
+            }
+            if (lay == 1) {  // [F][K]: column-major k x rows
+                v = GroupOperand{static_cast<const float2 *>(src), std::max<int64_t>(1, kk), true, false, -1};
+                return QCE_SUCCESS;
+            }
+            // permuted to [BO][K][F] in a temporary first
+            std::vector<int32_t> perm;
+            for (int32_t lab : BO) perm.push_back(find(l, r, lab));
+            for (int32_t lab : korder) perm.push_back(find(l, r, lab));
+            for (int32_t lab : forder) perm.push_back(find(l, r, lab));
+            GroupPermute p;
+            qce_status ps = plan_permute(h, r, e, perm.data(), p.d, p.total, p.identity);
+            if (ps != QCE_SUCCESS) return ps;
+            p.src = static_cast<const float2 *>(src);
+            p.dst_ws = (int64_t)temp;
+            temp += align256((size_t)p.total * sizeof(float2));
+            v = GroupOperand{nullptr, std::max<int64_t>(1, rows), false, false, p.dst_ws};
+            pre.push_back(p);
+            return QCE_SUCCESS;
+        };
+        qce_status ps = operand(lay_x, lx, rx, ex, X, m, SA, it.a);
+        if (ps == QCE_SUCCESS) ps = operand(lay_y, ly, ry, ey, Y, n, SB, it.b);
+        if (ps != QCE_SUCCESS) return ps;
+        GroupPermute post;
+        if (out_perm) {
+            // the GEMM writes [BO][SB][SA] (row-major) into a temporary, then
+            // the permute to lc
+            std::vector<int32_t> tl(BO);
+            tl.insert(tl.end(), SB.begin(), SB.end());
+            tl.insert(tl.end(), SA.begin(), SA.end());
+            std::vector<int64_t> te;
+            for (int32_t lab : tl) te.push_back(ext_of(lab));
+            std::vector<int32_t> perm;
+            for (int i = 0; i < rc; ++i) perm.push_back(find(tl.data(), rc, lc[i]));
+            ps = plan_permute(h, rc, te.data(), perm.data(), post.d, post.total, post.identity);
+            if (ps != QCE_SUCCESS) return ps;
+            it.c_ws = (int64_t)temp;
+            post.src_ws = it.c_ws;
+            post.dst = static_cast<float2 *>(C);
+            temp += align256((size_t)nc * 8);
+        } else {
+            it.C = static_cast<float2 *>(C);
+        }
+        it.m = m;
+        it.n = n;
+        it.k = kk;
+        it.ldc = std::max<int64_t>(1, m);
+        it.count = (int)count;
+        it.sa = kk * m;
+        it.sb = kk * n;
+        it.sc = m * n;
+        h->gitems.push_back(it);
+        for (const GroupPermute &q : pre) h->gpre.push_back(q);
+        if (out_perm) h->gpost.push_back(post);
+        h->gtemp = temp;
+        if (takes_stats) h->gentries += count;
+        return QCE_SUCCESS;
     }
 
     // workspace: panels | permuted X | permuted Y | temporary C
@@ -1441,8 +1897,6 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     } else {  // [F][K]: P[j][l] = y[l + j*k]
         vy = OperandView{static_cast<const float2 *>(Y), std::max<int64_t>(1, kk), true, false};
     }
-    int mode = h->mode;
-    if (mode == QCE_MODE_AUTO) mode = policy_mode(h, m, n, kk);
     float2 *Cg = out_perm ? reinterpret_cast<float2 *>(ws + offc) : static_cast<float2 *>(C);
     // batch entries in launches of at most kMaxBatch
     for (int64_t z0 = 0; z0 < std::max<int64_t>(count, 1); z0 += chunk) {
@@ -1478,6 +1932,11 @@ qce_status qce_group_begin(qce_handle *h) {
     if (h->grouping) return fail(h, QCE_ERR_INVALID_VALUE, "a group is already open");
     h->grouping = true;
     h->pending.clear();
+    h->gitems.clear();
+    h->gpre.clear();
+    h->gpost.clear();
+    h->gtemp = 0;
+    h->gentries = 0;
     return QCE_SUCCESS;
 }
 
@@ -1485,46 +1944,37 @@ qce_status qce_group_end(qce_handle *h) {
     if (!h) return QCE_ERR_INVALID_VALUE;
     if (!h->grouping) return fail(h, QCE_ERR_INVALID_VALUE, "no group is open");
     h->grouping = false;
+    DeviceGuard g(h->device);
+    // the recorded panel-path GEMMs (grouped launches)
+    if (!h->gitems.empty()) {
+        std::vector<GroupItem> items;
+        std::vector<GroupPermute> pre, post;
+        items.swap(h->gitems);
+        pre.swap(h->gpre);
+        post.swap(h->gpost);
+        const size_t temp = h->gtemp;
+        h->gtemp = 0;
+        h->gentries = 0;
+        qce_status gs = run_group_gemms(h, items, pre, post, temp);
+        if (gs != QCE_SUCCESS) {
+            h->pending.clear();
+            return gs;
+        }
+    }
     const int count = (int)h->pending.size();
     if (count == 0) return QCE_SUCCESS;
-    DeviceGuard g(h->device);
     std::vector<int64_t> starts(count + 1, 0);
     for (int i = 0; i < count; ++i) starts[i + 1] = starts[i] + (h->pending[i].n_out + 255) / 256;
     const size_t bi = align256(sizeof(SmallItem) * (size_t)count);
     const size_t need = bi + align256(sizeof(int64_t) * (size_t)(count + 1));
-    if (h->grp_used + need > h->grp_cap) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        QCE_HIP(h, hipStreamIsCapturing(h->stream, &cs));
-        if (cs != hipStreamCaptureStatusNone) {
-            h->pending.clear();
-            return fail(h, QCE_ERR_ALLOC, "group descriptor space full during stream capture "
-                                          "(run the work once before capturing, then qce_group_reset)");
-        }
-        QCE_HIP(h, hipStreamSynchronize(h->stream));  // earlier copies and launches are done
-        if (need > h->grp_cap) {
-            if (h->grp_dev) h->grp_old.push_back({h->grp_dev, h->grp_host});
-            h->grp_dev = nullptr;
-            h->grp_host = nullptr;
-            const size_t cap = std::max<size_t>(size_t(1) << 20, 4 * need);
-            if (hipMalloc(&h->grp_dev, cap) != hipSuccess ||
-                hipHostMalloc(reinterpret_cast<void **>(&h->grp_host), cap, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                if (h->grp_dev) (void)hipFree(h->grp_dev);
-                h->grp_dev = nullptr;
-                h->grp_host = nullptr;
-                h->grp_cap = 0;
-                h->pending.clear();
-                return fail(h, QCE_ERR_ALLOC, "group descriptor space of %zu bytes", cap);
-            }
-            h->grp_cap = cap;
-        }
-        h->grp_used = 0;
+    char *hp = nullptr, *dp = nullptr;
+    qce_status rs = grp_reserve(h, need, hp, dp);
+    if (rs != QCE_SUCCESS) {
+        h->pending.clear();
+        return rs;
     }
-    char *hp = h->grp_host + h->grp_used;
-    char *dp = h->grp_dev + h->grp_used;
     memcpy(hp, h->pending.data(), sizeof(SmallItem) * (size_t)count);
     memcpy(hp + bi, starts.data(), sizeof(int64_t) * (size_t)(count + 1));
-    h->grp_used += need;
     h->pending.clear();
     hipEvent_t e0 = span_begin(h);
     QCE_HIP(h, hipMemcpyAsync(dp, hp, need, hipMemcpyHostToDevice, h->stream));

@@ -127,6 +127,30 @@ constexpr int kMaxBatch = 65535;
 // -1 = the rule; >= 0 = that mode (statistics taken for its shifts and the
 // record).  mode_log (nullable) receives entry 0's mode at slot.  Batched:
 // entry z reads a / b shifted by z * bstride and writes st + z.
+struct StatsArgs {
+    MatDesc a, b;
+    int blocks_a, blocks_b;
+    DevState *st;           // entry z: st + z
+    StatsRecord *rec;       // entry z: rec + z * (blocks_a + blocks_b)
+    unsigned int *arrived;  // entry z: arrived[z] (zero between calls)
+    double t, t3;
+    int forced;             // -1: rule; >= 0: that mode (statistics for its shifts)
+    int *mode_log;          // nullable: mode of entry 0 at mode_log[slot]
+    int slot;
+};
+// One GEMM (or batch) of a grouped statistics launch: its blocks are
+// [block_start, block_start + (blocks_a + blocks_b) * batch) of the grid.
+struct GroupStatsEntry {
+    StatsArgs args;
+    int batch, pad;
+    int64_t block_start;
+};
+// fills `out` for launch_stats's arguments (block_start left 0)
+hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
+                             unsigned int *arrived, double t, double t3, int forced_mode, int batch,
+                             GroupStatsEntry &out);
+hipError_t launch_stats_grouped(const GroupStatsEntry *dev_entries, int count, int64_t total_blocks,
+                                hipStream_t s);
 int stats_blocks(const MatDesc &d);
 // upper bound of stats_blocks over every leading dimension of a rows x cols
 // operand stored either way (rows x cols or cols x rows)
@@ -146,6 +170,24 @@ hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int co
                                int64_t k, void *panels, const DevState *st, int which,
                                int forced_mode, int shift, hipStream_t s, int batch = 1,
                                int64_t xstride = 0, int64_t pstride = 0);
+
+// One operand of a grouped split launch (split.hip): the arguments of
+// launch_split_panels for a rows-contiguous or k-contiguous operand, with
+// its blocks [block_start, block_start + blocks * batch) of the grid.
+struct SplitJob {
+    const float2 *x;
+    int64_t ldx;
+    int kcontig, conj;
+    int64_t rows, k;
+    char *panels;
+    const DevState *st;  // nullable: forced_mode / shift
+    int which, forced_mode, shift, batch;
+    int64_t xstride, pstride;  // elements / panel bytes between batch entries
+    int64_t blocks;            // per batch entry: split_job_blocks
+    int64_t block_start;
+};
+int64_t split_job_blocks(int64_t rows, int64_t k, int kcontig);
+hipError_t launch_split_grouped(const SplitJob *dev_jobs, int count, int64_t total_blocks, hipStream_t s);
 
 struct GemmArgs {
     const void *panelsA;  // rows = m
@@ -170,6 +212,32 @@ hipError_t launch_gemm(const GemmArgs &g, int which_kernel, hipStream_t s);
 size_t gemm_partial_bytes(int64_t m, int64_t n, int64_t k, int batch = 1);  // per entry, either tile
 // tile of the panel GEMM for this output size (the tuned table)
 int gemm_tile(int64_t m, int64_t n, int64_t k, int batch = 1);
+
+// One entry of a grouped GEMM launch (gemm.hip): a GEMM (or a batch of
+// equally shaped ones, g.batch) over its own split panels, with its own
+// shape, alpha / beta, mode source (g.st per batch entry, or
+// g.forced_mode) and k splits.  The host fills g (partial set once the
+// split count is known); gemm_group_shape and gemm_group_schedule fill the
+// rest.
+struct GroupGemmEntry {
+    GemmArgs g;
+    int nbm, nbn, nsplit, pad;
+    int64_t tiles;       // nbm * nbn * nsplit * batch
+    int64_t tile_start;  // first tile id in the launch (a multiple of 8)
+    int64_t red_start, red_blocks;  // blocks of the split-k sum (0 if nsplit == 1)
+};
+// tile of a grouped launch (64 or 128): forced_tile if 64 or 128, else the
+// tuned table applied to the whole launch's output
+int gemm_group_tile(const GroupGemmEntry *e, int count, int forced_tile);
+// per-entry tile grid, k splits (counting every entry's tiles), partial
+// sizes (g.bsPartial elements per batch entry) and reduction blocks
+void gemm_group_shape(GroupGemmEntry *e, int count, int tile);
+// orders the entries by tile cost (heaviest first) and assigns the starts
+void gemm_group_schedule(GroupGemmEntry *e, int count, int64_t &total_tiles, int64_t &total_red);
+// queue: kGroupQueueWords zeroed device counters (left zeroed)
+constexpr int kGroupQueueWords = 9;
+hipError_t launch_gemm_grouped(const GroupGemmEntry *dev_entries, int count, int64_t total_tiles,
+                               int64_t total_red, int tile, unsigned int *queue, hipStream_t s);
 
 // Short-k, narrow-output GEMM with the split done on load (gemm.hip):
 // C (m x n, n <= 64) = alpha op(A) op(B) + beta C for k <= 128, reading the

@@ -329,9 +329,12 @@ static_assert(kSmemBytes <= 160 * 1024, "gfx950 LDS");
 // chunk).  blockIdx.y selects a range of k (split-k): with several ranges
 // the unscaled partial tile goes to g.partial and gemm_reduce_kernel
 // finishes the sum and the epilogue.
+// bid: the tile's index (mapped to a tile by tile_of), ks: its k range,
+// split: the k range is one of several (the partial tile is written).
 template <int MODE, int TILE>
 __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &g, int nbm, int nbn,
-                                                                int mode, char *smem_raw) {
+                                                                int mode, char *smem_raw, int bid, int ks,
+                                                                bool split) {
     int shift_total = 0;
     if (MODE == QCE_MODE_FP16X2 && mode == QCE_MODE_FP16X2_SCALED && g.st)
         shift_total = g.st->shift[0] + g.st->shift[1];
@@ -350,11 +353,11 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
     Stage *smem = reinterpret_cast<Stage *>(smem_raw);
 
     int mb, nb;
-    tile_of(blockIdx.x, nbm, nbn, mb, nb);
+    tile_of(bid, nbm, nbn, mb, nb);
     const int64_t kpad = round_up(g.k, kKPad);
     const int nkb = (int)(kpad / PanelFmt<MODE>::kBK);
     // this split's chunk range (split boundaries are multiples of the chunk depth)
-    const int kb0 = (int)((int64_t)blockIdx.y * g.kpad_per_split / PanelFmt<MODE>::kBK);
+    const int kb0 = (int)((int64_t)ks * g.kpad_per_split / PanelFmt<MODE>::kBK);
     const int kb1 = min(nkb, kb0 + (int)(g.kpad_per_split / PanelFmt<MODE>::kBK));
     const int nk = max(0, kb1 - kb0);
     // panel row block of the tile and, for 64-row tiles, its half
@@ -530,7 +533,6 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
     }
 
     // epilogue: D[j][i] -> C[i][j] (or the split's partial tile)
-    const bool split = gridDim.y > 1;
     const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
     const int l32 = lane & 31, hi = lane >> 5;
 #pragma unroll
@@ -554,7 +556,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
                     im = acc.im_m[ub][vb][r];
                 }
                 if (split) {
-                    g.partial[(int64_t)blockIdx.y * g.m * g.n + i + j * g.m] = make_float2(re, im);
+                    g.partial[(int64_t)ks * g.m * g.n + i + j * g.m] = make_float2(re, im);
                     continue;
                 }
                 if (shift_total) {
@@ -580,8 +582,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs &
 
 // Batched launches: entry blockIdx.z works on its own panels, C, partial
 // tiles and device state.
-__device__ inline void select_entry(GemmArgs &g) {
-    const int64_t z = blockIdx.z;
+__device__ inline void select_entry(GemmArgs &g, int64_t z) {
     g.panelsA = static_cast<const char *>(g.panelsA) + z * g.bsA;
     g.panelsB = static_cast<const char *>(g.panelsB) + z * g.bsB;
     g.C += z * g.bsC;
@@ -595,8 +596,8 @@ __device__ inline void select_entry(GemmArgs &g) {
 template <int MODE, int TILE>
 __global__ __launch_bounds__(kThreads, TILE == 128 ? 1 : 2) void gemm_kernel(GemmArgs g, int nbm, int nbn) {
     __shared__ __attribute__((aligned(16))) char smem[smem_bytes<MODE>() * TILE / kPanelRows];
-    select_entry(g);
-    gemm_body<MODE, TILE>(g, nbm, nbn, g.forced_mode, smem);
+    select_entry(g, blockIdx.z);
+    gemm_body<MODE, TILE>(g, nbm, nbn, g.forced_mode, smem, blockIdx.x, blockIdx.y, gridDim.y > 1);
 }
 
 // Statistics-selected mode: one launch that reads the device mode flag and
@@ -604,21 +605,22 @@ __global__ __launch_bounds__(kThreads, TILE == 128 ? 1 : 2) void gemm_kernel(Gem
 template <int TILE>
 __global__ __launch_bounds__(kThreads, TILE == 128 ? 1 : 2) void gemm_auto_kernel(GemmArgs g, int nbm, int nbn) {
     __shared__ __attribute__((aligned(16))) char smem[kSmemBytes * TILE / kPanelRows];
-    select_entry(g);
+    select_entry(g, blockIdx.z);
     const int mode = g.st->mode;
+    const int bid = blockIdx.x, ks = blockIdx.y;
+    const bool split = gridDim.y > 1;
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
-        gemm_body<QCE_MODE_FP16X2, TILE>(g, nbm, nbn, mode, smem);
+        gemm_body<QCE_MODE_FP16X2, TILE>(g, nbm, nbn, mode, smem, bid, ks, split);
     else if (mode == QCE_MODE_BF16X3)
-        gemm_body<QCE_MODE_BF16X3, TILE>(g, nbm, nbn, mode, smem);
+        gemm_body<QCE_MODE_BF16X3, TILE>(g, nbm, nbn, mode, smem, bid, ks, split);
     else
-        gemm_body<QCE_MODE_FP32, TILE>(g, nbm, nbn, mode, smem);
+        gemm_body<QCE_MODE_FP32, TILE>(g, nbm, nbn, mode, smem, bid, ks, split);
 }
 
-// Split-k: add the partial tiles in split order, then shift / alpha / beta.
-__global__ __launch_bounds__(kThreads) void gemm_reduce_kernel(GemmArgs g, int splits) {
-    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (o >= g.m * g.n) return;
-    select_entry(g);
+// Split-k: add the partial tiles in split order, then shift / alpha / beta
+// (output element o of batch entry z).
+__device__ inline void reduce_one(GemmArgs g, int splits, int64_t o, int64_t z) {
+    select_entry(g, z);
     const int mode = g.st ? g.st->mode : g.forced_mode;
     const int shift_total = (mode == QCE_MODE_FP16X2_SCALED && g.st) ? g.st->shift[0] + g.st->shift[1] : 0;
     float re = 0.f, im = 0.f;
@@ -641,6 +643,88 @@ __global__ __launch_bounds__(kThreads) void gemm_reduce_kernel(GemmArgs g, int s
         out.y += g.beta.x * c.y + g.beta.y * c.x;
     }
     *cp = out;
+}
+
+__global__ __launch_bounds__(kThreads) void gemm_reduce_kernel(GemmArgs g, int splits) {
+    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (o >= g.m * g.n) return;
+    reduce_one(g, splits, o, blockIdx.z);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM: GEMMs of different shapes (each possibly a batch) in one
+// persistent launch.  The entries' tiles form one sequence (each entry's
+// first tile id a multiple of 8, entries ordered by tile cost, heaviest
+// first); every XCD owns the ids congruent to its index mod 8 and hands them
+// out in increasing order through a device counter, so each XCD works on all
+// entries at once, heaviest tiles first, and the tiles of one entry that an
+// XCD receives are neighbours (tile_of's XCD ranges).  A workgroup takes
+// tiles until its XCD's ids run out; each tile reads its own entry's device
+// mode flag, so FP16X2, BF16X3 and FP32 tiles run side by side.  The last
+// workgroup to finish clears the counters for the next launch (no memset,
+// so the launch can sit in a captured graph).
+// ---------------------------------------------------------------------------
+__device__ inline int find_entry(const GroupGemmEntry *__restrict__ e, int count, int64_t t, bool red) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((red ? e[mid].red_start : e[mid].tile_start) <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kThreads, TILE == 128 ? 1 : 2) void gemm_grouped_kernel(
+    const GroupGemmEntry *__restrict__ ents, int count, int64_t total, unsigned int *queue) {
+    __shared__ __attribute__((aligned(16))) char smem[kSmemBytes * TILE / kPanelRows];
+    __shared__ int64_t next;
+    const int xcd = blockIdx.x % kXcds;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(&queue[xcd], 1u) * kXcds + xcd;
+        __syncthreads();
+        const int64_t t = next;
+        __syncthreads();  // every wave has read `next`, and the last tile's LDS reads are done
+        if (t >= total) break;
+        const int e = find_entry(ents, count, t, false);
+        const int64_t j = t - ents[e].tile_start;
+        if (j >= ents[e].tiles) continue;  // padding between entries
+        GemmArgs g = ents[e].g;
+        const int nbm = ents[e].nbm, nbn = ents[e].nbn, nsplit = ents[e].nsplit;
+        const int64_t per_z = (int64_t)nbm * nbn * nsplit;
+        const int64_t z = j / per_z, r = j % per_z;
+        const int ks = (int)(r / ((int64_t)nbm * nbn)), bid = (int)(r % ((int64_t)nbm * nbn));
+        select_entry(g, z);
+        const int mode = g.st ? g.st->mode : g.forced_mode;
+        if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
+            gemm_body<QCE_MODE_FP16X2, TILE>(g, nbm, nbn, mode, smem, bid, ks, nsplit > 1);
+        else if (mode == QCE_MODE_BF16X3)
+            gemm_body<QCE_MODE_BF16X3, TILE>(g, nbm, nbn, mode, smem, bid, ks, nsplit > 1);
+        else
+            gemm_body<QCE_MODE_FP32, TILE>(g, nbm, nbn, mode, smem, bid, ks, nsplit > 1);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[kXcds], 1u) == gridDim.x - 1) {
+            // every workgroup has taken its last id: no counter is read again
+            for (int x = 0; x <= kXcds; ++x) atomicExch(&queue[x], 0u);
+        }
+    }
+}
+
+// Split-k sums of the grouped launch's entries that split k.
+__global__ __launch_bounds__(kThreads) void gemm_grouped_reduce_kernel(const GroupGemmEntry *__restrict__ ents,
+                                                                       int count) {
+    const int64_t b = blockIdx.x;
+    const int e = find_entry(ents, count, b, true);
+    const int64_t j = b - ents[e].red_start;
+    if (j >= ents[e].red_blocks || ents[e].nsplit <= 1) return;
+    const GemmArgs &g = ents[e].g;
+    const int64_t per_z = (g.m * g.n + kThreads - 1) / kThreads;
+    const int64_t z = j / per_z;
+    const int64_t o = (j % per_z) * kThreads + threadIdx.x;
+    if (o >= g.m * g.n) return;
+    reduce_one(g, ents[e].nsplit, o, z);
 }
 
 __global__ void scale_c_kernel(float2 *C, int64_t m, int64_t n, int64_t ldc, float2 beta,
@@ -705,8 +789,10 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
             kk = e / kSkCols;
         }
         float2 v = make_float2(0.f, 0.f);
-        if (j < g.n && kk < g.k) v = g.b_kcontig ? g.B[kk + j * g.ldb] : g.B[j + kk * g.ldb];
-        if (g.b_conj) v.y = -v.y;
+        if (j < g.n && kk < g.k) {
+            v = g.b_kcontig ? g.B[kk + j * g.ldb] : g.B[j + kk * g.ldb];
+            if (g.b_conj) v.y = -v.y;  // (padding stays +0)
+        }
         char *row = lds + j * rb;
         if constexpr (MODE == QCE_MODE_FP16X2) {
             uint16_t h[4];
@@ -761,8 +847,10 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
         for (int u = 0; u < 8; ++u) {
             const int kk = kval(c, u);
             float2 x = make_float2(0.f, 0.f);
-            if (row_ok && kk < g.k) x = g.a_kcontig ? g.A[kk + i * g.lda] : g.A[i + (int64_t)kk * g.lda];
-            if (g.a_conj) x.y = -x.y;
+            if (row_ok && kk < g.k) {
+                x = g.a_kcontig ? g.A[kk + i * g.lda] : g.A[i + (int64_t)kk * g.lda];
+                if (g.a_conj) x.y = -x.y;
+            }
             v[u] = x;
         }
     };
@@ -956,6 +1044,90 @@ hipError_t launch_gemm(const GemmArgs &g0, int which, hipStream_t s) {
     const int64_t mn = g.m * g.n;
     hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads), 1, (unsigned)batch),
                        block, 0, s, g, nsplit);
+    return hipGetLastError();
+}
+
+int gemm_group_tile(const GroupGemmEntry *e, int count, int forced_tile) {
+    if (forced_tile == 64 || forced_tile == 128) return forced_tile;
+    int64_t tiles = 0, k = 0;
+    for (int i = 0; i < count; ++i) {
+        tiles += ((e[i].g.m + 127) / 128) * ((e[i].g.n + 127) / 128) * std::max(1, e[i].g.batch);
+        k = std::max(k, e[i].g.k);
+    }
+    // the table's rule on the whole launch's output (and its longest k)
+    int tile = 128;
+    const int64_t chunks = round_up(k, kKPad) / kKPad;
+    for (const TileRule &r : kTileRules)
+        if (tiles >= r.min_tiles128 && chunks >= r.min_chunks) tile = r.tile;
+    return tile;
+}
+
+void gemm_group_shape(GroupGemmEntry *e, int count, int tile) {
+    int64_t tiles = 0;
+    for (int i = 0; i < count; ++i)
+        tiles += ((e[i].g.m + tile - 1) / tile) * ((e[i].g.n + tile - 1) / tile) * std::max(1, e[i].g.batch);
+    for (int i = 0; i < count; ++i) {
+        GemmArgs &g = e[i].g;
+        g.tile = tile;
+        e[i].nbm = (int)((g.m + tile - 1) / tile);
+        e[i].nbn = (int)((g.n + tile - 1) / tile);
+        // k splits as for one GEMM, counting the whole launch's tiles
+        const int64_t pads = round_up(g.k, kKPad) / kKPad;
+        const int64_t min_chunks = tile == 64 ? 8 : 16;
+        int64_t s = 1;
+        if (tiles < 256 && pads >= 2 * min_chunks) s = std::max<int64_t>(1, std::min<int64_t>(512 / tiles, pads / min_chunks));
+        g.kpad_per_split = ((pads + s - 1) / s) * kKPad;
+        e[i].nsplit = (int)((round_up(g.k, kKPad) + g.kpad_per_split - 1) / g.kpad_per_split);
+        g.bsPartial = e[i].nsplit > 1 ? (int64_t)e[i].nsplit * g.m * g.n : 0;
+        e[i].tiles = (int64_t)e[i].nbm * e[i].nbn * e[i].nsplit * std::max(1, g.batch);
+        e[i].red_blocks = e[i].nsplit > 1 ? ((g.m * g.n + kThreads - 1) / kThreads) * std::max(1, g.batch) : 0;
+    }
+}
+
+void gemm_group_schedule(GroupGemmEntry *e, int count, int64_t &total_tiles, int64_t &total_red) {
+    // heaviest tiles (most k chunks per tile) first; stable for equal cost
+    std::stable_sort(e, e + count, [](const GroupGemmEntry &a, const GroupGemmEntry &b) {
+        return a.g.kpad_per_split > b.g.kpad_per_split;
+    });
+    total_tiles = 0;
+    total_red = 0;
+    for (int i = 0; i < count; ++i) {
+        e[i].tile_start = total_tiles;
+        total_tiles = round_up(total_tiles + e[i].tiles, kXcds);
+        e[i].red_start = total_red;
+        total_red += e[i].red_blocks;
+    }
+}
+
+hipError_t launch_gemm_grouped(const GroupGemmEntry *dev_entries, int count, int64_t total_tiles,
+                               int64_t total_red, int tile, unsigned int *queue, hipStream_t s) {
+    if (count <= 0 || total_tiles <= 0) return hipSuccess;
+    if (tile != 64 && tile != 128) return hipErrorInvalidValue;
+    // one workgroup per resident slot (at most one per tile), a multiple of
+    // the XCD count so that every XCD's ids are served
+    static int slots[2] = {0, 0};
+    int &sl = slots[tile == 64 ? 0 : 1];
+    if (sl == 0) {
+        int dev = 0, cus = 0, per = 0;
+        hipError_t err = hipGetDevice(&dev);
+        if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (err == hipSuccess)
+            err = tile == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_grouped_kernel<64>, kThreads, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_grouped_kernel<128>, kThreads, 0);
+        if (err != hipSuccess) return err;
+        sl = std::max(kXcds, (cus * std::max(per, 1)) / kXcds * kXcds);
+    }
+    const int64_t grid = std::min<int64_t>(sl, round_up(total_tiles, kXcds));
+    if (tile == 64)
+        hipLaunchKernelGGL(gemm_grouped_kernel<64>, dim3((unsigned)grid), dim3(kThreads), 0, s, dev_entries, count,
+                           total_tiles, queue);
+    else
+        hipLaunchKernelGGL(gemm_grouped_kernel<128>, dim3((unsigned)grid), dim3(kThreads), 0, s, dev_entries, count,
+                           total_tiles, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || total_red == 0) return e;
+    hipLaunchKernelGGL(gemm_grouped_reduce_kernel, dim3((unsigned)total_red), dim3(kThreads), 0, s, dev_entries,
+                       count);
     return hipGetLastError();
 }
 

@@ -44,15 +44,14 @@ __device__ inline int tile_slot(int tr, int tq) { return tr * 64 + (tq ^ (tr & 3
 // through LDS (read in runs of consecutive addresses), then converts like
 // the first layout (64 consecutive rows of one chunk per wave, 2 KB stores
 // per plane).
+//
+// Block bx of one operand's split (one batch entry); `tile` is the block's
+// 32 KB LDS staging tile (unused by kRowsContig).
 template <int LAYOUT>
-__global__ __launch_bounds__(kThreads) void split_panels_kernel(
+__device__ __attribute__((always_inline)) inline void split_body(
     const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
     int64_t rows_pad, int64_t nchunks, char *__restrict__ panels, const DevState *st, int which,
-    int forced_mode, int forced_shift, int64_t xstride, int64_t pstride, const GatherMap gm) {
-    // batch entry
-    x += (int64_t)blockIdx.z * xstride;
-    panels += (int64_t)blockIdx.z * pstride;
-    if (st) st += blockIdx.z;
+    int forced_mode, int forced_shift, const GatherMap &gm, int64_t bx, float2 *tile) {
     constexpr int kK = 16;  // k-values per chunk row
     float re[kK], im[kK];
     int64_t r, c;  // row and chunk
@@ -61,10 +60,9 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
         // Thread t loads the tile elements e = t + 256 i, whose bits are
         // the tile's index bits by increasing stride in x: the low bits of
         // e walk x's lowest bits wherever the tile holds them.
-        __shared__ float2 tile[64 * 64];
         const int64_t row_blocks = rows_pad / 64;
-        const int64_t r0 = (int64_t)(blockIdx.x % row_blocks) * 64;
-        const int64_t c0 = (int64_t)(blockIdx.x / row_blocks) * 4;
+        const int64_t r0 = (int64_t)(bx % row_blocks) * 64;
+        const int64_t c0 = (int64_t)(bx / row_blocks) * 4;
         const int64_t l0 = c0 * kK;
         if (r0 < rows && l0 < k) {
             int64_t base = 0;
@@ -135,10 +133,9 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
         // issued before its LDS stores); each thread then takes one chunk
         // row, with waves on consecutive rows as in the other layout (whose
         // panel stores are contiguous).
-        __shared__ float2 tile[64 * 64];
         const int64_t row_blocks = rows_pad / 64;
-        const int64_t r0 = (int64_t)(blockIdx.x % row_blocks) * 64;
-        const int64_t c0 = (int64_t)(blockIdx.x / row_blocks) * 4;
+        const int64_t r0 = (int64_t)(bx % row_blocks) * 64;
+        const int64_t c0 = (int64_t)(bx / row_blocks) * 4;
         constexpr int kE = 64 * 64 / kThreads;
         float2 v[kE];
 #pragma unroll
@@ -146,7 +143,11 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
             const int e = i * kThreads + threadIdx.x;
             const int tr = e >> 6, tq = e & 63;
             const int64_t rr = r0 + tr, l = c0 * kK + tq;
-            v[i] = rr < rows && l < k ? x[l + rr * ldx] : make_float2(0.f, 0.f);
+            v[i] = make_float2(0.f, 0.f);
+            if (rr < rows && l < k) {
+                v[i] = x[l + rr * ldx];
+                if (conj) v[i].y = -v[i].y;  // (padding stays +0)
+            }
         }
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
@@ -162,10 +163,10 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
         for (int j = 0; j < kK; ++j) {
             const float2 v = tile[tile_slot(tr, tc * kK + j)];
             re[j] = v.x;
-            im[j] = conj ? -v.y : v.y;
+            im[j] = v.y;
         }
     } else {
-        const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+        const int64_t t = bx * kThreads + threadIdx.x;
         if (t >= rows_pad * nchunks) return;
         r = t % rows_pad;
         c = t / rows_pad;
@@ -174,9 +175,12 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
         for (int j = 0; j < kK; ++j) {
             const int64_t l = l0 + j;
             float2 v = make_float2(0.f, 0.f);
-            if (r < rows && l < k) v = x[r + l * ldx];
+            if (r < rows && l < k) {
+                v = x[r + l * ldx];
+                if (conj) v.y = -v.y;  // (padding stays +0)
+            }
             re[j] = v.x;
-            im[j] = conj ? -v.y : v.y;
+            im[j] = v.y;
         }
     }
     const int mode = st ? st->mode : forced_mode;
@@ -228,6 +232,46 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
     }
 }
 
+template <int LAYOUT>
+__global__ __launch_bounds__(kThreads) void split_panels_kernel(
+    const float2 *__restrict__ x, int64_t ldx, int conj, int64_t rows, int64_t k,
+    int64_t rows_pad, int64_t nchunks, char *__restrict__ panels, const DevState *st, int which,
+    int forced_mode, int forced_shift, int64_t xstride, int64_t pstride, const GatherMap gm) {
+    __shared__ float2 tile[LAYOUT == kRowsContig ? 1 : 64 * 64];
+    // batch entry
+    x += (int64_t)blockIdx.z * xstride;
+    panels += (int64_t)blockIdx.z * pstride;
+    if (st) st += blockIdx.z;
+    split_body<LAYOUT>(x, ldx, conj, rows, k, rows_pad, nchunks, panels, st, which, forced_mode, forced_shift,
+                       gm, blockIdx.x, tile);
+}
+
+// Grouped launch: the blocks of every job (one operand of one GEMM, each a
+// batch) in one grid; block b belongs to the last job whose block_start <= b.
+__global__ __launch_bounds__(kThreads) void split_grouped_kernel(const SplitJob *__restrict__ jobs, int count) {
+    __shared__ float2 tile[64 * 64];
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const SplitJob &q = jobs[lo];
+    const int64_t j = b - q.block_start;
+    if (q.blocks <= 0 || j >= q.blocks * q.batch) return;
+    const int64_t z = j / q.blocks, bx = j % q.blocks;
+    const int64_t rows_pad = round_up(q.rows, kPanelRows), nchunks = round_up(q.k, kKPad) / kKPad;
+    const DevState *st = q.st ? q.st + z : nullptr;
+    const GatherMap gm{};
+    if (q.kcontig)
+        split_body<kKContig>(q.x + z * q.xstride, q.ldx, q.conj, q.rows, q.k, rows_pad, nchunks,
+                             q.panels + z * q.pstride, st, q.which, q.forced_mode, q.shift, gm, bx, tile);
+    else
+        split_body<kRowsContig>(q.x + z * q.xstride, q.ldx, q.conj, q.rows, q.k, rows_pad, nchunks,
+                                q.panels + z * q.pstride, st, q.which, q.forced_mode, q.shift, gm, bx, tile);
+}
+
 __global__ __launch_bounds__(kThreads) void split_planar_kernel(int mode, int shift,
                                                                 const float2 *__restrict__ x,
                                                                 int64_t n, uint16_t *planes) {
@@ -248,6 +292,20 @@ __global__ __launch_bounds__(kThreads) void split_planar_kernel(int mode, int sh
 }
 
 }  // namespace
+
+int64_t split_job_blocks(int64_t rows, int64_t k, int kcontig) {
+    const int64_t rows_pad = round_up(rows, kPanelRows);
+    const int64_t nchunks = round_up(k, kKPad) / kKPad;
+    if (rows_pad * nchunks == 0) return 0;
+    return kcontig ? (rows_pad / 64) * ((nchunks + 3) / 4) : (rows_pad * nchunks + kThreads - 1) / kThreads;
+}
+
+hipError_t launch_split_grouped(const SplitJob *dev_jobs, int count, int64_t total_blocks, hipStream_t s) {
+    if (count <= 0 || total_blocks <= 0) return hipSuccess;
+    if (total_blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(split_grouped_kernel, dim3((unsigned)total_blocks), dim3(kThreads), 0, s, dev_jobs, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_split_panels(const float2 *x, int64_t ldx, int kcontig, int conj, int64_t rows,
                                int64_t k, void *panels, const DevState *st, int which,

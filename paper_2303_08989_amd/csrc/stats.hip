@@ -133,31 +133,19 @@ __device__ inline int operand_level(const OperandStats &s, int emax, double t, d
     return QCE_MODE_FP32;
 }
 
-struct StatsArgs {
-    MatDesc a, b;
-    int blocks_a, blocks_b;
-    DevState *st;           // entry z: st + z
-    StatsRecord *rec;       // entry z: rec + z * (blocks_a + blocks_b)
-    unsigned int *arrived;  // entry z: arrived[z] (zero between calls)
-    double t, t3;
-    int forced;             // -1: rule; >= 0: that mode (statistics for its shifts)
-    int *mode_log;          // nullable: mode of entry 0 at mode_log[slot]
-    int slot;
-};
-
-__global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
+// Block bx of batch entry z of one statistics launch.
+__device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
     __shared__ unsigned int hist[kWaves * kWords * kCols];
     __shared__ unsigned int bins[kWords * 2];
     __shared__ int flag;
-    const int z = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     MatDesc a = g.a, b = g.b;
     a.ptr += (int64_t)z * a.bstride;
     b.ptr += (int64_t)z * b.bstride;
     const int total = g.blocks_a + g.blocks_b;
     StatsRecord *rec = g.rec + (int64_t)z * total;
-    const bool is_a = (int)blockIdx.x < g.blocks_a;
-    const int blk = is_a ? blockIdx.x : blockIdx.x - g.blocks_a;
+    const bool is_a = bx < g.blocks_a;
+    const int blk = is_a ? bx : bx - g.blocks_a;
     const int nblk = is_a ? g.blocks_a : g.blocks_b;
 
     {
@@ -197,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
         n1 = wave_sum(n1);
         n3 = wave_sum(n3);
         mb = wave_max(mb);
-        StatsRecord &r = rec[blockIdx.x];
+        StatsRecord &r = rec[bx];
         if (lane == 0) {
             r.nnz = nnz;
             r.n1 = n1;
@@ -286,6 +274,28 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
     g.arrived[z] = 0u;  // ready for the next call (stream order)
 }
 
+__global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
+    stats_body(g, blockIdx.z, blockIdx.x);
+}
+
+// Grouped launch: the blocks of every entry (each a batch) in one grid;
+// block b belongs to the last entry whose block_start <= b.
+__global__ __launch_bounds__(kThreads) void stats_grouped_kernel(const GroupStatsEntry *__restrict__ ents,
+                                                                 int count) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ents[mid].block_start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupStatsEntry &e = ents[lo];
+    const int per_z = e.args.blocks_a + e.args.blocks_b;
+    const int64_t j = b - e.block_start;
+    if (per_z <= 0 || j >= (int64_t)per_z * e.batch) return;
+    stats_body(e.args, (int)(j / per_z), (int)(j % per_z));
+}
+
 }  // namespace
 
 namespace {
@@ -332,6 +342,36 @@ bool stats_supported(const MatDesc &d) {
 
 size_t stats_record_bytes(const MatDesc &a, const MatDesc &b, int batch) {
     return sizeof(StatsRecord) * (size_t)(stats_blocks(a) + stats_blocks(b)) * (size_t)std::max(1, batch);
+}
+
+hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
+                             unsigned int *arrived, double t, double t3, int forced_mode, int batch,
+                             GroupStatsEntry &out) {
+    if (!stats_supported(a) || !stats_supported(b)) return hipErrorInvalidValue;
+    StatsArgs &g = out.args;
+    g.a = a;
+    g.b = b;
+    g.blocks_a = stats_blocks(a);
+    g.blocks_b = stats_blocks(b);
+    g.st = st;
+    g.rec = rec;
+    g.arrived = arrived;
+    g.t = t;
+    g.t3 = t3;
+    g.forced = forced_mode;
+    g.mode_log = nullptr;
+    g.slot = 0;
+    out.batch = std::max(1, batch);
+    out.block_start = 0;
+    return g.blocks_a + g.blocks_b > 0 ? hipSuccess : hipErrorInvalidValue;
+}
+
+hipError_t launch_stats_grouped(const GroupStatsEntry *dev_entries, int count, int64_t total_blocks,
+                                hipStream_t s) {
+    if (count <= 0 || total_blocks <= 0) return hipSuccess;
+    if (total_blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stats_grouped_kernel, dim3((unsigned)total_blocks), dim3(kThreads), 0, s, dev_entries, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,

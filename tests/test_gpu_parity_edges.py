@@ -290,7 +290,7 @@ def _split_values(rng, shape):
                                         ("bf16x3", 0), ("fp32", 0)])
 @pytest.mark.parametrize("layout,conj", [(0, False), (0, True), (1, False), (1, True)])
 def test_split_panels_bit_exact(qce, handle, mode, shift, layout, conj):
-    rng = np.random.default_rng(7 + layout + 3 * shift)
+    rng = np.random.default_rng(7 + layout + 3 * (shift + 8))
     rows, k = 200, 70                       # two row blocks, five chunks, ragged tails
     stored = (rows, k) if layout == 0 else (k, rows)
     ld = stored[0] + 9

@@ -106,7 +106,8 @@ def test_bit_equal_to_panel_path(qce, handles, dist, mode, m, n, k, opA, opB):
     C1, d1 = run(qce, h, A, B, m, n, k, opA, opB, mode=mode, beta=beta, C0=C0)
     C2, d2 = run(qce, hp, A, B, m, n, k, opA, opB, mode=mode, beta=beta, C0=C0)
     assert d1 == d2
-    assert np.array_equal(C1.view(np.uint32), C2.view(np.uint32)), (dist, mode, d1["mode_name"])
+    assert np.array_equal(np.ascontiguousarray(C1).view(np.uint32), np.ascontiguousarray(C2).view(np.uint32)), \
+        (dist, mode, d1["mode_name"])
     # the value of the mode that ran, to accumulation accuracy; and, where the
     # mode suits the data (AUTO's choice, or a wide-range mode), the exact product
     opa = A if opA == "N" else (A.T if opA == "T" else A.conj().T)

@@ -88,7 +88,8 @@ def test_tile64_equals_tile128_bits(qce, h, dist, mode, m, n, k):
     C64, d64 = run(qce, h, A, B, m, n, k, 64, mode)
     C128, d128 = run(qce, h, A, B, m, n, k, 128, mode)
     assert d64 == d128
-    assert np.array_equal(C64.view(np.uint32), C128.view(np.uint32)), (dist, mode)
+    assert np.array_equal(np.ascontiguousarray(C64).view(np.uint32),
+                          np.ascontiguousarray(C128).view(np.uint32)), (dist, mode)
 
 
 def test_tile64_batched_entries(qce, h):
