@@ -19,7 +19,8 @@ _lib = None
 def _clib():
     global _lib
     if _lib is None:
-        path = _build.build()
+        # QCE_ORACLE_LIB: another build of oracle.c (the sanitizer test's)
+        path = os.environ.get("QCE_ORACLE_LIB") or _build.build()
         lib = ctypes.CDLL(path)
         f64p = ctypes.POINTER(ctypes.c_double)
         f32p = ctypes.POINTER(ctypes.c_float)
