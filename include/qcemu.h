@@ -236,6 +236,32 @@ qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, 
                               int64_t ldc);
 
 /*
+ * qce_cgemm_emulated for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, semantics, errors and results (the same
+ * kernels), but the call allocates nothing: the panels, k-split partial
+ * tiles and statistics records live in a fixed scratch array that the
+ * library holds on every GPU it runs on until the process ends
+ * (qce_noalloc_scratch_bytes() bytes: 64 MiB, enough for example for
+ * m = n = k = 1024), and no timing record is made.  The handle's workspace
+ * is not used.
+ * Every call on one GPU shares that GPU's scratch, whatever the handle: calls
+ * that may overlap in time on one GPU (different streams, handles or host
+ * threads) race and give wrong results; calls ordered on one stream are
+ * safe.  Nothing in the scratch has to start at zero.
+ * Errors: those of qce_cgemm_emulated, plus INVALID_VALUE when the shape
+ * needs more scratch than the fixed size (qce_cgemm_workspace_size(m, n, k)
+ * > qce_noalloc_scratch_bytes()); nothing is enqueued then.
+ */
+qce_status qce_cgemm_emulated_noalloc(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                                      int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                                      const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
+                                      int64_t ldc);
+
+/* Bytes of the fixed scratch of qce_cgemm_emulated_noalloc. */
+size_t qce_noalloc_scratch_bytes(void);
+
+/*
  * Synchronises the handle's stream, then copies the decision record of the
  * most recent qce_cgemm_emulated (or the last GEMM inside qce_contract) to
  * *out (host).  For tests and logging only.  INVALID_VALUE if no GEMM ran.

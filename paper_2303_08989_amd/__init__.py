@@ -167,6 +167,22 @@ def cgemm(h, opA, opB, m, n, k, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0):
     return C
 
 
+def cgemm_noalloc(h, opA, opB, m, n, k, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0):
+    """``cgemm`` through ``qce_cgemm_emulated_noalloc``: no device memory is
+    allocated; the library's fixed per-GPU scratch holds the intermediates
+    (see ``noalloc_scratch_bytes``)."""
+    hh = h._bind_stream()
+    a, b = _c32(alpha), _c32(beta)
+    _check(hh, h.lib.qce_cgemm_emulated_noalloc(hh, _lib.OPS[opA], _lib.OPS[opB], int(m), int(n), int(k),
+                                                ctypes.byref(a), _ptr(A), int(lda), _ptr(B), int(ldb),
+                                                ctypes.byref(b), _ptr(C), int(ldc)))
+    return C
+
+
+def noalloc_scratch_bytes():
+    return int(_lib.load().qce_noalloc_scratch_bytes())
+
+
 def cgemm_batched_workspace_size(m, n, k, batch):
     return int(_lib.load().qce_cgemm_batched_workspace_size(int(m), int(n), int(k), int(batch)))
 

@@ -23,7 +23,8 @@ EXPORTS = (
     "qce_create", "qce_destroy", "qce_set_stream", "qce_set_mode", "qce_get_mode",
     "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_get_size_policy", "qce_set_gemm_tile",
     "qce_set_workspace",
-    "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_get_last_decision",
+    "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_cgemm_emulated_noalloc",
+    "qce_noalloc_scratch_bytes", "qce_get_last_decision",
     "qce_cgemm_batched_workspace_size", "qce_cgemm_strided_batched", "qce_cgemm_grouped",
     "qce_get_batch_decision",
     "qce_contract", "qce_group_begin", "qce_group_end", "qce_group_reset", "qce_permute", "qce_accumulate_f64", "qce_accumulate_n_f64", "qce_fidelity_f64",
@@ -102,6 +103,9 @@ def load():
         "qce_cgemm_workspace_size": (ctypes.c_size_t, [i64, i64, i64]),
         "qce_cgemm_emulated": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64,
                                     vp, i64, c32p, vp, i64]),
+        "qce_cgemm_emulated_noalloc": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64,
+                                            vp, i64, c32p, vp, i64]),
+        "qce_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "qce_get_last_decision": (st, [vp, ctypes.POINTER(QceDecision)]),
         "qce_cgemm_batched_workspace_size": (ctypes.c_size_t, [i64, i64, i64, i64]),
         "qce_cgemm_strided_batched": (st, [vp, ctypes.c_int, ctypes.c_int, i64, i64, i64, c32p, vp, i64, i64,

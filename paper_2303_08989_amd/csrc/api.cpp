@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,43 @@
 #include "gather.hpp"
 
 using namespace qce;
+
+// ---------------------------------------------------------------------------
+// Scratch of qce_cgemm_emulated_noalloc: a fixed array in every GPU's copy of
+// the library, held until the process ends.  Host code never uses the
+// array's name as an address: its device address is looked up once per
+// device (qce_create, with that device current) and kept in
+// g_scratch_ptr.  It holds one GEMM's panels, split-k partial tiles and
+// statistics records, all written before they are read, so nothing in it
+// needs clearing between calls.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the scratch on `device`, which must be current.
+hipError_t scratch_init(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 namespace {
 // A GEMM recorded for a grouped launch.  Operands as the panel writer reads
@@ -1028,6 +1066,11 @@ qce_status qce_create(qce_handle **out, int device) {
         release();
         return QCE_ERR_ALLOC;
     }
+    if (scratch_init(device) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return QCE_ERR_HIP;
+    }
     if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess || hipMemset(h->arrived, 0, arrived_bytes) != hipSuccess ||
         hipMemset(h->gqueue, 0, sizeof(unsigned int) * kGroupQueueWords) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -1179,6 +1222,37 @@ qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, 
     OperandView vb{reinterpret_cast<const float2 *>(B), ldb, opB == QCE_OP_N, opB == QCE_OP_C};
     return cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
                       static_cast<char *>(h->ws));
+}
+
+size_t qce_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+qce_status qce_cgemm_emulated_noalloc(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
+                                      int64_t k, const qce_c32 *alpha, const qce_c32 *A, int64_t lda,
+                                      const qce_c32 *B, int64_t ldb, const qce_c32 *beta, qce_c32 *C,
+                                      int64_t ldc) {
+    if (!h) return QCE_ERR_INVALID_VALUE;
+    bool noop = false;
+    qce_status st = cgemm_check(h, opA, opB, m, n, k, A, lda, B, ldb, C, ldc, &noop);
+    if (st != QCE_SUCCESS || noop) return st;
+    const size_t need = cgemm_ws_bytes(m, n, k);
+    if (need > kScratchBytes)
+        return fail(h, QCE_ERR_INVALID_VALUE,
+                    "a %lld x %lld x %lld GEMM needs %zu bytes of scratch; the fixed scratch holds %zu",
+                    (long long)m, (long long)n, (long long)k, need, kScratchBytes);
+    void *ws = scratch_ptr(h->device);
+    if (!ws) return fail(h, QCE_ERR_INTERNAL, "no scratch address for device %d", h->device);
+    DeviceGuard g(h->device);
+    const float2 al = alpha ? make_float2(alpha->re, alpha->im) : make_float2(1.f, 0.f);
+    const float2 be = beta ? make_float2(beta->re, beta->im) : make_float2(0.f, 0.f);
+    OperandView va{reinterpret_cast<const float2 *>(A), lda, opA != QCE_OP_N, opA == QCE_OP_C};
+    OperandView vb{reinterpret_cast<const float2 *>(B), ldb, opB == QCE_OP_N, opB == QCE_OP_C};
+    // no timing records here: a new event could allocate
+    const bool timing = h->timing;
+    h->timing = false;
+    st = cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
+                    static_cast<char *>(ws));
+    h->timing = timing;
+    return st;
 }
 
 qce_status qce_cgemm_strided_batched(qce_handle *h, qce_op opA, qce_op opB, int64_t m, int64_t n,
