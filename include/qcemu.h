@@ -129,6 +129,9 @@ typedef struct {
  *   QCE_SMALLK         1 (default) or 0: GEMMs with k <= 128 and n <= 64
  *                      split their operands as they load them (no panel
  *                      pass); 0 sends them through the panel path
+ *   QCE_GROUPED_GEMM   1 (default) or 0: inside a qce_contract group, the
+ *                      panel-path GEMMs are recorded and run as one
+ *                      grouped launch (0: they run at once, one by one)
  * The stream is the device's null stream until qce_set_stream.
  * Errors: INVALID_VALUE (h NULL, bad device or bad environment value),
  * ALLOC, HIP.

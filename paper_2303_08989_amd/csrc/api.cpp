@@ -129,6 +129,7 @@ struct qce_handle {
     bool grouping = false;
     bool fused_gather = true;  // permute fused into the split (qce_contract)
     bool smallk = true;        // short-k narrow GEMMs split on load (no panel pass)
+    bool group_gemms = true;   // panel-path contractions recorded in groups (grouped launch)
     int gemm_tile = 0;         // panel GEMM tile: 64, 128, or 0 for the tuned table
     std::vector<qce::SmallItem> pending;
     char *grp_dev = nullptr;   // descriptor arena on the device
@@ -1046,6 +1047,11 @@ qce_status qce_create(qce_handle **out, int device) {
         if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
         h->smallk = f == 1;
     }
+    if (const char *v = getenv("QCE_GROUPED_GEMM")) {
+        int64_t f = 0;
+        if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
+        h->group_gemms = f == 1;
+    }
     if (h->emul_min > h->auto_min) { delete h; return QCE_ERR_INVALID_VALUE; }
     DeviceGuard g(device);
     const size_t arrived_bytes = sizeof(unsigned int) * (kMaxBatch + 1);
@@ -1854,7 +1860,7 @@ qce_status qce_contract(qce_handle *h, const qce_tensor *a, const void *A, const
     // qce_group_end with the group's other such GEMMs, one launch per phase
     // (its permutes run there as well, into temporaries of the group).
     const bool takes_stats = mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED;
-    if (h->grouping && !gx && !gy && kk > 0 && m > 0 && n > 0 && !irregular_shape(m, n, kk) &&
+    if (h->grouping && h->group_gemms && !gx && !gy && kk > 0 && m > 0 && n > 0 && !irregular_shape(m, n, kk) &&
         !(h->smallk && smallk_shape(m, n, kk)) && count >= 1 && count <= kMaxBatch &&
         (!takes_stats || h->gentries + count <= kMaxBatch + 1)) {
         GroupItem it;
