@@ -324,12 +324,12 @@ def run_batching(h, args, torch, qce, synth):
     their index, so each step is one batched GEMM over 1024 slices with
     per-entry modes; each tree level's small contractions grouped into one
     launch), and that pass captured in a HIP graph and replayed."""
-    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, Executor, GraphPass
+    from paper_2303_08989_amd.executor import BatchedExecutor, Executor, GraphPass, plan_for_batching
     c = synth.grid_circuit(pattern="ABCDCDAB", depth=12, seed=1, **synth.GRID_53)
-    t0 = time.perf_counter()
-    plan = CircuitPlan(c, max_log2=18, restarts=4, varied=10)
-    t_plan = time.perf_counter() - t0
     nb = 10
+    t0 = time.perf_counter()
+    plan = plan_for_batching(c, max_log2=18, n_batch=nb, restarts=4)
+    t_plan = time.perf_counter() - t0
     x = synth.random_bitstrings(53, 1, seed=5)[0]
     h.set_mode("auto")
     bx = BatchedExecutor(h, plan, nb)
@@ -343,6 +343,7 @@ def run_batching(h, args, torch, qce, synth):
                     f"({len(plan.sliced)} sliced labels); slice ids 0..{n - 1} ({nb} labels varied), "
                     "AUTO with size policy",
         "plan_seconds": round(t_plan, 1),
+        "plan_estimated_pass_ms": round(plan.batched_estimate * 1e3, 3),
         "per_slice_gemm_log2_dims_range": [min(min(s3) for s3 in shapes), max(max(s3) for s3 in shapes)],
         "contractions_per_pass": len(plan.path),
         "batched_max_intermediate_log2": bx.max_intermediate(),

@@ -65,6 +65,45 @@ class CircuitPlan:
         return 1 << len(self.sliced)
 
 
+def batched_pass_estimate(plan, n_batch, flops_per_s=150e12, bytes_per_s=4e12, launch_s=2e-6):
+    """Estimated device seconds of one ``BatchedExecutor`` pass of ``plan``
+    with its first ``n_batch`` sliced labels kept as batch labels: per step
+    the larger of its flop time (8 m n k per entry) and the time to read both
+    operands and write the result, plus one launch.  Used to choose between
+    contraction orders for the batched pass, whose intermediates carry the
+    batch labels (so an order that is best per slice need not be best
+    batched)."""
+    batch = set(plan.sliced[:n_batch])
+    outer = set(plan.sliced[n_batch:])
+    labs = [frozenset(ls) - outer for ls in plan.label_sets]
+    total = 0.0
+    for a, b in plan.path:
+        la, lb = labs[a], labs[b]
+        shared = la & lb
+        out = (la ^ lb) | (shared & batch)
+        labs.append(out)
+        m, n = 2.0 ** len(la - shared), 2.0 ** len(lb - shared)
+        k, count = 2.0 ** len(shared - batch), 2.0 ** len(shared & batch)
+        flops = 8.0 * m * n * k * count
+        nbytes = 8.0 * (2.0 ** len(la) + 2.0 ** len(lb) + 2.0 ** len(out))
+        total += max(flops / flops_per_s, nbytes / bytes_per_s) + launch_s
+    return total
+
+
+def plan_for_batching(circuit, max_log2, n_batch, restarts=4, seed=0):
+    """The contraction order for batched passes: the plain greedy search
+    and its best candidate re-ordered by subtree reconfiguration are both
+    planned, and the one with the smaller ``batched_pass_estimate`` is
+    returned (with its estimate in ``plan.batched_estimate``)."""
+    cands = [CircuitPlan(circuit, max_log2=max_log2, restarts=restarts, seed=seed, varied=n_batch,
+                         alphas=(1.0,), noises=(0.1, 0.3, 1.0), reconfigure=False),
+             CircuitPlan(circuit, max_log2=max_log2, restarts=restarts, seed=seed, varied=n_batch,
+                         reconfigure="best")]
+    for p in cands:
+        p.batched_estimate = batched_pass_estimate(p, n_batch)
+    return min(cands, key=lambda p: p.batched_estimate)
+
+
 def level_batches(path, n_leaves, steps):
     """The path steps `steps` (ascending) in tree levels: a step is one level
     above the highest of its operands computed among `steps` (leaves and

@@ -139,3 +139,44 @@ def test_sliced_output_wires_give_scalar_leaves(standin):
         want = oracle.statevector_amplitudes(_rounded(c), [x])[0]
         acc = bx.amplitude(x).numpy()
         assert abs(complex(acc[0], acc[1]) - want) < 1e-6 * max(abs(want), 1e-3)
+
+
+def test_batched_pass_estimate_matches_the_pass(monkeypatch):
+    # the estimate's per-step shapes are those of the contractions a batched
+    # pass actually issues (recorded from the stand-in's calls)
+    import paper_2303_08989_amd as qce
+    from paper_2303_08989_amd.executor import BatchedExecutor, CircuitPlan, batched_pass_estimate
+    calls = []
+
+    def record(h, A, la, B, lb, lc, out=None):
+        calls.append((A.numel(), list(la), B.numel(), list(lb), list(lc)))
+        return _einsum(A, la, B, lb, lc)
+    monkeypatch.setattr(qce, "contract", record)
+    c = synth.grid_circuit(3, 4, 6, seed=3, pattern="ABCDCDAB")
+    plan = CircuitPlan(c, max_log2=3, restarts=1, varied=3)
+    nb = 2
+    bx = BatchedExecutor(None, plan, nb, device="cpu")
+    bx.run_pass(bx._leaves(0, 0), grouped=False)
+    assert len(calls) == len(plan.path)
+    fl_rate, by_rate, launch = 1e12, 1e11, 1e-6
+    want = 0.0
+    for na, la, nb_, lb, lc in calls:
+        shared = set(la) & set(lb)
+        batch = shared & set(lc)
+        m = na // 2 ** len(shared)
+        n = nb_ // 2 ** len(shared)
+        k = 2 ** len(shared - batch)
+        count = 2 ** len(batch)
+        flops = 8.0 * m * n * k * count
+        nbytes = 8.0 * (na + nb_ + 2 ** len(lc))
+        want += max(flops / fl_rate, nbytes / by_rate) + launch
+    got = batched_pass_estimate(plan, nb, flops_per_s=fl_rate, bytes_per_s=by_rate, launch_s=launch)
+    assert got == pytest.approx(want, rel=1e-12)
+
+
+def test_plan_for_batching_takes_the_cheaper_order():
+    from paper_2303_08989_amd.executor import batched_pass_estimate, plan_for_batching
+    c = synth.grid_circuit(3, 4, 8, seed=1, pattern="ABCDCDAB")
+    p = plan_for_batching(c, max_log2=4, n_batch=3, restarts=2)
+    assert p.batched_estimate == batched_pass_estimate(p, 3)
+    assert p.batched_estimate > 0
