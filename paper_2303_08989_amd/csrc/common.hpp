@@ -23,16 +23,19 @@ struct OperandStats {
 };
 
 constexpr int kMaxStatsBlocks = 4096;  // per operand
-constexpr int kRelBins = 31;            // exponent bins a block record keeps below its maximum
+constexpr int kRelBins = 32;            // exponent bins a block record keeps below its maximum
 
 // One statistics block's summary of its share of one operand (exact counts
 // of its FP32 components): nonzero finite, floor(log2|v|) >= -14 and
 // >= -110, non-finite, its largest exponent bin (e + 149; -1 if none) and
-// the counts of the kRelBins bins from there down (rel[d]: bin maxbin - d).
-struct StatsRecord {
+// the cumulative counts of the kRelBins bins from there down (cum[d]: bins
+// maxbin - d .. maxbin), so that the count of a window [x, maxbin] is one
+// entry.  160 bytes, 16-byte aligned (vector loads).
+struct __attribute__((aligned(16))) StatsRecord {
     unsigned int nnz, n1, n3, nonfinite;
     int maxbin;
-    unsigned int rel[kRelBins];
+    unsigned int pad[3];
+    unsigned int cum[kRelBins];
 };
 
 struct DevState {
@@ -259,6 +262,7 @@ struct SmallKArgs {
     int forced_mode;
     int batch;
     int64_t bsA, bsB, bsC;
+    int a_stage;  // set by launch_smallk: full row tiles of op(A) copied to LDS directly
 };
 bool smallk_shape(int64_t m, int64_t n, int64_t k);
 hipError_t launch_smallk(const SmallKArgs &g, hipStream_t s);

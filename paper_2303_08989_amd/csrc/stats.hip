@@ -48,11 +48,15 @@ __device__ inline int bin_of(float v) {
     return bin;
 }
 
+// The block's LDS histogram: word t (bins 2t, 2t + 1 as 16-bit halves) has
+// kWaves * kCols counters side by side, wave w's lane pair in column
+// w * kCols + lane % 32 (the 32 lanes of a half wave hit distinct banks).
+constexpr int kRow = kWaves * kCols;  // counters per word
 struct HistCounter {
     unsigned int *col;  // this lane's column (LDS)
     __device__ inline void operator()(float v) {
         const int bin = bin_of(v);
-        __hip_atomic_fetch_add(col + (bin >> 1) * kCols, 1u << ((bin & 1) << 4), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(col + (bin >> 1) * kRow, 1u << ((bin & 1) << 4), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 };
@@ -135,7 +139,7 @@ __device__ inline int operand_level(const OperandStats &s, int emax, double t, d
 
 // Block bx of batch entry z of one statistics launch.
 __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
-    __shared__ unsigned int hist[kWaves * kWords * kCols];
+    __shared__ __attribute__((aligned(16))) unsigned int hist[kWaves * kWords * kCols];
     __shared__ unsigned int bins[kWords * 2];
     __shared__ int flag;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -154,20 +158,30 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
     }
     __syncthreads();
     HistCounter c;
-    c.col = hist + w * kWords * kCols + (lane & 31);
+    c.col = hist + w * kCols + (lane & 31);
     scan_matrix(is_a ? a : b, blk, nblk, c);
     __syncthreads();
-    // the block's histogram: word t holds bins 2t and 2t + 1
-    for (int t = threadIdx.x; t < kWords; t += kThreads) {
+    // the block's histogram: two threads per word, each adding half of its
+    // kRow counters with 16-byte reads; a thread starts at a different
+    // 16-byte slot than its neighbours, so 16 consecutive threads cover all
+    // banks at every read
+    for (int p = threadIdx.x; p < 2 * kWords; p += kThreads) {
+        const int t = p >> 1, half = p & 1;
+        const uint4 *row = reinterpret_cast<const uint4 *>(hist + t * kRow + half * (kRow / 2));
         unsigned int lo = 0, hi = 0;
-        for (int ww = 0; ww < kWaves; ++ww)
-            for (int col = 0; col < kCols; ++col) {
-                const unsigned int v = hist[(ww * kWords + t) * kCols + col];
-                lo += v & 0xffffu;
-                hi += v >> 16;
-            }
-        bins[2 * t] = lo;
-        bins[2 * t + 1] = hi;
+#pragma unroll
+        for (int j = 0; j < kRow / 8; ++j) {
+            const uint4 v = row[(j + p) & (kRow / 8 - 1)];
+            lo += (v.x & 0xffffu) + (v.y & 0xffffu) + (v.z & 0xffffu) + (v.w & 0xffffu);
+            hi += (v.x >> 16) + (v.y >> 16) + (v.z >> 16) + (v.w >> 16);
+        }
+        // the other half's sums (the partner thread is the neighbouring lane)
+        lo += __shfl_xor(lo, 1);
+        hi += __shfl_xor(hi, 1);
+        if (!half) {
+            bins[2 * t] = lo;
+            bins[2 * t + 1] = hi;
+        }
     }
     __syncthreads();
     // the block's record (wave 0)
@@ -193,7 +207,12 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
             r.nonfinite = bins[kBinNonfinite];
             r.maxbin = mb;
         }
-        if (lane < kRelBins) r.rel[lane] = (mb - lane >= 0) ? bins[mb - lane] : 0u;
+        if (lane < kRelBins) {
+            // cumulative count of bins mb - lane .. mb
+            unsigned int c = 0;
+            for (int d = 0; d <= lane; ++d) c += mb - d >= 0 ? bins[mb - d] : 0u;
+            r.cum[lane] = c;
+        }
         __threadfence();  // the record is visible before this block arrives
     }
     __syncthreads();
@@ -202,45 +221,60 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
     if (!flag) return;
     __threadfence();  // every other block's record is visible to this one
 
-    // last block: both operands' statistics from the records, in block order
+    // last block: both operands' statistics from the records, 128 threads
+    // per operand (threads 0-127: A, 128-255: B), each over every 128th
+    // record; integer sums, so the order does not matter
+    __shared__ unsigned long long red[kWaves][5];
+    __shared__ int redmax[kWaves];
+    const int opd = threadIdx.x >> 7, t = threadIdx.x & 127;
+    const int r0 = opd == 0 ? 0 : g.blocks_a, nr = opd == 0 ? g.blocks_a : g.blocks_b;
+    unsigned long long nnz = 0, n1 = 0, n3 = 0, nf = 0;
+    int mb = -1;
+    for (int i = t; i < nr; i += 128) {
+        const uint4 c = *reinterpret_cast<const uint4 *>(&rec[r0 + i].nnz);
+        nnz += c.x;
+        n1 += c.y;
+        n3 += c.z;
+        nf += c.w;
+        mb = max(mb, rec[r0 + i].maxbin);
+    }
+    nnz = wave_sum64(nnz);
+    n1 = wave_sum64(n1);
+    n3 = wave_sum64(n3);
+    nf = wave_sum64(nf);
+    mb = wave_max(mb);
+    if (lane == 0) {
+        red[w][0] = nnz;
+        red[w][1] = n1;
+        red[w][2] = n3;
+        red[w][3] = nf;
+        redmax[w] = mb;
+    }
+    __syncthreads();
+    // the operand's largest bin (its two waves), then stage 2: the part of
+    // each block's top bins inside [gmax - 28, gmax], one cumulative entry
+    const int gmax = max(redmax[2 * opd], redmax[2 * opd + 1]);
+    unsigned long long n2 = 0;
+    for (int i = t; i < nr; i += 128) {
+        const int bm = rec[r0 + i].maxbin;
+        const int top = kWindowSpan - (gmax - bm);  // highest d inside the window (<= 28)
+        if (bm >= 0 && top >= 0) n2 += rec[r0 + i].cum[top];
+    }
+    n2 = wave_sum64(n2);
+    __syncthreads();
+    if (lane == 0) red[w][4] = n2;
+    __syncthreads();
     OperandStats s[2];
     int emaxbin[2];
-    for (int o = 0; o < 2; ++o) {
-        const int r0 = o == 0 ? 0 : g.blocks_a, nr = o == 0 ? g.blocks_a : g.blocks_b;
-        if (w == 0) {
-            unsigned long long nnz = 0, n1 = 0, n3 = 0, nf = 0;
-            int mb = -1;
-            for (int i = lane; i < nr; i += 64) {
-                const StatsRecord &r = rec[r0 + i];
-                nnz += r.nnz;
-                n1 += r.n1;
-                n3 += r.n3;
-                nf += r.nonfinite;
-                mb = max(mb, r.maxbin);
-            }
-            nnz = wave_sum64(nnz);
-            n1 = wave_sum64(n1);
-            n3 = wave_sum64(n3);
-            nf = wave_sum64(nf);
-            mb = wave_max(mb);
-            // stage 2: the part of each block's top bins inside [mb - 28, mb]
-            unsigned long long n2 = 0;
-            for (int i = lane; i < nr; i += 64) {
-                const StatsRecord &r = rec[r0 + i];
-                if (r.maxbin < 0) continue;
-                const int top = kWindowSpan - (mb - r.maxbin);  // highest d inside the window
-                for (int d = 0; d <= top && d < kRelBins; ++d) n2 += r.rel[d];
-            }
-            n2 = wave_sum64(n2);
-            s[o].nnz = nnz;
-            s[o].n1 = n1;
-            s[o].n2 = n2;
-            s[o].n3 = n3;
-            s[o].nonfinite = nf;
-            s[o].maxbits = 0;
-            s[o].pad = 0;
-            emaxbin[o] = mb;
-        }
+    for (int q = 0; q < 2; ++q) {
+        s[q].nnz = red[2 * q][0] + red[2 * q + 1][0];
+        s[q].n1 = red[2 * q][1] + red[2 * q + 1][1];
+        s[q].n3 = red[2 * q][2] + red[2 * q + 1][2];
+        s[q].nonfinite = red[2 * q][3] + red[2 * q + 1][3];
+        s[q].n2 = red[2 * q][4] + red[2 * q + 1][4];
+        s[q].maxbits = 0;
+        s[q].pad = 0;
+        emaxbin[q] = max(redmax[2 * q], redmax[2 * q + 1]);
     }
     if (threadIdx.x != 0) return;
     DevState *st = g.st + z;
