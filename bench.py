@@ -601,6 +601,42 @@ def run_circuits(h, args, torch, qce, synth):
         "largest_gemm_log2_mnk": [list(x) for x in big],
         "size_policy": list(default_policy),
     }
+    # the paper's protocol: the median over 10 bitstrings (Sec. 5.3), here
+    # of each bitstring's first c3_median_slices slice ids, AUTO and FP32
+    nmed = min(args.c3_median_slices, plan3.n_slices)
+    if args.c3_bitstrings > 0 and nmed > 0 and not args.c3_auto_only:
+        from paper_2303_08989_amd import tn
+        nv = max(0, (nmed - 1).bit_length())
+        share_m = tn.memoized_cost(plan3.label_sets, plan3.path, plan3.sliced, nv) / plan3.total_cost
+        xs3 = synth.random_bitstrings(53, args.c3_bitstrings, seed=7)
+        per = []
+        ex_a = Executor(h, plan3)
+        vec_a = torch.empty(nmed, dtype=torch.complex64, device="cuda")
+        vec_f = torch.empty(nmed, dtype=torch.complex64, device="cuda")
+        for xb in xs3:
+            row = {}
+            for key, mode, vec in (("auto", "auto", vec_a), ("fp32", "fp32", vec_f)):
+                h.set_mode(mode)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ex_a.amplitude(int(xb), range(nmed), slice_out=vec)
+                torch.cuda.synchronize()
+                row[key] = time.perf_counter() - t0
+            h.set_mode("auto")
+            fid = qce.fidelity_terms(h, vec_a, vec_f).cpu().numpy()
+            row["fidelity"] = float((fid[0] ** 2 + fid[1] ** 2) / (fid[2] * fid[3])) if fid[2] * fid[3] > 0 else 1.0
+            per.append(row)
+        med = float(np.median([r["auto"] for r in per]))
+        out["config3"]["median_over_bitstrings"] = {
+            "bitstrings": len(per), "slices_each": nmed,
+            "median_seconds_auto": round(med, 4),
+            "median_seconds_fp32": round(float(np.median([r["fp32"] for r in per])), 4),
+            "median_speedup_vs_fp32": round(float(np.median([r["fp32"] / r["auto"] for r in per])), 3),
+            "min_fidelity_auto_vs_fp32": min(r["fidelity"] for r in per),
+            "one_gpu_seconds_per_amplitude_extrapolated": round(med / share_m, 1),
+            "note": "each bitstring recomputes every node (leaves differ); the first bitstring includes "
+                    "no warm-up beyond the 64-slice runs above",
+        }
     if args.c3_auto_only:
         return out
     out["config3"].update({
@@ -640,6 +676,10 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     ap.add_argument("--c3-slices", type=int, default=64, help="slice ids of the 53-qubit network run here")
     ap.add_argument("--c3-restarts", type=int, default=8)
+    ap.add_argument("--c3-bitstrings", type=int, default=10,
+                    help="bitstrings of the 53-qubit median (0: skip)")
+    ap.add_argument("--c3-median-slices", type=int, default=16,
+                    help="slice ids per bitstring in the 53-qubit median")
     ap.add_argument("--no-protocol", action="store_true",
                     help="skip the per-case median / cache-flush / three-seed timing section")
     ap.add_argument("--protocol-reps", type=int, default=20)

@@ -2,13 +2,14 @@
 workgroup), run on the GPU.
 
 For a set of GEMM shapes -- the standalone CGEMM sizes and the matrix-core
-GEMMs of the batched sliced-network pass (each with its batch count) -- and
-for the FP16X2, BF16X3 and FP32 kernels, it times both tiles (hipEvents,
+GEMMs of the batched sliced-network pass (each with its batch count), and
+the groups of them that run as one grouped launch -- and for the FP16X2,
+BF16X3 and FP32 kernels, it times both tiles (hipEvents,
 median of repetitions, a 512 MiB buffer write before each so that operands
 are not served from the Infinity Cache), then writes
 
 * ``tile_table.inc``: rules by the number of 128 x 128 output tiles over all
-  batch entries (power-of-two buckets): each bucket takes the tile with the
+  batch entries and group entries (power-of-two buckets): each bucket takes the tile with the
   smaller summed time over its shapes and modes; consecutive buckets with
   the same tile merge.  The library compiles it in (``gemm_tile``).
 * ``autotune.json``: every timing.
@@ -26,13 +27,21 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# (m, n, k, batch): standalone sizes, then GEMMs of the batched pass of the
-# 53-qubit network (2^18 intermediates, 1024 slices) seen in its plan
+# (m, n, k, batch): standalone sizes, then the matrix-core GEMMs of the
+# batched pass of the 53-qubit network (2^18 intermediates, 1024 slices)
 DEFAULT_SHAPES = [
     (512, 512, 512, 1), (768, 768, 768, 1), (1024, 1024, 1024, 1), (1536, 1536, 1536, 1),
     (2048, 2048, 2048, 1), (4096, 4096, 4096, 1),
-    (256, 256, 1024, 4), (4096, 4096, 64, 4), (512, 512, 256, 16), (1024, 256, 128, 32),
-    (256, 512, 2048, 2), (2048, 1024, 512, 1), (8192, 256, 256, 1), (128, 128, 4096, 8),
+    (8192, 256, 32, 1), (512, 16384, 64, 1), (512, 256, 128, 1), (1024, 2048, 128, 1),
+    (1024, 512, 2048, 1), (2048, 512, 256, 1), (1024, 128, 2048, 1), (128, 4096, 512, 2),
+    (4096, 4096, 64, 4),
+]
+# groups of uneven GEMMs run as one grouped launch: the tree levels of that
+# batched pass with more than one matrix-core GEMM
+DEFAULT_GROUPS = [
+    [(8192, 256, 32), (512, 16384, 64), (512, 256, 128)],
+    [(1024, 2048, 128), (1024, 512, 2048)],
+    [(2048, 512, 256), (1024, 128, 2048)],
 ]
 MODES = ("fp16x2", "bf16x3", "fp32")
 
@@ -41,7 +50,11 @@ def _bucket(tiles128):
     return 0 if tiles128 <= 1 else int(math.floor(math.log2(tiles128)))
 
 
-def measure(shapes, reps=10):
+def _tiles128(shapes):
+    return sum(-(-m // 128) * -(-n // 128) * b for (m, n, k, b) in shapes)
+
+
+def measure(shapes, reps=10, groups=()):
     import torch
     import paper_2303_08989_amd as qce
     h = qce.Handle(0)
@@ -72,9 +85,38 @@ def measure(shapes, reps=10):
                     ev1.synchronize()
                     ts.append(ev0.elapsed_time(ev1))
                 rec[f"ms_{tile}"] = float(np.median(ts))
+            rec["tiles128"] = _tiles128([(m, n, k, batch)])
             rows.append(rec)
             print(json.dumps(rec), flush=True)
         del A, B, C
+    for grp in groups:
+        bufs = []
+        for (m, n, k) in grp:
+            bufs.append((torch.randn(m * k, dtype=torch.complex64, device="cuda", generator=g),
+                         torch.randn(k * n, dtype=torch.complex64, device="cuda", generator=g),
+                         torch.empty(m * n, dtype=torch.complex64, device="cuda")))
+        descs = [{"m": m, "n": n, "k": k, "A": A, "lda": m, "B": B, "ldb": k, "C": C, "ldc": m}
+                 for (m, n, k), (A, B, C) in zip(grp, bufs)]
+        for mode in MODES:
+            h.set_mode(mode)
+            rec = {"group": [list(x) for x in grp], "mode": mode,
+                   "tiles128": _tiles128([(m, n, k, 1) for (m, n, k) in grp])}
+            for tile in (64, 128):
+                h.set_gemm_tile(tile)
+                for _ in range(2):
+                    qce.cgemm_grouped(h, descs)
+                ts = []
+                for r in range(reps):
+                    flush.fill_(float(r))
+                    ev0.record()
+                    qce.cgemm_grouped(h, descs)
+                    ev1.record()
+                    ev1.synchronize()
+                    ts.append(ev0.elapsed_time(ev1))
+                rec[f"ms_{tile}"] = float(np.median(ts))
+            rows.append(rec)
+            print(json.dumps(rec), flush=True)
+        del bufs, descs
     h.set_gemm_tile(0)
     h.close()
     return rows
@@ -84,8 +126,7 @@ def table(rows):
     """Rules {min_tiles128, min_chunks, tile} from the timings."""
     sums = {}
     for r in rows:
-        t128 = -(-r["m"] // 128) * -(-r["n"] // 128) * r["batch"]
-        b = _bucket(t128)
+        b = _bucket(r["tiles128"])
         s = sums.setdefault(b, [0.0, 0.0])
         s[0] += r["ms_64"]
         s[1] += r["ms_128"]
@@ -122,7 +163,7 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
-    rows = measure(DEFAULT_SHAPES, args.reps)
+    rows = measure(DEFAULT_SHAPES, args.reps, DEFAULT_GROUPS)
     rules, sums = table(rows)
     write_table(rules, os.path.join(args.out, "tile_table.inc"))
     with open(os.path.join(args.out, "autotune.json"), "w") as f:

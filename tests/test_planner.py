@@ -137,7 +137,14 @@ def test_autotune_table_rules():
             dict(m=1024, n=1024, k=512, batch=1, ms_64=3.0, ms_128=2.0),    # 64 tiles -> 128
             dict(m=256, n=256, k=64, batch=16, ms_64=1.0, ms_128=1.5),      # 64 tiles (batched)
             dict(m=4096, n=4096, k=64, batch=1, ms_64=5.0, ms_128=4.0)]     # 1024 tiles -> 128
+    for r in rows:
+        r["tiles128"] = autotune._tiles128([(r["m"], r["n"], r["k"], r["batch"])])
+    # a grouped launch counts the tiles of all its entries: 32 + 32 -> the
+    # 64-tile bucket
+    rows.append(dict(tiles128=autotune._tiles128([(512, 1024, 64, 1), (1024, 512, 64, 1)]), ms_64=9.0, ms_128=1.0))
+    assert rows[-1]["tiles128"] == 64
     rules, sums = autotune.table(rows)
     assert rules[0] == (0, 0, 64)
     assert rules[1][2] == 128 and rules[1][0] == 64
     assert len(rules) == 2
+    assert sums["6"] == [13.0, 4.5]
