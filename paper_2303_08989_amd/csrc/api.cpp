@@ -95,7 +95,6 @@ struct qce_handle {
     // min(m, n, k) = 512 (the paper's A100 values are 2048 and 512)
     int64_t auto_min = 512, emul_min = 512;
     DevState *st = nullptr;        // device
-    unsigned int *arrived = nullptr;  // device, kMaxBatch + 1 zeroed arrival counters of the statistics launch
     DevState *dec_base = nullptr;  // decisions of the last call (st, or a batch's states in the workspace)
     int dec_count = 1;
     double *fid_partials = nullptr;  // device, kFidBlocks * 4
@@ -141,7 +140,7 @@ struct qce_handle {
     std::vector<GroupItem> gitems;
     std::vector<GroupPermute> gpre, gpost;
     size_t gtemp = 0;
-    int64_t gentries = 0;            // batch entries of gitems (arrival counters)
+    int64_t gentries = 0;            // batch entries of gitems that take statistics
     unsigned int *gqueue = nullptr;  // device, kGroupQueueWords zeroed tile counters of the grouped GEMM
     // decisions of the last grouped call in caller order: state index (>= 0)
     // or -1 - index into dec_host (entries that took no statistics)
@@ -513,8 +512,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         const bool stats = mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED;
         if (stats) {
             hipEvent_t e0 = span_begin(h);
-            QCE_HIP(h, launch_stats(da, db, dst, rec, h->arrived, h->t, h->t3,
-                                    mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, log, slot, s, nb));
+            QCE_HIP(h, launch_stats(da, db, dst, rec, h->t, h->t3, mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED,
+                                    log, slot, s, nb));
             span_end(h, e0, QCE_PHASE_STATS);
             q.st = dst;
             q.forced_mode = mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED;
@@ -549,8 +548,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
     }
     if (mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED) {
         hipEvent_t e0 = span_begin(h);
-        QCE_HIP(h, launch_stats(da, db, dst, rec, h->arrived, h->t, h->t3,
-                                mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, log, slot, s, nb));
+        QCE_HIP(h, launch_stats(da, db, dst, rec, h->t, h->t3, mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED,
+                                log, slot, s, nb));
         span_end(h, e0, QCE_PHASE_STATS);
         hipEvent_t e1 = span_begin(h);
         QCE_HIP(h, split_operand(a, m, k, panA, dst, 0, 0, s, nb, bt.sa, (int64_t)wl.pa));
@@ -885,7 +884,7 @@ qce_status run_group_gemms(qce_handle *h, std::vector<GroupItem> &items, const s
     };
     std::vector<GroupStatsEntry> sents;
     std::vector<SplitJob> jobs;
-    int64_t stat_blocks = 0, split_blocks = 0;
+    int64_t stat_blocks = 0, split_blocks = 0, selects = 0;
     for (int i = 0; i < count; ++i) {
         const GroupItem &it = items[i];
         GemmArgs &g = ents[i].g;
@@ -902,13 +901,14 @@ qce_status run_group_gemms(qce_handle *h, std::vector<GroupItem> &items, const s
             MatDesc da = it.a.kcontig ? MatDesc{pa, it.k, it.m, it.a.ld, it.sa} : MatDesc{pa, it.m, it.k, it.a.ld, it.sa};
             MatDesc db = it.b.kcontig ? MatDesc{pb, it.k, it.n, it.b.ld, it.sb} : MatDesc{pb, it.n, it.k, it.b.ld, it.sb};
             GroupStatsEntry se;
-            if (stats_group_entry(da, db, dst, reinterpret_cast<StatsRecord *>(ws + o.rec), h->arrived + o.st, h->t,
-                                  h->t3, it.mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, it.count,
-                                  se) != hipSuccess)
+            if (stats_group_entry(da, db, dst, reinterpret_cast<StatsRecord *>(ws + o.rec), h->t, h->t3,
+                                  it.mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED, it.count, se) != hipSuccess)
                 return fail(h, QCE_ERR_NOT_SUPPORTED, "statistics of a %lld x %lld x %lld grouped entry",
                             (long long)it.m, (long long)it.n, (long long)it.k);
             se.block_start = stat_blocks;
             stat_blocks += (int64_t)(se.args.blocks_a + se.args.blocks_b) * se.batch;
+            se.select_start = selects;
+            selects += se.batch;
             sents.push_back(se);
         }
         for (int w = 0; w < 2; ++w) {
@@ -957,7 +957,7 @@ qce_status run_group_gemms(qce_handle *h, std::vector<GroupItem> &items, const s
         if (!sents.empty()) {
             hipEvent_t e0 = span_begin(h);
             QCE_HIP(h, launch_stats_grouped(reinterpret_cast<const GroupStatsEntry *>(dp), (int)sents.size(),
-                                            stat_blocks, h->stream));
+                                            stat_blocks, selects, h->stream));
             span_end(h, e0, QCE_PHASE_STATS);
         }
         hipEvent_t e1 = span_begin(h);
@@ -1054,17 +1054,14 @@ qce_status qce_create(qce_handle **out, int device) {
     }
     if (h->emul_min > h->auto_min) { delete h; return QCE_ERR_INVALID_VALUE; }
     DeviceGuard g(device);
-    const size_t arrived_bytes = sizeof(unsigned int) * (kMaxBatch + 1);
     auto release = [h]() {
         if (h->st) (void)hipFree(h->st);
-        if (h->arrived) (void)hipFree(h->arrived);
         if (h->fid_partials) (void)hipFree(h->fid_partials);
         if (h->mode_log) (void)hipFree(h->mode_log);
         if (h->gqueue) (void)hipFree(h->gqueue);
         delete h;
     };
     if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
-        hipMalloc(&h->arrived, arrived_bytes) != hipSuccess ||
         hipMalloc(&h->fid_partials, sizeof(double) * 4 * kFidBlocks) != hipSuccess ||
         hipMalloc(&h->mode_log, sizeof(int) * kLogCap) != hipSuccess ||
         hipMalloc(&h->gqueue, sizeof(unsigned int) * kGroupQueueWords) != hipSuccess) {
@@ -1077,7 +1074,7 @@ qce_status qce_create(qce_handle **out, int device) {
         release();
         return QCE_ERR_HIP;
     }
-    if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess || hipMemset(h->arrived, 0, arrived_bytes) != hipSuccess ||
+    if (hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess ||
         hipMemset(h->gqueue, 0, sizeof(unsigned int) * kGroupQueueWords) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         release();
@@ -1100,7 +1097,6 @@ qce_status qce_destroy(qce_handle *h) {
     }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     (void)hipFree(h->st);
-    (void)hipFree(h->arrived);
     (void)hipFree(h->fid_partials);
     (void)hipFree(h->mode_log);
     (void)hipFree(h->gqueue);
@@ -1436,8 +1432,7 @@ qce_status qce_expstats(qce_handle *h, const qce_c32 *X, int64_t rows, int64_t c
     }
     qce_status sts = ensure_ws(h, stats_record_bytes(a, none));
     if (sts != QCE_SUCCESS) return sts;
-    QCE_HIP(h, launch_stats(a, none, h->st, static_cast<StatsRecord *>(h->ws), h->arrived, h->t, h->t3, -1,
-                            nullptr, 0, s));
+    QCE_HIP(h, launch_stats(a, none, h->st, static_cast<StatsRecord *>(h->ws), h->t, h->t3, -1, nullptr, 0, s));
     QCE_HIP(h, hipStreamSynchronize(s));
     QCE_HIP(h, hipMemcpy(out, &h->st->last, sizeof(qce_decision), hipMemcpyDeviceToHost));
     return QCE_SUCCESS;

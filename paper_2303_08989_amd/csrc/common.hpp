@@ -124,9 +124,9 @@ struct MatDesc {  // a stored column-major complex64 matrix
 // device state st + z (its own statistics, decision and record).
 constexpr int kMaxBatch = 65535;
 
-// Exponent statistics of both operands and the mode selection of Sec. 4.1
-// in one launch (stats.hip).  rec: stats_record_bytes of device scratch;
-// arrived: one zeroed counter per batch entry (left zeroed).  forced_mode:
+// Exponent statistics of both operands (one read, per-block records) and
+// the mode selection of Sec. 4.1 (one block per GEMM, next launch)
+// (stats.hip).  rec: stats_record_bytes of device scratch.  forced_mode:
 // -1 = the rule; >= 0 = that mode (statistics taken for its shifts and the
 // record).  mode_log (nullable) receives entry 0's mode at slot.  Batched:
 // entry z reads a / b shifted by z * bstride and writes st + z.
@@ -135,7 +135,6 @@ struct StatsArgs {
     int blocks_a, blocks_b;
     DevState *st;           // entry z: st + z
     StatsRecord *rec;       // entry z: rec + z * (blocks_a + blocks_b)
-    unsigned int *arrived;  // entry z: arrived[z] (zero between calls)
     double t, t3;
     int forced;             // -1: rule; >= 0: that mode (statistics for its shifts)
     int *mode_log;          // nullable: mode of entry 0 at mode_log[slot]
@@ -146,22 +145,22 @@ struct StatsArgs {
 struct GroupStatsEntry {
     StatsArgs args;
     int batch, pad;
-    int64_t block_start;
+    int64_t block_start;   // first statistics block
+    int64_t select_start;  // first block of the selection launch (one per batch entry)
 };
 // fills `out` for launch_stats's arguments (block_start left 0)
-hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
-                             unsigned int *arrived, double t, double t3, int forced_mode, int batch,
-                             GroupStatsEntry &out);
+hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec, double t,
+                             double t3, int forced_mode, int batch, GroupStatsEntry &out);
+// total_selects: sum of the entries' batch counts
 hipError_t launch_stats_grouped(const GroupStatsEntry *dev_entries, int count, int64_t total_blocks,
-                                hipStream_t s);
+                                int64_t total_selects, hipStream_t s);
 int stats_blocks(const MatDesc &d);
 // upper bound of stats_blocks over every leading dimension of a rows x cols
 // operand stored either way (rows x cols or cols x rows)
 int stats_blocks_bound(int64_t rows, int64_t cols);
 size_t stats_record_bytes(const MatDesc &a, const MatDesc &b, int batch = 1);
-hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
-                        unsigned int *arrived, double t, double t3, int forced_mode, int *mode_log,
-                        int slot, hipStream_t s, int batch = 1);
+hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec, double t, double t3,
+                        int forced_mode, int *mode_log, int slot, hipStream_t s, int batch = 1);
 
 // Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
 // kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:

@@ -1,4 +1,4 @@
-// Exponent statistics and mode selection (Sec. 4.1 and 4.2) in one launch.
+// Exponent statistics and mode selection (Sec. 4.1 and 4.2).
 //
 // Every FP32 component of both operands is read once (Sec. 4: all elements
 // are checked, no sampling) and binned by its exact exponent
@@ -8,16 +8,18 @@
 // count inside [e_max - 28, e_max], which only a histogram can give before
 // e_max is known.
 //
-// A block bins its share of one operand into a histogram in LDS (each lane
-// pair owns a column of 16-bit counters, so the LDS adds never contend on
-// an address across a wave), then writes a record: its nonzero, stage-1,
-// BF16X3-floor and non-finite counts, its largest exponent bin and the 31
-// bins just below it.  The last block of the launch to finish (an arrival
-// counter per GEMM) adds up the records in block order -- the stage-2 count
-// of a block is the part of its 31 bins inside the global window -- turns
-// both operands' statistics into the device mode flag and shifts, keeps a
-// record for the host and clears the counter for the next call.  Counts are
-// exact and deterministic, and nothing is copied to the host (Sec. 4.2).
+// stats_kernel: a block bins its share of one operand into a histogram in
+// LDS (each lane pair owns a column of 16-bit counters, so the LDS adds of
+// a half wave hit distinct banks), then writes a record: its nonzero,
+// stage-1, BF16X3-floor and non-finite counts, its largest exponent bin and
+// the cumulative counts of the 32 bins below it.  select_kernel (the next
+// launch, one block per GEMM) adds up the records -- the stage-2 count of a
+// block is one cumulative entry -- and turns both operands' statistics
+// into the device mode flag and shifts, with a record for the host.  The
+// kernel boundary publishes the records; a last-block-arrives scheme would
+// need a device-scope fence in every block, which on this part writes back
+// and invalidates the XCD's L2.  Counts are exact integers (the result does
+// not depend on block order), and nothing is copied to the host (Sec. 4.2).
 #include <algorithm>
 
 #include "common.hpp"
@@ -141,7 +143,6 @@ __device__ inline int operand_level(const OperandStats &s, int emax, double t, d
 __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
     __shared__ __attribute__((aligned(16))) unsigned int hist[kWaves * kWords * kCols];
     __shared__ unsigned int bins[kWords * 2];
-    __shared__ int flag;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     MatDesc a = g.a, b = g.b;
     a.ptr += (int64_t)z * a.bstride;
@@ -213,15 +214,17 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
             for (int d = 0; d <= lane; ++d) c += mb - d >= 0 ? bins[mb - d] : 0u;
             r.cum[lane] = c;
         }
-        __threadfence();  // the record is visible before this block arrives
     }
-    __syncthreads();
-    if (threadIdx.x == 0) flag = atomicAdd(&g.arrived[z], 1u) == (unsigned int)(total - 1);
-    __syncthreads();
-    if (!flag) return;
-    __threadfence();  // every other block's record is visible to this one
+}
 
-    // last block: both operands' statistics from the records, 128 threads
+// The decision of batch entry z from its blocks' records (one block of 256
+// threads, launched after the statistics launch: the kernel boundary makes
+// every record visible, with no device-wide fence in the statistics blocks).
+__device__ inline void select_body(const StatsArgs &g, int z) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int total = g.blocks_a + g.blocks_b;
+    const StatsRecord *rec = g.rec + (int64_t)z * total;
+    // both operands' statistics from the records, 128 threads
     // per operand (threads 0-127: A, 128-255: B), each over every 128th
     // record; integer sums, so the order does not matter
     __shared__ unsigned long long red[kWaves][5];
@@ -305,12 +308,13 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
         r.nonfinite[o] = (int64_t)s[o].nonfinite;
         r.emax[o] = emax[o];
     }
-    g.arrived[z] = 0u;  // ready for the next call (stream order)
 }
 
 __global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
     stats_body(g, blockIdx.z, blockIdx.x);
 }
+
+__global__ __launch_bounds__(kThreads) void select_kernel(StatsArgs g) { select_body(g, blockIdx.z); }
 
 // Grouped launch: the blocks of every entry (each a batch) in one grid;
 // block b belongs to the last entry whose block_start <= b.
@@ -328,6 +332,23 @@ __global__ __launch_bounds__(kThreads) void stats_grouped_kernel(const GroupStat
     const int64_t j = b - e.block_start;
     if (per_z <= 0 || j >= (int64_t)per_z * e.batch) return;
     stats_body(e.args, (int)(j / per_z), (int)(j % per_z));
+}
+
+// Grouped decisions: block b takes batch entry z of the last entry whose
+// select_start <= b.
+__global__ __launch_bounds__(kThreads) void select_grouped_kernel(const GroupStatsEntry *__restrict__ ents,
+                                                                  int count) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ents[mid].select_start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupStatsEntry &e = ents[lo];
+    const int64_t z = b - e.select_start;
+    if (z >= e.batch) return;
+    select_body(e.args, (int)z);
 }
 
 }  // namespace
@@ -378,9 +399,8 @@ size_t stats_record_bytes(const MatDesc &a, const MatDesc &b, int batch) {
     return sizeof(StatsRecord) * (size_t)(stats_blocks(a) + stats_blocks(b)) * (size_t)std::max(1, batch);
 }
 
-hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
-                             unsigned int *arrived, double t, double t3, int forced_mode, int batch,
-                             GroupStatsEntry &out) {
+hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec, double t,
+                             double t3, int forced_mode, int batch, GroupStatsEntry &out) {
     if (!stats_supported(a) || !stats_supported(b)) return hipErrorInvalidValue;
     StatsArgs &g = out.args;
     g.a = a;
@@ -389,7 +409,6 @@ hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, S
     g.blocks_b = stats_blocks(b);
     g.st = st;
     g.rec = rec;
-    g.arrived = arrived;
     g.t = t;
     g.t3 = t3;
     g.forced = forced_mode;
@@ -397,20 +416,24 @@ hipError_t stats_group_entry(const MatDesc &a, const MatDesc &b, DevState *st, S
     g.slot = 0;
     out.batch = std::max(1, batch);
     out.block_start = 0;
+    out.select_start = 0;
     return g.blocks_a + g.blocks_b > 0 ? hipSuccess : hipErrorInvalidValue;
 }
 
 hipError_t launch_stats_grouped(const GroupStatsEntry *dev_entries, int count, int64_t total_blocks,
-                                hipStream_t s) {
+                                int64_t total_selects, hipStream_t s) {
     if (count <= 0 || total_blocks <= 0) return hipSuccess;
-    if (total_blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (total_blocks > INT32_MAX || total_selects > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(stats_grouped_kernel, dim3((unsigned)total_blocks), dim3(kThreads), 0, s, dev_entries, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(select_grouped_kernel, dim3((unsigned)total_selects), dim3(kThreads), 0, s, dev_entries,
+                       count);
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec,
-                        unsigned int *arrived, double t, double t3, int forced_mode, int *mode_log,
-                        int slot, hipStream_t s, int batch) {
+hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec, double t, double t3,
+                        int forced_mode, int *mode_log, int slot, hipStream_t s, int batch) {
     if (!stats_supported(a) || !stats_supported(b)) return hipErrorInvalidValue;
     StatsArgs g;
     g.a = a;
@@ -419,7 +442,6 @@ hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsR
     g.blocks_b = stats_blocks(b);
     g.st = st;
     g.rec = rec;
-    g.arrived = arrived;
     g.t = t;
     g.t3 = t3;
     g.forced = forced_mode;
@@ -428,6 +450,9 @@ hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsR
     const int total = g.blocks_a + g.blocks_b;
     if (total == 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(stats_kernel, dim3(total, 1, std::max(1, batch)), dim3(kThreads), 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(select_kernel, dim3(1, 1, std::max(1, batch)), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 
