@@ -765,7 +765,14 @@ __host__ __device__ constexpr int sk_lds_bytes(int kpad) {
                : 2 * kSkCols * sk_row_bytes(kpad, 4);
 }
 
-template <int MODE>
+// The op(A) ring of the k <= 64 kernel: kSkRing stages of one chunk each
+// (16 k-values x 128 rows, [k][row]: k-value kk of the chunk's rows is 1 KB
+// at kk * 1024).
+constexpr int kSkRing = 4;
+constexpr int kSkChunkBytes = 16 * kSkRows * 8;
+constexpr int kSkStageBytes = kSkRing * kSkChunkBytes;
+
+template <int MODE, int KPAD>
 __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, char *lds) {
     constexpr int kE = MODE == QCE_MODE_FP32 ? 4 : 2;
     const int kpad = (int)round_up(g.k, kKPad);
@@ -816,12 +823,8 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, l32 = lane & 31, hi = lane >> 5;
     const int nbk = g.n > 32 ? 2 : 1;
     const int64_t ntiles = (g.m + kSkRows - 1) / kSkRows;
-    // the workgroup walks row tiles with op(B) kept in LDS
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t i = tile * kSkRows + w * 32 + l32;
-    const bool row_ok = i < g.m;
     Acc<MODE> acc;
-    {
+    auto zero_acc = [&]() {
         floatx16 zf;
 #pragma unroll
         for (int r = 0; r < 16; ++r) zf[r] = 0.f;
@@ -836,28 +839,14 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
                 acc.re_n[ub][0] = zf;
             }
         }
-    }
+    };
     // the 8 k-values of op(A) row i this lane supplies in chunk c: 16c + 8hi + u
     // (FP16 / BF16 fragments), or 16c + 8s + 4hi + jj with u = 4s + jj (FP32)
     auto kval = [&](int c, int u) {
         return MODE == QCE_MODE_FP32 ? 16 * c + 8 * (u >> 2) + 4 * hi + (u & 3) : 16 * c + 8 * hi + u;
     };
-    auto load = [&](float2 *v, int c) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int kk = kval(c, u);
-            float2 x = make_float2(0.f, 0.f);
-            if (row_ok && kk < g.k) {
-                x = g.a_kcontig ? g.A[kk + i * g.lda] : g.A[i + (int64_t)kk * g.lda];
-                if (g.a_conj) x.y = -x.y;
-            }
-            v[u] = x;
-        }
-    };
-    float2 cur[8], nxt[8];
-    load(cur, 0);
-    for (int c = 0; c < nchunks; ++c) {
-        if (c + 1 < nchunks) load(nxt, c + 1);
+    // the split and the MFMAs of chunk c (this lane's 8 op(A) values in cur)
+    auto mma_chunk = [&](const float2 *cur, int c) {
         if constexpr (MODE == QCE_MODE_FP16X2) {
             uint16_t h[4][8];
 #pragma unroll
@@ -917,11 +906,8 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
-    }
-
-    // epilogue: D[j][i] -> C[i][j]
+    };
+    auto epilogue = [&](int64_t i, bool row_ok) {
     const int shift_total = shA + shB;
     const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
 #pragma unroll
@@ -957,12 +943,99 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
             *cp = out;
         }
     }
-    }  // row tiles
+    };
+
+    int64_t first_reg_tile = blockIdx.x;  // first tile of the register path below
+    char *la = lds + sk_lds_bytes(KPAD);  // the op(A) ring (k <= 64 kernel only)
+    if (KPAD == 64 && g.a_stage) {
+        // Full row tiles of a rows-contiguous op(A) (k <= 64) stream through a
+        // ring of kSkRing LDS stages of one chunk each (16 k-values x 128
+        // rows, 16 KB), filled by direct buffer loads (no registers held)
+        // kSkRing - 1 chunks ahead across tile boundaries.  Chunk s of this
+        // workgroup is chunk s % nchunks of its (s / nchunks)-th full tile.
+        const int64_t nfull = g.m / kSkRows;
+        const int64_t G = gridDim.x;
+        const int64_t mine = blockIdx.x < nfull ? (nfull - 1 - blockIdx.x) / G + 1 : 0;
+        const int64_t S = mine * nchunks;
+        first_reg_tile = blockIdx.x + mine * G;
+        const int wsc = __builtin_amdgcn_readfirstlane(w);
+        const uint32_t voff = (uint32_t)(16 * lane + wsc * g.lda * 8);
+        auto issue = [&](int64_t sidx) {
+            const int64_t t = blockIdx.x + (sidx / nchunks) * G;
+            const int c = (int)(sidx % nchunks);
+            // rows t*128 .. +127 of k-values 16c .. 16c+15: thread (w, lane),
+            // copy q moves rows 2 lane, 2 lane + 1 of k-value 16c + 4q + w
+            const char *base = reinterpret_cast<const char *>(g.A + t * kSkRows + (int64_t)(16 * c) * g.lda);
+            const uint32_t extent = (uint32_t)((15 * g.lda + kSkRows) * 8);
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, extent, kRsrcWord3);
+            char *stage = la + (int)(sidx % kSkRing) * kSkChunkBytes;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, LDS_PTR(stage + (256 * q + 64 * wsc) * 16), 16, voff,
+                                                         (uint32_t)(4 * q * g.lda * 8), 0, 0);
+        };
+        for (int64_t sidx = 0; sidx < S && sidx < kSkRing - 1; ++sidx) issue(sidx);
+        for (int64_t sidx = 0; sidx < S; ++sidx) {
+            // chunk sidx has landed once at most the copies issued after it
+            // are outstanding (vector memory operations retire in order; the
+            // epilogue's stores only make the wait longer)
+            const int64_t after = min((int64_t)(kSkRing - 2), S - 1 - sidx);
+            if (after >= 2) wait_vmcnt<8>();
+            else if (after == 1) wait_vmcnt<4>();
+            else wait_vmcnt<0>();
+            __syncthreads();  // every wave's copies of chunk sidx, and every wave done with chunk sidx - 1
+            const int c = (int)(sidx % nchunks);
+            const float2 *st2 = reinterpret_cast<const float2 *>(la + (int)(sidx % kSkRing) * kSkChunkBytes);
+            float2 cur[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                float2 x = st2[(kval(c, u) - 16 * c) * kSkRows + w * 32 + l32];
+                if (g.a_conj) x.y = -x.y;
+                cur[u] = x;
+            }
+            if (sidx + kSkRing - 1 < S) issue(sidx + kSkRing - 1);  // into chunk sidx - 1's stage
+            if (c == 0) zero_acc();
+            mma_chunk(cur, c);
+            if (c == nchunks - 1) {
+                const int64_t t = blockIdx.x + (sidx / nchunks) * G;
+                epilogue(t * kSkRows + w * 32 + l32, true);
+            }
+        }
+    }
+    // the workgroup walks (its remaining) row tiles with op(B) kept in LDS,
+    // loading op(A) through registers one chunk ahead
+    for (int64_t tile = first_reg_tile; tile < ntiles; tile += gridDim.x) {
+        const int64_t i = tile * kSkRows + w * 32 + l32;
+        const bool row_ok = i < g.m;
+        auto load = [&](float2 *v, int c) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = kval(c, u);
+                float2 x = make_float2(0.f, 0.f);
+                if (row_ok && kk < g.k) {
+                    x = g.a_kcontig ? g.A[kk + i * g.lda] : g.A[i + (int64_t)kk * g.lda];
+                    if (g.a_conj) x.y = -x.y;
+                }
+                v[u] = x;
+            }
+        };
+        zero_acc();
+        float2 cur[8], nxt[8];
+        load(cur, 0);
+        for (int c = 0; c < nchunks; ++c) {
+            if (c + 1 < nchunks) load(nxt, c + 1);
+            mma_chunk(cur, c);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+        }
+        epilogue(i, row_ok);
+    }
 }
 
 template <int KPAD>
 __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
-    __shared__ __attribute__((aligned(16))) char lds[sk_lds_bytes(KPAD)];
+    __shared__ __attribute__((aligned(16))) char lds[sk_lds_bytes(KPAD) + (KPAD == 64 ? kSkStageBytes : 0)];
     const int64_t z = blockIdx.z;
     g.A += z * g.bsA;
     g.B += z * g.bsB;
@@ -970,11 +1043,11 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
     if (g.st) g.st += z;
     const int mode = g.forced_mode >= 0 ? g.forced_mode : g.st->mode;
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
-        smallk_body<QCE_MODE_FP16X2>(g, mode, lds);
+        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, lds);
     else if (mode == QCE_MODE_BF16X3)
-        smallk_body<QCE_MODE_BF16X3>(g, mode, lds);
+        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, lds);
     else
-        smallk_body<QCE_MODE_FP32>(g, mode, lds);
+        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, lds);
 }
 
 }  // namespace
@@ -1153,14 +1226,36 @@ hipError_t launch_smallk(const SmallKArgs &g, hipStream_t s) {
     if (!smallk_shape(g.m, g.n, g.k)) return hipErrorInvalidValue;
     if (g.forced_mode < 0 && !g.st) return hipErrorInvalidValue;
     const int batch = std::max(1, g.batch);
-    // at most one workgroup per CU per entry: op(B) is split into LDS once
-    // per workgroup and reused for every row tile it walks
+    // at most as many workgroups as fit on the device at once: op(B) is
+    // split into LDS once per workgroup and reused for every row tile it
+    // walks
+    const bool short64 = round_up(g.k, kKPad) <= 64;
+    static int slots[2] = {0, 0};
+    int &sl = slots[short64 ? 0 : 1];
+    if (sl == 0) {
+        int dev = 0, cus = 0, per = 0;
+        hipError_t err = hipGetDevice(&dev);
+        if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (err == hipSuccess)
+            err = short64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, smallk_kernel<64>, kThreads, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, smallk_kernel<128>, kThreads, 0);
+        if (err != hipSuccess) return err;
+        sl = std::max(1, cus * std::max(per, 1));
+    }
     const int64_t tiles = (g.m + kSkRows - 1) / kSkRows;
-    const dim3 grid((unsigned)std::min<int64_t>(tiles, 256), 1, (unsigned)batch), block(kThreads);
-    if (round_up(g.k, kKPad) <= 64)
-        hipLaunchKernelGGL(smallk_kernel<64>, grid, block, 0, s, g);
+    const dim3 grid((unsigned)std::min<int64_t>(tiles, sl), 1, (unsigned)batch), block(kThreads);
+    // LDS staging of op(A) (k <= 64 kernel): rows contiguous, 16-byte
+    // aligned copies in every batch entry, k a multiple of 16, and every
+    // copy's byte offset inside 32 bits
+    SmallKArgs q = g;
+    const int64_t extent = ((g.k - 1) * g.lda + kSkRows) * 8;
+    q.a_stage = short64 && !g.a_kcontig && g.k % kKPad == 0 && g.lda % 2 == 0 &&
+                (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (batch == 1 || g.bsA % 2 == 0) &&
+                extent + 4 * g.lda * 8 < (int64_t(1) << 32);
+    if (short64)
+        hipLaunchKernelGGL(smallk_kernel<64>, grid, block, 0, s, q);
     else
-        hipLaunchKernelGGL(smallk_kernel<128>, grid, block, 0, s, g);
+        hipLaunchKernelGGL(smallk_kernel<128>, grid, block, 0, s, q);
     return hipGetLastError();
 }
 
