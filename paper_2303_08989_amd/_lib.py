@@ -7,7 +7,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqcemu.so")
+# QCE_LIB: another build of the same library (the host-sanitizer variant)
+LIB_PATH = os.environ.get("QCE_LIB") or os.path.join(HERE, "libqcemu.so")
 
 # qce_mode values
 MODE_FP16X2, MODE_FP16X2_SCALED, MODE_BF16X3, MODE_FP32, MODE_AUTO = 0, 1, 2, 3, 4

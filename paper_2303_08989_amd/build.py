@@ -32,10 +32,19 @@ SOURCES = ["stats.hip", "split.hip", "gemm.hip", "direct.hip", "permute.hip", "r
            "api.cpp"]
 
 
-def _compile(src, verbose):
+# Host-side sanitizers (the device code is built as usual): AddressSanitizer
+# and UndefinedBehaviorSanitizer on the C-ABI layer and the launchers, for a
+# separate libqcemu_asan.so loaded through QCE_LIB with the clang ASan
+# runtime preloaded.
+SANITIZE_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+ASAN_LIB = os.path.join(HERE, "libqcemu_asan.so")
+
+
+def _compile(src, verbose, sanitize=False):
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, "-x", "hip", *COMMON_FLAGS, "-c", path, "-o", obj]
+    obj = os.path.join(BUILD, ("asan_" if sanitize else "") + src + ".o")
+    cmd = [HIPCC, "-x", "hip", *COMMON_FLAGS, *(SANITIZE_FLAGS if sanitize else []), "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,22 +57,33 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source and link the shared library (always rebuilds)."""
+def build(verbose=False, jobs=None, sanitize=False):
+    """Compile every source and link the shared library (always rebuilds).
+    sanitize: the host-sanitizer variant libqcemu_asan.so instead."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda s: _compile(s, verbose, sanitize), SOURCES))
+    out = ASAN_LIB if sanitize else LIB
+    tmp = out + ".tmp%d" % os.getpid()
+    link_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-shared-libsan"] if sanitize else []
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_san, "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def asan_runtime():
+    """Path of the clang ASan runtime to preload for libqcemu_asan.so."""
+    res = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = res.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else None
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--asan" in sys.argv))
