@@ -31,7 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # batched pass of the 53-qubit network (2^18 intermediates, 1024 slices)
 DEFAULT_SHAPES = [
     (512, 512, 512, 1), (768, 768, 768, 1), (1024, 1024, 1024, 1), (1536, 1536, 1536, 1),
-    (2048, 2048, 2048, 1), (4096, 4096, 4096, 1),
+    (2048, 2048, 2048, 1), (4096, 4096, 4096, 1), (8192, 8192, 8192, 1),
     (8192, 256, 32, 1), (512, 16384, 64, 1), (512, 256, 128, 1), (1024, 2048, 128, 1),
     (1024, 512, 2048, 1), (2048, 512, 256, 1), (1024, 128, 2048, 1), (128, 4096, 512, 2),
     (4096, 4096, 64, 4),
@@ -86,6 +86,7 @@ def measure(shapes, reps=10, groups=()):
                     ts.append(ev0.elapsed_time(ev1))
                 rec[f"ms_{tile}"] = float(np.median(ts))
             rec["tiles128"] = _tiles128([(m, n, k, batch)])
+            rec["chunks"] = -(-k // 16)
             rows.append(rec)
             print(json.dumps(rec), flush=True)
         del A, B, C
@@ -100,7 +101,8 @@ def measure(shapes, reps=10, groups=()):
         for mode in MODES:
             h.set_mode(mode)
             rec = {"group": [list(x) for x in grp], "mode": mode,
-                   "tiles128": _tiles128([(m, n, k, 1) for (m, n, k) in grp])}
+                   "tiles128": _tiles128([(m, n, k, 1) for (m, n, k) in grp]),
+                   "chunks": max(-(-k // 16) for (m, n, k) in grp)}
             for tile in (64, 128):
                 h.set_gemm_tile(tile)
                 for _ in range(2):
@@ -122,23 +124,35 @@ def measure(shapes, reps=10, groups=()):
     return rows
 
 
+# k classes of the table: fewer than LONG_K_CHUNKS chunks of 16 k-values
+# (output-dominated GEMMs) and the rest
+LONG_K_CHUNKS = 16
+
+
 def table(rows):
-    """Rules {min_tiles128, min_chunks, tile} from the timings."""
+    """Rules (min_tiles128, min_chunks, tile) from the timings: one rule per
+    measured power-of-two bucket of 128 x 128 tiles and k class (short or
+    long k), each taking the tile with the smaller summed median time over
+    its shapes and modes, listed in ascending order so that the last rule
+    whose thresholds a GEMM reaches is its own bucket's.  A bucket with only
+    one k class measured uses that class's tile for both."""
     sums = {}
     for r in rows:
-        b = _bucket(r["tiles128"])
-        s = sums.setdefault(b, [0.0, 0.0])
+        key = (_bucket(r["tiles128"]), LONG_K_CHUNKS if r.get("chunks", 0) >= LONG_K_CHUNKS else 0)
+        s = sums.setdefault(key, [0.0, 0.0])
         s[0] += r["ms_64"]
         s[1] += r["ms_128"]
     rules = []
-    for b in sorted(sums):
-        tile = 64 if sums[b][0] < sums[b][1] else 128
+    for b in sorted({k[0] for k in sums}):
         lo = 0 if b == 0 else 1 << b
-        if not rules or rules[-1][2] != tile:
-            rules.append((lo, 0, tile))
-    if rules and rules[0][0] != 0:
-        rules[0] = (0, 0, rules[0][2])
-    return rules, {str(b): v for b, v in sums.items()}
+        best = {c: (64 if sums[(b, c)][0] < sums[(b, c)][1] else 128) for c in (0, LONG_K_CHUNKS) if (b, c) in sums}
+        for c in (0, LONG_K_CHUNKS):
+            rules.append((lo, c, best.get(c, next(iter(best.values())))))
+    if rules:
+        rules[0] = (0,) + tuple(rules[0][1:])
+        if len(rules) > 1 and rules[1][0] != 0 and rules[0][1] == 0 and rules[1][1] != 0:
+            rules[1] = (0,) + tuple(rules[1][1:])
+    return rules, {f"{b}/{c}": v for (b, c), v in sums.items()}
 
 
 def write_table(rules, path):
@@ -146,7 +160,7 @@ def write_table(rules, path):
         "// Tile shape of the panel GEMM by output size, written by",
         "// paper_2303_08989_amd/autotune.py from timings of both tiles (the summed",
         "// median time over the measured shapes and modes of each power-of-two",
-        "// bucket of 128 x 128 output tiles, batch entries included).",
+        "// bucket of 128 x 128 output tiles, batch entries included, and k class).",
         "// { first count of 128 x 128 tiles (all batch entries), first chunk count",
         "//   (k / 16), tile }: the last rule whose firsts are both reached applies.",
         "static const TileRule kTileRules[] = {",

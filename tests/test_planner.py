@@ -130,21 +130,35 @@ def test_reconfigured_sliced_plan_numpy_matches_oracle():
 
 
 def test_autotune_table_rules():
-    # buckets of 128 x 128 tile counts take the faster tile; equal
-    # neighbours merge; the first rule starts at zero tiles
+    # cells (power-of-two bucket of 128 x 128 tiles, k class) take the
+    # faster tile; every bucket gets a rule for both k classes, in ascending
+    # order from zero tiles; the library's lookup (last rule whose
+    # thresholds are reached) then lands in a GEMM's own cell
     from paper_2303_08989_amd import autotune
-    rows = [dict(m=512, n=512, k=512, batch=1, ms_64=1.0, ms_128=2.0),      # 16 tiles -> 64
-            dict(m=1024, n=1024, k=512, batch=1, ms_64=3.0, ms_128=2.0),    # 64 tiles -> 128
-            dict(m=256, n=256, k=64, batch=16, ms_64=1.0, ms_128=1.5),      # 64 tiles (batched)
-            dict(m=4096, n=4096, k=64, batch=1, ms_64=5.0, ms_128=4.0)]     # 1024 tiles -> 128
+    rows = [dict(m=512, n=512, k=512, batch=1, ms_64=1.0, ms_128=2.0),      # 16 tiles, long k -> 64
+            dict(m=1024, n=1024, k=512, batch=1, ms_64=3.0, ms_128=2.0),    # 64 tiles, long k -> 128
+            dict(m=256, n=256, k=64, batch=16, ms_64=1.0, ms_128=1.5),      # 64 tiles, short k -> 64
+            dict(m=4096, n=4096, k=64, batch=1, ms_64=5.0, ms_128=4.0),     # 1024 tiles, short k -> 128
+            dict(m=4096, n=4096, k=4096, batch=1, ms_64=9.0, ms_128=4.0)]   # 1024 tiles, long k -> 128
     for r in rows:
         r["tiles128"] = autotune._tiles128([(r["m"], r["n"], r["k"], r["batch"])])
-    # a grouped launch counts the tiles of all its entries: 32 + 32 -> the
-    # 64-tile bucket
-    rows.append(dict(tiles128=autotune._tiles128([(512, 1024, 64, 1), (1024, 512, 64, 1)]), ms_64=9.0, ms_128=1.0))
+        r["chunks"] = -(-r["k"] // 16)
+    # a grouped launch counts the tiles of all its entries (32 + 32) and its
+    # longest k
+    rows.append(dict(tiles128=autotune._tiles128([(512, 1024, 64, 1), (1024, 512, 64, 1)]), chunks=4,
+                     ms_64=0.5, ms_128=1.0))
     assert rows[-1]["tiles128"] == 64
     rules, sums = autotune.table(rows)
-    assert rules[0] == (0, 0, 64)
-    assert rules[1][2] == 128 and rules[1][0] == 64
-    assert len(rules) == 2
-    assert sums["6"] == [13.0, 4.5]
+    assert sums["6/0"] == [1.5, 2.5] and sums["6/16"] == [3.0, 2.0]
+
+    def lookup(tiles, chunks):
+        tile = 128
+        for t0, c0, t in rules:
+            if tiles >= t0 and chunks >= c0:
+                tile = t
+        return tile
+    assert lookup(16, 32) == 64 and lookup(16, 1) == 64     # only long k measured: both classes
+    assert lookup(64, 32) == 128 and lookup(64, 4) == 64
+    assert lookup(100, 4) == 64 and lookup(100, 100) == 128
+    assert lookup(1024, 4) == 128 and lookup(5000, 256) == 128
+    assert rules[0][0] == 0 and rules == sorted(rules)
