@@ -889,6 +889,28 @@ def main():
         set_traffic(r)
     # the emulated hot path's kernels against the FP16 / BF16 MFMA peak
     roof_emulated = {k2: v for k2, v in roof_by_kernel.items() if "fp32" not in k2}
+    # tall-skinny cases (k <= 128, n <= 64): bound by HBM; algorithmic bytes
+    # of the GEMM kernel (A, B read once, C written) and of the whole AUTO
+    # call (plus the statistics' read of A and B)
+    roof_hbm = {}
+    for e in case_out:
+        m_, n_, k_ = e["shape"]
+        if n_ > 64 or k_ > 128:
+            continue
+        g_ms = sum(v for p, v in e["phase_ms"].items() if p.startswith("gemm"))
+        gemm_bytes = 8.0 * (m_ * k_ + k_ * n_ + m_ * n_)
+        call_bytes = gemm_bytes + 8.0 * (m_ * k_ + k_ * n_)
+        cls = "fp16x2" if e["mode"].startswith("fp16x2") else e["mode"]
+        tr = {"kernel": f"smallk_kernel[{cls}]", "case": f"{m_}x{n_}x{k_} dist {e['dist']}"}
+        set_traffic(tr)
+        roof_hbm[f"{m_}x{n_}x{k_} dist {e['dist']}"] = {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "gemm_kernel": tr["kernel"], "gemm_traffic": tr["traffic"], "traffic_source": tr["traffic_source"],
+            "gemm_kernel_ms": round(g_ms, 5), "gemm_bytes": gemm_bytes,
+            "gemm_achieved": round(gemm_bytes / (g_ms * 1e-3) / 1e9, 1) if g_ms else None,
+            "call_ms": e["ms"], "call_bytes": call_bytes,
+            "call_achieved": round(call_bytes / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] else None,
+            "mode": e["mode"]}
 
     protocol = None if args.no_protocol else run_protocol(h, args, torch, qce, synth, data)
     irregular = None if args.no_irregular else run_irregular(h, torch, qce)
@@ -955,6 +977,7 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "fp32_baseline": base or None,
         "roofline_by_kernel": roof_by_kernel,
         "roofline_emulated": roof_emulated,
+        "roofline_tall_skinny": roof_hbm or None,
         "protocol": protocol,
         "amplitudes": circuits,
         "irregular": irregular,
