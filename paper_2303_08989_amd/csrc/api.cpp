@@ -341,6 +341,43 @@ struct OperandView {
     const GatherMap *gm = nullptr;
 };
 
+// Both operands into panels in one launch when neither is read through a
+// bit map and they are small (below 2^24 elements in all: there the launch
+// overhead is the split's main cost); else one launch per operand.
+hipError_t split_operand(const OperandView &v, int64_t rows, int64_t k, char *panels, const DevState *st,
+                         int which, int forced_mode, hipStream_t s, int nb, int64_t xstride, int64_t pstride);
+hipError_t split_operands(const OperandView &a, const OperandView &b, int64_t m, int64_t n, int64_t k,
+                          char *panA, char *panB, const DevState *st, int forced_mode, hipStream_t s, int nb,
+                          int64_t sa, int64_t sb, int64_t pa, int64_t pb) {
+    if (a.gm || b.gm || (double)(m + n) * (double)k * (double)nb > (double)(int64_t(1) << 24)) {
+        hipError_t e = split_operand(a, m, k, panA, st, 0, forced_mode, s, nb, sa, pa);
+        if (e != hipSuccess) return e;
+        return split_operand(b, n, k, panB, st, 1, forced_mode, s, nb, sb, pb);
+    }
+    SplitJob ja{}, jb{};
+    const OperandView *v[2] = {&a, &b};
+    SplitJob *j[2] = {&ja, &jb};
+    for (int w = 0; w < 2; ++w) {
+        SplitJob &q = *j[w];
+        q.x = v[w]->ptr;
+        q.ldx = v[w]->ld;
+        q.kcontig = v[w]->kcontig;
+        q.conj = v[w]->conj;
+        q.rows = w ? n : m;
+        q.k = k;
+        q.panels = w ? panB : panA;
+        q.st = st;
+        q.which = w;
+        q.forced_mode = forced_mode;
+        q.shift = 0;
+        q.batch = nb;
+        q.xstride = w ? sb : sa;
+        q.pstride = w ? pb : pa;
+        q.blocks = split_job_blocks(q.rows, k, q.kcontig);
+    }
+    return launch_split_pair(ja, jb, s);
+}
+
 // Split one operand into panels (the mode and shift from the device state
 // when st is set).
 hipError_t split_operand(const OperandView &v, int64_t rows, int64_t k, char *panels, const DevState *st,
@@ -552,8 +589,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
                                 log, slot, s, nb));
         span_end(h, e0, QCE_PHASE_STATS);
         hipEvent_t e1 = span_begin(h);
-        QCE_HIP(h, split_operand(a, m, k, panA, dst, 0, 0, s, nb, bt.sa, (int64_t)wl.pa));
-        QCE_HIP(h, split_operand(b, n, k, panB, dst, 1, 0, s, nb, bt.sb, (int64_t)wl.pb));
+        QCE_HIP(h, split_operands(a, b, m, n, k, panA, panB, dst, 0, s, nb, bt.sa, bt.sb, (int64_t)wl.pa,
+                                  (int64_t)wl.pb));
         span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = dst;
         g.forced_mode = -1;
@@ -569,8 +606,8 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         h->last_on_device = true;
     } else {
         hipEvent_t e1 = span_begin(h);
-        QCE_HIP(h, split_operand(a, m, k, panA, nullptr, 0, mode, s, nb, bt.sa, (int64_t)wl.pa));
-        QCE_HIP(h, split_operand(b, n, k, panB, nullptr, 1, mode, s, nb, bt.sb, (int64_t)wl.pb));
+        QCE_HIP(h, split_operands(a, b, m, n, k, panA, panB, nullptr, mode, s, nb, bt.sa, bt.sb, (int64_t)wl.pa,
+                                  (int64_t)wl.pb));
         span_end(h, e1, QCE_PHASE_SPLIT);
         g.st = nullptr;
         g.forced_mode = mode;

@@ -190,6 +190,9 @@ struct SplitJob {
 };
 int64_t split_job_blocks(int64_t rows, int64_t k, int kcontig);
 hipError_t launch_split_grouped(const SplitJob *dev_jobs, int count, int64_t total_blocks, hipStream_t s);
+// both operands of one GEMM (or batch) in one launch (jobs by value;
+// block_start ignored)
+hipError_t launch_split_pair(const SplitJob &a, const SplitJob &b, hipStream_t s);
 
 struct GemmArgs {
     const void *panelsA;  // rows = m

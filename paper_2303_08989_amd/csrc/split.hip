@@ -246,6 +246,19 @@ __global__ __launch_bounds__(kThreads) void split_panels_kernel(
                        gm, blockIdx.x, tile);
 }
 
+__device__ __attribute__((always_inline)) inline void split_job_block(const SplitJob &q, int64_t j, float2 *tile) {
+    const int64_t z = j / q.blocks, bx = j % q.blocks;
+    const int64_t rows_pad = round_up(q.rows, kPanelRows), nchunks = round_up(q.k, kKPad) / kKPad;
+    const DevState *st = q.st ? q.st + z : nullptr;
+    const GatherMap gm{};
+    if (q.kcontig)
+        split_body<kKContig>(q.x + z * q.xstride, q.ldx, q.conj, q.rows, q.k, rows_pad, nchunks,
+                             q.panels + z * q.pstride, st, q.which, q.forced_mode, q.shift, gm, bx, tile);
+    else
+        split_body<kRowsContig>(q.x + z * q.xstride, q.ldx, q.conj, q.rows, q.k, rows_pad, nchunks,
+                                q.panels + z * q.pstride, st, q.which, q.forced_mode, q.shift, gm, bx, tile);
+}
+
 // Grouped launch: the blocks of every job (one operand of one GEMM, each a
 // batch) in one grid; block b belongs to the last job whose block_start <= b.
 __global__ __launch_bounds__(kThreads) void split_grouped_kernel(const SplitJob *__restrict__ jobs, int count) {
@@ -260,16 +273,16 @@ __global__ __launch_bounds__(kThreads) void split_grouped_kernel(const SplitJob 
     const SplitJob &q = jobs[lo];
     const int64_t j = b - q.block_start;
     if (q.blocks <= 0 || j >= q.blocks * q.batch) return;
-    const int64_t z = j / q.blocks, bx = j % q.blocks;
-    const int64_t rows_pad = round_up(q.rows, kPanelRows), nchunks = round_up(q.k, kKPad) / kKPad;
-    const DevState *st = q.st ? q.st + z : nullptr;
-    const GatherMap gm{};
-    if (q.kcontig)
-        split_body<kKContig>(q.x + z * q.xstride, q.ldx, q.conj, q.rows, q.k, rows_pad, nchunks,
-                             q.panels + z * q.pstride, st, q.which, q.forced_mode, q.shift, gm, bx, tile);
-    else
-        split_body<kRowsContig>(q.x + z * q.xstride, q.ldx, q.conj, q.rows, q.k, rows_pad, nchunks,
-                                q.panels + z * q.pstride, st, q.which, q.forced_mode, q.shift, gm, bx, tile);
+    split_job_block(q, j, tile);
+}
+
+// Both operands of one GEMM (or batch) in one launch, the jobs passed by
+// value: blocks [0, a.blocks * a.batch) split op(A), the rest op(B).
+__global__ __launch_bounds__(kThreads) void split_pair_kernel(const SplitJob a, const SplitJob b) {
+    __shared__ float2 tile[64 * 64];
+    const int64_t blk = blockIdx.x, na = a.blocks * a.batch;
+    if (blk < na) split_job_block(a, blk, tile);
+    else split_job_block(b, blk - na, tile);
 }
 
 __global__ __launch_bounds__(kThreads) void split_planar_kernel(int mode, int shift,
@@ -298,6 +311,14 @@ int64_t split_job_blocks(int64_t rows, int64_t k, int kcontig) {
     const int64_t nchunks = round_up(k, kKPad) / kKPad;
     if (rows_pad * nchunks == 0) return 0;
     return kcontig ? (rows_pad / 64) * ((nchunks + 3) / 4) : (rows_pad * nchunks + kThreads - 1) / kThreads;
+}
+
+hipError_t launch_split_pair(const SplitJob &a, const SplitJob &b, hipStream_t s) {
+    const int64_t total = a.blocks * a.batch + b.blocks * b.batch;
+    if (total <= 0) return hipSuccess;
+    if (total > INT32_MAX || a.blocks <= 0 || b.blocks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(split_pair_kernel, dim3((unsigned)total), dim3(kThreads), 0, s, a, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_split_grouped(const SplitJob *dev_jobs, int count, int64_t total_blocks, hipStream_t s) {
