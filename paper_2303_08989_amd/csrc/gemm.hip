@@ -772,8 +772,49 @@ constexpr int kSkRing = 4;
 constexpr int kSkChunkBytes = 16 * kSkRows * 8;
 constexpr int kSkStageBytes = kSkRing * kSkChunkBytes;
 
+// Eight 8-byte LDS reads of one lane's op(A) values in a ring stage, at
+// addr + 1024 d for its k-offsets d (0-7, or 0-3 and 8-11 for the FP32
+// fragment), as one asm block that also waits for them.  The compiler
+// would put a wait for every copy still in flight into the ring before an
+// LDS read it sees (it cannot tell the stages apart), which undoes the
+// ring; the ring's own counted wait and barrier order these reads.
+template <bool kFp32Frag>
+__device__ __attribute__((always_inline)) inline void ring_read8(uint32_t addr, float2 (&v)[8]) {
+    f32x4 r0, r1, r2, r3;
+    if constexpr (kFp32Frag) {
+        asm volatile(
+            "ds_read2st64_b64 %0, %4 offset0:0 offset1:2\n\t"
+            "ds_read2st64_b64 %1, %4 offset0:4 offset1:6\n\t"
+            "ds_read2st64_b64 %2, %4 offset0:16 offset1:18\n\t"
+            "ds_read2st64_b64 %3, %4 offset0:20 offset1:22\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+            : "v"(addr)
+            : "memory");
+    } else {
+        asm volatile(
+            "ds_read2st64_b64 %0, %4 offset0:0 offset1:2\n\t"
+            "ds_read2st64_b64 %1, %4 offset0:4 offset1:6\n\t"
+            "ds_read2st64_b64 %2, %4 offset0:8 offset1:10\n\t"
+            "ds_read2st64_b64 %3, %4 offset0:12 offset1:14\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+            : "v"(addr)
+            : "memory");
+    }
+    v[0] = make_float2(r0.x, r0.y);
+    v[1] = make_float2(r0.z, r0.w);
+    v[2] = make_float2(r1.x, r1.y);
+    v[3] = make_float2(r1.z, r1.w);
+    v[4] = make_float2(r2.x, r2.y);
+    v[5] = make_float2(r2.z, r2.w);
+    v[6] = make_float2(r3.x, r3.y);
+    v[7] = make_float2(r3.z, r3.w);
+}
+
 template <int MODE, int KPAD>
-__device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, char *lds) {
+__device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, char *lds,
+                                                                  char *la) {
     constexpr int kE = MODE == QCE_MODE_FP32 ? 4 : 2;
     const int kpad = (int)round_up(g.k, kKPad);
     const int rb = sk_row_bytes(kpad, kE);
@@ -785,19 +826,81 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
         shB = g.st->shift[1];
     }
 
-    // op(B) -> LDS planes (zeros beyond n and k)
-    for (int e = threadIdx.x; e < kSkCols * kpad; e += kThreads) {
-        int j, kk;
-        if (g.b_kcontig) {
-            kk = e % kpad;
-            j = e / kpad;
-        } else {
-            j = e % kSkCols;
-            kk = e / kSkCols;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, l32 = lane & 31, hi = lane >> 5;
+    const int64_t ntiles = (g.m + kSkRows - 1) / kSkRows;
+
+    // Full row tiles of a rows-contiguous op(A) (k <= 64) stream through a
+    // ring of kSkRing LDS stages of one chunk each (16 k-values x 128 rows,
+    // 16 KB), filled by direct buffer loads (no registers held) kSkRing - 1
+    // chunks ahead across tile boundaries.  Workgroup b takes a run of
+    // consecutive full tiles (b * (nfull / G) + min(b, nfull % G) on), so
+    // that the tiles in flight at once lie spread over all of op(A) and C:
+    // the rows of one chunk are lda apart, and neighbouring tiles in flight
+    // together would put every access of the device into a few HBM
+    // channels when lda is a large power of two.  Chunk s of the
+    // workgroup is chunk s % nchunks of its (s / nchunks)-th tile.  The
+    // first chunks are issued before op(B) is read, so both are in flight
+    // at once.
+    const bool ring = KPAD == 64 && g.a_stage;
+    const int64_t nfull = g.m / kSkRows;
+    const int64_t G = gridDim.x;
+    const int64_t per = nfull / G, rem = nfull % G;
+    const int64_t mine = ring ? per + (blockIdx.x < rem ? 1 : 0) : 0;
+    const int64_t first_tile = blockIdx.x * per + min((int64_t)blockIdx.x, rem);
+    const int64_t S = mine * nchunks;
+    const int wsc = __builtin_amdgcn_readfirstlane(w);
+    const uint32_t voff = (uint32_t)(16 * lane + wsc * g.lda * 8);
+    const uint32_t extent = (uint32_t)((15 * g.lda + kSkRows) * 8);
+    // the next chunk to copy: chunk ic of row tile it into stage is (all
+    // wave-uniform, advanced by counting: no divisions in the loop)
+    int ic = 0, is = 0;
+    int64_t it = first_tile, issued = 0;
+    auto issue_next = [&]() {
+        // rows it*128 .. +127 of k-values 16ic .. 16ic+15: thread (w, lane),
+        // copy q moves rows 2 lane, 2 lane + 1 of k-value 16ic + 4q + w
+        // (the address is wave-uniform: read it from the first lane, so the
+        // descriptor is built in scalar registers)
+        const uint64_t a64 = reinterpret_cast<uint64_t>(g.A + it * kSkRows + (int64_t)(16 * ic) * g.lda);
+        const uint64_t ua = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a64 >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a64);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(ua), (short)0, extent, kRsrcWord3);
+        char *stage = la + is * kSkChunkBytes;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, LDS_PTR(stage + (256 * q + 64 * wsc) * 16), 16, voff,
+                                                     (uint32_t)(4 * q * g.lda * 8), 0, 0);
+        if (++ic == nchunks) {
+            ic = 0;
+            ++it;
         }
+        if (++is == kSkRing) is = 0;
+        ++issued;
+    };
+    while (issued < S && issued < kSkRing - 1) issue_next();
+
+    // op(B) -> LDS planes (zeros beyond n and k): every load of a thread is
+    // issued (from a clamped, valid address) before any value is used
+    constexpr int kBPer = kSkCols * KPAD / kThreads;
+    float2 bv[kBPer];
+#pragma unroll
+    for (int q = 0; q < kBPer; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        const int kk = g.b_kcontig ? e % kpad : e / kSkCols;
+        const int j = g.b_kcontig ? e / kpad : e % kSkCols;
+        const bool ok = e < kSkCols * kpad && j < g.n && kk < g.k;
+        const int64_t idx = !ok ? 0 : g.b_kcontig ? kk + (int64_t)j * g.ldb : j + (int64_t)kk * g.ldb;
+        bv[q] = g.B[idx];
+    }
+#pragma unroll
+    for (int q = 0; q < kBPer; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        if (e >= kSkCols * kpad) break;
+        const int kk = g.b_kcontig ? e % kpad : e / kSkCols;
+        const int j = g.b_kcontig ? e / kpad : e % kSkCols;
         float2 v = make_float2(0.f, 0.f);
         if (j < g.n && kk < g.k) {
-            v = g.b_kcontig ? g.B[kk + j * g.ldb] : g.B[j + kk * g.ldb];
+            v = bv[q];
             if (g.b_conj) v.y = -v.y;  // (padding stays +0)
         }
         char *row = lds + j * rb;
@@ -820,9 +923,7 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     }
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, l32 = lane & 31, hi = lane >> 5;
     const int nbk = g.n > 32 ? 2 : 1;
-    const int64_t ntiles = (g.m + kSkRows - 1) / kSkRows;
     Acc<MODE> acc;
     auto zero_acc = [&]() {
         floatx16 zf;
@@ -910,6 +1011,32 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     auto epilogue = [&](int64_t i, bool row_ok) {
     const int shift_total = shA + shB;
     const bool alpha_one = g.alpha.x == 1.f && g.alpha.y == 0.f;
+    // the common case (C = A B, every column of the block in range, no
+    // shift) in a branch of its own: per output the combination and a store
+    if (alpha_one && g.beta_zero && shift_total == 0 && row_ok && g.n == nbk * 32) {
+        float2 *cp = g.C + i + (int64_t)(4 * hi) * g.ldc;
+#pragma unroll
+        for (int ub = 0; ub < 2; ++ub) {
+            if (ub >= nbk) break;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = ub * 32 + 8 * (r >> 2) + (r & 3);
+                float re, im;
+                if constexpr (MODE == QCE_MODE_FP16X2) {
+                    re = acc.re_m[ub][0][r] + acc.re_c[ub][0][r] * (1.0f / 2048.0f);
+                    im = acc.im_m[ub][0][r] + acc.im_c[ub][0][r] * (1.0f / 2048.0f);
+                } else if constexpr (MODE == QCE_MODE_BF16X3) {
+                    re = acc.re_m[ub][0][r] + acc.re_c[ub][0][r];
+                    im = acc.im_m[ub][0][r] + acc.im_c[ub][0][r];
+                } else {
+                    re = acc.re_m[ub][0][r] - acc.re_n[ub][0][r];
+                    im = acc.im_m[ub][0][r];
+                }
+                cp[(int64_t)j * g.ldc] = make_float2(re, im);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int ub = 0; ub < 2; ++ub) {
         if (ub >= nbk) break;
@@ -945,62 +1072,45 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     }
     };
 
-    int64_t first_reg_tile = blockIdx.x;  // first tile of the register path below
-    char *la = lds + sk_lds_bytes(KPAD);  // the op(A) ring (k <= 64 kernel only)
-    if (KPAD == 64 && g.a_stage) {
-        // Full row tiles of a rows-contiguous op(A) (k <= 64) stream through a
-        // ring of kSkRing LDS stages of one chunk each (16 k-values x 128
-        // rows, 16 KB), filled by direct buffer loads (no registers held)
-        // kSkRing - 1 chunks ahead across tile boundaries.  Chunk s of this
-        // workgroup is chunk s % nchunks of its (s / nchunks)-th full tile.
-        const int64_t nfull = g.m / kSkRows;
-        const int64_t G = gridDim.x;
-        const int64_t mine = blockIdx.x < nfull ? (nfull - 1 - blockIdx.x) / G + 1 : 0;
-        const int64_t S = mine * nchunks;
-        first_reg_tile = blockIdx.x + mine * G;
-        const int wsc = __builtin_amdgcn_readfirstlane(w);
-        const uint32_t voff = (uint32_t)(16 * lane + wsc * g.lda * 8);
-        auto issue = [&](int64_t sidx) {
-            const int64_t t = blockIdx.x + (sidx / nchunks) * G;
-            const int c = (int)(sidx % nchunks);
-            // rows t*128 .. +127 of k-values 16c .. 16c+15: thread (w, lane),
-            // copy q moves rows 2 lane, 2 lane + 1 of k-value 16c + 4q + w
-            const char *base = reinterpret_cast<const char *>(g.A + t * kSkRows + (int64_t)(16 * c) * g.lda);
-            const uint32_t extent = (uint32_t)((15 * g.lda + kSkRows) * 8);
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, extent, kRsrcWord3);
-            char *stage = la + (int)(sidx % kSkRing) * kSkChunkBytes;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, LDS_PTR(stage + (256 * q + 64 * wsc) * 16), 16, voff,
-                                                         (uint32_t)(4 * q * g.lda * 8), 0, 0);
-        };
-        for (int64_t sidx = 0; sidx < S && sidx < kSkRing - 1; ++sidx) issue(sidx);
+    // the register path below takes the tiles the ring does not (with the
+    // ring: the partial tile after the full ones)
+    const int64_t first_reg_tile = ring ? nfull + blockIdx.x : blockIdx.x;
+    if (ring) {
+        // LDS byte address of this lane's first value in stage 0 (the
+        // fragment's first k-value kval(c, 0) - 16 c, then its row)
+        const uint32_t ring_base =
+            (uint32_t)(uintptr_t)LDS_PTR(la) + (uint32_t)(((kval(0, 0)) * kSkRows + w * 32 + l32) * 8);
+        // chunk c of row tile t sits in stage cs
+        int c = 0, cs = 0;
+        int64_t t = first_tile;
         for (int64_t sidx = 0; sidx < S; ++sidx) {
             // chunk sidx has landed once at most the copies issued after it
             // are outstanding (vector memory operations retire in order; the
             // epilogue's stores only make the wait longer)
-            const int64_t after = min((int64_t)(kSkRing - 2), S - 1 - sidx);
+            static_assert(kSkRing == 4, "the waits below assume up to two chunks in flight after this one");
+            const int64_t after = issued - 1 - sidx;
             if (after >= 2) wait_vmcnt<8>();
             else if (after == 1) wait_vmcnt<4>();
             else wait_vmcnt<0>();
             __syncthreads();  // every wave's copies of chunk sidx, and every wave done with chunk sidx - 1
-            const int c = (int)(sidx % nchunks);
-            const float2 *st2 = reinterpret_cast<const float2 *>(la + (int)(sidx % kSkRing) * kSkChunkBytes);
+            // this lane's values: k-value kval(c, u) - 16 c of the chunk
+            // (1 KB apart), row w * 32 + l32
             float2 cur[8];
+            const uint32_t ra = ring_base + (uint32_t)(cs * kSkChunkBytes);
+            ring_read8<MODE == QCE_MODE_FP32>(ra, cur);
+            if (g.a_conj) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                float2 x = st2[(kval(c, u) - 16 * c) * kSkRows + w * 32 + l32];
-                if (g.a_conj) x.y = -x.y;
-                cur[u] = x;
+                for (int u = 0; u < 8; ++u) cur[u].y = -cur[u].y;
             }
-            if (sidx + kSkRing - 1 < S) issue(sidx + kSkRing - 1);  // into chunk sidx - 1's stage
+            if (issued < S) issue_next();  // into chunk sidx - 1's stage
             if (c == 0) zero_acc();
             mma_chunk(cur, c);
-            if (c == nchunks - 1) {
-                const int64_t t = blockIdx.x + (sidx / nchunks) * G;
-                epilogue(t * kSkRows + w * 32 + l32, true);
+            if (c == nchunks - 1) epilogue(t * kSkRows + w * 32 + l32, true);
+            if (++c == nchunks) {
+                c = 0;
+                ++t;
             }
+            if (++cs == kSkRing) cs = 0;
         }
     }
     // the workgroup walks (its remaining) row tiles with op(B) kept in LDS,
@@ -1008,16 +1118,19 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     for (int64_t tile = first_reg_tile; tile < ntiles; tile += gridDim.x) {
         const int64_t i = tile * kSkRows + w * 32 + l32;
         const bool row_ok = i < g.m;
+        // the 8 loads are issued (from clamped, valid addresses) before any
+        // value is used
         auto load = [&](float2 *v, int c) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int kk = kval(c, u);
-                float2 x = make_float2(0.f, 0.f);
-                if (row_ok && kk < g.k) {
-                    x = g.a_kcontig ? g.A[kk + i * g.lda] : g.A[i + (int64_t)kk * g.lda];
-                    if (g.a_conj) x.y = -x.y;
-                }
-                v[u] = x;
+                const bool ok = row_ok && kk < g.k;
+                v[u] = g.A[!ok ? 0 : g.a_kcontig ? kk + i * g.lda : i + (int64_t)kk * g.lda];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (!(row_ok && kval(c, u) < g.k)) v[u] = make_float2(0.f, 0.f);
+                else if (g.a_conj) v[u].y = -v[u].y;
             }
         };
         zero_acc();
@@ -1035,7 +1148,10 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
 
 template <int KPAD>
 __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
-    __shared__ __attribute__((aligned(16))) char lds[sk_lds_bytes(KPAD) + (KPAD == 64 ? kSkStageBytes : 0)];
+    // op(B)'s planes and the op(A) ring (k <= 64 kernel only) in LDS
+    // arrays of their own
+    __shared__ __attribute__((aligned(16))) char lds[sk_lds_bytes(KPAD)];
+    __shared__ __attribute__((aligned(16))) char ring[KPAD == 64 ? kSkStageBytes : 16];
     const int64_t z = blockIdx.z;
     g.A += z * g.bsA;
     g.B += z * g.bsB;
@@ -1043,11 +1159,11 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
     if (g.st) g.st += z;
     const int mode = g.forced_mode >= 0 ? g.forced_mode : g.st->mode;
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
-        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, lds);
+        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, lds, ring);
     else if (mode == QCE_MODE_BF16X3)
-        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, lds);
+        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, lds, ring);
     else
-        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, lds);
+        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, lds, ring);
 }
 
 }  // namespace

@@ -76,13 +76,15 @@ __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, 
         if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
             const int64_t n4 = nf >> 2;
             const float4 *p4 = reinterpret_cast<const float4 *>(p);
+            // kBatch 16-byte loads in flight per lane before any is binned
+            constexpr int kBatch = 16;
             int64_t i = tid;
-            for (; i + 7 * nthr < n4; i += 8 * nthr) {
-                float4 v[8];
+            for (; i + (kBatch - 1) * nthr < n4; i += kBatch * nthr) {
+                float4 v[kBatch];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = p4[i + u * nthr];
+                for (int u = 0; u < kBatch; ++u) v[u] = p4[i + u * nthr];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kBatch; ++u) {
                     f(v[u].x); f(v[u].y); f(v[u].z); f(v[u].w);
                 }
             }
@@ -208,78 +210,143 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
             r.nonfinite = bins[kBinNonfinite];
             r.maxbin = mb;
         }
-        if (lane < kRelBins) {
-            // cumulative count of bins mb - lane .. mb
-            unsigned int c = 0;
-            for (int d = 0; d <= lane; ++d) c += mb - d >= 0 ? bins[mb - d] : 0u;
-            r.cum[lane] = c;
+        // cumulative count of bins mb - d .. mb for d = lane < 32: lane d
+        // holds bin mb - d, then an inclusive scan over the 32 lanes
+        static_assert(kRelBins == 32, "one lane per cumulative entry in the low half of the wave");
+        unsigned int c = (lane < kRelBins && mb - lane >= 0) ? bins[mb - lane] : 0u;
+#pragma unroll
+        for (int o = 1; o < kRelBins; o <<= 1) {
+            const unsigned int up = __shfl_up(c, o, kRelBins);
+            if ((lane & (kRelBins - 1)) >= o) c += up;
         }
+        if (lane < kRelBins) r.cum[lane] = c;
     }
 }
 
 // The decision of batch entry z from its blocks' records (one block of 256
 // threads, launched after the statistics launch: the kernel boundary makes
 // every record visible, with no device-wide fence in the statistics blocks).
+// Thread t takes records t, t + 256, ... of both operands; each pass issues
+// the loads of kSelUnroll records before using any (the records come from
+// other XCDs' writes, so every round trip is long).
+constexpr int kSelUnroll = 4;
 __device__ inline void select_body(const StatsArgs &g, int z) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int total = g.blocks_a + g.blocks_b;
     const StatsRecord *rec = g.rec + (int64_t)z * total;
-    // both operands' statistics from the records, 128 threads
-    // per operand (threads 0-127: A, 128-255: B), each over every 128th
-    // record; integer sums, so the order does not matter
-    __shared__ unsigned long long red[kWaves][5];
-    __shared__ int redmax[kWaves];
-    const int opd = threadIdx.x >> 7, t = threadIdx.x & 127;
-    const int r0 = opd == 0 ? 0 : g.blocks_a, nr = opd == 0 ? g.blocks_a : g.blocks_b;
-    unsigned long long nnz = 0, n1 = 0, n3 = 0, nf = 0;
-    int mb = -1;
-    for (int i = t; i < nr; i += 128) {
-        const uint4 c = *reinterpret_cast<const uint4 *>(&rec[r0 + i].nnz);
-        nnz += c.x;
-        n1 += c.y;
-        n3 += c.z;
-        nf += c.w;
-        mb = max(mb, rec[r0 + i].maxbin);
+    __shared__ unsigned long long red[kWaves][2][5];
+    __shared__ int redmax[kWaves][2];
+    // pass 1: counts and largest bin of each operand (integer sums: the
+    // order does not matter); the first pass's largest bins stay in
+    // registers for pass 2
+    unsigned long long acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int mb[2] = {-1, -1};
+    int keep[kSelUnroll];
+    for (int base = threadIdx.x; base < total; base += kSelUnroll * kThreads) {
+        uint4 c[kSelUnroll];
+        int m[kSelUnroll];
+        // loads from clamped indices (no branch between them), masked after
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int i = min(base + u * kThreads, total - 1);
+            c[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
+            m[u] = rec[i].maxbin;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            if (base + u * kThreads >= total) {
+                c[u] = make_uint4(0, 0, 0, 0);
+                m[u] = -1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int o = base + u * kThreads < g.blocks_a ? 0 : 1;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (o != q) continue;
+                acc[q][0] += c[u].x;
+                acc[q][1] += c[u].y;
+                acc[q][2] += c[u].z;
+                acc[q][3] += c[u].w;
+                mb[q] = max(mb[q], m[u]);
+            }
+            if (base == (int)threadIdx.x) keep[u] = m[u];
+        }
     }
-    nnz = wave_sum64(nnz);
-    n1 = wave_sum64(n1);
-    n3 = wave_sum64(n3);
-    nf = wave_sum64(nf);
-    mb = wave_max(mb);
-    if (lane == 0) {
-        red[w][0] = nnz;
-        red[w][1] = n1;
-        red[w][2] = n3;
-        red[w][3] = nf;
-        redmax[w] = mb;
-    }
-    __syncthreads();
-    // the operand's largest bin (its two waves), then stage 2: the part of
-    // each block's top bins inside [gmax - 28, gmax], one cumulative entry
-    const int gmax = max(redmax[2 * opd], redmax[2 * opd + 1]);
-    unsigned long long n2 = 0;
-    for (int i = t; i < nr; i += 128) {
-        const int bm = rec[r0 + i].maxbin;
-        const int top = kWindowSpan - (gmax - bm);  // highest d inside the window (<= 28)
-        if (bm >= 0 && top >= 0) n2 += rec[r0 + i].cum[top];
-    }
-    n2 = wave_sum64(n2);
-    __syncthreads();
-    if (lane == 0) red[w][4] = n2;
-    __syncthreads();
-    OperandStats s[2];
-    int emaxbin[2];
+#pragma unroll
     for (int q = 0; q < 2; ++q) {
-        s[q].nnz = red[2 * q][0] + red[2 * q + 1][0];
-        s[q].n1 = red[2 * q][1] + red[2 * q + 1][1];
-        s[q].n3 = red[2 * q][2] + red[2 * q + 1][2];
-        s[q].nonfinite = red[2 * q][3] + red[2 * q + 1][3];
-        s[q].n2 = red[2 * q][4] + red[2 * q + 1][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[q][j] = wave_sum64(acc[q][j]);
+        mb[q] = wave_max(mb[q]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[w][q][j] = acc[q][j];
+            redmax[w][q] = mb[q];
+        }
+    }
+    __syncthreads();
+    int emaxbin[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        int gm = -1;
+        for (int v = 0; v < kWaves; ++v) gm = max(gm, redmax[v][q]);
+        emaxbin[q] = gm;
+    }
+    // pass 2 (stage 2): the part of each block's top bins inside
+    // [gmax - 28, gmax] of its operand, one cumulative entry per record
+    unsigned long long n2[2] = {0, 0};
+    for (int base = threadIdx.x; base < total; base += kSelUnroll * kThreads) {
+        int m[kSelUnroll];
+        if (base == (int)threadIdx.x) {
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u) m[u] = keep[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u) m[u] = rec[min(base + u * kThreads, total - 1)].maxbin;
+        }
+        unsigned int cv[kSelUnroll];
+        bool use[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int i = base + u * kThreads;
+            const int gmax = i < g.blocks_a ? emaxbin[0] : emaxbin[1];
+            const int top = kWindowSpan - (gmax - m[u]);  // highest d inside the window (<= 28)
+            use[u] = i < total && m[u] >= 0 && top >= 0;
+            cv[u] = rec[min(i, total - 1)].cum[min(max(top, 0), kRelBins - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) cv[u] = use[u] ? cv[u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            if (base + u * kThreads < g.blocks_a) n2[0] += cv[u];
+            else n2[1] += cv[u];
+        }
+    }
+    n2[0] = wave_sum64(n2[0]);
+    n2[1] = wave_sum64(n2[1]);
+    if (lane == 0) {
+        red[w][0][4] = n2[0];
+        red[w][1][4] = n2[1];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    OperandStats s[2];
+    for (int q = 0; q < 2; ++q) {
+        unsigned long long v[5] = {0, 0, 0, 0, 0};
+        for (int x = 0; x < kWaves; ++x)
+            for (int j = 0; j < 5; ++j) v[j] += red[x][q][j];
+        s[q].nnz = v[0];
+        s[q].n1 = v[1];
+        s[q].n3 = v[2];
+        s[q].nonfinite = v[3];
+        s[q].n2 = v[4];
         s[q].maxbits = 0;
         s[q].pad = 0;
-        emaxbin[q] = max(redmax[2 * q], redmax[2 * q + 1]);
     }
-    if (threadIdx.x != 0) return;
     DevState *st = g.st + z;
     int level[2], emax[2];
     for (int o = 0; o < 2; ++o) {
@@ -371,6 +438,52 @@ int64_t blocks_strided(int64_t rows, int64_t cols) {
     const int64_t cols_per_block = std::max<int64_t>(1, kMaxPerLane / per_col);
     return std::max(blocks_base(2 * rows * cols), (cols + cols_per_block - 1) / cols_per_block);
 }
+// the fewest blocks that keep every lane's count of d below kMaxPerLane
+int64_t blocks_min(const MatDesc &d) {
+    if (d.rows <= 0 || d.cols <= 0) return 0;
+    if (d.ld == d.rows || d.cols == 1) {
+        const int64_t nf = 2 * d.rows * d.cols;
+        return std::max<int64_t>(1, (nf + kThreads * (kMaxPerLane - 8) - 1) / (kThreads * (kMaxPerLane - 8)));
+    }
+    const int64_t per_col = 2 * ((d.rows + kThreads - 1) / kThreads);
+    const int64_t cols_per_block = std::max<int64_t>(1, kMaxPerLane / per_col);
+    return (d.cols + cols_per_block - 1) / cols_per_block;
+}
+
+// statistics blocks the device holds at once (0 if it cannot be queried)
+int stats_slots() {
+    static int slots = -1;
+    if (slots < 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stats_kernel, kThreads, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        slots = cus * std::max(per, 1);
+    }
+    return slots;
+}
+
+// A GEMM's pair of operands whose blocks exceed a whole number of rounds of
+// resident blocks by a few would leave those few to run alone after the
+// rest (e.g. 512 blocks of a 65536 x 64 operand and 1 of its 64 x 64
+// partner on 512 slots): trim both counts in proportion, never below what
+// the 16-bit counters need, so that the pair fills whole rounds.
+void fit_pair(const MatDesc &a, const MatDesc &b, int &ba, int &bb) {
+    const int slots = stats_slots();
+    const int total = ba + bb;
+    if (slots <= 0 || total <= slots || total % slots == 0) return;
+    const int target = total / slots * slots;
+    const int na = (int)blocks_min(a), nb = (int)blocks_min(b);
+    int fa = ba ? std::max<int>(na, (int)((int64_t)ba * target / total)) : 0;
+    fa = std::min(fa, ba);
+    int fb = bb ? std::max<int>(nb, std::min(bb, target - fa)) : 0;
+    fb = std::min(fb, bb);
+    ba = fa;
+    bb = fb;
+}
 }  // namespace
 
 int stats_blocks(const MatDesc &d) {
@@ -440,6 +553,7 @@ hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsR
     g.b = b;
     g.blocks_a = stats_blocks(a);
     g.blocks_b = stats_blocks(b);
+    if (batch <= 1) fit_pair(a, b, g.blocks_a, g.blocks_b);
     g.st = st;
     g.rec = rec;
     g.t = t;
