@@ -548,12 +548,15 @@ qce_status cgemm_core(qce_handle *h, int mode, const OperandView &a, const Opera
         q.bsC = bt.sc;
         const bool stats = mode == QCE_MODE_AUTO || mode == QCE_MODE_FP16X2_SCALED;
         if (stats) {
+            // the statistics launch only: every workgroup of the short-k
+            // kernel takes the decision from the records itself
             hipEvent_t e0 = span_begin(h);
             QCE_HIP(h, launch_stats(da, db, dst, rec, h->t, h->t3, mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED,
-                                    log, slot, s, nb));
+                                    log, slot, s, nb, false, &q.sel));
             span_end(h, e0, QCE_PHASE_STATS);
-            q.st = dst;
-            q.forced_mode = mode == QCE_MODE_AUTO ? -1 : QCE_MODE_FP16X2_SCALED;
+            q.st = nullptr;
+            q.select_here = 1;
+            q.forced_mode = -1;
         } else {
             q.st = nullptr;
             q.forced_mode = mode;

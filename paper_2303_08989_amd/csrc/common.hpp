@@ -22,7 +22,7 @@ struct OperandStats {
     unsigned int pad;
 };
 
-constexpr int kMaxStatsBlocks = 4096;  // per operand
+constexpr int kMaxStatsBlocks = 16384;  // per operand
 constexpr int kRelBins = 32;            // exponent bins a block record keeps below its maximum
 
 // One statistics block's summary of its share of one operand (exact counts
@@ -159,8 +159,11 @@ int stats_blocks(const MatDesc &d);
 // operand stored either way (rows x cols or cols x rows)
 int stats_blocks_bound(int64_t rows, int64_t cols);
 size_t stats_record_bytes(const MatDesc &a, const MatDesc &b, int batch = 1);
+// with_select = false: the statistics launch only, its arguments in
+// *args_out (nullable) for a consumer that selects in its own prologue
 hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec, double t, double t3,
-                        int forced_mode, int *mode_log, int slot, hipStream_t s, int batch = 1);
+                        int forced_mode, int *mode_log, int slot, hipStream_t s, int batch = 1,
+                        bool with_select = true, StatsArgs *args_out = nullptr);
 
 // Split a rows x k operand view into panels: P[r][l] = x[l + r*ldx] if
 // kcontig else x[r + l*ldx], imaginary part negated if conj.  st != nullptr:
@@ -265,6 +268,11 @@ struct SmallKArgs {
     int batch;
     int64_t bsA, bsB, bsC;
     int a_stage;  // set by launch_smallk: full row tiles of op(A) copied to LDS directly
+    // select_here: every workgroup takes the mode decision from the
+    // statistics records of `sel` itself (workgroup 0 of each batch entry
+    // publishes it to sel.st), in place of a selection launch
+    int select_here;
+    StatsArgs sel;
 };
 bool smallk_shape(int64_t m, int64_t n, int64_t k);
 hipError_t launch_smallk(const SmallKArgs &g, hipStream_t s);

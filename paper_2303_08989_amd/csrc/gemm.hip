@@ -34,6 +34,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "select.hpp"
 #include "split_math.hpp"
 
 namespace qce {
@@ -45,6 +46,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
 
@@ -813,18 +815,13 @@ __device__ __attribute__((always_inline)) inline void ring_read8(uint32_t addr, 
 }
 
 template <int MODE, int KPAD>
-__device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, char *lds,
-                                                                  char *la) {
+__device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, int shA, int shB,
+                                                                  char *lds, char *la) {
     constexpr int kE = MODE == QCE_MODE_FP32 ? 4 : 2;
     const int kpad = (int)round_up(g.k, kKPad);
     const int rb = sk_row_bytes(kpad, kE);
     const int pb = kSkCols * rb;
     const int nchunks = kpad / kKPad;
-    int shA = 0, shB = 0;
-    if (MODE == QCE_MODE_FP16X2 && mode == QCE_MODE_FP16X2_SCALED && g.st) {
-        shA = g.st->shift[0];
-        shB = g.st->shift[1];
-    }
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, l32 = lane & 31, hi = lane >> 5;
     const int64_t ntiles = (g.m + kSkRows - 1) / kSkRows;
@@ -880,24 +877,32 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     while (issued < S && issued < kSkRing - 1) issue_next();
 
     // op(B) -> LDS planes (zeros beyond n and k): every load of a thread is
-    // issued (from a clamped, valid address) before any value is used
+    // issued (from a clamped, valid address) before any value is used.
+    // Element q of a thread is (row j, k-value kk) of a 64 x KPAD index
+    // space (k-values inner when op(B) is k-contiguous, so that lanes read
+    // consecutive addresses), with compile-time shifts only; k-values from
+    // kpad on are not stored.
+    static_assert((KPAD & (KPAD - 1)) == 0 && kSkCols == 64, "power-of-two index space");
     constexpr int kBPer = kSkCols * KPAD / kThreads;
+    auto b_elem = [&](int q, int &j, int &kk) {
+        const unsigned e = threadIdx.x + (unsigned)(q * kThreads);
+        kk = (int)(g.b_kcontig ? (e & (KPAD - 1)) : (e >> 6));
+        j = (int)(g.b_kcontig ? (e / KPAD) : (e & 63));
+    };
     float2 bv[kBPer];
 #pragma unroll
     for (int q = 0; q < kBPer; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        const int kk = g.b_kcontig ? e % kpad : e / kSkCols;
-        const int j = g.b_kcontig ? e / kpad : e % kSkCols;
-        const bool ok = e < kSkCols * kpad && j < g.n && kk < g.k;
+        int j, kk;
+        b_elem(q, j, kk);
+        const bool ok = j < g.n && kk < g.k;
         const int64_t idx = !ok ? 0 : g.b_kcontig ? kk + (int64_t)j * g.ldb : j + (int64_t)kk * g.ldb;
         bv[q] = g.B[idx];
     }
 #pragma unroll
     for (int q = 0; q < kBPer; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        if (e >= kSkCols * kpad) break;
-        const int kk = g.b_kcontig ? e % kpad : e / kSkCols;
-        const int j = g.b_kcontig ? e / kpad : e % kSkCols;
+        int j, kk;
+        b_elem(q, j, kk);
+        if (kk >= kpad) continue;
         float2 v = make_float2(0.f, 0.f);
         if (j < g.n && kk < g.k) {
             v = bv[q];
@@ -1032,7 +1037,10 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
                     re = acc.re_m[ub][0][r] - acc.re_n[ub][0][r];
                     im = acc.im_m[ub][0][r];
                 }
-                cp[(int64_t)j * g.ldc] = make_float2(re, im);
+                // streamed out (C is not read again here), so the lines do not
+                // wait in L2 for the end-of-kernel write-back
+                const f32x2 val = {re, im};
+                __builtin_nontemporal_store(val, reinterpret_cast<f32x2 *>(cp + (int64_t)j * g.ldc));
             }
         }
         return;
@@ -1157,13 +1165,25 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
     g.B += z * g.bsB;
     g.C += z * g.bsC;
     if (g.st) g.st += z;
-    const int mode = g.forced_mode >= 0 ? g.forced_mode : g.st->mode;
+    int mode, shA = 0, shB = 0;
+    if (g.select_here) {
+        const SelectDecision d = select_block(g.sel, (int)z, blockIdx.x == 0);
+        mode = d.mode;
+        shA = d.shift[0];
+        shB = d.shift[1];
+    } else {
+        mode = g.forced_mode >= 0 ? g.forced_mode : g.st->mode;
+        if (mode == QCE_MODE_FP16X2_SCALED && g.st) {
+            shA = g.st->shift[0];
+            shB = g.st->shift[1];
+        }
+    }
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
-        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, lds, ring);
+        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, shA, shB, lds, ring);
     else if (mode == QCE_MODE_BF16X3)
-        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, lds, ring);
+        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, 0, 0, lds, ring);
     else
-        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, lds, ring);
+        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, 0, 0, lds, ring);
 }
 
 }  // namespace
@@ -1340,7 +1360,9 @@ bool smallk_shape(int64_t m, int64_t n, int64_t k) {
 
 hipError_t launch_smallk(const SmallKArgs &g, hipStream_t s) {
     if (!smallk_shape(g.m, g.n, g.k)) return hipErrorInvalidValue;
-    if (g.forced_mode < 0 && !g.st) return hipErrorInvalidValue;
+    if (g.forced_mode < 0 && !g.st && !g.select_here) return hipErrorInvalidValue;
+    if (g.select_here && (!g.sel.st || !g.sel.rec || g.sel.blocks_a + g.sel.blocks_b <= 0))
+        return hipErrorInvalidValue;
     const int batch = std::max(1, g.batch);
     // at most as many workgroups as fit on the device at once: op(B) is
     // split into LDS once per workgroup and reused for every row tile it

@@ -1,0 +1,214 @@
+// Mode selection from the exponent-statistics records (Sec. 4.1 and 4.2):
+// one block of 256 threads adds up a GEMM's per-block records and applies
+// the tolerance rule.  Used by the selection launch that follows the
+// statistics, and by consumer kernels that take the decision in their own
+// prologue (every block of such a kernel reaches the same decision from
+// the same integer counts; one block publishes it).
+#pragma once
+
+#include "common.hpp"
+
+namespace qce {
+namespace {
+namespace selimpl {
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+__device__ inline unsigned long long wave_sum64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+}  // namespace selimpl
+
+// the decision as every thread of the block returns it
+struct SelectDecision {
+    int mode;
+    int shift[2];
+};
+
+// Per-operand tolerance level (Sec. 4.1): FP16 if every element but a
+// fraction t lies in the FP16 window without shifting (and e_max <= 14: no
+// overflow); FP16 with scaling if the window shifted to e_max holds all but
+// a fraction t; BF16X3 if all but a fraction t3 lie above its floor and
+// e_max <= 126; else FP32.  Non-finite data -> FP32.
+__device__ inline int operand_level(const OperandStats &s, int emax, double t, double t3) {
+    if (s.nonfinite) return QCE_MODE_FP32;
+    if (s.nnz == 0) return QCE_MODE_FP16X2;
+    const double nnz = (double)s.nnz;
+    if (emax <= kFp16Emax && (double)(s.nnz - s.n1) <= t * nnz) return QCE_MODE_FP16X2;
+    if ((double)(s.nnz - s.n2) <= t * nnz) return QCE_MODE_FP16X2_SCALED;
+    if (emax <= kBf16x3Emax && (double)(s.nnz - s.n3) <= t3 * nnz) return QCE_MODE_BF16X3;
+    return QCE_MODE_FP32;
+}
+
+// The decision of batch entry z from its blocks' records (one block of 256
+// threads, launched after the statistics launch: the kernel boundary makes
+// every record visible, with no device-wide fence in the statistics blocks).
+// Thread t takes records t, t + 256, ... of both operands; each pass issues
+// the loads of kSelUnroll records before using any (the records come from
+// other XCDs' writes, so every round trip is long).
+constexpr int kSelUnroll = 4;
+__device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool publish) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int total = g.blocks_a + g.blocks_b;
+    const StatsRecord *rec = g.rec + (int64_t)z * total;
+    __shared__ unsigned long long red[selimpl::kWaves][2][5];
+    __shared__ int redmax[selimpl::kWaves][2];
+    // pass 1: counts and largest bin of each operand (integer sums: the
+    // order does not matter); the first pass's largest bins stay in
+    // registers for pass 2
+    unsigned long long acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int mb[2] = {-1, -1};
+    int keep[kSelUnroll];
+    for (int base = threadIdx.x; base < total; base += kSelUnroll * selimpl::kThreads) {
+        uint4 c[kSelUnroll];
+        int m[kSelUnroll];
+        // loads from clamped indices (no branch between them), masked after
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int i = min(base + u * selimpl::kThreads, total - 1);
+            c[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
+            m[u] = rec[i].maxbin;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            if (base + u * selimpl::kThreads >= total) {
+                c[u] = make_uint4(0, 0, 0, 0);
+                m[u] = -1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int o = base + u * selimpl::kThreads < g.blocks_a ? 0 : 1;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (o != q) continue;
+                acc[q][0] += c[u].x;
+                acc[q][1] += c[u].y;
+                acc[q][2] += c[u].z;
+                acc[q][3] += c[u].w;
+                mb[q] = max(mb[q], m[u]);
+            }
+            if (base == (int)threadIdx.x) keep[u] = m[u];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[q][j] = selimpl::wave_sum64(acc[q][j]);
+        mb[q] = selimpl::wave_max(mb[q]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[w][q][j] = acc[q][j];
+            redmax[w][q] = mb[q];
+        }
+    }
+    __syncthreads();
+    int emaxbin[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        int gm = -1;
+        for (int v = 0; v < selimpl::kWaves; ++v) gm = max(gm, redmax[v][q]);
+        emaxbin[q] = gm;
+    }
+    // pass 2 (stage 2): the part of each block's top bins inside
+    // [gmax - 28, gmax] of its operand, one cumulative entry per record
+    unsigned long long n2[2] = {0, 0};
+    for (int base = threadIdx.x; base < total; base += kSelUnroll * selimpl::kThreads) {
+        int m[kSelUnroll];
+        if (base == (int)threadIdx.x) {
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u) m[u] = keep[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u) m[u] = rec[min(base + u * selimpl::kThreads, total - 1)].maxbin;
+        }
+        unsigned int cv[kSelUnroll];
+        bool use[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            const int i = base + u * selimpl::kThreads;
+            const int gmax = i < g.blocks_a ? emaxbin[0] : emaxbin[1];
+            const int top = kWindowSpan - (gmax - m[u]);  // highest d inside the window (<= 28)
+            use[u] = i < total && m[u] >= 0 && top >= 0;
+            cv[u] = rec[min(i, total - 1)].cum[min(max(top, 0), kRelBins - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) cv[u] = use[u] ? cv[u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+            if (base + u * selimpl::kThreads < g.blocks_a) n2[0] += cv[u];
+            else n2[1] += cv[u];
+        }
+    }
+    n2[0] = selimpl::wave_sum64(n2[0]);
+    n2[1] = selimpl::wave_sum64(n2[1]);
+    if (lane == 0) {
+        red[w][0][4] = n2[0];
+        red[w][1][4] = n2[1];
+    }
+    __syncthreads();
+    // thread 0 applies the rule; publish: it also writes the device state
+    // (mode flag, shifts, the record for the host)
+    __shared__ SelectDecision out;
+    if (threadIdx.x == 0) {
+        OperandStats s[2];
+        for (int q = 0; q < 2; ++q) {
+            unsigned long long v[5] = {0, 0, 0, 0, 0};
+            for (int x = 0; x < selimpl::kWaves; ++x)
+                for (int j = 0; j < 5; ++j) v[j] += red[x][q][j];
+            s[q].nnz = v[0];
+            s[q].n1 = v[1];
+            s[q].n3 = v[2];
+            s[q].nonfinite = v[3];
+            s[q].n2 = v[4];
+            s[q].maxbits = 0;
+            s[q].pad = 0;
+        }
+        int level[2], emax[2];
+        for (int o = 0; o < 2; ++o) {
+            emax[o] = s[o].nnz ? emaxbin[o] - 149 : INT32_MIN;
+            level[o] = operand_level(s[o], emax[o], g.t, g.t3);
+        }
+        const int mode = g.forced >= 0 ? g.forced : max(level[0], level[1]);
+        int shv[2] = {0, 0};
+        if (mode == QCE_MODE_FP16X2_SCALED)
+            for (int o = 0; o < 2; ++o) shv[o] = s[o].nnz ? kFp16Emax - emax[o] : 0;
+        out.mode = mode;
+        out.shift[0] = shv[0];
+        out.shift[1] = shv[1];
+        if (publish) {
+            DevState *st = g.st + z;
+            st->mode = mode;
+            st->shift[0] = shv[0];
+            st->shift[1] = shv[1];
+            if (g.mode_log && z == 0) g.mode_log[g.slot] = mode;
+            qce_decision &r = st->last;
+            r.mode = mode;
+            r.sA = shv[0];
+            r.sB = shv[1];
+            r.stats_taken = 1;
+            for (int o = 0; o < 2; ++o) {
+                st->acc[o] = s[o];
+                r.nnz[o] = (int64_t)s[o].nnz;
+                r.n1[o] = (int64_t)s[o].n1;
+                r.n2[o] = (int64_t)s[o].n2;
+                r.n3[o] = (int64_t)s[o].n3;
+                r.nonfinite[o] = (int64_t)s[o].nonfinite;
+                r.emax[o] = emax[o];
+            }
+        }
+    }
+    __syncthreads();
+    return out;
+}
+
+}  // namespace
+}  // namespace qce

@@ -9,8 +9,8 @@
 // e_max is known.
 //
 // stats_kernel: a block bins its share of one operand into a histogram in
-// LDS (each lane pair owns a column of 16-bit counters, so the LDS adds of
-// a half wave hit distinct banks), then writes a record: its nonzero,
+// LDS (lane l of every wave adds into column l % 32 of 16-bit counters, so
+// the LDS adds of a half wave hit distinct banks), then writes a record: its nonzero,
 // stage-1, BF16X3-floor and non-finite counts, its largest exponent bin and
 // the cumulative counts of the 32 bins below it.  select_kernel (the next
 // launch, one block per GEMM) adds up the records -- the stage-2 count of a
@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "select.hpp"
 
 namespace qce {
 
@@ -33,12 +34,12 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kBinZero = 277, kBinNonfinite = 278;
 constexpr int kBins = 279;                 // exponent bins 0..276, zero, non-finite
 constexpr int kWords = (kBins + 1) / 2;    // two 16-bit counters per word
-constexpr int kCols = 32;                  // lanes l and l + 32 share a column
+constexpr int kCols = 32;                  // lanes l and l + 32 of every wave share a column
 constexpr int kBin1 = kFp16Emin + 149;     // stage 1: e >= -14
 constexpr int kBin3 = kBf16x3Emin + 149;   // BF16X3 floor: e >= -110
 // elements one lane may bin before a 16-bit counter of its column could
-// overflow (two lanes per column)
-constexpr int64_t kMaxPerLane = 32000;
+// overflow
+constexpr int64_t kMaxPerLane = 8000;  // eight lanes per column, 16-bit counters
 
 // exact exponent bin of one FP32 component
 __device__ inline int bin_of(float v) {
@@ -51,20 +52,26 @@ __device__ inline int bin_of(float v) {
 }
 
 // The block's LDS histogram: word t (bins 2t, 2t + 1 as 16-bit halves) has
-// kWaves * kCols counters side by side, wave w's lane pair in column
-// w * kCols + lane % 32 (the 32 lanes of a half wave hit distinct banks).
-constexpr int kRow = kWaves * kCols;  // counters per word
+// kCols counters side by side, lane l of every wave in column l % 32 (the
+// 32 lanes of a half wave hit distinct banks; the waves share the columns,
+// which keeps the histogram at 18 KB to clear and add up).
+constexpr int kRow = kCols;  // counters per word
 struct HistCounter {
     unsigned int *col;  // this lane's column (LDS)
-    __device__ inline void operator()(float v) {
+    // on = 0 adds nothing (the masked end of a batch: no branch, so the
+    // compiler cannot sink the batch's loads into one)
+    __device__ inline void operator()(float v, unsigned int on = 1u) {
         const int bin = bin_of(v);
-        __hip_atomic_fetch_add(col + (bin >> 1) * kRow, 1u << ((bin & 1) << 4), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(col + (bin >> 1) * kRow, on << ((bin & 1) << 4), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 };
 
 // Visit every FP32 component of a stored column-major complex matrix; the
-// work is split over `nblk` blocks starting at block index `blk`.
+// work is split over `nblk` blocks starting at block index `blk`.  Every
+// loop issues a batch of loads (from clamped, valid addresses where a
+// batch runs past the end) before binning any of them, so a lane never
+// waits for one load at a time.
 template <class F>
 __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, F &f) {
     if (d.rows <= 0 || d.cols <= 0) return;
@@ -74,10 +81,11 @@ __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, 
         const float *p = reinterpret_cast<const float *>(d.ptr);
         const int64_t nf = 2 * d.rows * d.cols;
         if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+            // kBatch 16-byte loads in flight per lane before any is binned;
+            // the rest in masked batches of kRest
+            constexpr int kBatch = 16, kRest = 8;
             const int64_t n4 = nf >> 2;
             const float4 *p4 = reinterpret_cast<const float4 *>(p);
-            // kBatch 16-byte loads in flight per lane before any is binned
-            constexpr int kBatch = 16;
             int64_t i = tid;
             for (; i + (kBatch - 1) * nthr < n4; i += kBatch * nthr) {
                 float4 v[kBatch];
@@ -88,62 +96,116 @@ __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, 
                     f(v[u].x); f(v[u].y); f(v[u].z); f(v[u].w);
                 }
             }
-            for (; i < n4; i += nthr) {
-                float4 v = p4[i];
-                f(v.x); f(v.y); f(v.z); f(v.w);
+            for (; i < n4; i += kRest * nthr) {
+                float4 v[kRest];
+#pragma unroll
+                for (int u = 0; u < kRest; ++u) v[u] = p4[min(i + u * nthr, n4 - 1)];
+#pragma unroll
+                for (int u = 0; u < kRest; ++u) {
+                    const unsigned int on = i + u * nthr < n4;
+                    f(v[u].x, on); f(v[u].y, on); f(v[u].z, on); f(v[u].w, on);
+                }
             }
             for (int64_t j = (n4 << 2) + tid; j < nf; j += nthr) f(p[j]);
         } else {
+            constexpr int kBatch = 16, kRest = 8;
             const int64_t n2 = nf >> 1;
             const float2 *p2 = reinterpret_cast<const float2 *>(p);
-            for (int64_t i = tid; i < n2; i += nthr) {
-                float2 v = p2[i];
-                f(v.x); f(v.y);
+            int64_t i = tid;
+            for (; i + (kBatch - 1) * nthr < n2; i += kBatch * nthr) {
+                float2 v[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) v[u] = p2[i + u * nthr];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    f(v[u].x); f(v[u].y);
+                }
+            }
+            for (; i < n2; i += kRest * nthr) {
+                float2 v[kRest];
+#pragma unroll
+                for (int u = 0; u < kRest; ++u) v[u] = p2[min(i + u * nthr, n2 - 1)];
+#pragma unroll
+                for (int u = 0; u < kRest; ++u) {
+                    const unsigned int on = i + u * nthr < n2;
+                    f(v[u].x, on); f(v[u].y, on);
+                }
             }
         }
     } else {
-        // strided: columns over blocks, rows over threads
-        for (int64_t c = blk; c < d.cols; c += nblk) {
-            const float2 *col = d.ptr + c * d.ld;
-            for (int64_t r = threadIdx.x; r < d.rows; r += kThreads) {
-                float2 v = col[r];
-                f(v.x); f(v.y);
+        // strided: the block's columns blk, blk + nblk, ... one after the
+        // other as a flat index e = (column number) * rows + row, threads
+        // over e; a thread's (column, row) advances by counting
+        constexpr int kBatch = 8;
+        const int64_t mycols = blk < d.cols ? (d.cols - 1 - blk) / nblk + 1 : 0;
+        const int64_t total = mycols * d.rows;
+        const int64_t dc = kThreads / d.rows, dr = kThreads % d.rows;
+        int64_t cl = threadIdx.x / d.rows, r = threadIdx.x % d.rows;
+        for (int64_t e = threadIdx.x; e < total; e += kBatch * kThreads) {
+            float2 v[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const bool ok = e + u * kThreads < total;
+                v[u] = d.ptr[ok ? (blk + cl * nblk) * d.ld + r : blk * d.ld];
+                cl += dc;
+                r += dr;
+                const bool wrap = r >= d.rows;
+                r -= wrap ? d.rows : 0;
+                cl += wrap ? 1 : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const unsigned int on = e + u * kThreads < total;
+                f(v[u].x, on); f(v[u].y, on);
             }
         }
     }
+}
+
+// Lane operations through DPP (GFX9 controls): no LDS round trip.
+constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]: lane ^ 1
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// inclusive prefix sum over the lanes: within each row of 16 lanes by
+// doubling shifts (lanes without a source add 0), then row 1 and 3 add the
+// last lane of the row before, rows 2 and 3 the last lane of row 1; with
+// rows = 2 only the first 32 lanes are scanned
+template <int kRows = 4>
+__device__ inline unsigned int lane_scan_add(unsigned int v) {
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr1, 0xf, 0xf, false);
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr2, 0xf, 0xf, false);
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr4, 0xf, 0xf, false);
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr8, 0xf, 0xf, false);
+    if constexpr (kRows == 2) {
+        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0x2, 0xf, false);
+    } else {
+        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0xa, 0xf, false);
+        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast31, 0xc, 0xf, false);
+    }
+    return v;
+}
+// sum and maximum over the 64 lanes, in every lane
+__device__ inline unsigned int lane_total(unsigned int v) {
+    return (unsigned int)__builtin_amdgcn_readlane((int)lane_scan_add(v), 63);
+}
+__device__ inline int lane_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr1, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr2, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr4, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr8, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowBcast15, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowBcast31, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ inline unsigned int wave_sum(unsigned int v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
-__device__ inline unsigned long long wave_sum64(unsigned long long v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ inline int wave_max(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
-// Per-operand tolerance level (Sec. 4.1): FP16 if every element but a
-// fraction t lies in the FP16 window without shifting (and e_max <= 14: no
-// overflow); FP16 with scaling if the window shifted to e_max holds all but
-// a fraction t; BF16X3 if all but a fraction t3 lie above its floor and
-// e_max <= 126; else FP32.  Non-finite data -> FP32.
-__device__ inline int operand_level(const OperandStats &s, int emax, double t, double t3) {
-    if (s.nonfinite) return QCE_MODE_FP32;
-    if (s.nnz == 0) return QCE_MODE_FP16X2;
-    const double nnz = (double)s.nnz;
-    if (emax <= kFp16Emax && (double)(s.nnz - s.n1) <= t * nnz) return QCE_MODE_FP16X2;
-    if ((double)(s.nnz - s.n2) <= t * nnz) return QCE_MODE_FP16X2_SCALED;
-    if (emax <= kBf16x3Emax && (double)(s.nnz - s.n3) <= t3 * nnz) return QCE_MODE_BF16X3;
-    return QCE_MODE_FP32;
-}
-
 // Block bx of batch entry z of one statistics launch.
 __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
-    __shared__ __attribute__((aligned(16))) unsigned int hist[kWaves * kWords * kCols];
+    __shared__ __attribute__((aligned(16))) unsigned int hist[kWords * kCols];
     __shared__ unsigned int bins[kWords * 2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     MatDesc a = g.a, b = g.b;
@@ -157,17 +219,16 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
 
     {
         uint4 *h4 = reinterpret_cast<uint4 *>(hist);
-        for (int i = threadIdx.x; i < kWaves * kWords * kCols / 4; i += kThreads) h4[i] = make_uint4(0, 0, 0, 0);
+        for (int i = threadIdx.x; i < kWords * kCols / 4; i += kThreads) h4[i] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
     HistCounter c;
-    c.col = hist + w * kCols + (lane & 31);
+    c.col = hist + (lane & 31);
     scan_matrix(is_a ? a : b, blk, nblk, c);
     __syncthreads();
     // the block's histogram: two threads per word, each adding half of its
-    // kRow counters with 16-byte reads; a thread starts at a different
-    // 16-byte slot than its neighbours, so 16 consecutive threads cover all
-    // banks at every read
+    // kRow counters with 16-byte reads (a thread starts at a different
+    // 16-byte slot than its neighbour)
     for (int p = threadIdx.x; p < 2 * kWords; p += kThreads) {
         const int t = p >> 1, half = p & 1;
         const uint4 *row = reinterpret_cast<const uint4 *>(hist + t * kRow + half * (kRow / 2));
@@ -179,8 +240,8 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
             hi += (v.x >> 16) + (v.y >> 16) + (v.z >> 16) + (v.w >> 16);
         }
         // the other half's sums (the partner thread is the neighbouring lane)
-        lo += __shfl_xor(lo, 1);
-        hi += __shfl_xor(hi, 1);
+        lo += (unsigned int)__builtin_amdgcn_mov_dpp((int)lo, kDppQuadSwap1, 0xf, 0xf, false);
+        hi += (unsigned int)__builtin_amdgcn_mov_dpp((int)hi, kDppQuadSwap1, 0xf, 0xf, false);
         if (!half) {
             bins[2 * t] = lo;
             bins[2 * t + 1] = hi;
@@ -198,10 +259,10 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
             n3 += bI >= kBin3 ? v : 0u;
             if (v) mb = bI;
         }
-        nnz = wave_sum(nnz);
-        n1 = wave_sum(n1);
-        n3 = wave_sum(n3);
-        mb = wave_max(mb);
+        nnz = lane_total(nnz);
+        n1 = lane_total(n1);
+        n3 = lane_total(n3);
+        mb = lane_max(mb);
         StatsRecord &r = rec[bx];
         if (lane == 0) {
             r.nnz = nnz;
@@ -214,166 +275,8 @@ __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
         // holds bin mb - d, then an inclusive scan over the 32 lanes
         static_assert(kRelBins == 32, "one lane per cumulative entry in the low half of the wave");
         unsigned int c = (lane < kRelBins && mb - lane >= 0) ? bins[mb - lane] : 0u;
-#pragma unroll
-        for (int o = 1; o < kRelBins; o <<= 1) {
-            const unsigned int up = __shfl_up(c, o, kRelBins);
-            if ((lane & (kRelBins - 1)) >= o) c += up;
-        }
+        c = lane_scan_add<2>(c);
         if (lane < kRelBins) r.cum[lane] = c;
-    }
-}
-
-// The decision of batch entry z from its blocks' records (one block of 256
-// threads, launched after the statistics launch: the kernel boundary makes
-// every record visible, with no device-wide fence in the statistics blocks).
-// Thread t takes records t, t + 256, ... of both operands; each pass issues
-// the loads of kSelUnroll records before using any (the records come from
-// other XCDs' writes, so every round trip is long).
-constexpr int kSelUnroll = 4;
-__device__ inline void select_body(const StatsArgs &g, int z) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int total = g.blocks_a + g.blocks_b;
-    const StatsRecord *rec = g.rec + (int64_t)z * total;
-    __shared__ unsigned long long red[kWaves][2][5];
-    __shared__ int redmax[kWaves][2];
-    // pass 1: counts and largest bin of each operand (integer sums: the
-    // order does not matter); the first pass's largest bins stay in
-    // registers for pass 2
-    unsigned long long acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-    int mb[2] = {-1, -1};
-    int keep[kSelUnroll];
-    for (int base = threadIdx.x; base < total; base += kSelUnroll * kThreads) {
-        uint4 c[kSelUnroll];
-        int m[kSelUnroll];
-        // loads from clamped indices (no branch between them), masked after
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            const int i = min(base + u * kThreads, total - 1);
-            c[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
-            m[u] = rec[i].maxbin;
-        }
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            if (base + u * kThreads >= total) {
-                c[u] = make_uint4(0, 0, 0, 0);
-                m[u] = -1;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            const int o = base + u * kThreads < g.blocks_a ? 0 : 1;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                if (o != q) continue;
-                acc[q][0] += c[u].x;
-                acc[q][1] += c[u].y;
-                acc[q][2] += c[u].z;
-                acc[q][3] += c[u].w;
-                mb[q] = max(mb[q], m[u]);
-            }
-            if (base == (int)threadIdx.x) keep[u] = m[u];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[q][j] = wave_sum64(acc[q][j]);
-        mb[q] = wave_max(mb[q]);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) red[w][q][j] = acc[q][j];
-            redmax[w][q] = mb[q];
-        }
-    }
-    __syncthreads();
-    int emaxbin[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        int gm = -1;
-        for (int v = 0; v < kWaves; ++v) gm = max(gm, redmax[v][q]);
-        emaxbin[q] = gm;
-    }
-    // pass 2 (stage 2): the part of each block's top bins inside
-    // [gmax - 28, gmax] of its operand, one cumulative entry per record
-    unsigned long long n2[2] = {0, 0};
-    for (int base = threadIdx.x; base < total; base += kSelUnroll * kThreads) {
-        int m[kSelUnroll];
-        if (base == (int)threadIdx.x) {
-#pragma unroll
-            for (int u = 0; u < kSelUnroll; ++u) m[u] = keep[u];
-        } else {
-#pragma unroll
-            for (int u = 0; u < kSelUnroll; ++u) m[u] = rec[min(base + u * kThreads, total - 1)].maxbin;
-        }
-        unsigned int cv[kSelUnroll];
-        bool use[kSelUnroll];
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            const int i = base + u * kThreads;
-            const int gmax = i < g.blocks_a ? emaxbin[0] : emaxbin[1];
-            const int top = kWindowSpan - (gmax - m[u]);  // highest d inside the window (<= 28)
-            use[u] = i < total && m[u] >= 0 && top >= 0;
-            cv[u] = rec[min(i, total - 1)].cum[min(max(top, 0), kRelBins - 1)];
-        }
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) cv[u] = use[u] ? cv[u] : 0u;
-#pragma unroll
-        for (int u = 0; u < kSelUnroll; ++u) {
-            if (base + u * kThreads < g.blocks_a) n2[0] += cv[u];
-            else n2[1] += cv[u];
-        }
-    }
-    n2[0] = wave_sum64(n2[0]);
-    n2[1] = wave_sum64(n2[1]);
-    if (lane == 0) {
-        red[w][0][4] = n2[0];
-        red[w][1][4] = n2[1];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    OperandStats s[2];
-    for (int q = 0; q < 2; ++q) {
-        unsigned long long v[5] = {0, 0, 0, 0, 0};
-        for (int x = 0; x < kWaves; ++x)
-            for (int j = 0; j < 5; ++j) v[j] += red[x][q][j];
-        s[q].nnz = v[0];
-        s[q].n1 = v[1];
-        s[q].n3 = v[2];
-        s[q].nonfinite = v[3];
-        s[q].n2 = v[4];
-        s[q].maxbits = 0;
-        s[q].pad = 0;
-    }
-    DevState *st = g.st + z;
-    int level[2], emax[2];
-    for (int o = 0; o < 2; ++o) {
-        emax[o] = s[o].nnz ? emaxbin[o] - 149 : INT32_MIN;
-        level[o] = operand_level(s[o], emax[o], g.t, g.t3);
-    }
-    const int mode = g.forced >= 0 ? g.forced : max(level[0], level[1]);
-    int shv[2] = {0, 0};
-    if (mode == QCE_MODE_FP16X2_SCALED)
-        for (int o = 0; o < 2; ++o) shv[o] = s[o].nnz ? kFp16Emax - emax[o] : 0;
-    st->mode = mode;
-    st->shift[0] = shv[0];
-    st->shift[1] = shv[1];
-    if (g.mode_log && z == 0) g.mode_log[g.slot] = mode;
-    qce_decision &r = st->last;
-    r.mode = mode;
-    r.sA = shv[0];
-    r.sB = shv[1];
-    r.stats_taken = 1;
-    for (int o = 0; o < 2; ++o) {
-        st->acc[o] = s[o];
-        r.nnz[o] = (int64_t)s[o].nnz;
-        r.n1[o] = (int64_t)s[o].n1;
-        r.n2[o] = (int64_t)s[o].n2;
-        r.n3[o] = (int64_t)s[o].n3;
-        r.nonfinite[o] = (int64_t)s[o].nonfinite;
-        r.emax[o] = emax[o];
     }
 }
 
@@ -381,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(StatsArgs g) {
     stats_body(g, blockIdx.z, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kThreads) void select_kernel(StatsArgs g) { select_body(g, blockIdx.z); }
+__global__ __launch_bounds__(kThreads) void select_kernel(StatsArgs g) { select_block(g, blockIdx.z, true); }
 
 // Grouped launch: the blocks of every entry (each a batch) in one grid;
 // block b belongs to the last entry whose block_start <= b.
@@ -415,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void select_grouped_kernel(const GroupSta
     const GroupStatsEntry &e = ents[lo];
     const int64_t z = b - e.select_start;
     if (z >= e.batch) return;
-    select_body(e.args, (int)z);
+    select_block(e.args, (int)z, true);
 }
 
 }  // namespace
@@ -546,7 +449,8 @@ hipError_t launch_stats_grouped(const GroupStatsEntry *dev_entries, int count, i
 }
 
 hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsRecord *rec, double t, double t3,
-                        int forced_mode, int *mode_log, int slot, hipStream_t s, int batch) {
+                        int forced_mode, int *mode_log, int slot, hipStream_t s, int batch, bool with_select,
+                        StatsArgs *args_out) {
     if (!stats_supported(a) || !stats_supported(b)) return hipErrorInvalidValue;
     StatsArgs g;
     g.a = a;
@@ -566,6 +470,8 @@ hipError_t launch_stats(const MatDesc &a, const MatDesc &b, DevState *st, StatsR
     hipLaunchKernelGGL(stats_kernel, dim3(total, 1, std::max(1, batch)), dim3(kThreads), 0, s, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (args_out) *args_out = g;
+    if (!with_select) return hipSuccess;
     hipLaunchKernelGGL(select_kernel, dim3(1, 1, std::max(1, batch)), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
