@@ -168,7 +168,7 @@ def run_protocol(h, args, torch, qce, synth, data):
         si = SHAPES.index((c["m"], c["n"], c["k"]))
         m, n, k = c["m"], c["n"], c["k"]
         per_seed = []
-        all_auto, all_best = [], []
+        all_auto, all_best, all_rule = [], [], []
         for rep in range(args.protocol_seeds):
             if rep == 0:
                 dA, dB, dC = c["dA"], c["dB"], c["dC"]
@@ -185,6 +185,18 @@ def run_protocol(h, args, torch, qce, synth, data):
 
             t_auto = timed(gemm("auto"))
             dec = h.last_decision()
+            # AUTO under the paper's size tiers (Sec. 4.3: statistics from
+            # 2048, the wide emulation from 512, plain FP32 below); the same
+            # call as AUTO where every dimension reaches 2048
+            if min(m, n, k) < RULE_TIERS[0]:
+                h.set_size_policy(*RULE_TIERS)
+                h.set_gemm_size_policy(True)
+                t_rule = timed(gemm("auto"))
+                rule_mode = h.last_decision()["mode_name"]
+                h.set_gemm_size_policy(False)
+                h.set_size_policy(*h.default_size_policy)
+            else:
+                t_rule, rule_mode = t_auto, dec["mode_name"]
             t_lib = timed(gemm("fp32"))
             h.set_mode("auto")
             tA = dA.view(k, m)
@@ -194,23 +206,31 @@ def run_protocol(h, args, torch, qce, synth, data):
             med = lambda v: float(np.median(v))  # noqa: E731
             per_seed.append({"seed": case_seed(c["dist"], si, rep), "mode": dec["mode_name"],
                              "auto_ms": round(med(t_auto), 5), "fp32_lib_ms": round(med(t_lib), 5),
-                             "rocblas_ms": round(med(t_rb), 5)})
+                             "rocblas_ms": round(med(t_rb), 5),
+                             "size_rule_mode": rule_mode, "size_rule_ms": round(med(t_rule), 5)})
             all_auto += t_auto
+            all_rule += t_rule
             all_best.append(min(med(t_lib), med(t_rb)))
             del out
             if rep:
                 del dA, dB, dC
         med_auto = float(np.median(all_auto))
+        med_rule = float(np.median(all_rule))
         best = float(np.median(all_best))
         eff = 8.0 * m * n * k
         cases.append({"shape": [m, n, k], "dist": c["dist"], "median_ms": round(med_auto, 5),
                       "tflops": round(eff / (med_auto * 1e-3) / 1e12, 3),
                       "median_best_fp32_ms": round(best, 5),
-                      "speedup_vs_best_fp32": round(best / med_auto, 3), "seeds": per_seed})
+                      "speedup_vs_best_fp32": round(best / med_auto, 3),
+                      "size_rule_median_ms": round(med_rule, 5),
+                      "size_rule_speedup_vs_best_fp32": round(best / med_rule, 3), "seeds": per_seed})
     del flush
     torch.cuda.synchronize()
     return {"reps_per_seed": reps, "seeds": args.protocol_seeds, "flush_bytes": 512 << 20,
-            "statistic": "median of hipEvent times per call", "cases": cases}
+            "statistic": "median of hipEvent times per call",
+            "size_rule": "AUTO with qce_set_gemm_size_policy and the paper's tiers (auto_min, emul_min) = "
+                         f"{RULE_TIERS}: statistics only when min(m, n, k) >= {RULE_TIERS[0]}",
+            "cases": cases}
 
 
 def run_gradients(h, args, torch, qce, synth):
@@ -655,6 +675,10 @@ def run_circuits(h, args, torch, qce, synth):
                      "gemms_by_mode": res["auto_t05"]["timing"]["gemms_by_mode"]},
     })
     return out
+
+
+# the paper's size tiers of the automatic selection (Sec. 4.3)
+RULE_TIERS = (2048, 512)
 
 
 def main():

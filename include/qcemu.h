@@ -132,6 +132,9 @@ typedef struct {
  *   QCE_GROUPED_GEMM   1 (default) or 0: inside a qce_contract group, the
  *                      panel-path GEMMs are recorded and run as one
  *                      grouped launch (0: they run at once, one by one)
+ *   QCE_GEMM_SIZE_POLICY 0 (default) or 1: the size policy applies to the
+ *                      CGEMM entry points in AUTO mode too
+ *                      (qce_set_gemm_size_policy)
  * The stream is the device's null stream until qce_set_stream.
  * Errors: INVALID_VALUE (h NULL, bad device or bad environment value),
  * ALLOC, HIP.
@@ -171,11 +174,26 @@ qce_status qce_set_underflow_tolerance(qce_handle *h, double t, double t3);
  * Requires 0 <= emul_min <= auto_min, else INVALID_VALUE.
  * Default auto_min = emul_min = 512: the thresholds are a calibration of
  * statistics cost against GEMM time; the paper's (2048, 512) are its A100
- * values, and on gfx950 statistics already pay off from 512 (so the BF16X3
- * tier is empty by default).
+ * values.  The defaults suit qce_contract's grouped circuit contractions,
+ * where one statistics launch serves many GEMMs; a lone 512^3 CGEMM call
+ * does better with the paper's tiers (BF16X3 without statistics), see
+ * qce_set_gemm_size_policy.
  */
 qce_status qce_set_size_policy(qce_handle *h, int64_t auto_min, int64_t emul_min);
 qce_status qce_get_size_policy(const qce_handle *h, int64_t *auto_min, int64_t *emul_min);
+
+/*
+ * Size policy for the CGEMM entry points too (Sec. 4.3, where the library
+ * takes statistics only above a size and runs the smaller GEMMs on the wide
+ * emulation or plain FP32): enable = 1 makes qce_cgemm_emulated,
+ * qce_cgemm_emulated_noalloc, qce_cgemm_strided_batched and
+ * qce_cgemm_grouped in AUTO mode run each GEMM in the mode the size policy
+ * above gives its (m, n, k) -- AUTO with statistics, BF16X3 or FP32 without
+ * statistics; 0 (the default) keeps AUTO = statistics on every GEMM.  The
+ * environment variable QCE_GEMM_SIZE_POLICY (0 or 1) sets it at
+ * qce_create.  INVALID_VALUE for other values.
+ */
+qce_status qce_set_gemm_size_policy(qce_handle *h, int32_t enable);
 
 /*
  * Tile of the panel GEMM kernel for later calls: 128 (128 x 128 outputs per

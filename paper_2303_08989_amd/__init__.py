@@ -95,6 +95,10 @@ class Handle:
     def set_size_policy(self, auto_min, emul_min):
         _check(self._h, self.lib.qce_set_size_policy(self._h, int(auto_min), int(emul_min)))
 
+    def set_gemm_size_policy(self, enable=True):
+        """Apply the size policy to the CGEMM entry points in AUTO mode too (Sec. 4.3)."""
+        _check(self._h, self.lib.qce_set_gemm_size_policy(self._h, 1 if enable else 0))
+
     def size_policy(self):
         """(auto_min, emul_min) of the size policy (Sec. 4.3)."""
         a, e = ctypes.c_int64(), ctypes.c_int64()

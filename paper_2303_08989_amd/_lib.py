@@ -22,7 +22,8 @@ STATUS = {0: "QCE_SUCCESS", 1: "QCE_ERR_INVALID_VALUE", 2: "QCE_ERR_NOT_SUPPORTE
 # every symbol include/qcemu.h declares
 EXPORTS = (
     "qce_create", "qce_destroy", "qce_set_stream", "qce_set_mode", "qce_get_mode",
-    "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_get_size_policy", "qce_set_gemm_tile",
+    "qce_set_underflow_tolerance", "qce_set_size_policy", "qce_get_size_policy", "qce_set_gemm_size_policy",
+    "qce_set_gemm_tile",
     "qce_set_workspace",
     "qce_cgemm_workspace_size", "qce_cgemm_emulated", "qce_cgemm_emulated_noalloc",
     "qce_noalloc_scratch_bytes", "qce_get_last_decision",
@@ -99,6 +100,7 @@ def load():
         "qce_set_underflow_tolerance": (st, [vp, f64, f64]),
         "qce_set_size_policy": (st, [vp, i64, i64]),
         "qce_get_size_policy": (st, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "qce_set_gemm_size_policy": (st, [vp, i32]),
         "qce_set_gemm_tile": (st, [vp, i32]),
         "qce_set_workspace": (st, [vp, vp, ctypes.c_size_t]),
         "qce_cgemm_workspace_size": (ctypes.c_size_t, [i64, i64, i64]),

@@ -128,6 +128,7 @@ struct qce_handle {
     bool grouping = false;
     bool fused_gather = true;  // permute fused into the split (qce_contract)
     bool smallk = true;        // short-k narrow GEMMs split on load (no panel pass)
+    bool gemm_policy = false;  // the size policy also applies to the CGEMM entry points in AUTO mode
     bool group_gemms = true;   // panel-path contractions recorded in groups (grouped launch)
     int gemm_tile = 0;         // panel GEMM tile: 64, 128, or 0 for the tuned table
     std::vector<qce::SmallItem> pending;
@@ -648,6 +649,12 @@ int policy_mode(const qce_handle *h, int64_t m, int64_t n, int64_t k) {
     return QCE_MODE_FP32;
 }
 
+// The mode of a CGEMM entry-point call: the handle's mode, or in AUTO mode
+// with the CGEMM size policy switched on, the size policy's choice.
+int gemm_mode(const qce_handle *h, int64_t m, int64_t n, int64_t k) {
+    return h->mode == QCE_MODE_AUTO && h->gemm_policy ? policy_mode(h, m, n, k) : h->mode;
+}
+
 size_t cgemm_ws_bytes(int64_t m, int64_t n, int64_t k, int count = 1) {
     return cgemm_ws_layout(m, n, k, count).total;
 }
@@ -1087,6 +1094,11 @@ qce_status qce_create(qce_handle **out, int device) {
         if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
         h->smallk = f == 1;
     }
+    if (const char *v = getenv("QCE_GEMM_SIZE_POLICY")) {
+        int64_t f = 0;
+        if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
+        h->gemm_policy = f == 1;
+    }
     if (const char *v = getenv("QCE_GROUPED_GEMM")) {
         int64_t f = 0;
         if (!parse_i64(v, &f) || (f != 0 && f != 1)) { delete h; return QCE_ERR_INVALID_VALUE; }
@@ -1191,6 +1203,12 @@ qce_status qce_set_gemm_tile(qce_handle *h, int32_t tile) {
     return QCE_SUCCESS;
 }
 
+qce_status qce_set_gemm_size_policy(qce_handle *h, int32_t enable) {
+    if (!h || (enable != 0 && enable != 1)) return QCE_ERR_INVALID_VALUE;
+    h->gemm_policy = enable == 1;
+    return QCE_SUCCESS;
+}
+
 qce_status qce_get_size_policy(const qce_handle *h, int64_t *auto_min, int64_t *emul_min) {
     if (!h || !auto_min || !emul_min) return QCE_ERR_INVALID_VALUE;
     *auto_min = h->auto_min;
@@ -1262,7 +1280,7 @@ qce_status qce_cgemm_emulated(qce_handle *h, qce_op opA, qce_op opB, int64_t m, 
     if (st != QCE_SUCCESS) return st;
     OperandView va{reinterpret_cast<const float2 *>(A), lda, opA != QCE_OP_N, opA == QCE_OP_C};
     OperandView vb{reinterpret_cast<const float2 *>(B), ldb, opB == QCE_OP_N, opB == QCE_OP_C};
-    return cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
+    return cgemm_core(h, gemm_mode(h, m, n, k), va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
                       static_cast<char *>(h->ws));
 }
 
@@ -1291,7 +1309,7 @@ qce_status qce_cgemm_emulated_noalloc(qce_handle *h, qce_op opA, qce_op opB, int
     // no timing records here: a new event could allocate
     const bool timing = h->timing;
     h->timing = false;
-    st = cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
+    st = cgemm_core(h, gemm_mode(h, m, n, k), va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
                     static_cast<char *>(ws));
     h->timing = timing;
     return st;
@@ -1330,7 +1348,7 @@ qce_status qce_cgemm_strided_batched(qce_handle *h, qce_op opA, qce_op opB, int6
     bt.sa = strideA;
     bt.sb = strideB;
     bt.sc = strideC;
-    return cgemm_core(h, h->mode, va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
+    return cgemm_core(h, gemm_mode(h, m, n, k), va, vb, m, n, k, al, be, reinterpret_cast<float2 *>(C), ldc,
                       static_cast<char *>(h->ws), bt);
 }
 
@@ -1363,7 +1381,7 @@ qce_status qce_cgemm_grouped(qce_handle *h, int64_t count, const qce_gemm_desc *
             continue;
         }
         GroupItem it;
-        it.mode = h->mode;
+        it.mode = gemm_mode(h, d.m, d.n, d.k);
         it.a = GroupOperand{reinterpret_cast<const float2 *>(d.A), d.lda, d.opA != QCE_OP_N, d.opA == QCE_OP_C, -1};
         it.b = GroupOperand{reinterpret_cast<const float2 *>(d.B), d.ldb, d.opB == QCE_OP_N, d.opB == QCE_OP_C, -1};
         it.m = d.m;
