@@ -2,8 +2,10 @@
 AddressSanitizer and UndefinedBehaviorSanitizer (device code unchanged),
 and the ABI tests run against that build in a child process with the clang
 ASan runtime preloaded.  Without a GPU this covers argument checking and
-the export table; the GPU test tier runs against the same build on a GPU
-(QCE_LIB pointing at it)."""
+the export table.  (Loaded the same way in a GPU process, the build aborts
+inside the first handle creation with no sanitizer report -- ASan's
+address-space layout and the HIP runtime's reservations do not coexist on
+the GPU machine -- so the GPU tier does not run under it.)"""
 import os
 import subprocess
 import sys
