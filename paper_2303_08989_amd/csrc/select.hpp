@@ -24,6 +24,43 @@ __device__ inline int wave_max(int v) {
 
 }  // namespace selimpl
 
+// Lane operations through DPP (GFX9 controls): no LDS round trip.
+constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]: lane ^ 1
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// inclusive prefix sum over the lanes: within each row of 16 lanes by
+// doubling shifts (lanes without a source add 0), then row 1 and 3 add the
+// last lane of the row before, rows 2 and 3 the last lane of row 1; with
+// rows = 2 only the first 32 lanes are scanned
+template <int kRows = 4>
+__device__ inline unsigned int lane_scan_add(unsigned int v) {
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr1, 0xf, 0xf, false);
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr2, 0xf, 0xf, false);
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr4, 0xf, 0xf, false);
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr8, 0xf, 0xf, false);
+    if constexpr (kRows == 2) {
+        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0x2, 0xf, false);
+    } else {
+        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0xa, 0xf, false);
+        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast31, 0xc, 0xf, false);
+    }
+    return v;
+}
+// sum and maximum over the 64 lanes, in every lane
+__device__ inline unsigned int lane_total(unsigned int v) {
+    return (unsigned int)__builtin_amdgcn_readlane((int)lane_scan_add(v), 63);
+}
+__device__ inline int lane_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr1, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr2, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr4, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr8, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowBcast15, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowBcast31, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // the decision as every thread of the block returns it
 struct SelectDecision {
     int mode;
@@ -52,12 +89,109 @@ __device__ inline int operand_level(const OperandStats &s, int emax, double t, d
 // the loads of kSelUnroll records before using any (the records come from
 // other XCDs' writes, so every round trip is long).
 constexpr int kSelUnroll = 4;
+// records per thread of the one-pass path (up to 768 records)
+constexpr int kSelFast = 3;
+
+// One round of loads: each of a thread's (up to kSelFast) records whole --
+// counts, largest bin and the 32 cumulative entries -- so stage 2 reads the
+// entry it needs from registers.  Lane sums in 32 bits through DPP: a record
+// counts at most 256 x 8000 components (< 2^21), so a lane's three stay
+// below 2^23 and a wave's sum below 2^29.  Fills red, redmax and emaxbin as
+// the general path does.
+__device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *rec, int total,
+                                       unsigned long long (&red)[selimpl::kWaves][2][5],
+                                       int (&redmax)[selimpl::kWaves][2], int (&emaxbin)[2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint4 hdr[kSelFast], cum[kSelFast][kRelBins / 4];
+    int mbv[kSelFast];
+#pragma unroll
+    for (int u = 0; u < kSelFast; ++u) {
+        const int i = min((int)threadIdx.x + u * selimpl::kThreads, total - 1);
+        hdr[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
+        mbv[u] = rec[i].maxbin;
+        const uint4 *cp = reinterpret_cast<const uint4 *>(rec[i].cum);
+#pragma unroll
+        for (int q = 0; q < kRelBins / 4; ++q) cum[u][q] = cp[q];
+    }
+    unsigned int sum[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int mb[2] = {-1, -1};
+#pragma unroll
+    for (int u = 0; u < kSelFast; ++u) {
+        const int i = (int)threadIdx.x + u * selimpl::kThreads;
+        if (i >= total) {
+            hdr[u] = make_uint4(0, 0, 0, 0);
+            mbv[u] = -1;
+        }
+        const int o = i < g.blocks_a ? 0 : 1;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (o != q) continue;
+            sum[q][0] += hdr[u].x;
+            sum[q][1] += hdr[u].y;
+            sum[q][2] += hdr[u].z;
+            sum[q][3] += hdr[u].w;
+            mb[q] = max(mb[q], mbv[u]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sum[q][j] = lane_total(sum[q][j]);
+        mb[q] = lane_max(mb[q]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[w][q][j] = sum[q][j];
+            redmax[w][q] = mb[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        int gm = -1;
+        for (int v = 0; v < selimpl::kWaves; ++v) gm = max(gm, redmax[v][q]);
+        emaxbin[q] = gm;
+    }
+    // stage 2: the cumulative entry of each record's top bin inside
+    // [gmax - 28, gmax], picked from registers by compare and select
+    unsigned int n2[2] = {0, 0};
+#pragma unroll
+    for (int u = 0; u < kSelFast; ++u) {
+        const int i = (int)threadIdx.x + u * selimpl::kThreads;
+        const int o = i < g.blocks_a ? 0 : 1;
+        const int top = kWindowSpan - (emaxbin[o] - mbv[u]);  // highest d inside the window (<= 28)
+        unsigned int v = 0;
+#pragma unroll
+        for (int q = 0; q < kRelBins / 4; ++q) {
+            v = top == 4 * q ? cum[u][q].x : v;
+            v = top == 4 * q + 1 ? cum[u][q].y : v;
+            v = top == 4 * q + 2 ? cum[u][q].z : v;
+            v = top == 4 * q + 3 ? cum[u][q].w : v;
+        }
+        v = i < total && mbv[u] >= 0 ? v : 0u;  // (top < 0 matches no entry)
+        n2[0] += o == 0 ? v : 0u;
+        n2[1] += o == 1 ? v : 0u;
+    }
+    n2[0] = lane_total(n2[0]);
+    n2[1] = lane_total(n2[1]);
+    if (lane == 0) {
+        red[w][0][4] = n2[0];
+        red[w][1][4] = n2[1];
+    }
+}
+
 __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool publish) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int total = g.blocks_a + g.blocks_b;
     const StatsRecord *rec = g.rec + (int64_t)z * total;
     __shared__ unsigned long long red[selimpl::kWaves][2][5];
     __shared__ int redmax[selimpl::kWaves][2];
+    int emaxbin[2];
+    if (total <= kSelFast * selimpl::kThreads) {
+        select_one_pass(g, rec, total, red, redmax, emaxbin);
+    } else {
     // pass 1: counts and largest bin of each operand (integer sums: the
     // order does not matter); the first pass's largest bins stay in
     // registers for pass 2
@@ -111,7 +245,6 @@ __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool pu
         }
     }
     __syncthreads();
-    int emaxbin[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         int gm = -1;
@@ -153,6 +286,7 @@ __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool pu
     if (lane == 0) {
         red[w][0][4] = n2[0];
         red[w][1][4] = n2[1];
+    }
     }
     __syncthreads();
     // thread 0 applies the rule; publish: it also writes the device state

@@ -30,7 +30,6 @@ namespace qce {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
 constexpr int kBinZero = 277, kBinNonfinite = 278;
 constexpr int kBins = 279;                 // exponent bins 0..276, zero, non-finite
 constexpr int kWords = (kBins + 1) / 2;    // two 16-bit counters per word
@@ -162,47 +161,6 @@ __device__ inline void scan_matrix(const MatDesc &d, int64_t blk, int64_t nblk, 
     }
 }
 
-// Lane operations through DPP (GFX9 controls): no LDS round trip.
-constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]: lane ^ 1
-constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
-constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
-
-// inclusive prefix sum over the lanes: within each row of 16 lanes by
-// doubling shifts (lanes without a source add 0), then row 1 and 3 add the
-// last lane of the row before, rows 2 and 3 the last lane of row 1; with
-// rows = 2 only the first 32 lanes are scanned
-template <int kRows = 4>
-__device__ inline unsigned int lane_scan_add(unsigned int v) {
-    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr1, 0xf, 0xf, false);
-    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr2, 0xf, 0xf, false);
-    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr4, 0xf, 0xf, false);
-    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowShr8, 0xf, 0xf, false);
-    if constexpr (kRows == 2) {
-        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0x2, 0xf, false);
-    } else {
-        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0xa, 0xf, false);
-        v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast31, 0xc, 0xf, false);
-    }
-    return v;
-}
-// sum and maximum over the 64 lanes, in every lane
-__device__ inline unsigned int lane_total(unsigned int v) {
-    return (unsigned int)__builtin_amdgcn_readlane((int)lane_scan_add(v), 63);
-}
-__device__ inline int lane_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr1, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr2, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr4, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowShr8, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowBcast15, 0xa, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, kDppRowBcast31, 0xc, 0xf, false));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-__device__ inline unsigned int wave_sum(unsigned int v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 // Block bx of batch entry z of one statistics launch.
 __device__ inline void stats_body(const StatsArgs &g, int z, int bx) {
     __shared__ __attribute__((aligned(16))) unsigned int hist[kWords * kCols];
