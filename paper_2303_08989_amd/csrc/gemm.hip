@@ -814,9 +814,120 @@ __device__ __attribute__((always_inline)) inline void ring_read8(uint32_t addr, 
     v[7] = make_float2(r3.z, r3.w);
 }
 
+// The short-k kernel's mode-independent start: the op(A) ring's state with
+// its first copies issued, and every op(B) load of the thread issued.
+//
+// Full row tiles of a rows-contiguous op(A) (k <= 64) stream through a ring
+// of kSkRing LDS stages of one chunk each (16 k-values x 128 rows, 16 KB),
+// filled by direct buffer loads (no registers held) kSkRing - 1 chunks ahead
+// across tile boundaries.  Workgroup b takes a run of consecutive full tiles
+// (b * (nfull / G) + min(b, nfull % G) on), so that the tiles in flight at
+// once lie spread over all of op(A) and C: the rows of one chunk are lda
+// apart, and neighbouring tiles in flight together would put every access of
+// the device into a few HBM channels when lda is a large power of two.
+// Chunk s of the workgroup is chunk s % nchunks of its (s / nchunks)-th
+// tile.
+template <int KPAD>
+struct SkStart {
+    static constexpr int kBPer = kSkCols * KPAD / kThreads;
+    bool ring;
+    int nchunks, wsc;
+    int64_t nfull, G, mine, first_tile, S;
+    uint32_t voff, extent;
+    // the next chunk to copy: chunk ic of row tile it into stage is (all
+    // wave-uniform, advanced by counting: no divisions in the loop)
+    int ic, is;
+    int64_t it, issued;
+    float2 bv[kBPer];  // op(B) element q of this thread (see sk_b_elem)
+
+    // Copies chunk ic of row tile it into stage is and advances to the next
+    // chunk.  live = false issues the same four copies through a descriptor
+    // of no records (every access out of range: nothing is read) and
+    // advances nothing, so that a fixed number of copies is issued either
+    // way.
+    __device__ __attribute__((always_inline)) void issue(const SmallKArgs &g, char *la, bool live) {
+        // rows it*128 .. +127 of k-values 16ic .. 16ic+15: thread (w, lane),
+        // copy q moves rows 2 lane, 2 lane + 1 of k-value 16ic + 4q + w
+        // (the address is wave-uniform: read it from the first lane, so the
+        // descriptor is built in scalar registers)
+        const uint64_t a64 = reinterpret_cast<uint64_t>(g.A + it * kSkRows + (int64_t)(16 * ic) * g.lda);
+        const uint64_t ua = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a64 >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a64);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(ua), (short)0, live ? extent : 0u,
+                                              kRsrcWord3);
+        char *stage = la + is * kSkChunkBytes;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, LDS_PTR(stage + (256 * q + 64 * wsc) * 16), 16, voff,
+                                                     (uint32_t)(4 * q * g.lda * 8), 0, 0);
+        const int ic1 = ic + 1 == nchunks ? 0 : ic + 1;
+        it += live && ic1 == 0 ? 1 : 0;
+        ic = live ? ic1 : ic;
+        is = live ? (is + 1 == kSkRing ? 0 : is + 1) : is;
+        issued += live ? 1 : 0;
+    }
+};
+
+// Element q of a thread's op(B) loads is (row j, k-value kk) of a 64 x KPAD
+// index space (k-values inner when op(B) is k-contiguous, so that lanes read
+// consecutive addresses), with compile-time shifts only.
+template <int KPAD>
+__device__ __attribute__((always_inline)) inline void sk_b_elem(const SmallKArgs &g, int q, int &j, int &kk) {
+    static_assert((KPAD & (KPAD - 1)) == 0 && kSkCols == 64, "power-of-two index space");
+    const unsigned e = threadIdx.x + (unsigned)(q * kThreads);
+    kk = (int)(g.b_kcontig ? (e & (KPAD - 1)) : (e >> 6));
+    j = (int)(g.b_kcontig ? (e / KPAD) : (e & 63));
+}
+
+template <int KPAD>
+__device__ __attribute__((always_inline)) inline void sk_load_b(const SmallKArgs &g, SkStart<KPAD> &r) {
+#pragma unroll
+    for (int q = 0; q < SkStart<KPAD>::kBPer; ++q) {
+        int j, kk;
+        sk_b_elem<KPAD>(g, q, j, kk);
+        const bool ok = j < g.n && kk < g.k;
+        const int64_t idx = !ok ? 0 : g.b_kcontig ? kk + (int64_t)j * g.ldb : j + (int64_t)kk * g.ldb;
+        r.bv[q] = g.B[idx];
+    }
+}
+
+template <int KPAD>
+__device__ __attribute__((always_inline)) inline void sk_start(const SmallKArgs &g, char *la, SkStart<KPAD> &r) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kpad = (int)round_up(g.k, kKPad);
+    r.nchunks = kpad / kKPad;
+    r.ring = KPAD == 64 && g.a_stage;
+    r.nfull = g.m / kSkRows;
+    r.G = gridDim.x;
+    const int64_t per = r.nfull / r.G, rem = r.nfull % r.G;
+    r.mine = r.ring ? per + (blockIdx.x < rem ? 1 : 0) : 0;
+    r.first_tile = blockIdx.x * per + min((int64_t)blockIdx.x, rem);
+    r.S = r.mine * r.nchunks;
+    r.wsc = __builtin_amdgcn_readfirstlane(w);
+    r.voff = (uint32_t)(16 * lane + r.wsc * g.lda * 8);
+    r.extent = (uint32_t)((15 * g.lda + kSkRows) * 8);
+    r.ic = 0;
+    r.is = 0;
+    r.it = r.first_tile;
+    r.issued = 0;
+    // the first kSkRing - 1 chunks (copies of no records past this
+    // workgroup's last chunk, into stages it never reads): a fixed count,
+    // which lets the compiler's waits for the loads issued before and after
+    // count exactly
+    if constexpr (KPAD == 64) {
+#pragma unroll
+        for (int p = 0; p < kSkRing - 1; ++p) r.issue(g, la, r.issued < r.S);
+    }
+    // the k <= 64 kernel also issues op(B)'s loads here (the k <= 128 one,
+    // whose op(B) takes twice the registers, in its body after the mode is
+    // known)
+    if constexpr (KPAD == 64) sk_load_b<KPAD>(g, r);
+}
+
 template <int MODE, int KPAD>
 __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKArgs &g, int mode, int shA, int shB,
-                                                                  char *lds, char *la) {
+                                                                  char *lds, char *la, SkStart<KPAD> &r) {
     constexpr int kE = MODE == QCE_MODE_FP32 ? 4 : 2;
     const int kpad = (int)round_up(g.k, kKPad);
     const int rb = sk_row_bytes(kpad, kE);
@@ -826,86 +937,18 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, l32 = lane & 31, hi = lane >> 5;
     const int64_t ntiles = (g.m + kSkRows - 1) / kSkRows;
 
-    // Full row tiles of a rows-contiguous op(A) (k <= 64) stream through a
-    // ring of kSkRing LDS stages of one chunk each (16 k-values x 128 rows,
-    // 16 KB), filled by direct buffer loads (no registers held) kSkRing - 1
-    // chunks ahead across tile boundaries.  Workgroup b takes a run of
-    // consecutive full tiles (b * (nfull / G) + min(b, nfull % G) on), so
-    // that the tiles in flight at once lie spread over all of op(A) and C:
-    // the rows of one chunk are lda apart, and neighbouring tiles in flight
-    // together would put every access of the device into a few HBM
-    // channels when lda is a large power of two.  Chunk s of the
-    // workgroup is chunk s % nchunks of its (s / nchunks)-th tile.  The
-    // first chunks are issued before op(B) is read, so both are in flight
-    // at once.
-    const bool ring = KPAD == 64 && g.a_stage;
-    const int64_t nfull = g.m / kSkRows;
-    const int64_t G = gridDim.x;
-    const int64_t per = nfull / G, rem = nfull % G;
-    const int64_t mine = ring ? per + (blockIdx.x < rem ? 1 : 0) : 0;
-    const int64_t first_tile = blockIdx.x * per + min((int64_t)blockIdx.x, rem);
-    const int64_t S = mine * nchunks;
-    const int wsc = __builtin_amdgcn_readfirstlane(w);
-    const uint32_t voff = (uint32_t)(16 * lane + wsc * g.lda * 8);
-    const uint32_t extent = (uint32_t)((15 * g.lda + kSkRows) * 8);
-    // the next chunk to copy: chunk ic of row tile it into stage is (all
-    // wave-uniform, advanced by counting: no divisions in the loop)
-    int ic = 0, is = 0;
-    int64_t it = first_tile, issued = 0;
-    auto issue_next = [&]() {
-        // rows it*128 .. +127 of k-values 16ic .. 16ic+15: thread (w, lane),
-        // copy q moves rows 2 lane, 2 lane + 1 of k-value 16ic + 4q + w
-        // (the address is wave-uniform: read it from the first lane, so the
-        // descriptor is built in scalar registers)
-        const uint64_t a64 = reinterpret_cast<uint64_t>(g.A + it * kSkRows + (int64_t)(16 * ic) * g.lda);
-        const uint64_t ua = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a64 >> 32)) << 32) |
-                            (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a64);
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(ua), (short)0, extent, kRsrcWord3);
-        char *stage = la + is * kSkChunkBytes;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, LDS_PTR(stage + (256 * q + 64 * wsc) * 16), 16, voff,
-                                                     (uint32_t)(4 * q * g.lda * 8), 0, 0);
-        if (++ic == nchunks) {
-            ic = 0;
-            ++it;
-        }
-        if (++is == kSkRing) is = 0;
-        ++issued;
-    };
-    while (issued < S && issued < kSkRing - 1) issue_next();
-
-    // op(B) -> LDS planes (zeros beyond n and k): every load of a thread is
-    // issued (from a clamped, valid address) before any value is used.
-    // Element q of a thread is (row j, k-value kk) of a 64 x KPAD index
-    // space (k-values inner when op(B) is k-contiguous, so that lanes read
-    // consecutive addresses), with compile-time shifts only; k-values from
-    // kpad on are not stored.
-    static_assert((KPAD & (KPAD - 1)) == 0 && kSkCols == 64, "power-of-two index space");
-    constexpr int kBPer = kSkCols * KPAD / kThreads;
-    auto b_elem = [&](int q, int &j, int &kk) {
-        const unsigned e = threadIdx.x + (unsigned)(q * kThreads);
-        kk = (int)(g.b_kcontig ? (e & (KPAD - 1)) : (e >> 6));
-        j = (int)(g.b_kcontig ? (e / KPAD) : (e & 63));
-    };
-    float2 bv[kBPer];
+    // op(B) -> LDS planes (zeros beyond n and k; k-values from kpad on are
+    // not stored)
+    constexpr int kBPer = SkStart<KPAD>::kBPer;
+    if constexpr (KPAD != 64) sk_load_b<KPAD>(g, r);
 #pragma unroll
     for (int q = 0; q < kBPer; ++q) {
         int j, kk;
-        b_elem(q, j, kk);
-        const bool ok = j < g.n && kk < g.k;
-        const int64_t idx = !ok ? 0 : g.b_kcontig ? kk + (int64_t)j * g.ldb : j + (int64_t)kk * g.ldb;
-        bv[q] = g.B[idx];
-    }
-#pragma unroll
-    for (int q = 0; q < kBPer; ++q) {
-        int j, kk;
-        b_elem(q, j, kk);
+        sk_b_elem<KPAD>(g, q, j, kk);
         if (kk >= kpad) continue;
         float2 v = make_float2(0.f, 0.f);
         if (j < g.n && kk < g.k) {
-            v = bv[q];
+            v = r.bv[q];
             if (g.b_conj) v.y = -v.y;  // (padding stays +0)
         }
         char *row = lds + j * rb;
@@ -1082,21 +1125,22 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
 
     // the register path below takes the tiles the ring does not (with the
     // ring: the partial tile after the full ones)
-    const int64_t first_reg_tile = ring ? nfull + blockIdx.x : blockIdx.x;
-    if (ring) {
+    const int64_t first_reg_tile = r.ring ? r.nfull + blockIdx.x : blockIdx.x;
+    const int64_t S = r.S;
+    if (r.ring) {
         // LDS byte address of this lane's first value in stage 0 (the
         // fragment's first k-value kval(c, 0) - 16 c, then its row)
         const uint32_t ring_base =
             (uint32_t)(uintptr_t)LDS_PTR(la) + (uint32_t)(((kval(0, 0)) * kSkRows + w * 32 + l32) * 8);
         // chunk c of row tile t sits in stage cs
         int c = 0, cs = 0;
-        int64_t t = first_tile;
+        int64_t t = r.first_tile;
         for (int64_t sidx = 0; sidx < S; ++sidx) {
             // chunk sidx has landed once at most the copies issued after it
             // are outstanding (vector memory operations retire in order; the
             // epilogue's stores only make the wait longer)
             static_assert(kSkRing == 4, "the waits below assume up to two chunks in flight after this one");
-            const int64_t after = issued - 1 - sidx;
+            const int64_t after = r.issued - 1 - sidx;
             if (after >= 2) wait_vmcnt<8>();
             else if (after == 1) wait_vmcnt<4>();
             else wait_vmcnt<0>();
@@ -1110,7 +1154,7 @@ __device__ __attribute__((always_inline)) inline void smallk_body(const SmallKAr
 #pragma unroll
                 for (int u = 0; u < 8; ++u) cur[u].y = -cur[u].y;
             }
-            if (issued < S) issue_next();  // into chunk sidx - 1's stage
+            if (r.issued < S) r.issue(g, la, true);  // into chunk sidx - 1's stage
             if (c == 0) zero_acc();
             mma_chunk(cur, c);
             if (c == nchunks - 1) epilogue(t * kSkRows + w * 32 + l32, true);
@@ -1165,9 +1209,17 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
     g.B += z * g.bsB;
     g.C += z * g.bsC;
     if (g.st) g.st += z;
+    // mode-independent loads first -- the selection's records (where they
+    // fit in registers), then the op(A) ring's first copies and op(B) --
+    // so that the selection's reductions run while the operands arrive
+    SelectHead sr;
+    const bool early = g.select_here && select_one_pass_fits(g.sel);
+    if (early) select_load_head(g.sel, (int)z, sr);
+    SkStart<KPAD> r;
+    sk_start<KPAD>(g, ring, r);
     int mode, shA = 0, shB = 0;
     if (g.select_here) {
-        const SelectDecision d = select_block(g.sel, (int)z, blockIdx.x == 0);
+        const SelectDecision d = select_block(g.sel, (int)z, blockIdx.x == 0, early ? &sr : nullptr);
         mode = d.mode;
         shA = d.shift[0];
         shB = d.shift[1];
@@ -1179,11 +1231,11 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(SmallKArgs g) {
         }
     }
     if (mode == QCE_MODE_FP16X2 || mode == QCE_MODE_FP16X2_SCALED)
-        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, shA, shB, lds, ring);
+        smallk_body<QCE_MODE_FP16X2, KPAD>(g, mode, shA, shB, lds, ring, r);
     else if (mode == QCE_MODE_BF16X3)
-        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, 0, 0, lds, ring);
+        smallk_body<QCE_MODE_BF16X3, KPAD>(g, mode, 0, 0, lds, ring, r);
     else
-        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, 0, 0, lds, ring);
+        smallk_body<QCE_MODE_FP32, KPAD>(g, mode, 0, 0, lds, ring, r);
 }
 
 }  // namespace

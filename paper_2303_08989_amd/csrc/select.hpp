@@ -61,6 +61,17 @@ __device__ inline int lane_max(int v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Workgroup barrier that waits for this wave's LDS operations only: global
+// loads issued before the selection (a consumer kernel's own operand
+// copies) stay in flight; the selection's record loads are waited for
+// where their registers are used.
+__device__ __attribute__((always_inline)) inline void sel_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt at their maxima (no wait)
+    asm volatile("s_barrier" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // the decision as every thread of the block returns it
 struct SelectDecision {
     int mode;
@@ -92,27 +103,45 @@ constexpr int kSelUnroll = 4;
 // records per thread of the one-pass path (up to 768 records)
 constexpr int kSelFast = 3;
 
-// One round of loads: each of a thread's (up to kSelFast) records whole --
-// counts, largest bin and the 32 cumulative entries -- so stage 2 reads the
-// entry it needs from registers.  Lane sums in 32 bits through DPP: a record
+// At most kSelFast records per thread, held in registers: counts and
+// largest bin, and (where the caller loaded them in the same round) the 32
+// cumulative entries, so that stage 2 picks the entry it needs from
+// registers.  Lane sums in 32 bits through DPP: a record
 // counts at most 256 x 8000 components (< 2^21), so a lane's three stay
 // below 2^23 and a wave's sum below 2^29.  Fills red, redmax and emaxbin as
 // the general path does.
-__device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *rec, int total,
-                                       unsigned long long (&red)[selimpl::kWaves][2][5],
-                                       int (&redmax)[selimpl::kWaves][2], int (&emaxbin)[2]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint4 hdr[kSelFast], cum[kSelFast][kRelBins / 4];
+// a thread's records of the one-pass path (counts and largest bin), loaded
+// ahead of their use
+struct SelectHead {
+    uint4 hdr[kSelFast];
     int mbv[kSelFast];
+};
+__device__ inline bool select_one_pass_fits(const StatsArgs &g) {
+    return g.blocks_a + g.blocks_b <= kSelFast * selimpl::kThreads;
+}
+// issues the loads of batch entry z's record heads (every thread of the block)
+__device__ inline void select_load_head(const StatsArgs &g, int z, SelectHead &r) {
+    const int total = g.blocks_a + g.blocks_b;
+    const StatsRecord *rec = g.rec + (int64_t)z * total;
 #pragma unroll
     for (int u = 0; u < kSelFast; ++u) {
         const int i = min((int)threadIdx.x + u * selimpl::kThreads, total - 1);
-        hdr[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
-        mbv[u] = rec[i].maxbin;
-        const uint4 *cp = reinterpret_cast<const uint4 *>(rec[i].cum);
-#pragma unroll
-        for (int q = 0; q < kRelBins / 4; ++q) cum[u][q] = cp[q];
+        r.hdr[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
+        r.mbv[u] = rec[i].maxbin;
     }
+}
+
+// kHaveCum: the records' cumulative entries are in cum (registers); else
+// stage 2 loads the one entry it needs per record (a consumer kernel that
+// preloaded only the heads, keeping its registers for its own operands)
+template <bool kHaveCum>
+__device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *rec, int total, SelectHead &r,
+                                       const uint4 (&cum)[kSelFast][kRelBins / 4],
+                                       unsigned long long (&red)[selimpl::kWaves][2][5],
+                                       int (&redmax)[selimpl::kWaves][2], int (&emaxbin)[2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint4 (&hdr)[kSelFast] = r.hdr;
+    int (&mbv)[kSelFast] = r.mbv;
     unsigned int sum[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     int mb[2] = {-1, -1};
 #pragma unroll
@@ -147,7 +176,7 @@ __device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *re
             redmax[w][q] = mb[q];
         }
     }
-    __syncthreads();
+    sel_barrier();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         int gm = -1;
@@ -163,12 +192,17 @@ __device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *re
         const int o = i < g.blocks_a ? 0 : 1;
         const int top = kWindowSpan - (emaxbin[o] - mbv[u]);  // highest d inside the window (<= 28)
         unsigned int v = 0;
+        if constexpr (kHaveCum) {
 #pragma unroll
-        for (int q = 0; q < kRelBins / 4; ++q) {
-            v = top == 4 * q ? cum[u][q].x : v;
-            v = top == 4 * q + 1 ? cum[u][q].y : v;
-            v = top == 4 * q + 2 ? cum[u][q].z : v;
-            v = top == 4 * q + 3 ? cum[u][q].w : v;
+            for (int q = 0; q < kRelBins / 4; ++q) {
+                v = top == 4 * q ? cum[u][q].x : v;
+                v = top == 4 * q + 1 ? cum[u][q].y : v;
+                v = top == 4 * q + 2 ? cum[u][q].z : v;
+                v = top == 4 * q + 3 ? cum[u][q].w : v;
+            }
+        } else {
+            v = rec[min(i, total - 1)].cum[min(max(top, 0), kRelBins - 1)];
+            v = top >= 0 ? v : 0u;
         }
         v = i < total && mbv[u] >= 0 ? v : 0u;  // (top < 0 matches no entry)
         n2[0] += o == 0 ? v : 0u;
@@ -182,15 +216,34 @@ __device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *re
     }
 }
 
-__device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool publish) {
+// The decision of batch entry z (every thread of the block).  pre: the
+// thread's record heads already loaded by select_load_head (only where
+// select_one_pass_fits), else nullptr.
+__device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool publish,
+                                              SelectHead *pre = nullptr) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int total = g.blocks_a + g.blocks_b;
     const StatsRecord *rec = g.rec + (int64_t)z * total;
     __shared__ unsigned long long red[selimpl::kWaves][2][5];
     __shared__ int redmax[selimpl::kWaves][2];
     int emaxbin[2];
-    if (total <= kSelFast * selimpl::kThreads) {
-        select_one_pass(g, rec, total, red, redmax, emaxbin);
+    if (pre) {
+        const uint4 none[kSelFast][kRelBins / 4] = {};
+        select_one_pass<false>(g, rec, total, *pre, none, red, redmax, emaxbin);
+    } else if (select_one_pass_fits(g)) {
+        // one round of loads: heads and cumulative entries
+        SelectHead hd;
+        uint4 cum[kSelFast][kRelBins / 4];
+#pragma unroll
+        for (int u = 0; u < kSelFast; ++u) {
+            const int i = min((int)threadIdx.x + u * selimpl::kThreads, total - 1);
+            hd.hdr[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
+            hd.mbv[u] = rec[i].maxbin;
+            const uint4 *cp = reinterpret_cast<const uint4 *>(rec[i].cum);
+#pragma unroll
+            for (int q = 0; q < kRelBins / 4; ++q) cum[u][q] = cp[q];
+        }
+        select_one_pass<true>(g, rec, total, hd, cum, red, redmax, emaxbin);
     } else {
     // pass 1: counts and largest bin of each operand (integer sums: the
     // order does not matter); the first pass's largest bins stay in
@@ -244,7 +297,7 @@ __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool pu
             redmax[w][q] = mb[q];
         }
     }
-    __syncthreads();
+    sel_barrier();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         int gm = -1;
@@ -288,7 +341,7 @@ __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool pu
         red[w][1][4] = n2[1];
     }
     }
-    __syncthreads();
+    sel_barrier();
     // thread 0 applies the rule; publish: it also writes the device state
     // (mode flag, shifts, the record for the host)
     __shared__ SelectDecision out;
@@ -340,7 +393,7 @@ __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool pu
             }
         }
     }
-    __syncthreads();
+    sel_barrier();
     return out;
 }
 
