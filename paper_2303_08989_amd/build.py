@@ -41,20 +41,48 @@ SANITIZE_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fs
 ASAN_LIB = os.path.join(HERE, "libqcemu_asan.so")
 
 
+# the compiler's per-kernel resource remarks (registers, scratch, LDS,
+# occupancy), kept next to the objects for the build checks in tests/
+RESOURCE_REMARKS = "-Rpass-analysis=kernel-resource-usage"
+RESOURCES = os.path.join(BUILD, "kernel_resources.txt")
+
+
 def _compile(src, verbose, sanitize=False):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, ("asan_" if sanitize else "") + src + ".o")
-    cmd = [HIPCC, "-x", "hip", *COMMON_FLAGS, *(SANITIZE_FLAGS if sanitize else []), "-c", path, "-o", obj]
+    cmd = [HIPCC, "-x", "hip", *COMMON_FLAGS, *(SANITIZE_FLAGS if sanitize else []), RESOURCE_REMARKS,
+           "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
-                     if "packed-fp32-ops" not in l)
+    lines = (res.stdout + res.stderr).splitlines()
+    remarks = [l for l in lines if "kernel-resource-usage" in l]
+    msgs = "\n".join(l for l in lines if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{msgs}")
     if verbose and msgs.strip():
         print(msgs)
-    return obj
+    return obj, remarks
+
+
+def parse_resources(remarks):
+    """{kernel symbol: {"VGPRs": .., "AGPRs": .., "ScratchSize": .., ...}} from
+    the compiler's resource remarks."""
+    out, cur = {}, None
+    for l in remarks:
+        body = l.split("remark:", 1)[-1].strip()
+        body = body.replace("[-Rpass-analysis=kernel-resource-usage]", "").strip()
+        if body.startswith("Function Name:"):
+            cur = body.split(":", 1)[1].strip()
+            out[cur] = {}
+        elif cur and ":" in body:
+            key, val = body.split(":", 1)
+            key = key.split("[")[0].strip()
+            try:
+                out[cur][key] = int(val.strip().split()[0])
+            except ValueError:
+                pass
+    return out
 
 
 def build(verbose=False, jobs=None, sanitize=False):
@@ -63,7 +91,11 @@ def build(verbose=False, jobs=None, sanitize=False):
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, sanitize), SOURCES))
+        done = list(ex.map(lambda s: _compile(s, verbose, sanitize), SOURCES))
+    objs = [o for o, _ in done]
+    if not sanitize:
+        with open(RESOURCES, "w") as f:
+            f.write("\n".join(r for _, rem in done for r in rem) + "\n")
     out = ASAN_LIB if sanitize else LIB
     tmp = out + ".tmp%d" % os.getpid()
     link_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
