@@ -216,35 +216,12 @@ __device__ inline void select_one_pass(const StatsArgs &g, const StatsRecord *re
     }
 }
 
-// The decision of batch entry z (every thread of the block).  pre: the
-// thread's record heads already loaded by select_load_head (only where
-// select_one_pass_fits), else nullptr.
-__device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool publish,
-                                              SelectHead *pre = nullptr) {
+// More records than one round of loads holds: two passes over them, each
+// thread issuing the loads of kSelUnroll records before using any.
+__device__ inline void select_two_pass(const StatsArgs &g, const StatsRecord *rec, int total,
+                                       unsigned long long (&red)[selimpl::kWaves][2][5],
+                                       int (&redmax)[selimpl::kWaves][2], int (&emaxbin)[2]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int total = g.blocks_a + g.blocks_b;
-    const StatsRecord *rec = g.rec + (int64_t)z * total;
-    __shared__ unsigned long long red[selimpl::kWaves][2][5];
-    __shared__ int redmax[selimpl::kWaves][2];
-    int emaxbin[2];
-    if (pre) {
-        const uint4 none[kSelFast][kRelBins / 4] = {};
-        select_one_pass<false>(g, rec, total, *pre, none, red, redmax, emaxbin);
-    } else if (select_one_pass_fits(g)) {
-        // one round of loads: heads and cumulative entries
-        SelectHead hd;
-        uint4 cum[kSelFast][kRelBins / 4];
-#pragma unroll
-        for (int u = 0; u < kSelFast; ++u) {
-            const int i = min((int)threadIdx.x + u * selimpl::kThreads, total - 1);
-            hd.hdr[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
-            hd.mbv[u] = rec[i].maxbin;
-            const uint4 *cp = reinterpret_cast<const uint4 *>(rec[i].cum);
-#pragma unroll
-            for (int q = 0; q < kRelBins / 4; ++q) cum[u][q] = cp[q];
-        }
-        select_one_pass<true>(g, rec, total, hd, cum, red, redmax, emaxbin);
-    } else {
     // pass 1: counts and largest bin of each operand (integer sums: the
     // order does not matter); the first pass's largest bins stay in
     // registers for pass 2
@@ -340,6 +317,37 @@ __device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool pu
         red[w][0][4] = n2[0];
         red[w][1][4] = n2[1];
     }
+}
+
+// The decision of batch entry z (every thread of the block).  pre: the
+// thread's record heads already loaded by select_load_head (only where
+// select_one_pass_fits), else nullptr.
+__device__ inline SelectDecision select_block(const StatsArgs &g, int z, bool publish,
+                                              SelectHead *pre = nullptr) {
+    const int total = g.blocks_a + g.blocks_b;
+    const StatsRecord *rec = g.rec + (int64_t)z * total;
+    __shared__ unsigned long long red[selimpl::kWaves][2][5];
+    __shared__ int redmax[selimpl::kWaves][2];
+    int emaxbin[2];
+    if (pre) {
+        const uint4 none[kSelFast][kRelBins / 4] = {};
+        select_one_pass<false>(g, rec, total, *pre, none, red, redmax, emaxbin);
+    } else if (select_one_pass_fits(g)) {
+        // one round of loads: heads and cumulative entries
+        SelectHead hd;
+        uint4 cum[kSelFast][kRelBins / 4];
+#pragma unroll
+        for (int u = 0; u < kSelFast; ++u) {
+            const int i = min((int)threadIdx.x + u * selimpl::kThreads, total - 1);
+            hd.hdr[u] = *reinterpret_cast<const uint4 *>(&rec[i].nnz);
+            hd.mbv[u] = rec[i].maxbin;
+            const uint4 *cp = reinterpret_cast<const uint4 *>(rec[i].cum);
+#pragma unroll
+            for (int q = 0; q < kRelBins / 4; ++q) cum[u][q] = cp[q];
+        }
+        select_one_pass<true>(g, rec, total, hd, cum, red, redmax, emaxbin);
+    } else {
+        select_two_pass(g, rec, total, red, redmax, emaxbin);
     }
     sel_barrier();
     // thread 0 applies the rule; publish: it also writes the device state
