@@ -28,6 +28,9 @@ namespace qce {
 namespace {
 
 constexpr int kThreads = 256;
+// k-values (direct_kernel) or k-ranges (direct_reduce_kernel) a thread has
+// in flight at once
+constexpr int kUnroll = 8;
 
 __device__ inline float2 load_view(const float2 *p, int64_t ld, int kcontig, int conj, int64_t r,
                                    int64_t l) {
@@ -61,7 +64,27 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs d) {
     const int64_t k1 = min(d.k, k0 + d.kchunk);
     float re = 0.f, im = 0.f;
     if (i < d.m && j < d.n) {
-        for (int64_t l = k0 + kl; l < k1; l += d.kl) {
+        // kUnroll k-values per round: every load of a round is issued before
+        // its products, which then run in k order (the same sequence of
+        // fused multiply-adds as one k-value at a time)
+        const int64_t step = d.kl;
+        int64_t l = k0 + kl;
+        for (; l + (kUnroll - 1) * step < k1; l += kUnroll * step) {
+            float2 a[kUnroll], b[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                a[u] = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i, l + u * step);
+                b[u] = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l + u * step);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                re = fmaf(a[u].x, b[u].x, re);
+                re = fmaf(-a[u].y, b[u].y, re);
+                im = fmaf(a[u].x, b[u].y, im);
+                im = fmaf(a[u].y, b[u].x, im);
+            }
+        }
+        for (; l < k1; l += step) {
             const float2 a = load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i, l);
             const float2 b = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l);
             re = fmaf(a.x, b.x, re);
@@ -100,16 +123,52 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DirectArgs d) {
     *cp = out;
 }
 
-__global__ __launch_bounds__(kThreads) void direct_reduce_kernel(DirectArgs d, int splits) {
-    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (o >= d.m * d.n) return;
+// The partial tiles of the k-ranges added up: `ways` threads per output
+// (a power of two), thread w adding ranges w, w + ways, ... in order
+// (kUnroll loads in flight), then the ways sums pairwise in LDS in a fixed
+// order, so the result does not depend on timing.
+__global__ __launch_bounds__(kThreads) void direct_reduce_kernel(DirectArgs d, int splits, int ways) {
+    __shared__ float2 red[kThreads];
     select_entry(d);
+    const int t = threadIdx.x;
+    const int w = t & (ways - 1);
+    const int64_t mn = d.m * d.n;
+    const int64_t o = (int64_t)blockIdx.x * (kThreads / ways) + t / ways;
     float re = 0.f, im = 0.f;
-    for (int s = 0; s < splits; ++s) {
-        const float2 p = d.partial[(int64_t)s * d.m * d.n + o];
-        re += p.x;
-        im += p.y;
+    if (o < mn) {
+        const float2 *p = d.partial + o;
+        int s = w;
+        for (; s + (kUnroll - 1) * ways < splits; s += kUnroll * ways) {
+            float2 v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) v[u] = p[(int64_t)(s + u * ways) * mn];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                re += v[u].x;
+                im += v[u].y;
+            }
+        }
+        for (; s < splits; s += ways) {
+            const float2 v = p[(int64_t)s * mn];
+            re += v.x;
+            im += v.y;
+        }
     }
+    if (ways > 1) {
+        red[t] = make_float2(re, im);
+        __syncthreads();
+        for (int h = ways >> 1; h > 0; h >>= 1) {
+            if (w < h) {
+                const float2 u = red[t + h];
+                red[t].x += u.x;
+                red[t].y += u.y;
+            }
+            __syncthreads();
+        }
+        re = red[t].x;
+        im = red[t].y;
+    }
+    if (w != 0 || o >= mn) return;
     const int64_t i = o % d.m, j = o / d.m;
     float2 out = make_float2(d.alpha.x * re - d.alpha.y * im, d.alpha.x * im + d.alpha.y * re);
     if (d.alpha.x == 1.f && d.alpha.y == 0.f) out = make_float2(re, im);
@@ -131,6 +190,110 @@ __device__ inline float2 scale_out(const DirectArgs &d, float re, float im, floa
         out.y += d.beta.x * c.y + d.beta.y * c.x;
     }
     return out;
+}
+
+// Sum over the 64 lanes of a wave in a fixed order (an inclusive scan by DPP
+// row shifts and row broadcasts; lanes without a source add +0), the total
+// in lane 63.
+__device__ inline float lane_scan_f(float v) {
+    auto add = [](float x, int y) { return x + __int_as_float(y); };
+    v = add(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = add(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = add(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = add(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = add(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = add(v, __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+// A small output (up to 8 x 8 per group, at most four groups) with a long
+// k: every thread of a group accumulates the group's whole T x T output
+// tile over its own k-values (a column of op(A) and a row of op(B) per
+// k-value, each element read once), two k-values in flight; the k-values
+// of a block are split over the group's d.kl threads (whole waves).  The
+// tile is then added up over each wave's lanes (lane_scan_f) and over the
+// group's waves in LDS, in a fixed order.  d.ti x d.tj groups of tiles
+// cover the output (groups along m first).
+template <int T>
+__global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
+    __shared__ float red[kThreads / 64][2 * T * T];
+    select_entry(d);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int kl = d.kl, gi = d.ti;
+    const int g = t / kl, q = t % kl;
+    const int64_t i0 = (int64_t)(g % gi) * T, j0 = (int64_t)(g / gi) * T;
+    const int64_t k0 = (int64_t)blockIdx.y * d.kchunk;
+    const int64_t k1 = min(d.k, k0 + d.kchunk);
+    float re[T][T], im[T][T];
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+#pragma unroll
+        for (int c = 0; c < T; ++c) re[r][c] = im[r][c] = 0.f;
+    auto fma_tile = [&](const float2 (&a)[T], const float2 (&b)[T]) {
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+#pragma unroll
+            for (int c = 0; c < T; ++c) {
+                re[r][c] = fmaf(a[r].x, b[c].x, re[r][c]);
+                re[r][c] = fmaf(-a[r].y, b[c].y, re[r][c]);
+                im[r][c] = fmaf(a[r].x, b[c].y, im[r][c]);
+                im[r][c] = fmaf(a[r].y, b[c].x, im[r][c]);
+            }
+    };
+    // rows i0 + r >= m and columns j0 + c >= n read nothing (the bounds are
+    // uniform over a group, hence over a wave)
+    auto load = [&](float2 (&a)[T], float2 (&b)[T], int64_t l) {
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+            a[r] = i0 + r < d.m ? load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i0 + r, l) : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+            b[c] = j0 + c < d.n ? load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j0 + c, l) : make_float2(0.f, 0.f);
+    };
+    int64_t l = k0 + q;
+    for (; l + kl < k1; l += 2 * (int64_t)kl) {
+        float2 a0[T], b0[T], a1[T], b1[T];
+        load(a0, b0, l);
+        load(a1, b1, l + kl);
+        fma_tile(a0, b0);
+        fma_tile(a1, b1);
+    }
+    if (l < k1) {
+        float2 a0[T], b0[T];
+        load(a0, b0, l);
+        fma_tile(a0, b0);
+    }
+    // each wave's sums (lane 63 holds them after the scan)
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+            const float sr = lane_scan_f(re[r][c]), si = lane_scan_f(im[r][c]);
+            if (lane == 63) {
+                red[wv][2 * (r + c * T)] = sr;
+                red[wv][2 * (r + c * T) + 1] = si;
+            }
+        }
+    __syncthreads();
+    // thread t: output (r, c) of group t / T^2, its waves added in order
+    const int groups = kThreads / kl;
+    if (t >= groups * T * T) return;
+    const int g2 = t / (T * T), o2 = t % (T * T);
+    const int r = o2 % T, c = o2 / T;
+    const int64_t i = (int64_t)(g2 % gi) * T + r, j = (int64_t)(g2 / gi) * T + c;
+    if (i >= d.m || j >= d.n) return;
+    const int w0 = g2 * (kl / 64);
+    float sr = 0.f, si = 0.f;
+    for (int x = 0; x < kl / 64; ++x) {
+        sr += red[w0 + x][2 * o2];
+        si += red[w0 + x][2 * o2 + 1];
+    }
+    if (gridDim.y > 1) {
+        d.partial[(int64_t)blockIdx.y * d.m * d.n + i + j * d.m] = make_float2(sr, si);
+        return;
+    }
+    float2 *cp = d.C + i + j * d.ldc;
+    *cp = scale_out(d, sr, si, cp);
 }
 
 // VEC: A's columns hold its rows contiguously (op(A) = A) and C's rows are
@@ -238,6 +401,13 @@ __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
 }
 
 constexpr int64_t kShortK = 16;
+// threads a split-k reduction aims for (below this, outputs share their
+// k-ranges among several threads)
+constexpr int64_t kReduceThreads = 32768;
+// direct_outer_kernel: shortest k it takes, and the fewest k-values a
+// thread keeps when the k range is split over blocks
+constexpr int64_t kOuterMinK = 1024;
+constexpr int64_t kOuterPerThread = 8;
 
 int pow2_at_least(int64_t x) {
     int p = 1;
@@ -245,9 +415,35 @@ int pow2_at_least(int64_t x) {
     return p;
 }
 
+// The tile of direct_outer_kernel for an m x n output with this k (2, 4 or
+// 8), or 0: tiles of 2 and 4 for a single group, of 8 for up to four
+// groups (a power of two along each side); k long enough that every thread
+// has several k-values.
+int outer_tile(int64_t m, int64_t n, int64_t k) {
+    if (k < kOuterMinK) return 0;
+    for (int T : {2, 4, 8}) {
+        const int64_t gi = pow2_at_least((m + T - 1) / T), gj = pow2_at_least((n + T - 1) / T);
+        if (gi * gj == 1 || (T == 8 && gi * gj <= 4)) return T;
+    }
+    return 0;
+}
+
 }  // namespace
 
-void direct_plan(DirectArgs &d, int64_t &splits) {
+// Returns the tile of direct_outer_kernel, or 0 for direct_kernel.
+int direct_plan(DirectArgs &d, int64_t &splits) {
+    if (const int T = outer_tile(d.m, d.n, d.k)) {
+        d.ti = pow2_at_least((d.m + T - 1) / T);
+        d.tj = pow2_at_least((d.n + T - 1) / T);
+        d.kl = kThreads / (d.ti * d.tj);
+        // blocks over k while each thread keeps at least kOuterPerThread
+        // k-values, up to 1024 blocks
+        splits = 1;
+        while (splits < 1024 && d.k / (splits * 2) >= (int64_t)d.kl * kOuterPerThread) splits *= 2;
+        d.kchunk = (d.k + splits - 1) / splits;
+        splits = (d.k + d.kchunk - 1) / d.kchunk;
+        return T;
+    }
     // threads per output: enough to fill the block when the output is small,
     // and to spread a long k
     const int64_t mn = d.m * d.n;
@@ -269,6 +465,7 @@ void direct_plan(DirectArgs &d, int64_t &splits) {
     d.kchunk = (d.k + splits - 1) / splits;
     splits = (d.k + d.kchunk - 1) / d.kchunk;
     if (splits < 1) splits = 1;
+    return 0;
 }
 
 size_t direct_ws_bytes(int64_t m, int64_t n, int64_t k, int batch) {
@@ -326,15 +523,27 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
         return hipGetLastError();
     }
     int64_t splits = 1;
-    direct_plan(d, splits);
-    const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);
+    const int outer = direct_plan(d, splits);
     d.bsPartial = splits * d.m * d.n;
-    hipLaunchKernelGGL(direct_kernel, dim3((unsigned)tiles, (unsigned)splits, nz), dim3(kThreads), 0, s, d);
+    if (outer) {
+        const dim3 g(1, (unsigned)splits, nz), t(kThreads);
+        if (outer == 2) hipLaunchKernelGGL(direct_outer_kernel<2>, g, t, 0, s, d);
+        else if (outer == 4) hipLaunchKernelGGL(direct_outer_kernel<4>, g, t, 0, s, d);
+        else hipLaunchKernelGGL(direct_outer_kernel<8>, g, t, 0, s, d);
+    } else {
+        const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);
+        hipLaunchKernelGGL(direct_kernel, dim3((unsigned)tiles, (unsigned)splits, nz), dim3(kThreads), 0, s, d);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splits == 1) return e;
+    // threads per output: a few outputs with many k-ranges would otherwise
+    // leave one thread per output walking every range
     const int64_t mn = d.m * d.n;
-    hipLaunchKernelGGL(direct_reduce_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads), 1, nz),
-                       dim3(kThreads), 0, s, d, (int)splits);
+    int ways = 1;
+    while (ways < kThreads && ways < splits && mn * ways < kReduceThreads) ways *= 2;
+    const int64_t per_block = kThreads / ways;
+    hipLaunchKernelGGL(direct_reduce_kernel, dim3((unsigned)((mn + per_block - 1) / per_block), 1, nz),
+                       dim3(kThreads), 0, s, d, (int)splits, ways);
     return hipGetLastError();
 }
 

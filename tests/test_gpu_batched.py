@@ -88,10 +88,11 @@ def run_single(qce, h, A, B, m, n, k, opA="N", opB="N", mode="auto"):
 
 
 @pytest.mark.parametrize("mode", ["auto", "fp16x2", "fp16x2_scaled", "bf16x3", "fp32"])
-@pytest.mark.parametrize("m,n,k", [(200, 150, 96), (130, 100, 3000), (40, 3000, 5), (5, 7, 300), (8, 1, 20000)])
+@pytest.mark.parametrize("m,n,k", [(200, 150, 96), (130, 100, 3000), (40, 3000, 5), (5, 7, 300), (8, 1, 20000),
+                                   (16, 16, 5000)])
 def test_integer_exact(qce, h, mode, m, n, k):
-    # regular tiles, split-k (few tiles, long k), short k, and a dot-like
-    # irregular shape with a split k
+    # regular tiles, split-k (few tiles, long k), short k, and dot-like
+    # irregular shapes with a split k (one and four tiles of outputs)
     rng = np.random.default_rng(m + n + k)
     batch = 3
     As = [synth.random_matrix(m, k, "int", rng) for _ in range(batch)]

@@ -358,7 +358,26 @@ def test_long_k_thin_outputs_alpha_beta(qce, handle, opA, m, n, k):
     assert np.array_equal(C.astype(np.complex128), want)
 
 
-@pytest.mark.parametrize("m,n,k", [(1, 1, 1 << 22), (20000, 3, 5), (8, 9, 300000)])
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C"), ("C", "T")])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1024), (2, 3, 5000), (4, 4, 262144), (8, 8, 1 << 20), (16, 16, 70000),
+                                   (32, 8, 65536), (8, 32, 4096), (24, 5, 3000), (7, 13, 100000)])
+def test_small_output_long_k_alpha_beta(qce, handle, opA, opB, m, n, k):
+    # outputs of up to four 8 x 8 tiles with a long k: each thread adds a
+    # whole tile over its own k-values, then the lanes, waves and k ranges
+    # are added up; with and without a split of k, rows and columns of a
+    # tile past the output, every operand layout; integer inputs exact
+    rng = np.random.default_rng(m + 5 * n + k)
+    sa, sb = shapes_of(m, n, k, opA, opB)
+    A = synth.random_matrix(*sa, "int", rng)
+    B = synth.random_matrix(*sb, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    C, _ = run(qce, handle, A, B, m, n, k, opA, opB, alpha=complex(1, -1), beta=complex(-2, 1), C0=C0)
+    want = oracle.cgemm(A, B, opA, opB, alpha=complex(1, -1), beta=complex(-2, 1), C0=C0)
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1 << 22), (20000, 3, 5), (8, 9, 300000), (8, 8, 1 << 22),
+                                   (16, 16, 1 << 20)])
 def test_irregular_float_accuracy(qce, handle, m, n, k):
     A, B = synth.gemm_operands(m, n, k, "a", seed=31)
     exact = oracle.cgemm(A, B)
