@@ -213,8 +213,11 @@ __device__ inline float lane_scan_f(float v) {
 // of a block are split over the group's d.kl threads (whole waves).  The
 // tile is then added up over each wave's lanes (lane_scan_f) and over the
 // group's waves in LDS, in a fixed order.  d.ti x d.tj groups of tiles
-// cover the output (groups along m first).
-template <int T>
+// cover the output (groups along m first).  VEC: both operands hold their
+// rows contiguously (not conjugate-transposed views of k-contiguous data),
+// 16-byte aligned with even leading dimensions: a k-value's values are read
+// two at a time.
+template <int T, bool VEC>
 __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
     __shared__ float red[kThreads / 64][2 * T * T];
     select_entry(d);
@@ -243,12 +246,36 @@ __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
     // rows i0 + r >= m and columns j0 + c >= n read nothing (the bounds are
     // uniform over a group, hence over a wave)
     auto load = [&](float2 (&a)[T], float2 (&b)[T], int64_t l) {
+        if constexpr (VEC) {
+            // rows r, r + 1 of column l: one 16-byte load (i0 and the
+            // leading dimensions are even, the operands 16-byte aligned)
+            auto pair = [](const float2 *p, int64_t ld, int conj, int64_t rows, int64_t r, int64_t l,
+                           float2 &x, float2 &y) {
+                const float2 *q = p + r + l * ld;
+                if (r + 1 < rows) {
+                    const float4 v = *reinterpret_cast<const float4 *>(q);
+                    x = make_float2(v.x, conj ? -v.y : v.y);
+                    y = make_float2(v.z, conj ? -v.w : v.w);
+                } else {
+                    x = r < rows ? *q : make_float2(0.f, 0.f);
+                    if (conj) x.y = -x.y;
+                    y = make_float2(0.f, 0.f);
+                }
+            };
 #pragma unroll
-        for (int r = 0; r < T; ++r)
-            a[r] = i0 + r < d.m ? load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i0 + r, l) : make_float2(0.f, 0.f);
+            for (int r = 0; r < T; r += 2) pair(d.A, d.lda, d.a_conj, d.m, i0 + r, l, a[r], a[r + 1]);
 #pragma unroll
-        for (int c = 0; c < T; ++c)
-            b[c] = j0 + c < d.n ? load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j0 + c, l) : make_float2(0.f, 0.f);
+            for (int c = 0; c < T; c += 2) pair(d.B, d.ldb, d.b_conj, d.n, j0 + c, l, b[c], b[c + 1]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+                a[r] = i0 + r < d.m ? load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i0 + r, l)
+                                    : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int c = 0; c < T; ++c)
+                b[c] = j0 + c < d.n ? load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j0 + c, l)
+                                    : make_float2(0.f, 0.f);
+        }
     };
     int64_t l = k0 + q;
     for (; l + kl < k1; l += 2 * (int64_t)kl) {
@@ -527,9 +554,17 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
     d.bsPartial = splits * d.m * d.n;
     if (outer) {
         const dim3 g(1, (unsigned)splits, nz), t(kThreads);
-        if (outer == 2) hipLaunchKernelGGL(direct_outer_kernel<2>, g, t, 0, s, d);
-        else if (outer == 4) hipLaunchKernelGGL(direct_outer_kernel<4>, g, t, 0, s, d);
-        else hipLaunchKernelGGL(direct_outer_kernel<8>, g, t, 0, s, d);
+        auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+        const bool vec = !d.a_kcontig && !d.b_kcontig && d.lda % 2 == 0 && d.ldb % 2 == 0 && al16(d.A) &&
+                         al16(d.B) && (nz == 1 || (d.bsA % 2 == 0 && d.bsB % 2 == 0));
+        switch (outer * (vec ? -1 : 1)) {
+        case 2: hipLaunchKernelGGL((direct_outer_kernel<2, false>), g, t, 0, s, d); break;
+        case 4: hipLaunchKernelGGL((direct_outer_kernel<4, false>), g, t, 0, s, d); break;
+        case 8: hipLaunchKernelGGL((direct_outer_kernel<8, false>), g, t, 0, s, d); break;
+        case -2: hipLaunchKernelGGL((direct_outer_kernel<2, true>), g, t, 0, s, d); break;
+        case -4: hipLaunchKernelGGL((direct_outer_kernel<4, true>), g, t, 0, s, d); break;
+        default: hipLaunchKernelGGL((direct_outer_kernel<8, true>), g, t, 0, s, d); break;
+        }
     } else {
         const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);
         hipLaunchKernelGGL(direct_kernel, dim3((unsigned)tiles, (unsigned)splits, nz), dim3(kThreads), 0, s, d);

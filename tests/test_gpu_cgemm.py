@@ -376,6 +376,22 @@ def test_small_output_long_k_alpha_beta(qce, handle, opA, opB, m, n, k):
     assert np.array_equal(C.astype(np.complex128), want)
 
 
+@pytest.mark.parametrize("opB", ["T", "C"])
+@pytest.mark.parametrize("m,n,k", [(8, 8, 1 << 20), (2, 4, 5000), (7, 5, 70000), (16, 16, 70000), (24, 7, 3000),
+                                   (1, 1, 4096)])
+def test_small_output_long_k_paired_loads(qce, handle, opB, m, n, k):
+    # the same kernel with op(A) = A and op(B) = B^T or B^H stored with even
+    # leading dimensions (rows padded to an even count): a k-value's values
+    # are read two at a time, and an odd m or n ends in a single value
+    rng = np.random.default_rng(3 * m + n + k)
+    A = synth.random_matrix(m + m % 2, k, "int", rng)
+    B = synth.random_matrix(n + n % 2, k, "int", rng)
+    C0 = synth.random_matrix(m, n, "int", rng)
+    C, _ = run(qce, handle, A, B, m, n, k, "N", opB, alpha=complex(0, 1), beta=complex(1, 1), C0=C0)
+    want = oracle.cgemm(A[:m], B[:n], "N", opB, alpha=complex(0, 1), beta=complex(1, 1), C0=C0)
+    assert np.array_equal(C.astype(np.complex128), want)
+
+
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1 << 22), (20000, 3, 5), (8, 9, 300000), (8, 8, 1 << 22),
                                    (16, 16, 1 << 20)])
 def test_irregular_float_accuracy(qce, handle, m, n, k):
