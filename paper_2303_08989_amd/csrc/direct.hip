@@ -31,6 +31,8 @@ constexpr int kThreads = 256;
 // k-values (direct_kernel) or k-ranges (direct_reduce_kernel) a thread has
 // in flight at once
 constexpr int kUnroll = 8;
+// longest k of the short-k kernels (direct_rows_kernel, direct_cols_kernel)
+constexpr int kShortK = 16;
 
 __device__ inline float2 load_view(const float2 *p, int64_t ld, int kcontig, int conj, int64_t r,
                                    int64_t l) {
@@ -381,12 +383,21 @@ __global__ __launch_bounds__(kThreads) void direct_rows_kernel(DirectArgs d) {
 
 // VEC: column j of B holds its k values contiguously and column j of C its
 // m values, both 16-byte aligned with k and m even: two complex values per
-// load and per store (the products are added in the same order).
+// load and per store (the products are added in the same order).  Without
+// it the column's B values are all loaded before the products, and where
+// C's columns are adjacent (ldc = m, C = alpha A B, 2 <= m <= 8, C 16-byte
+// aligned) the block's 256 columns, one contiguous run of C, are staged in
+// LDS and written by consecutive lanes, 16 bytes each.
 template <int MT, bool VEC>
 __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
+    constexpr bool kCanStage = !VEC && MT >= 2 && MT <= 8;
+    __shared__ __attribute__((aligned(16))) float2 stage[kThreads * (kCanStage ? MT : 1)];
     select_entry(d);
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j >= d.n) return;
+    const bool active = j < d.n;
+    const bool staged = kCanStage && d.m >= 2 && d.beta_zero && d.ldc == d.m &&
+                        (reinterpret_cast<uintptr_t>(d.C) & 15) == 0;
+    if (!staged && !active) return;
     float re[MT], im[MT];
 #pragma unroll
     for (int ii = 0; ii < MT; ++ii) re[ii] = im[ii] = 0.f;
@@ -401,33 +412,65 @@ __global__ __launch_bounds__(kThreads) void direct_cols_kernel(DirectArgs d) {
             im[ii] = fmaf(a.y, bv.x, im[ii]);
         }
     };
-    if constexpr (VEC) {
-        const float4 *bp = reinterpret_cast<const float4 *>(d.B + j * d.ldb);
-        for (int64_t l2 = 0; l2 < d.k / 2; ++l2) {
-            const float4 v = bp[l2];
-            add(2 * l2, make_float2(v.x, d.b_conj ? -v.y : v.y));
-            add(2 * l2 + 1, make_float2(v.z, d.b_conj ? -v.w : v.w));
-        }
+    if (active) {
+        if constexpr (VEC) {
+            const float4 *bp = reinterpret_cast<const float4 *>(d.B + j * d.ldb);
+            for (int64_t l2 = 0; l2 < d.k / 2; ++l2) {
+                const float4 v = bp[l2];
+                add(2 * l2, make_float2(v.x, d.b_conj ? -v.y : v.y));
+                add(2 * l2 + 1, make_float2(v.z, d.b_conj ? -v.w : v.w));
+            }
+        } else {
+            float2 bv[kShortK];
 #pragma unroll
-        for (int ii = 0; ii < MT; ii += 2) {
-            if (ii >= d.m) break;
-            float2 *cp = d.C + ii + j * d.ldc;
+            for (int l = 0; l < kShortK; ++l) {
+                if (l >= d.k) break;
+                bv[l] = load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l);
+            }
+#pragma unroll
+            for (int l = 0; l < kShortK; ++l) {
+                if (l >= d.k) break;
+                add(l, bv[l]);
+            }
+        }
+    }
+    if (staged) {
+        // beta = 0: scale_out does not read C
+        if (active) {
+#pragma unroll
+            for (int ii = 0; ii < MT; ++ii) {
+                if (ii >= d.m) break;
+                stage[threadIdx.x * d.m + ii] = scale_out(d, re[ii], im[ii], nullptr);
+            }
+        }
+        __syncthreads();
+        const int64_t j0 = (int64_t)blockIdx.x * kThreads;
+        const int64_t len = min((int64_t)kThreads, d.n - j0) * d.m;
+        float2 *base = d.C + j0 * d.m;  // 16-byte aligned: j0 is a multiple of 256
+        for (int64_t e = 2 * (int64_t)threadIdx.x; e < len; e += 2 * kThreads) {
+            if (e + 1 < len) {
+                const float2 u = stage[e], v = stage[e + 1];
+                *reinterpret_cast<float4 *>(base + e) = make_float4(u.x, u.y, v.x, v.y);
+            } else {
+                base[e] = stage[e];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int ii = 0; ii < MT; ii += (VEC ? 2 : 1)) {
+        if (ii >= d.m) break;
+        float2 *cp = d.C + ii + j * d.ldc;
+        if constexpr (VEC) {
             const float2 o0 = scale_out(d, re[ii], im[ii], cp);
             const float2 o1 = scale_out(d, re[ii + 1], im[ii + 1], cp + 1);
             *reinterpret_cast<float4 *>(cp) = make_float4(o0.x, o0.y, o1.x, o1.y);
-        }
-    } else {
-        for (int64_t l = 0; l < d.k; ++l) add(l, load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j, l));
-#pragma unroll
-        for (int ii = 0; ii < MT; ++ii) {
-            if (ii >= d.m) break;
-            float2 *cp = d.C + ii + j * d.ldc;
+        } else {
             *cp = scale_out(d, re[ii], im[ii], cp);
         }
     }
 }
 
-constexpr int64_t kShortK = 16;
 // threads a split-k reduction aims for (below this, outputs share their
 // k-ranges among several threads)
 constexpr int64_t kReduceThreads = 32768;

@@ -317,21 +317,24 @@ def test_short_k_ops_alpha_beta(qce, handle, opA, opB, m, n, k):
     assert np.array_equal(C.astype(np.complex128), want)
 
 
+@pytest.mark.parametrize("beta", [complex(-1, 1), 0j])
 @pytest.mark.parametrize("shift", [0, 1])
 @pytest.mark.parametrize("m,n,k", [(2, 5000, 2), (6, 3000, 8), (16, 777, 16), (30, 513, 10),
                                    (7, 300, 8), (6, 300, 5), (64, 300, 8), (1000, 5, 16), (34, 100, 3),
-                                   (33, 70, 2)])
-def test_short_k_columns_alpha_beta(qce, handle, m, n, k, shift):
+                                   (33, 70, 2), (3, 1000, 7), (8, 257, 16)])
+def test_short_k_columns_alpha_beta(qce, handle, m, n, k, shift, beta):
     # short k: one output column per thread below 32 rows, one or two rows
     # per thread from 32.  Even sizes with the operands read whole and C
     # 16-byte aligned move two complex values per load and store; odd
     # sizes, or B and C one element off that alignment (shift), go element
-    # by element.  Integer inputs: exact either way.
+    # by element; with beta = 0, up to 8 rows and C aligned, a block's
+    # columns are staged in LDS and stored as one run.  Integer inputs:
+    # exact either way.
     rng = np.random.default_rng(7 * m + n + k)
     A = synth.random_matrix(m, k, "int", rng)
     B = synth.random_matrix(k, n, "int", rng)
     C0 = synth.random_matrix(m, n, "int", rng)
-    alpha, beta = complex(2, -1), complex(-1, 1)
+    alpha = complex(2, -1)
     pad = torch.zeros(shift, dtype=torch.complex64, device="cuda")
     dB = torch.cat([pad, dev(B)])[shift:]
     dC = torch.cat([pad, dev(C0)])[shift:]
