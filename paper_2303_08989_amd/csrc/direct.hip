@@ -208,9 +208,9 @@ __device__ inline float lane_scan_f(float v) {
     return v;
 }
 
-// A small output (up to 8 x 8 per group, at most four groups) with a long
-// k: every thread of a group accumulates the group's whole T x T output
-// tile over its own k-values (a column of op(A) and a row of op(B) per
+// A small output (up to 8 x 8, 4 x 16 or 16 x 4 per group, at most four
+// groups) with a long k: every thread of a group accumulates the group's
+// whole TM x TN output tile over its own k-values (a column of op(A) and a row of op(B) per
 // k-value, each element read once), two k-values in flight; the k-values
 // of a block are split over the group's d.kl threads (whole waves).  The
 // tile is then added up over each wave's lanes (lane_scan_f) and over the
@@ -219,26 +219,26 @@ __device__ inline float lane_scan_f(float v) {
 // rows contiguously (not conjugate-transposed views of k-contiguous data),
 // 16-byte aligned with even leading dimensions: a k-value's values are read
 // two at a time.
-template <int T, bool VEC>
+template <int TM, int TN, bool VEC>
 __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
-    __shared__ float red[kThreads / 64][2 * T * T];
+    __shared__ float red[kThreads / 64][2 * TM * TN];
     select_entry(d);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int kl = d.kl, gi = d.ti;
     const int g = t / kl, q = t % kl;
-    const int64_t i0 = (int64_t)(g % gi) * T, j0 = (int64_t)(g / gi) * T;
+    const int64_t i0 = (int64_t)(g % gi) * TM, j0 = (int64_t)(g / gi) * TN;
     const int64_t k0 = (int64_t)blockIdx.y * d.kchunk;
     const int64_t k1 = min(d.k, k0 + d.kchunk);
-    float re[T][T], im[T][T];
+    float re[TM][TN], im[TM][TN];
 #pragma unroll
-    for (int r = 0; r < T; ++r)
+    for (int r = 0; r < TM; ++r)
 #pragma unroll
-        for (int c = 0; c < T; ++c) re[r][c] = im[r][c] = 0.f;
-    auto fma_tile = [&](const float2 (&a)[T], const float2 (&b)[T]) {
+        for (int c = 0; c < TN; ++c) re[r][c] = im[r][c] = 0.f;
+    auto fma_tile = [&](const float2 (&a)[TM], const float2 (&b)[TN]) {
 #pragma unroll
-        for (int r = 0; r < T; ++r)
+        for (int r = 0; r < TM; ++r)
 #pragma unroll
-            for (int c = 0; c < T; ++c) {
+            for (int c = 0; c < TN; ++c) {
                 re[r][c] = fmaf(a[r].x, b[c].x, re[r][c]);
                 re[r][c] = fmaf(-a[r].y, b[c].y, re[r][c]);
                 im[r][c] = fmaf(a[r].x, b[c].y, im[r][c]);
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
     };
     // rows i0 + r >= m and columns j0 + c >= n read nothing (the bounds are
     // uniform over a group, hence over a wave)
-    auto load = [&](float2 (&a)[T], float2 (&b)[T], int64_t l) {
+    auto load = [&](float2 (&a)[TM], float2 (&b)[TN], int64_t l) {
         if constexpr (VEC) {
             // rows r, r + 1 of column l: one 16-byte load (i0 and the
             // leading dimensions are even, the operands 16-byte aligned)
@@ -265,51 +265,51 @@ __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
                 }
             };
 #pragma unroll
-            for (int r = 0; r < T; r += 2) pair(d.A, d.lda, d.a_conj, d.m, i0 + r, l, a[r], a[r + 1]);
+            for (int r = 0; r < TM; r += 2) pair(d.A, d.lda, d.a_conj, d.m, i0 + r, l, a[r], a[r + 1]);
 #pragma unroll
-            for (int c = 0; c < T; c += 2) pair(d.B, d.ldb, d.b_conj, d.n, j0 + c, l, b[c], b[c + 1]);
+            for (int c = 0; c < TN; c += 2) pair(d.B, d.ldb, d.b_conj, d.n, j0 + c, l, b[c], b[c + 1]);
         } else {
 #pragma unroll
-            for (int r = 0; r < T; ++r)
+            for (int r = 0; r < TM; ++r)
                 a[r] = i0 + r < d.m ? load_view(d.A, d.lda, d.a_kcontig, d.a_conj, i0 + r, l)
                                     : make_float2(0.f, 0.f);
 #pragma unroll
-            for (int c = 0; c < T; ++c)
+            for (int c = 0; c < TN; ++c)
                 b[c] = j0 + c < d.n ? load_view(d.B, d.ldb, d.b_kcontig, d.b_conj, j0 + c, l)
                                     : make_float2(0.f, 0.f);
         }
     };
     int64_t l = k0 + q;
     for (; l + kl < k1; l += 2 * (int64_t)kl) {
-        float2 a0[T], b0[T], a1[T], b1[T];
+        float2 a0[TM], b0[TN], a1[TM], b1[TN];
         load(a0, b0, l);
         load(a1, b1, l + kl);
         fma_tile(a0, b0);
         fma_tile(a1, b1);
     }
     if (l < k1) {
-        float2 a0[T], b0[T];
+        float2 a0[TM], b0[TN];
         load(a0, b0, l);
         fma_tile(a0, b0);
     }
     // each wave's sums (lane 63 holds them after the scan)
 #pragma unroll
-    for (int r = 0; r < T; ++r)
+    for (int r = 0; r < TM; ++r)
 #pragma unroll
-        for (int c = 0; c < T; ++c) {
+        for (int c = 0; c < TN; ++c) {
             const float sr = lane_scan_f(re[r][c]), si = lane_scan_f(im[r][c]);
             if (lane == 63) {
-                red[wv][2 * (r + c * T)] = sr;
-                red[wv][2 * (r + c * T) + 1] = si;
+                red[wv][2 * (r + c * TM)] = sr;
+                red[wv][2 * (r + c * TM) + 1] = si;
             }
         }
     __syncthreads();
-    // thread t: output (r, c) of group t / T^2, its waves added in order
+    // thread t: output (r, c) of group t / (TM TN), its waves added in order
     const int groups = kThreads / kl;
-    if (t >= groups * T * T) return;
-    const int g2 = t / (T * T), o2 = t % (T * T);
-    const int r = o2 % T, c = o2 / T;
-    const int64_t i = (int64_t)(g2 % gi) * T + r, j = (int64_t)(g2 / gi) * T + c;
+    if (t >= groups * TM * TN) return;
+    const int g2 = t / (TM * TN), o2 = t % (TM * TN);
+    const int r = o2 % TM, c = o2 / TM;
+    const int64_t i = (int64_t)(g2 % gi) * TM + r, j = (int64_t)(g2 / gi) * TN + c;
     if (i >= d.m || j >= d.n) return;
     const int w0 = g2 * (kl / 64);
     float sr = 0.f, si = 0.f;
@@ -485,26 +485,32 @@ int pow2_at_least(int64_t x) {
     return p;
 }
 
-// The tile of direct_outer_kernel for an m x n output with this k (2, 4 or
-// 8), or 0: tiles of 2 and 4 for a single group, of 8 for up to four
-// groups (a power of two along each side); k long enough that every thread
-// has several k-values.
+// The tile of direct_outer_kernel for an m x n output with this k (1 + its
+// index in kOuterTiles), or 0: 2 x 2 and 4 x 4 for a single group, the
+// 64-output tiles for up to four groups (a power of two along each side);
+// k long enough that every thread has several k-values.
+struct OuterTile {
+    int tm, tn;
+};
+constexpr OuterTile kOuterTiles[] = {{2, 2}, {4, 4}, {8, 8}, {4, 16}, {16, 4}};
 int outer_tile(int64_t m, int64_t n, int64_t k) {
     if (k < kOuterMinK) return 0;
-    for (int T : {2, 4, 8}) {
-        const int64_t gi = pow2_at_least((m + T - 1) / T), gj = pow2_at_least((n + T - 1) / T);
-        if (gi * gj == 1 || (T == 8 && gi * gj <= 4)) return T;
+    for (int q = 0; q < 5; ++q) {
+        const int tm = kOuterTiles[q].tm, tn = kOuterTiles[q].tn;
+        const int64_t gi = pow2_at_least((m + tm - 1) / tm), gj = pow2_at_least((n + tn - 1) / tn);
+        if (gi * gj == 1 || (tm * tn == 64 && gi * gj <= 4)) return q + 1;
     }
     return 0;
 }
 
 }  // namespace
 
-// Returns the tile of direct_outer_kernel, or 0 for direct_kernel.
+// Returns outer_tile's choice for direct_outer_kernel, or 0 for direct_kernel.
 int direct_plan(DirectArgs &d, int64_t &splits) {
-    if (const int T = outer_tile(d.m, d.n, d.k)) {
-        d.ti = pow2_at_least((d.m + T - 1) / T);
-        d.tj = pow2_at_least((d.n + T - 1) / T);
+    if (const int q = outer_tile(d.m, d.n, d.k)) {
+        const OuterTile &tt = kOuterTiles[q - 1];
+        d.ti = pow2_at_least((d.m + tt.tm - 1) / tt.tm);
+        d.tj = pow2_at_least((d.n + tt.tn - 1) / tt.tn);
         d.kl = kThreads / (d.ti * d.tj);
         // blocks over k while each thread keeps at least kOuterPerThread
         // k-values, up to 1024 blocks
@@ -512,7 +518,7 @@ int direct_plan(DirectArgs &d, int64_t &splits) {
         while (splits < 1024 && d.k / (splits * 2) >= (int64_t)d.kl * kOuterPerThread) splits *= 2;
         d.kchunk = (d.k + splits - 1) / splits;
         splits = (d.k + d.kchunk - 1) / d.kchunk;
-        return T;
+        return q;
     }
     // threads per output: enough to fill the block when the output is small,
     // and to spread a long k
@@ -601,12 +607,16 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
         const bool vec = !d.a_kcontig && !d.b_kcontig && d.lda % 2 == 0 && d.ldb % 2 == 0 && al16(d.A) &&
                          al16(d.B) && (nz == 1 || (d.bsA % 2 == 0 && d.bsB % 2 == 0));
         switch (outer * (vec ? -1 : 1)) {
-        case 2: hipLaunchKernelGGL((direct_outer_kernel<2, false>), g, t, 0, s, d); break;
-        case 4: hipLaunchKernelGGL((direct_outer_kernel<4, false>), g, t, 0, s, d); break;
-        case 8: hipLaunchKernelGGL((direct_outer_kernel<8, false>), g, t, 0, s, d); break;
-        case -2: hipLaunchKernelGGL((direct_outer_kernel<2, true>), g, t, 0, s, d); break;
-        case -4: hipLaunchKernelGGL((direct_outer_kernel<4, true>), g, t, 0, s, d); break;
-        default: hipLaunchKernelGGL((direct_outer_kernel<8, true>), g, t, 0, s, d); break;
+        case 1: hipLaunchKernelGGL((direct_outer_kernel<2, 2, false>), g, t, 0, s, d); break;
+        case 2: hipLaunchKernelGGL((direct_outer_kernel<4, 4, false>), g, t, 0, s, d); break;
+        case 3: hipLaunchKernelGGL((direct_outer_kernel<8, 8, false>), g, t, 0, s, d); break;
+        case 4: hipLaunchKernelGGL((direct_outer_kernel<4, 16, false>), g, t, 0, s, d); break;
+        case 5: hipLaunchKernelGGL((direct_outer_kernel<16, 4, false>), g, t, 0, s, d); break;
+        case -1: hipLaunchKernelGGL((direct_outer_kernel<2, 2, true>), g, t, 0, s, d); break;
+        case -2: hipLaunchKernelGGL((direct_outer_kernel<4, 4, true>), g, t, 0, s, d); break;
+        case -3: hipLaunchKernelGGL((direct_outer_kernel<8, 8, true>), g, t, 0, s, d); break;
+        case -4: hipLaunchKernelGGL((direct_outer_kernel<4, 16, true>), g, t, 0, s, d); break;
+        default: hipLaunchKernelGGL((direct_outer_kernel<16, 4, true>), g, t, 0, s, d); break;
         }
     } else {
         const int64_t tiles = ((d.m + d.ti - 1) / d.ti) * ((d.n + d.tj - 1) / d.tj);

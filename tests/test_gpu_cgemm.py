@@ -363,12 +363,14 @@ def test_long_k_thin_outputs_alpha_beta(qce, handle, opA, m, n, k):
 
 @pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C"), ("C", "T")])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1024), (2, 3, 5000), (4, 4, 262144), (8, 8, 1 << 20), (16, 16, 70000),
-                                   (32, 8, 65536), (8, 32, 4096), (24, 5, 3000), (7, 13, 100000)])
+                                   (32, 8, 65536), (8, 32, 4096), (24, 5, 3000), (7, 13, 100000), (4, 64, 70000),
+                                   (64, 4, 5000), (3, 40, 3000), (50, 2, 2000)])
 def test_small_output_long_k_alpha_beta(qce, handle, opA, opB, m, n, k):
-    # outputs of up to four 8 x 8 tiles with a long k: each thread adds a
-    # whole tile over its own k-values, then the lanes, waves and k ranges
-    # are added up; with and without a split of k, rows and columns of a
-    # tile past the output, every operand layout; integer inputs exact
+    # outputs of up to four 8 x 8, 4 x 16 or 16 x 4 tiles with a long k:
+    # each thread adds a whole tile over its own k-values, then the lanes,
+    # waves and k ranges are added up; with and without a split of k, rows
+    # and columns of a tile past the output, every operand layout; integer
+    # inputs exact
     rng = np.random.default_rng(m + 5 * n + k)
     sa, sb = shapes_of(m, n, k, opA, opB)
     A = synth.random_matrix(*sa, "int", rng)
@@ -381,7 +383,7 @@ def test_small_output_long_k_alpha_beta(qce, handle, opA, opB, m, n, k):
 
 @pytest.mark.parametrize("opB", ["T", "C"])
 @pytest.mark.parametrize("m,n,k", [(8, 8, 1 << 20), (2, 4, 5000), (7, 5, 70000), (16, 16, 70000), (24, 7, 3000),
-                                   (1, 1, 4096)])
+                                   (1, 1, 4096), (4, 64, 70000), (3, 40, 3000), (50, 2, 2000)])
 def test_small_output_long_k_paired_loads(qce, handle, opB, m, n, k):
     # the same kernel with op(A) = A and op(B) = B^T or B^H stored with even
     # leading dimensions (rows padded to an even count): a k-value's values
