@@ -208,8 +208,8 @@ __device__ inline float lane_scan_f(float v) {
     return v;
 }
 
-// A small output (up to 8 x 8, 4 x 16 or 16 x 4 per group, at most four
-// groups) with a long k: every thread of a group accumulates the group's
+// A small output (one tile of kOuterTiles, or up to four 8 x 8, 4 x 16 or
+// 16 x 4 tiles) with a long k: every thread of a group accumulates the group's
 // whole TM x TN output tile over its own k-values (a column of op(A) and a row of op(B) per
 // k-value, each element read once), two k-values in flight; the k-values
 // of a block are split over the group's d.kl threads (whole waves).  The
@@ -486,20 +486,28 @@ int pow2_at_least(int64_t x) {
 }
 
 // The tile of direct_outer_kernel for an m x n output with this k (1 + its
-// index in kOuterTiles), or 0: 2 x 2 and 4 x 4 for a single group, the
-// 64-output tiles for up to four groups (a power of two along each side);
-// k long enough that every thread has several k-values.
+// index in kOuterTiles), or 0; the groups of tiles are a power of two
+// along each side, and k is long enough that every thread has several
+// k-values.
 struct OuterTile {
     int tm, tn;
 };
-constexpr OuterTile kOuterTiles[] = {{2, 2}, {4, 4}, {8, 8}, {4, 16}, {16, 4}};
+constexpr OuterTile kOuterTiles[] = {{2, 2}, {4, 4}, {8, 2}, {2, 8}, {8, 8}, {4, 16}, {16, 4}};
+constexpr int kOuterTileCount = sizeof(kOuterTiles) / sizeof(kOuterTiles[0]);
 int outer_tile(int64_t m, int64_t n, int64_t k) {
-    if (k < kOuterMinK) return 0;
-    for (int q = 0; q < 5; ++q) {
+    // a single row or column (a GEMV) is left to direct_kernel, measured
+    // faster there (8 x 1 over k = 2^16, 128 entries: 168 against 205 us)
+    if (k < kOuterMinK || m == 1 || n == 1) return 0;
+    auto groups = [&](int q) {
         const int tm = kOuterTiles[q].tm, tn = kOuterTiles[q].tn;
-        const int64_t gi = pow2_at_least((m + tm - 1) / tm), gj = pow2_at_least((n + tn - 1) / tn);
-        if (gi * gj == 1 || (tm * tn == 64 && gi * gj <= 4)) return q + 1;
-    }
+        return pow2_at_least((m + tm - 1) / tm) * pow2_at_least((n + tn - 1) / tn);
+    };
+    // the smallest tile that holds the whole output (each operand element
+    // read by one group), else a 64-output tile in up to four groups
+    for (int q = 0; q < kOuterTileCount; ++q)
+        if (groups(q) == 1) return q + 1;
+    for (int q = 0; q < kOuterTileCount; ++q)
+        if (kOuterTiles[q].tm * kOuterTiles[q].tn == 64 && groups(q) <= 4) return q + 1;
     return 0;
 }
 
@@ -609,13 +617,17 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
         switch (outer * (vec ? -1 : 1)) {
         case 1: hipLaunchKernelGGL((direct_outer_kernel<2, 2, false>), g, t, 0, s, d); break;
         case 2: hipLaunchKernelGGL((direct_outer_kernel<4, 4, false>), g, t, 0, s, d); break;
-        case 3: hipLaunchKernelGGL((direct_outer_kernel<8, 8, false>), g, t, 0, s, d); break;
-        case 4: hipLaunchKernelGGL((direct_outer_kernel<4, 16, false>), g, t, 0, s, d); break;
-        case 5: hipLaunchKernelGGL((direct_outer_kernel<16, 4, false>), g, t, 0, s, d); break;
+        case 3: hipLaunchKernelGGL((direct_outer_kernel<8, 2, false>), g, t, 0, s, d); break;
+        case 4: hipLaunchKernelGGL((direct_outer_kernel<2, 8, false>), g, t, 0, s, d); break;
+        case 5: hipLaunchKernelGGL((direct_outer_kernel<8, 8, false>), g, t, 0, s, d); break;
+        case 6: hipLaunchKernelGGL((direct_outer_kernel<4, 16, false>), g, t, 0, s, d); break;
+        case 7: hipLaunchKernelGGL((direct_outer_kernel<16, 4, false>), g, t, 0, s, d); break;
         case -1: hipLaunchKernelGGL((direct_outer_kernel<2, 2, true>), g, t, 0, s, d); break;
         case -2: hipLaunchKernelGGL((direct_outer_kernel<4, 4, true>), g, t, 0, s, d); break;
-        case -3: hipLaunchKernelGGL((direct_outer_kernel<8, 8, true>), g, t, 0, s, d); break;
-        case -4: hipLaunchKernelGGL((direct_outer_kernel<4, 16, true>), g, t, 0, s, d); break;
+        case -3: hipLaunchKernelGGL((direct_outer_kernel<8, 2, true>), g, t, 0, s, d); break;
+        case -4: hipLaunchKernelGGL((direct_outer_kernel<2, 8, true>), g, t, 0, s, d); break;
+        case -5: hipLaunchKernelGGL((direct_outer_kernel<8, 8, true>), g, t, 0, s, d); break;
+        case -6: hipLaunchKernelGGL((direct_outer_kernel<4, 16, true>), g, t, 0, s, d); break;
         default: hipLaunchKernelGGL((direct_outer_kernel<16, 4, true>), g, t, 0, s, d); break;
         }
     } else {

@@ -364,7 +364,7 @@ def test_long_k_thin_outputs_alpha_beta(qce, handle, opA, m, n, k):
 @pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C"), ("C", "T")])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1024), (2, 3, 5000), (4, 4, 262144), (8, 8, 1 << 20), (16, 16, 70000),
                                    (32, 8, 65536), (8, 32, 4096), (24, 5, 3000), (7, 13, 100000), (4, 64, 70000),
-                                   (64, 4, 5000), (3, 40, 3000), (50, 2, 2000)])
+                                   (64, 4, 5000), (3, 40, 3000), (50, 2, 2000), (1, 8, 5000), (6, 2, 3000)])
 def test_small_output_long_k_alpha_beta(qce, handle, opA, opB, m, n, k):
     # outputs of up to four 8 x 8, 4 x 16 or 16 x 4 tiles with a long k:
     # each thread adds a whole tile over its own k-values, then the lanes,
