@@ -19,6 +19,11 @@
 // up to 8 columns (its A values are read once for all of them; the B values
 // are the same for the whole block), direct_cols_kernel gives a thread one
 // column and every row of a short m (it writes m contiguous outputs).
+//
+// A small output with a long k (the adjoint of a gate against a large
+// tensor, the last thin contraction of a slice) takes direct_outer_kernel:
+// every thread accumulates a whole output tile over its own k-values, so
+// each operand element is read once.
 #include "common.hpp"
 
 #include <algorithm>
