@@ -214,16 +214,16 @@ __device__ inline float lane_scan_f(float v) {
 }
 
 // A small output (one tile of kOuterTiles, or up to four 8 x 8, 4 x 16 or
-// 16 x 4 tiles) with a long k: every thread of a group accumulates the group's
-// whole TM x TN output tile over its own k-values (a column of op(A) and a row of op(B) per
-// k-value, each element read once), two k-values in flight; the k-values
-// of a block are split over the group's d.kl threads (whole waves).  The
-// tile is then added up over each wave's lanes (lane_scan_f) and over the
-// group's waves in LDS, in a fixed order.  d.ti x d.tj groups of tiles
-// cover the output (groups along m first).  VEC: both operands hold their
-// rows contiguously (not conjugate-transposed views of k-contiguous data),
-// 16-byte aligned with even leading dimensions: a k-value's values are read
-// two at a time.
+// 16 x 4 tiles) with a long k: every thread of a group accumulates the
+// group's whole TM x TN output tile over its own k-values (for each, TM
+// values of op(A) and TN of op(B), every element read once), two k-values
+// in flight; the k-values of a block are split over the group's d.kl
+// threads (whole waves).  The tile is then added up over each wave's lanes
+// (lane_scan_f) and over the group's waves in LDS, in a fixed order.
+// d.ti x d.tj groups of tiles cover the output (groups along m first).
+// VEC: both operand views hold a k-value's rows contiguously
+// (P[r][l] = x[r + l ld]), 16-byte aligned with even leading dimensions:
+// the values are read two at a time.
 template <int TM, int TN, bool VEC>
 __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
     __shared__ float red[kThreads / 64][2 * TM * TN];
