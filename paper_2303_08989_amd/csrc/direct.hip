@@ -330,6 +330,128 @@ __global__ __launch_bounds__(kThreads) void direct_outer_kernel(DirectArgs d) {
     *cp = scale_out(d, sr, si, cp);
 }
 
+// The 8 x 8 tile of direct_outer_kernel with VEC operands, four lanes per
+// k-value: lane p of a quad loads rows 2p, 2p + 1 of the k-value's op(A)
+// and op(B) values (one 16-byte load each; consecutive quads take
+// consecutive k-values, so a wave's load covers 16 whole 64-byte runs),
+// takes the quad's other op(B) values by DPP and accumulates rows 2p, 2p + 1
+// of the tile.  The quads' tiles are then added over the wave (lanes p,
+// p + 4, ...) and over the group's waves in LDS, in a fixed order.
+__device__ inline float quad_bcast(float x, int src) {
+    // quad_perm [src, src, src, src]
+    switch (src) {
+    case 0: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x00, 0xf, 0xf, false));
+    case 1: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x55, 0xf, 0xf, false));
+    case 2: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xaa, 0xf, 0xf, false));
+    default: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xff, 0xf, 0xf, false));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void direct_outer_quad_kernel(DirectArgs d) {
+    __shared__ float red[kThreads / 64][2 * 64];
+    select_entry(d);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, p = lane & 3;
+    const int kl = d.kl, gi = d.ti;
+    const int g = t / kl, q = (t % kl) >> 2;
+    const int64_t nq = kl >> 2;  // k-values a group takes per round
+    const int64_t ia = (int64_t)(g % gi) * 8 + 2 * p, jb = (int64_t)(g / gi) * 8 + 2 * p;
+    const int64_t k0 = (int64_t)blockIdx.y * d.kchunk;
+    const int64_t k1 = min(d.k, k0 + d.kchunk);
+    float re[2][8], im[2][8];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) re[r][c] = im[r][c] = 0.f;
+    // rows r, r + 1 of column l (zeros past rows)
+    auto pair = [](const float2 *x, int64_t ld, int conj, int64_t rows, int64_t r, int64_t l, float2 &u,
+                   float2 &v) {
+        const float2 *ptr = x + r + l * ld;
+        if (r + 1 < rows) {
+            const float4 w = *reinterpret_cast<const float4 *>(ptr);
+            u = make_float2(w.x, conj ? -w.y : w.y);
+            v = make_float2(w.z, conj ? -w.w : w.w);
+        } else {
+            u = r < rows ? *ptr : make_float2(0.f, 0.f);
+            if (conj) u.y = -u.y;
+            v = make_float2(0.f, 0.f);
+        }
+    };
+    auto step = [&](const float2 (&a)[2], const float2 (&bp)[2]) {
+        float2 b[8];
+#pragma unroll
+        for (int src = 0; src < 4; ++src)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                b[2 * src + h] = make_float2(quad_bcast(bp[h].x, src), quad_bcast(bp[h].y, src));
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                re[r][c] = fmaf(a[r].x, b[c].x, re[r][c]);
+                re[r][c] = fmaf(-a[r].y, b[c].y, re[r][c]);
+                im[r][c] = fmaf(a[r].x, b[c].y, im[r][c]);
+                im[r][c] = fmaf(a[r].y, b[c].x, im[r][c]);
+            }
+    };
+    // a quad's lanes share l, so a quad is active or idle as a whole
+    int64_t l = k0 + q;
+    for (; l + nq < k1; l += 2 * nq) {
+        float2 a0[2], b0[2], a1[2], b1[2];
+        pair(d.A, d.lda, d.a_conj, d.m, ia, l, a0[0], a0[1]);
+        pair(d.B, d.ldb, d.b_conj, d.n, jb, l, b0[0], b0[1]);
+        pair(d.A, d.lda, d.a_conj, d.m, ia, l + nq, a1[0], a1[1]);
+        pair(d.B, d.ldb, d.b_conj, d.n, jb, l + nq, b1[0], b1[1]);
+        step(a0, b0);
+        step(a1, b1);
+    }
+    if (l < k1) {
+        float2 a0[2], b0[2];
+        pair(d.A, d.lda, d.a_conj, d.m, ia, l, a0[0], a0[1]);
+        pair(d.B, d.ldb, d.b_conj, d.n, jb, l, b0[0], b0[1]);
+        step(a0, b0);
+    }
+    // over the wave's quads: lanes 12 + p of each row of 16 add up their
+    // row (shifts by 4 and 8), then the rows are added pairwise
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float v[2] = {re[r][c], im[r][c]};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float x = v[h];
+                x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, false));
+                x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, false));
+                x += __shfl_xor(x, 16);
+                x += __shfl_xor(x, 32);
+                v[h] = x;
+            }
+            if (lane >= 12 && lane < 16) {
+                const int o = 2 * p + r + 8 * c;
+                red[wv][2 * o] = v[0];
+                red[wv][2 * o + 1] = v[1];
+            }
+        }
+    __syncthreads();
+    const int groups = kThreads / kl;
+    if (t >= groups * 64) return;
+    const int g2 = t / 64, o2 = t % 64;
+    const int64_t i = (int64_t)(g2 % gi) * 8 + o2 % 8, j = (int64_t)(g2 / gi) * 8 + o2 / 8;
+    if (i >= d.m || j >= d.n) return;
+    const int w0 = g2 * (kl / 64);
+    float sr = 0.f, si = 0.f;
+    for (int x = 0; x < kl / 64; ++x) {
+        sr += red[w0 + x][2 * o2];
+        si += red[w0 + x][2 * o2 + 1];
+    }
+    if (gridDim.y > 1) {
+        d.partial[(int64_t)blockIdx.y * d.m * d.n + i + j * d.m] = make_float2(sr, si);
+        return;
+    }
+    float2 *cp = d.C + i + j * d.ldc;
+    *cp = scale_out(d, sr, si, cp);
+}
+
 // VEC: A's columns hold its rows contiguously (op(A) = A) and C's rows are
 // contiguous too, both 16-byte aligned with m even: a thread takes two
 // consecutive rows, one 16-byte load per k-value and one 16-byte store per
@@ -483,6 +605,8 @@ constexpr int64_t kReduceThreads = 32768;
 // thread keeps when the k range is split over blocks
 constexpr int64_t kOuterMinK = 1024;
 constexpr int64_t kOuterPerThread = 8;
+// direct_outer_quad_kernel: shortest k it takes
+constexpr int64_t kQuadMinK = int64_t(1) << 20;
 
 int pow2_at_least(int64_t x) {
     int p = 1;
@@ -631,7 +755,12 @@ hipError_t launch_direct(DirectArgs d, hipStream_t s) {
         case -2: hipLaunchKernelGGL((direct_outer_kernel<4, 4, true>), g, t, 0, s, d); break;
         case -3: hipLaunchKernelGGL((direct_outer_kernel<8, 2, true>), g, t, 0, s, d); break;
         case -4: hipLaunchKernelGGL((direct_outer_kernel<2, 8, true>), g, t, 0, s, d); break;
-        case -5: hipLaunchKernelGGL((direct_outer_kernel<8, 8, true>), g, t, 0, s, d); break;
+        case -5:
+            // four lanes per k-value from k = 2^20 (8 x 8 x 2^22: 148 against 166
+            // us); below that the one-lane kernel measured faster (20 against 27 us)
+            if (d.k >= kQuadMinK) hipLaunchKernelGGL(direct_outer_quad_kernel, g, t, 0, s, d);
+            else hipLaunchKernelGGL((direct_outer_kernel<8, 8, true>), g, t, 0, s, d);
+            break;
         case -6: hipLaunchKernelGGL((direct_outer_kernel<4, 16, true>), g, t, 0, s, d); break;
         default: hipLaunchKernelGGL((direct_outer_kernel<16, 4, true>), g, t, 0, s, d); break;
         }

@@ -383,11 +383,13 @@ def test_small_output_long_k_alpha_beta(qce, handle, opA, opB, m, n, k):
 
 @pytest.mark.parametrize("opB", ["T", "C"])
 @pytest.mark.parametrize("m,n,k", [(8, 8, 1 << 20), (2, 4, 5000), (7, 5, 70000), (16, 16, 70000), (24, 7, 3000),
-                                   (1, 1, 4096), (4, 64, 70000), (3, 40, 3000), (50, 2, 2000)])
+                                   (1, 1, 4096), (4, 64, 70000), (3, 40, 3000), (50, 2, 2000), (16, 16, 1 << 20),
+                                   (5, 7, 1 << 20), (24, 3, 1 << 20)])
 def test_small_output_long_k_paired_loads(qce, handle, opB, m, n, k):
     # the same kernel with op(A) = A and op(B) = B^T or B^H stored with even
     # leading dimensions (rows padded to an even count): a k-value's values
-    # are read two at a time, and an odd m or n ends in a single value
+    # are read two at a time, and an odd m or n ends in a single value; from
+    # k = 2^20 the 8 x 8 tiles take four lanes per k-value
     rng = np.random.default_rng(3 * m + n + k)
     A = synth.random_matrix(m + m % 2, k, "int", rng)
     B = synth.random_matrix(n + n % 2, k, "int", rng)
